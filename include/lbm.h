@@ -1,0 +1,237 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) lattice Boltzmann library for
+ * quasi-static linear elasticity in 2D on periodic lattices.
+ *
+ * Method: Boolakee, Geier, De Lorenzis, "A new lattice Boltzmann scheme for
+ * linear elastic solids: periodic problems" (arXiv 2208.14870).  The library
+ * solves the damped Navier-Cauchy problem of Sec. 2.1 (Eq. linelasdamp,
+ * kappa du/dt = mu lap u + K grad div u + b, with the periodicity of
+ * Eq. periodicity and u0 = 0) by pseudo-time stepping of the single-
+ * distribution D2Q8 scheme of Algorithm 1 until the steady-state residual
+ * falls below a tolerance (Sec. 2.1: ||du/dt|| < TOL "in some norm").
+ *
+ * Units.  Everything is in lattice units: dx = dt = 1, kappa = 1, U = 1.
+ * Material parameters are the lattice Lame parameters lambda~, mu~ (Eq.
+ * scaling_example: mu~ = dt mu / (kappa dx^2)); the body force is the per-step
+ * force g = b (Sec. 3.3.2, g^(2) = L U^-1 b~ with diffusive scaling).
+ *
+ * Data layout.  Every field passed across this ABI is an FP64 array in
+ * device memory of shape [ny][nx] (x fastest), one array per component.
+ * Node (i, j) sits at (i + 1/2, j + 1/2) (Sec. 6.1).  Population arrays are
+ * [8][ny][nx] in the one-index order of the velocity table of Sec. 5:
+ * 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1).
+ *
+ * Streams and ownership.  All device work is enqueued on the HIP stream given
+ * at creation (NULL = the null stream).  Device pointers passed in are read
+ * in stream order; the caller keeps them alive until the stream has
+ * synchronised.  Workspaces and arenas are caller-owned device memory; the
+ * library never frees caller memory.  Handles are not thread-safe; distinct
+ * handles are independent.  No exception or abort crosses the ABI: every call
+ * returns a status and lbm_last_error() describes the last failure.
+ *
+ * Numerics.  LBM_FP64 stores and computes in FP64.  LBM_FP32 stores the
+ * populations in FP32 and computes in FP32.  LBM_FP16 stores the populations
+ * in FP16 scaled by a per-lattice power of two (the problem is linear and the
+ * rest equilibrium of the scheme is zero) and computes in FP32.  Residuals,
+ * displacements and error norms are always produced in FP64.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_solver lbm_solver;
+typedef struct lbm_batch lbm_batch;
+
+/* Storage precision of the populations. */
+enum lbm_precision { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16 = 2 };
+
+/* Status codes: 0 ok, > 0 informational, < 0 error. */
+enum lbm_status {
+    LBM_OK = 0,
+    LBM_NOT_CONVERGED = 1,   /* solve stopped at max_steps above tolerance            */
+    LBM_W_NONZERO_MEAN = 2,  /* force accepted, but its mean is not zero: no steady
+                                state exists (the mean of u is conserved, Sec. 7.2)   */
+    LBM_E_ARG = -1,          /* invalid argument (null pointer, size, tolerance)       */
+    LBM_E_MATERIAL = -2,     /* mu <= 0, lambda + mu <= 0, non-finite, or theta,
+                                omega outside the admissible range                    */
+    LBM_E_WORKSPACE = -3,    /* workspace / arena too small, or no room for a lattice */
+    LBM_E_HIP = -4,          /* a HIP runtime call failed                              */
+    LBM_E_DIVERGED = -5,     /* residual or populations became non-finite              */
+    LBM_E_STATE = -6         /* call not valid in the current state (e.g. no force)   */
+};
+
+/* ------------------------------------------------------------------------ */
+/* Single lattice                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Bytes of device workspace an nx x ny lattice needs at `precision`: two
+ * population buffers, the force, the FP64 displacement of the last residual
+ * check and reduction scratch.  With `with_polish` != 0 (FP32/FP16 only) the
+ * workspace also holds the FP64 state the solver switches to for the final
+ * polishing phase (lbm_set_polish).  Returns 0 for invalid sizes. */
+size_t lbm_workspace_bytes(int nx, int ny, int precision, int with_polish);
+
+/* Create a solver for a periodic nx x ny lattice (nx, ny >= 1; N = 1 or 2 are
+ * valid, neighbours then coincide).  `workspace` is caller-owned device memory
+ * of at least lbm_workspace_bytes(nx, ny, precision, with_polish) bytes,
+ * 256-byte aligned; `stream` is a hipStream_t (NULL = null stream).  The state
+ * starts at f = 0 (equilibrium for u0 = 0, Sec. 6.2).  The force must be set
+ * before stepping.  On success *out receives the handle (free with
+ * lbm_destroy).  Errors: LBM_E_ARG, LBM_E_WORKSPACE, LBM_E_HIP. */
+int lbm_create(int nx, int ny, int precision, int with_polish, void *workspace,
+               size_t workspace_bytes, void *stream, lbm_solver **out);
+
+/* Release the handle (never frees the workspace).  Waits for the stream. */
+int lbm_destroy(lbm_solver *s);
+
+/* Material in lattice units.  Sets the relaxation rates of Table "scheme":
+ * tau_11 = mu/theta, tau_s = 2K/(1+theta), tau_d = 2 mu/(1-theta),
+ * K = lambda + mu, omega = 1/(tau + 1/2) (Eq. relaxation_rate), with
+ * theta = 1/3 and omega_12 = omega_21 = omega_22 = 1 unless changed by
+ * lbm_set_rates.  Requires mu > 0 and lambda + mu > 0 (then every omega lies
+ * in (0, 2), the long-wave stability bound of Eq. stability); finite-k
+ * stability is not checked here.  Errors: LBM_E_MATERIAL. */
+int lbm_set_material(lbm_solver *s, double lame_lambda, double lame_mu);
+
+/* Optional: the free parameters of the collision (Sec. 3.3.2 remarks,
+ * App. C): theta in (0, 1) (third-order equilibrium constant) and the rates
+ * omega_12, omega_21, omega_22 in (0, 2).  Defaults 1/3, 1, 1, 1 (the fast
+ * path).  Re-derives the rates of the current material.  Errors:
+ * LBM_E_MATERIAL. */
+int lbm_set_rates(lbm_solver *s, double theta, double omega12, double omega21, double omega22);
+
+/* Body force g (per-step force in lattice units), FP64 device arrays
+ * [ny][nx].  Copied into the workspace (converted to the arithmetic type).
+ * Returns LBM_W_NONZERO_MEAN (force accepted unchanged) if
+ * |mean| > 1e-12 * rms for either component.  Errors: LBM_E_ARG, LBM_E_HIP. */
+int lbm_set_body_force(lbm_solver *s, const double *gx, const double *gy);
+
+/* f := 0 (u0 = 0 initialisation at equilibrium, Sec. 6.2), step count := 0,
+ * back to the creation precision. */
+int lbm_reset(lbm_solver *s);
+
+/* Advance nsteps >= 0 steps of Algorithm 1 (asynchronous on the stream). */
+int lbm_step(lbm_solver *s, long long nsteps);
+
+/* Pseudo-time stepping to steady state (blocking).  Steps and evaluates
+ * r(n) = ||u(n) - u(n-1)||_2 / ||u(n)||_2 (FP64 sums over all nodes and both
+ * components; 0 if both vanish) after every `check_every` >= 1 steps of this
+ * call, and stops at the first check with r <= tol (LBM_OK) or after
+ * max_steps steps of this call (LBM_NOT_CONVERGED).  The state left behind is
+ * f(n) with n = *steps_done steps taken by this call; *residual = the last
+ * r evaluated (NaN if none).  With a polish threshold set (lbm_set_polish), an
+ * FP32/FP16 solver switches to FP64 storage once r <= r_switch or r stops
+ * decreasing, and continues in FP64.  Errors: LBM_E_ARG, LBM_E_STATE (no
+ * force), LBM_E_DIVERGED (non-finite residual; state left readable),
+ * LBM_E_HIP. */
+int lbm_solve_to_tol(lbm_solver *s, double tol, long long max_steps, int check_every,
+                     long long *steps_done, double *residual);
+
+/* Enable the FP64 polishing phase of lbm_solve_to_tol for FP32/FP16
+ * storage: switch when r <= r_switch (0 disables).  Needs a workspace made
+ * with with_polish != 0.  Errors: LBM_E_STATE. */
+int lbm_set_polish(lbm_solver *s, double r_switch);
+
+/* Current storage precision (changes to LBM_FP64 after a polish switch). */
+int lbm_current_precision(const lbm_solver *s);
+
+/* Steps taken since creation or the last reset. */
+long long lbm_steps_done(const lbm_solver *s);
+
+/* Displacement u(n) = (mbar_10, mbar_01) = (m10 + gx/2, m01 + gy/2) of the
+ * current state (Table "solution"; Sec. 7.1), FP64 device arrays [ny][nx]. */
+int lbm_get_displacement(lbm_solver *s, double *ux, double *uy);
+
+/* Cauchy stress of the current state in lattice units from the bared
+ * second-order moments (Eq. compute_bared, Table "solution" without the
+ * 1/eps factor): sxx = -(mb_s + mb_d)/2, syy = -(mb_s - mb_d)/2,
+ * sxy = -mb_11, mb_a = (1 - omega_a/2) m_a.  FP64 device arrays. */
+int lbm_get_stress(lbm_solver *s, double *sxx, double *syy, double *sxy);
+
+/* Error norms of the current displacement against a reference field
+ * (FP64 device arrays [ny][nx]); out[4] (host) = { sum |e_i|_2^2,
+ * sum |ref_i|_2^2, max |e_i|_inf, max |ref_i|_inf } with e = u - ref: the
+ * grid norms of Sec. 7.1 before the dx weighting.  Blocking. */
+int lbm_error_norms(lbm_solver *s, const double *ux_ref, const double *uy_ref, double out[4]);
+
+/* Checkpoint / restart: the pre-collision populations f(n) as FP64 device
+ * arrays [8][ny][nx] (paper order, unscaled).  set leaves the step count
+ * unchanged. */
+int lbm_get_populations(lbm_solver *s, double *f);
+int lbm_set_populations(lbm_solver *s, const double *f);
+
+/* Tile shape of the step kernel: tile width 2^bx_log2 threads (0..8, the
+ * height is 256 >> bx_log2 threads) and rows_per_thread in {1, 2, 4}.
+ * Used by the autotuner; defaults are chosen per precision. */
+int lbm_set_tile(lbm_solver *s, int bx_log2, int rows_per_thread);
+
+/* Diagnostic: nsteps of streaming alone (no collision), for bit-exact checks
+ * of the periodic index arithmetic (Eq. streaming, Sec. 6.1). */
+int lbm_debug_stream_only(lbm_solver *s, long long nsteps);
+
+/* Message for the last failed call on this handle (never NULL).  With a NULL
+ * handle: the last failure of lbm_create / lbm_batch_create in this thread. */
+const char *lbm_last_error(const lbm_solver *s);
+
+/* ------------------------------------------------------------------------ */
+/* Batches: many independent lattices of uneven size and material stepped    */
+/* together, one persistent launch per step over a (lattice, tile) work list. */
+/* ------------------------------------------------------------------------ */
+
+/* Bytes of arena one lattice occupies in a batch at `precision` (with
+ * `with_polish`: plus its FP64 polish state).  Used for admission. */
+size_t lbm_batch_slot_bytes(int nx, int ny, int precision, int with_polish);
+
+/* Create a batch over a caller-owned device arena (256-byte aligned) that
+ * holds the lattices and the batch bookkeeping; up to max_slots lattices.
+ * Errors: LBM_E_ARG, LBM_E_WORKSPACE, LBM_E_HIP. */
+int lbm_batch_create(int max_slots, void *arena, size_t arena_bytes, void *stream,
+                     lbm_batch **out);
+int lbm_batch_destroy(lbm_batch *b);
+
+/* Add a lattice: material (lattice units), FP64 device force arrays [ny][nx]
+ * (copied), storage precision, optional polish reservation.  The lattice
+ * starts at f = 0 and joins the next step.  *slot receives its id.
+ * LBM_E_WORKSPACE if the arena has no room (nothing changed). */
+int lbm_batch_add(lbm_batch *b, int nx, int ny, int precision, int with_polish,
+                  double lame_lambda, double lame_mu, const double *gx, const double *gy,
+                  int *slot);
+
+/* Remove a lattice and return its memory to the arena. */
+int lbm_batch_remove(lbm_batch *b, int slot);
+
+/* Advance every active lattice by nsteps >= 1.  With check != 0 the last two
+ * steps also evaluate each lattice's residual r(n) (as in lbm_solve_to_tol)
+ * at its step count after the call; read them with lbm_batch_residuals.
+ * Chunks are replayed from captured HIP graphs.  Asynchronous. */
+int lbm_batch_step(lbm_batch *b, long long nsteps, int check);
+
+/* Blocking: residual of the last checked chunk and step count per slot,
+ * written for slots 0..max_slots-1 (NaN / -1 for unused slots). */
+int lbm_batch_residuals(lbm_batch *b, double *r_host, long long *steps_host);
+
+/* Switch a FP32/FP16 lattice to FP64 storage (polish phase); needs its
+ * polish reservation. */
+int lbm_batch_promote(lbm_batch *b, int slot);
+
+/* Current displacement of one lattice (FP64 device arrays [ny][nx]). */
+int lbm_batch_get_displacement(lbm_batch *b, int slot, double *ux, double *uy);
+
+/* Tile shape for all lattices of the batch (see lbm_set_tile). */
+int lbm_batch_set_tile(lbm_batch *b, int bx_log2, int rows_per_thread);
+
+/* Number of active lattices, and arena bytes in use / free (largest hole). */
+int lbm_batch_info(const lbm_batch *b, int *active, size_t *used_bytes, size_t *largest_free);
+
+const char *lbm_batch_last_error(const lbm_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,570 @@
+// Batches of independent periodic lattices (uneven sizes and materials)
+// stepped together: one persistent launch per storage precision and step
+// walks a work list of (lattice, tile) items; per-lattice arithmetic is the
+// single-lattice kernel's, so a lattice gives the same populations alone
+// and in a batch.  Lattices live in a caller-owned device arena managed by a
+// first-fit allocator; chunks of steps are replayed from captured HIP graphs
+// whose kernel arguments (descriptor table, work list, per-precision item
+// ranges) stay valid while lattices join and leave.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_device.hpp"
+#include "lbm_host.hpp"
+
+using namespace lbm;
+using namespace lbm_host;
+
+namespace {
+
+thread_local std::string g_batch_create_error;
+
+// First-fit allocator over [0, size) with coalescing of free neighbours.
+class Arena {
+  public:
+    void init(size_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+        size_ = size;
+        used_ = 0;
+    }
+    // returns offset or SIZE_MAX
+    size_t alloc(size_t bytes) {
+        bytes = al(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const size_t off = it->first, rem = it->second - bytes;
+                free_.erase(it);
+                if (rem) free_[off + bytes] = rem;
+                used_ += bytes;
+                return off;
+            }
+        }
+        return SIZE_MAX;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = al(bytes);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t used() const { return used_; }
+    size_t largest() const {
+        size_t m = 0;
+        for (auto& kv : free_) m = std::max(m, kv.second);
+        return m;
+    }
+
+  private:
+    std::map<size_t, size_t> free_;
+    size_t size_ = 0, used_ = 0;
+};
+
+struct BSlot {
+    bool active = false;
+    Lattice L;
+    size_t off = 0, bytes = 0;
+    long long steps = 0;
+    long long checked_phase = -1;  // phase value right after the last check launch
+    int first = 0, count = 0;
+};
+
+// Work-list entry per slot, uploaded to build the items on the device.
+struct SlotRow {
+    int slot, first, tiles_x, count;
+};
+
+__global__ __launch_bounds__(kBlock) void k_build_items_all(Item* items, const SlotRow* rows,
+                                                            int nrows) {
+    if ((int)blockIdx.y >= nrows) return;
+    const SlotRow r = rows[blockIdx.y];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < r.count; i += gridDim.x * kBlock) {
+        Item it;
+        it.slot = r.slot;
+        it.tx = i % r.tiles_x;
+        it.ty = i / r.tiles_x;
+        it.pad_ = 0;
+        items[r.first + i] = it;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_set_counts(int* first, int* count, const SlotRow* rows,
+                                                       int nrows, int nslots) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= nslots) return;
+    int f = 0, c = 0;
+    for (int i = 0; i < nrows; ++i)
+        if (rows[i].slot == s) {
+            f = rows[i].first;
+            c = rows[i].count;
+        }
+    first[s] = f;
+    count[s] = c;
+}
+
+}  // namespace
+
+struct lbm_batch {
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    int cus = 256;
+    char* base = nullptr;
+    size_t bytes = 0;
+    int max_slots = 0;
+    // bookkeeping regions (device)
+    SlotDesc* d_desc = nullptr;
+    int* d_first = nullptr;
+    int* d_count = nullptr;
+    int* d_range = nullptr;  // 3 x {begin, end}: one range per precision
+    double* d_result = nullptr;
+    Item* d_items = nullptr;
+    double* d_partial = nullptr;
+    SlotRow* d_rows = nullptr;
+    double* d_red = nullptr;  // kErrBlocks x 4 + 8 doubles of reduction scratch
+    long long cap_items = 0;
+    // host
+    SlotRow* h_rows = nullptr;  // pinned staging (max_slots rows + 3 ranges)
+    double* h_result = nullptr;  // pinned, 4 x max_slots
+    size_t heap_off = 0;
+    Arena arena;
+    std::vector<BSlot> slots;
+    int range_host[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    long long phase = 0;
+    int bx_log2 = 6, vy = 1;
+    std::string err;
+    std::map<std::tuple<long long, int, int, unsigned, unsigned, unsigned>, hipGraphExec_t> graphs;
+
+    int fail(int code, const std::string& m) {
+        err = m;
+        return code;
+    }
+    int hip_fail(hipError_t e, const char* where) {
+        err = std::string(where) + ": " + hipGetErrorString(e);
+        return LBM_E_HIP;
+    }
+    void drop_graphs() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
+    int sel(const BSlot& s) const { return s.L.cur ^ (int)(phase & 1); }
+
+    unsigned grid_for(int prec) const {
+        const int n = range_host[prec][1] - range_host[prec][0];
+        if (n <= 0) return 0;
+        unsigned g = 8;
+        while (g < (unsigned)n && g < (unsigned)cus * 8) g <<= 1;
+        return std::min(g, (unsigned)cus * 8 / 8 * 8);
+    }
+
+    hipError_t write_desc(int slot) {
+        hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(1), 0, stream, d_desc + slot,
+                           slots[slot].L.desc());
+        return hipGetLastError();
+    }
+
+    // Recompute the work list: items grouped by precision, then by slot id.
+    int rebuild() {
+        long long total = 0;
+        int nrows = 0;
+        hipError_t e = hipStreamSynchronize(stream);  // staging buffer reuse
+        if (e != hipSuccess) return hip_fail(e, "rebuild");
+        for (int p = 0; p < 3; ++p) {
+            range_host[p][0] = (int)total;
+            for (int i = 0; i < max_slots; ++i) {
+                BSlot& s = slots[i];
+                if (!s.active || s.L.prec != p) continue;
+                s.L.bx_log2 = bx_log2;
+                s.L.vy = vy;
+                s.first = (int)total;
+                s.count = s.L.nitems();
+                total += s.count;
+                h_rows[nrows++] = SlotRow{i, s.first, s.L.tiles_x(), s.count};
+            }
+            range_host[p][1] = (int)total;
+        }
+        if (total > cap_items) return fail(LBM_E_WORKSPACE, "work list exceeds batch capacity");
+        int* rng = reinterpret_cast<int*>(h_rows + max_slots);
+        for (int p = 0; p < 3; ++p) {
+            rng[2 * p] = range_host[p][0];
+            rng[2 * p + 1] = range_host[p][1];
+        }
+        e = hipMemcpyAsync(d_rows, h_rows, (max_slots + 2) * sizeof(SlotRow),
+                           hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return hip_fail(e, "rebuild upload");
+        if (nrows > 0)
+            hipLaunchKernelGGL(k_build_items_all, dim3(64, nrows), dim3(kBlock), 0, stream, d_items,
+                               d_rows, nrows);
+        hipLaunchKernelGGL(k_set_counts, dim3(blocks_for(max_slots)), dim3(kBlock), 0, stream,
+                           d_first, d_count, d_rows, nrows, max_slots);
+        e = hipMemcpyAsync(d_range, rng, 6 * sizeof(int), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "rebuild");
+        for (int i = 0; i < max_slots; ++i)
+            if (slots[i].active && (e = write_desc(i)) != hipSuccess) return hip_fail(e, "desc");
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "rebuild");
+        return LBM_OK;
+    }
+
+    StepLaunch args(int prec, int flip) const {
+        StepLaunch a;
+        a.slots = d_desc;
+        a.items = d_items;
+        a.range = d_range + 2 * prec;
+        a.partial = d_partial;
+        a.flip = flip;
+        return a;
+    }
+
+    hipError_t enqueue(long long nsteps, bool check, hipStream_t st, long long ph) {
+        hipError_t e = hipSuccess;
+        for (long long i = 0; i < nsteps; ++i, ++ph) {
+            const int mode = !check ? kPlain
+                                    : (i == nsteps - 1 ? kCheck : (i == nsteps - 2 ? kWriteU : kPlain));
+            for (int p = 0; p < 3; ++p) {
+                const unsigned g = grid_for(p);
+                if (!g) continue;
+                e = launch_step(p, mode, false, vy, g, st, args(p, (int)(ph & 1)));
+                if (e != hipSuccess) return e;
+            }
+        }
+        if (check) {
+            FinalizeLaunch F;
+            F.first = d_first;
+            F.count = d_count;
+            F.partial = d_partial;
+            F.result = d_result;
+            F.nslots = max_slots;
+            hipLaunchKernelGGL(k_finalize, dim3(max_slots), dim3(kBlock), 0, st, F);
+            e = hipGetLastError();
+        }
+        return e;
+    }
+};
+
+extern "C" {
+
+size_t lbm_batch_slot_bytes(int nx, int ny, int precision, int with_polish) {
+    if (nx < 1 || ny < 1 || !valid_prec(precision)) return 0;
+    return lattice_bytes((long long)nx * ny, precision, with_polish != 0);
+}
+
+int lbm_batch_create(int max_slots, void* arena, size_t arena_bytes, void* stream,
+                     lbm_batch** out) {
+    if (!out || max_slots < 1) {
+        g_batch_create_error = "batch_create: invalid arguments";
+        return LBM_E_ARG;
+    }
+    *out = nullptr;
+    if (!arena || (reinterpret_cast<uintptr_t>(arena) % kAlign)) {
+        g_batch_create_error = "batch_create: arena NULL or not 256-byte aligned";
+        return LBM_E_WORKSPACE;
+    }
+    lbm_batch* b = new lbm_batch();
+    b->stream = reinterpret_cast<hipStream_t>(stream);
+    b->max_slots = max_slots;
+    b->base = reinterpret_cast<char*>(arena);
+    b->bytes = arena_bytes;
+    // work-list capacity: one item per 256 sites of the smallest per-site
+    // footprint (half storage, 56 B/site) plus ragged tiles of every slot
+    b->cap_items = (long long)(arena_bytes / (56 * 256)) + (long long)max_slots * 1024 + 1024;
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        size_t o = off;
+        off += al(n);
+        return b->base + o;
+    };
+    b->d_desc = reinterpret_cast<SlotDesc*>(take(max_slots * sizeof(SlotDesc)));
+    b->d_first = reinterpret_cast<int*>(take(max_slots * sizeof(int)));
+    b->d_count = reinterpret_cast<int*>(take(max_slots * sizeof(int)));
+    b->d_range = reinterpret_cast<int*>(take(6 * sizeof(int)));
+    b->d_result = reinterpret_cast<double*>(take(4 * max_slots * sizeof(double)));
+    b->d_rows = reinterpret_cast<SlotRow*>(take((max_slots + 2) * sizeof(SlotRow)));
+    b->d_red = reinterpret_cast<double*>(take((kErrBlocks * 4 + 8) * sizeof(double)));
+    b->d_items = reinterpret_cast<Item*>(take(b->cap_items * sizeof(Item)));
+    b->d_partial = reinterpret_cast<double*>(take(b->cap_items * 3 * sizeof(double)));
+    if (off > arena_bytes) {
+        g_batch_create_error = "batch_create: arena smaller than the batch bookkeeping (" +
+                               std::to_string(off) + " bytes)";
+        delete b;
+        return LBM_E_WORKSPACE;
+    }
+    b->heap_off = off;
+    b->arena.init(arena_bytes - off);
+    b->slots.resize(max_slots);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&b->h_rows), (max_slots + 2) * sizeof(SlotRow),
+                          hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&b->h_result), 4 * max_slots * sizeof(double),
+                          hipHostMallocDefault);
+    if (e == hipSuccess) e = zero_bytes(b->d_result, 4 * max_slots * sizeof(double), b->stream);
+    if (e != hipSuccess) {
+        g_batch_create_error = std::string("batch_create: ") + hipGetErrorString(e);
+        if (b->cap) (void)hipStreamDestroy(b->cap);
+        if (b->h_rows) (void)hipHostFree(b->h_rows);
+        if (b->h_result) (void)hipHostFree(b->h_result);
+        delete b;
+        return LBM_E_HIP;
+    }
+    int rc = b->rebuild();
+    if (rc != LBM_OK) {
+        g_batch_create_error = b->err;
+        lbm_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch* b) {
+    if (!b) return LBM_E_ARG;
+    (void)hipStreamSynchronize(b->stream);
+    b->drop_graphs();
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->h_rows) (void)hipHostFree(b->h_rows);
+    if (b->h_result) (void)hipHostFree(b->h_result);
+    delete b;
+    return LBM_OK;
+}
+
+int lbm_batch_add(lbm_batch* b, int nx, int ny, int precision, int with_polish, double lam,
+                  double mu, const double* gx, const double* gy, int* slot) {
+    if (!b) return LBM_E_ARG;
+    if (nx < 1 || ny < 1 || !valid_prec(precision) || !gx || !gy || !slot ||
+        (long long)nx * ny > (1LL << 31))
+        return b->fail(LBM_E_ARG, "batch_add: invalid size, precision or NULL pointer");
+    Rates r;
+    if (!material_rates(lam, mu, r, b->err)) return LBM_E_MATERIAL;
+    int id = -1;
+    for (int i = 0; i < b->max_slots; ++i)
+        if (!b->slots[i].active) {
+            id = i;
+            break;
+        }
+    if (id < 0) return b->fail(LBM_E_WORKSPACE, "batch_add: all slots in use");
+    const long long N = (long long)nx * ny;
+    const size_t need = lattice_bytes(N, precision, with_polish != 0);
+    long long items_now = b->range_host[2][1];
+    if (items_now + max_items(nx, ny) > b->cap_items)
+        return b->fail(LBM_E_WORKSPACE, "batch_add: work list full");
+    const size_t off = b->arena.alloc(need);
+    if (off == SIZE_MAX) return b->fail(LBM_E_WORKSPACE, "batch_add: arena has no room");
+    BSlot& s = b->slots[id];
+    s = BSlot();
+    s.off = off;
+    s.bytes = need;
+    Lattice& L = s.L;
+    L.nx = nx;
+    L.ny = ny;
+    L.N = N;
+    L.prec0 = L.prec = precision;
+    L.polish = with_polish != 0 && precision != LBM_FP64;
+    L.rates = r;
+    L.lam = lam;
+    L.mu = mu;
+    L.has_material = L.has_force = true;
+    carve_lattice(b->base + b->heap_off + off, N, precision, L.polish, L.mem);
+    hipError_t e = upload_force(L, gx, gy, b->stream);
+    if (e == hipSuccess) e = zero_bytes(L.mem.buf[0], 8 * N * elem_bytes(precision), b->stream);
+    if (e == hipSuccess) e = zero_bytes(L.mem.u, 2 * N * 8, b->stream);
+    if (e != hipSuccess) {
+        b->arena.release(off, need);
+        s = BSlot();
+        return b->hip_fail(e, "batch_add");
+    }
+    if (precision == LBM_FP16) {
+        // initial scale from max |g| (blocking two-stage reduction)
+        hipLaunchKernelGGL(k_force_stats, dim3(kErrBlocks), dim3(kBlock), 0, b->stream, gx, gy, N,
+                           b->d_red);
+        hipLaunchKernelGGL(k_reduce4<kForceMask>, dim3(1), dim3(kBlock), 0, b->stream, b->d_red,
+                           kErrBlocks, b->d_red + 4 * kErrBlocks);
+        e = hipMemcpyAsync(b->h_result, b->d_red + 4 * kErrBlocks, 4 * 8, hipMemcpyDeviceToHost,
+                           b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) {
+            b->arena.release(off, need);
+            s = BSlot();
+            return b->hip_fail(e, "batch_add force stats");
+        }
+        L.gmax = b->h_result[3];
+        L.e_scale = initial_half_exponent(L, L.gmax);
+    }
+    // the next launch reads buf[cur ^ (phase & 1)] = buf[0]
+    L.cur = (int)(b->phase & 1);
+    s.active = true;
+    s.steps = 0;
+    s.checked_phase = -1;
+    int rc = b->rebuild();
+    if (rc != LBM_OK) {
+        b->arena.release(off, need);
+        s = BSlot();
+        b->rebuild();
+        return rc;
+    }
+    *slot = id;
+    return LBM_OK;
+}
+
+int lbm_batch_remove(lbm_batch* b, int slot) {
+    if (!b) return LBM_E_ARG;
+    if (slot < 0 || slot >= b->max_slots || !b->slots[slot].active)
+        return b->fail(LBM_E_ARG, "batch_remove: no such slot");
+    (void)hipStreamSynchronize(b->stream);
+    BSlot& s = b->slots[slot];
+    b->arena.release(s.off, s.bytes);
+    s = BSlot();
+    return b->rebuild();
+}
+
+int lbm_batch_set_tile(lbm_batch* b, int bx_log2, int rows_per_thread) {
+    if (!b) return LBM_E_ARG;
+    if (bx_log2 < 3 || bx_log2 > 8 ||
+        !(rows_per_thread == 1 || rows_per_thread == 2 || rows_per_thread == 4))
+        return b->fail(LBM_E_ARG, "batch_set_tile: bx_log2 in 3..8, rows_per_thread in {1,2,4}");
+    b->bx_log2 = bx_log2;
+    b->vy = rows_per_thread;
+    b->drop_graphs();
+    return b->rebuild();
+}
+
+int lbm_batch_step(lbm_batch* b, long long nsteps, int check) {
+    if (!b) return LBM_E_ARG;
+    if (nsteps < 1 || (check && nsteps < 2))
+        return b->fail(LBM_E_ARG, "batch_step: nsteps >= 1 (>= 2 with check)");
+    if (b->range_host[2][1] == 0) return LBM_OK;  // nothing active
+    hipError_t e;
+    const int flip0 = (int)(b->phase & 1);
+    if (nsteps >= 4) {
+        auto key = std::make_tuple(nsteps, check ? 1 : 0, flip0, b->grid_for(0), b->grid_for(1),
+                                   b->grid_for(2));
+        auto it = b->graphs.find(key);
+        if (it == b->graphs.end()) {
+            if (b->graphs.size() > 16) b->drop_graphs();
+            hipGraph_t gr;
+            if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return b->hip_fail(e, "capture");
+            hipError_t le = b->enqueue(nsteps, check != 0, b->cap, b->phase);
+            if ((e = hipStreamEndCapture(b->cap, &gr)) != hipSuccess) return b->hip_fail(e, "capture");
+            if (le != hipSuccess) {
+                (void)hipGraphDestroy(gr);
+                return b->hip_fail(le, "capture launch");
+            }
+            hipGraphExec_t ex;
+            e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            if (e != hipSuccess) return b->hip_fail(e, "instantiate");
+            it = b->graphs.emplace(key, ex).first;
+        }
+        if ((e = hipGraphLaunch(it->second, b->stream)) != hipSuccess)
+            return b->hip_fail(e, "graph launch");
+    } else {
+        if ((e = b->enqueue(nsteps, check != 0, b->stream, b->phase)) != hipSuccess)
+            return b->hip_fail(e, "batch_step");
+    }
+    b->phase += nsteps;
+    for (auto& s : b->slots)
+        if (s.active) {
+            s.steps += nsteps;
+            if (check) s.checked_phase = b->phase;
+        }
+    return LBM_OK;
+}
+
+int lbm_batch_residuals(lbm_batch* b, double* r_host, long long* steps_host) {
+    if (!b) return LBM_E_ARG;
+    if (!r_host || !steps_host) return b->fail(LBM_E_ARG, "batch_residuals: NULL output");
+    hipError_t e = hipMemcpyAsync(b->h_result, b->d_result, 4 * b->max_slots * sizeof(double),
+                                  hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return b->hip_fail(e, "batch_residuals");
+    for (int i = 0; i < b->max_slots; ++i) {
+        const BSlot& s = b->slots[i];
+        steps_host[i] = s.active ? s.steps : -1;
+        if (!s.active || s.checked_phase != b->phase) {
+            r_host[i] = NAN;
+            continue;
+        }
+        const double d2 = b->h_result[4 * i], u2 = b->h_result[4 * i + 1];
+        double r = (u2 == 0.0) ? (d2 == 0.0 ? 0.0 : INFINITY) : std::sqrt(d2 / u2);
+        if (d2 != d2 || u2 != u2 || !std::isfinite(u2)) r = NAN;
+        r_host[i] = r;
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_promote(lbm_batch* b, int slot) {
+    if (!b) return LBM_E_ARG;
+    if (slot < 0 || slot >= b->max_slots || !b->slots[slot].active)
+        return b->fail(LBM_E_ARG, "batch_promote: no such slot");
+    BSlot& s = b->slots[slot];
+    Lattice& L = s.L;
+    if (L.prec == LBM_FP64) return LBM_OK;
+    if (!L.polish) return b->fail(LBM_E_STATE, "batch_promote: lattice added without polish");
+    const int sl = b->sel(s);
+    const long long n = 8 * L.N;
+    const double factor = (L.prec == LBM_FP16) ? std::ldexp(1.0, L.e_scale) : 1.0;
+    if (L.prec == LBM_FP32)
+        hipLaunchKernelGGL((k_recast<float, double>), dim3(blocks_for(n)), dim3(kBlock), 0,
+                           b->stream, reinterpret_cast<const float*>(L.mem.buf[sl]),
+                           reinterpret_cast<double*>(L.mem.pbuf[0]), n, factor);
+    else
+        hipLaunchKernelGGL((k_recast<__half, double>), dim3(blocks_for(n)), dim3(kBlock), 0,
+                           b->stream, reinterpret_cast<const __half*>(L.mem.buf[sl]),
+                           reinterpret_cast<double*>(L.mem.pbuf[0]), n, factor);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return b->hip_fail(e, "batch_promote");
+    L.prec = LBM_FP64;
+    L.cur = (int)(b->phase & 1);
+    return b->rebuild();
+}
+
+int lbm_batch_get_displacement(lbm_batch* b, int slot, double* ux, double* uy) {
+    if (!b) return LBM_E_ARG;
+    if (slot < 0 || slot >= b->max_slots || !b->slots[slot].active || !ux || !uy)
+        return b->fail(LBM_E_ARG, "batch_get_displacement: no such slot or NULL output");
+    const BSlot& s = b->slots[slot];
+    hipError_t e = extract_u(s.L.prec, s.L.desc(), b->sel(s), ux, uy, b->stream);
+    if (e != hipSuccess) return b->hip_fail(e, "batch_get_displacement");
+    return LBM_OK;
+}
+
+int lbm_batch_info(const lbm_batch* b, int* active, size_t* used_bytes, size_t* largest_free) {
+    if (!b) return LBM_E_ARG;
+    int a = 0;
+    for (auto& s : b->slots) a += s.active ? 1 : 0;
+    if (active) *active = a;
+    if (used_bytes) *used_bytes = b->arena.used();
+    if (largest_free) *largest_free = b->arena.largest();
+    return LBM_OK;
+}
+
+const char* lbm_batch_last_error(const lbm_batch* b) {
+    if (!b) return g_batch_create_error.c_str();
+    return b->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,591 @@
+// Host side of the C ABI declared in include/lbm.h: single-lattice solvers
+// and batches of lattices sharing one persistent step launch.
+//
+// Scheme: Boolakee, Geier, De Lorenzis, arXiv 2208.14870 (Algorithm 1,
+// Table "scheme").  Every step of the method runs in the kernels of
+// lbm_device.hpp; this file owns handles, validation, memory layout inside
+// caller-owned workspaces, work lists, HIP graph capture of step chunks and
+// the pseudo-time convergence loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_device.hpp"
+#include "lbm_host.hpp"
+
+using namespace lbm;
+using namespace lbm_host;
+
+namespace {
+thread_local std::string g_create_error;
+}  // namespace
+
+// ===========================================================================
+// single-lattice solver
+// ===========================================================================
+struct lbm_solver {
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;  // private stream used only for graph capture
+    int cus = 256;
+    Lattice L;
+    // workspace regions
+    SlotDesc* d_desc = nullptr;
+    Item* d_items = nullptr;
+    int* d_range = nullptr;  // {0, nitems}
+    int* d_first = nullptr;
+    int* d_count = nullptr;
+    double* d_partial = nullptr;
+    double* d_result = nullptr;
+    double* d_red = nullptr;  // kErrBlocks x 4 + 4
+    double* h_result = nullptr;  // pinned, 8 doubles
+    long long max_items_ = 0;
+    int nitems = 0;
+    unsigned grid = 0;
+    long long phase = 0;  // launches since the descriptor was written
+    long long steps = 0;
+    double r_switch = 0.0;
+    std::string err;
+    std::map<std::tuple<long long, int, int>, hipGraphExec_t> graphs;
+
+    int fail(int code, const std::string& m) {
+        err = m;
+        return code;
+    }
+    int hip_fail(hipError_t e, const char* where) {
+        err = std::string(where) + ": " + hipGetErrorString(e);
+        return LBM_E_HIP;
+    }
+    int sel() const { return L.cur ^ (int)(phase & 1); }
+
+    void drop_graphs() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
+
+    // Rewrite descriptor + work list (after any change of layout or parameters).
+    int sync_desc() {
+        // keep the state buffer: fold the phase parity into cur
+        L.cur = sel();
+        phase = 0;
+        SlotDesc d = L.desc();
+        nitems = L.nitems();
+        if (nitems > max_items_) return fail(LBM_E_WORKSPACE, "tile shape exceeds work-list space");
+        hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(1), 0, stream, d_desc, d);
+        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, stream, d_range, 0);
+        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, stream, d_range + 1, nitems);
+        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, stream, d_first, 0);
+        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, stream, d_count, nitems);
+        hipLaunchKernelGGL(k_build_items, dim3(blocks_for(nitems)), dim3(kBlock), 0, stream,
+                           d_items, 0, 0, d.tiles_x, nitems);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+        const unsigned gmax = (unsigned)cus * 8;
+        unsigned g = (unsigned)((nitems + 7) / 8 * 8);
+        grid = std::max(8u, std::min(g, gmax));
+        drop_graphs();
+        return LBM_OK;
+    }
+
+    StepLaunch launch_args(int flip) const {
+        StepLaunch a;
+        a.slots = d_desc;
+        a.items = d_items;
+        a.range = d_range;
+        a.partial = d_partial;
+        a.flip = flip;
+        return a;
+    }
+
+    hipError_t enqueue_one(int mode, hipStream_t st, long long& ph) {
+        hipError_t e = launch_step(L.prec, mode, L.general(), L.general() ? 1 : L.vy, grid, st,
+                                   launch_args((int)(ph & 1)));
+        ++ph;
+        return e;
+    }
+
+    hipError_t enqueue_finalize(hipStream_t st) {
+        FinalizeLaunch F;
+        F.first = d_first;
+        F.count = d_count;
+        F.partial = d_partial;
+        F.result = d_result;
+        F.nslots = 1;
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, F);
+        return hipGetLastError();
+    }
+
+    // Enqueue `nplain` plain steps, then (optionally) a writeU step, then
+    // (optionally) a check step + finalize.  Long runs are replayed from
+    // captured graphs.
+    hipError_t enqueue_chunk(long long nplain, bool writeu, bool check) {
+        const long long kGraphChunk = 64;
+        hipError_t e;
+        while (nplain >= kGraphChunk) {
+            if ((e = run_graph(kGraphChunk, false, false)) != hipSuccess) return e;
+            nplain -= kGraphChunk;
+        }
+        if (nplain > 0 || writeu || check) {
+            if (nplain + (writeu ? 1 : 0) + (check ? 1 : 0) >= 4)
+                return run_graph(nplain, writeu, check);
+            long long ph = phase;
+            for (long long i = 0; i < nplain; ++i)
+                if ((e = enqueue_one(kPlain, stream, ph)) != hipSuccess) return e;
+            if (writeu && (e = enqueue_one(kWriteU, stream, ph)) != hipSuccess) return e;
+            if (check) {
+                if ((e = enqueue_one(kCheck, stream, ph)) != hipSuccess) return e;
+                if ((e = enqueue_finalize(stream)) != hipSuccess) return e;
+            }
+            phase = ph;
+        }
+        return hipSuccess;
+    }
+
+    hipError_t run_graph(long long nplain, bool writeu, bool check) {
+        const int flip0 = (int)(phase & 1);
+        const int kind = (writeu ? 1 : 0) | (check ? 2 : 0);
+        auto key = std::make_tuple(nplain, kind, flip0);
+        auto it = graphs.find(key);
+        hipError_t e;
+        if (it == graphs.end()) {
+            if (graphs.size() > 16) drop_graphs();
+            hipGraph_t gr;
+            if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return e;
+            long long ph = phase;
+            for (long long i = 0; i < nplain; ++i) (void)enqueue_one(kPlain, cap, ph);
+            if (writeu) (void)enqueue_one(kWriteU, cap, ph);
+            if (check) {
+                (void)enqueue_one(kCheck, cap, ph);
+                (void)enqueue_finalize(cap);
+            }
+            hipError_t le = hipGetLastError();
+            if ((e = hipStreamEndCapture(cap, &gr)) != hipSuccess) return e;
+            if (le != hipSuccess) {
+                (void)hipGraphDestroy(gr);
+                return le;
+            }
+            hipGraphExec_t ex;
+            e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            if (e != hipSuccess) return e;
+            it = graphs.emplace(key, ex).first;
+        }
+        if ((e = hipGraphLaunch(it->second, stream)) != hipSuccess) return e;
+        phase += nplain + (writeu ? 1 : 0) + (check ? 1 : 0);
+        return hipSuccess;
+    }
+};
+
+extern "C" {
+
+size_t lbm_workspace_bytes(int nx, int ny, int precision, int with_polish) {
+    if (nx < 1 || ny < 1 || !valid_prec(precision)) return 0;
+    const long long N = (long long)nx * ny;
+    const long long mi = max_items(nx, ny);
+    size_t b = al(sizeof(SlotDesc)) + 4 * al(sizeof(int)) + al(4 * 8) + al(mi * sizeof(Item)) +
+               al(mi * 3 * 8) + al((kErrBlocks * 4 + 8) * 8);
+    b += lattice_bytes(N, precision, with_polish != 0);
+    return b;
+}
+
+int lbm_create(int nx, int ny, int precision, int with_polish, void* workspace,
+               size_t workspace_bytes, void* stream, lbm_solver** out) {
+    if (!out) {
+        g_create_error = "lbm_create: out is NULL";
+        return LBM_E_ARG;
+    }
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || !valid_prec(precision) || (long long)nx * ny > (1LL << 31)) {
+        g_create_error = "lbm_create: invalid size or precision";
+        return LBM_E_ARG;
+    }
+    const size_t need = lbm_workspace_bytes(nx, ny, precision, with_polish);
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) % kAlign)) {
+        g_create_error = "lbm_create: workspace NULL, misaligned or smaller than " +
+                         std::to_string(need) + " bytes";
+        return LBM_E_WORKSPACE;
+    }
+    lbm_solver* s = new lbm_solver();
+    s->stream = reinterpret_cast<hipStream_t>(stream);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->h_result), 8 * sizeof(double),
+                                           hipHostMallocDefault);
+    if (e != hipSuccess) {
+        g_create_error = std::string("lbm_create: ") + hipGetErrorString(e);
+        if (s->cap) (void)hipStreamDestroy(s->cap);
+        delete s;
+        return LBM_E_HIP;
+    }
+    Lattice& L = s->L;
+    L.nx = nx;
+    L.ny = ny;
+    L.N = (long long)nx * ny;
+    L.prec0 = L.prec = precision;
+    L.polish = with_polish != 0 && precision != LBM_FP64;
+    L.bx_log2 = default_bx_log2(precision, nx);
+    L.vy = 1;
+    char* base = reinterpret_cast<char*>(workspace);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base + off;
+        off += al(bytes);
+        return p;
+    };
+    s->max_items_ = max_items(nx, ny);
+    s->d_desc = reinterpret_cast<SlotDesc*>(take(sizeof(SlotDesc)));
+    s->d_range = reinterpret_cast<int*>(take(2 * sizeof(int)));
+    s->d_first = reinterpret_cast<int*>(take(sizeof(int)));
+    s->d_count = reinterpret_cast<int*>(take(sizeof(int)));
+    take(sizeof(int));
+    s->d_result = reinterpret_cast<double*>(take(4 * 8));
+    s->d_items = reinterpret_cast<Item*>(take(s->max_items_ * sizeof(Item)));
+    s->d_partial = reinterpret_cast<double*>(take(s->max_items_ * 3 * 8));
+    s->d_red = reinterpret_cast<double*>(take((kErrBlocks * 4 + 8) * 8));
+    carve_lattice(base + off, L.N, precision, L.polish, L.mem);
+    int rc = lbm_reset(s);
+    if (rc != LBM_OK) {
+        g_create_error = s->err;
+        lbm_destroy(s);
+        return rc;
+    }
+    *out = s;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_solver* s) {
+    if (!s) return LBM_E_ARG;
+    (void)hipStreamSynchronize(s->stream);
+    s->drop_graphs();
+    if (s->cap) (void)hipStreamDestroy(s->cap);
+    if (s->h_result) (void)hipHostFree(s->h_result);
+    delete s;
+    return LBM_OK;
+}
+
+int lbm_reset(lbm_solver* s) {
+    if (!s) return LBM_E_ARG;
+    Lattice& L = s->L;
+    L.prec = L.prec0;
+    L.cur = 0;
+    s->phase = 0;
+    s->steps = 0;
+    hipError_t e = zero_bytes(L.mem.buf[0], 8 * L.N * elem_bytes(L.prec0), s->stream);
+    if (e == hipSuccess) e = zero_bytes(L.mem.u, 2 * L.N * 8, s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "lbm_reset");
+    return s->sync_desc();
+}
+
+int lbm_set_material(lbm_solver* s, double lame_lambda, double lame_mu) {
+    if (!s) return LBM_E_ARG;
+    Rates r = s->L.rates;
+    if (!material_rates(lame_lambda, lame_mu, r, s->err)) return LBM_E_MATERIAL;
+    s->L.rates = r;
+    s->L.lam = lame_lambda;
+    s->L.mu = lame_mu;
+    s->L.has_material = true;
+    if (s->L.prec0 == LBM_FP16 && s->L.has_force && s->steps == 0)
+        s->L.e_scale = initial_half_exponent(s->L, s->L.gmax);
+    return s->sync_desc();
+}
+
+int lbm_set_rates(lbm_solver* s, double theta, double w12, double w21, double w22) {
+    if (!s) return LBM_E_ARG;
+    auto ok = [](double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; };
+    if (!(theta > 0.0 && theta < 1.0) || !ok(w12) || !ok(w21) || !ok(w22))
+        return s->fail(LBM_E_MATERIAL, "rates: need 0 < theta < 1 and 0 < omega < 2");
+    Rates r = s->L.rates;
+    r.theta = theta;
+    r.w12 = w12;
+    r.w21 = w21;
+    r.w22 = w22;
+    if (s->L.has_material && !material_rates(s->L.lam, s->L.mu, r, s->err)) return LBM_E_MATERIAL;
+    s->L.rates = r;
+    return s->sync_desc();
+}
+
+int lbm_set_body_force(lbm_solver* s, const double* gx, const double* gy) {
+    if (!s) return LBM_E_ARG;
+    if (!gx || !gy) return s->fail(LBM_E_ARG, "set_body_force: NULL force");
+    Lattice& L = s->L;
+    hipError_t e = upload_force(L, gx, gy, s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "set_body_force");
+    // mean / rms / max of the force (two-stage FP64 reduction)
+    hipLaunchKernelGGL(k_force_stats, dim3(kErrBlocks), dim3(kBlock), 0, s->stream, gx, gy, L.N,
+                       s->d_red);
+    hipLaunchKernelGGL(k_reduce4<kForceMask>, dim3(1), dim3(kBlock), 0, s->stream, s->d_red,
+                       kErrBlocks, s->d_red + 4 * kErrBlocks);
+    if ((e = hipGetLastError()) != hipSuccess) return s->hip_fail(e, "force stats");
+    if ((e = hipMemcpyAsync(s->h_result, s->d_red + 4 * kErrBlocks, 4 * 8,
+                            hipMemcpyDeviceToHost, s->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(s->stream)) != hipSuccess)
+        return s->hip_fail(e, "force stats");
+    const double sx = s->h_result[0], sy = s->h_result[1], s2 = s->h_result[2],
+                 gmax = s->h_result[3];
+    if (!std::isfinite(s2)) return s->fail(LBM_E_ARG, "set_body_force: non-finite force");
+    L.has_force = true;
+    L.gmax = gmax;
+    if (L.prec0 == LBM_FP16 && s->steps == 0) L.e_scale = initial_half_exponent(L, gmax);
+    int rc = s->sync_desc();
+    if (rc != LBM_OK) return rc;
+    const double N = (double)L.N;
+    const double rms = std::sqrt(s2 / (2.0 * N));
+    if (std::fabs(sx / N) > 1e-12 * rms || std::fabs(sy / N) > 1e-12 * rms) {
+        s->err = "body force has a non-zero mean: no steady state (mean of u grows)";
+        return LBM_W_NONZERO_MEAN;
+    }
+    return LBM_OK;
+}
+
+int lbm_set_tile(lbm_solver* s, int bx_log2, int rows_per_thread) {
+    if (!s) return LBM_E_ARG;
+    if (bx_log2 < 0 || bx_log2 > 8 ||
+        !(rows_per_thread == 1 || rows_per_thread == 2 || rows_per_thread == 4))
+        return s->fail(LBM_E_ARG, "set_tile: bx_log2 in 0..8, rows_per_thread in {1,2,4}");
+    s->L.bx_log2 = bx_log2;
+    s->L.vy = rows_per_thread;
+    return s->sync_desc();
+}
+
+int lbm_step(lbm_solver* s, long long nsteps) {
+    if (!s || nsteps < 0) return s ? s->fail(LBM_E_ARG, "step: nsteps < 0") : LBM_E_ARG;
+    if (!s->L.has_material || !s->L.has_force)
+        return s->fail(LBM_E_STATE, "step: material and body force must be set first");
+    hipError_t e = s->enqueue_chunk(nsteps, false, false);
+    if (e != hipSuccess) return s->hip_fail(e, "lbm_step");
+    s->steps += nsteps;
+    return LBM_OK;
+}
+
+int lbm_set_polish(lbm_solver* s, double r_switch) {
+    if (!s) return LBM_E_ARG;
+    if (r_switch > 0.0 && (!s->L.polish || s->L.prec0 == LBM_FP64))
+        return s->fail(LBM_E_STATE, "set_polish: FP32/FP16 solver created with_polish needed");
+    s->r_switch = r_switch > 0.0 ? r_switch : 0.0;
+    return LBM_OK;
+}
+
+int lbm_current_precision(const lbm_solver* s) { return s ? s->L.prec : LBM_E_ARG; }
+long long lbm_steps_done(const lbm_solver* s) { return s ? s->steps : -1; }
+
+namespace {
+// Switch the solver to FP64 storage: exact widening of the current state.
+int promote_solver(lbm_solver* s) {
+    Lattice& L = s->L;
+    if (L.prec == LBM_FP64 || !L.polish) return LBM_OK;
+    const int sl = s->sel();
+    const long long n = 8 * L.N;
+    const double factor = (L.prec == LBM_FP16) ? std::ldexp(1.0, L.e_scale) : 1.0;
+    if (L.prec == LBM_FP32)
+        hipLaunchKernelGGL((k_recast<float, double>), dim3(blocks_for(n)), dim3(kBlock), 0,
+                           s->stream, reinterpret_cast<const float*>(L.mem.buf[sl]),
+                           reinterpret_cast<double*>(L.mem.pbuf[0]), n, factor);
+    else
+        hipLaunchKernelGGL((k_recast<__half, double>), dim3(blocks_for(n)), dim3(kBlock), 0,
+                           s->stream, reinterpret_cast<const __half*>(L.mem.buf[sl]),
+                           reinterpret_cast<double*>(L.mem.pbuf[0]), n, factor);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return s->hip_fail(e, "promote");
+    L.prec = LBM_FP64;
+    L.cur = 0;
+    s->phase = 0;
+    L.bx_log2 = default_bx_log2(LBM_FP64, L.nx);
+    L.vy = 1;
+    L.cur = 0;
+    // sync_desc folds phase into cur: phase is 0 so cur stays 0
+    return s->sync_desc();
+}
+
+// Rescale half storage so that max |stored| stays within [2^10, 2^14].
+int rescale_half(lbm_solver* s, double fmax_stored) {
+    Lattice& L = s->L;
+    if (L.prec != LBM_FP16 || !(fmax_stored > 0.0) || !std::isfinite(fmax_stored)) return LBM_OK;
+    int k = 0;
+    if (fmax_stored > 16384.0) k = (int)std::ceil(std::log2(fmax_stored / 4096.0));
+    else if (fmax_stored < 1024.0) k = -(int)std::floor(std::log2(4096.0 / fmax_stored));
+    if (k == 0) return LBM_OK;
+    const int sl = s->sel();
+    const long long n = 8 * L.N;
+    __half* p = reinterpret_cast<__half*>(L.mem.buf[sl]);
+    hipLaunchKernelGGL((k_recast<__half, __half>), dim3(blocks_for(n)), dim3(kBlock), 0, s->stream,
+                       p, p, n, std::ldexp(1.0, -k));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return s->hip_fail(e, "rescale");
+    L.e_scale += k;
+    return s->sync_desc();
+}
+}  // namespace
+
+int lbm_solve_to_tol(lbm_solver* s, double tol, long long max_steps, int check_every,
+                     long long* steps_done, double* residual) {
+    if (!s) return LBM_E_ARG;
+    if (!(tol >= 0.0) || max_steps < 0 || check_every < 1 || !steps_done || !residual)
+        return s->fail(LBM_E_ARG, "solve_to_tol: need tol >= 0, max_steps >= 0, check_every >= 1");
+    if (!s->L.has_material || !s->L.has_force)
+        return s->fail(LBM_E_STATE, "solve_to_tol: material and body force must be set first");
+    const long long K = check_every;
+    long long n = 0;             // steps taken by this call
+    bool have_prev_u = false;    // u buffer holds u(n - 1)
+    double r = NAN, r_last = INFINITY;
+    int nondecreasing = 0;
+    *residual = NAN;
+    *steps_done = 0;
+    while (true) {
+        const long long j = (n == 0) ? K : n - 1 + K;  // step index of the next check
+        if (j > max_steps) {
+            const long long rest = max_steps - n;
+            hipError_t e = s->enqueue_chunk(rest, false, false);
+            if (e != hipSuccess) return s->hip_fail(e, "solve_to_tol");
+            s->steps += rest;
+            n = max_steps;
+            if ((e = hipStreamSynchronize(s->stream)) != hipSuccess)
+                return s->hip_fail(e, "solve_to_tol");
+            *steps_done = n;
+            *residual = r;
+            return LBM_NOT_CONVERGED;
+        }
+        const bool need_writeu = !(have_prev_u && j - 1 == n - 1);
+        const long long nplain = need_writeu ? (j - 1 - n) : 0;
+        hipError_t e = s->enqueue_chunk(nplain, need_writeu, true);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->h_result, s->d_result, 4 * 8, hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return s->hip_fail(e, "solve_to_tol");
+        const double d2 = s->h_result[0], u2 = s->h_result[1], fm = s->h_result[2];
+        r = (u2 == 0.0) ? (d2 == 0.0 ? 0.0 : INFINITY) : std::sqrt(d2 / u2);
+        if (d2 != d2 || u2 != u2 || !std::isfinite(u2) || !std::isfinite(fm)) r = NAN;
+        *residual = r;
+        const long long after = j + 1;  // steps after the check launch
+        s->steps += after - n;
+        n = after;
+        have_prev_u = true;
+        if (!std::isfinite(r) && !(u2 == 0.0 && d2 != 0.0)) {
+            *steps_done = n;
+            s->err = "solve_to_tol: residual is not finite (diverged)";
+            return LBM_E_DIVERGED;
+        }
+        if (r <= tol || j == max_steps) {
+            // the check launch advanced to j + 1; its source buffer still holds f(j)
+            s->phase -= 1;
+            s->steps -= 1;
+            n = j;
+            *steps_done = n;
+            return (r <= tol) ? LBM_OK : LBM_NOT_CONVERGED;
+        }
+        // precision management between chunks
+        if (s->L.prec == LBM_FP16) {
+            int rc = rescale_half(s, fm);
+            if (rc != LBM_OK) return rc;
+        }
+        if (s->r_switch > 0.0 && s->L.prec != LBM_FP64) {
+            nondecreasing = (r >= r_last) ? nondecreasing + 1 : 0;
+            if (r <= s->r_switch || nondecreasing >= 2) {
+                int rc = promote_solver(s);
+                if (rc != LBM_OK) return rc;
+                have_prev_u = true;  // u buffer (FP64, unscaled) is unaffected
+            }
+        }
+        r_last = r;
+    }
+}
+
+int lbm_get_displacement(lbm_solver* s, double* ux, double* uy) {
+    if (!s) return LBM_E_ARG;
+    if (!ux || !uy) return s->fail(LBM_E_ARG, "get_displacement: NULL output");
+    if (!s->L.has_force) return s->fail(LBM_E_STATE, "get_displacement: no body force set");
+    hipError_t e = extract_u(s->L.prec, s->L.desc(), s->sel(), ux, uy, s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "get_displacement");
+    return LBM_OK;
+}
+
+int lbm_get_stress(lbm_solver* s, double* sxx, double* syy, double* sxy) {
+    if (!s) return LBM_E_ARG;
+    if (!sxx || !syy || !sxy) return s->fail(LBM_E_ARG, "get_stress: NULL output");
+    if (!s->L.has_material) return s->fail(LBM_E_STATE, "get_stress: no material set");
+    const SlotDesc d = s->L.desc();
+    hipError_t e;
+    if (s->L.prec == LBM_FP64) e = launch_stress<double>(d, s->sel(), s->L.rates, sxx, syy, sxy, s->stream);
+    else if (s->L.prec == LBM_FP32) e = launch_stress<float>(d, s->sel(), s->L.rates, sxx, syy, sxy, s->stream);
+    else e = launch_stress<__half>(d, s->sel(), s->L.rates, sxx, syy, sxy, s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "get_stress");
+    return LBM_OK;
+}
+
+int lbm_error_norms(lbm_solver* s, const double* ux_ref, const double* uy_ref, double out[4]) {
+    if (!s) return LBM_E_ARG;
+    if (!ux_ref || !uy_ref || !out) return s->fail(LBM_E_ARG, "error_norms: NULL argument");
+    if (!s->L.has_force) return s->fail(LBM_E_STATE, "error_norms: no body force set");
+    // displacement into the u planes of the workspace, then the two-stage reduction
+    double* ux = s->L.mem.u;
+    double* uy = s->L.mem.u + s->L.N;
+    hipError_t e = extract_u(s->L.prec, s->L.desc(), s->sel(), ux, uy, s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "error_norms");
+    hipLaunchKernelGGL(k_err_norms, dim3(kErrBlocks), dim3(kBlock), 0, s->stream, ux, uy, ux_ref,
+                       uy_ref, s->L.N, s->d_red);
+    hipLaunchKernelGGL(k_reduce4<kErrMask>, dim3(1), dim3(kBlock), 0, s->stream, s->d_red,
+                       kErrBlocks, s->d_red + 4 * kErrBlocks);
+    if ((e = hipGetLastError()) == hipSuccess)
+        e = hipMemcpyAsync(s->h_result, s->d_red + 4 * kErrBlocks, 4 * 8, hipMemcpyDeviceToHost,
+                           s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "error_norms");
+    for (int c = 0; c < 4; ++c) out[c] = s->h_result[c];
+    return LBM_OK;
+}
+
+int lbm_get_populations(lbm_solver* s, double* f) {
+    if (!s) return LBM_E_ARG;
+    if (!f) return s->fail(LBM_E_ARG, "get_populations: NULL output");
+    const SlotDesc d = s->L.desc();
+    hipError_t e;
+    if (s->L.prec == LBM_FP64) e = launch_get_f<double>(d, s->sel(), f, s->stream);
+    else if (s->L.prec == LBM_FP32) e = launch_get_f<float>(d, s->sel(), f, s->stream);
+    else e = launch_get_f<__half>(d, s->sel(), f, s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "get_populations");
+    return LBM_OK;
+}
+
+int lbm_set_populations(lbm_solver* s, const double* f) {
+    if (!s) return LBM_E_ARG;
+    if (!f) return s->fail(LBM_E_ARG, "set_populations: NULL input");
+    const SlotDesc d = s->L.desc();
+    const double sc = d.gscale;
+    hipError_t e;
+    if (s->L.prec == LBM_FP64) e = launch_set_f<double>(d, s->sel(), f, sc, s->stream);
+    else if (s->L.prec == LBM_FP32) e = launch_set_f<float>(d, s->sel(), f, sc, s->stream);
+    else e = launch_set_f<__half>(d, s->sel(), f, sc, s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "set_populations");
+    return LBM_OK;
+}
+
+int lbm_debug_stream_only(lbm_solver* s, long long nsteps) {
+    if (!s || nsteps < 0) return LBM_E_ARG;
+    hipError_t e = hipSuccess;
+    for (long long i = 0; i < nsteps && e == hipSuccess; ++i) {
+        const StepLaunch a = s->launch_args((int)(s->phase & 1));
+        if (s->L.prec == LBM_FP64) e = launch_stream_only<double>(s->grid, s->stream, a);
+        else if (s->L.prec == LBM_FP32) e = launch_stream_only<float>(s->grid, s->stream, a);
+        else e = launch_stream_only<__half>(s->grid, s->stream, a);
+        ++s->phase;
+    }
+    if (e != hipSuccess) return s->hip_fail(e, "debug_stream_only");
+    s->steps += nsteps;
+    return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_solver* s) {
+    if (!s) return g_create_error.c_str();
+    return s->err.c_str();
+}
+
+}  // extern "C"

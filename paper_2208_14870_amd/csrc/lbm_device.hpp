@@ -1,0 +1,596 @@
+// Device code of the MI355X (gfx950) lattice Boltzmann elasticity library.
+//
+// Scheme: Boolakee, Geier, De Lorenzis, arXiv 2208.14870.  One time step is
+// Algorithm 1 -- moments, half forcing, equilibria (Table "scheme"),
+// relaxation (Eq. collision), second half forcing, back-transformation
+// (Eq. moments_post) and streaming (Eq. streaming) -- fused into one pass
+// over the lattice in "pull" form: each site gathers the post-collision
+// populations of its upstream neighbours from buffer A (periodic wrap by
+// index arithmetic, Sec. 6.1), collides them in registers and writes its own
+// post-collision populations to buffer B.  The stored state is therefore the
+// post-collision field f*(n-1); f(n) is obtained by the same gather.
+//
+// Populations: D2Q8 (the rest population is never read by any equilibrium
+// or relaxed moment, Sec. 3.3.2), one-index order of the velocity table of
+// Sec. 5: 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1)
+// 8:(1,-1), stored as eight SoA planes [q][y][x], x fastest.
+//
+// Storage precision S in {double, float, __half}; arithmetic type C is
+// double for double storage and float otherwise.  Half storage holds the
+// populations times a per-lattice power of two 2^-e (the problem is linear,
+// and the rest equilibrium of this scheme is identically zero, so the stored
+// value is the deviation from rest); the force is multiplied by the same
+// factor inside the kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int kBlock = 256;  // threads per workgroup (4 wave64s)
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// per-lattice descriptor (device memory, read once per tile)
+// ---------------------------------------------------------------------------
+struct SlotDesc {
+    void* buf[2];          // two population buffers, 8 planes each
+    const void* g;         // force, 2 planes in the arithmetic type
+    double* u;             // 2 planes FP64: displacement of the last check launch
+    long long plane;       // elements per plane = nx * ny
+    int nx, ny;
+    int cur;               // buffer index holding the state at launch flip 0
+    int tiles_x, tiles_y;  // tile grid of this lattice
+    int bx_log2;           // tile width in threads = 1 << bx_log2 (tile height = 256 >> bx_log2)
+    int general;           // nonzero: general omega_12/21/22 and theta (host sets the launch variant)
+    int pad_;
+    // fast-path coefficients (omega_12 = omega_21 = omega_22 = 1)
+    double cs, cd, c11, hth, tq;
+    // general-path rates
+    double a11, as, ad, theta, w12, w21, a22;
+    double gscale;     // factor applied to the force (2^-e for half storage, else 1)
+    double inv_scale;  // 1 / storage factor, applied to outputs
+};
+
+struct Item {
+    int slot;
+    int tx, ty;
+    int pad_;
+};
+
+// ---------------------------------------------------------------------------
+// storage traits
+// ---------------------------------------------------------------------------
+template <typename S> struct Store;
+template <> struct Store<double> {
+    using C = double;
+    __device__ static __forceinline__ C ld(const double* p) { return *p; }
+    __device__ static __forceinline__ void st(double* p, C v) { __builtin_nontemporal_store(v, p); }
+};
+template <> struct Store<float> {
+    using C = float;
+    __device__ static __forceinline__ C ld(const float* p) { return *p; }
+    __device__ static __forceinline__ void st(float* p, C v) { __builtin_nontemporal_store(v, p); }
+};
+template <> struct Store<__half> {
+    using C = float;
+    __device__ static __forceinline__ C ld(const __half* p) { return __half2float(*p); }
+    __device__ static __forceinline__ void st(__half* p, C v) {
+        __half h = __float2half_rn(v);
+        __builtin_nontemporal_store(__half_as_ushort(h), reinterpret_cast<unsigned short*>(p));
+    }
+};
+
+// ---------------------------------------------------------------------------
+// collision of one site (Algorithm 1, collision block), in registers
+// ---------------------------------------------------------------------------
+template <typename C>
+struct Coef {
+    C cs, cd, c11, hth, tq;           // fast path
+    C a11, as, ad, theta, w12, w21, a22;  // general path
+    C gscale;
+    __device__ __forceinline__ void load(const SlotDesc& d) {
+        cs = (C)d.cs; cd = (C)d.cd; c11 = (C)d.c11; hth = (C)d.hth; tq = (C)d.tq;
+        a11 = (C)d.a11; as = (C)d.as; ad = (C)d.ad; theta = (C)d.theta;
+        w12 = (C)d.w12; w21 = (C)d.w21; a22 = (C)d.a22;
+        gscale = (C)d.gscale;
+    }
+};
+
+// f[0..7] in: pre-collision populations; out: post-collision populations.
+// gx, gy: (scaled) force.  Returns the bared first-order moments (ux, uy).
+//
+// Moments (Eqs. moments / replace_raw, transformed directly into the
+// collision set as the paper recommends):
+//   m10 = f1 - f3 + f5 - f6 - f7 + f8      m01 = f2 - f4 + f5 + f6 - f7 - f8
+//   m11 = f5 - f6 + f7 - f8                ms  = f1 + f2 + f3 + f4 + 2(f5+f6+f7+f8)
+//   md  = f1 - f2 + f3 - f4                m12 = f5 - f6 - f7 + f8
+//   m21 = f5 + f6 - f7 - f8                m22 = f5 + f6 + f7 + f8
+// Bared first moments ux = m10 + gx/2, uy = m01 + gy/2 (Eqs. coll10/coll01);
+// equilibria m12_eq = theta ux, m21_eq = theta uy, all others 0 (Table
+// "scheme"); relaxation m* = omega m_eq + (1 - omega) m (Eq. collision);
+// m10* = ux + gx/2, m01* = uy + gy/2 (Eqs. coll10post/coll01post); then
+// f* = M^-1 m* with the exact (dyadic) inverse of the transform of Sec. 5.
+//
+// Fast path (omega_12 = omega_21 = omega_22 = 1, so m12* = theta ux,
+// m21* = theta uy, m22* = 0), with cs = (1-omega_s)/4, cd = (1-omega_d)/4,
+// c11 = (1-omega_11)/4, hth = (1-theta)/2, tq = theta/4:
+//   f1*,f3* = cs ms + cd md +- (hth ux + gx/4)
+//   f2*,f4* = cs ms - cd md +- (hth uy + gy/4)
+//   f5*,f7* =  c11 m11 +- tq (ux + uy)
+//   f6*,f8* = -c11 m11 -+ tq (ux - uy)
+template <typename C, bool GENERAL>
+__device__ __forceinline__ void collide(C f[8], C gx, C gy, const Coef<C>& k, C& ux, C& uy) {
+    const C p = f[4] - f[6];   // f5 - f7
+    const C q = f[5] - f[7];   // f6 - f8
+    const C h13 = f[0] + f[2];
+    const C h24 = f[1] + f[3];
+    const C sac = f[4] + f[6];
+    const C sbd = f[5] + f[7];
+    const C m12 = p - q;
+    const C m21 = p + q;
+    const C m10 = (f[0] - f[2]) + m12;
+    const C m01 = (f[1] - f[3]) + m21;
+    const C m11 = sac - sbd;
+    const C ms = (h13 + h24) + C(2) * (sac + sbd);
+    const C md = h13 - h24;
+    const C hgx = C(0.5) * gx, hgy = C(0.5) * gy;
+    ux = m10 + hgx;
+    uy = m01 + hgy;
+    if constexpr (!GENERAL) {
+        const C a = k.cs * ms + k.cd * md;
+        const C b = k.cs * ms - k.cd * md;
+        const C ex = k.hth * ux + C(0.5) * hgx;
+        const C ey = k.hth * uy + C(0.5) * hgy;
+        const C s = k.c11 * m11;
+        const C t1 = k.tq * (ux + uy);
+        const C t2 = k.tq * (ux - uy);
+        f[0] = a + ex;
+        f[2] = a - ex;
+        f[1] = b + ey;
+        f[3] = b - ey;
+        f[4] = s + t1;
+        f[6] = s - t1;
+        f[5] = -(s + t2);
+        f[7] = t2 - s;
+    } else {
+        const C m22 = sac + sbd;
+        const C s10 = ux + hgx, s01 = uy + hgy;
+        const C s11 = k.a11 * m11;
+        const C sss = k.as * ms;
+        const C sdd = k.ad * md;
+        const C s12 = k.w12 * (k.theta * ux) + (C(1) - k.w12) * m12;
+        const C s21 = k.w21 * (k.theta * uy) + (C(1) - k.w21) * m21;
+        const C s22 = k.a22 * m22;
+        const C A = C(0.5) * (sss + sdd) - s22;  // m20* - m22*
+        const C B = C(0.5) * (sss - sdd) - s22;  // m02* - m22*
+        const C ex = s10 - s12, ey = s01 - s21;
+        f[0] = C(0.5) * (A + ex);
+        f[2] = C(0.5) * (A - ex);
+        f[1] = C(0.5) * (B + ey);
+        f[3] = C(0.5) * (B - ey);
+        f[4] = C(0.25) * ((s22 + s11) + (s12 + s21));
+        f[5] = C(0.25) * ((s22 - s11) - (s12 - s21));
+        f[6] = C(0.25) * ((s22 + s11) - (s12 + s21));
+        f[7] = C(0.25) * ((s22 - s11) + (s12 - s21));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pull-gather of the 8 populations arriving at (x, y)
+// ---------------------------------------------------------------------------
+template <typename S>
+__device__ __forceinline__ void gather(const S* __restrict__ src, long long plane, int nx, int ny,
+                                       int x, int y, typename Store<S>::C f[8]) {
+    const int xm = (x == 0) ? nx - 1 : x - 1;
+    const int xp = (x == nx - 1) ? 0 : x + 1;
+    const int ym = (y == 0) ? ny - 1 : y - 1;
+    const int yp = (y == ny - 1) ? 0 : y + 1;
+    const long long r0 = (long long)y * nx, rm = (long long)ym * nx, rp = (long long)yp * nx;
+    f[0] = Store<S>::ld(src + 0 * plane + r0 + xm);  // c1 = ( 1, 0) from (x-1, y)
+    f[1] = Store<S>::ld(src + 1 * plane + rm + x);   // c2 = ( 0, 1) from (x, y-1)
+    f[2] = Store<S>::ld(src + 2 * plane + r0 + xp);  // c3 = (-1, 0) from (x+1, y)
+    f[3] = Store<S>::ld(src + 3 * plane + rp + x);   // c4 = ( 0,-1) from (x, y+1)
+    f[4] = Store<S>::ld(src + 4 * plane + rm + xm);  // c5 = ( 1, 1) from (x-1, y-1)
+    f[5] = Store<S>::ld(src + 5 * plane + rm + xp);  // c6 = (-1, 1) from (x+1, y-1)
+    f[6] = Store<S>::ld(src + 6 * plane + rp + xp);  // c7 = (-1,-1) from (x+1, y+1)
+    f[7] = Store<S>::ld(src + 7 * plane + rp + xm);  // c8 = ( 1,-1) from (x-1, y+1)
+}
+
+// ---------------------------------------------------------------------------
+// wave64 / block reductions (fixed order: deterministic)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Reduce (sum, sum, max) over the 256 threads; result valid in thread 0.
+__device__ __forceinline__ void block_reduce3(double& a, double& b, double& m, double* lds) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    m = wave_max(m);
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    if (l == 0) {
+        lds[3 * w + 0] = a;
+        lds[3 * w + 1] = b;
+        lds[3 * w + 2] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = (lds[0] + lds[3]) + (lds[6] + lds[9]);
+        b = (lds[1] + lds[4]) + (lds[7] + lds[10]);
+        m = fmax(fmax(lds[2], lds[5]), fmax(lds[8], lds[11]));
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// the fused stream + collide step over a work list of tiles
+// ---------------------------------------------------------------------------
+enum StepMode : int {
+    kPlain = 0,   // advance only
+    kWriteU = 1,  // advance and store u (FP64, unscaled) of this launch
+    kCheck = 2,   // advance, store u, and reduce |u - u_prev|^2, |u|^2, max |f*| per tile
+};
+
+struct StepLaunch {
+    const SlotDesc* slots;
+    const Item* items;
+    const int* range;   // device pair {begin, end}: items [begin, end) of the work list
+    double* partial;    // 3 doubles per item (check mode)
+    int flip;           // launch parity: source buffer = buf[cur ^ flip]
+};
+
+// Blocks are spread over the 8 XCDs round-robin by the hardware; item ranges
+// are assigned so that each XCD walks one contiguous slice of the work list
+// (neighbouring tiles share cache lines of the shifted rows in one L2).
+__device__ __forceinline__ void xcd_slice(const int* range, int& last, int& stride, int& start) {
+    const int begin = range[0];
+    const int nitems = range[1] - begin;
+    const int G = gridDim.x;
+    const int nx8 = (G % 8 == 0) ? 8 : 1;
+    const int xcd = blockIdx.x % nx8;
+    const int lb = blockIdx.x / nx8;
+    const int first = begin + (int)(((long long)nitems * xcd) / nx8);
+    last = begin + (int)(((long long)nitems * (xcd + 1)) / nx8);
+    stride = G / nx8;
+    start = first + lb;
+}
+
+template <typename S, int MODE, bool GENERAL, int VY>
+static __global__ __launch_bounds__(kBlock) void k_step(StepLaunch L) {
+    using C = typename Store<S>::C;
+    __shared__ double lds[12];
+    int last, stride, it;
+    xcd_slice(L.range, last, stride, it);
+    for (; it < last; it += stride) {
+        const Item item = L.items[it];
+        const SlotDesc& d = L.slots[item.slot];
+        const int nx = d.nx, ny = d.ny;
+        const long long plane = d.plane;
+        const int sel = d.cur ^ L.flip;
+        const S* __restrict__ src = reinterpret_cast<const S*>(d.buf[sel]);
+        S* __restrict__ dst = reinterpret_cast<S*>(d.buf[sel ^ 1]);
+        const C* __restrict__ g = reinterpret_cast<const C*>(d.g);
+        Coef<C> k;
+        k.load(d);
+        const int bxl = d.bx_log2;
+        const int lx = threadIdx.x & ((1 << bxl) - 1);
+        const int ly = threadIdx.x >> bxl;
+        const int th = kBlock >> bxl;  // tile height in threads
+        const int x = (item.tx << bxl) + lx;
+        const int y0 = item.ty * th * VY + ly;
+        double dsum = 0.0, ssum = 0.0, fmaxv = 0.0;
+        C f[VY][8];
+        bool ok[VY];
+#pragma unroll
+        for (int j = 0; j < VY; ++j) {
+            const int y = y0 + j * th;
+            ok[j] = (x < nx) && (y < ny);
+            if (ok[j]) gather<S>(src, plane, nx, ny, x, y, f[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < VY; ++j) {
+            if (!ok[j]) continue;
+            const int y = y0 + j * th;
+            const long long s = (long long)y * nx + x;
+            const C gx = g[s] * k.gscale;
+            const C gy = g[plane + s] * k.gscale;
+            C ux, uy;
+            collide<C, GENERAL>(f[j], gx, gy, k, ux, uy);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * plane + s, f[j][q]);
+            if constexpr (MODE != kPlain) {
+                const double uxd = (double)ux * d.inv_scale, uyd = (double)uy * d.inv_scale;
+                if constexpr (MODE == kCheck) {
+                    const double dx = uxd - d.u[s], dy = uyd - d.u[plane + s];
+                    dsum += dx * dx + dy * dy;
+                    ssum += uxd * uxd + uyd * uyd;
+                    double m = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) m = fmax(m, (double)fabs(f[j][q]));
+                    fmaxv = fmax(fmaxv, m);
+                }
+                d.u[s] = uxd;
+                d.u[plane + s] = uyd;
+            }
+        }
+        if constexpr (MODE == kCheck) {
+            block_reduce3(dsum, ssum, fmaxv, lds);
+            if (threadIdx.x == 0) {
+                L.partial[3 * it + 0] = dsum;
+                L.partial[3 * it + 1] = ssum;
+                L.partial[3 * it + 2] = fmaxv;
+            }
+        }
+    }
+}
+
+// Streaming alone (no collision): bit-exact check of the index arithmetic.
+template <typename S>
+static __global__ __launch_bounds__(kBlock) void k_stream_only(StepLaunch L) {
+    using C = typename Store<S>::C;
+    int last, stride, it;
+    xcd_slice(L.range, last, stride, it);
+    for (; it < last; it += stride) {
+        const Item item = L.items[it];
+        const SlotDesc& d = L.slots[item.slot];
+        const int sel = d.cur ^ L.flip;
+        const S* src = reinterpret_cast<const S*>(d.buf[sel]);
+        S* dst = reinterpret_cast<S*>(d.buf[sel ^ 1]);
+        const int bxl = d.bx_log2;
+        const int x = (item.tx << bxl) + (threadIdx.x & ((1 << bxl) - 1));
+        const int y = item.ty * (kBlock >> bxl) + (threadIdx.x >> bxl);
+        if (x >= d.nx || y >= d.ny) continue;
+        C f[8];
+        gather<S>(src, d.plane, d.nx, d.ny, x, y, f);
+        const long long s = (long long)y * d.nx + x;
+        for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * d.plane + s, f[q]);
+    }
+}
+
+// Per-slot deterministic sum of the tile partials: one block per slot,
+// items of a slot are contiguous in the work list.
+struct FinalizeLaunch {
+    const int* first;   // per slot: first item
+    const int* count;   // per slot: number of items (0 = inactive)
+    const double* partial;
+    double* result;     // 4 doubles per slot: sum d, sum s, max |f|, unused
+    int nslots;
+};
+
+static __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeLaunch F) {
+    __shared__ double lds[12];
+    const int slot = blockIdx.x;
+    if (slot >= F.nslots) return;
+    const int cnt = F.count[slot];
+    if (cnt == 0) return;
+    const int f0 = F.first[slot];
+    double a = 0.0, b = 0.0, m = 0.0;
+    for (int i = threadIdx.x; i < cnt; i += kBlock) {
+        a += F.partial[3 * (f0 + i) + 0];
+        b += F.partial[3 * (f0 + i) + 1];
+        m = fmax(m, F.partial[3 * (f0 + i) + 2]);
+    }
+    block_reduce3(a, b, m, lds);
+    if (threadIdx.x == 0) {
+        F.result[4 * slot + 0] = a;
+        F.result[4 * slot + 1] = b;
+        F.result[4 * slot + 2] = m;
+        F.result[4 * slot + 3] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-lattice helpers (1 thread per site)
+// ---------------------------------------------------------------------------
+
+// u(n) = bared first moments of f(n) (gathered from the stored post-collision
+// field), FP64 and unscaled (Table "solution").
+template <typename S>
+static __global__ __launch_bounds__(kBlock) void k_extract_u(SlotDesc d, int sel, double* ux,
+                                                      double* uy) {
+    using C = typename Store<S>::C;
+    const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= d.plane) return;
+    const int x = (int)(s % d.nx), y = (int)(s / d.nx);
+    C f[8];
+    gather<S>(reinterpret_cast<const S*>(d.buf[sel]), d.plane, d.nx, d.ny, x, y, f);
+    const C* g = reinterpret_cast<const C*>(d.g);
+    const double m10 = (double)((f[0] - f[2]) + ((f[4] - f[6]) - (f[5] - f[7])));
+    const double m01 = (double)((f[1] - f[3]) + ((f[4] - f[6]) + (f[5] - f[7])));
+    const double gsc = d.gscale;
+    ux[s] = (m10 + 0.5 * (double)g[s] * gsc) * d.inv_scale;
+    uy[s] = (m01 + 0.5 * (double)g[d.plane + s] * gsc) * d.inv_scale;
+}
+
+// Stress from the bared second-order moments of f(n) (Eq. compute_bared with
+// zero equilibria, Table "solution" in lattice units): sxx = -(mb_s + mb_d)/2,
+// syy = -(mb_s - mb_d)/2, sxy = -mb_11, mb = (1 - omega/2) m.
+template <typename S>
+static __global__ __launch_bounds__(kBlock) void k_extract_stress(SlotDesc d, int sel, double bs,
+                                                           double bd, double b11, double* sxx,
+                                                           double* syy, double* sxy) {
+    using C = typename Store<S>::C;
+    const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= d.plane) return;
+    const int x = (int)(s % d.nx), y = (int)(s / d.nx);
+    C f[8];
+    gather<S>(reinterpret_cast<const S*>(d.buf[sel]), d.plane, d.nx, d.ny, x, y, f);
+    const double h13 = (double)f[0] + (double)f[2], h24 = (double)f[1] + (double)f[3];
+    const double sac = (double)f[4] + (double)f[6], sbd = (double)f[5] + (double)f[7];
+    const double ms = (h13 + h24) + 2.0 * (sac + sbd);
+    const double md = h13 - h24;
+    const double m11 = sac - sbd;
+    const double mbs = bs * ms, mbd = bd * md, mb11 = b11 * m11;
+    sxx[s] = -0.5 * (mbs + mbd) * d.inv_scale;
+    syy[s] = -0.5 * (mbs - mbd) * d.inv_scale;
+    sxy[s] = -mb11 * d.inv_scale;
+}
+
+// Populations f(n) in the paper's order, FP64 unscaled: gather of the stored field.
+template <typename S>
+static __global__ __launch_bounds__(kBlock) void k_get_f(SlotDesc d, int sel, double* out) {
+    using C = typename Store<S>::C;
+    const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= d.plane) return;
+    const int x = (int)(s % d.nx), y = (int)(s / d.nx);
+    C f[8];
+    gather<S>(reinterpret_cast<const S*>(d.buf[sel]), d.plane, d.nx, d.ny, x, y, f);
+    for (int q = 0; q < 8; ++q) out[q * d.plane + s] = (double)f[q] * d.inv_scale;
+}
+
+// Load a state f(n) given in the paper's order: the stored field is
+// f*(n-1)(x) = f(n)(x + c_q), i.e. the inverse of the gather.
+template <typename S>
+static __global__ __launch_bounds__(kBlock) void k_set_f(SlotDesc d, int sel, const double* in,
+                                                  double scale) {
+    const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= d.plane) return;
+    const int x = (int)(s % d.nx), y = (int)(s / d.nx);
+    const int xm = (x == 0) ? d.nx - 1 : x - 1, xp = (x == d.nx - 1) ? 0 : x + 1;
+    const int ym = (y == 0) ? d.ny - 1 : y - 1, yp = (y == d.ny - 1) ? 0 : y + 1;
+    S* dst = reinterpret_cast<S*>(d.buf[sel]);
+    const int cx[8] = {1, 0, -1, 0, 1, -1, -1, 1};
+    const int cy[8] = {0, 1, 0, -1, 1, 1, -1, -1};
+    for (int q = 0; q < 8; ++q) {
+        const int xs = cx[q] > 0 ? xp : (cx[q] < 0 ? xm : x);
+        const int ys = cy[q] > 0 ? yp : (cy[q] < 0 ? ym : y);
+        const double v = in[q * d.plane + (long long)ys * d.nx + xs] * scale;
+        Store<S>::st(dst + q * d.plane + s, (typename Store<S>::C)v);
+    }
+}
+
+// Convert an FP64 array to the arithmetic type (force upload).
+template <typename C>
+static __global__ __launch_bounds__(kBlock) void k_convert(const double* in, C* out, long long n) {
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = (C)in[i];
+}
+
+// out = in * factor elementwise, between storage types (promotion for the
+// FP64 polish phase, power-of-two rescaling of half storage).
+template <typename SI, typename SO>
+static __global__ __launch_bounds__(kBlock) void k_recast(const SI* in, SO* out, long long n,
+                                                   double factor) {
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double v = (double)Store<SI>::ld(in + i) * factor;
+    Store<SO>::st(out + i, (typename Store<SO>::C)v);
+}
+
+// Zero fill by a kernel (safe inside captured graphs).
+static __global__ __launch_bounds__(kBlock) void k_zero(unsigned int* p, long long nwords) {
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i < nwords) p[i] = 0u;
+}
+
+// Deterministic (fixed-order) block reduction of four values; MAXMASK bit c
+// set means entry c is reduced with max instead of +.  Result in thread 0.
+template <int MAXMASK>
+__device__ __forceinline__ void block_reduce4(double v[4], double* lds) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double w = __shfl_xor(v[c], o, kWave);
+            v[c] = ((MAXMASK >> c) & 1) ? fmax(v[c], w) : v[c] + w;
+        }
+    }
+    const int wv = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    if (l == 0)
+        for (int c = 0; c < 4; ++c) lds[4 * wv + c] = v[c];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            v[c] = ((MAXMASK >> c) & 1)
+                       ? fmax(fmax(lds[c], lds[4 + c]), fmax(lds[8 + c], lds[12 + c]))
+                       : (lds[c] + lds[4 + c]) + (lds[8 + c] + lds[12 + c]);
+    }
+    __syncthreads();
+}
+
+// Error norms against a reference field, stage 1: per block
+// (sum |e|^2, sum |ref|^2, max |e|_inf, max |ref|_inf), e = u - ref (the grid
+// norms of Sec. 7.1 before the dx weighting).
+constexpr int kErrMask = 0xC;
+static __global__ __launch_bounds__(kBlock) void k_err_norms(const double* ux, const double* uy,
+                                                      const double* rx, const double* ry,
+                                                      long long n, double* partial) {
+    __shared__ double lds[16];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock) {
+        const double ex = ux[i] - rx[i], ey = uy[i] - ry[i];
+        v[0] += ex * ex + ey * ey;
+        v[1] += rx[i] * rx[i] + ry[i] * ry[i];
+        v[2] = fmax(v[2], fmax(fabs(ex), fabs(ey)));
+        v[3] = fmax(v[3], fmax(fabs(rx[i]), fabs(ry[i])));
+    }
+    block_reduce4<kErrMask>(v, lds);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) partial[4 * blockIdx.x + c] = v[c];
+}
+
+// Force statistics, stage 1: per block (sum gx, sum gy, sum gx^2 + gy^2,
+// max |g|_inf).
+constexpr int kForceMask = 0x8;
+static __global__ __launch_bounds__(kBlock) void k_force_stats(const double* gx, const double* gy,
+                                                        long long n, double* partial) {
+    __shared__ double lds[16];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock) {
+        v[0] += gx[i];
+        v[1] += gy[i];
+        v[2] += gx[i] * gx[i] + gy[i] * gy[i];
+        v[3] = fmax(v[3], fmax(fabs(gx[i]), fabs(gy[i])));
+    }
+    block_reduce4<kForceMask>(v, lds);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) partial[4 * blockIdx.x + c] = v[c];
+}
+
+// Stage 2: one block combines the block partials in a fixed order.
+template <int MAXMASK>
+static __global__ __launch_bounds__(kBlock) void k_reduce4(const double* partial, int nparts,
+                                                    double* out) {
+    __shared__ double lds[16];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nparts; i += kBlock)
+        for (int c = 0; c < 4; ++c)
+            v[c] = ((MAXMASK >> c) & 1) ? fmax(v[c], partial[4 * i + c])
+                                         : v[c] + partial[4 * i + c];
+    block_reduce4<MAXMASK>(v, lds);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) out[c] = v[c];
+}
+
+// Write the work list of one lattice: tiles in row-major tile order.
+static __global__ __launch_bounds__(kBlock) void k_build_items(Item* items, int first, int slot,
+                                                        int tiles_x, int count) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= count) return;
+    Item it;
+    it.slot = slot;
+    it.tx = i % tiles_x;
+    it.ty = i / tiles_x;
+    it.pad_ = 0;
+    items[first + i] = it;
+}
+
+// Small device-side stores (stream-ordered, safe inside captured graphs).
+static __global__ void k_set_int(int* p, int v) { *p = v; }
+static __global__ void k_set_desc(SlotDesc* p, SlotDesc v) { *p = v; }
+
+}  // namespace lbm

@@ -1,0 +1,285 @@
+// Host-side internals shared by the single-lattice solver and the batch:
+// material -> relaxation rates (Table "scheme"), lattice memory layout inside
+// caller-owned device memory, kernel dispatch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "lbm.h"
+#include "lbm_device.hpp"
+
+namespace lbm_host {
+using namespace lbm;
+
+
+constexpr size_t kAlign = 256;
+inline size_t al(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+inline size_t elem_bytes(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2); }
+inline size_t arith_bytes(int prec) { return prec == LBM_FP64 ? 8 : 4; }
+inline bool valid_prec(int p) { return p == LBM_FP64 || p == LBM_FP32 || p == LBM_FP16; }
+
+inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+constexpr int kErrBlocks = 1024;  // grid of the two-stage FP64 reductions
+
+struct Rates {
+    double theta = 1.0 / 3.0, w12 = 1.0, w21 = 1.0, w22 = 1.0;  // free parameters
+    double w11 = 0, ws = 0, wd = 0;                              // from the material
+};
+
+// Table "scheme": tau_11 = mu/theta, tau_s = 2K/(1+theta), tau_d = 2mu/(1-theta),
+// K = lambda + mu, omega = 1/(tau + 1/2) (Eq. relaxation_rate).
+inline bool material_rates(double lam, double mu, Rates& r, std::string& err) {
+    const double K = lam + mu;
+    if (!std::isfinite(lam) || !std::isfinite(mu) || !(mu > 0.0) || !(K > 0.0)) {
+        err = "material: need finite lambda, mu with mu > 0 and lambda + mu > 0";
+        return false;
+    }
+    const double th = r.theta;
+    r.w11 = 1.0 / (mu / th + 0.5);
+    r.ws = 1.0 / (2.0 * K / (1.0 + th) + 0.5);
+    r.wd = 1.0 / (2.0 * mu / (1.0 - th) + 0.5);
+    return true;
+}
+
+inline void fill_coefs(SlotDesc& d, const Rates& r) {
+    d.cs = 0.25 * (1.0 - r.ws);
+    d.cd = 0.25 * (1.0 - r.wd);
+    d.c11 = 0.25 * (1.0 - r.w11);
+    d.hth = 0.5 * (1.0 - r.theta);
+    d.tq = 0.25 * r.theta;
+    d.a11 = 1.0 - r.w11;
+    d.as = 1.0 - r.ws;
+    d.ad = 1.0 - r.wd;
+    d.theta = r.theta;
+    d.w12 = r.w12;
+    d.w21 = r.w21;
+    d.a22 = 1.0 - r.w22;
+    d.general = (r.w12 != 1.0 || r.w21 != 1.0 || r.w22 != 1.0) ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// kernel dispatch
+// ---------------------------------------------------------------------------
+template <typename S, int MODE>
+inline hipError_t launch_step_t(bool general, int vy, unsigned grid, hipStream_t st,
+                         const StepLaunch& L) {
+    if (general) {
+        hipLaunchKernelGGL((k_step<S, MODE, true, 1>), dim3(grid), dim3(kBlock), 0, st, L);
+    } else if (vy == 1) {
+        hipLaunchKernelGGL((k_step<S, MODE, false, 1>), dim3(grid), dim3(kBlock), 0, st, L);
+    } else if (vy == 2) {
+        hipLaunchKernelGGL((k_step<S, MODE, false, 2>), dim3(grid), dim3(kBlock), 0, st, L);
+    } else {
+        hipLaunchKernelGGL((k_step<S, MODE, false, 4>), dim3(grid), dim3(kBlock), 0, st, L);
+    }
+    return hipGetLastError();
+}
+
+template <typename S>
+inline hipError_t launch_step_s(int mode, bool general, int vy, unsigned grid, hipStream_t st,
+                         const StepLaunch& L) {
+    switch (mode) {
+        case kPlain: return launch_step_t<S, kPlain>(general, vy, grid, st, L);
+        case kWriteU: return launch_step_t<S, kWriteU>(general, vy, grid, st, L);
+        default: return launch_step_t<S, kCheck>(general, vy, grid, st, L);
+    }
+}
+
+inline hipError_t launch_step(int prec, int mode, bool general, int vy, unsigned grid, hipStream_t st,
+                       const StepLaunch& L) {
+    if (prec == LBM_FP64) return launch_step_s<double>(mode, general, vy, grid, st, L);
+    if (prec == LBM_FP32) return launch_step_s<float>(mode, general, vy, grid, st, L);
+    return launch_step_s<__half>(mode, general, vy, grid, st, L);
+}
+
+// ---------------------------------------------------------------------------
+// one lattice: memory regions, material, scale, tiles (shared by solver and batch)
+// ---------------------------------------------------------------------------
+struct LatticeMem {
+    void* buf[2] = {nullptr, nullptr};  // populations, creation precision
+    void* g = nullptr;                  // force, arithmetic type of creation precision
+    double* u = nullptr;                // 2 planes
+    void* pbuf[2] = {nullptr, nullptr}; // FP64 polish populations
+    double* pg = nullptr;               // FP64 force (polish)
+};
+
+inline size_t lattice_bytes(long long N, int prec, bool polish) {
+    size_t b = 2 * al(8 * N * elem_bytes(prec)) + al(2 * N * arith_bytes(prec)) + al(2 * N * 8);
+    if (polish && prec != LBM_FP64) b += 2 * al(8 * N * 8) + al(2 * N * 8);
+    return b;
+}
+
+inline void carve_lattice(char* base, long long N, int prec, bool polish, LatticeMem& m) {
+    size_t off = 0;
+    for (int i = 0; i < 2; ++i) {
+        m.buf[i] = base + off;
+        off += al(8 * N * elem_bytes(prec));
+    }
+    m.g = base + off;
+    off += al(2 * N * arith_bytes(prec));
+    m.u = reinterpret_cast<double*>(base + off);
+    off += al(2 * N * 8);
+    if (polish && prec != LBM_FP64) {
+        for (int i = 0; i < 2; ++i) {
+            m.pbuf[i] = base + off;
+            off += al(8 * N * 8);
+        }
+        m.pg = reinterpret_cast<double*>(base + off);
+        off += al(2 * N * 8);
+    }
+}
+
+struct Lattice {
+    int nx = 0, ny = 0;
+    long long N = 0;
+    int prec0 = LBM_FP64;  // creation precision
+    int prec = LBM_FP64;   // current storage precision
+    bool polish = false;
+    LatticeMem mem;
+    Rates rates;
+    double lam = 0, mu = 0;
+    bool has_material = false, has_force = false;
+    int e_scale = 0;  // half storage: stored = f * 2^-e
+    double gmax = 0;  // max |g| of the force (initial half scale)
+    int bx_log2 = 6, vy = 1;
+    int cur = 0;  // buffer with the state at flip 0
+
+    void* state_buf(int i) const {
+        return (prec == prec0) ? mem.buf[i] : mem.pbuf[i];
+    }
+    const void* force() const { return (prec == prec0) ? mem.g : (const void*)mem.pg; }
+    int tiles_x() const { return (nx + (1 << bx_log2) - 1) >> bx_log2; }
+    int tile_h() const { return (kBlock >> bx_log2) * vy; }
+    int tiles_y() const { return (ny + tile_h() - 1) / tile_h(); }
+    int nitems() const { return tiles_x() * tiles_y(); }
+
+    SlotDesc desc() const {
+        SlotDesc d;
+        std::memset(&d, 0, sizeof(d));
+        d.buf[0] = state_buf(0);
+        d.buf[1] = state_buf(1);
+        d.g = force();
+        d.u = mem.u;
+        d.plane = N;
+        d.nx = nx;
+        d.ny = ny;
+        d.cur = cur;
+        d.tiles_x = tiles_x();
+        d.tiles_y = tiles_y();
+        d.bx_log2 = bx_log2;
+        fill_coefs(d, rates);
+        const double sc = (prec == LBM_FP16) ? std::ldexp(1.0, -e_scale) : 1.0;
+        d.gscale = sc;
+        d.inv_scale = 1.0 / sc;
+        return d;
+    }
+    bool general() const { return rates.w12 != 1.0 || rates.w21 != 1.0 || rates.w22 != 1.0; }
+};
+
+// Upper bound of the number of tiles for any admissible tile shape.
+inline long long max_items(int nx, int ny) { return (long long)nx * ny / 256 + nx + ny + 2; }
+
+inline int default_bx_log2(int prec, int nx) {
+    (void)prec;
+    int b = 6;  // 64 x 4 threads
+    while (b > 3 && (1 << b) > 2 * nx) --b;
+    return b;
+}
+
+template <typename S>
+inline hipError_t launch_extract_u(const SlotDesc& d, int sel, double* ux, double* uy, hipStream_t st) {
+    hipLaunchKernelGGL(k_extract_u<S>, dim3(blocks_for(d.plane)), dim3(kBlock), 0, st, d, sel,
+                       ux, uy);
+    return hipGetLastError();
+}
+inline hipError_t extract_u(int prec, const SlotDesc& d, int sel, double* ux, double* uy,
+                     hipStream_t st) {
+    if (prec == LBM_FP64) return launch_extract_u<double>(d, sel, ux, uy, st);
+    if (prec == LBM_FP32) return launch_extract_u<float>(d, sel, ux, uy, st);
+    return launch_extract_u<__half>(d, sel, ux, uy, st);
+}
+
+template <typename S>
+inline hipError_t launch_stress(const SlotDesc& d, int sel, const Rates& r, double* a, double* b,
+                         double* c, hipStream_t st) {
+    hipLaunchKernelGGL(k_extract_stress<S>, dim3(blocks_for(d.plane)), dim3(kBlock), 0, st, d,
+                       sel, 1.0 - 0.5 * r.ws, 1.0 - 0.5 * r.wd, 1.0 - 0.5 * r.w11, a, b, c);
+    return hipGetLastError();
+}
+
+template <typename S>
+inline hipError_t launch_get_f(const SlotDesc& d, int sel, double* f, hipStream_t st) {
+    hipLaunchKernelGGL(k_get_f<S>, dim3(blocks_for(d.plane)), dim3(kBlock), 0, st, d, sel, f);
+    return hipGetLastError();
+}
+
+template <typename S>
+inline hipError_t launch_set_f(const SlotDesc& d, int sel, const double* f, double scale,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_set_f<S>, dim3(blocks_for(d.plane)), dim3(kBlock), 0, st, d, sel, f,
+                       scale);
+    return hipGetLastError();
+}
+
+template <typename S>
+inline hipError_t launch_stream_only(unsigned grid, hipStream_t st, const StepLaunch& L) {
+    hipLaunchKernelGGL(k_stream_only<S>, dim3(grid), dim3(kBlock), 0, st, L);
+    return hipGetLastError();
+}
+
+inline hipError_t zero_bytes(void* p, size_t bytes, hipStream_t st) {
+    const long long words = (long long)(bytes / 4);
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(blocks_for(words)), dim3(kBlock), 0, st,
+                       reinterpret_cast<unsigned int*>(p), words);
+    return hipGetLastError();
+}
+
+// Convert the FP64 force into the lattice's arithmetic type (and keep the
+// FP64 copy for the polish phase).
+inline hipError_t upload_force(const Lattice& L, const double* gx, const double* gy, hipStream_t st) {
+    hipError_t e;
+    const long long N = L.N;
+    if (L.prec0 == LBM_FP64) {
+        double* g = reinterpret_cast<double*>(L.mem.g);
+        if ((e = hipMemcpyAsync(g, gx, N * 8, hipMemcpyDeviceToDevice, st)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(g + N, gy, N * 8, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+            return e;
+    } else {
+        float* g = reinterpret_cast<float*>(L.mem.g);
+        hipLaunchKernelGGL(k_convert<float>, dim3(blocks_for(N)), dim3(kBlock), 0, st, gx, g, N);
+        hipLaunchKernelGGL(k_convert<float>, dim3(blocks_for(N)), dim3(kBlock), 0, st, gy, g + N,
+                           N);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (L.mem.pg) {
+            if ((e = hipMemcpyAsync(L.mem.pg, gx, N * 8, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+                return e;
+            if ((e = hipMemcpyAsync(L.mem.pg + N, gy, N * 8, hipMemcpyDeviceToDevice, st)) !=
+                hipSuccess)
+                return e;
+        }
+    }
+    return hipSuccess;
+}
+
+// Initial power-of-two scale for half storage: the steady state of a load g
+// is bounded by roughly max|g| / (mu k_min^2) with k_min = 2 pi / max(nx, ny);
+// the populations are O(|u|).  Chosen so that this bound maps to ~2^12.
+inline int initial_half_exponent(const Lattice& L, double gmax) {
+    if (!(gmax > 0.0)) return 0;
+    const double nmax = (double)std::max(L.nx, L.ny);
+    const double kmin = 2.0 * M_PI / nmax;
+    const double diff = std::min(L.mu, L.lam + L.mu);
+    double bound = gmax / (std::max(diff, 1e-300) * kmin * kmin) + gmax;
+    int e = (int)std::ceil(std::log2(bound / 4096.0));
+    return std::max(-100, std::min(100, e));
+}
+
+}  // namespace lbm_host

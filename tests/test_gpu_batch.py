@@ -1,0 +1,149 @@
+"""Batched lattices (one persistent launch per step over a tile work list)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2208_14870_amd import problem as P
+from gpu_common import dev, host, need_gpu, omega, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+GIB = 1 << 30
+
+
+def _batch(max_slots=16, arena=GIB):
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    return lbm.Batch(max_slots, arena)
+
+
+def _cases():
+    specs = [(64, 64, 0.3, (1, 1)), (96, 96, 0.1, (2, 1)), (33, 65, 0.45, (1, 2)),
+             (128, 40, 0.2, (3, 1)), (7, 5, 0.3, (1, 1)), (192, 192, 0.48, (4, 3))]
+    out = []
+    for nx, ny, nu, (kx, ky) in specs:
+        mat = P.Material.from_shear_poisson(1.0, nu)
+        u = P.trig_product((1e-3, 1e-3), ("s", "c"), ("c", "s"), 2 * np.pi * kx / nx,
+                           2 * np.pi * ky / ny)
+        out.append(P.manufactured_case(nx, mat, u, f"b{nx}x{ny}", ny=ny))
+    return out
+
+
+def test_batch_fp64_matches_oracle():
+    say("batch fp64 6 lattices 40 steps")
+    b = _batch()
+    cases = _cases()
+    slots = [b.add(c.nx, c.ny, c.material.lame_lambda, c.material.lame_mu, dev(c.gx), dev(c.gy),
+                   "fp64") for c in cases]
+    b.step(40)
+    for c, s in zip(cases, slots):
+        f = O.run(O.zero_state(c.nx, c.ny), c.gx, c.gy, omega(c.material), 40)
+        ox, oy = O.displacement(f, c.gx, c.gy)
+        ux, uy = (host(t) for t in b.displacement(s))
+        assert rel_l2(ux, ox, uy, oy) <= 1e-12, c.label
+
+
+def test_batch_residual_matches_single_solver_and_oracle():
+    """Residual of a checked chunk equals the single-lattice solver's and the
+    oracle's r(n - 1) after n steps."""
+    say("batch fp64 residual")
+    from paper_2208_14870_amd import lbm
+    c = _cases()[1]
+    b = _batch()
+    s = b.add(c.nx, c.ny, c.material.lame_lambda, c.material.lame_mu, dev(c.gx), dev(c.gy), "fp64")
+    b.step(30, check=True)
+    r, n = b.residuals()
+    assert n[s] == 30
+    f29 = O.run(O.zero_state(c.nx, c.ny), c.gx, c.gy, omega(c.material), 28)
+    u28 = O.displacement(f29, c.gx, c.gy)
+    f29 = O.run(f29, c.gx, c.gy, omega(c.material), 1)
+    u29 = O.displacement(f29, c.gx, c.gy)
+    want = O.residual(u29[0], u29[1], u28[0], u28[1])
+    assert r[s] == pytest.approx(want, rel=1e-9)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_alone_vs_mix_identical(prec):
+    """A lattice gives bit-identical displacement and residual alone and in a mix."""
+    say(f"batch alone vs mix {prec}")
+    cases = _cases()
+    probe = cases[2]
+    b1 = _batch()
+    s1 = b1.add(probe.nx, probe.ny, probe.material.lame_lambda, probe.material.lame_mu,
+                dev(probe.gx), dev(probe.gy), prec)
+    b1.step(100, check=True)
+    r1, _ = b1.residuals()
+    u1 = [host(t) for t in b1.displacement(s1)]
+    b2 = _batch()
+    ids = {}
+    for c in cases:
+        ids[c.label] = b2.add(c.nx, c.ny, c.material.lame_lambda, c.material.lame_mu,
+                              dev(c.gx), dev(c.gy), prec)
+    b2.step(100, check=True)
+    r2, _ = b2.residuals()
+    u2 = [host(t) for t in b2.displacement(ids[probe.label])]
+    np.testing.assert_array_equal(u1[0], u2[0])
+    np.testing.assert_array_equal(u1[1], u2[1])
+    assert r1[s1] == r2[ids[probe.label]]
+
+
+def test_join_and_leave_mid_run():
+    """Lattices added later and removals do not disturb the others."""
+    say("batch join/leave")
+    cases = _cases()
+    b = _batch()
+    a = b.add(cases[0].nx, cases[0].ny, cases[0].material.lame_lambda, cases[0].material.lame_mu,
+              dev(cases[0].gx), dev(cases[0].gy), "fp64")
+    x = b.add(cases[3].nx, cases[3].ny, cases[3].material.lame_lambda, cases[3].material.lame_mu,
+              dev(cases[3].gx), dev(cases[3].gy), "fp64")
+    b.step(17)
+    b.remove(x)
+    c = cases[4]
+    late = b.add(c.nx, c.ny, c.material.lame_lambda, c.material.lame_mu, dev(c.gx), dev(c.gy),
+                 "fp64")
+    b.step(23)
+    for case, slot, n in ((cases[0], a, 40), (c, late, 23)):
+        f = O.run(O.zero_state(case.nx, case.ny), case.gx, case.gy, omega(case.material), n)
+        ox, oy = O.displacement(f, case.gx, case.gy)
+        ux, uy = (host(t) for t in b.displacement(slot))
+        assert rel_l2(ux, ox, uy, oy) <= 1e-12
+
+
+def test_promote_to_fp64():
+    """FP32 lattice with polish reservation switches to FP64 mid-run."""
+    say("batch promote")
+    c = _cases()[0]
+    b = _batch()
+    s = b.add(c.nx, c.ny, c.material.lame_lambda, c.material.lame_mu, dev(c.gx), dev(c.gy),
+              "fp32", with_polish=True)
+    b.step(200)
+    b.promote(s)
+    b.step(300)
+    f = O.run(O.zero_state(c.nx, c.ny), c.gx, c.gy, omega(c.material), 500)
+    ox, oy = O.displacement(f, c.gx, c.gy)
+    ux, uy = (host(t) for t in b.displacement(s))
+    err = rel_l2(ux, ox, uy, oy)
+    say(f"  fp32->fp64 rel err vs oracle: {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_arena_admission():
+    """A lattice that does not fit is refused and nothing changes."""
+    say("batch admission")
+    from paper_2208_14870_amd import lbm
+    per = lbm.Batch.slot_bytes(256, 256, "fp32")
+    b = _batch(max_slots=64, arena=64 << 20)
+    c = P.single_1024(0.3, 1, 1, n=256)
+    got = []
+    while True:
+        s = b.add(256, 256, c.material.lame_lambda, c.material.lame_mu, dev(c.gx), dev(c.gy),
+                  "fp32")
+        if s is None:
+            break
+        got.append(s)
+    assert 1 <= len(got) <= (64 << 20) // per
+    active, used, largest = b.info()
+    assert active == len(got) and largest < per
+    b.remove(got[0])
+    assert b.add(256, 256, c.material.lame_lambda, c.material.lame_mu, dev(c.gx), dev(c.gy),
+                 "fp32") is not None

@@ -1,0 +1,328 @@
+"""GPU path (C ABI via the Python binding) against the FP64 CPU oracle.
+
+Bars: streaming/index arithmetic bit-exact; FP64 within 1e-12 relative;
+reduced precisions within tolerances derived from their rounding unit
+(stated per test).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2208_14870_amd import problem as P
+from gpu_common import dev, host, need_gpu, omega, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(nx, ny, prec="fp64", polish=False):
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    return lbm.Solver(nx, ny, prec, with_polish=polish)
+
+
+def _rand_state(nx, ny, seed, scale=1e-3):
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal((8, ny, nx)) * scale
+    gx = P.remove_mean(rng.standard_normal((ny, nx)) * scale * 0.1)
+    gy = P.remove_mean(rng.standard_normal((ny, nx)) * scale * 0.1)
+    return f, gx, gy
+
+
+# ---------------------------------------------------------------------------
+# streaming and state transfer: bit-exact
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec,nx,ny", [
+    ("fp64", 1, 1), ("fp64", 2, 2), ("fp64", 3, 3), ("fp64", 5, 3), ("fp64", 67, 33),
+    ("fp64", 256, 64), ("fp32", 2, 7), ("fp32", 130, 9), ("fp32", 64, 64), ("fp16", 3, 5),
+    ("fp16", 97, 31)])
+def test_streaming_bit_exact(prec, nx, ny):
+    say(f"streaming bit-exact {prec} {nx}x{ny}")
+    s = _solver(nx, ny, prec)
+    top = {"fp64": 1 << 40, "fp32": 1 << 23, "fp16": 2000}[prec]
+    rng = np.random.default_rng(nx * 1000 + ny)
+    f = rng.integers(-top, top, size=(8, ny, nx)).astype(np.float64)
+    s.set_populations(dev(f))
+    for steps in (1, 4):
+        s.stream_only(steps)
+        f = O.stream_only(f, steps)
+        np.testing.assert_array_equal(host(s.populations()), f)
+
+
+def test_populations_roundtrip_fp64():
+    say("populations roundtrip fp64 37x21")
+    s = _solver(37, 21)
+    f, _, _ = _rand_state(37, 21, 1)
+    s.set_populations(dev(f))
+    np.testing.assert_array_equal(host(s.populations()), f)
+
+
+# ---------------------------------------------------------------------------
+# FP64 parity
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nx,ny,steps", [(1, 1, 5), (2, 2, 7), (3, 4, 9), (32, 32, 100),
+                                         (67, 45, 50), (130, 7, 30), (64, 257, 20)])
+def test_fp64_steps_from_random_state(nx, ny, steps):
+    """Arbitrary state and force (ragged tiles, N = 1, 2): n steps agree to 1e-12."""
+    say(f"fp64 random state {nx}x{ny} steps {steps}")
+    mat = P.Material.from_shear_poisson(0.8, 0.25)
+    f0, gx, gy = _rand_state(nx, ny, nx + 7 * ny)
+    s = _solver(nx, ny)
+    s.set_material(mat.lame_lambda, mat.lame_mu)
+    s.set_body_force(dev(gx), dev(gy))
+    s.set_populations(dev(f0))
+    s.step(1)
+    f1 = O.run(f0, gx, gy, omega(mat), 1)
+    g1 = host(s.populations())
+    assert rel_l2(g1, f1) <= 1e-14
+    s.step(steps - 1)
+    fn = O.run(f1, gx, gy, omega(mat), steps - 1)
+    assert rel_l2(host(s.populations()), fn) <= 1e-12
+    ux, uy = (host(t) for t in s.displacement())
+    ox, oy = O.displacement(fn, gx, gy)
+    assert rel_l2(ux, ox, uy, oy) <= 1e-12
+
+
+def test_fp64_config_32_solve_matches_oracle():
+    """32 x 32, nu = 0.3, mu = 1, manufactured sinusoid, tol 1e-10, check every
+    step: identical stop step, displacement within 1e-12."""
+    say("fp64 single-32 solve_to_tol")
+    c = P.single_32()
+    s = _solver(32, 32)
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    n, r, st = s.solve_to_tol(1e-10, 100000, 1)
+    f, on, orr, ost = O.solve_to_tol(O.zero_state(32, 32), c.gx, c.gy, omega(c.material), 1e-10,
+                                     100000, 1)
+    assert st == 0 and ost == 0
+    assert n == on
+    assert r == pytest.approx(orr, rel=1e-8)
+    ux, uy = (host(t) for t in s.displacement())
+    ox, oy = O.displacement(f, c.gx, c.gy)
+    assert rel_l2(ux, ox, uy, oy) <= 1e-12
+    err = s.error_norms(dev(c.ux_exact), dev(c.uy_exact))
+    want = O.error_norms(ox, oy, c.ux_exact, c.uy_exact)
+    assert err["rel_l2"] == pytest.approx(want["rel_l2_plain"], rel=1e-9)
+
+
+@pytest.mark.parametrize("K", [2, 7, 64, 250])
+def test_fp64_check_interval_matches_oracle(K):
+    """Residual checks every K steps: same stop step and residual as the oracle."""
+    say(f"fp64 check interval {K}")
+    c = P.single_1024(0.3, 1, 1, n=48)
+    s = _solver(48, 48)
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    n, r, st = s.solve_to_tol(1e-9, 20000, K)
+    f, on, orr, ost = O.solve_to_tol(O.zero_state(48, 48), c.gx, c.gy, omega(c.material), 1e-9,
+                                     20000, K)
+    assert (st, n) == (ost, on)
+    assert r == pytest.approx(orr, rel=1e-7)
+    ux, uy = (host(t) for t in s.displacement())
+    ox, oy = O.displacement(f, c.gx, c.gy)
+    assert rel_l2(ux, ox, uy, oy) <= 1e-12
+
+
+def test_fp64_max_steps_not_converged():
+    say("fp64 max_steps")
+    c = P.single_32()
+    s = _solver(32, 32)
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    n, r, st = s.solve_to_tol(1e-14, 50, 10)
+    assert (n, st) == (50, 1)
+    f, on, orr, ost = O.solve_to_tol(O.zero_state(32, 32), c.gx, c.gy, omega(c.material), 1e-14,
+                                     50, 10)
+    assert (on, ost) == (50, 1)
+    assert r == pytest.approx(orr, rel=1e-9)
+    ux, uy = (host(t) for t in s.displacement())
+    ox, oy = O.displacement(f, c.gx, c.gy)
+    assert rel_l2(ux, ox, uy, oy) <= 1e-12
+
+
+def test_fp64_general_rates():
+    """theta = 0.4, omega_12 = omega_21 = 1.2, omega_22 = 0.8 (general path)."""
+    say("fp64 general rates")
+    nx, ny = 40, 24
+    mat = P.Material.from_shear_poisson(0.6, 0.35)
+    f0, gx, gy = _rand_state(nx, ny, 5)
+    s = _solver(nx, ny)
+    s.set_material(mat.lame_lambda, mat.lame_mu)
+    s.set_rates(0.4, 1.2, 1.2, 0.8)
+    s.set_body_force(dev(gx), dev(gy))
+    s.set_populations(dev(f0))
+    s.step(60)
+    om = O.omega_vector(mat.lame_lambda, mat.lame_mu, 0.4, 1.2, 1.2, 0.8)
+    fn = O.run(f0, gx, gy, om, 60, theta=0.4)
+    assert rel_l2(host(s.populations()), fn) <= 1e-12
+
+
+def test_fp64_stress_matches_oracle():
+    say("fp64 stress")
+    c = P.paper_e1(24)
+    s = _solver(24, 24)
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    s.step(300)
+    f = O.run(O.zero_state(24, 24), c.gx, c.gy, omega(c.material), 300)
+    want = O.stress(f, omega(c.material))
+    got = [host(t) for t in s.stress()]
+    for a, b in zip(got, want):
+        assert rel_l2(a, b) <= 1e-12
+
+
+@pytest.mark.parametrize("nx,ny,tile", [(96, 64, (5, 1)), (96, 64, (7, 2)), (100, 90, (4, 4)),
+                                        (33, 65, (0, 1)), (33, 65, (8, 4))])
+def test_fp64_tile_shapes(nx, ny, tile):
+    """Every tile shape gives the oracle's result (ragged edges included)."""
+    say(f"fp64 tile {tile} {nx}x{ny}")
+    mat = P.Material.from_shear_poisson(1.0, 0.45)
+    f0, gx, gy = _rand_state(nx, ny, 11)
+    s = _solver(nx, ny)
+    s.set_tile(*tile)
+    s.set_material(mat.lame_lambda, mat.lame_mu)
+    s.set_body_force(dev(gx), dev(gy))
+    s.set_populations(dev(f0))
+    s.step(25)
+    fn = O.run(f0, gx, gy, omega(mat), 25)
+    assert rel_l2(host(s.populations()), fn) <= 1e-12
+
+
+def test_fp64_full_size_1024_sampled():
+    """1024 x 1024 in the benchmark's launch configuration: 20 steps from a
+    random state against the oracle on the whole lattice."""
+    say("fp64 1024x1024 20 steps")
+    n = 1024
+    c = P.single_1024(0.45, 4, 3)
+    rng = np.random.default_rng(9)
+    f0 = rng.standard_normal((8, n, n)) * 1e-3
+    s = _solver(n, n)
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    s.set_populations(dev(f0))
+    s.step(20)
+    fn = O.run(f0, c.gx, c.gy, omega(c.material), 20)
+    assert rel_l2(host(s.populations()), fn) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# reduced precision (error against the FP64 oracle stated as a number)
+# ---------------------------------------------------------------------------
+
+def test_fp32_error_vs_oracle_config_32():
+    """FP32 storage + FP32 arithmetic, 32 x 32 solved to r <= 1e-6 (reachable in
+    FP32): displacement within 1e-5 relative of the FP64 oracle at the same
+    step count.  FP32 rounding (6e-8) amplified by the slowest mode's
+    1/(1 - lambda) ~ 30 steps and the residual stopping error stays below it."""
+    say("fp32 single-32")
+    c = P.single_32()
+    s = _solver(32, 32, "fp32")
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    n, r, st = s.solve_to_tol(1e-6, 10000, 1)
+    assert st == 0
+    f = O.run(O.zero_state(32, 32), c.gx, c.gy, omega(c.material), n)
+    ox, oy = O.displacement(f, c.gx, c.gy)
+    ux, uy = (host(t) for t in s.displacement())
+    err = rel_l2(ux, ox, uy, oy)
+    say(f"  fp32 rel err vs fp64 oracle at step {n}: {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_fp32_1024_error_vs_oracle():
+    """1024 x 1024, 20 steps from a random state: FP32 within 1e-6 of FP64."""
+    say("fp32 1024x1024 20 steps")
+    n = 1024
+    c = P.single_1024(0.3, 1, 1)
+    rng = np.random.default_rng(2)
+    f0 = rng.standard_normal((8, n, n)) * 1e-3
+    s = _solver(n, n, "fp32")
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    s.set_populations(dev(f0))
+    s.step(20)
+    fn = O.run(f0, c.gx, c.gy, omega(c.material), 20)
+    err = rel_l2(host(s.populations()), fn)
+    say(f"  fp32 population rel err: {err:.3e}")
+    assert err <= 1e-6
+
+
+def test_fp16_error_vs_oracle():
+    """Scaled FP16 storage, FP32 arithmetic: 64 x 64 manufactured problem
+    after 2000 steps; half rounding (4.9e-4) amplified by slow modes -- stated,
+    bound 5e-2."""
+    say("fp16 64x64")
+    c = P.single_1024(0.3, 1, 1, n=64)
+    s = _solver(64, 64, "fp16")
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    s.step(2000)
+    f = O.run(O.zero_state(64, 64), c.gx, c.gy, omega(c.material), 2000)
+    ox, oy = O.displacement(f, c.gx, c.gy)
+    ux, uy = (host(t) for t in s.displacement())
+    err = rel_l2(ux, ox, uy, oy)
+    say(f"  fp16 rel err vs fp64 oracle: {err:.3e}")
+    assert err <= 5e-2
+
+
+def test_fp32_polish_reaches_fp64_tolerance():
+    """FP32 storage with the FP64 polish phase reaches r <= 1e-11 and then agrees
+    with the FP64 steady state to the residual's stopping error."""
+    say("fp32 polish single-32")
+    c = P.single_32()
+    s = _solver(32, 32, "fp32", polish=True)
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    s.set_polish(1e-6)
+    n, r, st = s.solve_to_tol(1e-11, 100000, 1)
+    assert st == 0 and r <= 1e-11
+    from paper_2208_14870_amd import lbm
+    assert s.current_precision == lbm.FP64
+    f, on, _, _ = O.solve_to_tol(O.zero_state(32, 32), c.gx, c.gy, omega(c.material), 1e-13,
+                                 100000, 1)
+    ox, oy = O.displacement(f, c.gx, c.gy)
+    ux, uy = (host(t) for t in s.displacement())
+    err = rel_l2(ux, ox, uy, oy)
+    say(f"  polished rel err vs converged fp64 oracle: {err:.3e}")
+    assert err <= 1e-9
+
+
+# ---------------------------------------------------------------------------
+# failure handling
+# ---------------------------------------------------------------------------
+
+def test_divergence_is_reported():
+    """Unstable material of Sec. 7.3.5 (nu = -0.4, E~ = 0.082): the solve reports
+    LBM_E_DIVERGED and the state stays readable."""
+    say("fp64 divergence 48x48")
+    from paper_2208_14870_amd import lbm
+    c = P.gaussian_hill_case(48, P.Material.from_young_poisson(0.082, -0.4))
+    s = _solver(48, 48)
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    with pytest.raises(lbm.Diverged):
+        s.solve_to_tol(1e-10, 400000, 500)
+    s.displacement()
+
+
+def test_invalid_arguments():
+    say("argument validation")
+    from paper_2208_14870_amd import lbm
+    s = _solver(8, 8)
+    with pytest.raises(lbm.LbmError):
+        s.set_material(1.0, 0.0)
+    with pytest.raises(lbm.LbmError):
+        s.set_material(-3.0, 1.0)
+    with pytest.raises(lbm.LbmError):
+        s.step(1)  # no material / force yet
+    s.set_material(1.0, 1.0)
+    rng = np.random.default_rng(0)
+    assert s.set_body_force(dev(rng.standard_normal((8, 8)) + 1.0),
+                            dev(rng.standard_normal((8, 8)))) == 2  # non-zero mean warning
+    with pytest.raises(lbm.LbmError):
+        s.set_tile(9, 1)
+    with pytest.raises(lbm.LbmError):
+        s.solve_to_tol(1e-6, 10, 0)
