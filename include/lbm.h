@@ -165,10 +165,12 @@ int lbm_error_norms(lbm_solver *s, const double *ux_ref, const double *uy_ref, d
 int lbm_get_populations(lbm_solver *s, double *f);
 int lbm_set_populations(lbm_solver *s, const double *f);
 
-/* Tile shape of the step kernel: tile width 2^bx_log2 threads (0..8, the
- * height is 256 >> bx_log2 threads) and rows_per_thread in {1, 2, 4}.
- * Used by the autotuner; defaults are chosen per precision. */
-int lbm_set_tile(lbm_solver *s, int bx_log2, int rows_per_thread);
+/* Launch shape of the step kernel: tile width 2^bx_log2 threads (0..8; the
+ * tile height is 256 >> bx_log2 threads times rows_per_thread in {1, 2, 4})
+ * and blocks_per_cu: 0 launches one workgroup per tile, k > 0 launches a
+ * persistent grid of k workgroups per compute unit that walks the tiles.
+ * Results do not depend on the shape.  Used by the autotuner. */
+int lbm_set_tile(lbm_solver *s, int bx_log2, int rows_per_thread, int blocks_per_cu);
 
 /* Diagnostic: nsteps of streaming alone (no collision), for bit-exact checks
  * of the periodic index arithmetic (Eq. streaming, Sec. 6.1). */
@@ -222,8 +224,9 @@ int lbm_batch_promote(lbm_batch *b, int slot);
 /* Current displacement of one lattice (FP64 device arrays [ny][nx]). */
 int lbm_batch_get_displacement(lbm_batch *b, int slot, double *ux, double *uy);
 
-/* Tile shape for all lattices of the batch (see lbm_set_tile). */
-int lbm_batch_set_tile(lbm_batch *b, int bx_log2, int rows_per_thread);
+/* Launch shape for all lattices of the batch (see lbm_set_tile; bx_log2 in
+ * 3..8). */
+int lbm_batch_set_tile(lbm_batch *b, int bx_log2, int rows_per_thread, int blocks_per_cu);
 
 /* Number of active lattices, and arena bytes in use / free (largest hole). */
 int lbm_batch_info(const lbm_batch *b, int *active, size_t *used_bytes, size_t *largest_free);

@@ -1,0 +1,135 @@
+"""Launch-shape autotuner for the step kernel.
+
+Times candidate launch shapes (tile width, rows per thread, persistent grid
+or one workgroup per tile) with HIP events on the solver's stream and keeps
+the fastest.  Results are cached in a JSON file keyed by GPU architecture,
+storage precision, workload kind and a size bucket (log2 of the sites per
+step), so a shape is measured once per machine and size class.
+
+Tuning advances the state of the object it times; tune a scratch instance
+(or reset the solver afterwards).  The shape never changes results: every
+shape computes the same per-site arithmetic.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Callable, Dict, Iterable, List, Optional, Tuple
+
+import torch
+
+Shape = Tuple[int, int, int]  # (bx_log2, rows_per_thread, blocks_per_cu)
+
+DEFAULT_CACHE = os.environ.get("LBM_AUTOTUNE_CACHE",
+                               os.path.join(os.path.expanduser("~"), ".cache",
+                                            "lbm_elastic_autotune.json"))
+
+
+def candidates(nx: int, min_bx: int = 3) -> List[Shape]:
+    out = []
+    for b in (5, 6, 7, 8):
+        if b < min_bx or (1 << b) > max(2 * nx, 1 << min_bx):
+            continue
+        for v in (1, 2, 4):
+            for k in (0, 4):
+                out.append((b, v, k))
+    return out
+
+
+def _arch() -> str:
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def _key(kind: str, precision: str, sites: int) -> str:
+    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}"
+
+
+def _load(path: str) -> Dict[str, list]:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path: str, data: Dict[str, list]):
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def time_shapes(set_shape: Callable[[Shape], None], step: Callable[[int], None],
+                shapes: Iterable[Shape], sites: int, target_ms: float = 3.0,
+                repeats: int = 3) -> List[Tuple[float, Shape]]:
+    """Returns [(microseconds per step, shape)] sorted fastest first."""
+    res = []
+    for shp in shapes:
+        set_shape(shp)
+        step(4)  # warm the shape (graph capture, caches)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step(4)
+        e1.record()
+        torch.cuda.synchronize()
+        per = max(e0.elapsed_time(e1) / 4, 1e-4)
+        n = max(4, min(4000, int(target_ms / per)))
+        best = float("inf")
+        for _ in range(repeats):
+            e0.record()
+            step(n)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, 1e3 * e0.elapsed_time(e1) / n)
+        res.append((best, shp))
+    res.sort()
+    return res
+
+
+def tune_solver(solver, precision: str, cache_path: Optional[str] = DEFAULT_CACHE,
+                force: bool = False) -> Shape:
+    """Pick and apply the fastest launch shape for a single-lattice solver."""
+    sites = solver.nx * solver.ny
+    key = _key("single", precision, sites)
+    cache = _load(cache_path) if cache_path else {}
+    if not force and key in cache:
+        shp = tuple(cache[key])
+        solver.set_tile(*shp)
+        return shp
+    res = time_shapes(lambda s: solver.set_tile(*s), solver.step, candidates(solver.nx, 0),
+                      sites)
+    shp = res[0][1]
+    solver.set_tile(*shp)
+    if cache_path:
+        cache[key] = list(shp)
+        _store(cache_path, cache)
+    return shp
+
+
+def tune_batch(batch, precision: str, sites: int, cache_path: Optional[str] = DEFAULT_CACHE,
+               force: bool = False) -> Shape:
+    """Pick and apply the fastest launch shape for a batch (sites = total sites)."""
+    key = _key("batch", precision, sites)
+    cache = _load(cache_path) if cache_path else {}
+    if not force and key in cache:
+        shp = tuple(cache[key])
+        batch.set_tile(*shp)
+        return shp
+    res = time_shapes(lambda s: batch.set_tile(*s), lambda n: batch.step(n), candidates(64, 3),
+                      sites)
+    shp = res[0][1]
+    batch.set_tile(*shp)
+    if cache_path:
+        cache[key] = list(shp)
+        _store(cache_path, cache)
+    return shp

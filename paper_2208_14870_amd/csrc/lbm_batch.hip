@@ -149,7 +149,8 @@ struct lbm_batch {
     std::vector<BSlot> slots;
     int range_host[3][2] = {{0, 0}, {0, 0}, {0, 0}};
     long long phase = 0;
-    int bx_log2 = 6, vy = 1;
+    int bx_log2 = 6, vy = 2;
+    int blocks_per_cu = 0;  // 0: one workgroup per tile; k: persistent k per CU
     std::string err;
     std::map<std::tuple<long long, int, int, unsigned, unsigned, unsigned>, hipGraphExec_t> graphs;
 
@@ -170,9 +171,11 @@ struct lbm_batch {
     unsigned grid_for(int prec) const {
         const int n = range_host[prec][1] - range_host[prec][0];
         if (n <= 0) return 0;
+        // power-of-two buckets keep captured graphs valid while the list changes
         unsigned g = 8;
-        while (g < (unsigned)n && g < (unsigned)cus * 8) g <<= 1;
-        return std::min(g, (unsigned)cus * 8 / 8 * 8);
+        while (g < (unsigned)n) g <<= 1;
+        if (blocks_per_cu > 0) g = std::min(g, (unsigned)(cus * blocks_per_cu + 7) / 8 * 8);
+        return g;
     }
 
     hipError_t write_desc(int slot) {
@@ -232,6 +235,7 @@ struct lbm_batch {
         a.range = d_range + 2 * prec;
         a.partial = d_partial;
         a.flip = flip;
+        a.rows = vy;
         return a;
     }
 
@@ -381,6 +385,7 @@ int lbm_batch_add(lbm_batch* b, int nx, int ny, int precision, int with_polish, 
     L.nx = nx;
     L.ny = ny;
     L.N = N;
+    L.plane = plane_of(N);
     L.prec0 = L.prec = precision;
     L.polish = with_polish != 0 && precision != LBM_FP64;
     L.rates = r;
@@ -389,8 +394,8 @@ int lbm_batch_add(lbm_batch* b, int nx, int ny, int precision, int with_polish, 
     L.has_material = L.has_force = true;
     carve_lattice(b->base + b->heap_off + off, N, precision, L.polish, L.mem);
     hipError_t e = upload_force(L, gx, gy, b->stream);
-    if (e == hipSuccess) e = zero_bytes(L.mem.buf[0], 8 * N * elem_bytes(precision), b->stream);
-    if (e == hipSuccess) e = zero_bytes(L.mem.u, 2 * N * 8, b->stream);
+    if (e == hipSuccess) e = zero_bytes(L.mem.buf[0], 8 * L.plane * elem_bytes(precision), b->stream);
+    if (e == hipSuccess) e = zero_bytes(L.mem.u, 2 * L.plane * 8, b->stream);
     if (e != hipSuccess) {
         b->arena.release(off, need);
         s = BSlot();
@@ -440,13 +445,16 @@ int lbm_batch_remove(lbm_batch* b, int slot) {
     return b->rebuild();
 }
 
-int lbm_batch_set_tile(lbm_batch* b, int bx_log2, int rows_per_thread) {
+int lbm_batch_set_tile(lbm_batch* b, int bx_log2, int rows_per_thread, int blocks_per_cu) {
     if (!b) return LBM_E_ARG;
     if (bx_log2 < 3 || bx_log2 > 8 ||
-        !(rows_per_thread == 1 || rows_per_thread == 2 || rows_per_thread == 4))
-        return b->fail(LBM_E_ARG, "batch_set_tile: bx_log2 in 3..8, rows_per_thread in {1,2,4}");
+        !(rows_per_thread == 1 || rows_per_thread == 2 || rows_per_thread == 4) ||
+        blocks_per_cu < 0 || blocks_per_cu > 64)
+        return b->fail(LBM_E_ARG,
+                       "batch_set_tile: bx_log2 in 3..8, rows_per_thread in {1,2,4}, blocks_per_cu in 0..64");
     b->bx_log2 = bx_log2;
     b->vy = rows_per_thread;
+    b->blocks_per_cu = blocks_per_cu;
     b->drop_graphs();
     return b->rebuild();
 }
@@ -525,7 +533,7 @@ int lbm_batch_promote(lbm_batch* b, int slot) {
     if (L.prec == LBM_FP64) return LBM_OK;
     if (!L.polish) return b->fail(LBM_E_STATE, "batch_promote: lattice added without polish");
     const int sl = b->sel(s);
-    const long long n = 8 * L.N;
+    const long long n = 8 * L.plane;
     const double factor = (L.prec == LBM_FP16) ? std::ldexp(1.0, L.e_scale) : 1.0;
     if (L.prec == LBM_FP32)
         hipLaunchKernelGGL((k_recast<float, double>), dim3(blocks_for(n)), dim3(kBlock), 0,

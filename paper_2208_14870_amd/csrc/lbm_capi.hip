@@ -52,8 +52,11 @@ struct lbm_solver {
     long long phase = 0;  // launches since the descriptor was written
     long long steps = 0;
     double r_switch = 0.0;
+    int blocks_per_cu = 0;  // 0: one workgroup per tile; k: persistent k per CU
     std::string err;
-    std::map<std::tuple<long long, int, int>, hipGraphExec_t> graphs;
+    // captured chunks keyed by (plain steps, writeU/check kind, start parity,
+    // precision, rows per thread, general path, grid)
+    std::map<std::tuple<long long, int, int, int, int, int, unsigned>, hipGraphExec_t> graphs;
 
     int fail(int code, const std::string& m) {
         err = m;
@@ -87,10 +90,9 @@ struct lbm_solver {
                            d_items, 0, 0, d.tiles_x, nitems);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "descriptor upload");
-        const unsigned gmax = (unsigned)cus * 8;
         unsigned g = (unsigned)((nitems + 7) / 8 * 8);
-        grid = std::max(8u, std::min(g, gmax));
-        drop_graphs();
+        if (blocks_per_cu > 0) g = std::min(g, (unsigned)(cus * blocks_per_cu + 7) / 8 * 8);
+        grid = std::max(8u, g);
         return LBM_OK;
     }
 
@@ -101,11 +103,12 @@ struct lbm_solver {
         a.range = d_range;
         a.partial = d_partial;
         a.flip = flip;
+        a.rows = L.eff_vy();
         return a;
     }
 
     hipError_t enqueue_one(int mode, hipStream_t st, long long& ph) {
-        hipError_t e = launch_step(L.prec, mode, L.general(), L.general() ? 1 : L.vy, grid, st,
+        hipError_t e = launch_step(L.prec, mode, L.general(), L.eff_vy(), grid, st,
                                    launch_args((int)(ph & 1)));
         ++ph;
         return e;
@@ -151,11 +154,11 @@ struct lbm_solver {
     hipError_t run_graph(long long nplain, bool writeu, bool check) {
         const int flip0 = (int)(phase & 1);
         const int kind = (writeu ? 1 : 0) | (check ? 2 : 0);
-        auto key = std::make_tuple(nplain, kind, flip0);
+        auto key = std::make_tuple(nplain, kind, flip0, L.prec, L.eff_vy(), L.general() ? 1 : 0, grid);
         auto it = graphs.find(key);
         hipError_t e;
         if (it == graphs.end()) {
-            if (graphs.size() > 16) drop_graphs();
+            if (graphs.size() > 32) drop_graphs();
             hipGraph_t gr;
             if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
                 return e;
@@ -231,10 +234,10 @@ int lbm_create(int nx, int ny, int precision, int with_polish, void* workspace,
     L.nx = nx;
     L.ny = ny;
     L.N = (long long)nx * ny;
+    L.plane = plane_of(L.N);
     L.prec0 = L.prec = precision;
     L.polish = with_polish != 0 && precision != LBM_FP64;
-    L.bx_log2 = default_bx_log2(precision, nx);
-    L.vy = 1;
+    default_tile(precision, nx, ny, L.bx_log2, L.vy);
     char* base = reinterpret_cast<char*>(workspace);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -280,8 +283,8 @@ int lbm_reset(lbm_solver* s) {
     L.cur = 0;
     s->phase = 0;
     s->steps = 0;
-    hipError_t e = zero_bytes(L.mem.buf[0], 8 * L.N * elem_bytes(L.prec0), s->stream);
-    if (e == hipSuccess) e = zero_bytes(L.mem.u, 2 * L.N * 8, s->stream);
+    hipError_t e = zero_bytes(L.mem.buf[0], 8 * L.plane * elem_bytes(L.prec0), s->stream);
+    if (e == hipSuccess) e = zero_bytes(L.mem.u, 2 * L.plane * 8, s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "lbm_reset");
     return s->sync_desc();
 }
@@ -347,13 +350,16 @@ int lbm_set_body_force(lbm_solver* s, const double* gx, const double* gy) {
     return LBM_OK;
 }
 
-int lbm_set_tile(lbm_solver* s, int bx_log2, int rows_per_thread) {
+int lbm_set_tile(lbm_solver* s, int bx_log2, int rows_per_thread, int blocks_per_cu) {
     if (!s) return LBM_E_ARG;
     if (bx_log2 < 0 || bx_log2 > 8 ||
-        !(rows_per_thread == 1 || rows_per_thread == 2 || rows_per_thread == 4))
-        return s->fail(LBM_E_ARG, "set_tile: bx_log2 in 0..8, rows_per_thread in {1,2,4}");
+        !(rows_per_thread == 1 || rows_per_thread == 2 || rows_per_thread == 4) ||
+        blocks_per_cu < 0 || blocks_per_cu > 64)
+        return s->fail(LBM_E_ARG,
+                       "set_tile: bx_log2 in 0..8, rows_per_thread in {1,2,4}, blocks_per_cu in 0..64");
     s->L.bx_log2 = bx_log2;
     s->L.vy = rows_per_thread;
+    s->blocks_per_cu = blocks_per_cu;
     return s->sync_desc();
 }
 
@@ -384,7 +390,7 @@ int promote_solver(lbm_solver* s) {
     Lattice& L = s->L;
     if (L.prec == LBM_FP64 || !L.polish) return LBM_OK;
     const int sl = s->sel();
-    const long long n = 8 * L.N;
+    const long long n = 8 * L.plane;
     const double factor = (L.prec == LBM_FP16) ? std::ldexp(1.0, L.e_scale) : 1.0;
     if (L.prec == LBM_FP32)
         hipLaunchKernelGGL((k_recast<float, double>), dim3(blocks_for(n)), dim3(kBlock), 0,
@@ -399,9 +405,7 @@ int promote_solver(lbm_solver* s) {
     L.prec = LBM_FP64;
     L.cur = 0;
     s->phase = 0;
-    L.bx_log2 = default_bx_log2(LBM_FP64, L.nx);
-    L.vy = 1;
-    L.cur = 0;
+    default_tile(LBM_FP64, L.nx, L.ny, L.bx_log2, L.vy);
     // sync_desc folds phase into cur: phase is 0 so cur stays 0
     return s->sync_desc();
 }
@@ -415,7 +419,7 @@ int rescale_half(lbm_solver* s, double fmax_stored) {
     else if (fmax_stored < 1024.0) k = -(int)std::floor(std::log2(4096.0 / fmax_stored));
     if (k == 0) return LBM_OK;
     const int sl = s->sel();
-    const long long n = 8 * L.N;
+    const long long n = 8 * L.plane;
     __half* p = reinterpret_cast<__half*>(L.mem.buf[sl]);
     hipLaunchKernelGGL((k_recast<__half, __half>), dim3(blocks_for(n)), dim3(kBlock), 0, s->stream,
                        p, p, n, std::ldexp(1.0, -k));
@@ -527,7 +531,7 @@ int lbm_error_norms(lbm_solver* s, const double* ux_ref, const double* uy_ref, d
     if (!s->L.has_force) return s->fail(LBM_E_STATE, "error_norms: no body force set");
     // displacement into the u planes of the workspace, then the two-stage reduction
     double* ux = s->L.mem.u;
-    double* uy = s->L.mem.u + s->L.N;
+    double* uy = s->L.mem.u + s->L.plane;
     hipError_t e = extract_u(s->L.prec, s->L.desc(), s->sel(), ux, uy, s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "error_norms");
     hipLaunchKernelGGL(k_err_norms, dim3(kErrBlocks), dim3(kBlock), 0, s->stream, ux, uy, ux_ref,

@@ -248,6 +248,7 @@ struct StepLaunch {
     const int* range;   // device pair {begin, end}: items [begin, end) of the work list
     double* partial;    // 3 doubles per item (check mode)
     int flip;           // launch parity: source buffer = buf[cur ^ flip]
+    int rows;           // rows per thread of the tiles (the step kernel takes it as VY)
 };
 
 // Blocks are spread over the 8 XCDs round-robin by the hardware; item ranges
@@ -348,13 +349,16 @@ static __global__ __launch_bounds__(kBlock) void k_stream_only(StepLaunch L) {
         const S* src = reinterpret_cast<const S*>(d.buf[sel]);
         S* dst = reinterpret_cast<S*>(d.buf[sel ^ 1]);
         const int bxl = d.bx_log2;
+        const int th = kBlock >> bxl;
         const int x = (item.tx << bxl) + (threadIdx.x & ((1 << bxl) - 1));
-        const int y = item.ty * (kBlock >> bxl) + (threadIdx.x >> bxl);
-        if (x >= d.nx || y >= d.ny) continue;
-        C f[8];
-        gather<S>(src, d.plane, d.nx, d.ny, x, y, f);
-        const long long s = (long long)y * d.nx + x;
-        for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * d.plane + s, f[q]);
+        for (int j = 0; j < L.rows; ++j) {
+            const int y = item.ty * th * L.rows + (threadIdx.x >> bxl) + j * th;
+            if (x >= d.nx || y >= d.ny) continue;
+            C f[8];
+            gather<S>(src, d.plane, d.nx, d.ny, x, y, f);
+            const long long s = (long long)y * d.nx + x;
+            for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * d.plane + s, f[q]);
+        }
     }
 }
 
@@ -401,7 +405,7 @@ static __global__ __launch_bounds__(kBlock) void k_extract_u(SlotDesc d, int sel
                                                       double* uy) {
     using C = typename Store<S>::C;
     const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= d.plane) return;
+    if (s >= (long long)d.nx * d.ny) return;
     const int x = (int)(s % d.nx), y = (int)(s / d.nx);
     C f[8];
     gather<S>(reinterpret_cast<const S*>(d.buf[sel]), d.plane, d.nx, d.ny, x, y, f);
@@ -422,7 +426,7 @@ static __global__ __launch_bounds__(kBlock) void k_extract_stress(SlotDesc d, in
                                                            double* syy, double* sxy) {
     using C = typename Store<S>::C;
     const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= d.plane) return;
+    if (s >= (long long)d.nx * d.ny) return;
     const int x = (int)(s % d.nx), y = (int)(s / d.nx);
     C f[8];
     gather<S>(reinterpret_cast<const S*>(d.buf[sel]), d.plane, d.nx, d.ny, x, y, f);
@@ -442,11 +446,12 @@ template <typename S>
 static __global__ __launch_bounds__(kBlock) void k_get_f(SlotDesc d, int sel, double* out) {
     using C = typename Store<S>::C;
     const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= d.plane) return;
+    if (s >= (long long)d.nx * d.ny) return;
     const int x = (int)(s % d.nx), y = (int)(s / d.nx);
     C f[8];
     gather<S>(reinterpret_cast<const S*>(d.buf[sel]), d.plane, d.nx, d.ny, x, y, f);
-    for (int q = 0; q < 8; ++q) out[q * d.plane + s] = (double)f[q] * d.inv_scale;
+    const long long N = (long long)d.nx * d.ny;  // external layout [8][ny][nx]
+    for (int q = 0; q < 8; ++q) out[q * N + s] = (double)f[q] * d.inv_scale;
 }
 
 // Load a state f(n) given in the paper's order: the stored field is
@@ -455,17 +460,18 @@ template <typename S>
 static __global__ __launch_bounds__(kBlock) void k_set_f(SlotDesc d, int sel, const double* in,
                                                   double scale) {
     const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= d.plane) return;
+    if (s >= (long long)d.nx * d.ny) return;
     const int x = (int)(s % d.nx), y = (int)(s / d.nx);
     const int xm = (x == 0) ? d.nx - 1 : x - 1, xp = (x == d.nx - 1) ? 0 : x + 1;
     const int ym = (y == 0) ? d.ny - 1 : y - 1, yp = (y == d.ny - 1) ? 0 : y + 1;
     S* dst = reinterpret_cast<S*>(d.buf[sel]);
+    const long long N = (long long)d.nx * d.ny;  // external layout [8][ny][nx]
     const int cx[8] = {1, 0, -1, 0, 1, -1, -1, 1};
     const int cy[8] = {0, 1, 0, -1, 1, 1, -1, -1};
     for (int q = 0; q < 8; ++q) {
         const int xs = cx[q] > 0 ? xp : (cx[q] < 0 ? xm : x);
         const int ys = cy[q] > 0 ? yp : (cy[q] < 0 ? ym : y);
-        const double v = in[q * d.plane + (long long)ys * d.nx + xs] * scale;
+        const double v = in[q * N + (long long)ys * d.nx + xs] * scale;
         Store<S>::st(dst + q * d.plane + s, (typename Store<S>::C)v);
     }
 }

@@ -110,35 +110,48 @@ struct LatticeMem {
     double* pg = nullptr;               // FP64 force (polish)
 };
 
+// Elements between consecutive planes of one array (populations, force,
+// displacement).  Large planes get 1024 elements of padding so that the 18
+// concurrent streams of a step do not start on the same HBM channels (a
+// power-of-two plane size otherwise aligns them); small planes only round up
+// to 64 elements.
+inline long long plane_of(long long N) {
+    const long long r = (N + 63) / 64 * 64;
+    return N >= (1LL << 16) ? r + 1024 : r;
+}
+
 inline size_t lattice_bytes(long long N, int prec, bool polish) {
-    size_t b = 2 * al(8 * N * elem_bytes(prec)) + al(2 * N * arith_bytes(prec)) + al(2 * N * 8);
-    if (polish && prec != LBM_FP64) b += 2 * al(8 * N * 8) + al(2 * N * 8);
+    const long long P = plane_of(N);
+    size_t b = 2 * al(8 * P * elem_bytes(prec)) + al(2 * P * arith_bytes(prec)) + al(2 * P * 8);
+    if (polish && prec != LBM_FP64) b += 2 * al(8 * P * 8) + al(2 * P * 8);
     return b;
 }
 
 inline void carve_lattice(char* base, long long N, int prec, bool polish, LatticeMem& m) {
+    const long long P = plane_of(N);
     size_t off = 0;
     for (int i = 0; i < 2; ++i) {
         m.buf[i] = base + off;
-        off += al(8 * N * elem_bytes(prec));
+        off += al(8 * P * elem_bytes(prec));
     }
     m.g = base + off;
-    off += al(2 * N * arith_bytes(prec));
+    off += al(2 * P * arith_bytes(prec));
     m.u = reinterpret_cast<double*>(base + off);
-    off += al(2 * N * 8);
+    off += al(2 * P * 8);
     if (polish && prec != LBM_FP64) {
         for (int i = 0; i < 2; ++i) {
             m.pbuf[i] = base + off;
-            off += al(8 * N * 8);
+            off += al(8 * P * 8);
         }
         m.pg = reinterpret_cast<double*>(base + off);
-        off += al(2 * N * 8);
+        off += al(2 * P * 8);
     }
 }
 
 struct Lattice {
     int nx = 0, ny = 0;
-    long long N = 0;
+    long long N = 0;      // sites
+    long long plane = 0;  // elements between planes (>= N, see plane_of)
     int prec0 = LBM_FP64;  // creation precision
     int prec = LBM_FP64;   // current storage precision
     bool polish = false;
@@ -156,7 +169,9 @@ struct Lattice {
     }
     const void* force() const { return (prec == prec0) ? mem.g : (const void*)mem.pg; }
     int tiles_x() const { return (nx + (1 << bx_log2) - 1) >> bx_log2; }
-    int tile_h() const { return (kBlock >> bx_log2) * vy; }
+    // the general-rates variant is instantiated for one row per thread only
+    int eff_vy() const { return general() ? 1 : vy; }
+    int tile_h() const { return (kBlock >> bx_log2) * eff_vy(); }
     int tiles_y() const { return (ny + tile_h() - 1) / tile_h(); }
     int nitems() const { return tiles_x() * tiles_y(); }
 
@@ -167,7 +182,7 @@ struct Lattice {
         d.buf[1] = state_buf(1);
         d.g = force();
         d.u = mem.u;
-        d.plane = N;
+        d.plane = plane;
         d.nx = nx;
         d.ny = ny;
         d.cur = cur;
@@ -186,16 +201,27 @@ struct Lattice {
 // Upper bound of the number of tiles for any admissible tile shape.
 inline long long max_items(int nx, int ny) { return (long long)nx * ny / 256 + nx + ny + 2; }
 
-inline int default_bx_log2(int prec, int nx) {
-    (void)prec;
-    int b = 6;  // 64 x 4 threads
-    while (b > 3 && (1 << b) > 2 * nx) --b;
-    return b;
+// Default launch shape per storage precision and lattice size (measured on
+// MI355X: one workgroup per tile; wide tiles; several rows per thread for
+// lattices whose step is short enough that launch overhead matters).
+inline void default_tile(int prec, int nx, int ny, int& bx_log2, int& vy) {
+    const bool big = (long long)nx * ny >= (1LL << 22);
+    if (prec == LBM_FP64) {
+        bx_log2 = 7;
+        vy = 1;
+    } else if (prec == LBM_FP32) {
+        bx_log2 = 8;
+        vy = big ? 1 : 4;
+    } else {
+        bx_log2 = big ? 6 : 7;
+        vy = 4;
+    }
+    while (bx_log2 > 3 && (1 << bx_log2) > 2 * nx) --bx_log2;
 }
 
 template <typename S>
 inline hipError_t launch_extract_u(const SlotDesc& d, int sel, double* ux, double* uy, hipStream_t st) {
-    hipLaunchKernelGGL(k_extract_u<S>, dim3(blocks_for(d.plane)), dim3(kBlock), 0, st, d, sel,
+    hipLaunchKernelGGL(k_extract_u<S>, dim3(blocks_for((long long)d.nx * d.ny)), dim3(kBlock), 0, st, d, sel,
                        ux, uy);
     return hipGetLastError();
 }
@@ -209,21 +235,21 @@ inline hipError_t extract_u(int prec, const SlotDesc& d, int sel, double* ux, do
 template <typename S>
 inline hipError_t launch_stress(const SlotDesc& d, int sel, const Rates& r, double* a, double* b,
                          double* c, hipStream_t st) {
-    hipLaunchKernelGGL(k_extract_stress<S>, dim3(blocks_for(d.plane)), dim3(kBlock), 0, st, d,
+    hipLaunchKernelGGL(k_extract_stress<S>, dim3(blocks_for((long long)d.nx * d.ny)), dim3(kBlock), 0, st, d,
                        sel, 1.0 - 0.5 * r.ws, 1.0 - 0.5 * r.wd, 1.0 - 0.5 * r.w11, a, b, c);
     return hipGetLastError();
 }
 
 template <typename S>
 inline hipError_t launch_get_f(const SlotDesc& d, int sel, double* f, hipStream_t st) {
-    hipLaunchKernelGGL(k_get_f<S>, dim3(blocks_for(d.plane)), dim3(kBlock), 0, st, d, sel, f);
+    hipLaunchKernelGGL(k_get_f<S>, dim3(blocks_for((long long)d.nx * d.ny)), dim3(kBlock), 0, st, d, sel, f);
     return hipGetLastError();
 }
 
 template <typename S>
 inline hipError_t launch_set_f(const SlotDesc& d, int sel, const double* f, double scale,
                         hipStream_t st) {
-    hipLaunchKernelGGL(k_set_f<S>, dim3(blocks_for(d.plane)), dim3(kBlock), 0, st, d, sel, f,
+    hipLaunchKernelGGL(k_set_f<S>, dim3(blocks_for((long long)d.nx * d.ny)), dim3(kBlock), 0, st, d, sel, f,
                        scale);
     return hipGetLastError();
 }
@@ -246,22 +272,22 @@ inline hipError_t zero_bytes(void* p, size_t bytes, hipStream_t st) {
 // FP64 copy for the polish phase).
 inline hipError_t upload_force(const Lattice& L, const double* gx, const double* gy, hipStream_t st) {
     hipError_t e;
-    const long long N = L.N;
+    const long long N = L.N, P = L.plane;
     if (L.prec0 == LBM_FP64) {
         double* g = reinterpret_cast<double*>(L.mem.g);
         if ((e = hipMemcpyAsync(g, gx, N * 8, hipMemcpyDeviceToDevice, st)) != hipSuccess) return e;
-        if ((e = hipMemcpyAsync(g + N, gy, N * 8, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        if ((e = hipMemcpyAsync(g + P, gy, N * 8, hipMemcpyDeviceToDevice, st)) != hipSuccess)
             return e;
     } else {
         float* g = reinterpret_cast<float*>(L.mem.g);
         hipLaunchKernelGGL(k_convert<float>, dim3(blocks_for(N)), dim3(kBlock), 0, st, gx, g, N);
-        hipLaunchKernelGGL(k_convert<float>, dim3(blocks_for(N)), dim3(kBlock), 0, st, gy, g + N,
+        hipLaunchKernelGGL(k_convert<float>, dim3(blocks_for(N)), dim3(kBlock), 0, st, gy, g + P,
                            N);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (L.mem.pg) {
             if ((e = hipMemcpyAsync(L.mem.pg, gx, N * 8, hipMemcpyDeviceToDevice, st)) != hipSuccess)
                 return e;
-            if ((e = hipMemcpyAsync(L.mem.pg + N, gy, N * 8, hipMemcpyDeviceToDevice, st)) !=
+            if ((e = hipMemcpyAsync(L.mem.pg + P, gy, N * 8, hipMemcpyDeviceToDevice, st)) !=
                 hipSuccess)
                 return e;
         }

@@ -66,7 +66,7 @@ def load() -> ctypes.CDLL:
         "lbm_error_norms": (i, [vp, vp, vp, pd]),
         "lbm_get_populations": (i, [vp, vp]),
         "lbm_set_populations": (i, [vp, vp]),
-        "lbm_set_tile": (i, [vp, i, i]),
+        "lbm_set_tile": (i, [vp, i, i, i]),
         "lbm_debug_stream_only": (i, [vp, ll]),
         "lbm_last_error": (ctypes.c_char_p, [vp]),
         "lbm_batch_slot_bytes": (sz, [i, i, i, i]),
@@ -78,7 +78,7 @@ def load() -> ctypes.CDLL:
         "lbm_batch_residuals": (i, [vp, pd, pll]),
         "lbm_batch_promote": (i, [vp, i]),
         "lbm_batch_get_displacement": (i, [vp, i, vp, vp]),
-        "lbm_batch_set_tile": (i, [vp, i, i]),
+        "lbm_batch_set_tile": (i, [vp, i, i, i]),
         "lbm_batch_info": (i, [vp, pi, ctypes.POINTER(sz), ctypes.POINTER(sz)]),
         "lbm_batch_last_error": (ctypes.c_char_p, [vp]),
     }
@@ -205,8 +205,9 @@ class Solver:
     def steps_done(self) -> int:
         return self.lib.lbm_steps_done(self.h)
 
-    def set_tile(self, bx_log2: int, rows_per_thread: int):
-        self._check(self.lib.lbm_set_tile(self.h, int(bx_log2), int(rows_per_thread)))
+    def set_tile(self, bx_log2: int, rows_per_thread: int, blocks_per_cu: int = 0):
+        self._check(self.lib.lbm_set_tile(self.h, int(bx_log2), int(rows_per_thread),
+                                          int(blocks_per_cu)))
 
     def displacement(self, out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None):
         shp = (self.ny, self.nx)
@@ -324,8 +325,9 @@ class Batch:
     def promote(self, slot: int):
         self._check(self.lib.lbm_batch_promote(self.h, int(slot)))
 
-    def set_tile(self, bx_log2: int, rows_per_thread: int):
-        self._check(self.lib.lbm_batch_set_tile(self.h, int(bx_log2), int(rows_per_thread)))
+    def set_tile(self, bx_log2: int, rows_per_thread: int, blocks_per_cu: int = 0):
+        self._check(self.lib.lbm_batch_set_tile(self.h, int(bx_log2), int(rows_per_thread),
+                                                int(blocks_per_cu)))
 
     def displacement(self, slot: int):
         shp = self.shapes[slot]

@@ -1,0 +1,180 @@
+"""Continuous-batching server for periodic elasticity solves.
+
+Requests (a lattice size, a material and a body load) arrive over time.  The
+server keeps one device arena; a request is admitted as soon as a slot and
+its HBM footprint (FP32 state plus the FP64 polish reservation) are free,
+joins the resident batch at the next chunk boundary, and every admitted
+lattice advances in the same persistent step launches.  After each chunk of
+`chunk` steps the FP64 residual of every lattice is read; a lattice in FP32
+switches to FP64 storage once its residual reaches `r_switch` or stops
+decreasing, and retires when r <= tol: its displacement is copied to the host
+and its memory returns to the arena.  Latency = result on host - arrival.
+
+Each lattice steps whole chunks from its admission on, with its own promote
+and retire decisions taken only from its own residuals, so its result is
+the same alone and in any mix (the per-site arithmetic and the per-lattice
+reduction order do not depend on the other lattices).
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from collections import deque
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import lbm
+from .problem import Case, Request
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    n: int
+    t_arrival: float
+    t_admit: float
+    t_done: float
+    steps: int
+    residual: float
+    promoted_at: int
+    ux: Optional[np.ndarray] = None
+    uy: Optional[np.ndarray] = None
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+@dataclasses.dataclass
+class _Active:
+    req: Request
+    case: Case
+    t_admit: float
+    last_r: float = float("inf")
+    nondecreasing: int = 0
+    promoted_at: int = -1
+    g: tuple = ()
+
+
+class Server:
+    def __init__(self, arena_bytes: int, max_slots: int = 1024, chunk: int = 200,
+                 tol: float = 1e-8, r_switch: float = 1e-6, precision: str = "fp32",
+                 polish: bool = True, max_steps: int = 10 ** 8, keep_results: bool = False,
+                 tile: Optional[tuple] = None):
+        self.batch = lbm.Batch(max_slots, arena_bytes)
+        if tile is not None:
+            self.batch.set_tile(*tile)
+        self.chunk = int(chunk)
+        self.tol = tol
+        self.r_switch = r_switch
+        self.precision = precision
+        self.polish = polish and precision != "fp64"
+        self.max_steps = max_steps
+        self.keep = keep_results
+        self.active: Dict[int, _Active] = {}
+        self.results: List[Result] = []
+        self.failed: List[int] = []
+        self.site_updates = 0
+
+    def footprint(self, n: int) -> int:
+        return lbm.Batch.slot_bytes(n, n, self.precision, self.polish)
+
+    def _admit(self, req: Request, case: Case, now: float) -> bool:
+        gx = torch.from_numpy(case.gx).cuda()
+        gy = torch.from_numpy(case.gy).cuda()
+        slot = self.batch.add(case.nx, case.ny, case.material.lame_lambda, case.material.lame_mu,
+                              gx, gy, self.precision, self.polish)
+        if slot is None:
+            return False
+        self.active[slot] = _Active(req, case, now, g=(gx, gy))
+        return True
+
+    def _retire(self, slot: int, a: _Active, steps: int, r: float, now_fn):
+        ux, uy = self.batch.displacement(slot)
+        hx, hy = ux.cpu().numpy(), uy.cpu().numpy()  # blocking copy to host
+        t = now_fn()
+        self.results.append(Result(a.req.rid, a.req.n, a.req.t_arrival, a.t_admit, t, steps, r,
+                                   a.promoted_at, hx if self.keep else None,
+                                   hy if self.keep else None))
+        self.batch.remove(slot)
+        del self.active[slot]
+
+    def run(self, requests: List[Request], admit_window_s: float, wall_budget_s: float,
+            cases: Optional[Dict[int, Case]] = None) -> dict:
+        """Serve `requests` (arrival times relative to the start).  Arrivals
+        after `admit_window_s` are not offered; the loop stops when everything
+        offered has retired or after `wall_budget_s` seconds."""
+        pending = deque(sorted((r for r in requests if r.t_arrival < admit_window_s),
+                               key=lambda r: r.t_arrival))
+        offered = len(pending)
+        queue: deque = deque()
+        t0 = time.perf_counter()
+
+        def now():
+            return time.perf_counter() - t0
+
+        gpu_time = 0.0
+        while True:
+            t = now()
+            while pending and pending[0].t_arrival <= t:
+                queue.append(pending.popleft())
+            # admission: arrival order, backfilling smaller requests that fit
+            skipped = deque()
+            while queue:
+                req = queue.popleft()
+                case = cases[req.rid] if cases is not None else req.case()
+                if not self._admit(req, case, now()):
+                    skipped.append(req)
+                    if len(skipped) > 64:
+                        break
+            skipped.extend(queue)
+            queue = skipped
+            if self.active:
+                g0 = time.perf_counter()
+                self.batch.step(self.chunk, check=True)
+                r, steps = self.batch.residuals()
+                gpu_time += time.perf_counter() - g0
+                for slot in list(self.active):
+                    a = self.active[slot]
+                    self.site_updates += a.case.nx * a.case.ny * self.chunk
+                    rs = r[slot]
+                    if not np.isfinite(rs):
+                        self.failed.append(a.req.rid)
+                        self.batch.remove(slot)
+                        del self.active[slot]
+                        continue
+                    if rs <= self.tol or steps[slot] >= self.max_steps:
+                        self._retire(slot, a, steps[slot], rs, now)
+                        continue
+                    if self.polish and a.promoted_at < 0:
+                        a.nondecreasing = a.nondecreasing + 1 if rs >= a.last_r else 0
+                        if rs <= self.r_switch or a.nondecreasing >= 2:
+                            self.batch.promote(slot)
+                            a.promoted_at = steps[slot]
+                    a.last_r = rs
+            elif not pending and not queue:
+                break
+            else:
+                nxt = pending[0].t_arrival if pending else t
+                time.sleep(max(0.0, min(nxt - now(), 0.005)))
+            if now() > wall_budget_s:
+                break
+        elapsed = now()
+        lat = np.array([x.latency for x in self.results]) if self.results else np.array([])
+        return {
+            "offered": offered,
+            "completed": len(self.results),
+            "failed": len(self.failed),
+            "backlog": len(queue) + len(pending) + len(self.active),
+            "elapsed_s": elapsed,
+            "solves_per_s": len(self.results) / elapsed if elapsed > 0 else 0.0,
+            "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
+            "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
+            "gpu_busy_s": gpu_time,
+            "mlups_while_busy": self.site_updates / gpu_time / 1e6 if gpu_time > 0 else 0.0,
+        }
+
+    def close(self):
+        self.batch.close()
