@@ -123,6 +123,77 @@ def hbm_probe(prec, steps=200):
     return {"mlups": sites / us, "us_per_step": us, "gbs": gbs, "frac": gbs / PEAK_HBM_GBS}
 
 
+def batch_run(prec: str, nlat: int = 512, steps: int = 2000, chunk: int = 100):
+    """Batched workload: `nlat` lattices (seed 4, sides {64..512}, nu ~ U[0.05, 0.48]),
+    one launch per step over the tile work list, graph-replayed chunks with a
+    residual check at the end of each chunk."""
+    import torch
+    from paper_2208_14870_amd import autotune, lbm, problem as P
+    cases = P.batch_cases(nlat, seed=4)
+    sites = sum(c.nx * c.ny for c in cases)
+    arena = int(sites * lbm.Batch.slot_bytes(1024, 1024, prec) / (1024 * 1024) * 1.3) + (1 << 30)
+    b = lbm.Batch(nlat + 8, arena)
+    for c in cases:
+        b.add(c.nx, c.ny, c.material.lame_lambda, c.material.lame_mu,
+              torch.from_numpy(c.gx).cuda(), torch.from_numpy(c.gy).cuda(), prec)
+    shape = autotune.tune_batch(b, prec, sites)
+    b.step(chunk, check=True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps // chunk):
+        b.step(chunk, check=True)
+        b.residuals()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n = steps // chunk * chunk
+    us = 1e3 * e0.elapsed_time(e1) / n
+    b.close()
+    gbs = BYTES_PER_SITE[prec] * sites / (us * 1e-6) / 1e9
+    return {"lattices": nlat, "sites": sites, "steps": n, "mlups": sites * n / wall / 1e6,
+            "us_per_step": round(us, 2), "gbs": round(gbs, 1),
+            "frac": round(gbs / PEAK_HBM_GBS, 4), "tile": list(shape)}
+
+
+def batch_solves(prec: str, nlat: int = 512, tol: float = 1e-6, chunk: int = 200):
+    """Solve every lattice of the batched workload to r <= tol with per-lattice
+    retirement (FP32 switches to FP64 only if its residual stalls)."""
+    import torch
+    from paper_2208_14870_amd import lbm, problem as P
+    from paper_2208_14870_amd.serving import Server
+    cases = P.batch_cases(nlat, seed=4)
+    reqs = [P.Request(i, 0.0, c.nx, c.material.poisson, 0) for i, c in enumerate(cases)]
+    sites = sum(c.nx * c.ny for c in cases)
+    arena = int(sites * lbm.Batch.slot_bytes(1024, 1024, prec, True) / (1024 * 1024) * 1.3)
+    srv = Server(arena + (1 << 30), max_slots=nlat + 8, chunk=chunk, tol=tol, r_switch=0.0,
+                 precision=prec, polish=(prec != "fp64"), keep_results=True)
+    st = srv.run(reqs, 1.0, 600.0, cases={i: c for i, c in enumerate(cases)})
+    srv.close()
+    res = {r.rid: r for r in srv.results}
+    return st, res
+
+
+def serving_run(rate: float = 2000.0, window: float = 1.0, budget: float = 25.0):
+    """Poisson arrivals (seed 5), sides log-uniform 64..2048, 8-mode loads, tol 1e-8,
+    FP32 storage with FP64 polish, admission by arena footprint."""
+    import torch
+    from paper_2208_14870_amd import problem as P
+    from paper_2208_14870_amd.serving import Server
+    reqs = P.request_stream(rate, window, seed=5)
+    free, _ = torch.cuda.mem_get_info()
+    arena = min(64 << 30, int(free * 0.5))
+    srv = Server(arena, max_slots=4096, chunk=200, tol=1e-8, r_switch=1e-6)
+    st = srv.run(reqs, window, budget)
+    srv.close()
+    st["offered_rate_hz"] = rate
+    st["admission_window_s"] = window
+    st["arena_bytes"] = arena
+    return st
+
+
 def cpu_baseline(seconds: float):
     """The FP64 CPU oracle, as it stands, on a bounded sample of the workload
     (the first 1024 x 1024 case), timed on this host's cores."""
@@ -226,6 +297,29 @@ def main():
         log("HBM-bound probe: 8192x8192 FP32 / FP16")
         out["hbm_8192"] = {p: {k: round(v, 4) for k, v in hbm_probe(p).items()}
                            for p in ("fp32", "fp16")}
+        log("batched: 512 lattices FP32 / FP64, 2000 steps")
+        out["batch"] = {"fp32": batch_run("fp32"), "fp64": batch_run("fp64")}
+        log("batched solves to r <= 1e-6 (FP32 vs FP64)")
+        s32, res32 = batch_solves("fp32")
+        s64, res64 = batch_solves("fp64")
+        errs = []
+        for rid, r64 in res64.items():
+            r32 = res32.get(rid)
+            if r32 is None:
+                continue
+            num = float(((r32.ux - r64.ux) ** 2).sum() + ((r32.uy - r64.uy) ** 2).sum())
+            den = float((r64.ux ** 2).sum() + (r64.uy ** 2).sum())
+            errs.append(math.sqrt(num / den))
+        out["batch"]["solves"] = {
+            "tol": 1e-6,
+            "fp32": {k: s32[k] for k in ("completed", "elapsed_s", "solves_per_s",
+                                         "p50_latency_s", "p99_latency_s")},
+            "fp64": {k: s64[k] for k in ("completed", "elapsed_s", "solves_per_s",
+                                         "p50_latency_s", "p99_latency_s")},
+            "fp32_vs_fp64_rel_l2_max": max(errs) if errs else None,
+            "fp32_vs_fp64_rel_l2_median": sorted(errs)[len(errs) // 2] if errs else None}
+        log("serving: Poisson 2000 req/s, sides 64..2048, tol 1e-8")
+        out["serving"] = serving_run()
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
         out["paper_context"] = {"mlups": 0.25, "note": "derived from ~1.6 s for ~1e3 steps of "

@@ -61,17 +61,19 @@ struct Item {
 };
 
 // ---------------------------------------------------------------------------
-// storage traits
+// storage traits.  Every population is read once and written once per step,
+// so loads and stores carry the non-temporal hint (measured on MI355X: best
+// for both cache-resident and HBM-resident lattices).
 // ---------------------------------------------------------------------------
 template <typename S> struct Store;
 template <> struct Store<double> {
     using C = double;
-    __device__ static __forceinline__ C ld(const double* p) { return *p; }
+    __device__ static __forceinline__ C ld(const double* p) { return __builtin_nontemporal_load(p); }
     __device__ static __forceinline__ void st(double* p, C v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<float> {
     using C = float;
-    __device__ static __forceinline__ C ld(const float* p) { return *p; }
+    __device__ static __forceinline__ C ld(const float* p) { return __builtin_nontemporal_load(p); }
     __device__ static __forceinline__ void st(float* p, C v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<__half> {

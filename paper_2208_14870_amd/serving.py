@@ -122,13 +122,19 @@ class Server:
                 queue.append(pending.popleft())
             # admission: arrival order, backfilling smaller requests that fit
             skipped = deque()
+            _, _, largest = self.batch.info()
             while queue:
                 req = queue.popleft()
+                if (len(self.active) >= self.batch.max_slots or
+                        self.footprint(req.n) > largest):
+                    skipped.append(req)
+                    if largest < self.footprint(64) or len(self.active) >= self.batch.max_slots:
+                        break
+                    continue
                 case = cases[req.rid] if cases is not None else req.case()
                 if not self._admit(req, case, now()):
                     skipped.append(req)
-                    if len(skipped) > 64:
-                        break
+                _, _, largest = self.batch.info()
             skipped.extend(queue)
             queue = skipped
             if self.active:

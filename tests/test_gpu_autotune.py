@@ -1,0 +1,42 @@
+"""The autotuner picks a valid launch shape and the results do not change."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2208_14870_amd import problem as P
+from gpu_common import dev, host, need_gpu, omega, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tune_solver_and_cache(tmp_path):
+    say("autotune solver 256x256 fp64")
+    need_gpu()
+    from paper_2208_14870_amd import autotune, lbm
+    c = P.single_1024(0.3, 1, 1, n=256)
+    s = lbm.Solver(256, 256, "fp64")
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    cache = str(tmp_path / "tune.json")
+    shp = autotune.tune_solver(s, "fp64", cache_path=cache)
+    assert shp in autotune.candidates(256, 0)
+    assert autotune.tune_solver(s, "fp64", cache_path=cache) == shp  # from the cache
+    s.reset()
+    s.step(50)
+    f = O.run(O.zero_state(256, 256), c.gx, c.gy, omega(c.material), 50)
+    ox, oy = O.displacement(f, c.gx, c.gy)
+    ux, uy = (host(t) for t in s.displacement())
+    assert rel_l2(ux, ox, uy, oy) <= 1e-12
+
+
+def test_tune_batch(tmp_path):
+    say("autotune batch")
+    need_gpu()
+    from paper_2208_14870_amd import autotune, lbm
+    cases = P.batch_cases(6, seed=4, sides=(64, 96, 128))
+    b = lbm.Batch(16, 1 << 30)
+    for c in cases:
+        b.add(c.nx, c.ny, c.material.lame_lambda, c.material.lame_mu, dev(c.gx), dev(c.gy), "fp32")
+    shp = autotune.tune_batch(b, "fp32", sum(c.nx * c.ny for c in cases),
+                              cache_path=str(tmp_path / "t.json"))
+    assert shp in autotune.candidates(64, 3)

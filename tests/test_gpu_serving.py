@@ -1,0 +1,77 @@
+"""Continuous-batching server: admission by footprint, per-request retirement,
+identical results alone and in the mix."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2208_14870_amd import problem as P
+from gpu_common import need_gpu, omega, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests():
+    rng = np.random.default_rng(11)
+    sizes = [64, 72, 96, 64, 128, 80, 96, 112, 64, 144]
+    return [P.Request(i, 0.01 * i, n, float(rng.uniform(0.05, 0.49)), int(rng.integers(1 << 30)))
+            for i, n in enumerate(sizes)]
+
+
+def _server(arena=1 << 30, **kw):
+    from paper_2208_14870_amd.serving import Server
+    need_gpu()
+    return Server(arena, max_slots=64, chunk=100, tol=1e-8, keep_results=True, **kw)
+
+
+def test_serving_completes_and_alone_equals_mix():
+    say("serving mix of 10 + 3 alone")
+    reqs = _requests()
+    cases = {r.rid: r.case() for r in reqs}
+    srv = _server()
+    stats = srv.run(reqs, admit_window_s=10.0, wall_budget_s=120.0, cases=cases)
+    srv.close()
+    assert stats["completed"] == len(reqs) and stats["backlog"] == 0 and stats["failed"] == 0
+    mix = {r.rid: r for r in srv.results}
+    for rid in (0, 4, 9):
+        alone = _server()
+        req = [r for r in reqs if r.rid == rid][0]
+        st = alone.run([P.Request(rid, 0.0, req.n, req.nu, req.seed)], 10.0, 60.0, cases=cases)
+        alone.close()
+        assert st["completed"] == 1
+        a, m = alone.results[0], mix[rid]
+        say(f"  rid {rid} n {req.n}: steps alone {a.steps} mix {m.steps}, promoted {a.promoted_at}")
+        assert a.steps == m.steps and a.promoted_at == m.promoted_at
+        np.testing.assert_array_equal(a.ux, m.ux)
+        np.testing.assert_array_equal(a.uy, m.uy)
+        assert a.residual == m.residual
+
+
+def test_serving_result_matches_oracle():
+    """FP32 phase + FP64 polish result against the FP64 oracle at the same step."""
+    say("serving vs oracle")
+    req = P.Request(0, 0.0, 64, 0.3, 1234)
+    case = req.case()
+    srv = _server()
+    srv.run([req], 1.0, 60.0, cases={0: case})
+    srv.close()
+    res = srv.results[0]
+    assert res.residual <= 1e-8
+    f = O.run(O.zero_state(64, 64), case.gx, case.gy, omega(case.material), res.steps)
+    ox, oy = O.displacement(f, case.gx, case.gy)
+    err = rel_l2(res.ux, ox, res.uy, oy)
+    say(f"  steps {res.steps}, promoted at {res.promoted_at}, rel err vs oracle {err:.2e}")
+    assert err <= 1e-6
+
+
+def test_serving_admission_respects_footprint():
+    """An arena that holds only a few lattices at once still serves everything."""
+    say("serving small arena")
+    from paper_2208_14870_amd import lbm
+    reqs = _requests()
+    per = lbm.Batch.slot_bytes(144, 144, "fp32", True)
+    srv = _server(arena=3 * per + (8 << 20))
+    stats = srv.run(reqs, 10.0, 180.0, cases={r.rid: r.case() for r in reqs})
+    srv.close()
+    assert stats["completed"] == len(reqs)
+    # arrival order is kept except for backfilling
+    assert all(x.latency >= 0 for x in srv.results)
