@@ -158,9 +158,11 @@ def batch_run(prec: str, nlat: int = 512, steps: int = 2000, chunk: int = 100):
             "frac": round(gbs / PEAK_HBM_GBS, 4), "tile": list(shape)}
 
 
-def batch_solves(prec: str, nlat: int = 512, tol: float = 1e-6, chunk: int = 200):
+def batch_solves(prec: str, nlat: int = 512, tol: float = 1e-6, chunk: int = 200,
+                 fixed_steps=None):
     """Solve every lattice of the batched workload to r <= tol with per-lattice
-    retirement (FP32 switches to FP64 only if its residual stalls)."""
+    retirement (FP32 switches to FP64 only if its residual stalls); with
+    `fixed_steps` each lattice stops after that many steps instead."""
     import torch
     from paper_2208_14870_amd import lbm, problem as P
     from paper_2208_14870_amd.serving import Server
@@ -170,7 +172,8 @@ def batch_solves(prec: str, nlat: int = 512, tol: float = 1e-6, chunk: int = 200
     arena = int(sites * lbm.Batch.slot_bytes(1024, 1024, prec, True) / (1024 * 1024) * 1.3)
     srv = Server(arena + (1 << 30), max_slots=nlat + 8, chunk=chunk, tol=tol, r_switch=0.0,
                  precision=prec, polish=(prec != "fp64"), keep_results=True)
-    st = srv.run(reqs, 1.0, 600.0, cases={i: c for i, c in enumerate(cases)})
+    st = srv.run(reqs, 1.0, 600.0, cases={i: c for i, c in enumerate(cases)},
+                 fixed_steps=fixed_steps)
     srv.close()
     res = {r.rid: r for r in srv.results}
     return st, res
@@ -301,7 +304,9 @@ def main():
         out["batch"] = {"fp32": batch_run("fp32"), "fp64": batch_run("fp64")}
         log("batched solves to r <= 1e-6 (FP32 vs FP64)")
         s32, res32 = batch_solves("fp32")
-        s64, res64 = batch_solves("fp64")
+        s64, _ = batch_solves("fp64")
+        # FP64 reference at exactly the step count each FP32 solve stopped at
+        _, res64 = batch_solves("fp64", fixed_steps={rid: r.steps for rid, r in res32.items()})
         errs = []
         for rid, r64 in res64.items():
             r32 = res32.get(rid)
@@ -316,8 +321,8 @@ def main():
                                          "p50_latency_s", "p99_latency_s")},
             "fp64": {k: s64[k] for k in ("completed", "elapsed_s", "solves_per_s",
                                          "p50_latency_s", "p99_latency_s")},
-            "fp32_vs_fp64_rel_l2_max": max(errs) if errs else None,
-            "fp32_vs_fp64_rel_l2_median": sorted(errs)[len(errs) // 2] if errs else None}
+            "fp32_vs_fp64_same_step_rel_l2_max": max(errs) if errs else None,
+            "fp32_vs_fp64_same_step_rel_l2_median": sorted(errs)[len(errs) // 2] if errs else None}
         log("serving: Poisson 2000 req/s, sides 64..2048, tol 1e-8")
         out["serving"] = serving_run()
         log("CPU oracle baseline")

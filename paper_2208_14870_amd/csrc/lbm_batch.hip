@@ -547,7 +547,12 @@ int lbm_batch_promote(lbm_batch* b, int slot) {
     if (e != hipSuccess) return b->hip_fail(e, "batch_promote");
     L.prec = LBM_FP64;
     L.cur = (int)(b->phase & 1);
-    return b->rebuild();
+    int rc = b->rebuild();
+    if (rc != LBM_OK) return rc;
+    // reset the undamped staggered modes excited by the narrow phase
+    e = neutral_reset(LBM_FP64, L.desc(), b->sel(s), b->d_red, b->h_result, b->stream);
+    if (e != hipSuccess) return b->hip_fail(e, "batch_promote: neutral modes");
+    return LBM_OK;
 }
 
 int lbm_batch_get_displacement(lbm_batch* b, int slot, double* ux, double* uy) {

@@ -407,7 +407,13 @@ int promote_solver(lbm_solver* s) {
     s->phase = 0;
     default_tile(LBM_FP64, L.nx, L.ny, L.bx_log2, L.vy);
     // sync_desc folds phase into cur: phase is 0 so cur stays 0
-    return s->sync_desc();
+    int rc = s->sync_desc();
+    if (rc != LBM_OK) return rc;
+    // the narrow phase leaves rounding noise in the two undamped staggered
+    // modes; reset them so the FP64 phase can converge
+    e = neutral_reset(LBM_FP64, L.desc(), s->sel(), s->d_red, s->h_result, s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "promote: neutral modes");
+    return LBM_OK;
 }
 
 // Rescale half storage so that max |stored| stays within [2^10, 2^14].

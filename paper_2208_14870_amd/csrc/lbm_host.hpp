@@ -268,6 +268,38 @@ inline hipError_t zero_bytes(void* p, size_t bytes, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Reset the two neutral staggered modes (k = (pi,0), (0,pi)) of the stored
+// state to their fixed point (blocking: one FP64 reduction + one update).
+// scratch: kErrBlocks * 4 + 4 doubles of device memory; host: 4 pinned doubles.
+template <typename S>
+inline hipError_t neutral_reset_t(const SlotDesc& d, int sel, double* scratch, double* host,
+                                  hipStream_t st) {
+    hipLaunchKernelGGL(k_neutral_sums<S>, dim3(kErrBlocks), dim3(kBlock), 0, st, d, sel, scratch);
+    hipLaunchKernelGGL(k_reduce4<0>, dim3(1), dim3(kBlock), 0, st, scratch, kErrBlocks,
+                       scratch + 4 * kErrBlocks);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host, scratch + 4 * kErrBlocks, 4 * sizeof(double),
+                           hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    const double N = (double)d.nx * d.ny;
+    // J_S -> G/2 ; the update changes J_S by 2 eps N per unit eps
+    const double ex = (d.nx % 2 == 0) ? (0.5 * host[2] - host[0]) / (2.0 * N) : 0.0;
+    const double ey = (d.ny % 2 == 0) ? (0.5 * host[3] - host[1]) / (2.0 * N) : 0.0;
+    const double sc = 1.0 / d.inv_scale;  // into storage units
+    hipLaunchKernelGGL(k_neutral_fix<S>, dim3(blocks_for((long long)d.nx * d.ny)), dim3(kBlock), 0,
+                       st, d, sel, ex * sc, ey * sc);
+    return hipGetLastError();
+}
+
+inline hipError_t neutral_reset(int prec, const SlotDesc& d, int sel, double* scratch,
+                                double* host, hipStream_t st) {
+    if (prec == LBM_FP64) return neutral_reset_t<double>(d, sel, scratch, host, st);
+    if (prec == LBM_FP32) return neutral_reset_t<float>(d, sel, scratch, host, st);
+    return neutral_reset_t<__half>(d, sel, scratch, host, st);
+}
+
 // Convert the FP64 force into the lattice's arithmetic type (and keep the
 // FP64 copy for the polish phase).
 inline hipError_t upload_force(const Lattice& L, const double* gx, const double* gy, hipStream_t st) {

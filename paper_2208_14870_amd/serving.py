@@ -102,10 +102,13 @@ class Server:
         del self.active[slot]
 
     def run(self, requests: List[Request], admit_window_s: float, wall_budget_s: float,
-            cases: Optional[Dict[int, Case]] = None) -> dict:
+            cases: Optional[Dict[int, Case]] = None,
+            fixed_steps: Optional[Dict[int, int]] = None) -> dict:
         """Serve `requests` (arrival times relative to the start).  Arrivals
         after `admit_window_s` are not offered; the loop stops when everything
-        offered has retired or after `wall_budget_s` seconds."""
+        offered has retired or after `wall_budget_s` seconds.  With
+        `fixed_steps`, request rid retires after exactly that many steps
+        (a multiple of the chunk) instead of at the tolerance."""
         pending = deque(sorted((r for r in requests if r.t_arrival < admit_window_s),
                                key=lambda r: r.t_arrival))
         offered = len(pending)
@@ -150,6 +153,10 @@ class Server:
                         self.failed.append(a.req.rid)
                         self.batch.remove(slot)
                         del self.active[slot]
+                        continue
+                    if fixed_steps is not None:
+                        if steps[slot] >= fixed_steps[a.req.rid]:
+                            self._retire(slot, a, steps[slot], rs, now)
                         continue
                     if rs <= self.tol or steps[slot] >= self.max_steps:
                         self._retire(slot, a, steps[slot], rs, now)

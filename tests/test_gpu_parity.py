@@ -294,6 +294,28 @@ def test_fp32_polish_reaches_fp64_tolerance():
     assert err <= 1e-9
 
 
+@pytest.mark.parametrize("n", [64, 96])
+def test_fp32_polish_random_load_converges(n):
+    """Random 8-mode load: FP32 noise excites the undamped staggered modes; the
+    switch to FP64 resets them, so the polished solve reaches r <= 1e-10 and
+    matches the FP64 oracle at the same step."""
+    say(f"fp32 polish random load {n}")
+    req = P.Request(0, 0.0, n, 0.3, 1234)
+    c = req.case()
+    s = _solver(n, n, "fp32", polish=True)
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    s.set_polish(1e-6)
+    steps, r, st = s.solve_to_tol(1e-10, 20000, 100)
+    assert st == 0 and r <= 1e-10, (steps, r)
+    f = O.run(O.zero_state(n, n), c.gx, c.gy, omega(c.material), steps)
+    ox, oy = O.displacement(f, c.gx, c.gy)
+    ux, uy = (host(t) for t in s.displacement())
+    err = rel_l2(ux, ox, uy, oy)
+    say(f"  steps {steps} r {r:.2e} rel err vs oracle {err:.2e}")
+    assert err <= 1e-6
+
+
 # ---------------------------------------------------------------------------
 # failure handling
 # ---------------------------------------------------------------------------

@@ -28,7 +28,7 @@ def test_serving_completes_and_alone_equals_mix():
     reqs = _requests()
     cases = {r.rid: r.case() for r in reqs}
     srv = _server()
-    stats = srv.run(reqs, admit_window_s=10.0, wall_budget_s=120.0, cases=cases)
+    stats = srv.run(reqs, admit_window_s=10.0, wall_budget_s=60.0, cases=cases)
     srv.close()
     assert stats["completed"] == len(reqs) and stats["backlog"] == 0 and stats["failed"] == 0
     mix = {r.rid: r for r in srv.results}
@@ -52,7 +52,7 @@ def test_serving_result_matches_oracle():
     req = P.Request(0, 0.0, 64, 0.3, 1234)
     case = req.case()
     srv = _server()
-    srv.run([req], 1.0, 60.0, cases={0: case})
+    srv.run([req], 1.0, 30.0, cases={0: case})
     srv.close()
     res = srv.results[0]
     assert res.residual <= 1e-8
@@ -70,7 +70,7 @@ def test_serving_admission_respects_footprint():
     reqs = _requests()
     per = lbm.Batch.slot_bytes(144, 144, "fp32", True)
     srv = _server(arena=3 * per + (8 << 20))
-    stats = srv.run(reqs, 10.0, 180.0, cases={r.rid: r.case() for r in reqs})
+    stats = srv.run(reqs, 10.0, 60.0, cases={r.rid: r.case() for r in reqs})
     srv.close()
     assert stats["completed"] == len(reqs)
     # arrival order is kept except for backfilling

@@ -366,3 +366,48 @@ def test_gaussian_hill_instability():
         amp[name] = max(np.max(np.abs(ux)), np.max(np.abs(uy)))
     assert amp["s"] < 1e-2
     assert not np.isfinite(amp["u"]) or amp["u"] > 1e3
+
+
+# ---------------------------------------------------------------------------
+# undamped staggered modes (used by the precision switch of the GPU library)
+# ---------------------------------------------------------------------------
+
+def test_staggered_first_moment_is_neutral():
+    """For even nx, J = sum_x (-1)^x m10 satisfies J(n+1) = -J(n) - sum_x (-1)^x gx
+    exactly (any rates): the k = (pi, 0) mode has eigenvalue -1; same in y."""
+    rng = np.random.default_rng(5)
+    nx, ny = 10, 6
+    f = rng.standard_normal((8, ny, nx))
+    gx = rng.standard_normal((ny, nx))
+    gy = rng.standard_normal((ny, nx))
+    mat = P.Material.from_shear_poisson(0.7, 0.2)
+    om = O.omega_vector(mat.lame_lambda, mat.lame_mu, 0.4, 1.3, 0.9, 1.1)
+    M = S.printed_M()
+    px = (-1.0) ** np.arange(nx)[None, :]
+    py = (-1.0) ** np.arange(ny)[:, None]
+
+    def J(ff):
+        m = np.einsum("ij,jyx->iyx", M, ff)
+        return np.sum(px * m[0]), np.sum(py * m[1])
+    j0 = J(f)
+    j1 = J(O.run(f, gx, gy, om, 1, theta=0.4))
+    assert j1[0] == pytest.approx(-j0[0] - np.sum(px * gx), rel=1e-12)
+    assert j1[1] == pytest.approx(-j0[1] - np.sum(py * gy), rel=1e-12)
+
+
+def test_neutral_modes_in_spectrum():
+    """The per-mode operator has an eigenvalue -1 exactly at k = (pi, 0) and (0, pi)
+    and nowhere else on a 32 x 32 lattice besides k = 0."""
+    m = P.Material.from_shear_poisson(1.0, 0.3)
+    mm = S.ModeModel(m.lame_lambda, m.lame_mu)
+    n = 32
+    found = []
+    for a in range(n):
+        for b in range(n):
+            if (a, b) == (0, 0):
+                continue
+            ev = np.linalg.eigvals(mm.L(2 * math.pi * a / n, 2 * math.pi * b / n))
+            if np.max(np.abs(ev)) > 1 - 1e-12:
+                found.append((a, b))
+                assert np.min(np.abs(ev + 1)) < 1e-12
+    assert sorted(found) == [(0, n // 2), (n // 2, 0)]
