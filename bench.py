@@ -15,8 +15,11 @@ Also reported on the same JSON line:
                    (72 B per FP32 site update) / average launch duration from
                    HIP events on the library's stream, against 8 TB/s;
   fp64          -- the same workload with FP64 storage;
-  hbm_8192      -- 8192 x 8192 FP32 and scaled-FP16 step throughput (the
-                   working set exceeds the 256 MB last-level cache);
+  large_8192    -- 8192 x 8192 FP64 / FP32 / scaled-FP16 step throughput (the
+                   working set exceeds the 256 MB last-level cache) and the
+                   reduced-precision displacement error on a 256^2 downsample;
+  batch         -- 512 uneven lattices in one launch per step; solves/s;
+  serving       -- Poisson arrivals, continuous batching, p50/p99 latency;
   cpu_baseline  -- the FP64 CPU oracle on a bounded sample of the workload.
 Inputs are seeded and synthetic (no dataset is involved).
 """
@@ -34,6 +37,24 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_SITE = {"fp64": 144, "fp32": 72, "fp16": 40}  # 8 pops in + 8 out + 2 force
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel from the committed counter
+    summary (FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy), or None when the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_step_fp32_1024_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in ("paper_2208_14870_amd/csrc/lbm_device.hpp", "paper_2208_14870_amd/csrc/lbm_host.hpp"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def log(msg: str):
@@ -99,28 +120,49 @@ def run_workload(solvers, nchunks, chunk):
             "last": last[-len(solvers):]}
 
 
-def hbm_probe(prec, steps=200):
-    """Steps/s of the plain step on the 8192 x 8192 random-load lattice."""
+def large_lattice(steps=2000):
+    """8192 x 8192 random 16-mode load (seed 3): plain-step throughput per
+    storage precision and the FP32 / scaled-FP16 displacement error against
+    the FP64 run (the FP64 GPU path is checked against the oracle on sampled
+    sites at this size) on the 256 x 256 downsample (nodes 32i, 32j) after
+    `steps` steps from rest."""
     import torch
     from paper_2208_14870_amd import lbm, problem as P
     c = P.single_8192()
-    s = lbm.Solver(c.nx, c.ny, prec)
-    s.set_material(c.material.lame_lambda, c.material.lame_mu)
-    s.set_body_force(torch.from_numpy(c.gx).cuda(), torch.from_numpy(c.gy).cuda())
+    gx = torch.from_numpy(c.gx).cuda()
+    gy = torch.from_numpy(c.gy).cuda()
+    mat = c.material
     del c
-    s.step(20)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    s.step(steps)
-    e1.record()
-    torch.cuda.synchronize()
-    us = 1e3 * e0.elapsed_time(e1) / steps
     sites = 8192 * 8192
-    gbs = BYTES_PER_SITE[prec] * sites / (us * 1e-6) / 1e9
-    s.close()
-    return {"mlups": sites / us, "us_per_step": us, "gbs": gbs, "frac": gbs / PEAK_HBM_GBS}
+    out, u = {}, {}
+    for prec in ("fp64", "fp32", "fp16"):
+        s = lbm.Solver(8192, 8192, prec)
+        s.set_material(mat.lame_lambda, mat.lame_mu)
+        s.set_body_force(gx, gy)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / steps
+        ux, uy = s.displacement()
+        u[prec] = (ux[::32, ::32].clone(), uy[::32, ::32].clone())
+        del ux, uy
+        s.close()
+        del s
+        gbs = BYTES_PER_SITE[prec] * sites / (us * 1e-6) / 1e9
+        out[prec] = {"mlups": round(sites / us, 1), "us_per_step": round(us, 2),
+                     "gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    rx, ry = u["fp64"]
+    den = float(torch.sum(rx ** 2) + torch.sum(ry ** 2))
+    for prec in ("fp32", "fp16"):
+        ax, ay = u[prec]
+        num = float(torch.sum((ax - rx) ** 2) + torch.sum((ay - ry) ** 2))
+        out[prec]["rel_l2_vs_fp64_downsample_256"] = math.sqrt(num / den)
+    out["steps"] = steps
+    return out
 
 
 def batch_run(prec: str, nlat: int = 512, steps: int = 2000, chunk: int = 100):
@@ -159,7 +201,7 @@ def batch_run(prec: str, nlat: int = 512, steps: int = 2000, chunk: int = 100):
 
 
 def batch_solves(prec: str, nlat: int = 512, tol: float = 1e-6, chunk: int = 200,
-                 fixed_steps=None):
+                 fixed_steps=None, r_switch: float = 0.0):
     """Solve every lattice of the batched workload to r <= tol with per-lattice
     retirement (FP32 switches to FP64 only if its residual stalls); with
     `fixed_steps` each lattice stops after that many steps instead."""
@@ -170,7 +212,7 @@ def batch_solves(prec: str, nlat: int = 512, tol: float = 1e-6, chunk: int = 200
     reqs = [P.Request(i, 0.0, c.nx, c.material.poisson, 0) for i, c in enumerate(cases)]
     sites = sum(c.nx * c.ny for c in cases)
     arena = int(sites * lbm.Batch.slot_bytes(1024, 1024, prec, True) / (1024 * 1024) * 1.3)
-    srv = Server(arena + (1 << 30), max_slots=nlat + 8, chunk=chunk, tol=tol, r_switch=0.0,
+    srv = Server(arena + (1 << 30), max_slots=nlat + 8, chunk=chunk, tol=tol, r_switch=r_switch,
                  precision=prec, polish=(prec != "fp64"), keep_results=True)
     st = srv.run(reqs, 1.0, 600.0, cases={i: c for i, c in enumerate(cases)},
                  fixed_steps=fixed_steps)
@@ -179,7 +221,7 @@ def batch_solves(prec: str, nlat: int = 512, tol: float = 1e-6, chunk: int = 200
     return st, res
 
 
-def serving_run(rate: float = 2000.0, window: float = 1.0, budget: float = 25.0):
+def serving_run(rate: float = 2000.0, window: float = 1.0, budget: float = 20.0):
     """Poisson arrivals (seed 5), sides log-uniform 64..2048, 8-mode loads, tol 1e-8,
     FP32 storage with FP64 polish, admission by arena footprint."""
     import torch
@@ -271,11 +313,12 @@ def main():
                    "storage": "fp32", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(r32["kernel_gbs"], 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(r32["kernel_gbs"] / PEAK_HBM_GBS, 4), "traffic": None,
+                     "frac": round(r32["kernel_gbs"] / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic(),
                      "kernel": "k_step<float, plain> (72 B/site-update algorithmic)",
                      "avg_launch_us": round(r32["plain_kernel_avg_us"], 3),
                      "note": "1024^2 working set (~72 MB) fits the 256 MB last-level cache; "
-                             "the HBM-bound figure is hbm_8192"},
+                             "the HBM-bound figures are under large_8192"},
         "fp32_last_residual": r32["last"][0][0],
         "fp32_rel_l2_vs_manufactured": [round(x[1], 6) for x in r32["last"]],
     }
@@ -297,34 +340,38 @@ def main():
                        "avg_launch_us": round(r64["plain_kernel_avg_us"], 3)}
         out["fp32_speedup_over_fp64"] = round(r32["mlups"] / r64["mlups"], 3)
         out["fp32_rel_l2_vs_fp64"] = math.sqrt(num / den)
-        log("HBM-bound probe: 8192x8192 FP32 / FP16")
-        out["hbm_8192"] = {p: {k: round(v, 4) for k, v in hbm_probe(p).items()}
-                           for p in ("fp32", "fp16")}
+        log("8192x8192 random load: FP64 / FP32 / FP16, 2000 steps")
+        out["large_8192"] = large_lattice()
         log("batched: 512 lattices FP32 / FP64, 2000 steps")
         out["batch"] = {"fp32": batch_run("fp32"), "fp64": batch_run("fp64")}
-        log("batched solves to r <= 1e-6 (FP32 vs FP64)")
+        log("batched solves to r <= 1e-6 (FP32, FP32 + FP64 polish, FP64)")
+        keys = ("completed", "elapsed_s", "solves_per_s", "p50_latency_s", "p99_latency_s")
+
+        def err_vs_fp64(res):
+            # FP64 reference at exactly the step count each solve stopped at
+            _, ref = batch_solves("fp64", fixed_steps={rid: r.steps for rid, r in res.items()})
+            errs = []
+            for rid, r64 in ref.items():
+                r = res[rid]
+                num = float(((r.ux - r64.ux) ** 2).sum() + ((r.uy - r64.uy) ** 2).sum())
+                den = float((r64.ux ** 2).sum() + (r64.uy ** 2).sum())
+                errs.append(math.sqrt(num / den))
+            errs.sort()
+            return {"same_step_rel_l2_vs_fp64_max": errs[-1],
+                    "same_step_rel_l2_vs_fp64_median": errs[len(errs) // 2]}
         s32, res32 = batch_solves("fp32")
+        sp, resp = batch_solves("fp32", r_switch=1e-5)
         s64, _ = batch_solves("fp64")
-        # FP64 reference at exactly the step count each FP32 solve stopped at
-        _, res64 = batch_solves("fp64", fixed_steps={rid: r.steps for rid, r in res32.items()})
-        errs = []
-        for rid, r64 in res64.items():
-            r32 = res32.get(rid)
-            if r32 is None:
-                continue
-            num = float(((r32.ux - r64.ux) ** 2).sum() + ((r32.uy - r64.uy) ** 2).sum())
-            den = float((r64.ux ** 2).sum() + (r64.uy ** 2).sum())
-            errs.append(math.sqrt(num / den))
         out["batch"]["solves"] = {
             "tol": 1e-6,
-            "fp32": {k: s32[k] for k in ("completed", "elapsed_s", "solves_per_s",
-                                         "p50_latency_s", "p99_latency_s")},
-            "fp64": {k: s64[k] for k in ("completed", "elapsed_s", "solves_per_s",
-                                         "p50_latency_s", "p99_latency_s")},
-            "fp32_vs_fp64_same_step_rel_l2_max": max(errs) if errs else None,
-            "fp32_vs_fp64_same_step_rel_l2_median": sorted(errs)[len(errs) // 2] if errs else None}
+            "fp32": dict({k: s32[k] for k in keys}, **err_vs_fp64(res32)),
+            "fp32_polish_at_1e-5": dict({k: sp[k] for k in keys}, **err_vs_fp64(resp)),
+            "fp64": {k: s64[k] for k in keys}}
         log("serving: Poisson 2000 req/s, sides 64..2048, tol 1e-8")
         out["serving"] = serving_run()
+        sustain = max(0.5, 0.8 * out["serving"]["solves_per_s"])
+        log(f"serving at 0.8x the measured completion rate ({sustain:.1f} req/s)")
+        out["serving_sustained"] = serving_run(rate=sustain, window=15.0, budget=30.0)
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
         out["paper_context"] = {"mlups": 0.25, "note": "derived from ~1.6 s for ~1e3 steps of "

@@ -4,6 +4,7 @@ Bars: streaming/index arithmetic bit-exact; FP64 within 1e-12 relative;
 reduced precisions within tolerances derived from their rounding unit
 (stated per test).
 """
+import functools
 import math
 
 import numpy as np
@@ -210,6 +211,56 @@ def test_fp64_full_size_1024_sampled():
     s.step(20)
     fn = O.run(f0, c.gx, c.gy, omega(c.material), 20)
     assert rel_l2(host(s.populations()), fn) <= 1e-12
+
+
+@functools.lru_cache(maxsize=1)
+def _case_8192():
+    return P.single_8192()
+
+
+def _window_oracle(case, om, steps, sites, halo):
+    """f(steps) from f = 0 at the given sites, each computed by the oracle on a
+    periodic window of half-width `halo` > steps around the site (the light cone
+    of a site after n steps has radius n, so the window's own wrap never reaches
+    the centre)."""
+    w = 2 * halo + 1
+    out = []
+    for (y, x) in sites:
+        ys = (np.arange(y - halo, y + halo + 1)) % case.ny
+        xs = (np.arange(x - halo, x + halo + 1)) % case.nx
+        gx = np.ascontiguousarray(case.gx[np.ix_(ys, xs)])
+        gy = np.ascontiguousarray(case.gy[np.ix_(ys, xs)])
+        f = O.run(O.zero_state(w, w), gx, gy, om, steps)
+        ux, uy = O.displacement(f, gx, gy)
+        out.append((ux[halo, halo], uy[halo, halo]))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("fp16", 2e-2)])
+def test_full_size_8192_sampled(prec, tol):
+    """8192 x 8192 random 16-mode load in the benchmark's launch configuration:
+    displacement after 12 steps at sampled sites (corners and edges included)
+    against the oracle evaluated site by site on light-cone windows."""
+    say(f"8192x8192 {prec} sampled")
+    import torch
+    c = _case_8192()
+    s = _solver(8192, 8192, prec)
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    steps = 12
+    s.step(steps)
+    ux, uy = s.displacement()
+    rng = np.random.default_rng(1)
+    sites = [(0, 0), (0, 8191), (8191, 0), (8191, 8191), (4096, 0), (0, 4096)]
+    sites += [tuple(int(v) for v in rng.integers(0, 8192, 2)) for _ in range(26)]
+    iy = torch.tensor([p[0] for p in sites], device="cuda")
+    ix = torch.tensor([p[1] for p in sites], device="cuda")
+    got = np.stack([host(ux[iy, ix]), host(uy[iy, ix])], axis=1)
+    want = _window_oracle(c, omega(c.material), steps, sites, steps + 2)
+    scale = np.max(np.abs(want))
+    err = np.max(np.abs(got - want)) / scale
+    say(f"  max rel err at {len(sites)} sites: {err:.2e}")
+    assert err <= tol
 
 
 # ---------------------------------------------------------------------------
