@@ -93,6 +93,9 @@ def make_solvers(cases, prec):
     return out
 
 
+STEPS_PER_LAUNCH = 2  # the library's default: plain steps run through the fused two-step kernel
+
+
 def run_workload(solvers, nchunks, chunk):
     """nchunks x (chunk steps per lattice: plain steps, then the residual check
     pair, then displacement + error norms).  Returns timing and last metrics."""
@@ -115,7 +118,8 @@ def run_workload(solvers, nchunks, chunk):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     plain_ms = sum(a.elapsed_time(b) for a, b in ev)
-    plain_launches = len(ev) * (chunk - 2)
+    per = chunk - 2
+    plain_launches = len(ev) * (per // STEPS_PER_LAUNCH + per % STEPS_PER_LAUNCH)
     return {"wall_s": wall, "plain_kernel_avg_us": 1e3 * plain_ms / plain_launches,
             "last": last[-len(solvers):]}
 
@@ -146,7 +150,7 @@ def large_lattice(steps=2000):
         s.step(steps)
         e1.record()
         torch.cuda.synchronize()
-        us = 1e3 * e0.elapsed_time(e1) / steps
+        us = 1e3 * e0.elapsed_time(e1) / steps  # per step (two steps per fused launch)
         ux, uy = s.displacement()
         u[prec] = (ux[::32, ::32].clone(), uy[::32, ::32].clone())
         del ux, uy
@@ -284,7 +288,8 @@ def main():
         updates = nsites * args.chunk * args.steps * len(solvers)
         res["mlups"] = updates / res["wall_s"] / 1e6
         avg = res["plain_kernel_avg_us"]
-        res["kernel_gbs"] = BYTES_PER_SITE[prec] * nsites / (avg * 1e-6) / 1e9
+        # algorithmic bytes per launch = bytes per site-update x site-updates per launch
+        res["kernel_gbs"] = BYTES_PER_SITE[prec] * STEPS_PER_LAUNCH * nsites / (avg * 1e-6) / 1e9
         u = [s.displacement() for s, _ in solvers]
         for s, _ in solvers:
             s.close()
@@ -315,10 +320,14 @@ def main():
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(r32["kernel_gbs"] / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic(),
-                     "kernel": "k_step<float, plain> (72 B/site-update algorithmic)",
+                     "kernel": "k_step2<float, 16>: two fused steps per launch, 72 B per "
+                               "site-update algorithmic, 2 x 1024^2 site-updates per launch",
                      "avg_launch_us": round(r32["plain_kernel_avg_us"], 3),
-                     "note": "1024^2 working set (~72 MB) fits the 256 MB last-level cache; "
-                             "the HBM-bound figures are under large_8192"},
+                     "steps_per_launch": STEPS_PER_LAUNCH,
+                     "note": "the fused kernel moves the populations through HBM once per two "
+                             "steps (36 B per site-update), so frac can approach or pass 1; "
+                             "1024^2 (~72 MB) also fits the 256 MB last-level cache; the "
+                             "HBM-resident figures are under large_8192"},
         "fp32_last_residual": r32["last"][0][0],
         "fp32_rel_l2_vs_manufactured": [round(x[1], 6) for x in r32["last"]],
     }

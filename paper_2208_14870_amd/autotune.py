@@ -19,7 +19,7 @@ from typing import Callable, Dict, Iterable, List, Optional, Tuple
 
 import torch
 
-Shape = Tuple[int, int, int]  # (bx_log2, rows_per_thread, blocks_per_cu)
+Shape = Tuple[int, int, int, int]  # (bx_log2, rows_per_thread, blocks_per_cu, steps_per_launch)
 
 DEFAULT_CACHE = os.environ.get("LBM_AUTOTUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache",
@@ -27,14 +27,21 @@ DEFAULT_CACHE = os.environ.get("LBM_AUTOTUNE_CACHE",
 
 
 def candidates(nx: int, min_bx: int = 3) -> List[Shape]:
-    out = []
+    """Single-step tile shapes plus the fused two-step kernel (whose tile is fixed)
+    with one workgroup per tile or a persistent grid."""
+    out = [(6, 4, k, 2) for k in (0, 4)]
     for b in (5, 6, 7, 8):
         if b < min_bx or (1 << b) > max(2 * nx, 1 << min_bx):
             continue
         for v in (1, 2, 4):
             for k in (0, 4):
-                out.append((b, v, k))
+                out.append((b, v, k, 1))
     return out
+
+
+def _apply(obj, shp: Shape):
+    obj.set_time_blocking(shp[3])
+    obj.set_tile(shp[0], shp[1], shp[2])
 
 
 def _arch() -> str:
@@ -45,7 +52,7 @@ def _arch() -> str:
 
 
 def _key(kind: str, precision: str, sites: int) -> str:
-    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}"
+    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}|v2"
 
 
 def _load(path: str) -> Dict[str, list]:
@@ -104,12 +111,11 @@ def tune_solver(solver, precision: str, cache_path: Optional[str] = DEFAULT_CACH
     cache = _load(cache_path) if cache_path else {}
     if not force and key in cache:
         shp = tuple(cache[key])
-        solver.set_tile(*shp)
+        _apply(solver, shp)
         return shp
-    res = time_shapes(lambda s: solver.set_tile(*s), solver.step, candidates(solver.nx, 0),
-                      sites)
+    res = time_shapes(lambda s: _apply(solver, s), solver.step, candidates(solver.nx, 0), sites)
     shp = res[0][1]
-    solver.set_tile(*shp)
+    _apply(solver, shp)
     if cache_path:
         cache[key] = list(shp)
         _store(cache_path, cache)
@@ -123,12 +129,12 @@ def tune_batch(batch, precision: str, sites: int, cache_path: Optional[str] = DE
     cache = _load(cache_path) if cache_path else {}
     if not force and key in cache:
         shp = tuple(cache[key])
-        batch.set_tile(*shp)
+        _apply(batch, shp)
         return shp
-    res = time_shapes(lambda s: batch.set_tile(*s), lambda n: batch.step(n), candidates(64, 3),
+    res = time_shapes(lambda s: _apply(batch, s), lambda n: batch.step(n), candidates(64, 3),
                       sites)
     shp = res[0][1]
-    batch.set_tile(*shp)
+    _apply(batch, shp)
     if cache_path:
         cache[key] = list(shp)
         _store(cache_path, cache)

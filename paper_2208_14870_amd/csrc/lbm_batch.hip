@@ -151,6 +151,7 @@ struct lbm_batch {
     long long phase = 0;
     int bx_log2 = 6, vy = 2;
     int blocks_per_cu = 0;  // 0: one workgroup per tile; k: persistent k per CU
+    int tb = 2;             // steps per launch of plain steps (2: fused two-step kernel)
     std::string err;
     std::map<std::tuple<long long, int, int, unsigned, unsigned, unsigned>, hipGraphExec_t> graphs;
 
@@ -197,6 +198,7 @@ struct lbm_batch {
                 if (!s.active || s.L.prec != p) continue;
                 s.L.bx_log2 = bx_log2;
                 s.L.vy = vy;
+                s.L.tb = tb;
                 s.first = (int)total;
                 s.count = s.L.nitems();
                 total += s.count;
@@ -235,31 +237,54 @@ struct lbm_batch {
         a.range = d_range + 2 * prec;
         a.partial = d_partial;
         a.flip = flip;
-        a.rows = vy;
+        a.rows = eff_vy(prec);
         return a;
+    }
+
+    // rows per thread of the tiles of one precision's lattices
+    int eff_vy(int prec) const { return tb == 2 ? (prec == LBM_FP64 ? 2 : 4) : vy; }
+
+    long long launches(long long nsteps, bool check) const {
+        const long long np = check ? nsteps - 2 : nsteps;
+        return (tb == 2 ? np / 2 + np % 2 : np) + (check ? 2 : 0);
     }
 
     hipError_t enqueue(long long nsteps, bool check, hipStream_t st, long long ph) {
         hipError_t e = hipSuccess;
-        for (long long i = 0; i < nsteps; ++i, ++ph) {
-            const int mode = !check ? kPlain
-                                    : (i == nsteps - 1 ? kCheck : (i == nsteps - 2 ? kWriteU : kPlain));
-            for (int p = 0; p < 3; ++p) {
+        const long long np = check ? nsteps - 2 : nsteps;
+        auto each = [&](auto&& fn) {
+            for (int p = 0; p < 3 && e == hipSuccess; ++p) {
                 const unsigned g = grid_for(p);
-                if (!g) continue;
-                e = launch_step(p, mode, false, vy, g, st, args(p, (int)(ph & 1)));
-                if (e != hipSuccess) return e;
+                if (g) e = fn(p, g);
             }
-        }
-        if (check) {
-            FinalizeLaunch F;
-            F.first = d_first;
-            F.count = d_count;
-            F.partial = d_partial;
-            F.result = d_result;
-            F.nslots = max_slots;
-            hipLaunchKernelGGL(k_finalize, dim3(max_slots), dim3(kBlock), 0, st, F);
-            e = hipGetLastError();
+        };
+        long long i = 0;
+        if (tb == 2)
+            for (; i + 1 < np && e == hipSuccess; i += 2, ++ph)
+                each([&](int p, unsigned g) { return launch_step2(p, g, st, args(p, (int)(ph & 1))); });
+        for (; i < np && e == hipSuccess; ++i, ++ph)
+            each([&](int p, unsigned g) {
+                return launch_step(p, kPlain, false, eff_vy(p), g, st, args(p, (int)(ph & 1)));
+            });
+        if (check && e == hipSuccess) {
+            each([&](int p, unsigned g) {
+                return launch_step(p, kWriteU, false, eff_vy(p), g, st, args(p, (int)(ph & 1)));
+            });
+            ++ph;
+            each([&](int p, unsigned g) {
+                return launch_step(p, kCheck, false, eff_vy(p), g, st, args(p, (int)(ph & 1)));
+            });
+            ++ph;
+            if (e == hipSuccess) {
+                FinalizeLaunch F;
+                F.first = d_first;
+                F.count = d_count;
+                F.partial = d_partial;
+                F.result = d_result;
+                F.nslots = max_slots;
+                hipLaunchKernelGGL(k_finalize, dim3(max_slots), dim3(kBlock), 0, st, F);
+                e = hipGetLastError();
+            }
         }
         return e;
     }
@@ -459,6 +484,15 @@ int lbm_batch_set_tile(lbm_batch* b, int bx_log2, int rows_per_thread, int block
     return b->rebuild();
 }
 
+int lbm_batch_set_time_blocking(lbm_batch* b, int steps_per_launch) {
+    if (!b) return LBM_E_ARG;
+    if (steps_per_launch != 1 && steps_per_launch != 2)
+        return b->fail(LBM_E_ARG, "batch_set_time_blocking: steps_per_launch must be 1 or 2");
+    b->tb = steps_per_launch;
+    b->drop_graphs();
+    return b->rebuild();
+}
+
 int lbm_batch_step(lbm_batch* b, long long nsteps, int check) {
     if (!b) return LBM_E_ARG;
     if (nsteps < 1 || (check && nsteps < 2))
@@ -466,9 +500,9 @@ int lbm_batch_step(lbm_batch* b, long long nsteps, int check) {
     if (b->range_host[2][1] == 0) return LBM_OK;  // nothing active
     hipError_t e;
     const int flip0 = (int)(b->phase & 1);
-    if (nsteps >= 4) {
-        auto key = std::make_tuple(nsteps, check ? 1 : 0, flip0, b->grid_for(0), b->grid_for(1),
-                                   b->grid_for(2));
+    if (b->launches(nsteps, check != 0) >= 4) {
+        auto key = std::make_tuple(nsteps, (check ? 1 : 0) | (b->tb == 2 ? 2 : 0), flip0,
+                                   b->grid_for(0), b->grid_for(1), b->grid_for(2));
         auto it = b->graphs.find(key);
         if (it == b->graphs.end()) {
             if (b->graphs.size() > 16) b->drop_graphs();
@@ -493,7 +527,7 @@ int lbm_batch_step(lbm_batch* b, long long nsteps, int check) {
         if ((e = b->enqueue(nsteps, check != 0, b->stream, b->phase)) != hipSuccess)
             return b->hip_fail(e, "batch_step");
     }
-    b->phase += nsteps;
+    b->phase += b->launches(nsteps, check != 0);
     for (auto& s : b->slots)
         if (s.active) {
             s.steps += nsteps;

@@ -114,6 +114,12 @@ struct lbm_solver {
         return e;
     }
 
+    hipError_t enqueue_pair(hipStream_t st, long long& ph) {
+        hipError_t e = launch_step2(L.prec, grid, st, launch_args((int)(ph & 1)));
+        ++ph;  // one buffer flip for two steps
+        return e;
+    }
+
     hipError_t enqueue_finalize(hipStream_t st) {
         FinalizeLaunch F;
         F.first = d_first;
@@ -125,9 +131,29 @@ struct lbm_solver {
         return hipGetLastError();
     }
 
-    // Enqueue `nplain` plain steps, then (optionally) a writeU step, then
-    // (optionally) a check step + finalize.  Long runs are replayed from
-    // captured graphs.
+    // Launches for `nplain` plain steps (pairs through the fused kernel when
+    // enabled), then optionally a writeU step and a check step + finalize.
+    hipError_t enqueue_seq(long long nplain, bool writeu, bool check, hipStream_t st,
+                           long long& ph) {
+        hipError_t e = hipSuccess;
+        long long i = 0;
+        if (L.fused())
+            for (; i + 1 < nplain && e == hipSuccess; i += 2) e = enqueue_pair(st, ph);
+        for (; i < nplain && e == hipSuccess; ++i) e = enqueue_one(kPlain, st, ph);
+        if (e == hipSuccess && writeu) e = enqueue_one(kWriteU, st, ph);
+        if (e == hipSuccess && check) {
+            e = enqueue_one(kCheck, st, ph);
+            if (e == hipSuccess) e = enqueue_finalize(st);
+        }
+        return e;
+    }
+
+    long long launches(long long nplain, bool writeu, bool check) const {
+        const long long p = L.fused() ? nplain / 2 + nplain % 2 : nplain;
+        return p + (writeu ? 1 : 0) + (check ? 1 : 0);
+    }
+
+    // Enqueue a chunk; long runs are replayed from captured graphs.
     hipError_t enqueue_chunk(long long nplain, bool writeu, bool check) {
         const long long kGraphChunk = 64;
         hipError_t e;
@@ -136,16 +162,9 @@ struct lbm_solver {
             nplain -= kGraphChunk;
         }
         if (nplain > 0 || writeu || check) {
-            if (nplain + (writeu ? 1 : 0) + (check ? 1 : 0) >= 4)
-                return run_graph(nplain, writeu, check);
+            if (launches(nplain, writeu, check) >= 4) return run_graph(nplain, writeu, check);
             long long ph = phase;
-            for (long long i = 0; i < nplain; ++i)
-                if ((e = enqueue_one(kPlain, stream, ph)) != hipSuccess) return e;
-            if (writeu && (e = enqueue_one(kWriteU, stream, ph)) != hipSuccess) return e;
-            if (check) {
-                if ((e = enqueue_one(kCheck, stream, ph)) != hipSuccess) return e;
-                if ((e = enqueue_finalize(stream)) != hipSuccess) return e;
-            }
+            if ((e = enqueue_seq(nplain, writeu, check, stream, ph)) != hipSuccess) return e;
             phase = ph;
         }
         return hipSuccess;
@@ -153,7 +172,7 @@ struct lbm_solver {
 
     hipError_t run_graph(long long nplain, bool writeu, bool check) {
         const int flip0 = (int)(phase & 1);
-        const int kind = (writeu ? 1 : 0) | (check ? 2 : 0);
+        const int kind = (writeu ? 1 : 0) | (check ? 2 : 0) | (L.fused() ? 4 : 0);
         auto key = std::make_tuple(nplain, kind, flip0, L.prec, L.eff_vy(), L.general() ? 1 : 0, grid);
         auto it = graphs.find(key);
         hipError_t e;
@@ -163,13 +182,7 @@ struct lbm_solver {
             if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
                 return e;
             long long ph = phase;
-            for (long long i = 0; i < nplain; ++i) (void)enqueue_one(kPlain, cap, ph);
-            if (writeu) (void)enqueue_one(kWriteU, cap, ph);
-            if (check) {
-                (void)enqueue_one(kCheck, cap, ph);
-                (void)enqueue_finalize(cap);
-            }
-            hipError_t le = hipGetLastError();
+            hipError_t le = enqueue_seq(nplain, writeu, check, cap, ph);
             if ((e = hipStreamEndCapture(cap, &gr)) != hipSuccess) return e;
             if (le != hipSuccess) {
                 (void)hipGraphDestroy(gr);
@@ -182,10 +195,11 @@ struct lbm_solver {
             it = graphs.emplace(key, ex).first;
         }
         if ((e = hipGraphLaunch(it->second, stream)) != hipSuccess) return e;
-        phase += nplain + (writeu ? 1 : 0) + (check ? 1 : 0);
+        phase += launches(nplain, writeu, check);
         return hipSuccess;
     }
 };
+
 
 extern "C" {
 
@@ -360,6 +374,14 @@ int lbm_set_tile(lbm_solver* s, int bx_log2, int rows_per_thread, int blocks_per
     s->L.bx_log2 = bx_log2;
     s->L.vy = rows_per_thread;
     s->blocks_per_cu = blocks_per_cu;
+    return s->sync_desc();
+}
+
+int lbm_set_time_blocking(lbm_solver* s, int steps_per_launch) {
+    if (!s) return LBM_E_ARG;
+    if (steps_per_launch != 1 && steps_per_launch != 2)
+        return s->fail(LBM_E_ARG, "set_time_blocking: steps_per_launch must be 1 or 2");
+    s->L.tb = steps_per_launch;
     return s->sync_desc();
 }
 

@@ -338,6 +338,96 @@ static __global__ __launch_bounds__(kBlock) void k_step(StepLaunch L) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// two fused steps per launch (temporal blocking)
+// ---------------------------------------------------------------------------
+// A workgroup owns an output tile of 64 x TH sites.  Step A advances the tile
+// plus a one-site ring (66 x (TH+2) sites, periodic coordinates) from the
+// stored field in HBM and keeps the post-collision populations in LDS, rounded
+// to the storage type exactly as a store to HBM would; step B gathers from LDS,
+// collides again and writes the tile.  The result is that of two single steps,
+// with one HBM read and one HBM write of the populations per two updates.
+constexpr int kTW = 64;  // tile width of the fused kernel (the work list uses 2^6 columns)
+
+// LDS copies of the intermediate populations are held in the storage type.
+template <typename S>
+__device__ __forceinline__ typename Store<S>::C lds_ld(const S* p) {
+    return (typename Store<S>::C)(*p);
+}
+template <>
+__device__ __forceinline__ float lds_ld<__half>(const __half* p) { return __half2float(*p); }
+template <typename S>
+__device__ __forceinline__ void lds_st(S* p, typename Store<S>::C v) { *p = (S)v; }
+template <>
+__device__ __forceinline__ void lds_st<__half>(__half* p, float v) { *p = __float2half_rn(v); }
+
+__device__ __forceinline__ int wrap_coord(int v, int n) {
+    if (v < 0) v += n;
+    if (v >= n) {
+        v -= n;
+        if (v >= n) v %= n;
+    }
+    return v;
+}
+
+template <typename S, int TH>
+static __global__ __launch_bounds__(kBlock) void k_step2(StepLaunch L) {
+    using C = typename Store<S>::C;
+    constexpr int RW = kTW + 2, RH = TH + 2, RN = RW * RH;
+    __shared__ S lds[8 * RN];
+    int last, stride, it;
+    xcd_slice(L.range, last, stride, it);
+    for (; it < last; it += stride) {
+        const Item item = L.items[it];
+        const SlotDesc& d = L.slots[item.slot];
+        const int nx = d.nx, ny = d.ny;
+        const long long plane = d.plane;
+        const int sel = d.cur ^ L.flip;
+        const S* __restrict__ src = reinterpret_cast<const S*>(d.buf[sel]);
+        S* __restrict__ dst = reinterpret_cast<S*>(d.buf[sel ^ 1]);
+        const C* __restrict__ g = reinterpret_cast<const C*>(d.g);
+        Coef<C> k;
+        k.load(d);
+        const int x0 = item.tx * kTW, y0 = item.ty * TH;
+        // step A: tile + ring, HBM -> LDS
+        for (int idx = threadIdx.x; idx < RN; idx += kBlock) {
+            const int i = idx % RW, j = idx / RW;
+            const int xw = wrap_coord(x0 - 1 + i, nx), yw = wrap_coord(y0 - 1 + j, ny);
+            C f[8];
+            gather<S>(src, plane, nx, ny, xw, yw, f);
+            const long long sidx = (long long)yw * nx + xw;
+            C ux, uy;
+            collide<C, false>(f, g[sidx] * k.gscale, g[plane + sidx] * k.gscale, k, ux, uy);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) lds_st<S>(lds + q * RN + idx, f[q]);
+        }
+        __syncthreads();
+        // step B: tile, LDS -> HBM
+        for (int idx = threadIdx.x; idx < kTW * TH; idx += kBlock) {
+            const int i = idx % kTW, j = idx / kTW;
+            const int x = x0 + i, y = y0 + j;
+            if (x < nx && y < ny) {
+                const int r = (j + 1) * RW + (i + 1);
+                C f[8];
+                f[0] = lds_ld<S>(lds + 0 * RN + r - 1);       // c1 = ( 1, 0)
+                f[1] = lds_ld<S>(lds + 1 * RN + r - RW);      // c2 = ( 0, 1)
+                f[2] = lds_ld<S>(lds + 2 * RN + r + 1);       // c3 = (-1, 0)
+                f[3] = lds_ld<S>(lds + 3 * RN + r + RW);      // c4 = ( 0,-1)
+                f[4] = lds_ld<S>(lds + 4 * RN + r - RW - 1);  // c5 = ( 1, 1)
+                f[5] = lds_ld<S>(lds + 5 * RN + r - RW + 1);  // c6 = (-1, 1)
+                f[6] = lds_ld<S>(lds + 6 * RN + r + RW + 1);  // c7 = (-1,-1)
+                f[7] = lds_ld<S>(lds + 7 * RN + r + RW - 1);  // c8 = ( 1,-1)
+                const long long sidx = (long long)y * nx + x;
+                C ux, uy;
+                collide<C, false>(f, g[sidx] * k.gscale, g[plane + sidx] * k.gscale, k, ux, uy);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * plane + sidx, f[q]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Streaming alone (no collision): bit-exact check of the index arithmetic.
 template <typename S>
 static __global__ __launch_bounds__(kBlock) void k_stream_only(StepLaunch L) {

@@ -92,6 +92,17 @@ inline hipError_t launch_step_s(int mode, bool general, int vy, unsigned grid, h
     }
 }
 
+// Fused two-step launch (plain steps only, fast path).
+inline hipError_t launch_step2(int prec, unsigned grid, hipStream_t st, const StepLaunch& L) {
+    if (prec == LBM_FP64)
+        hipLaunchKernelGGL((k_step2<double, 8>), dim3(grid), dim3(kBlock), 0, st, L);
+    else if (prec == LBM_FP32)
+        hipLaunchKernelGGL((k_step2<float, 16>), dim3(grid), dim3(kBlock), 0, st, L);
+    else
+        hipLaunchKernelGGL((k_step2<__half, 16>), dim3(grid), dim3(kBlock), 0, st, L);
+    return hipGetLastError();
+}
+
 inline hipError_t launch_step(int prec, int mode, bool general, int vy, unsigned grid, hipStream_t st,
                        const StepLaunch& L) {
     if (prec == LBM_FP64) return launch_step_s<double>(mode, general, vy, grid, st, L);
@@ -162,16 +173,20 @@ struct Lattice {
     int e_scale = 0;  // half storage: stored = f * 2^-e
     double gmax = 0;  // max |g| of the force (initial half scale)
     int bx_log2 = 6, vy = 1;
+    int tb = 2;   // steps per launch of plain steps (2: fused two-step kernel)
     int cur = 0;  // buffer with the state at flip 0
 
     void* state_buf(int i) const {
         return (prec == prec0) ? mem.buf[i] : mem.pbuf[i];
     }
     const void* force() const { return (prec == prec0) ? mem.g : (const void*)mem.pg; }
-    int tiles_x() const { return (nx + (1 << bx_log2) - 1) >> bx_log2; }
-    // the general-rates variant is instantiated for one row per thread only
-    int eff_vy() const { return general() ? 1 : vy; }
-    int tile_h() const { return (kBlock >> bx_log2) * eff_vy(); }
+    int tiles_x() const { return (nx + (1 << eff_bxl()) - 1) >> eff_bxl(); }
+    // The fused two-step kernel has a fixed tile (64 wide, 16 rows; 8 rows in
+    // FP64); the general-rates variant runs one row per thread.
+    bool fused() const { return tb == 2 && !general(); }
+    int eff_bxl() const { return fused() ? 6 : bx_log2; }
+    int eff_vy() const { return fused() ? (prec == LBM_FP64 ? 2 : 4) : (general() ? 1 : vy); }
+    int tile_h() const { return (kBlock >> eff_bxl()) * eff_vy(); }
     int tiles_y() const { return (ny + tile_h() - 1) / tile_h(); }
     int nitems() const { return tiles_x() * tiles_y(); }
 
@@ -188,7 +203,7 @@ struct Lattice {
         d.cur = cur;
         d.tiles_x = tiles_x();
         d.tiles_y = tiles_y();
-        d.bx_log2 = bx_log2;
+        d.bx_log2 = eff_bxl();
         fill_coefs(d, rates);
         const double sc = (prec == LBM_FP16) ? std::ldexp(1.0, -e_scale) : 1.0;
         d.gscale = sc;

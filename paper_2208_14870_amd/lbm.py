@@ -68,6 +68,7 @@ def load() -> ctypes.CDLL:
         "lbm_set_populations": (i, [vp, vp]),
         "lbm_set_tile": (i, [vp, i, i, i]),
         "lbm_debug_stream_only": (i, [vp, ll]),
+        "lbm_set_time_blocking": (i, [vp, i]),
         "lbm_last_error": (ctypes.c_char_p, [vp]),
         "lbm_batch_slot_bytes": (sz, [i, i, i, i]),
         "lbm_batch_create": (i, [i, vp, sz, vp, ctypes.POINTER(vp)]),
@@ -80,6 +81,7 @@ def load() -> ctypes.CDLL:
         "lbm_batch_get_displacement": (i, [vp, i, vp, vp]),
         "lbm_batch_set_tile": (i, [vp, i, i, i]),
         "lbm_batch_info": (i, [vp, pi, ctypes.POINTER(sz), ctypes.POINTER(sz)]),
+        "lbm_batch_set_time_blocking": (i, [vp, i]),
         "lbm_batch_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sigs.items():
@@ -209,6 +211,9 @@ class Solver:
         self._check(self.lib.lbm_set_tile(self.h, int(bx_log2), int(rows_per_thread),
                                           int(blocks_per_cu)))
 
+    def set_time_blocking(self, steps_per_launch: int):
+        self._check(self.lib.lbm_set_time_blocking(self.h, int(steps_per_launch)))
+
     def displacement(self, out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None):
         shp = (self.ny, self.nx)
         if out is None:
@@ -328,6 +333,9 @@ class Batch:
     def set_tile(self, bx_log2: int, rows_per_thread: int, blocks_per_cu: int = 0):
         self._check(self.lib.lbm_batch_set_tile(self.h, int(bx_log2), int(rows_per_thread),
                                                 int(blocks_per_cu)))
+
+    def set_time_blocking(self, steps_per_launch: int):
+        self._check(self.lib.lbm_batch_set_time_blocking(self.h, int(steps_per_launch)))
 
     def displacement(self, slot: int):
         shp = self.shapes[slot]
