@@ -44,7 +44,7 @@ def measured_traffic():
     summary (FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy), or None when the
     kernel sources changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_step_fp32_1024_traffic.json")
+    path = os.path.join(ROOT, "profiles", "k_step2_fp32_1024_traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
