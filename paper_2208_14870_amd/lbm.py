@@ -166,7 +166,18 @@ class Solver:
         return self._nbytes
 
     # -- API ----------------------------------------------------------------
-    def set_material(self, lame_lambda: float, lame_mu: float):
+    def set_material(self, lame_lambda: float, lame_mu: float, check_stability: bool = False):
+        """Lattice Lame parameters.  With check_stability, refuse materials whose
+        amplification matrix has spectral radius > 1 (Sec. 5): on this lattice's
+        own wavevectors for small lattices, on the paper's k-grid otherwise."""
+        if check_stability:
+            from . import stability
+            small = self.nx * self.ny <= 65536
+            if not stability.is_stable(lame_lambda, lame_mu,
+                                       nx=self.nx if small else None,
+                                       ny=self.ny if small else None):
+                raise ValueError("material is linearly unstable for this scheme "
+                                 "(sup_k rho(L(k)) > 1)")
         self._check(self.lib.lbm_set_material(self.h, float(lame_lambda), float(lame_mu)))
 
     def set_rates(self, theta: float, w12: float = 1.0, w21: float = 1.0, w22: float = 1.0):

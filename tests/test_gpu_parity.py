@@ -421,6 +421,16 @@ def test_divergence_is_reported():
     s.displacement()
 
 
+def test_stability_check_refuses_unstable_material():
+    say("stability check")
+    m = P.Material.from_young_poisson(0.082, -0.4)
+    s = _solver(48, 48)
+    with pytest.raises(ValueError):
+        s.set_material(m.lame_lambda, m.lame_mu, check_stability=True)
+    ok = P.Material.from_shear_poisson(1.0, 0.3)
+    s.set_material(ok.lame_lambda, ok.lame_mu, check_stability=True)
+
+
 def test_invalid_arguments():
     say("argument validation")
     from paper_2208_14870_amd import lbm
