@@ -172,12 +172,13 @@ int lbm_set_populations(lbm_solver *s, const double *f);
  * Results do not depend on the shape.  Used by the autotuner. */
 int lbm_set_tile(lbm_solver *s, int bx_log2, int rows_per_thread, int blocks_per_cu);
 
-/* Temporal blocking: with steps_per_launch = 2, plain steps run in pairs
- * through a kernel that advances a 64 x 16 tile (64 x 8 in FP64) plus a
- * one-site ring in LDS and then the tile again, so populations cross HBM once
- * per two steps.  Results are identical to single steps.  Residual-check steps,
- * odd remainders and the general-rates variant run one step per launch.
- * Overrides the tile shape of lbm_set_tile while active.  Default 2. */
+/* Temporal blocking: with steps_per_launch = k in {2, 3, 4}, plain steps run k at
+ * a time through a kernel that advances a 64 x 16 tile (64 x 8 in FP64) plus
+ * a ring of k-1 sites in LDS and then narrower rings down to the tile, so
+ * populations cross HBM once per k steps.  Results are identical to single
+ * steps.  Residual-check steps, remainders and the general-rates variant run
+ * one step per launch.  Overrides the tile shape of lbm_set_tile while
+ * active.  Default 4 (FP64, FP32), 2 or 3 (FP16, by lattice size). */
 int lbm_set_time_blocking(lbm_solver *s, int steps_per_launch);
 
 /* Diagnostic: nsteps of streaming alone (no collision), for bit-exact checks
@@ -236,8 +237,8 @@ int lbm_batch_get_displacement(lbm_batch *b, int slot, double *ux, double *uy);
  * 3..8). */
 int lbm_batch_set_tile(lbm_batch *b, int bx_log2, int rows_per_thread, int blocks_per_cu);
 
-/* Temporal blocking for all lattices of the batch (see lbm_set_time_blocking);
- * default 2. */
+/* Temporal blocking for all lattices of the batch (see lbm_set_time_blocking,
+ * 1..4); default 4. */
 int lbm_batch_set_time_blocking(lbm_batch *b, int steps_per_launch);
 
 /* Number of active lattices, and arena bytes in use / free (largest hole). */

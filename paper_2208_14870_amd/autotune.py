@@ -29,7 +29,7 @@ DEFAULT_CACHE = os.environ.get("LBM_AUTOTUNE_CACHE",
 def candidates(nx: int, min_bx: int = 3) -> List[Shape]:
     """Single-step tile shapes plus the fused two-step kernel (whose tile is fixed)
     with one workgroup per tile or a persistent grid."""
-    out = [(6, 4, k, 2) for k in (0, 4)]
+    out = [(6, 4, k, t) for t in (4, 3, 2) for k in (0, 4)]
     for b in (5, 6, 7, 8):
         if b < min_bx or (1 << b) > max(2 * nx, 1 << min_bx):
             continue
@@ -52,7 +52,7 @@ def _arch() -> str:
 
 
 def _key(kind: str, precision: str, sites: int) -> str:
-    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}|v2"
+    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}|v3"
 
 
 def _load(path: str) -> Dict[str, list]:

@@ -151,7 +151,7 @@ struct lbm_batch {
     long long phase = 0;
     int bx_log2 = 6, vy = 2;
     int blocks_per_cu = 0;  // 0: one workgroup per tile; k: persistent k per CU
-    int tb = 2;             // steps per launch of plain steps (2: fused two-step kernel)
+    int tb = 4;             // plain steps per launch (2..4: fused multi-step kernel)
     std::string err;
     std::map<std::tuple<long long, int, int, unsigned, unsigned, unsigned>, hipGraphExec_t> graphs;
 
@@ -242,11 +242,11 @@ struct lbm_batch {
     }
 
     // rows per thread of the tiles of one precision's lattices
-    int eff_vy(int prec) const { return tb == 2 ? (prec == LBM_FP64 ? 2 : 4) : vy; }
+    int eff_vy(int prec) const { return tb >= 2 ? fused_th(prec, tb) / 4 : vy; }
 
     long long launches(long long nsteps, bool check) const {
         const long long np = check ? nsteps - 2 : nsteps;
-        return (tb == 2 ? np / 2 + np % 2 : np) + (check ? 2 : 0);
+        return (tb >= 2 ? np / tb + np % tb : np) + (check ? 2 : 0);
     }
 
     hipError_t enqueue(long long nsteps, bool check, hipStream_t st, long long ph) {
@@ -259,9 +259,9 @@ struct lbm_batch {
             }
         };
         long long i = 0;
-        if (tb == 2)
-            for (; i + 1 < np && e == hipSuccess; i += 2, ++ph)
-                each([&](int p, unsigned g) { return launch_step2(p, g, st, args(p, (int)(ph & 1))); });
+        if (tb >= 2)
+            for (; i + tb <= np && e == hipSuccess; i += tb, ++ph)
+                each([&](int p, unsigned g) { return launch_stepN(p, tb, g, st, args(p, (int)(ph & 1))); });
         for (; i < np && e == hipSuccess; ++i, ++ph)
             each([&](int p, unsigned g) {
                 return launch_step(p, kPlain, false, eff_vy(p), g, st, args(p, (int)(ph & 1)));
@@ -486,8 +486,8 @@ int lbm_batch_set_tile(lbm_batch* b, int bx_log2, int rows_per_thread, int block
 
 int lbm_batch_set_time_blocking(lbm_batch* b, int steps_per_launch) {
     if (!b) return LBM_E_ARG;
-    if (steps_per_launch != 1 && steps_per_launch != 2)
-        return b->fail(LBM_E_ARG, "batch_set_time_blocking: steps_per_launch must be 1 or 2");
+    if (steps_per_launch < 1 || steps_per_launch > 4)
+        return b->fail(LBM_E_ARG, "batch_set_time_blocking: steps_per_launch must be in 1..4");
     b->tb = steps_per_launch;
     b->drop_graphs();
     return b->rebuild();
@@ -501,7 +501,7 @@ int lbm_batch_step(lbm_batch* b, long long nsteps, int check) {
     hipError_t e;
     const int flip0 = (int)(b->phase & 1);
     if (b->launches(nsteps, check != 0) >= 4) {
-        auto key = std::make_tuple(nsteps, (check ? 1 : 0) | (b->tb == 2 ? 2 : 0), flip0,
+        auto key = std::make_tuple(nsteps, (check ? 1 : 0) | (b->tb << 1), flip0,
                                    b->grid_for(0), b->grid_for(1), b->grid_for(2));
         auto it = b->graphs.find(key);
         if (it == b->graphs.end()) {

@@ -114,9 +114,9 @@ struct lbm_solver {
         return e;
     }
 
-    hipError_t enqueue_pair(hipStream_t st, long long& ph) {
-        hipError_t e = launch_step2(L.prec, grid, st, launch_args((int)(ph & 1)));
-        ++ph;  // one buffer flip for two steps
+    hipError_t enqueue_fused(hipStream_t st, long long& ph) {
+        hipError_t e = launch_stepN(L.prec, L.tb, grid, st, launch_args((int)(ph & 1)));
+        ++ph;  // one buffer flip for L.tb steps
         return e;
     }
 
@@ -138,7 +138,7 @@ struct lbm_solver {
         hipError_t e = hipSuccess;
         long long i = 0;
         if (L.fused())
-            for (; i + 1 < nplain && e == hipSuccess; i += 2) e = enqueue_pair(st, ph);
+            for (; i + L.tb <= nplain && e == hipSuccess; i += L.tb) e = enqueue_fused(st, ph);
         for (; i < nplain && e == hipSuccess; ++i) e = enqueue_one(kPlain, st, ph);
         if (e == hipSuccess && writeu) e = enqueue_one(kWriteU, st, ph);
         if (e == hipSuccess && check) {
@@ -149,7 +149,7 @@ struct lbm_solver {
     }
 
     long long launches(long long nplain, bool writeu, bool check) const {
-        const long long p = L.fused() ? nplain / 2 + nplain % 2 : nplain;
+        const long long p = L.fused() ? nplain / L.tb + nplain % L.tb : nplain;
         return p + (writeu ? 1 : 0) + (check ? 1 : 0);
     }
 
@@ -172,7 +172,7 @@ struct lbm_solver {
 
     hipError_t run_graph(long long nplain, bool writeu, bool check) {
         const int flip0 = (int)(phase & 1);
-        const int kind = (writeu ? 1 : 0) | (check ? 2 : 0) | (L.fused() ? 4 : 0);
+        const int kind = (writeu ? 1 : 0) | (check ? 2 : 0) | (L.fused() ? 4 * L.tb : 0);
         auto key = std::make_tuple(nplain, kind, flip0, L.prec, L.eff_vy(), L.general() ? 1 : 0, grid);
         auto it = graphs.find(key);
         hipError_t e;
@@ -252,6 +252,7 @@ int lbm_create(int nx, int ny, int precision, int with_polish, void* workspace,
     L.prec0 = L.prec = precision;
     L.polish = with_polish != 0 && precision != LBM_FP64;
     default_tile(precision, nx, ny, L.bx_log2, L.vy);
+    L.tb = default_time_blocking(precision, nx, ny);
     char* base = reinterpret_cast<char*>(workspace);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -379,8 +380,8 @@ int lbm_set_tile(lbm_solver* s, int bx_log2, int rows_per_thread, int blocks_per
 
 int lbm_set_time_blocking(lbm_solver* s, int steps_per_launch) {
     if (!s) return LBM_E_ARG;
-    if (steps_per_launch != 1 && steps_per_launch != 2)
-        return s->fail(LBM_E_ARG, "set_time_blocking: steps_per_launch must be 1 or 2");
+    if (steps_per_launch < 1 || steps_per_launch > 4)
+        return s->fail(LBM_E_ARG, "set_time_blocking: steps_per_launch must be in 1..4");
     s->L.tb = steps_per_launch;
     return s->sync_desc();
 }
@@ -428,6 +429,7 @@ int promote_solver(lbm_solver* s) {
     L.cur = 0;
     s->phase = 0;
     default_tile(LBM_FP64, L.nx, L.ny, L.bx_log2, L.vy);
+    L.tb = default_time_blocking(LBM_FP64, L.nx, L.ny);
     // sync_desc folds phase into cur: phase is 0 so cur stays 0
     int rc = s->sync_desc();
     if (rc != LBM_OK) return rc;

@@ -339,14 +339,16 @@ static __global__ __launch_bounds__(kBlock) void k_step(StepLaunch L) {
 }
 
 // ---------------------------------------------------------------------------
-// two fused steps per launch (temporal blocking)
+// NS fused steps per launch (temporal blocking)
 // ---------------------------------------------------------------------------
-// A workgroup owns an output tile of 64 x TH sites.  Step A advances the tile
-// plus a one-site ring (66 x (TH+2) sites, periodic coordinates) from the
-// stored field in HBM and keeps the post-collision populations in LDS, rounded
-// to the storage type exactly as a store to HBM would; step B gathers from LDS,
-// collides again and writes the tile.  The result is that of two single steps,
-// with one HBM read and one HBM write of the populations per two updates.
+// A workgroup owns an output tile of 64 x TH sites.  Step 1 advances the tile
+// plus a ring of NS-1 sites (periodic coordinates) from the stored field in
+// HBM and keeps the post-collision populations in LDS, rounded to the storage
+// type exactly as a store to HBM would; each middle step gathers from LDS into
+// registers, waits for the whole workgroup, collides and writes back in place
+// on a ring one site narrower; the last step advances the tile and writes it
+// to HBM.  The result is that of NS single steps, with one HBM read and one
+// HBM write of the populations per NS updates.
 constexpr int kTW = 64;  // tile width of the fused kernel (the work list uses 2^6 columns)
 
 // LDS copies of the intermediate populations are held in the storage type.
@@ -363,6 +365,7 @@ __device__ __forceinline__ void lds_st<__half>(__half* p, float v) { *p = __floa
 
 __device__ __forceinline__ int wrap_coord(int v, int n) {
     if (v < 0) v += n;
+    if (v < 0) v = ((v % n) + n) % n;
     if (v >= n) {
         v -= n;
         if (v >= n) v %= n;
@@ -370,10 +373,24 @@ __device__ __forceinline__ int wrap_coord(int v, int n) {
     return v;
 }
 
-template <typename S, int TH>
-static __global__ __launch_bounds__(kBlock) void k_step2(StepLaunch L) {
+// Gather of the 8 populations arriving at LDS position r (row stride RW).
+template <typename S, int RW, int RN>
+__device__ __forceinline__ void lds_gather(const S* lds, int r, typename Store<S>::C f[8]) {
+    f[0] = lds_ld<S>(lds + 0 * RN + r - 1);       // c1 = ( 1, 0)
+    f[1] = lds_ld<S>(lds + 1 * RN + r - RW);      // c2 = ( 0, 1)
+    f[2] = lds_ld<S>(lds + 2 * RN + r + 1);       // c3 = (-1, 0)
+    f[3] = lds_ld<S>(lds + 3 * RN + r + RW);      // c4 = ( 0,-1)
+    f[4] = lds_ld<S>(lds + 4 * RN + r - RW - 1);  // c5 = ( 1, 1)
+    f[5] = lds_ld<S>(lds + 5 * RN + r - RW + 1);  // c6 = (-1, 1)
+    f[6] = lds_ld<S>(lds + 6 * RN + r + RW + 1);  // c7 = (-1,-1)
+    f[7] = lds_ld<S>(lds + 7 * RN + r + RW - 1);  // c8 = ( 1,-1)
+}
+
+template <typename S, int TH, int NS>
+static __global__ __launch_bounds__(kBlock) void k_stepN(StepLaunch L) {
     using C = typename Store<S>::C;
-    constexpr int RW = kTW + 2, RH = TH + 2, RN = RW * RH;
+    constexpr int R = NS - 1;  // ring width of the first step
+    constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
     __shared__ S lds[8 * RN];
     int last, stride, it;
     xcd_slice(L.range, last, stride, it);
@@ -389,10 +406,10 @@ static __global__ __launch_bounds__(kBlock) void k_step2(StepLaunch L) {
         Coef<C> k;
         k.load(d);
         const int x0 = item.tx * kTW, y0 = item.ty * TH;
-        // step A: tile + ring, HBM -> LDS
+        // step 1: tile + ring R, HBM -> LDS
         for (int idx = threadIdx.x; idx < RN; idx += kBlock) {
             const int i = idx % RW, j = idx / RW;
-            const int xw = wrap_coord(x0 - 1 + i, nx), yw = wrap_coord(y0 - 1 + j, ny);
+            const int xw = wrap_coord(x0 - R + i, nx), yw = wrap_coord(y0 - R + j, ny);
             C f[8];
             gather<S>(src, plane, nx, ny, xw, yw, f);
             const long long sidx = (long long)yw * nx + xw;
@@ -402,21 +419,44 @@ static __global__ __launch_bounds__(kBlock) void k_step2(StepLaunch L) {
             for (int q = 0; q < 8; ++q) lds_st<S>(lds + q * RN + idx, f[q]);
         }
         __syncthreads();
-        // step B: tile, LDS -> HBM
+        // middle steps: ring R - m, LDS -> registers -> LDS (in place)
+#pragma unroll
+        for (int m = 1; m < R; ++m) {
+            const int w = kTW + 2 * (R - m), h = TH + 2 * (R - m), n = w * h;
+            constexpr int NM = (RN + kBlock - 1) / kBlock;
+            C f[NM][8];
+#pragma unroll
+            for (int a = 0; a < NM; ++a) {
+                const int e = threadIdx.x + a * kBlock;
+                if (e < n) {
+                    const int i = e % w + m, j = e / w + m;
+                    lds_gather<S, RW, RN>(lds, j * RW + i, f[a]);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < NM; ++a) {
+                const int e = threadIdx.x + a * kBlock;
+                if (e < n) {
+                    const int i = e % w + m, j = e / w + m;
+                    const int xw = wrap_coord(x0 - R + i, nx), yw = wrap_coord(y0 - R + j, ny);
+                    const long long sidx = (long long)yw * nx + xw;
+                    C ux, uy;
+                    collide<C, false>(f[a], g[sidx] * k.gscale, g[plane + sidx] * k.gscale, k,
+                                      ux, uy);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) lds_st<S>(lds + q * RN + j * RW + i, f[a][q]);
+                }
+            }
+            __syncthreads();
+        }
+        // last step: tile, LDS -> HBM
         for (int idx = threadIdx.x; idx < kTW * TH; idx += kBlock) {
             const int i = idx % kTW, j = idx / kTW;
             const int x = x0 + i, y = y0 + j;
             if (x < nx && y < ny) {
-                const int r = (j + 1) * RW + (i + 1);
                 C f[8];
-                f[0] = lds_ld<S>(lds + 0 * RN + r - 1);       // c1 = ( 1, 0)
-                f[1] = lds_ld<S>(lds + 1 * RN + r - RW);      // c2 = ( 0, 1)
-                f[2] = lds_ld<S>(lds + 2 * RN + r + 1);       // c3 = (-1, 0)
-                f[3] = lds_ld<S>(lds + 3 * RN + r + RW);      // c4 = ( 0,-1)
-                f[4] = lds_ld<S>(lds + 4 * RN + r - RW - 1);  // c5 = ( 1, 1)
-                f[5] = lds_ld<S>(lds + 5 * RN + r - RW + 1);  // c6 = (-1, 1)
-                f[6] = lds_ld<S>(lds + 6 * RN + r + RW + 1);  // c7 = (-1,-1)
-                f[7] = lds_ld<S>(lds + 7 * RN + r + RW - 1);  // c8 = ( 1,-1)
+                lds_gather<S, RW, RN>(lds, (j + R) * RW + (i + R), f);
                 const long long sidx = (long long)y * nx + x;
                 C ux, uy;
                 collide<C, false>(f, g[sidx] * k.gscale, g[plane + sidx] * k.gscale, k, ux, uy);

@@ -92,15 +92,32 @@ inline hipError_t launch_step_s(int mode, bool general, int vy, unsigned grid, h
     }
 }
 
-// Fused two-step launch (plain steps only, fast path).
-inline hipError_t launch_step2(int prec, unsigned grid, hipStream_t st, const StepLaunch& L) {
-    if (prec == LBM_FP64)
-        hipLaunchKernelGGL((k_step2<double, 8>), dim3(grid), dim3(kBlock), 0, st, L);
-    else if (prec == LBM_FP32)
-        hipLaunchKernelGGL((k_step2<float, 16>), dim3(grid), dim3(kBlock), 0, st, L);
-    else
-        hipLaunchKernelGGL((k_step2<__half, 16>), dim3(grid), dim3(kBlock), 0, st, L);
+// Fused launch of `ns` plain steps (fast path): tile 64 x fused_th(prec, ns).
+inline int fused_th(int prec, int ns) {
+    (void)ns;
+    return prec == LBM_FP64 ? 8 : 16;
+}
+
+template <typename S, int TH>
+inline void launch_stepN_t(int ns, unsigned grid, hipStream_t st, const StepLaunch& L) {
+    if (ns == 2) hipLaunchKernelGGL((k_stepN<S, TH, 2>), dim3(grid), dim3(kBlock), 0, st, L);
+    else if (ns == 3) hipLaunchKernelGGL((k_stepN<S, TH, 3>), dim3(grid), dim3(kBlock), 0, st, L);
+    else hipLaunchKernelGGL((k_stepN<S, TH, 4>), dim3(grid), dim3(kBlock), 0, st, L);
+}
+
+inline hipError_t launch_stepN(int prec, int ns, unsigned grid, hipStream_t st,
+                               const StepLaunch& L) {
+    if (prec == LBM_FP64) launch_stepN_t<double, 8>(ns, grid, st, L);
+    else if (prec == LBM_FP32) launch_stepN_t<float, 16>(ns, grid, st, L);
+    else launch_stepN_t<__half, 16>(ns, grid, st, L);
     return hipGetLastError();
+}
+
+// Default steps per launch (measured on MI355X): four for FP64/FP32; half
+// storage is register-bound beyond two on large lattices.
+inline int default_time_blocking(int prec, int nx, int ny) {
+    if (prec == LBM_FP16) return (long long)nx * ny >= (1LL << 22) ? 2 : 3;
+    return 4;
 }
 
 inline hipError_t launch_step(int prec, int mode, bool general, int vy, unsigned grid, hipStream_t st,
@@ -173,7 +190,7 @@ struct Lattice {
     int e_scale = 0;  // half storage: stored = f * 2^-e
     double gmax = 0;  // max |g| of the force (initial half scale)
     int bx_log2 = 6, vy = 1;
-    int tb = 2;   // steps per launch of plain steps (2: fused two-step kernel)
+    int tb = 4;   // plain steps per launch (2..4: fused multi-step kernel)
     int cur = 0;  // buffer with the state at flip 0
 
     void* state_buf(int i) const {
@@ -183,9 +200,9 @@ struct Lattice {
     int tiles_x() const { return (nx + (1 << eff_bxl()) - 1) >> eff_bxl(); }
     // The fused two-step kernel has a fixed tile (64 wide, 16 rows; 8 rows in
     // FP64); the general-rates variant runs one row per thread.
-    bool fused() const { return tb == 2 && !general(); }
+    bool fused() const { return tb >= 2 && !general(); }
     int eff_bxl() const { return fused() ? 6 : bx_log2; }
-    int eff_vy() const { return fused() ? (prec == LBM_FP64 ? 2 : 4) : (general() ? 1 : vy); }
+    int eff_vy() const { return fused() ? fused_th(prec, tb) / 4 : (general() ? 1 : vy); }
     int tile_h() const { return (kBlock >> eff_bxl()) * eff_vy(); }
     int tiles_y() const { return (ny + tile_h() - 1) / tile_h(); }
     int nitems() const { return tiles_x() * tiles_y(); }

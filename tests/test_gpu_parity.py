@@ -268,35 +268,32 @@ def test_full_size_8192_sampled(prec, tol):
     ("fp64", 64, 8, 4), ("fp32", 2, 2, 5), ("fp32", 65, 17, 9), ("fp32", 256, 48, 12),
     ("fp16", 5, 3, 5), ("fp16", 97, 31, 8), ("fp64", 1024, 1024, 6)])
 def test_time_blocking_identical_to_single_steps(prec, nx, ny, steps):
-    """Two steps per launch (tile + ring in LDS) give bit-identical populations to
-    single steps (ragged tiles, lattices smaller than the tile, odd step counts),
+    """Two to four steps per launch (tile + ring in LDS) give bit-identical
+    populations to single steps (ragged tiles, lattices smaller than the tile,
+    step counts that leave remainders, checks interleaved with fused launches),
     and the FP64 result matches the oracle."""
     say(f"time blocking {prec} {nx}x{ny} steps {steps}")
     mat = P.Material.from_shear_poisson(0.9, 0.3)
     f0, gx, gy = _rand_state(nx, ny, 3 + nx)
-    out = []
-    for tb in (1, 2):
+    res = {}
+    for tb in (1, 2, 3, 4):
         s = _solver(nx, ny, prec)
         s.set_material(mat.lame_lambda, mat.lame_mu)
         s.set_body_force(dev(gx), dev(gy))
         s.set_populations(dev(f0))
         s.set_time_blocking(tb)
         s.step(steps)
-        out.append(host(s.populations()))
-        if tb == 2:
-            n, r, st = s.solve_to_tol(0.0, 9, 3)  # checks interleaved with fused pairs
-            out.append(host(s.populations()))
-            s.set_time_blocking(1)
-            s.set_populations(dev(out[0]))
-            n2, r2, _ = s.solve_to_tol(0.0, 9, 3)
-            out.append(host(s.populations()))
-            # the residual's summation order follows the tile shape: equal to rounding
-            assert n == n2 and r == pytest.approx(r2, rel=1e-12)
-            np.testing.assert_array_equal(out[-1], out[-2])
-    np.testing.assert_array_equal(out[0], out[1])
+        a = host(s.populations())
+        n, r, st = s.solve_to_tol(0.0, 11, 5)  # residual checks between fused launches
+        res[tb] = (a, host(s.populations()), n, r)
+    for tb in (2, 3, 4):
+        np.testing.assert_array_equal(res[tb][0], res[1][0])
+        np.testing.assert_array_equal(res[tb][1], res[1][1])
+        # the residual's summation order follows the tile shape: equal to rounding
+        assert res[tb][2] == res[1][2] and res[tb][3] == pytest.approx(res[1][3], rel=1e-12)
     if prec == "fp64":
         fn = O.run(f0, gx, gy, omega(mat), steps)
-        assert rel_l2(out[1], fn) <= 1e-12
+        assert rel_l2(res[2][0], fn) <= 1e-12
 
 
 # ---------------------------------------------------------------------------
