@@ -331,6 +331,10 @@ def main():
         "fp32_last_residual": r32["last"][0][0],
         "fp32_rel_l2_vs_manufactured": [round(x[1], 6) for x in r32["last"]],
     }
+    tr = out["roofline"]["traffic"]
+    if tr:
+        # measured HBM bytes per launch over the same launch duration
+        out["roofline"]["measured_hbm_gbs"] = round(tr / (r32["plain_kernel_avg_us"] * 1e-6) / 1e9, 1)
     if args.calib_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

@@ -178,7 +178,7 @@ int lbm_set_tile(lbm_solver *s, int bx_log2, int rows_per_thread, int blocks_per
  * populations cross HBM once per k steps.  Results are identical to single
  * steps.  Residual-check steps, remainders and the general-rates variant run
  * one step per launch.  Overrides the tile shape of lbm_set_tile while
- * active.  Default 4 (FP64, FP32), 2 or 3 (FP16, by lattice size). */
+ * active.  Default 4. */
 int lbm_set_time_blocking(lbm_solver *s, int steps_per_launch);
 
 /* Diagnostic: nsteps of streaming alone (no collision), for bit-exact checks

@@ -113,10 +113,12 @@ inline hipError_t launch_stepN(int prec, int ns, unsigned grid, hipStream_t st,
     return hipGetLastError();
 }
 
-// Default steps per launch (measured on MI355X): four for FP64/FP32; half
-// storage is register-bound beyond two on large lattices.
+// Default steps per launch (measured on MI355X: four is fastest or tied for
+// every storage type at 1024^2 and 8192^2).
 inline int default_time_blocking(int prec, int nx, int ny) {
-    if (prec == LBM_FP16) return (long long)nx * ny >= (1LL << 22) ? 2 : 3;
+    (void)prec;
+    (void)nx;
+    (void)ny;
     return 4;
 }
 
