@@ -126,7 +126,10 @@ int lbm_step(lbm_solver *s, long long nsteps);
  * f(n) with n = *steps_done steps taken by this call; *residual = the last
  * r evaluated (NaN if none).  With a polish threshold set (lbm_set_polish), an
  * FP32/FP16 solver switches to FP64 storage once r <= r_switch or r stops
- * decreasing, and continues in FP64.  Errors: LBM_E_ARG, LBM_E_STATE (no
+ * decreasing, resets the two undamped modes that narrow storage leaves
+ * rounding noise in (the staggered first moments at k = (pi,0), (0,pi) to
+ * their fixed point, the mean first moments to their exact value: the
+ * initial sums plus steps * sum g), and continues in FP64.  Errors: LBM_E_ARG, LBM_E_STATE (no
  * force), LBM_E_DIVERGED (non-finite residual; state left readable),
  * LBM_E_HIP. */
 int lbm_solve_to_tol(lbm_solver *s, double tol, long long max_steps, int check_every,
@@ -161,7 +164,8 @@ int lbm_error_norms(lbm_solver *s, const double *ux_ref, const double *uy_ref, d
 
 /* Checkpoint / restart: the pre-collision populations f(n) as FP64 device
  * arrays [8][ny][nx] (paper order, unscaled).  set leaves the step count
- * unchanged. */
+ * unchanged and is blocking (it records the mean first moments of the given
+ * state for the polish switch). */
 int lbm_get_populations(lbm_solver *s, double *f);
 int lbm_set_populations(lbm_solver *s, const double *f);
 
@@ -227,7 +231,8 @@ int lbm_batch_step(lbm_batch *b, long long nsteps, int check);
 int lbm_batch_residuals(lbm_batch *b, double *r_host, long long *steps_host);
 
 /* Switch a FP32/FP16 lattice to FP64 storage (polish phase); needs its
- * polish reservation. */
+ * polish reservation.  Resets the undamped modes as lbm_solve_to_tol's
+ * switch does.  Blocking. */
 int lbm_batch_promote(lbm_batch *b, int slot);
 
 /* Current displacement of one lattice (FP64 device arrays [ny][nx]). */

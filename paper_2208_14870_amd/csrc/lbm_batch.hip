@@ -139,11 +139,11 @@ struct lbm_batch {
     Item* d_items = nullptr;
     double* d_partial = nullptr;
     SlotRow* d_rows = nullptr;
-    double* d_red = nullptr;  // kErrBlocks x 4 + 8 doubles of reduction scratch
+    double* d_red = nullptr;  // kErrBlocks x 8 + 8 doubles of reduction scratch
     long long cap_items = 0;
     // host
     SlotRow* h_rows = nullptr;  // pinned staging (max_slots rows + 3 ranges)
-    double* h_result = nullptr;  // pinned, 4 x max_slots
+    double* h_result = nullptr;  // pinned, max(4 x max_slots, 8)
     size_t heap_off = 0;
     Arena arena;
     std::vector<BSlot> slots;
@@ -328,7 +328,7 @@ int lbm_batch_create(int max_slots, void* arena, size_t arena_bytes, void* strea
     b->d_range = reinterpret_cast<int*>(take(6 * sizeof(int)));
     b->d_result = reinterpret_cast<double*>(take(4 * max_slots * sizeof(double)));
     b->d_rows = reinterpret_cast<SlotRow*>(take((max_slots + 2) * sizeof(SlotRow)));
-    b->d_red = reinterpret_cast<double*>(take((kErrBlocks * 4 + 8) * sizeof(double)));
+    b->d_red = reinterpret_cast<double*>(take((kErrBlocks * 8 + 8) * sizeof(double)));
     b->d_items = reinterpret_cast<Item*>(take(b->cap_items * sizeof(Item)));
     b->d_partial = reinterpret_cast<double*>(take(b->cap_items * 3 * sizeof(double)));
     if (off > arena_bytes) {
@@ -348,7 +348,8 @@ int lbm_batch_create(int max_slots, void* arena, size_t arena_bytes, void* strea
         e = hipHostMalloc(reinterpret_cast<void**>(&b->h_rows), (max_slots + 2) * sizeof(SlotRow),
                           hipHostMallocDefault);
     if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&b->h_result), 4 * max_slots * sizeof(double),
+        e = hipHostMalloc(reinterpret_cast<void**>(&b->h_result),
+                          std::max(4 * max_slots, 8) * sizeof(double),
                           hipHostMallocDefault);
     if (e == hipSuccess) e = zero_bytes(b->d_result, 4 * max_slots * sizeof(double), b->stream);
     if (e != hipSuccess) {
@@ -426,8 +427,9 @@ int lbm_batch_add(lbm_batch* b, int nx, int ny, int precision, int with_polish, 
         s = BSlot();
         return b->hip_fail(e, "batch_add");
     }
-    if (precision == LBM_FP16) {
-        // initial scale from max |g| (blocking two-stage reduction)
+    if (precision == LBM_FP16 || L.polish) {
+        // sum g (the mean first moments at promotion) and the initial half
+        // scale from max |g| (blocking two-stage reduction)
         hipLaunchKernelGGL(k_force_stats, dim3(kErrBlocks), dim3(kBlock), 0, b->stream, gx, gy, N,
                            b->d_red);
         hipLaunchKernelGGL(k_reduce4<kForceMask>, dim3(1), dim3(kBlock), 0, b->stream, b->d_red,
@@ -441,7 +443,8 @@ int lbm_batch_add(lbm_batch* b, int nx, int ny, int precision, int with_polish, 
             return b->hip_fail(e, "batch_add force stats");
         }
         L.gmax = b->h_result[3];
-        L.e_scale = initial_half_exponent(L, L.gmax);
+        L.rebase_force(0, b->h_result[0], b->h_result[1]);
+        if (precision == LBM_FP16) L.e_scale = initial_half_exponent(L, L.gmax);
     }
     // the next launch reads buf[cur ^ (phase & 1)] = buf[0]
     L.cur = (int)(b->phase & 1);
@@ -583,8 +586,10 @@ int lbm_batch_promote(lbm_batch* b, int slot) {
     L.cur = (int)(b->phase & 1);
     int rc = b->rebuild();
     if (rc != LBM_OK) return rc;
-    // reset the undamped staggered modes excited by the narrow phase
-    e = neutral_reset(LBM_FP64, L.desc(), b->sel(s), b->d_red, b->h_result, b->stream);
+    // reset the undamped modes (staggered moments, mean) excited by the narrow phase
+    double target[2];
+    L.mean_target(s.steps, target);
+    e = neutral_reset(LBM_FP64, L.desc(), b->sel(s), target, b->d_red, b->h_result, b->stream);
     if (e != hipSuccess) return b->hip_fail(e, "batch_promote: neutral modes");
     return LBM_OK;
 }

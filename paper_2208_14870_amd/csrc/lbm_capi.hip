@@ -44,7 +44,7 @@ struct lbm_solver {
     int* d_count = nullptr;
     double* d_partial = nullptr;
     double* d_result = nullptr;
-    double* d_red = nullptr;  // kErrBlocks x 4 + 4
+    double* d_red = nullptr;  // kErrBlocks x 8 + 8
     double* h_result = nullptr;  // pinned, 8 doubles
     long long max_items_ = 0;
     int nitems = 0;
@@ -208,7 +208,7 @@ size_t lbm_workspace_bytes(int nx, int ny, int precision, int with_polish) {
     const long long N = (long long)nx * ny;
     const long long mi = max_items(nx, ny);
     size_t b = al(sizeof(SlotDesc)) + 4 * al(sizeof(int)) + al(4 * 8) + al(mi * sizeof(Item)) +
-               al(mi * 3 * 8) + al((kErrBlocks * 4 + 8) * 8);
+               al(mi * 3 * 8) + al((kErrBlocks * 8 + 8) * 8);
     b += lattice_bytes(N, precision, with_polish != 0);
     return b;
 }
@@ -269,7 +269,7 @@ int lbm_create(int nx, int ny, int precision, int with_polish, void* workspace,
     s->d_result = reinterpret_cast<double*>(take(4 * 8));
     s->d_items = reinterpret_cast<Item*>(take(s->max_items_ * sizeof(Item)));
     s->d_partial = reinterpret_cast<double*>(take(s->max_items_ * 3 * 8));
-    s->d_red = reinterpret_cast<double*>(take((kErrBlocks * 4 + 8) * 8));
+    s->d_red = reinterpret_cast<double*>(take((kErrBlocks * 8 + 8) * 8));
     carve_lattice(base + off, L.N, precision, L.polish, L.mem);
     int rc = lbm_reset(s);
     if (rc != LBM_OK) {
@@ -298,6 +298,8 @@ int lbm_reset(lbm_solver* s) {
     L.cur = 0;
     s->phase = 0;
     s->steps = 0;
+    L.mbase[0] = L.mbase[1] = 0.0;
+    L.mbase_steps = 0;
     hipError_t e = zero_bytes(L.mem.buf[0], 8 * L.plane * elem_bytes(L.prec0), s->stream);
     if (e == hipSuccess) e = zero_bytes(L.mem.u, 2 * L.plane * 8, s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "lbm_reset");
@@ -353,6 +355,7 @@ int lbm_set_body_force(lbm_solver* s, const double* gx, const double* gy) {
     if (!std::isfinite(s2)) return s->fail(LBM_E_ARG, "set_body_force: non-finite force");
     L.has_force = true;
     L.gmax = gmax;
+    L.rebase_force(s->steps, sx, sy);
     if (L.prec0 == LBM_FP16 && s->steps == 0) L.e_scale = initial_half_exponent(L, gmax);
     int rc = s->sync_desc();
     if (rc != LBM_OK) return rc;
@@ -433,9 +436,12 @@ int promote_solver(lbm_solver* s) {
     // sync_desc folds phase into cur: phase is 0 so cur stays 0
     int rc = s->sync_desc();
     if (rc != LBM_OK) return rc;
-    // the narrow phase leaves rounding noise in the two undamped staggered
-    // modes; reset them so the FP64 phase can converge
-    e = neutral_reset(LBM_FP64, L.desc(), s->sel(), s->d_red, s->h_result, s->stream);
+    // the narrow phase leaves rounding noise in the undamped modes (the
+    // staggered moments and the mean); reset them so that the FP64 phase
+    // converges to the exact trajectory's fixed point
+    double target[2];
+    L.mean_target(s->steps, target);
+    e = neutral_reset(LBM_FP64, L.desc(), s->sel(), target, s->d_red, s->h_result, s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "promote: neutral modes");
     return LBM_OK;
 }
@@ -598,7 +604,13 @@ int lbm_set_populations(lbm_solver* s, const double* f) {
     if (s->L.prec == LBM_FP64) e = launch_set_f<double>(d, s->sel(), f, sc, s->stream);
     else if (s->L.prec == LBM_FP32) e = launch_set_f<float>(d, s->sel(), f, sc, s->stream);
     else e = launch_set_f<__half>(d, s->sel(), f, sc, s->stream);
+    if (e == hipSuccess)
+        e = neutral_measure(s->L.prec, d, s->sel(), s->d_red, s->h_result, s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "set_populations");
+    // the mean first moments of the given state start the exact trajectory
+    s->L.mbase[0] = s->h_result[4];
+    s->L.mbase[1] = s->h_result[5];
+    s->L.mbase_steps = s->steps;
     return LBM_OK;
 }
 
@@ -614,6 +626,7 @@ int lbm_debug_stream_only(lbm_solver* s, long long nsteps) {
     }
     if (e != hipSuccess) return s->hip_fail(e, "debug_stream_only");
     s->steps += nsteps;
+    s->L.mbase_steps += nsteps;  // streaming alone adds no force
     return LBM_OK;
 }
 

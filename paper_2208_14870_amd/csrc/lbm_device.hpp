@@ -731,17 +731,20 @@ static __global__ __launch_bounds__(kBlock) void k_build_items(Item* items, int 
 static __global__ void k_set_int(int* p, int v) { *p = v; }
 static __global__ void k_set_desc(SlotDesc* p, SlotDesc v) { *p = v; }
 
-// Neutral staggered modes.  For even nx the staggered first moment
+// Neutral modes.  (1) The mean first moments: collision adds g to m10, m01 and
+// streaming permutes, so sum_x m10(f(n)) = sum_x m10(f(0)) + n sum_x gx exactly
+// (eigenvalue 1 at k = 0).  (2) The staggered first moments: for even nx,
 // J = sum_x (-1)^x m10(f(n)) obeys J(n+1) = -J(n) - sum_x (-1)^x gx for any
-// relaxation rates (collision adds gx to m10; streaming by c_x = +-1 flips
-// the sign of (-1)^x), and likewise in y with m01, gy: the modes k = (pi, 0)
-// and (0, pi) have eigenvalue -1 and are never damped.  A state whose J is
-// off its fixed point oscillates with period two forever.  These kernels
-// measure and reset those two amplitudes on the stored (post-collision)
-// field S, whose staggered moment is J_S = J_f + G with fixed point G/2.
+// relaxation rates (streaming with c_x = +-1 flips (-1)^x), and likewise in y
+// with m01, gy: eigenvalue -1 at k = (pi, 0), (0, pi).  Neither mode is ever
+// damped, so rounding noise from narrow storage stays in them for good.  These
+// kernels measure both on the stored (post-collision) field S, whose sums
+// equal those of f(n) for the mean and J_S = J_f + G (fixed point G/2) for the
+// staggered mode, and reset them.
 //
-// Stage 1: per block (sum (-1)^x m10(S), sum (-1)^y m01(S), sum (-1)^x gx,
-// sum (-1)^y gy), unscaled FP64.
+// Stage 1: per block two groups of four sums, unscaled FP64:
+// (sum (-1)^x m10(S), sum (-1)^y m01(S), sum (-1)^x gx, sum (-1)^y gy) and
+// (sum m10(S), sum m01(S), 0, 0).
 template <typename S>
 static __global__ __launch_bounds__(kBlock) void k_neutral_sums(SlotDesc d, int sel,
                                                                 double* partial) {
@@ -751,36 +754,44 @@ static __global__ __launch_bounds__(kBlock) void k_neutral_sums(SlotDesc d, int 
     const S* st = reinterpret_cast<const S*>(d.buf[sel]);
     const C* g = reinterpret_cast<const C*>(d.g);
     const double sx = (d.nx % 2 == 0) ? 1.0 : 0.0, sy = (d.ny % 2 == 0) ? 1.0 : 0.0;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    double v[4] = {0.0, 0.0, 0.0, 0.0}, w[4] = {0.0, 0.0, 0.0, 0.0};
     for (long long s = (long long)blockIdx.x * kBlock + threadIdx.x; s < N;
          s += (long long)gridDim.x * kBlock) {
         const int x = (int)(s % d.nx), y = (int)(s / d.nx);
         double f[8];
         for (int q = 0; q < 8; ++q) f[q] = (double)Store<S>::ld(st + q * d.plane + s);
-        const double m10 = (f[0] - f[2]) + ((f[4] - f[6]) - (f[5] - f[7]));
-        const double m01 = (f[1] - f[3]) + ((f[4] - f[6]) + (f[5] - f[7]));
+        const double m10 = ((f[0] - f[2]) + ((f[4] - f[6]) - (f[5] - f[7]))) * d.inv_scale;
+        const double m01 = ((f[1] - f[3]) + ((f[4] - f[6]) + (f[5] - f[7]))) * d.inv_scale;
         const double px = (x & 1) ? -sx : sx, py = (y & 1) ? -sy : sy;
-        v[0] += px * m10 * d.inv_scale;
-        v[1] += py * m01 * d.inv_scale;
+        v[0] += px * m10;
+        v[1] += py * m01;
         v[2] += px * (double)g[s];
         v[3] += py * (double)g[d.plane + s];
+        w[0] += m10;
+        w[1] += m01;
     }
     block_reduce4<0>(v, lds);
+    block_reduce4<0>(w, lds);
     if (threadIdx.x == 0)
-        for (int c = 0; c < 4; ++c) partial[4 * blockIdx.x + c] = v[c];
+        for (int c = 0; c < 4; ++c) {
+            partial[4 * blockIdx.x + c] = v[c];
+            partial[4 * (gridDim.x + blockIdx.x) + c] = w[c];
+        }
 }
 
-// Stage 2: S1 += ex (-1)^x, S3 -= ex (-1)^x, S2 += ey (-1)^y, S4 -= ey (-1)^y
-// (changes only the staggered m10 / m01; ex, ey already in storage units).
+// Stage 2: S1 += (ex (-1)^x + mx), S3 -= (ex (-1)^x + mx),
+//          S2 += (ey (-1)^y + my), S4 -= (ey (-1)^y + my)
+// (changes only m10 / m01 of S: the staggered and the uniform parts; all
+// amounts already in storage units).
 template <typename S>
 static __global__ __launch_bounds__(kBlock) void k_neutral_fix(SlotDesc d, int sel, double ex,
-                                                               double ey) {
+                                                               double ey, double mx, double my) {
     using C = typename Store<S>::C;
     const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (s >= (long long)d.nx * d.ny) return;
     const int x = (int)(s % d.nx), y = (int)(s / d.nx);
     S* st = reinterpret_cast<S*>(d.buf[sel]);
-    const double px = (x & 1) ? -ex : ex, py = (y & 1) ? -ey : ey;
+    const double px = ((x & 1) ? -ex : ex) + mx, py = ((y & 1) ? -ey : ey) + my;
     S* p0 = st + 0 * d.plane + s;
     S* p1 = st + 1 * d.plane + s;
     S* p2 = st + 2 * d.plane + s;

@@ -191,6 +191,25 @@ struct Lattice {
     bool has_material = false, has_force = false;
     int e_scale = 0;  // half storage: stored = f * 2^-e
     double gmax = 0;  // max |g| of the force (initial half scale)
+    // The mean first moments of the exact trajectory: sum_x m10, sum_x m01 were
+    // mbase at step mbase_steps and grow by gsum = sum_x g (FP64) per step.
+    double gsum[2] = {0, 0};
+    double mbase[2] = {0, 0};
+    long long mbase_steps = 0;
+    void mean_target(long long steps, double out[2]) const {
+        out[0] = mbase[0] + (double)(steps - mbase_steps) * gsum[0];
+        out[1] = mbase[1] + (double)(steps - mbase_steps) * gsum[1];
+    }
+    // a new force from step `steps` on
+    void rebase_force(long long steps, double sx, double sy) {
+        double m[2];
+        mean_target(steps, m);
+        mbase[0] = m[0];
+        mbase[1] = m[1];
+        mbase_steps = steps;
+        gsum[0] = sx;
+        gsum[1] = sy;
+    }
     int bx_log2 = 6, vy = 1;
     int tb = 4;   // plain steps per launch (2..4: fused multi-step kernel)
     int cur = 0;  // buffer with the state at flip 0
@@ -302,36 +321,56 @@ inline hipError_t zero_bytes(void* p, size_t bytes, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Reset the two neutral staggered modes (k = (pi,0), (0,pi)) of the stored
-// state to their fixed point (blocking: one FP64 reduction + one update).
-// scratch: kErrBlocks * 4 + 4 doubles of device memory; host: 4 pinned doubles.
+// Measure the neutral modes of the stored state (blocking): out[0..3] =
+// staggered sums and their force terms, out[4..5] = sum m10, sum m01.
+// scratch: 8 * kErrBlocks + 8 doubles of device memory; host: 8 pinned doubles.
 template <typename S>
-inline hipError_t neutral_reset_t(const SlotDesc& d, int sel, double* scratch, double* host,
-                                  hipStream_t st) {
+inline hipError_t neutral_measure_t(const SlotDesc& d, int sel, double* scratch, double* host,
+                                    hipStream_t st) {
     hipLaunchKernelGGL(k_neutral_sums<S>, dim3(kErrBlocks), dim3(kBlock), 0, st, d, sel, scratch);
-    hipLaunchKernelGGL(k_reduce4<0>, dim3(1), dim3(kBlock), 0, st, scratch, kErrBlocks,
-                       scratch + 4 * kErrBlocks);
+    double* out = scratch + 8 * kErrBlocks;
+    hipLaunchKernelGGL(k_reduce4<0>, dim3(1), dim3(kBlock), 0, st, scratch, kErrBlocks, out);
+    hipLaunchKernelGGL(k_reduce4<0>, dim3(1), dim3(kBlock), 0, st, scratch + 4 * kErrBlocks,
+                       kErrBlocks, out + 4);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)
-        e = hipMemcpyAsync(host, scratch + 4 * kErrBlocks, 4 * sizeof(double),
-                           hipMemcpyDeviceToHost, st);
+        e = hipMemcpyAsync(host, out, 8 * sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
+}
+
+inline hipError_t neutral_measure(int prec, const SlotDesc& d, int sel, double* scratch,
+                                  double* host, hipStream_t st) {
+    if (prec == LBM_FP64) return neutral_measure_t<double>(d, sel, scratch, host, st);
+    if (prec == LBM_FP32) return neutral_measure_t<float>(d, sel, scratch, host, st);
+    return neutral_measure_t<__half>(d, sel, scratch, host, st);
+}
+
+// Reset the neutral modes of the stored state to their exact values: the
+// staggered moments to their fixed point and the mean first moments to
+// `mean_target` (sum_x m10, sum_x m01 of the exact trajectory).
+template <typename S>
+inline hipError_t neutral_reset_t(const SlotDesc& d, int sel, const double mean_target[2],
+                                  double* scratch, double* host, hipStream_t st) {
+    hipError_t e = neutral_measure_t<S>(d, sel, scratch, host, st);
     if (e != hipSuccess) return e;
     const double N = (double)d.nx * d.ny;
-    // J_S -> G/2 ; the update changes J_S by 2 eps N per unit eps
+    // J_S -> G/2 ; an update of eps changes J_S by 2 eps N (and the mean by 2 eps N)
     const double ex = (d.nx % 2 == 0) ? (0.5 * host[2] - host[0]) / (2.0 * N) : 0.0;
     const double ey = (d.ny % 2 == 0) ? (0.5 * host[3] - host[1]) / (2.0 * N) : 0.0;
+    const double mx = (mean_target[0] - host[4]) / (2.0 * N);
+    const double my = (mean_target[1] - host[5]) / (2.0 * N);
     const double sc = 1.0 / d.inv_scale;  // into storage units
     hipLaunchKernelGGL(k_neutral_fix<S>, dim3(blocks_for((long long)d.nx * d.ny)), dim3(kBlock), 0,
-                       st, d, sel, ex * sc, ey * sc);
+                       st, d, sel, ex * sc, ey * sc, mx * sc, my * sc);
     return hipGetLastError();
 }
 
-inline hipError_t neutral_reset(int prec, const SlotDesc& d, int sel, double* scratch,
-                                double* host, hipStream_t st) {
-    if (prec == LBM_FP64) return neutral_reset_t<double>(d, sel, scratch, host, st);
-    if (prec == LBM_FP32) return neutral_reset_t<float>(d, sel, scratch, host, st);
-    return neutral_reset_t<__half>(d, sel, scratch, host, st);
+inline hipError_t neutral_reset(int prec, const SlotDesc& d, int sel, const double mean_target[2],
+                                double* scratch, double* host, hipStream_t st) {
+    if (prec == LBM_FP64) return neutral_reset_t<double>(d, sel, mean_target, scratch, host, st);
+    if (prec == LBM_FP32) return neutral_reset_t<float>(d, sel, mean_target, scratch, host, st);
+    return neutral_reset_t<__half>(d, sel, mean_target, scratch, host, st);
 }
 
 // Convert the FP64 force into the lattice's arithmetic type (and keep the
