@@ -177,13 +177,32 @@ int lbm_set_populations(lbm_solver *s, const double *f);
 int lbm_set_tile(lbm_solver *s, int bx_log2, int rows_per_thread, int blocks_per_cu);
 
 /* Temporal blocking: with steps_per_launch = k in {2, 3, 4}, plain steps run k at
- * a time through a kernel that advances a 64 x 16 tile (64 x 8 in FP64) plus
- * a ring of k-1 sites in LDS and then narrower rings down to the tile, so
- * populations cross HBM once per k steps.  Results are identical to single
- * steps.  Residual-check steps, remainders and the general-rates variant run
- * one step per launch.  Overrides the tile shape of lbm_set_tile while
- * active.  Default 4. */
+ * a time through one fused kernel, so populations cross HBM once per k steps.
+ * Results are identical to single steps.  Residual-check steps, remainders
+ * and the general-rates variant run one step per launch.  Overrides the tile
+ * shape of lbm_set_tile while active.  Default 4.  The fused kernel is chosen
+ * with lbm_set_fused_kernel. */
 int lbm_set_time_blocking(lbm_solver *s, int steps_per_launch);
+
+/* Fused kernel kinds (both give identical results). */
+enum lbm_fused_kernel {
+    /* LDS tile: a workgroup advances a 64-wide tile (16 rows in FP32, 8 on
+     * lattices of up to 2^21 sites and in FP64, 12 in FP16) plus a ring of
+     * k-1 sites in LDS, then narrower rings down to the tile. */
+    LBM_FUSED_TILE = 0,
+    /* Register wavefront: a wave owns a strip of 64 - 2k columns plus a ring
+     * of k columns per side and marches along y through segments of
+     * `segment_rows` rows, keeping three rows of every intermediate step in
+     * registers (x neighbours through cross-lane moves); no LDS. */
+    LBM_FUSED_WAVEFRONT = 1
+};
+
+/* Select the fused kernel for steps_per_launch >= 2.  segment_rows (1..2^20)
+ * is used by LBM_FUSED_WAVEFRONT only: each strip is split into segments of
+ * that many rows, each recomputing 2k halo rows.  Default: the wavefront with
+ * 256-row segments for FP64 lattices of at least 2^22 sites (also after a
+ * polish switch), the tile kernel otherwise.  Errors: LBM_E_ARG. */
+int lbm_set_fused_kernel(lbm_solver *s, int kind, int segment_rows);
 
 /* Diagnostic: nsteps of streaming alone (no collision), for bit-exact checks
  * of the periodic index arithmetic (Eq. streaming, Sec. 6.1). */

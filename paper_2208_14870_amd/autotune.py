@@ -1,8 +1,9 @@
 """Launch-shape autotuner for the step kernel.
 
 Times candidate launch shapes (tile width, rows per thread, persistent grid
-or one workgroup per tile) with HIP events on the solver's stream and keeps
-the fastest.  Results are cached in a JSON file keyed by GPU architecture,
+or one workgroup per tile, steps per launch, and for a single lattice the
+fused kernel: LDS tile or register wavefront with its segment height) with
+HIP events on the solver's stream and keeps the fastest.  Results are cached in a JSON file keyed by GPU architecture,
 storage precision, workload kind and a size bucket (log2 of the sites per
 step), so a shape is measured once per machine and size class.
 
@@ -19,29 +20,41 @@ from typing import Callable, Dict, Iterable, List, Optional, Tuple
 
 import torch
 
-Shape = Tuple[int, int, int, int]  # (bx_log2, rows_per_thread, blocks_per_cu, steps_per_launch)
+# (bx_log2, rows_per_thread, blocks_per_cu, steps_per_launch, wavefront_rows);
+# wavefront_rows 0 = LDS tile kernel for the fused launches
+Shape = Tuple[int, int, int, int, int]
 
 DEFAULT_CACHE = os.environ.get("LBM_AUTOTUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache",
                                             "lbm_elastic_autotune.json"))
 
 
-def candidates(nx: int, min_bx: int = 3) -> List[Shape]:
-    """Single-step tile shapes plus the fused two-step kernel (whose tile is fixed)
-    with one workgroup per tile or a persistent grid."""
-    out = [(6, 4, k, t) for t in (4, 3, 2) for k in (0, 4)]
+def candidates(nx: int, min_bx: int = 3, ny: int = 0, wavefront: bool = False) -> List[Shape]:
+    """Single-step tile shapes, the fused LDS tile kernel (whose tile is fixed)
+    with one workgroup per tile or a persistent grid, and (single lattices) the
+    register wavefront with a few segment heights."""
+    out = [(6, 4, k, t, 0) for t in (4, 3, 2) for k in (0, 4)]
+    if wavefront:
+        for rows in (32, 64, 128, 256):
+            if rows <= max(ny, 32):
+                out += [(6, 4, 0, t, rows) for t in (4, 3)]
     for b in (5, 6, 7, 8):
         if b < min_bx or (1 << b) > max(2 * nx, 1 << min_bx):
             continue
         for v in (1, 2, 4):
             for k in (0, 4):
-                out.append((b, v, k, 1))
+                out.append((b, v, k, 1, 0))
     return out
 
 
 def _apply(obj, shp: Shape):
     obj.set_time_blocking(shp[3])
     obj.set_tile(shp[0], shp[1], shp[2])
+    if hasattr(obj, "set_fused_kernel"):
+        if shp[4] > 0:
+            obj.set_fused_kernel("wavefront", shp[4])
+        else:
+            obj.set_fused_kernel("tile")
 
 
 def _arch() -> str:
@@ -52,7 +65,7 @@ def _arch() -> str:
 
 
 def _key(kind: str, precision: str, sites: int) -> str:
-    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}|v3"
+    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}|v4"
 
 
 def _load(path: str) -> Dict[str, list]:
@@ -113,7 +126,8 @@ def tune_solver(solver, precision: str, cache_path: Optional[str] = DEFAULT_CACH
         shp = tuple(cache[key])
         _apply(solver, shp)
         return shp
-    res = time_shapes(lambda s: _apply(solver, s), solver.step, candidates(solver.nx, 0), sites)
+    res = time_shapes(lambda s: _apply(solver, s), solver.step,
+                      candidates(solver.nx, 0, solver.ny, wavefront=True), sites)
     shp = res[0][1]
     _apply(solver, shp)
     if cache_path:

@@ -199,6 +199,7 @@ struct lbm_batch {
                 s.L.bx_log2 = bx_log2;
                 s.L.vy = vy;
                 s.L.tb = tb;
+                s.L.th = fused_th(p, 1LL << 22);  // one tile height per precision
                 s.first = (int)total;
                 s.count = s.L.nitems();
                 total += s.count;
@@ -242,7 +243,7 @@ struct lbm_batch {
     }
 
     // rows per thread of the tiles of one precision's lattices
-    int eff_vy(int prec) const { return tb >= 2 ? fused_th(prec, tb) / 4 : vy; }
+    int eff_vy(int prec) const { return tb >= 2 ? fused_th(prec, 1LL << 22) / 4 : vy; }
 
     long long launches(long long nsteps, bool check) const {
         const long long np = check ? nsteps - 2 : nsteps;
@@ -261,7 +262,7 @@ struct lbm_batch {
         long long i = 0;
         if (tb >= 2)
             for (; i + tb <= np && e == hipSuccess; i += tb, ++ph)
-                each([&](int p, unsigned g) { return launch_stepN(p, tb, g, st, args(p, (int)(ph & 1))); });
+                each([&](int p, unsigned g) { return launch_stepN(p, tb, fused_th(p, 1LL << 22), g, st, args(p, (int)(ph & 1))); });
         for (; i < np && e == hipSuccess; ++i, ++ph)
             each([&](int p, unsigned g) {
                 return launch_step(p, kPlain, false, eff_vy(p), g, st, args(p, (int)(ph & 1)));

@@ -115,7 +115,10 @@ struct lbm_solver {
     }
 
     hipError_t enqueue_fused(hipStream_t st, long long& ph) {
-        hipError_t e = launch_stepN(L.prec, L.tb, grid, st, launch_args((int)(ph & 1)));
+        hipError_t e =
+            L.wave_hs > 0
+                ? launch_wave(L.prec, L.tb, L.nx, L.ny, L.wave_hs, d_desc, (int)(ph & 1), st)
+                : launch_stepN(L.prec, L.tb, L.th, grid, st, launch_args((int)(ph & 1)));
         ++ph;  // one buffer flip for L.tb steps
         return e;
     }
@@ -172,7 +175,8 @@ struct lbm_solver {
 
     hipError_t run_graph(long long nplain, bool writeu, bool check) {
         const int flip0 = (int)(phase & 1);
-        const int kind = (writeu ? 1 : 0) | (check ? 2 : 0) | (L.fused() ? 4 * L.tb : 0);
+        const int kind = (writeu ? 1 : 0) | (check ? 2 : 0) | (L.fused() ? 4 * L.tb : 0) |
+                         (L.fused() ? (L.th << 5) | (L.wave_hs << 10) : 0);
         auto key = std::make_tuple(nplain, kind, flip0, L.prec, L.eff_vy(), L.general() ? 1 : 0, grid);
         auto it = graphs.find(key);
         hipError_t e;
@@ -253,6 +257,8 @@ int lbm_create(int nx, int ny, int precision, int with_polish, void* workspace,
     L.polish = with_polish != 0 && precision != LBM_FP64;
     default_tile(precision, nx, ny, L.bx_log2, L.vy);
     L.tb = default_time_blocking(precision, nx, ny);
+    L.th = fused_th(precision, (long long)nx * ny);
+    L.wave_hs = default_wave_rows(precision, nx, ny);
     char* base = reinterpret_cast<char*>(workspace);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -389,6 +395,20 @@ int lbm_set_time_blocking(lbm_solver* s, int steps_per_launch) {
     return s->sync_desc();
 }
 
+int lbm_set_fused_kernel(lbm_solver* s, int kind, int segment_rows) {
+    if (!s) return LBM_E_ARG;
+    if (kind == LBM_FUSED_TILE) {
+        s->L.wave_hs = 0;
+    } else if (kind == LBM_FUSED_WAVEFRONT) {
+        if (segment_rows < 1 || segment_rows > (1 << 20))
+            return s->fail(LBM_E_ARG, "set_fused_kernel: segment_rows must be in 1..2^20");
+        s->L.wave_hs = segment_rows;
+    } else {
+        return s->fail(LBM_E_ARG, "set_fused_kernel: kind must be LBM_FUSED_TILE or LBM_FUSED_WAVEFRONT");
+    }
+    return s->sync_desc();
+}
+
 int lbm_step(lbm_solver* s, long long nsteps) {
     if (!s || nsteps < 0) return s ? s->fail(LBM_E_ARG, "step: nsteps < 0") : LBM_E_ARG;
     if (!s->L.has_material || !s->L.has_force)
@@ -433,6 +453,8 @@ int promote_solver(lbm_solver* s) {
     s->phase = 0;
     default_tile(LBM_FP64, L.nx, L.ny, L.bx_log2, L.vy);
     L.tb = default_time_blocking(LBM_FP64, L.nx, L.ny);
+    L.th = fused_th(LBM_FP64, L.N);
+    L.wave_hs = default_wave_rows(LBM_FP64, L.nx, L.ny);
     // sync_desc folds phase into cur: phase is 0 so cur stays 0
     int rc = s->sync_desc();
     if (rc != LBM_OK) return rc;

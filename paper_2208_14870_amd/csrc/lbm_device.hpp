@@ -65,23 +65,44 @@ struct Item {
 // so loads and stores carry the non-temporal hint (measured on MI355X: best
 // for both cache-resident and HBM-resident lattices).
 // ---------------------------------------------------------------------------
+//
+// Pointers taken from a descriptor in memory are generic, and the compiler
+// then emits flat instructions, which also count on the LDS/scalar counter:
+// a wait for an LDS read or a descriptor load would wait for every flat
+// store in flight.  All lattice memory is global, so accesses go through
+// an explicit global address-space pointer.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> glob(T* p) { return (gptr<T>)p; }
+
 template <typename S> struct Store;
 template <> struct Store<double> {
     using C = double;
-    __device__ static __forceinline__ C ld(const double* p) { return __builtin_nontemporal_load(p); }
-    __device__ static __forceinline__ void st(double* p, C v) { __builtin_nontemporal_store(v, p); }
+    __device__ static __forceinline__ C ld(const double* p) {
+        return __builtin_nontemporal_load(glob(p));
+    }
+    __device__ static __forceinline__ void st(double* p, C v) {
+        __builtin_nontemporal_store(v, glob(p));
+    }
 };
 template <> struct Store<float> {
     using C = float;
-    __device__ static __forceinline__ C ld(const float* p) { return __builtin_nontemporal_load(p); }
-    __device__ static __forceinline__ void st(float* p, C v) { __builtin_nontemporal_store(v, p); }
+    __device__ static __forceinline__ C ld(const float* p) {
+        return __builtin_nontemporal_load(glob(p));
+    }
+    __device__ static __forceinline__ void st(float* p, C v) {
+        __builtin_nontemporal_store(v, glob(p));
+    }
 };
 template <> struct Store<__half> {
     using C = float;
-    __device__ static __forceinline__ C ld(const __half* p) { return __half2float(*p); }
+    __device__ static __forceinline__ C ld(const __half* p) {
+        return __half2float(__ushort_as_half(*glob(reinterpret_cast<const unsigned short*>(p))));
+    }
     __device__ static __forceinline__ void st(__half* p, C v) {
         __half h = __float2half_rn(v);
-        __builtin_nontemporal_store(__half_as_ushort(h), reinterpret_cast<unsigned short*>(p));
+        __builtin_nontemporal_store(__half_as_ushort(h), glob(reinterpret_cast<unsigned short*>(p)));
     }
 };
 
@@ -123,8 +144,16 @@ struct Coef {
 //   f2*,f4* = cs ms - cd md +- (hth uy + gy/4)
 //   f5*,f7* =  c11 m11 +- tq (ux + uy)
 //   f6*,f8* = -c11 m11 -+ tq (ux - uy)
+//
+// Rounding is fixed by the source: contraction is off inside and the fused
+// multiply-adds are written out, so every kernel that calls this (single
+// step, fused steps, any unrolled copy) rounds every site identically.
+__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename C, bool GENERAL>
 __device__ __forceinline__ void collide(C f[8], C gx, C gy, const Coef<C>& k, C& ux, C& uy) {
+#pragma clang fp contract(off)
     const C p = f[4] - f[6];   // f5 - f7
     const C q = f[5] - f[7];   // f6 - f8
     const C h13 = f[0] + f[2];
@@ -142,10 +171,11 @@ __device__ __forceinline__ void collide(C f[8], C gx, C gy, const Coef<C>& k, C&
     ux = m10 + hgx;
     uy = m01 + hgy;
     if constexpr (!GENERAL) {
-        const C a = k.cs * ms + k.cd * md;
-        const C b = k.cs * ms - k.cd * md;
-        const C ex = k.hth * ux + C(0.5) * hgx;
-        const C ey = k.hth * uy + C(0.5) * hgy;
+        const C dd = k.cd * md;
+        const C a = fmac(k.cs, ms, dd);
+        const C b = fmac(k.cs, ms, -dd);
+        const C ex = fmac(k.hth, ux, C(0.5) * hgx);
+        const C ey = fmac(k.hth, uy, C(0.5) * hgy);
         const C s = k.c11 * m11;
         const C t1 = k.tq * (ux + uy);
         const C t2 = k.tq * (ux - uy);
@@ -306,8 +336,8 @@ static __global__ __launch_bounds__(kBlock) void k_step(StepLaunch L) {
             if (!ok[j]) continue;
             const int y = y0 + j * th;
             const long long s = (long long)y * nx + x;
-            const C gx = g[s] * k.gscale;
-            const C gy = g[plane + s] * k.gscale;
+            const C gx = glob(g)[s] * k.gscale;
+            const C gy = glob(g)[plane + s] * k.gscale;
             C ux, uy;
             collide<C, GENERAL>(f[j], gx, gy, k, ux, uy);
 #pragma unroll
@@ -315,7 +345,7 @@ static __global__ __launch_bounds__(kBlock) void k_step(StepLaunch L) {
             if constexpr (MODE != kPlain) {
                 const double uxd = (double)ux * d.inv_scale, uyd = (double)uy * d.inv_scale;
                 if constexpr (MODE == kCheck) {
-                    const double dx = uxd - d.u[s], dy = uyd - d.u[plane + s];
+                    const double dx = uxd - glob(d.u)[s], dy = uyd - glob(d.u)[plane + s];
                     dsum += dx * dx + dy * dy;
                     ssum += uxd * uxd + uyd * uyd;
                     double m = 0.0;
@@ -323,16 +353,16 @@ static __global__ __launch_bounds__(kBlock) void k_step(StepLaunch L) {
                     for (int q = 0; q < 8; ++q) m = fmax(m, (double)fabs(f[j][q]));
                     fmaxv = fmax(fmaxv, m);
                 }
-                d.u[s] = uxd;
-                d.u[plane + s] = uyd;
+                glob(d.u)[s] = uxd;
+                glob(d.u)[plane + s] = uyd;
             }
         }
         if constexpr (MODE == kCheck) {
             block_reduce3(dsum, ssum, fmaxv, lds);
             if (threadIdx.x == 0) {
-                L.partial[3 * it + 0] = dsum;
-                L.partial[3 * it + 1] = ssum;
-                L.partial[3 * it + 2] = fmaxv;
+                glob(L.partial)[3 * it + 0] = dsum;
+                glob(L.partial)[3 * it + 1] = ssum;
+                glob(L.partial)[3 * it + 2] = fmaxv;
             }
         }
     }
@@ -349,6 +379,12 @@ static __global__ __launch_bounds__(kBlock) void k_step(StepLaunch L) {
 // on a ring one site narrower; the last step advances the tile and writes it
 // to HBM.  The result is that of NS single steps, with one HBM read and one
 // HBM write of the populations per NS updates.
+//
+// Every thread keeps the same NM sites of the ring region (site e = thread +
+// a * 256, a < NM) in all NS steps, so that step 1 issues all its population
+// and force loads before it waits once, the force stays in registers, and the
+// later steps touch only LDS until the final store.  Sites past the region
+// (e >= RN) load a valid address and store nothing.
 constexpr int kTW = 64;  // tile width of the fused kernel (the work list uses 2^6 columns)
 
 // LDS copies of the intermediate populations are held in the storage type.
@@ -386,11 +422,52 @@ __device__ __forceinline__ void lds_gather(const S* lds, int r, typename Store<S
     f[7] = lds_ld<S>(lds + 7 * RN + r + RW - 1);  // c8 = ( 1,-1)
 }
 
+// Step 1 of the fused kernel for one tile: gathers the ring region from the
+// stored field (periodic coordinates), collides, and writes the post-collision
+// populations to LDS; returns the scaled force of the thread's sites.  Every
+// slot loads (the last slot's spare lanes re-read the region's last site), so
+// all loads are issued before the first use.
+template <typename S, int TH, int NS>
+__device__ __forceinline__ void stepN_first(const S* __restrict__ src,
+                                            const typename Store<S>::C* __restrict__ g,
+                                            long long plane, int nx, int ny, int x0, int y0,
+                                            const Coef<typename Store<S>::C>& k, S* lds,
+                                            typename Store<S>::C gx[], typename Store<S>::C gy[]) {
+    using C = typename Store<S>::C;
+    constexpr int R = NS - 1;
+    constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
+    constexpr int NM = (RN + kBlock - 1) / kBlock;
+    C f[NM][8];
+#pragma unroll
+    for (int a = 0; a < NM; ++a) {
+        const int e = min((int)threadIdx.x + a * kBlock, RN - 1);
+        const int i = e % RW, j = e / RW;
+        const int xw = wrap_coord(x0 - R + i, nx), yw = wrap_coord(y0 - R + j, ny);
+        gather<S>(src, plane, nx, ny, xw, yw, f[a]);
+        const long long sidx = (long long)yw * nx + xw;
+        gx[a] = glob(g)[sidx];
+        gy[a] = glob(g)[plane + sidx];
+    }
+#pragma unroll
+    for (int a = 0; a < NM; ++a) {
+        const int e = (int)threadIdx.x + a * kBlock;
+        gx[a] *= k.gscale;
+        gy[a] *= k.gscale;
+        C ux, uy;
+        collide<C, false>(f[a], gx[a], gy[a], k, ux, uy);
+        if (e < RN) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) lds_st<S>(lds + q * RN + e, f[a][q]);
+        }
+    }
+}
+
 template <typename S, int TH, int NS>
 static __global__ __launch_bounds__(kBlock) void k_stepN(StepLaunch L) {
     using C = typename Store<S>::C;
     constexpr int R = NS - 1;  // ring width of the first step
     constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
+    constexpr int NM = (RN + kBlock - 1) / kBlock;  // ring sites per thread
     __shared__ S lds[8 * RN];
     int last, stride, it;
     xcd_slice(L.range, last, stride, it);
@@ -406,65 +483,193 @@ static __global__ __launch_bounds__(kBlock) void k_stepN(StepLaunch L) {
         Coef<C> k;
         k.load(d);
         const int x0 = item.tx * kTW, y0 = item.ty * TH;
+        C f[NM][8], gx[NM], gy[NM];
         // step 1: tile + ring R, HBM -> LDS
-        for (int idx = threadIdx.x; idx < RN; idx += kBlock) {
-            const int i = idx % RW, j = idx / RW;
-            const int xw = wrap_coord(x0 - R + i, nx), yw = wrap_coord(y0 - R + j, ny);
-            C f[8];
-            gather<S>(src, plane, nx, ny, xw, yw, f);
-            const long long sidx = (long long)yw * nx + xw;
-            C ux, uy;
-            collide<C, false>(f, g[sidx] * k.gscale, g[plane + sidx] * k.gscale, k, ux, uy);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) lds_st<S>(lds + q * RN + idx, f[q]);
-        }
+        stepN_first<S, TH, NS>(src, g, plane, nx, ny, x0, y0, k, lds, gx, gy);
         __syncthreads();
         // middle steps: ring R - m, LDS -> registers -> LDS (in place)
 #pragma unroll
         for (int m = 1; m < R; ++m) {
-            const int w = kTW + 2 * (R - m), h = TH + 2 * (R - m), n = w * h;
-            constexpr int NM = (RN + kBlock - 1) / kBlock;
-            C f[NM][8];
 #pragma unroll
             for (int a = 0; a < NM; ++a) {
-                const int e = threadIdx.x + a * kBlock;
-                if (e < n) {
-                    const int i = e % w + m, j = e / w + m;
-                    lds_gather<S, RW, RN>(lds, j * RW + i, f[a]);
-                }
+                const int e = (int)threadIdx.x + a * kBlock;
+                const int i = e % RW, j = e / RW;
+                if (e < RN && i >= m && i < RW - m && j >= m && j < RH - m)
+                    lds_gather<S, RW, RN>(lds, e, f[a]);
             }
             __syncthreads();
 #pragma unroll
             for (int a = 0; a < NM; ++a) {
-                const int e = threadIdx.x + a * kBlock;
-                if (e < n) {
-                    const int i = e % w + m, j = e / w + m;
-                    const int xw = wrap_coord(x0 - R + i, nx), yw = wrap_coord(y0 - R + j, ny);
-                    const long long sidx = (long long)yw * nx + xw;
+                const int e = (int)threadIdx.x + a * kBlock;
+                const int i = e % RW, j = e / RW;
+                if (e < RN && i >= m && i < RW - m && j >= m && j < RH - m) {
                     C ux, uy;
-                    collide<C, false>(f[a], g[sidx] * k.gscale, g[plane + sidx] * k.gscale, k,
-                                      ux, uy);
+                    collide<C, false>(f[a], gx[a], gy[a], k, ux, uy);
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) lds_st<S>(lds + q * RN + j * RW + i, f[a][q]);
+                    for (int q = 0; q < 8; ++q) lds_st<S>(lds + q * RN + e, f[a][q]);
                 }
             }
             __syncthreads();
         }
-        // last step: tile, LDS -> HBM
-        for (int idx = threadIdx.x; idx < kTW * TH; idx += kBlock) {
-            const int i = idx % kTW, j = idx / kTW;
-            const int x = x0 + i, y = y0 + j;
-            if (x < nx && y < ny) {
-                C f[8];
-                lds_gather<S, RW, RN>(lds, (j + R) * RW + (i + R), f);
-                const long long sidx = (long long)y * nx + x;
-                C ux, uy;
-                collide<C, false>(f, g[sidx] * k.gscale, g[plane + sidx] * k.gscale, k, ux, uy);
+        // last step: the tile, LDS -> HBM
 #pragma unroll
-                for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * plane + sidx, f[q]);
+        for (int a = 0; a < NM; ++a) {
+            const int e = (int)threadIdx.x + a * kBlock;
+            const int i = e % RW, j = e / RW;
+            const int x = x0 + i - R, y = y0 + j - R;
+            if (e < RN && i >= R && i < R + kTW && j >= R && j < R + TH && x < nx && y < ny) {
+                lds_gather<S, RW, RN>(lds, e, f[a]);
+                C ux, uy;
+                collide<C, false>(f[a], gx[a], gy[a], k, ux, uy);
+                const long long sidx = (long long)y * nx + x;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * plane + sidx, f[a][q]);
             }
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// NS fused steps per launch, register wavefront
+// ---------------------------------------------------------------------------
+// One wave owns a strip of 64 lanes = W = 64 - 2 NS output columns plus NS
+// ring columns per side, and marches up a segment of rows.  At row t it loads
+// the stored field's row t (level 0) and advances level k = 1..NS at row t - k
+// from level k-1's rows t-k-1, t-k, t-k+1, which it keeps in registers: the
+// y neighbours are earlier rows of the same lane, the x neighbours come from
+// lanes l -+ 1 through a whole-wave DPP shift.  Level NS is stored.  Each
+// level loses one valid lane per side, so after NS levels lanes NS..63-NS hold
+// the output.  No LDS and no barrier; every intermediate level is rounded to
+// the storage type exactly as a store would round it, so the result equals NS
+// single steps bit for bit.
+__device__ __forceinline__ float lane_from_left(float v) {  // lane l <- lane l-1
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_from_right(float v) {  // lane l <- lane l+1
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double lane_from_left(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_from_right(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// value as the storage type would hold it
+template <typename S>
+__device__ __forceinline__ typename Store<S>::C as_stored(typename Store<S>::C v) { return v; }
+template <>
+__device__ __forceinline__ float as_stored<__half>(float v) { return __half2float(__float2half_rn(v)); }
+
+struct WaveLaunch {
+    const SlotDesc* slots;
+    int flip;
+    int strips, segs, hs;  // strips of W output columns, segments of hs rows
+};
+
+template <typename S, int NS>
+static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
+    using C = typename Store<S>::C;
+    constexpr int W = kWave - 2 * NS;
+    constexpr int PF = 3;  // rows loaded ahead
+    // wave index as a scalar: the row loop and the row bases stay scalar
+    const int wid = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlock / kWave) +
+                                                   (int)(threadIdx.x >> 6));
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    if (wid >= L.strips * L.segs) return;  // whole waves leave; no barrier follows
+    const SlotDesc& d = L.slots[0];
+    const int nx = d.nx, ny = d.ny;
+    const long long plane = d.plane;
+    const int sel = d.cur ^ L.flip;
+    const S* __restrict__ src = reinterpret_cast<const S*>(d.buf[sel]);
+    S* __restrict__ dst = reinterpret_cast<S*>(d.buf[sel ^ 1]);
+    const C* __restrict__ g = reinterpret_cast<const C*>(d.g);
+    Coef<C> k;
+    k.load(d);
+    const int sx = wid % L.strips, sy = wid / L.strips;
+    const int xs = sx * W, ya = sy * L.hs, yb = min(ya + L.hs, ny);
+    const int x = xs - NS + lane;
+    const int xw = wrap_coord(x, nx);
+    const bool out_lane = lane >= NS && lane < NS + W && x < nx;
+    // loads of row t: scalar row base + per-lane byte offset of the column
+    const unsigned xs_b = (unsigned)xw * (unsigned)sizeof(S), xg_b = (unsigned)xw * (unsigned)sizeof(C);
+    auto load_row = [&](int t, C* a, C* gg) {
+        const long long r = (long long)wrap_coord(t, ny) * nx;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            a[q] = Store<S>::ld(reinterpret_cast<const S*>(
+                reinterpret_cast<const char*>(src + (q * plane + r)) + xs_b));
+        gg[0] = *glob(reinterpret_cast<const C*>(reinterpret_cast<const char*>(g + r) + xg_b));
+        gg[1] = *glob(reinterpret_cast<const C*>(reinterpret_cast<const char*>(g + (plane + r)) + xg_b));
+    };
+    C A0[6][8];       // level 0 rows by iteration mod 6 (three back, three ahead)
+    C Gp[6][2];       // force rows, same slots
+    C A[NS][3][8];    // levels 1..NS-1 (index lv-1 unused for lv = 0), rows mod 3
+    C G[NS + 1][2];   // force of rows t, t-1, ..., t-NS
+#pragma unroll
+    for (int j = 0; j <= NS; ++j) G[j][0] = G[j][1] = C(0);
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) A0[r][q] = C(0);
+#pragma unroll
+    for (int lv = 0; lv < NS; ++lv)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) A[lv][r][q] = C(0);
+    const int t_first = ya - NS;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) load_row(t_first + u, A0[u], Gp[u]);
+    for (int t0 = t_first; t0 < yb + NS; t0 += 6) {
+#pragma unroll
+        for (int u = 0; u < 6; ++u) {
+            const int t = t0 + u;
+            load_row(t + PF, A0[(u + PF) % 6], Gp[(u + PF) % 6]);
+#pragma unroll
+            for (int j = NS; j > 0; --j) {
+                G[j][0] = G[j - 1][0];
+                G[j][1] = G[j - 1][1];
+            }
+            G[0][0] = Gp[u][0] * k.gscale;
+            G[0][1] = Gp[u][1] * k.gscale;
+#pragma unroll
+            for (int lv = 1; lv <= NS; ++lv) {
+                // level lv-1 rows t-lv+1 (this iteration), t-lv, t-lv-1
+                const C* R0 = lv == 1 ? A0[u] : A[lv - 1][u % 3];
+                const C* R1 = lv == 1 ? A0[(u + 5) % 6] : A[lv - 1][(u + 2) % 3];
+                const C* R2 = lv == 1 ? A0[(u + 4) % 6] : A[lv - 1][(u + 1) % 3];
+                C f[8];
+                f[0] = lane_from_left(R1[0]);   // c1 = ( 1, 0) from (x-1, y)
+                f[1] = R2[1];                   // c2 = ( 0, 1) from (x, y-1)
+                f[2] = lane_from_right(R1[2]);  // c3 = (-1, 0) from (x+1, y)
+                f[3] = R0[3];                   // c4 = ( 0,-1) from (x, y+1)
+                f[4] = lane_from_left(R2[4]);   // c5 = ( 1, 1) from (x-1, y-1)
+                f[5] = lane_from_right(R2[5]);  // c6 = (-1, 1) from (x+1, y-1)
+                f[6] = lane_from_right(R0[6]);  // c7 = (-1,-1) from (x+1, y+1)
+                f[7] = lane_from_left(R0[7]);   // c8 = ( 1,-1) from (x-1, y+1)
+                C ux, uy;
+                collide<C, false>(f, G[lv][0], G[lv][1], k, ux, uy);
+                if (lv < NS) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) A[lv][u % 3][q] = as_stored<S>(f[q]);
+                } else {
+                    const int y = t - NS;
+                    if (out_lane && y >= ya && y < yb) {
+                        const long long o = (long long)y * nx + x;
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * plane + o, f[q]);
+                    }
+                }
+            }
+        }
     }
 }
 

@@ -76,6 +76,8 @@ inline hipError_t launch_step_t(bool general, int vy, unsigned grid, hipStream_t
         hipLaunchKernelGGL((k_step<S, MODE, false, 1>), dim3(grid), dim3(kBlock), 0, st, L);
     } else if (vy == 2) {
         hipLaunchKernelGGL((k_step<S, MODE, false, 2>), dim3(grid), dim3(kBlock), 0, st, L);
+    } else if (vy == 3) {
+        hipLaunchKernelGGL((k_step<S, MODE, false, 3>), dim3(grid), dim3(kBlock), 0, st, L);
     } else {
         hipLaunchKernelGGL((k_step<S, MODE, false, 4>), dim3(grid), dim3(kBlock), 0, st, L);
     }
@@ -92,10 +94,13 @@ inline hipError_t launch_step_s(int mode, bool general, int vy, unsigned grid, h
     }
 }
 
-// Fused launch of `ns` plain steps (fast path): tile 64 x fused_th(prec, ns).
-inline int fused_th(int prec, int ns) {
-    (void)ns;
-    return prec == LBM_FP64 ? 8 : 16;
+// Tile height of the fused LDS kernel (width 64), measured on MI355X: FP64 8
+// (two workgroups per CU by LDS); FP32 16, or 8 on lattices of up to 2^21
+// sites, where more and smaller tiles balance the grid better; FP16 12.
+inline int fused_th(int prec, long long sites) {
+    if (prec == LBM_FP64) return 8;
+    if (prec == LBM_FP32) return sites <= (1LL << 21) ? 8 : 16;
+    return 12;
 }
 
 template <typename S, int TH>
@@ -105,12 +110,48 @@ inline void launch_stepN_t(int ns, unsigned grid, hipStream_t st, const StepLaun
     else hipLaunchKernelGGL((k_stepN<S, TH, 4>), dim3(grid), dim3(kBlock), 0, st, L);
 }
 
-inline hipError_t launch_stepN(int prec, int ns, unsigned grid, hipStream_t st,
+// th must be a height fused_th returns for prec.
+inline hipError_t launch_stepN(int prec, int ns, int th, unsigned grid, hipStream_t st,
                                const StepLaunch& L) {
-    if (prec == LBM_FP64) launch_stepN_t<double, 8>(ns, grid, st, L);
-    else if (prec == LBM_FP32) launch_stepN_t<float, 16>(ns, grid, st, L);
-    else launch_stepN_t<__half, 16>(ns, grid, st, L);
+    if (prec == LBM_FP64 && th == 8) launch_stepN_t<double, 8>(ns, grid, st, L);
+    else if (prec == LBM_FP32 && th == 8) launch_stepN_t<float, 8>(ns, grid, st, L);
+    else if (prec == LBM_FP32 && th == 16) launch_stepN_t<float, 16>(ns, grid, st, L);
+    else if (prec == LBM_FP16 && th == 12) launch_stepN_t<__half, 12>(ns, grid, st, L);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+// Register-wavefront launch of `ns` plain steps on slot 0 (single lattice),
+// segments of hs rows.
+template <typename S>
+inline void launch_wave_t(int ns, unsigned grid, hipStream_t st, const WaveLaunch& W) {
+    if (ns == 2) hipLaunchKernelGGL((k_wave<S, 2>), dim3(grid), dim3(kBlock), 0, st, W);
+    else if (ns == 3) hipLaunchKernelGGL((k_wave<S, 3>), dim3(grid), dim3(kBlock), 0, st, W);
+    else hipLaunchKernelGGL((k_wave<S, 4>), dim3(grid), dim3(kBlock), 0, st, W);
+}
+
+inline hipError_t launch_wave(int prec, int ns, int nx, int ny, int hs, const SlotDesc* slots,
+                              int flip, hipStream_t st) {
+    WaveLaunch W;
+    W.slots = slots;
+    W.flip = flip;
+    W.strips = (nx + (kWave - 2 * ns) - 1) / (kWave - 2 * ns);
+    W.hs = hs;
+    W.segs = (ny + hs - 1) / hs;
+    const long long waves = (long long)W.strips * W.segs;
+    const unsigned grid = (unsigned)((waves + kBlock / kWave - 1) / (kBlock / kWave));
+    if (prec == LBM_FP64) launch_wave_t<double>(ns, grid, st, W);
+    else if (prec == LBM_FP32) launch_wave_t<float>(ns, grid, st, W);
+    else launch_wave_t<__half>(ns, grid, st, W);
+    return hipGetLastError();
+}
+
+// Default fused kernel: the register wavefront (segments of 256 rows) for
+// FP64 lattices of at least 2^22 sites, where it beats the LDS tile kernel
+// on MI355X; the tile kernel otherwise.  Returns the segment height, 0 for
+// the tile kernel.
+inline int default_wave_rows(int prec, int nx, int ny) {
+    return (prec == LBM_FP64 && (long long)nx * ny >= (1LL << 22)) ? 256 : 0;
 }
 
 // Default steps per launch (measured on MI355X: four is fastest or tied for
@@ -211,19 +252,21 @@ struct Lattice {
         gsum[1] = sy;
     }
     int bx_log2 = 6, vy = 1;
-    int tb = 4;   // plain steps per launch (2..4: fused multi-step kernel)
-    int cur = 0;  // buffer with the state at flip 0
+    int tb = 4;       // plain steps per launch (2..4: fused multi-step kernel)
+    int th = 16;      // tile height of the fused LDS kernel (fused_th)
+    int wave_hs = 0;  // > 0: fused launches use the register wavefront, segments of wave_hs rows
+    int cur = 0;      // buffer with the state at flip 0
 
     void* state_buf(int i) const {
         return (prec == prec0) ? mem.buf[i] : mem.pbuf[i];
     }
     const void* force() const { return (prec == prec0) ? mem.g : (const void*)mem.pg; }
     int tiles_x() const { return (nx + (1 << eff_bxl()) - 1) >> eff_bxl(); }
-    // The fused two-step kernel has a fixed tile (64 wide, 16 rows; 8 rows in
-    // FP64); the general-rates variant runs one row per thread.
+    // The fused kernel has a tile 64 wide and th rows high; the general-rates
+    // variant runs one row per thread.
     bool fused() const { return tb >= 2 && !general(); }
     int eff_bxl() const { return fused() ? 6 : bx_log2; }
-    int eff_vy() const { return fused() ? fused_th(prec, tb) / 4 : (general() ? 1 : vy); }
+    int eff_vy() const { return fused() ? th / 4 : (general() ? 1 : vy); }
     int tile_h() const { return (kBlock >> eff_bxl()) * eff_vy(); }
     int tiles_y() const { return (ny + tile_h() - 1) / tile_h(); }
     int nitems() const { return tiles_x() * tiles_y(); }

@@ -69,6 +69,7 @@ def load() -> ctypes.CDLL:
         "lbm_set_tile": (i, [vp, i, i, i]),
         "lbm_debug_stream_only": (i, [vp, ll]),
         "lbm_set_time_blocking": (i, [vp, i]),
+        "lbm_set_fused_kernel": (i, [vp, i, i]),
         "lbm_last_error": (ctypes.c_char_p, [vp]),
         "lbm_batch_slot_bytes": (sz, [i, i, i, i]),
         "lbm_batch_create": (i, [i, vp, sz, vp, ctypes.POINTER(vp)]),
@@ -224,6 +225,12 @@ class Solver:
 
     def set_time_blocking(self, steps_per_launch: int):
         self._check(self.lib.lbm_set_time_blocking(self.h, int(steps_per_launch)))
+
+    def set_fused_kernel(self, kind: str, segment_rows: int = 256):
+        """kind "tile" (LDS tile kernel) or "wavefront" (register wavefront with
+        segments of `segment_rows` rows); see lbm_set_fused_kernel."""
+        k = {"tile": 0, "wavefront": 1}[kind]
+        self._check(self.lib.lbm_set_fused_kernel(self.h, k, int(segment_rows)))
 
     def displacement(self, out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None):
         shp = (self.ny, self.nx)

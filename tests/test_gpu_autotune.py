@@ -19,7 +19,7 @@ def test_tune_solver_and_cache(tmp_path):
     s.set_body_force(dev(c.gx), dev(c.gy))
     cache = str(tmp_path / "tune.json")
     shp = autotune.tune_solver(s, "fp64", cache_path=cache)
-    assert shp in autotune.candidates(256, 0)
+    assert shp in autotune.candidates(256, 0, 256, wavefront=True)
     assert autotune.tune_solver(s, "fp64", cache_path=cache) == shp  # from the cache
     s.reset()
     s.step(50)

@@ -296,6 +296,49 @@ def test_time_blocking_identical_to_single_steps(prec, nx, ny, steps):
         assert rel_l2(res[2][0], fn) <= 1e-12
 
 
+@pytest.mark.parametrize("prec,nx,ny,steps,rows", [
+    ("fp64", 1, 1, 6, 256), ("fp64", 3, 5, 7, 1), ("fp64", 67, 33, 21, 4), ("fp64", 130, 9, 10, 16),
+    ("fp64", 257, 48, 12, 7), ("fp32", 2, 2, 5, 3), ("fp32", 65, 17, 9, 5), ("fp32", 200, 70, 12, 32),
+    ("fp16", 5, 3, 5, 2), ("fp16", 97, 31, 8, 9), ("fp64", 1024, 1024, 8, 256)])
+def test_wavefront_identical_to_single_steps(prec, nx, ny, steps, rows):
+    """The register-wavefront fused kernel (strips of 64 - 2k columns, segments of
+    `rows` rows, several strips and segments, ragged edges, lattices narrower
+    than a strip) gives populations bit-identical to single steps, with residual
+    checks interleaved; the FP64 result matches the oracle."""
+    say(f"wavefront {prec} {nx}x{ny} steps {steps} rows {rows}")
+    mat = P.Material.from_shear_poisson(0.9, 0.3)
+    f0, gx, gy = _rand_state(nx, ny, 5 + nx)
+    res = {}
+    for tb in (1, 2, 3, 4):
+        s = _solver(nx, ny, prec)
+        s.set_material(mat.lame_lambda, mat.lame_mu)
+        s.set_body_force(dev(gx), dev(gy))
+        s.set_populations(dev(f0))
+        s.set_time_blocking(tb)
+        s.set_fused_kernel("wavefront", rows)
+        s.step(steps)
+        a = host(s.populations())
+        n, r, st = s.solve_to_tol(0.0, 11, 5)
+        res[tb] = (a, host(s.populations()), n, r)
+    for tb in (2, 3, 4):
+        np.testing.assert_array_equal(res[tb][0], res[1][0])
+        np.testing.assert_array_equal(res[tb][1], res[1][1])
+        assert res[tb][2] == res[1][2] and res[tb][3] == pytest.approx(res[1][3], rel=1e-12)
+    if prec == "fp64" and nx * ny <= 20000:
+        fn = O.run(f0, gx, gy, omega(mat), steps)
+        assert rel_l2(res[3][0], fn) <= 1e-12
+
+
+def test_fused_kernel_argument_errors():
+    from paper_2208_14870_amd import lbm
+    s = _solver(16, 16, "fp32")
+    with pytest.raises(lbm.LbmError):
+        s.set_fused_kernel("wavefront", 0)
+    with pytest.raises(KeyError):
+        s.set_fused_kernel("other", 4)
+    s.set_fused_kernel("tile")
+
+
 # ---------------------------------------------------------------------------
 # reduced precision (error against the FP64 oracle stated as a number)
 # ---------------------------------------------------------------------------
