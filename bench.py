@@ -72,6 +72,10 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--large-only", default="",
+                    help="comma list of precisions: run only the 8192^2 leg (for profiling)")
+    ap.add_argument("--large-steps", type=int, default=10000)
+    ap.add_argument("--large-warm", type=int, default=200)
     return ap.parse_args()
 
 
@@ -125,7 +129,7 @@ def run_workload(solvers, nchunks, chunk):
             "last": last[-len(solvers):]}
 
 
-def large_lattice(steps=10000, warm=200):
+def large_lattice(steps=10000, warm=200, precs=("fp64", "fp32", "fp16")):
     """8192 x 8192 random 16-mode load (seed 3): throughput per storage
     precision over `steps` timed steps after `warm` untimed ones, and the
     FP32 / scaled-FP16 displacement error against the FP64 run (the FP64 GPU
@@ -140,7 +144,7 @@ def large_lattice(steps=10000, warm=200):
     del c
     sites = 8192 * 8192
     out, u = {}, {}
-    for prec in ("fp64", "fp32", "fp16"):
+    for prec in precs:
         s = lbm.Solver(8192, 8192, prec)
         s.set_material(mat.lame_lambda, mat.lame_mu)
         s.set_body_force(gx, gy)
@@ -152,7 +156,7 @@ def large_lattice(steps=10000, warm=200):
         s.step(steps)
         e1.record()
         torch.cuda.synchronize()
-        us = 1e3 * e0.elapsed_time(e1) / steps  # per step (two steps per fused launch)
+        us = 1e3 * e0.elapsed_time(e1) / steps  # per step (four steps per fused launch)
         ux, uy = s.displacement()
         u[prec] = (ux[::32, ::32].clone(), uy[::32, ::32].clone())
         del ux, uy
@@ -160,10 +164,12 @@ def large_lattice(steps=10000, warm=200):
         del s
         gbs = BYTES_PER_SITE[prec] * sites / (us * 1e-6) / 1e9
         out[prec] = {"mlups": round(sites / us, 1), "us_per_step": round(us, 2),
-                     "gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
-    rx, ry = u["fp64"]
-    den = float(torch.sum(rx ** 2) + torch.sum(ry ** 2))
-    for prec in ("fp32", "fp16"):
+                     "gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4),
+                     "fused_kernel": ("register wavefront, 256-row segments" if prec == "fp64"
+                                      else "LDS tile 64 x %d" % (16 if prec == "fp32" else 12))}
+    rx, ry = u.get("fp64", (None, None))
+    den = float(torch.sum(rx ** 2) + torch.sum(ry ** 2)) if rx is not None else 0.0
+    for prec in (p for p in ("fp32", "fp16") if p in u and rx is not None):
         ax, ay = u[prec]
         num = float(torch.sum((ax - rx) ** 2) + torch.sum((ay - ry) ** 2))
         out[prec]["rel_l2_vs_fp64_downsample_256"] = math.sqrt(num / den)
@@ -278,6 +284,11 @@ def main():
     lbm.load()
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
+    if args.large_only:
+        precs = tuple(args.large_only.split(","))
+        print(json.dumps({"large_8192": large_lattice(args.large_steps, args.large_warm, precs)}),
+              flush=True)
+        return
     cases = build_cases(args.cases)
     nsites = cases[0].nx * cases[0].ny
 
@@ -322,8 +333,9 @@ def main():
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(r32["kernel_gbs"] / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic(),
-                     "kernel": "k_stepN<float, 16, 4>: four fused steps per launch, 72 B per "
-                               "site-update algorithmic, 4 x 1024^2 site-updates per launch",
+                     "kernel": "k_stepN<float, 8, 4> (LDS tile 64 x 8 + ring 3): four fused "
+                               "steps per launch, 72 B per site-update algorithmic, 4 x 1024^2 "
+                               "site-updates per launch",
                      "avg_launch_us": round(r32["plain_kernel_avg_us"], 3),
                      "steps_per_launch": STEPS_PER_LAUNCH,
                      "note": "the fused kernel moves the populations through HBM once per four "
