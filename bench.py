@@ -57,6 +57,16 @@ def measured_traffic():
     return rec["traffic_bytes_per_launch"]
 
 
+def calib_copy():
+    """One device copy of 1 GiB: the calibration kernel for the HBM byte counters."""
+    import torch
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
 def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
@@ -285,6 +295,8 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     if args.large_only:
+        if args.calib_copy:
+            calib_copy()
         precs = tuple(args.large_only.split(","))
         print(json.dumps({"large_8192": large_lattice(args.large_steps, args.large_warm, precs)}),
               flush=True)
@@ -350,11 +362,7 @@ def main():
         # measured HBM bytes per launch over the same launch duration
         out["roofline"]["measured_hbm_gbs"] = round(tr / (r32["plain_kernel_avg_us"] * 1e-6) / 1e9, 1)
     if args.calib_copy:
-        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        calib_copy()
     if not args.no_extras:
         log("comparison: 1024x1024 FP64")
         r64, u64 = measure("fp64")
