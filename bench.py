@@ -175,8 +175,9 @@ def large_lattice(steps=10000, warm=200, precs=("fp64", "fp32", "fp16")):
         gbs = BYTES_PER_SITE[prec] * sites / (us * 1e-6) / 1e9
         out[prec] = {"mlups": round(sites / us, 1), "us_per_step": round(us, 2),
                      "gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4),
-                     "fused_kernel": ("register wavefront, 256-row segments" if prec == "fp64"
-                                      else "LDS tile 64 x %d" % (16 if prec == "fp32" else 12))}
+                     "fused_kernel": {"fp64": "register wavefront, 1 column per lane, 256-row segments",
+                                      "fp32": "register wavefront, 2 columns per lane, 64-row segments",
+                                      "fp16": "LDS tile 64 x 12"}[prec]}
     rx, ry = u.get("fp64", (None, None))
     den = float(torch.sum(rx ** 2) + torch.sum(ry ** 2)) if rx is not None else 0.0
     for prec in (p for p in ("fp32", "fp16") if p in u and rx is not None):

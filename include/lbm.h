@@ -190,8 +190,9 @@ enum lbm_fused_kernel {
      * lattices of up to 2^21 sites and in FP64, 12 in FP16) plus a ring of
      * k-1 sites in LDS, then narrower rings down to the tile. */
     LBM_FUSED_TILE = 0,
-    /* Register wavefront: a wave owns a strip of 64 - 2k columns plus a ring
-     * of k columns per side and marches along y through segments of
+    /* Register wavefront: a wave owns a strip of columns (one per lane, or
+     * two per lane for FP32/FP16 on even widths) with a ring of k columns
+     * per side (4 with two per lane) and marches along y through segments of
      * `segment_rows` rows, keeping three rows of every intermediate step in
      * registers (x neighbours through cross-lane moves); no LDS. */
     LBM_FUSED_WAVEFRONT = 1
@@ -199,9 +200,11 @@ enum lbm_fused_kernel {
 
 /* Select the fused kernel for steps_per_launch >= 2.  segment_rows (1..2^20)
  * is used by LBM_FUSED_WAVEFRONT only: each strip is split into segments of
- * that many rows, each recomputing 2k halo rows.  Default: the wavefront with
- * 256-row segments for FP64 lattices of at least 2^22 sites (also after a
- * polish switch), the tile kernel otherwise.  Errors: LBM_E_ARG. */
+ * that many rows, each recomputing 2k halo rows.  Default: the wavefront for
+ * FP64 lattices of at least 2^22 sites (also after a polish switch) and for
+ * even-width FP32 lattices of at least 2^25 sites, with the tallest segment of
+ * 256, 128, 64 or 32 rows that still gives 18 waves per compute unit; the
+ * tile kernel otherwise.  Errors: LBM_E_ARG. */
 int lbm_set_fused_kernel(lbm_solver *s, int kind, int segment_rows);
 
 /* Diagnostic: nsteps of streaming alone (no collision), for bit-exact checks

@@ -258,7 +258,7 @@ int lbm_create(int nx, int ny, int precision, int with_polish, void* workspace,
     default_tile(precision, nx, ny, L.bx_log2, L.vy);
     L.tb = default_time_blocking(precision, nx, ny);
     L.th = fused_th(precision, (long long)nx * ny);
-    L.wave_hs = default_wave_rows(precision, nx, ny);
+    L.wave_hs = default_wave_rows(precision, nx, ny, s->cus);
     char* base = reinterpret_cast<char*>(workspace);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -454,7 +454,7 @@ int promote_solver(lbm_solver* s) {
     default_tile(LBM_FP64, L.nx, L.ny, L.bx_log2, L.vy);
     L.tb = default_time_blocking(LBM_FP64, L.nx, L.ny);
     L.th = fused_th(LBM_FP64, L.N);
-    L.wave_hs = default_wave_rows(LBM_FP64, L.nx, L.ny);
+    L.wave_hs = default_wave_rows(LBM_FP64, L.nx, L.ny, s->cus);
     // sync_desc folds phase into cur: phase is 0 so cur stays 0
     int rc = s->sync_desc();
     if (rc != LBM_OK) return rc;

@@ -533,16 +533,19 @@ static __global__ __launch_bounds__(kBlock) void k_stepN(StepLaunch L) {
 // ---------------------------------------------------------------------------
 // NS fused steps per launch, register wavefront
 // ---------------------------------------------------------------------------
-// One wave owns a strip of 64 lanes = W = 64 - 2 NS output columns plus NS
-// ring columns per side, and marches up a segment of rows.  At row t it loads
-// the stored field's row t (level 0) and advances level k = 1..NS at row t - k
-// from level k-1's rows t-k-1, t-k, t-k+1, which it keeps in registers: the
-// y neighbours are earlier rows of the same lane, the x neighbours come from
-// lanes l -+ 1 through a whole-wave DPP shift.  Level NS is stored.  Each
-// level loses one valid lane per side, so after NS levels lanes NS..63-NS hold
-// the output.  No LDS and no barrier; every intermediate level is rounded to
-// the storage type exactly as a store would round it, so the result equals NS
-// single steps bit for bit.
+// One wave owns a strip of 64 V columns (V adjacent columns per lane): W
+// output columns plus R ring columns per side, and marches up a segment of
+// rows.  At row t it loads the stored field's row t (level 0) and advances
+// level k = 1..NS at row t - k from level k-1's rows t-k-1, t-k, t-k+1, which
+// it keeps in registers: the y neighbours are earlier rows of the same lane,
+// the x neighbours are the lane's other column or, across lanes, come through
+// a whole-wave DPP shift.  Level NS is stored.  Each level loses one valid
+// column per side, so after NS <= R levels the W middle columns hold the
+// output.  No LDS and no barrier; every intermediate level is rounded to the
+// storage type exactly as a store would round it, so the result equals NS
+// single steps bit for bit.  V = 2 (FP32, FP16) needs an even nx, so that a
+// lane's column pair stays adjacent across the periodic wrap; its ring is 4
+// columns for every NS so that pairs stay aligned.
 __device__ __forceinline__ float lane_from_left(float v) {  // lane l <- lane l-1
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
 }
@@ -568,16 +571,56 @@ __device__ __forceinline__ typename Store<S>::C as_stored(typename Store<S>::C v
 template <>
 __device__ __forceinline__ float as_stored<__half>(float v) { return __half2float(__float2half_rn(v)); }
 
+// V consecutive storage elements as arithmetic values (one vector access).
+template <typename S, int V> struct VecIO;
+template <typename S> struct VecIO<S, 1> {
+    using C = typename Store<S>::C;
+    __device__ static __forceinline__ void ld(const S* p, C o[1]) { o[0] = Store<S>::ld(p); }
+    __device__ static __forceinline__ void st(S* p, const C v[1]) { Store<S>::st(p, v[0]); }
+};
+typedef float wf2 __attribute__((ext_vector_type(2)));
+template <> struct VecIO<float, 2> {
+    __device__ static __forceinline__ void ld(const float* p, float o[2]) {
+        const wf2 v = __builtin_nontemporal_load(glob(reinterpret_cast<const wf2*>(p)));
+        o[0] = v.x;
+        o[1] = v.y;
+    }
+    __device__ static __forceinline__ void st(float* p, const float v[2]) {
+        wf2 w;
+        w.x = v[0];
+        w.y = v[1];
+        __builtin_nontemporal_store(w, glob(reinterpret_cast<wf2*>(p)));
+    }
+};
+template <> struct VecIO<__half, 2> {
+    __device__ static __forceinline__ void ld(const __half* p, float o[2]) {
+        const unsigned u = __builtin_nontemporal_load(glob(reinterpret_cast<const unsigned*>(p)));
+        o[0] = __half2float(__ushort_as_half((unsigned short)(u & 0xffffu)));
+        o[1] = __half2float(__ushort_as_half((unsigned short)(u >> 16)));
+    }
+    __device__ static __forceinline__ void st(__half* p, const float v[2]) {
+        const unsigned u = (unsigned)__half_as_ushort(__float2half_rn(v[0])) |
+                           ((unsigned)__half_as_ushort(__float2half_rn(v[1])) << 16);
+        __builtin_nontemporal_store(u, glob(reinterpret_cast<unsigned*>(p)));
+    }
+};
+
+template <int NS, int V>
+__host__ __device__ constexpr int wave_ring() { return V == 1 ? NS : 4; }
+template <int NS, int V>
+__host__ __device__ constexpr int wave_width() { return kWave * V - 2 * wave_ring<NS, V>(); }
+
 struct WaveLaunch {
     const SlotDesc* slots;
     int flip;
     int strips, segs, hs;  // strips of W output columns, segments of hs rows
 };
 
-template <typename S, int NS>
+template <typename S, int NS, int V>
 static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
     using C = typename Store<S>::C;
-    constexpr int W = kWave - 2 * NS;
+    constexpr int R = wave_ring<NS, V>();
+    constexpr int W = wave_width<NS, V>();
     constexpr int PF = 3;  // rows loaded ahead
     // wave index as a scalar: the row loop and the row bases stay scalar
     const int wid = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlock / kWave) +
@@ -595,36 +638,44 @@ static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
     k.load(d);
     const int sx = wid % L.strips, sy = wid / L.strips;
     const int xs = sx * W, ya = sy * L.hs, yb = min(ya + L.hs, ny);
-    const int x = xs - NS + lane;
+    const int x = xs - R + V * lane;  // first column of this lane
     const int xw = wrap_coord(x, nx);
-    const bool out_lane = lane >= NS && lane < NS + W && x < nx;
+    const bool out_lane = lane >= R / V && lane < (R + W) / V && x < nx;
     // loads of row t: scalar row base + per-lane byte offset of the column
     const unsigned xs_b = (unsigned)xw * (unsigned)sizeof(S), xg_b = (unsigned)xw * (unsigned)sizeof(C);
-    auto load_row = [&](int t, C* a, C* gg) {
+    auto load_row = [&](int t, C (*a)[V], C (*gg)[V]) {
         const long long r = (long long)wrap_coord(t, ny) * nx;
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-            a[q] = Store<S>::ld(reinterpret_cast<const S*>(
-                reinterpret_cast<const char*>(src + (q * plane + r)) + xs_b));
-        gg[0] = *glob(reinterpret_cast<const C*>(reinterpret_cast<const char*>(g + r) + xg_b));
-        gg[1] = *glob(reinterpret_cast<const C*>(reinterpret_cast<const char*>(g + (plane + r)) + xg_b));
+            VecIO<S, V>::ld(reinterpret_cast<const S*>(
+                                reinterpret_cast<const char*>(src + (q * plane + r)) + xs_b),
+                            a[q]);
+        VecIO<C, V>::ld(reinterpret_cast<const C*>(reinterpret_cast<const char*>(g + r) + xg_b), gg[0]);
+        VecIO<C, V>::ld(reinterpret_cast<const C*>(reinterpret_cast<const char*>(g + (plane + r)) + xg_b),
+                        gg[1]);
     };
-    C A0[6][8];       // level 0 rows by iteration mod 6 (three back, three ahead)
-    C Gp[6][2];       // force rows, same slots
-    C A[NS][3][8];    // levels 1..NS-1 (index lv-1 unused for lv = 0), rows mod 3
-    C G[NS + 1][2];   // force of rows t, t-1, ..., t-NS
+    C A0[6][8][V];      // level 0 rows by iteration mod 6 (three back, three ahead)
+    C Gp[6][2][V];      // force rows, same slots
+    C A[NS][3][8][V];   // levels 1..NS-1 (index 0 unused), rows mod 3
+    C G[NS + 1][2][V];  // force of rows t, t-1, ..., t-NS
 #pragma unroll
-    for (int j = 0; j <= NS; ++j) G[j][0] = G[j][1] = C(0);
+    for (int j = 0; j <= NS; ++j)
+#pragma unroll
+        for (int c = 0; c < V; ++c) G[j][0][c] = G[j][1][c] = C(0);
 #pragma unroll
     for (int r = 0; r < 6; ++r)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) A0[r][q] = C(0);
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int c = 0; c < V; ++c) A0[r][q][c] = C(0);
 #pragma unroll
     for (int lv = 0; lv < NS; ++lv)
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
-            for (int q = 0; q < 8; ++q) A[lv][r][q] = C(0);
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int c = 0; c < V; ++c) A[lv][r][q][c] = C(0);
     const int t_first = ya - NS;
 #pragma unroll
     for (int u = 0; u < PF; ++u) load_row(t_first + u, A0[u], Gp[u]);
@@ -634,38 +685,63 @@ static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
             const int t = t0 + u;
             load_row(t + PF, A0[(u + PF) % 6], Gp[(u + PF) % 6]);
 #pragma unroll
-            for (int j = NS; j > 0; --j) {
-                G[j][0] = G[j - 1][0];
-                G[j][1] = G[j - 1][1];
+            for (int j = NS; j > 0; --j)
+#pragma unroll
+                for (int c = 0; c < V; ++c) {
+                    G[j][0][c] = G[j - 1][0][c];
+                    G[j][1][c] = G[j - 1][1][c];
+                }
+#pragma unroll
+            for (int c = 0; c < V; ++c) {
+                G[0][0][c] = Gp[u][0][c] * k.gscale;
+                G[0][1][c] = Gp[u][1][c] * k.gscale;
             }
-            G[0][0] = Gp[u][0] * k.gscale;
-            G[0][1] = Gp[u][1] * k.gscale;
 #pragma unroll
             for (int lv = 1; lv <= NS; ++lv) {
                 // level lv-1 rows t-lv+1 (this iteration), t-lv, t-lv-1
-                const C* R0 = lv == 1 ? A0[u] : A[lv - 1][u % 3];
-                const C* R1 = lv == 1 ? A0[(u + 5) % 6] : A[lv - 1][(u + 2) % 3];
-                const C* R2 = lv == 1 ? A0[(u + 4) % 6] : A[lv - 1][(u + 1) % 3];
-                C f[8];
-                f[0] = lane_from_left(R1[0]);   // c1 = ( 1, 0) from (x-1, y)
-                f[1] = R2[1];                   // c2 = ( 0, 1) from (x, y-1)
-                f[2] = lane_from_right(R1[2]);  // c3 = (-1, 0) from (x+1, y)
-                f[3] = R0[3];                   // c4 = ( 0,-1) from (x, y+1)
-                f[4] = lane_from_left(R2[4]);   // c5 = ( 1, 1) from (x-1, y-1)
-                f[5] = lane_from_right(R2[5]);  // c6 = (-1, 1) from (x+1, y-1)
-                f[6] = lane_from_right(R0[6]);  // c7 = (-1,-1) from (x+1, y+1)
-                f[7] = lane_from_left(R0[7]);   // c8 = ( 1,-1) from (x-1, y+1)
-                C ux, uy;
-                collide<C, false>(f, G[lv][0], G[lv][1], k, ux, uy);
+                const C(*R0)[V] = lv == 1 ? A0[u] : A[lv - 1][u % 3];
+                const C(*R1)[V] = lv == 1 ? A0[(u + 5) % 6] : A[lv - 1][(u + 2) % 3];
+                const C(*R2)[V] = lv == 1 ? A0[(u + 4) % 6] : A[lv - 1][(u + 1) % 3];
+                // value of population q at column c - 1 / c + 1 of a row
+                auto left = [&](const C(*row)[V], int q, int c) {
+                    return c > 0 ? row[q][c - 1] : lane_from_left(row[q][V - 1]);
+                };
+                auto right = [&](const C(*row)[V], int q, int c) {
+                    return c < V - 1 ? row[q][c + 1] : lane_from_right(row[q][0]);
+                };
+                C f[V][8];
+#pragma unroll
+                for (int c = 0; c < V; ++c) {
+                    f[c][0] = left(R1, 0, c);   // c1 = ( 1, 0) from (x-1, y)
+                    f[c][1] = R2[1][c];         // c2 = ( 0, 1) from (x, y-1)
+                    f[c][2] = right(R1, 2, c);  // c3 = (-1, 0) from (x+1, y)
+                    f[c][3] = R0[3][c];         // c4 = ( 0,-1) from (x, y+1)
+                    f[c][4] = left(R2, 4, c);   // c5 = ( 1, 1) from (x-1, y-1)
+                    f[c][5] = right(R2, 5, c);  // c6 = (-1, 1) from (x+1, y-1)
+                    f[c][6] = right(R0, 6, c);  // c7 = (-1,-1) from (x+1, y+1)
+                    f[c][7] = left(R0, 7, c);   // c8 = ( 1,-1) from (x-1, y+1)
+                }
+#pragma unroll
+                for (int c = 0; c < V; ++c) {
+                    C ux, uy;
+                    collide<C, false>(f[c], G[lv][0][c], G[lv][1][c], k, ux, uy);
+                }
                 if (lv < NS) {
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) A[lv][u % 3][q] = as_stored<S>(f[q]);
+                    for (int q = 0; q < 8; ++q)
+#pragma unroll
+                        for (int c = 0; c < V; ++c) A[lv][u % 3][q][c] = as_stored<S>(f[c][q]);
                 } else {
                     const int y = t - NS;
                     if (out_lane && y >= ya && y < yb) {
                         const long long o = (long long)y * nx + x;
 #pragma unroll
-                        for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * plane + o, f[q]);
+                        for (int q = 0; q < 8; ++q) {
+                            C v[V];
+#pragma unroll
+                            for (int c = 0; c < V; ++c) v[c] = f[c][q];
+                            VecIO<S, V>::st(dst + q * plane + o, v);
+                        }
                     }
                 }
             }

@@ -122,36 +122,57 @@ inline hipError_t launch_stepN(int prec, int ns, int th, unsigned grid, hipStrea
 }
 
 // Register-wavefront launch of `ns` plain steps on slot 0 (single lattice),
-// segments of hs rows.
-template <typename S>
+// segments of hs rows; two columns per lane for FP32/FP16 on even-width lattices.
+template <typename S, int V>
 inline void launch_wave_t(int ns, unsigned grid, hipStream_t st, const WaveLaunch& W) {
-    if (ns == 2) hipLaunchKernelGGL((k_wave<S, 2>), dim3(grid), dim3(kBlock), 0, st, W);
-    else if (ns == 3) hipLaunchKernelGGL((k_wave<S, 3>), dim3(grid), dim3(kBlock), 0, st, W);
-    else hipLaunchKernelGGL((k_wave<S, 4>), dim3(grid), dim3(kBlock), 0, st, W);
+    if (ns == 2) hipLaunchKernelGGL((k_wave<S, 2, V>), dim3(grid), dim3(kBlock), 0, st, W);
+    else if (ns == 3) hipLaunchKernelGGL((k_wave<S, 3, V>), dim3(grid), dim3(kBlock), 0, st, W);
+    else hipLaunchKernelGGL((k_wave<S, 4, V>), dim3(grid), dim3(kBlock), 0, st, W);
+}
+
+inline int wave_cols_per_lane(int prec, int nx) { return (prec != LBM_FP64 && nx % 2 == 0) ? 2 : 1; }
+
+inline int wave_width_of(int ns, int v) {
+    if (v == 2) return wave_width<4, 2>();
+    return ns == 2 ? wave_width<2, 1>() : ns == 3 ? wave_width<3, 1>() : wave_width<4, 1>();
 }
 
 inline hipError_t launch_wave(int prec, int ns, int nx, int ny, int hs, const SlotDesc* slots,
                               int flip, hipStream_t st) {
+    const int v = wave_cols_per_lane(prec, nx);
+    const int w = wave_width_of(ns, v);
     WaveLaunch W;
     W.slots = slots;
     W.flip = flip;
-    W.strips = (nx + (kWave - 2 * ns) - 1) / (kWave - 2 * ns);
+    W.strips = (nx + w - 1) / w;
     W.hs = hs;
     W.segs = (ny + hs - 1) / hs;
     const long long waves = (long long)W.strips * W.segs;
     const unsigned grid = (unsigned)((waves + kBlock / kWave - 1) / (kBlock / kWave));
-    if (prec == LBM_FP64) launch_wave_t<double>(ns, grid, st, W);
-    else if (prec == LBM_FP32) launch_wave_t<float>(ns, grid, st, W);
-    else launch_wave_t<__half>(ns, grid, st, W);
+    if (prec == LBM_FP64) launch_wave_t<double, 1>(ns, grid, st, W);
+    else if (prec == LBM_FP32 && v == 2) launch_wave_t<float, 2>(ns, grid, st, W);
+    else if (prec == LBM_FP32) launch_wave_t<float, 1>(ns, grid, st, W);
+    else if (v == 2) launch_wave_t<__half, 2>(ns, grid, st, W);
+    else launch_wave_t<__half, 1>(ns, grid, st, W);
     return hipGetLastError();
 }
 
-// Default fused kernel: the register wavefront (segments of 256 rows) for
-// FP64 lattices of at least 2^22 sites, where it beats the LDS tile kernel
-// on MI355X; the tile kernel otherwise.  Returns the segment height, 0 for
-// the tile kernel.
-inline int default_wave_rows(int prec, int nx, int ny) {
-    return (prec == LBM_FP64 && (long long)nx * ny >= (1LL << 22)) ? 256 : 0;
+// Default fused kernel (measured on MI355X): the register wavefront for FP64
+// lattices of at least 2^22 sites and for even-width FP32 lattices of at least
+// 2^25 sites, the LDS tile kernel otherwise (smaller lattices, FP16).  The
+// segment height is the tallest of 256, 128, 64, 32 rows that still gives
+// 18 waves per compute unit (fewer leave SIMDs idle; shorter segments
+// recompute more halo rows).  Returns the segment height, 0 for the tile kernel.
+inline int default_wave_rows(int prec, int nx, int ny, int cus) {
+    const long long n = (long long)nx * ny;
+    const bool use = (prec == LBM_FP64 && n >= (1LL << 22)) ||
+                     (prec == LBM_FP32 && n >= (1LL << 25) && nx % 2 == 0);
+    if (!use) return 0;
+    const long long strips = (nx + wave_width_of(4, wave_cols_per_lane(prec, nx)) - 1) /
+                             wave_width_of(4, wave_cols_per_lane(prec, nx));
+    for (int hs = 256; hs > 32; hs /= 2)
+        if (strips * ((ny + hs - 1) / hs) >= 18LL * cus) return hs;
+    return 32;
 }
 
 // Default steps per launch (measured on MI355X: four is fastest or tied for

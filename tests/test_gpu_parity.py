@@ -299,12 +299,15 @@ def test_time_blocking_identical_to_single_steps(prec, nx, ny, steps):
 @pytest.mark.parametrize("prec,nx,ny,steps,rows", [
     ("fp64", 1, 1, 6, 256), ("fp64", 3, 5, 7, 1), ("fp64", 67, 33, 21, 4), ("fp64", 130, 9, 10, 16),
     ("fp64", 257, 48, 12, 7), ("fp32", 2, 2, 5, 3), ("fp32", 65, 17, 9, 5), ("fp32", 200, 70, 12, 32),
-    ("fp16", 5, 3, 5, 2), ("fp16", 97, 31, 8, 9), ("fp64", 1024, 1024, 8, 256)])
+    ("fp16", 5, 3, 5, 2), ("fp16", 97, 31, 8, 9), ("fp64", 1024, 1024, 8, 256),
+    ("fp32", 4, 3, 6, 1), ("fp32", 256, 48, 10, 16), ("fp16", 2, 2, 5, 3), ("fp16", 130, 20, 8, 6),
+    ("fp32", 1024, 64, 8, 32)])
 def test_wavefront_identical_to_single_steps(prec, nx, ny, steps, rows):
-    """The register-wavefront fused kernel (strips of 64 - 2k columns, segments of
-    `rows` rows, several strips and segments, ragged edges, lattices narrower
-    than a strip) gives populations bit-identical to single steps, with residual
-    checks interleaved; the FP64 result matches the oracle."""
+    """The register-wavefront fused kernel (one column per lane: strips of 64 - 2k
+    columns; two columns per lane for FP32/FP16 on even widths: strips of 120;
+    segments of `rows` rows, several strips and segments, ragged edges, lattices
+    narrower than a strip) gives populations bit-identical to single steps, with
+    residual checks interleaved; the FP64 result matches the oracle."""
     say(f"wavefront {prec} {nx}x{ny} steps {steps} rows {rows}")
     mat = P.Material.from_shear_poisson(0.9, 0.3)
     f0, gx, gy = _rand_state(nx, ny, 5 + nx)
