@@ -189,6 +189,43 @@ def large_lattice(steps=10000, warm=200, precs=("fp64", "fp32", "fp16")):
     return out
 
 
+def inplace_run(n=8192, steps=400, warm=8):
+    """In-place streaming (one population buffer) against the two-buffer solver
+    at one step per launch, 8192 x 8192 random load: GLUPS and workspace bytes."""
+    import torch
+    from paper_2208_14870_amd import lbm, problem as P
+    c = P.single_8192() if n == 8192 else P.single_1024(0.3, 1, 1, n=n)
+    gx = torch.from_numpy(c.gx).cuda()
+    gy = torch.from_numpy(c.gy).cuda()
+    out = {}
+    for prec in ("fp32", "fp64"):
+        row = {}
+        for inplace in (False, True):
+            s = lbm.Solver(n, n, prec, inplace=inplace)
+            s.set_time_blocking(1)
+            s.set_material(c.material.lame_lambda, c.material.lame_mu)
+            s.set_body_force(gx, gy)
+            s.step(warm)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.step(steps)
+            e1.record()
+            torch.cuda.synchronize()
+            us = 1e3 * e0.elapsed_time(e1) / steps
+            gbs = BYTES_PER_SITE[prec] * n * n / (us * 1e-6) / 1e9
+            row["inplace" if inplace else "two_buffers"] = {
+                "mlups": round(n * n / us, 1), "gbs": round(gbs, 1),
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "workspace_bytes": s.workspace_bytes}
+            s.close()
+            del s
+        out[prec] = row
+    out["lattice"] = [n, n]
+    out["steps"] = steps
+    return out
+
+
 def batch_run(prec: str, nlat: int = 512, steps: int = 2000, chunk: int = 100):
     """Batched workload: `nlat` lattices (seed 4, sides {64..512}, nu ~ U[0.05, 0.48]),
     one launch per step over the tile work list, graph-replayed chunks with a
@@ -378,6 +415,8 @@ def main():
         out["fp32_rel_l2_vs_fp64"] = math.sqrt(num / den)
         log("8192x8192 random load: FP64 / FP32 / FP16, 200 + 10000 steps")
         out["large_8192"] = large_lattice()
+        log("in-place streaming vs two buffers, 8192x8192, one step per launch")
+        out["inplace_8192"] = inplace_run()
         log("batched: 512 lattices FP32 / FP64, 2000 steps")
         out["batch"] = {"fp32": batch_run("fp32"), "fp64": batch_run("fp64")}
         log("batched solves to r <= 1e-6 (FP32, FP32 + FP64 polish, FP64)")

@@ -86,6 +86,25 @@ size_t lbm_workspace_bytes(int nx, int ny, int precision, int with_polish);
 int lbm_create(int nx, int ny, int precision, int with_polish, void *workspace,
                size_t workspace_bytes, void *stream, lbm_solver **out);
 
+/* In-place streaming (one population buffer instead of two: the "AA" access
+ * pattern of optimised lattice Boltzmann codes).  An even step reads each
+ * site's own populations and writes the post-collision values into the
+ * opposite directions' slots of the same site; an odd step reads those slots
+ * at the neighbours and pushes the new post-collision values to the
+ * neighbours' own slots.  Every step reads and writes each population once
+ * and every memory location is touched by one site only, so one buffer
+ * suffices and the bytes per site-update are those of lbm_step; the
+ * population footprint halves (about twice the lattice per GPU).  Results are
+ * identical to the two-buffer solver (bit for bit in every precision).  Same
+ * handle and entry points, with these differences: one step per launch
+ * (lbm_set_time_blocking accepts only 1, lbm_set_fused_kernel returns
+ * LBM_E_STATE), no polish phase, and lbm_solve_to_tol evaluates its residual
+ * with a launch that does not step (the state cannot step back in place).
+ * Workspace: lbm_workspace_bytes_inplace (0 for invalid sizes). */
+size_t lbm_workspace_bytes_inplace(int nx, int ny, int precision);
+int lbm_create_inplace(int nx, int ny, int precision, void *workspace, size_t workspace_bytes,
+                       void *stream, lbm_solver **out);
+
 /* Release the handle (never frees the workspace).  Waits for the stream. */
 int lbm_destroy(lbm_solver *s);
 

@@ -265,15 +265,15 @@ struct lbm_batch {
                 each([&](int p, unsigned g) { return launch_stepN(p, tb, fused_th(p, 1LL << 22), g, st, args(p, (int)(ph & 1))); });
         for (; i < np && e == hipSuccess; ++i, ++ph)
             each([&](int p, unsigned g) {
-                return launch_step(p, kPlain, false, eff_vy(p), g, st, args(p, (int)(ph & 1)));
+                return launch_step(p, kPlain, false, eff_vy(p), kLayPull, g, st, args(p, (int)(ph & 1)));
             });
         if (check && e == hipSuccess) {
             each([&](int p, unsigned g) {
-                return launch_step(p, kWriteU, false, eff_vy(p), g, st, args(p, (int)(ph & 1)));
+                return launch_step(p, kWriteU, false, eff_vy(p), kLayPull, g, st, args(p, (int)(ph & 1)));
             });
             ++ph;
             each([&](int p, unsigned g) {
-                return launch_step(p, kCheck, false, eff_vy(p), g, st, args(p, (int)(ph & 1)));
+                return launch_step(p, kCheck, false, eff_vy(p), kLayPull, g, st, args(p, (int)(ph & 1)));
             });
             ++ph;
             if (e == hipSuccess) {
@@ -600,7 +600,7 @@ int lbm_batch_get_displacement(lbm_batch* b, int slot, double* ux, double* uy) {
     if (slot < 0 || slot >= b->max_slots || !b->slots[slot].active || !ux || !uy)
         return b->fail(LBM_E_ARG, "batch_get_displacement: no such slot or NULL output");
     const BSlot& s = b->slots[slot];
-    hipError_t e = extract_u(s.L.prec, s.L.desc(), b->sel(s), ux, uy, b->stream);
+    hipError_t e = extract_u(s.L.prec, s.L.desc(), b->sel(s), kLayPull, ux, uy, b->stream);
     if (e != hipSuccess) return b->hip_fail(e, "batch_get_displacement");
     return LBM_OK;
 }

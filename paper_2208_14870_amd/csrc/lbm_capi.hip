@@ -108,7 +108,8 @@ struct lbm_solver {
     }
 
     hipError_t enqueue_one(int mode, hipStream_t st, long long& ph) {
-        hipError_t e = launch_step(L.prec, mode, L.general(), L.eff_vy(), grid, st,
+        hipError_t e = launch_step(L.prec, mode, L.general(), L.eff_vy(),
+                                   L.layout(L.cur ^ (int)(ph & 1)), grid, st,
                                    launch_args((int)(ph & 1)));
         ++ph;
         return e;
@@ -145,15 +146,22 @@ struct lbm_solver {
         for (; i < nplain && e == hipSuccess; ++i) e = enqueue_one(kPlain, st, ph);
         if (e == hipSuccess && writeu) e = enqueue_one(kWriteU, st, ph);
         if (e == hipSuccess && check) {
-            e = enqueue_one(kCheck, st, ph);
+            if (L.inplace) {
+                // u(n) of the current state without a step (no flip)
+                e = launch_check_state(L.prec, L.eff_vy(), L.layout(L.cur ^ (int)(ph & 1)), grid,
+                                       st, launch_args((int)(ph & 1)));
+            } else {
+                e = enqueue_one(kCheck, st, ph);
+            }
             if (e == hipSuccess) e = enqueue_finalize(st);
         }
         return e;
     }
 
+    // buffer flips (launch-parity increments) of enqueue_seq
     long long launches(long long nplain, bool writeu, bool check) const {
         const long long p = L.fused() ? nplain / L.tb + nplain % L.tb : nplain;
-        return p + (writeu ? 1 : 0) + (check ? 1 : 0);
+        return p + (writeu ? 1 : 0) + (check && !L.inplace ? 1 : 0);
     }
 
     // Enqueue a chunk; long runs are replayed from captured graphs.
@@ -177,7 +185,8 @@ struct lbm_solver {
         const int flip0 = (int)(phase & 1);
         const int kind = (writeu ? 1 : 0) | (check ? 2 : 0) | (L.fused() ? 4 * L.tb : 0) |
                          (L.fused() ? (L.th << 5) | (L.wave_hs << 10) : 0);
-        auto key = std::make_tuple(nplain, kind, flip0, L.prec, L.eff_vy(), L.general() ? 1 : 0, grid);
+        auto key = std::make_tuple(nplain, kind, flip0 ^ (L.cur << 1), L.prec, L.eff_vy(),
+                                   (L.general() ? 1 : 0) | (L.inplace ? 2 : 0), grid);
         auto it = graphs.find(key);
         hipError_t e;
         if (it == graphs.end()) {
@@ -207,18 +216,27 @@ struct lbm_solver {
 
 extern "C" {
 
-size_t lbm_workspace_bytes(int nx, int ny, int precision, int with_polish) {
+static size_t workspace_bytes(int nx, int ny, int precision, bool polish, bool inplace) {
     if (nx < 1 || ny < 1 || !valid_prec(precision)) return 0;
     const long long N = (long long)nx * ny;
     const long long mi = max_items(nx, ny);
     size_t b = al(sizeof(SlotDesc)) + 4 * al(sizeof(int)) + al(4 * 8) + al(mi * sizeof(Item)) +
                al(mi * 3 * 8) + al((kErrBlocks * 8 + 8) * 8);
-    b += lattice_bytes(N, precision, with_polish != 0);
+    b += lattice_bytes(N, precision, polish, inplace);
     return b;
 }
 
-int lbm_create(int nx, int ny, int precision, int with_polish, void* workspace,
-               size_t workspace_bytes, void* stream, lbm_solver** out) {
+size_t lbm_workspace_bytes(int nx, int ny, int precision, int with_polish) {
+    return workspace_bytes(nx, ny, precision, with_polish != 0, false);
+}
+
+size_t lbm_workspace_bytes_inplace(int nx, int ny, int precision) {
+    return workspace_bytes(nx, ny, precision, false, true);
+}
+
+static int create_solver(int nx, int ny, int precision, int with_polish, bool inplace,
+                         void* workspace, size_t workspace_bytes_given, void* stream,
+                         lbm_solver** out) {
     if (!out) {
         g_create_error = "lbm_create: out is NULL";
         return LBM_E_ARG;
@@ -228,8 +246,9 @@ int lbm_create(int nx, int ny, int precision, int with_polish, void* workspace,
         g_create_error = "lbm_create: invalid size or precision";
         return LBM_E_ARG;
     }
-    const size_t need = lbm_workspace_bytes(nx, ny, precision, with_polish);
-    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) % kAlign)) {
+    const size_t need = workspace_bytes(nx, ny, precision, with_polish != 0, inplace);
+    if (!workspace || workspace_bytes_given < need ||
+        (reinterpret_cast<uintptr_t>(workspace) % kAlign)) {
         g_create_error = "lbm_create: workspace NULL, misaligned or smaller than " +
                          std::to_string(need) + " bytes";
         return LBM_E_WORKSPACE;
@@ -254,11 +273,12 @@ int lbm_create(int nx, int ny, int precision, int with_polish, void* workspace,
     L.N = (long long)nx * ny;
     L.plane = plane_of(L.N);
     L.prec0 = L.prec = precision;
-    L.polish = with_polish != 0 && precision != LBM_FP64;
+    L.polish = with_polish != 0 && precision != LBM_FP64 && !inplace;
+    L.inplace = inplace;
     default_tile(precision, nx, ny, L.bx_log2, L.vy);
-    L.tb = default_time_blocking(precision, nx, ny);
+    L.tb = inplace ? 1 : default_time_blocking(precision, nx, ny);
     L.th = fused_th(precision, (long long)nx * ny);
-    L.wave_hs = default_wave_rows(precision, nx, ny, s->cus);
+    L.wave_hs = inplace ? 0 : default_wave_rows(precision, nx, ny, s->cus);
     char* base = reinterpret_cast<char*>(workspace);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -276,7 +296,7 @@ int lbm_create(int nx, int ny, int precision, int with_polish, void* workspace,
     s->d_items = reinterpret_cast<Item*>(take(s->max_items_ * sizeof(Item)));
     s->d_partial = reinterpret_cast<double*>(take(s->max_items_ * 3 * 8));
     s->d_red = reinterpret_cast<double*>(take((kErrBlocks * 8 + 8) * 8));
-    carve_lattice(base + off, L.N, precision, L.polish, L.mem);
+    carve_lattice(base + off, L.N, precision, L.polish, L.mem, inplace);
     int rc = lbm_reset(s);
     if (rc != LBM_OK) {
         g_create_error = s->err;
@@ -285,6 +305,18 @@ int lbm_create(int nx, int ny, int precision, int with_polish, void* workspace,
     }
     *out = s;
     return LBM_OK;
+}
+
+int lbm_create(int nx, int ny, int precision, int with_polish, void* workspace,
+               size_t workspace_bytes_given, void* stream, lbm_solver** out) {
+    return create_solver(nx, ny, precision, with_polish, false, workspace, workspace_bytes_given,
+                         stream, out);
+}
+
+int lbm_create_inplace(int nx, int ny, int precision, void* workspace,
+                       size_t workspace_bytes_given, void* stream, lbm_solver** out) {
+    return create_solver(nx, ny, precision, 0, true, workspace, workspace_bytes_given, stream,
+                         out);
 }
 
 int lbm_destroy(lbm_solver* s) {
@@ -391,12 +423,16 @@ int lbm_set_time_blocking(lbm_solver* s, int steps_per_launch) {
     if (!s) return LBM_E_ARG;
     if (steps_per_launch < 1 || steps_per_launch > 4)
         return s->fail(LBM_E_ARG, "set_time_blocking: steps_per_launch must be in 1..4");
+    if (s->L.inplace && steps_per_launch != 1)
+        return s->fail(LBM_E_STATE, "set_time_blocking: in-place streaming runs one step per launch");
     s->L.tb = steps_per_launch;
     return s->sync_desc();
 }
 
 int lbm_set_fused_kernel(lbm_solver* s, int kind, int segment_rows) {
     if (!s) return LBM_E_ARG;
+    if (s->L.inplace)
+        return s->fail(LBM_E_STATE, "set_fused_kernel: in-place streaming has no fused kernel");
     if (kind == LBM_FUSED_TILE) {
         s->L.wave_hs = 0;
     } else if (kind == LBM_FUSED_WAVEFRONT) {
@@ -502,8 +538,12 @@ int lbm_solve_to_tol(lbm_solver* s, double tol, long long max_steps, int check_e
     int nondecreasing = 0;
     *residual = NAN;
     *steps_done = 0;
+    const bool inplace = s->L.inplace;
     while (true) {
-        const long long j = (n == 0) ? K : n - 1 + K;  // step index of the next check
+        // step index of the next check.  Two buffers: the check launch is step
+        // j + 1, computing u(j) on the way, and steps back if it stops.  In
+        // place: steps run to j and a launch without a step computes u(j).
+        const long long j = inplace ? n + K : ((n == 0) ? K : n - 1 + K);
         if (j > max_steps) {
             const long long rest = max_steps - n;
             hipError_t e = s->enqueue_chunk(rest, false, false);
@@ -516,8 +556,10 @@ int lbm_solve_to_tol(lbm_solver* s, double tol, long long max_steps, int check_e
             *residual = r;
             return LBM_NOT_CONVERGED;
         }
-        const bool need_writeu = !(have_prev_u && j - 1 == n - 1);
-        const long long nplain = need_writeu ? (j - 1 - n) : 0;
+        const bool need_writeu = inplace ? !(have_prev_u && j - 1 == n)
+                                         : !(have_prev_u && j - 1 == n - 1);
+        const long long nplain =
+            inplace ? (j - n - (need_writeu ? 1 : 0)) : (need_writeu ? (j - 1 - n) : 0);
         hipError_t e = s->enqueue_chunk(nplain, need_writeu, true);
         if (e == hipSuccess)
             e = hipMemcpyAsync(s->h_result, s->d_result, 4 * 8, hipMemcpyDeviceToHost, s->stream);
@@ -527,7 +569,7 @@ int lbm_solve_to_tol(lbm_solver* s, double tol, long long max_steps, int check_e
         r = (u2 == 0.0) ? (d2 == 0.0 ? 0.0 : INFINITY) : std::sqrt(d2 / u2);
         if (d2 != d2 || u2 != u2 || !std::isfinite(u2) || !std::isfinite(fm)) r = NAN;
         *residual = r;
-        const long long after = j + 1;  // steps after the check launch
+        const long long after = inplace ? j : j + 1;  // steps after the check launch
         s->steps += after - n;
         n = after;
         have_prev_u = true;
@@ -537,9 +579,11 @@ int lbm_solve_to_tol(lbm_solver* s, double tol, long long max_steps, int check_e
             return LBM_E_DIVERGED;
         }
         if (r <= tol || j == max_steps) {
-            // the check launch advanced to j + 1; its source buffer still holds f(j)
-            s->phase -= 1;
-            s->steps -= 1;
+            if (!inplace) {
+                // the check launch advanced to j + 1; its source buffer still holds f(j)
+                s->phase -= 1;
+                s->steps -= 1;
+            }
             n = j;
             *steps_done = n;
             return (r <= tol) ? LBM_OK : LBM_NOT_CONVERGED;
@@ -565,7 +609,8 @@ int lbm_get_displacement(lbm_solver* s, double* ux, double* uy) {
     if (!s) return LBM_E_ARG;
     if (!ux || !uy) return s->fail(LBM_E_ARG, "get_displacement: NULL output");
     if (!s->L.has_force) return s->fail(LBM_E_STATE, "get_displacement: no body force set");
-    hipError_t e = extract_u(s->L.prec, s->L.desc(), s->sel(), ux, uy, s->stream);
+    hipError_t e = extract_u(s->L.prec, s->L.desc(), s->sel(), s->L.layout(s->sel()), ux, uy,
+                             s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "get_displacement");
     return LBM_OK;
 }
@@ -576,9 +621,9 @@ int lbm_get_stress(lbm_solver* s, double* sxx, double* syy, double* sxy) {
     if (!s->L.has_material) return s->fail(LBM_E_STATE, "get_stress: no material set");
     const SlotDesc d = s->L.desc();
     hipError_t e;
-    if (s->L.prec == LBM_FP64) e = launch_stress<double>(d, s->sel(), s->L.rates, sxx, syy, sxy, s->stream);
-    else if (s->L.prec == LBM_FP32) e = launch_stress<float>(d, s->sel(), s->L.rates, sxx, syy, sxy, s->stream);
-    else e = launch_stress<__half>(d, s->sel(), s->L.rates, sxx, syy, sxy, s->stream);
+    if (s->L.prec == LBM_FP64) e = launch_stress<double>(d, s->sel(), s->L.layout(s->sel()), s->L.rates, sxx, syy, sxy, s->stream);
+    else if (s->L.prec == LBM_FP32) e = launch_stress<float>(d, s->sel(), s->L.layout(s->sel()), s->L.rates, sxx, syy, sxy, s->stream);
+    else e = launch_stress<__half>(d, s->sel(), s->L.layout(s->sel()), s->L.rates, sxx, syy, sxy, s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "get_stress");
     return LBM_OK;
 }
@@ -590,7 +635,8 @@ int lbm_error_norms(lbm_solver* s, const double* ux_ref, const double* uy_ref, d
     // displacement into the u planes of the workspace, then the two-stage reduction
     double* ux = s->L.mem.u;
     double* uy = s->L.mem.u + s->L.plane;
-    hipError_t e = extract_u(s->L.prec, s->L.desc(), s->sel(), ux, uy, s->stream);
+    hipError_t e = extract_u(s->L.prec, s->L.desc(), s->sel(), s->L.layout(s->sel()), ux, uy,
+                             s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "error_norms");
     hipLaunchKernelGGL(k_err_norms, dim3(kErrBlocks), dim3(kBlock), 0, s->stream, ux, uy, ux_ref,
                        uy_ref, s->L.N, s->d_red);
@@ -610,9 +656,9 @@ int lbm_get_populations(lbm_solver* s, double* f) {
     if (!f) return s->fail(LBM_E_ARG, "get_populations: NULL output");
     const SlotDesc d = s->L.desc();
     hipError_t e;
-    if (s->L.prec == LBM_FP64) e = launch_get_f<double>(d, s->sel(), f, s->stream);
-    else if (s->L.prec == LBM_FP32) e = launch_get_f<float>(d, s->sel(), f, s->stream);
-    else e = launch_get_f<__half>(d, s->sel(), f, s->stream);
+    if (s->L.prec == LBM_FP64) e = launch_get_f<double>(d, s->sel(), s->L.layout(s->sel()), f, s->stream);
+    else if (s->L.prec == LBM_FP32) e = launch_get_f<float>(d, s->sel(), s->L.layout(s->sel()), f, s->stream);
+    else e = launch_get_f<__half>(d, s->sel(), s->L.layout(s->sel()), f, s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "get_populations");
     return LBM_OK;
 }
@@ -623,10 +669,10 @@ int lbm_set_populations(lbm_solver* s, const double* f) {
     const SlotDesc d = s->L.desc();
     const double sc = d.gscale;
     hipError_t e;
-    if (s->L.prec == LBM_FP64) e = launch_set_f<double>(d, s->sel(), f, sc, s->stream);
-    else if (s->L.prec == LBM_FP32) e = launch_set_f<float>(d, s->sel(), f, sc, s->stream);
-    else e = launch_set_f<__half>(d, s->sel(), f, sc, s->stream);
-    if (e == hipSuccess)
+    if (s->L.prec == LBM_FP64) e = launch_set_f<double>(d, s->sel(), s->L.layout(s->sel()), f, sc, s->stream);
+    else if (s->L.prec == LBM_FP32) e = launch_set_f<float>(d, s->sel(), s->L.layout(s->sel()), f, sc, s->stream);
+    else e = launch_set_f<__half>(d, s->sel(), s->L.layout(s->sel()), f, sc, s->stream);
+    if (e == hipSuccess && !s->L.inplace)  // in place: no polish switch, no mean target
         e = neutral_measure(s->L.prec, d, s->sel(), s->d_red, s->h_result, s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "set_populations");
     // the mean first moments of the given state start the exact trajectory
@@ -641,9 +687,10 @@ int lbm_debug_stream_only(lbm_solver* s, long long nsteps) {
     hipError_t e = hipSuccess;
     for (long long i = 0; i < nsteps && e == hipSuccess; ++i) {
         const StepLaunch a = s->launch_args((int)(s->phase & 1));
-        if (s->L.prec == LBM_FP64) e = launch_stream_only<double>(s->grid, s->stream, a);
-        else if (s->L.prec == LBM_FP32) e = launch_stream_only<float>(s->grid, s->stream, a);
-        else e = launch_stream_only<__half>(s->grid, s->stream, a);
+        const int lay = s->L.layout(s->sel());
+        if (s->L.prec == LBM_FP64) e = launch_stream_only<double>(s->grid, s->stream, a, lay);
+        else if (s->L.prec == LBM_FP32) e = launch_stream_only<float>(s->grid, s->stream, a, lay);
+        else e = launch_stream_only<__half>(s->grid, s->stream, a, lay);
         ++s->phase;
     }
     if (e != hipSuccess) return s->hip_fail(e, "debug_stream_only");

@@ -151,6 +151,16 @@ struct Coef {
 __device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Bared first moments ux = m10 + gx/2, uy = m01 + gy/2 of a site (the
+// collision's own operations, also used by the residual check without a step).
+template <typename C>
+__device__ __forceinline__ void bared_u(const C f[8], C gx, C gy, C& ux, C& uy) {
+#pragma clang fp contract(off)
+    const C p = f[4] - f[6], q = f[5] - f[7];
+    ux = ((f[0] - f[2]) + (p - q)) + C(0.5) * gx;
+    uy = ((f[1] - f[3]) + (p + q)) + C(0.5) * gy;
+}
+
 template <typename C, bool GENERAL>
 __device__ __forceinline__ void collide(C f[8], C gx, C gy, const Coef<C>& k, C& ux, C& uy) {
 #pragma clang fp contract(off)
@@ -211,24 +221,77 @@ __device__ __forceinline__ void collide(C f[8], C gx, C gy, const Coef<C>& k, C&
 }
 
 // ---------------------------------------------------------------------------
-// pull-gather of the 8 populations arriving at (x, y)
+// storage layouts of the populations
 // ---------------------------------------------------------------------------
-template <typename S>
-__device__ __forceinline__ void gather(const S* __restrict__ src, long long plane, int nx, int ny,
-                                       int x, int y, typename Store<S>::C f[8]) {
+// kLayPull: two buffers; a buffer holds the post-collision field f*(n-1) at
+//   its own sites (plane q = f*_q), and a step pulls f(n)(x) = f*(x - c_q).
+// In-place streaming (one buffer, the "AA" access pattern) alternates two
+// layouts of the same buffer, so that every step reads and writes each
+// population once and a site touches only locations no other site touches:
+// kLayNatural: the buffer holds f(n) itself (plane q at x = f_q(x)); the step
+//   reads a site's own planes and writes f*_q into plane opp(q) of the same
+//   site, leaving kLaySwapped.
+// kLaySwapped: plane opp(q) at x holds f*_q(x), so f(n)_q(x) is plane opp(q)
+//   at x - c_q; the step reads those and writes f*_q into plane q at x + c_q,
+//   which is f(n+1)_q there: the buffer is back in kLayNatural.
+enum Layout : int { kLayPull = 0, kLayNatural = 1, kLaySwapped = 2 };
+
+// opposite direction: c_opp(q) = -c_q (paper order 1..8 -> 0..7)
+__host__ __device__ constexpr int opp(int q) { return q < 4 ? q ^ 2 : 4 + ((q - 4) ^ 2); }
+
+// ---------------------------------------------------------------------------
+// pull-gather of the 8 populations arriving at (x, y); SWAP reads plane opp(q)
+// ---------------------------------------------------------------------------
+template <typename S, bool SWAP = false>
+__device__ __forceinline__ void gather(const S* src, long long plane, int nx, int ny, int x, int y,
+                                       typename Store<S>::C f[8]) {
     const int xm = (x == 0) ? nx - 1 : x - 1;
     const int xp = (x == nx - 1) ? 0 : x + 1;
     const int ym = (y == 0) ? ny - 1 : y - 1;
     const int yp = (y == ny - 1) ? 0 : y + 1;
     const long long r0 = (long long)y * nx, rm = (long long)ym * nx, rp = (long long)yp * nx;
-    f[0] = Store<S>::ld(src + 0 * plane + r0 + xm);  // c1 = ( 1, 0) from (x-1, y)
-    f[1] = Store<S>::ld(src + 1 * plane + rm + x);   // c2 = ( 0, 1) from (x, y-1)
-    f[2] = Store<S>::ld(src + 2 * plane + r0 + xp);  // c3 = (-1, 0) from (x+1, y)
-    f[3] = Store<S>::ld(src + 3 * plane + rp + x);   // c4 = ( 0,-1) from (x, y+1)
-    f[4] = Store<S>::ld(src + 4 * plane + rm + xm);  // c5 = ( 1, 1) from (x-1, y-1)
-    f[5] = Store<S>::ld(src + 5 * plane + rm + xp);  // c6 = (-1, 1) from (x+1, y-1)
-    f[6] = Store<S>::ld(src + 6 * plane + rp + xp);  // c7 = (-1,-1) from (x+1, y+1)
-    f[7] = Store<S>::ld(src + 7 * plane + rp + xm);  // c8 = ( 1,-1) from (x-1, y+1)
+    auto pl = [](int q) { return SWAP ? opp(q) : q; };
+    f[0] = Store<S>::ld(src + pl(0) * plane + r0 + xm);  // c1 = ( 1, 0) from (x-1, y)
+    f[1] = Store<S>::ld(src + pl(1) * plane + rm + x);   // c2 = ( 0, 1) from (x, y-1)
+    f[2] = Store<S>::ld(src + pl(2) * plane + r0 + xp);  // c3 = (-1, 0) from (x+1, y)
+    f[3] = Store<S>::ld(src + pl(3) * plane + rp + x);   // c4 = ( 0,-1) from (x, y+1)
+    f[4] = Store<S>::ld(src + pl(4) * plane + rm + xm);  // c5 = ( 1, 1) from (x-1, y-1)
+    f[5] = Store<S>::ld(src + pl(5) * plane + rm + xp);  // c6 = (-1, 1) from (x+1, y-1)
+    f[6] = Store<S>::ld(src + pl(6) * plane + rp + xp);  // c7 = (-1,-1) from (x+1, y+1)
+    f[7] = Store<S>::ld(src + pl(7) * plane + rp + xm);  // c8 = ( 1,-1) from (x-1, y+1)
+}
+
+// push of f*_q to plane q at x + c_q (in-place odd step)
+template <typename S>
+__device__ __forceinline__ void scatter(S* dst, long long plane, int nx, int ny, int x, int y,
+                                        const typename Store<S>::C f[8]) {
+    const int xm = (x == 0) ? nx - 1 : x - 1;
+    const int xp = (x == nx - 1) ? 0 : x + 1;
+    const int ym = (y == 0) ? ny - 1 : y - 1;
+    const int yp = (y == ny - 1) ? 0 : y + 1;
+    const long long r0 = (long long)y * nx, rm = (long long)ym * nx, rp = (long long)yp * nx;
+    Store<S>::st(dst + 0 * plane + r0 + xp, f[0]);  // c1 = ( 1, 0) to (x+1, y)
+    Store<S>::st(dst + 1 * plane + rp + x, f[1]);   // c2 = ( 0, 1) to (x, y+1)
+    Store<S>::st(dst + 2 * plane + r0 + xm, f[2]);  // c3 = (-1, 0) to (x-1, y)
+    Store<S>::st(dst + 3 * plane + rm + x, f[3]);   // c4 = ( 0,-1) to (x, y-1)
+    Store<S>::st(dst + 4 * plane + rp + xp, f[4]);  // c5 = ( 1, 1) to (x+1, y+1)
+    Store<S>::st(dst + 5 * plane + rp + xm, f[5]);  // c6 = (-1, 1) to (x-1, y+1)
+    Store<S>::st(dst + 6 * plane + rm + xm, f[6]);  // c7 = (-1,-1) to (x-1, y-1)
+    Store<S>::st(dst + 7 * plane + rm + xp, f[7]);  // c8 = ( 1,-1) to (x+1, y-1)
+}
+
+// f(n) at (x, y) from a buffer in any layout
+template <typename S>
+__device__ __forceinline__ void load_state(const S* buf, long long plane, int nx, int ny, int x,
+                                           int y, int layout, typename Store<S>::C f[8]) {
+    if (layout == kLayPull) {
+        gather<S, false>(buf, plane, nx, ny, x, y, f);
+    } else if (layout == kLaySwapped) {
+        gather<S, true>(buf, plane, nx, ny, x, y, f);
+    } else {
+        const long long s = (long long)y * nx + x;
+        for (int q = 0; q < 8; ++q) f[q] = Store<S>::ld(buf + q * plane + s);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -299,7 +362,9 @@ __device__ __forceinline__ void xcd_slice(const int* range, int& last, int& stri
     start = first + lb;
 }
 
-template <typename S, int MODE, bool GENERAL, int VY>
+// LAY: kLayPull (read buf[sel], write buf[sel ^ 1]) or an in-place layout
+// (read and write buf[sel]; see Layout).
+template <typename S, int MODE, bool GENERAL, int VY, int LAY = kLayPull>
 static __global__ __launch_bounds__(kBlock) void k_step(StepLaunch L) {
     using C = typename Store<S>::C;
     __shared__ double lds[12];
@@ -311,8 +376,10 @@ static __global__ __launch_bounds__(kBlock) void k_step(StepLaunch L) {
         const int nx = d.nx, ny = d.ny;
         const long long plane = d.plane;
         const int sel = d.cur ^ L.flip;
-        const S* __restrict__ src = reinterpret_cast<const S*>(d.buf[sel]);
-        S* __restrict__ dst = reinterpret_cast<S*>(d.buf[sel ^ 1]);
+        // in place, source and destination are one buffer (no restrict): each
+        // location is read and then written by the same site only
+        const S* src = reinterpret_cast<const S*>(d.buf[sel]);
+        S* dst = reinterpret_cast<S*>(d.buf[LAY == kLayPull ? (sel ^ 1) : sel]);
         const C* __restrict__ g = reinterpret_cast<const C*>(d.g);
         Coef<C> k;
         k.load(d);
@@ -329,7 +396,7 @@ static __global__ __launch_bounds__(kBlock) void k_step(StepLaunch L) {
         for (int j = 0; j < VY; ++j) {
             const int y = y0 + j * th;
             ok[j] = (x < nx) && (y < ny);
-            if (ok[j]) gather<S>(src, plane, nx, ny, x, y, f[j]);
+            if (ok[j]) load_state<S>(src, plane, nx, ny, x, y, LAY, f[j]);
         }
 #pragma unroll
         for (int j = 0; j < VY; ++j) {
@@ -340,8 +407,15 @@ static __global__ __launch_bounds__(kBlock) void k_step(StepLaunch L) {
             const C gy = glob(g)[plane + s] * k.gscale;
             C ux, uy;
             collide<C, GENERAL>(f[j], gx, gy, k, ux, uy);
+            if constexpr (LAY == kLayPull) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * plane + s, f[j][q]);
+                for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * plane + s, f[j][q]);
+            } else if constexpr (LAY == kLayNatural) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) Store<S>::st(dst + opp(q) * plane + s, f[j][q]);
+            } else {
+                scatter<S>(dst, plane, nx, ny, x, y, f[j]);
+            }
             if constexpr (MODE != kPlain) {
                 const double uxd = (double)ux * d.inv_scale, uyd = (double)uy * d.inv_scale;
                 if constexpr (MODE == kCheck) {
@@ -749,8 +823,9 @@ static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
     }
 }
 
-// Streaming alone (no collision): bit-exact check of the index arithmetic.
-template <typename S>
+// Streaming alone (no collision): bit-exact check of the index arithmetic,
+// in any layout (in place, an even and an odd step together stream twice).
+template <typename S, int LAY = kLayPull>
 static __global__ __launch_bounds__(kBlock) void k_stream_only(StepLaunch L) {
     using C = typename Store<S>::C;
     int last, stride, it;
@@ -760,7 +835,7 @@ static __global__ __launch_bounds__(kBlock) void k_stream_only(StepLaunch L) {
         const SlotDesc& d = L.slots[item.slot];
         const int sel = d.cur ^ L.flip;
         const S* src = reinterpret_cast<const S*>(d.buf[sel]);
-        S* dst = reinterpret_cast<S*>(d.buf[sel ^ 1]);
+        S* dst = reinterpret_cast<S*>(d.buf[LAY == kLayPull ? (sel ^ 1) : sel]);
         const int bxl = d.bx_log2;
         const int th = kBlock >> bxl;
         const int x = (item.tx << bxl) + (threadIdx.x & ((1 << bxl) - 1));
@@ -768,9 +843,67 @@ static __global__ __launch_bounds__(kBlock) void k_stream_only(StepLaunch L) {
             const int y = item.ty * th * L.rows + (threadIdx.x >> bxl) + j * th;
             if (x >= d.nx || y >= d.ny) continue;
             C f[8];
-            gather<S>(src, d.plane, d.nx, d.ny, x, y, f);
+            load_state<S>(src, d.plane, d.nx, d.ny, x, y, LAY, f);
             const long long s = (long long)y * d.nx + x;
-            for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * d.plane + s, f[q]);
+            if (LAY == kLayPull)
+                for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * d.plane + s, f[q]);
+            else if (LAY == kLayNatural)
+                for (int q = 0; q < 8; ++q) Store<S>::st(dst + opp(q) * d.plane + s, f[q]);
+            else
+                scatter<S>(dst, d.plane, d.nx, d.ny, x, y, f);
+        }
+    }
+}
+
+// Residual check without a step (in-place streaming, which cannot step back
+// after the check): u(n) from the stored field in layout LAY; per tile the
+// FP64 partials sum |u(n) - u_prev|^2, sum |u(n)|^2 and max |f|; u(n) is
+// stored as the next u_prev.
+template <typename S, int LAY, int VY>
+static __global__ __launch_bounds__(kBlock) void k_check_state(StepLaunch L) {
+    using C = typename Store<S>::C;
+    __shared__ double lds[12];
+    int last, stride, it;
+    xcd_slice(L.range, last, stride, it);
+    for (; it < last; it += stride) {
+        const Item item = L.items[it];
+        const SlotDesc& d = L.slots[item.slot];
+        const int nx = d.nx, ny = d.ny;
+        const long long plane = d.plane;
+        const S* src = reinterpret_cast<const S*>(d.buf[d.cur ^ L.flip]);
+        const C* g = reinterpret_cast<const C*>(d.g);
+        Coef<C> k;
+        k.load(d);
+        const int bxl = d.bx_log2;
+        const int th = kBlock >> bxl;
+        const int x = (item.tx << bxl) + (threadIdx.x & ((1 << bxl) - 1));
+        double dsum = 0.0, ssum = 0.0, fmaxv = 0.0;
+#pragma unroll
+        for (int j = 0; j < VY; ++j) {
+            const int y = item.ty * th * VY + (threadIdx.x >> bxl) + j * th;
+            if (x >= nx || y >= ny) continue;
+            C f[8];
+            load_state<S>(src, plane, nx, ny, x, y, LAY, f);
+            const long long s = (long long)y * nx + x;
+            // u exactly as the collision forms it (same type and operations)
+            C ux, uy;
+            bared_u<C>(f, glob(g)[s] * k.gscale, glob(g)[plane + s] * k.gscale, ux, uy);
+            const double uxd = (double)ux * d.inv_scale, uyd = (double)uy * d.inv_scale;
+            const double dx = uxd - glob(d.u)[s], dy = uyd - glob(d.u)[plane + s];
+            dsum += dx * dx + dy * dy;
+            ssum += uxd * uxd + uyd * uyd;
+            double m = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) m = fmax(m, (double)fabs(f[q]));
+            fmaxv = fmax(fmaxv, m);
+            glob(d.u)[s] = uxd;
+            glob(d.u)[plane + s] = uyd;
+        }
+        block_reduce3(dsum, ssum, fmaxv, lds);
+        if (threadIdx.x == 0) {
+            glob(L.partial)[3 * it + 0] = dsum;
+            glob(L.partial)[3 * it + 1] = ssum;
+            glob(L.partial)[3 * it + 2] = fmaxv;
         }
     }
 }
@@ -811,17 +944,17 @@ static __global__ __launch_bounds__(kBlock) void k_finalize(FinalizeLaunch F) {
 // per-lattice helpers (1 thread per site)
 // ---------------------------------------------------------------------------
 
-// u(n) = bared first moments of f(n) (gathered from the stored post-collision
-// field), FP64 and unscaled (Table "solution").
+// u(n) = bared first moments of f(n) (read from the stored field in its
+// layout), FP64 and unscaled (Table "solution").
 template <typename S>
-static __global__ __launch_bounds__(kBlock) void k_extract_u(SlotDesc d, int sel, double* ux,
-                                                      double* uy) {
+static __global__ __launch_bounds__(kBlock) void k_extract_u(SlotDesc d, int sel, int layout,
+                                                             double* ux, double* uy) {
     using C = typename Store<S>::C;
     const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (s >= (long long)d.nx * d.ny) return;
     const int x = (int)(s % d.nx), y = (int)(s / d.nx);
     C f[8];
-    gather<S>(reinterpret_cast<const S*>(d.buf[sel]), d.plane, d.nx, d.ny, x, y, f);
+    load_state<S>(reinterpret_cast<const S*>(d.buf[sel]), d.plane, d.nx, d.ny, x, y, layout, f);
     const C* g = reinterpret_cast<const C*>(d.g);
     const double m10 = (double)((f[0] - f[2]) + ((f[4] - f[6]) - (f[5] - f[7])));
     const double m01 = (double)((f[1] - f[3]) + ((f[4] - f[6]) + (f[5] - f[7])));
@@ -834,15 +967,16 @@ static __global__ __launch_bounds__(kBlock) void k_extract_u(SlotDesc d, int sel
 // zero equilibria, Table "solution" in lattice units): sxx = -(mb_s + mb_d)/2,
 // syy = -(mb_s - mb_d)/2, sxy = -mb_11, mb = (1 - omega/2) m.
 template <typename S>
-static __global__ __launch_bounds__(kBlock) void k_extract_stress(SlotDesc d, int sel, double bs,
-                                                           double bd, double b11, double* sxx,
-                                                           double* syy, double* sxy) {
+static __global__ __launch_bounds__(kBlock) void k_extract_stress(SlotDesc d, int sel, int layout,
+                                                                  double bs, double bd, double b11,
+                                                                  double* sxx, double* syy,
+                                                                  double* sxy) {
     using C = typename Store<S>::C;
     const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (s >= (long long)d.nx * d.ny) return;
     const int x = (int)(s % d.nx), y = (int)(s / d.nx);
     C f[8];
-    gather<S>(reinterpret_cast<const S*>(d.buf[sel]), d.plane, d.nx, d.ny, x, y, f);
+    load_state<S>(reinterpret_cast<const S*>(d.buf[sel]), d.plane, d.nx, d.ny, x, y, layout, f);
     const double h13 = (double)f[0] + (double)f[2], h24 = (double)f[1] + (double)f[3];
     const double sac = (double)f[4] + (double)f[6], sbd = (double)f[5] + (double)f[7];
     const double ms = (h13 + h24) + 2.0 * (sac + sbd);
@@ -854,24 +988,26 @@ static __global__ __launch_bounds__(kBlock) void k_extract_stress(SlotDesc d, in
     sxy[s] = -mb11 * d.inv_scale;
 }
 
-// Populations f(n) in the paper's order, FP64 unscaled: gather of the stored field.
+// Populations f(n) in the paper's order, FP64 unscaled, from the stored field.
 template <typename S>
-static __global__ __launch_bounds__(kBlock) void k_get_f(SlotDesc d, int sel, double* out) {
+static __global__ __launch_bounds__(kBlock) void k_get_f(SlotDesc d, int sel, int layout,
+                                                         double* out) {
     using C = typename Store<S>::C;
     const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (s >= (long long)d.nx * d.ny) return;
     const int x = (int)(s % d.nx), y = (int)(s / d.nx);
     C f[8];
-    gather<S>(reinterpret_cast<const S*>(d.buf[sel]), d.plane, d.nx, d.ny, x, y, f);
+    load_state<S>(reinterpret_cast<const S*>(d.buf[sel]), d.plane, d.nx, d.ny, x, y, layout, f);
     const long long N = (long long)d.nx * d.ny;  // external layout [8][ny][nx]
     for (int q = 0; q < 8; ++q) out[q * N + s] = (double)f[q] * d.inv_scale;
 }
 
-// Load a state f(n) given in the paper's order: the stored field is
-// f*(n-1)(x) = f(n)(x + c_q), i.e. the inverse of the gather.
+// Load a state f(n) given in the paper's order.  kLayPull and kLaySwapped
+// store f*(n-1)(x) = f(n)(x + c_q) (the inverse of the gather), in plane q or
+// plane opp(q); kLayNatural stores f(n) itself.
 template <typename S>
-static __global__ __launch_bounds__(kBlock) void k_set_f(SlotDesc d, int sel, const double* in,
-                                                  double scale) {
+static __global__ __launch_bounds__(kBlock) void k_set_f(SlotDesc d, int sel, int layout,
+                                                         const double* in, double scale) {
     const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (s >= (long long)d.nx * d.ny) return;
     const int x = (int)(s % d.nx), y = (int)(s / d.nx);
@@ -882,10 +1018,12 @@ static __global__ __launch_bounds__(kBlock) void k_set_f(SlotDesc d, int sel, co
     const int cx[8] = {1, 0, -1, 0, 1, -1, -1, 1};
     const int cy[8] = {0, 1, 0, -1, 1, 1, -1, -1};
     for (int q = 0; q < 8; ++q) {
-        const int xs = cx[q] > 0 ? xp : (cx[q] < 0 ? xm : x);
-        const int ys = cy[q] > 0 ? yp : (cy[q] < 0 ? ym : y);
+        const bool nat = layout == kLayNatural;
+        const int xs = nat ? x : (cx[q] > 0 ? xp : (cx[q] < 0 ? xm : x));
+        const int ys = nat ? y : (cy[q] > 0 ? yp : (cy[q] < 0 ? ym : y));
         const double v = in[q * N + (long long)ys * d.nx + xs] * scale;
-        Store<S>::st(dst + q * d.plane + s, (typename Store<S>::C)v);
+        const int plane_q = layout == kLaySwapped ? opp(q) : q;
+        Store<S>::st(dst + plane_q * d.plane + s, (typename Store<S>::C)v);
     }
 }
 

@@ -67,31 +67,60 @@ inline void fill_coefs(SlotDesc& d, const Rates& r) {
 // ---------------------------------------------------------------------------
 // kernel dispatch
 // ---------------------------------------------------------------------------
-template <typename S, int MODE>
-inline hipError_t launch_step_t(bool general, int vy, unsigned grid, hipStream_t st,
-                         const StepLaunch& L) {
+template <typename S, int MODE, int LAY>
+inline hipError_t launch_step_l(bool general, int vy, unsigned grid, hipStream_t st,
+                                const StepLaunch& L) {
     if (general) {
-        hipLaunchKernelGGL((k_step<S, MODE, true, 1>), dim3(grid), dim3(kBlock), 0, st, L);
+        hipLaunchKernelGGL((k_step<S, MODE, true, 1, LAY>), dim3(grid), dim3(kBlock), 0, st, L);
     } else if (vy == 1) {
-        hipLaunchKernelGGL((k_step<S, MODE, false, 1>), dim3(grid), dim3(kBlock), 0, st, L);
+        hipLaunchKernelGGL((k_step<S, MODE, false, 1, LAY>), dim3(grid), dim3(kBlock), 0, st, L);
     } else if (vy == 2) {
-        hipLaunchKernelGGL((k_step<S, MODE, false, 2>), dim3(grid), dim3(kBlock), 0, st, L);
+        hipLaunchKernelGGL((k_step<S, MODE, false, 2, LAY>), dim3(grid), dim3(kBlock), 0, st, L);
     } else if (vy == 3) {
-        hipLaunchKernelGGL((k_step<S, MODE, false, 3>), dim3(grid), dim3(kBlock), 0, st, L);
+        hipLaunchKernelGGL((k_step<S, MODE, false, 3, LAY>), dim3(grid), dim3(kBlock), 0, st, L);
     } else {
-        hipLaunchKernelGGL((k_step<S, MODE, false, 4>), dim3(grid), dim3(kBlock), 0, st, L);
+        hipLaunchKernelGGL((k_step<S, MODE, false, 4, LAY>), dim3(grid), dim3(kBlock), 0, st, L);
     }
     return hipGetLastError();
 }
 
+template <typename S, int MODE>
+inline hipError_t launch_step_t(bool general, int vy, int layout, unsigned grid, hipStream_t st,
+                                const StepLaunch& L) {
+    if (layout == kLayNatural) return launch_step_l<S, MODE, kLayNatural>(general, vy, grid, st, L);
+    if (layout == kLaySwapped) return launch_step_l<S, MODE, kLaySwapped>(general, vy, grid, st, L);
+    return launch_step_l<S, MODE, kLayPull>(general, vy, grid, st, L);
+}
+
 template <typename S>
-inline hipError_t launch_step_s(int mode, bool general, int vy, unsigned grid, hipStream_t st,
-                         const StepLaunch& L) {
+inline hipError_t launch_step_s(int mode, bool general, int vy, int layout, unsigned grid,
+                                hipStream_t st, const StepLaunch& L) {
     switch (mode) {
-        case kPlain: return launch_step_t<S, kPlain>(general, vy, grid, st, L);
-        case kWriteU: return launch_step_t<S, kWriteU>(general, vy, grid, st, L);
-        default: return launch_step_t<S, kCheck>(general, vy, grid, st, L);
+        case kPlain: return launch_step_t<S, kPlain>(general, vy, layout, grid, st, L);
+        case kWriteU: return launch_step_t<S, kWriteU>(general, vy, layout, grid, st, L);
+        default: return launch_step_t<S, kCheck>(general, vy, layout, grid, st, L);
     }
+}
+
+// Non-advancing residual check of an in-place lattice (layout natural or swapped).
+template <typename S, int LAY>
+inline void launch_check_state_l(int vy, unsigned grid, hipStream_t st, const StepLaunch& L) {
+    if (vy == 1) hipLaunchKernelGGL((k_check_state<S, LAY, 1>), dim3(grid), dim3(kBlock), 0, st, L);
+    else if (vy == 2) hipLaunchKernelGGL((k_check_state<S, LAY, 2>), dim3(grid), dim3(kBlock), 0, st, L);
+    else if (vy == 3) hipLaunchKernelGGL((k_check_state<S, LAY, 3>), dim3(grid), dim3(kBlock), 0, st, L);
+    else hipLaunchKernelGGL((k_check_state<S, LAY, 4>), dim3(grid), dim3(kBlock), 0, st, L);
+}
+template <typename S>
+inline void launch_check_state_s(int vy, int layout, unsigned grid, hipStream_t st, const StepLaunch& L) {
+    if (layout == kLaySwapped) launch_check_state_l<S, kLaySwapped>(vy, grid, st, L);
+    else launch_check_state_l<S, kLayNatural>(vy, grid, st, L);
+}
+inline hipError_t launch_check_state(int prec, int vy, int layout, unsigned grid, hipStream_t st,
+                                     const StepLaunch& L) {
+    if (prec == LBM_FP64) launch_check_state_s<double>(vy, layout, grid, st, L);
+    else if (prec == LBM_FP32) launch_check_state_s<float>(vy, layout, grid, st, L);
+    else launch_check_state_s<__half>(vy, layout, grid, st, L);
+    return hipGetLastError();
 }
 
 // Tile height of the fused LDS kernel (width 64), measured on MI355X: FP64 8
@@ -184,11 +213,11 @@ inline int default_time_blocking(int prec, int nx, int ny) {
     return 4;
 }
 
-inline hipError_t launch_step(int prec, int mode, bool general, int vy, unsigned grid, hipStream_t st,
-                       const StepLaunch& L) {
-    if (prec == LBM_FP64) return launch_step_s<double>(mode, general, vy, grid, st, L);
-    if (prec == LBM_FP32) return launch_step_s<float>(mode, general, vy, grid, st, L);
-    return launch_step_s<__half>(mode, general, vy, grid, st, L);
+inline hipError_t launch_step(int prec, int mode, bool general, int vy, int layout, unsigned grid,
+                              hipStream_t st, const StepLaunch& L) {
+    if (prec == LBM_FP64) return launch_step_s<double>(mode, general, vy, layout, grid, st, L);
+    if (prec == LBM_FP32) return launch_step_s<float>(mode, general, vy, layout, grid, st, L);
+    return launch_step_s<__half>(mode, general, vy, layout, grid, st, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -212,19 +241,22 @@ inline long long plane_of(long long N) {
     return N >= (1LL << 16) ? r + 1024 : r;
 }
 
-inline size_t lattice_bytes(long long N, int prec, bool polish) {
+// In place (one population buffer), no polish reservation.
+inline size_t lattice_bytes(long long N, int prec, bool polish, bool inplace = false) {
     const long long P = plane_of(N);
-    size_t b = 2 * al(8 * P * elem_bytes(prec)) + al(2 * P * arith_bytes(prec)) + al(2 * P * 8);
+    size_t b = (inplace ? 1 : 2) * al(8 * P * elem_bytes(prec)) + al(2 * P * arith_bytes(prec)) +
+               al(2 * P * 8);
     if (polish && prec != LBM_FP64) b += 2 * al(8 * P * 8) + al(2 * P * 8);
     return b;
 }
 
-inline void carve_lattice(char* base, long long N, int prec, bool polish, LatticeMem& m) {
+inline void carve_lattice(char* base, long long N, int prec, bool polish, LatticeMem& m,
+                          bool inplace = false) {
     const long long P = plane_of(N);
     size_t off = 0;
     for (int i = 0; i < 2; ++i) {
         m.buf[i] = base + off;
-        off += al(8 * P * elem_bytes(prec));
+        if (!inplace || i == 1) off += al(8 * P * elem_bytes(prec));
     }
     m.g = base + off;
     off += al(2 * P * arith_bytes(prec));
@@ -277,6 +309,10 @@ struct Lattice {
     int th = 16;      // tile height of the fused LDS kernel (fused_th)
     int wave_hs = 0;  // > 0: fused launches use the register wavefront, segments of wave_hs rows
     int cur = 0;      // buffer with the state at flip 0
+    bool inplace = false;  // one buffer, in-place streaming (layout alternates per step)
+    // layout of the stored field for buffer selector `sel` = cur ^ launch parity
+    // (in place, the selector flips every step and starts at 0 in kLayNatural)
+    int layout(int sel) const { return !inplace ? kLayPull : (sel ? kLaySwapped : kLayNatural); }
 
     void* state_buf(int i) const {
         return (prec == prec0) ? mem.buf[i] : mem.pbuf[i];
@@ -285,7 +321,7 @@ struct Lattice {
     int tiles_x() const { return (nx + (1 << eff_bxl()) - 1) >> eff_bxl(); }
     // The fused kernel has a tile 64 wide and th rows high; the general-rates
     // variant runs one row per thread.
-    bool fused() const { return tb >= 2 && !general(); }
+    bool fused() const { return tb >= 2 && !general() && !inplace; }
     int eff_bxl() const { return fused() ? 6 : bx_log2; }
     int eff_vy() const { return fused() ? th / 4 : (general() ? 1 : vy); }
     int tile_h() const { return (kBlock >> eff_bxl()) * eff_vy(); }
@@ -337,43 +373,52 @@ inline void default_tile(int prec, int nx, int ny, int& bx_log2, int& vy) {
 }
 
 template <typename S>
-inline hipError_t launch_extract_u(const SlotDesc& d, int sel, double* ux, double* uy, hipStream_t st) {
-    hipLaunchKernelGGL(k_extract_u<S>, dim3(blocks_for((long long)d.nx * d.ny)), dim3(kBlock), 0, st, d, sel,
-                       ux, uy);
+inline hipError_t launch_extract_u(const SlotDesc& d, int sel, int layout, double* ux, double* uy,
+                                   hipStream_t st) {
+    hipLaunchKernelGGL(k_extract_u<S>, dim3(blocks_for((long long)d.nx * d.ny)), dim3(kBlock), 0, st,
+                       d, sel, layout, ux, uy);
     return hipGetLastError();
 }
-inline hipError_t extract_u(int prec, const SlotDesc& d, int sel, double* ux, double* uy,
-                     hipStream_t st) {
-    if (prec == LBM_FP64) return launch_extract_u<double>(d, sel, ux, uy, st);
-    if (prec == LBM_FP32) return launch_extract_u<float>(d, sel, ux, uy, st);
-    return launch_extract_u<__half>(d, sel, ux, uy, st);
+inline hipError_t extract_u(int prec, const SlotDesc& d, int sel, int layout, double* ux,
+                            double* uy, hipStream_t st) {
+    if (prec == LBM_FP64) return launch_extract_u<double>(d, sel, layout, ux, uy, st);
+    if (prec == LBM_FP32) return launch_extract_u<float>(d, sel, layout, ux, uy, st);
+    return launch_extract_u<__half>(d, sel, layout, ux, uy, st);
 }
 
 template <typename S>
-inline hipError_t launch_stress(const SlotDesc& d, int sel, const Rates& r, double* a, double* b,
-                         double* c, hipStream_t st) {
-    hipLaunchKernelGGL(k_extract_stress<S>, dim3(blocks_for((long long)d.nx * d.ny)), dim3(kBlock), 0, st, d,
-                       sel, 1.0 - 0.5 * r.ws, 1.0 - 0.5 * r.wd, 1.0 - 0.5 * r.w11, a, b, c);
-    return hipGetLastError();
-}
-
-template <typename S>
-inline hipError_t launch_get_f(const SlotDesc& d, int sel, double* f, hipStream_t st) {
-    hipLaunchKernelGGL(k_get_f<S>, dim3(blocks_for((long long)d.nx * d.ny)), dim3(kBlock), 0, st, d, sel, f);
+inline hipError_t launch_stress(const SlotDesc& d, int sel, int layout, const Rates& r, double* a,
+                                double* b, double* c, hipStream_t st) {
+    hipLaunchKernelGGL(k_extract_stress<S>, dim3(blocks_for((long long)d.nx * d.ny)), dim3(kBlock), 0,
+                       st, d, sel, layout, 1.0 - 0.5 * r.ws, 1.0 - 0.5 * r.wd, 1.0 - 0.5 * r.w11,
+                       a, b, c);
     return hipGetLastError();
 }
 
 template <typename S>
-inline hipError_t launch_set_f(const SlotDesc& d, int sel, const double* f, double scale,
-                        hipStream_t st) {
-    hipLaunchKernelGGL(k_set_f<S>, dim3(blocks_for((long long)d.nx * d.ny)), dim3(kBlock), 0, st, d, sel, f,
-                       scale);
+inline hipError_t launch_get_f(const SlotDesc& d, int sel, int layout, double* f, hipStream_t st) {
+    hipLaunchKernelGGL(k_get_f<S>, dim3(blocks_for((long long)d.nx * d.ny)), dim3(kBlock), 0, st, d,
+                       sel, layout, f);
     return hipGetLastError();
 }
 
 template <typename S>
-inline hipError_t launch_stream_only(unsigned grid, hipStream_t st, const StepLaunch& L) {
-    hipLaunchKernelGGL(k_stream_only<S>, dim3(grid), dim3(kBlock), 0, st, L);
+inline hipError_t launch_set_f(const SlotDesc& d, int sel, int layout, const double* f,
+                               double scale, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_f<S>, dim3(blocks_for((long long)d.nx * d.ny)), dim3(kBlock), 0, st, d,
+                       sel, layout, f, scale);
+    return hipGetLastError();
+}
+
+template <typename S>
+inline hipError_t launch_stream_only(unsigned grid, hipStream_t st, const StepLaunch& L,
+                                     int layout) {
+    if (layout == kLayNatural)
+        hipLaunchKernelGGL((k_stream_only<S, kLayNatural>), dim3(grid), dim3(kBlock), 0, st, L);
+    else if (layout == kLaySwapped)
+        hipLaunchKernelGGL((k_stream_only<S, kLaySwapped>), dim3(grid), dim3(kBlock), 0, st, L);
+    else
+        hipLaunchKernelGGL((k_stream_only<S, kLayPull>), dim3(grid), dim3(kBlock), 0, st, L);
     return hipGetLastError();
 }
 

@@ -70,6 +70,8 @@ def load() -> ctypes.CDLL:
         "lbm_debug_stream_only": (i, [vp, ll]),
         "lbm_set_time_blocking": (i, [vp, i]),
         "lbm_set_fused_kernel": (i, [vp, i, i]),
+        "lbm_workspace_bytes_inplace": (sz, [i, i, i]),
+        "lbm_create_inplace": (i, [i, i, i, vp, sz, vp, ctypes.POINTER(vp)]),
         "lbm_last_error": (ctypes.c_char_p, [vp]),
         "lbm_batch_slot_bytes": (sz, [i, i, i, i]),
         "lbm_batch_create": (i, [i, vp, sz, vp, ctypes.POINTER(vp)]),
@@ -118,25 +120,40 @@ def _aligned_buffer(nbytes: int, device) -> Tuple[torch.Tensor, int]:
 
 
 class Solver:
-    """One periodic nx x ny lattice (lbm_create ... lbm_destroy)."""
+    """One periodic nx x ny lattice (lbm_create ... lbm_destroy); with
+    inplace=True, one population buffer with in-place streaming
+    (lbm_create_inplace)."""
 
     def __init__(self, nx: int, ny: int, precision: str = "fp64", with_polish: bool = False,
-                 device: str = "cuda"):
+                 device: str = "cuda", inplace: bool = False):
         self.lib = load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the HIP library cannot run")
         self.nx, self.ny = int(nx), int(ny)
         self.device = torch.device(device)
         self.precision = PRECISIONS[precision]
-        nbytes = self.lib.lbm_workspace_bytes(self.nx, self.ny, self.precision, int(with_polish))
+        self.inplace = bool(inplace)
+        if self.inplace and with_polish:
+            raise ValueError("in-place streaming has no polish phase")
+        if self.inplace:
+            nbytes = self.lib.lbm_workspace_bytes_inplace(self.nx, self.ny, self.precision)
+        else:
+            nbytes = self.lib.lbm_workspace_bytes(self.nx, self.ny, self.precision,
+                                                  int(with_polish))
         if nbytes == 0:
             raise ValueError("invalid lattice size or precision")
         self._ws, self._ws_ptr = _aligned_buffer(nbytes, self.device)
         self._nbytes = nbytes
         h = ctypes.c_void_p()
-        rc = self.lib.lbm_create(self.nx, self.ny, self.precision, int(with_polish),
-                                 ctypes.c_void_p(self._ws_ptr), nbytes,
-                                 ctypes.c_void_p(_stream_ptr(self.device)), ctypes.byref(h))
+        stream = ctypes.c_void_p(_stream_ptr(self.device))
+        if self.inplace:
+            rc = self.lib.lbm_create_inplace(self.nx, self.ny, self.precision,
+                                             ctypes.c_void_p(self._ws_ptr), nbytes, stream,
+                                             ctypes.byref(h))
+        else:
+            rc = self.lib.lbm_create(self.nx, self.ny, self.precision, int(with_polish),
+                                     ctypes.c_void_p(self._ws_ptr), nbytes, stream,
+                                     ctypes.byref(h))
         if rc != 0:
             raise LbmError(rc, self.lib.lbm_last_error(None).decode())
         self.h = h

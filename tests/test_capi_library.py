@@ -50,6 +50,21 @@ def test_workspace_sizes_without_gpu(lib):
     assert lib.lbm_workspace_bytes(n, n, 1, 1) >= b32 + n * n * (2 * 8 * 8 + 2 * 8)
 
 
+def test_inplace_workspace_holds_one_population_buffer(lib):
+    lib.lbm_workspace_bytes.restype = ctypes.c_size_t
+    lib.lbm_workspace_bytes.argtypes = [ctypes.c_int] * 4
+    lib.lbm_workspace_bytes_inplace.restype = ctypes.c_size_t
+    lib.lbm_workspace_bytes_inplace.argtypes = [ctypes.c_int] * 3
+    assert lib.lbm_workspace_bytes_inplace(0, 4, 1) == 0
+    n = 2048
+    for prec, esz in ((0, 8), (1, 4), (2, 2)):
+        two = lib.lbm_workspace_bytes(n, n, prec, 0)
+        one = lib.lbm_workspace_bytes_inplace(n, n, prec)
+        # one buffer of 8 planes (padded) fewer
+        assert two - one >= 8 * n * n * esz
+        assert two - one <= 8 * (n * n + 2048) * esz + 256
+
+
 def test_binding_has_no_cpu_fallback():
     """The Python binding raises when no GPU is visible instead of computing."""
     import torch

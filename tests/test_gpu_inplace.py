@@ -1,0 +1,144 @@
+"""In-place streaming (one population buffer, lbm_create_inplace): identical
+results to the two-buffer solver, bit for bit, in every precision."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2208_14870_amd import problem as P
+from gpu_common import dev, host, need_gpu, omega, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(nx, ny, prec, mat, gx, gy, f0=None, rates=None):
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    out = []
+    for inplace in (False, True):
+        s = lbm.Solver(nx, ny, prec, inplace=inplace)
+        if not inplace:
+            s.set_time_blocking(1)
+        if rates is not None:
+            s.set_rates(*rates)
+        s.set_material(mat.lame_lambda, mat.lame_mu)
+        s.set_body_force(dev(gx), dev(gy))
+        if f0 is not None:
+            s.set_populations(dev(f0))
+        out.append(s)
+    return out
+
+
+def _rand(nx, ny, seed, scale=1e-3):
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal((8, ny, nx)) * scale
+    gx = P.remove_mean(rng.standard_normal((ny, nx)) * scale * 0.1)
+    gy = P.remove_mean(rng.standard_normal((ny, nx)) * scale * 0.1)
+    return f, gx, gy
+
+
+@pytest.mark.parametrize("prec,nx,ny", [
+    ("fp64", 1, 1), ("fp64", 3, 5), ("fp64", 67, 33), ("fp64", 2, 7), ("fp32", 65, 17),
+    ("fp32", 256, 48), ("fp16", 97, 31), ("fp16", 4, 4)])
+def test_inplace_identical_to_two_buffers(prec, nx, ny):
+    """After odd and even step counts the populations f(n), the displacement and
+    the stress equal the two-buffer solver's exactly; FP64 matches the oracle."""
+    say(f"inplace {prec} {nx}x{ny}")
+    mat = P.Material.from_shear_poisson(0.8, 0.3)
+    f0, gx, gy = _rand(nx, ny, 11 + nx)
+    a, b = _pair(nx, ny, prec, mat, gx, gy, f0)
+    done = 0
+    for n in (1, 2, 5, 8):  # cumulative 1, 3, 8, 16: odd and even
+        a.step(n)
+        b.step(n)
+        done += n
+        np.testing.assert_array_equal(host(b.populations()), host(a.populations()))
+        for ta, tb in zip(a.displacement(), b.displacement()):
+            np.testing.assert_array_equal(host(tb), host(ta))
+        for ta, tb in zip(a.stress(), b.stress()):
+            np.testing.assert_array_equal(host(tb), host(ta))
+    if prec == "fp64" and nx * ny <= 5000:
+        fn = O.run(f0, gx, gy, omega(mat), done)
+        assert rel_l2(host(b.populations()), fn) <= 1e-12
+
+
+def test_inplace_general_rates():
+    say("inplace general rates")
+    mat = P.Material.from_shear_poisson(0.6, 0.25)
+    f0, gx, gy = _rand(40, 24, 3)
+    a, b = _pair(40, 24, "fp64", mat, gx, gy, f0, rates=(0.3, 1.2, 0.9, 1.1))
+    a.step(9)
+    b.step(9)
+    np.testing.assert_array_equal(host(b.populations()), host(a.populations()))
+
+
+@pytest.mark.parametrize("prec,K", [("fp64", 1), ("fp64", 2), ("fp64", 7), ("fp32", 50),
+                                    ("fp16", 25)])
+def test_inplace_solve_to_tol(prec, K):
+    """Same stop step, residual and state as the two-buffer solver."""
+    say(f"inplace solve {prec} K={K}")
+    c = P.single_32()
+    a, b = _pair(32, 32, prec, c.material, c.gx, c.gy)
+    tol = {"fp64": 1e-10, "fp32": 1e-6, "fp16": 1e-3}[prec]
+    ra = a.solve_to_tol(tol, 20000, K)
+    rb = b.solve_to_tol(tol, 20000, K)
+    assert ra[0] == rb[0] and ra[2] == rb[2]
+    assert rb[1] == pytest.approx(ra[1], rel=1e-12)
+    assert a.steps_done == b.steps_done == ra[0]
+    np.testing.assert_array_equal(host(b.populations()), host(a.populations()))
+    if prec == "fp64":
+        assert ra[0] == 113 or K > 1  # the oracle's stop step at K = 1
+
+
+def test_inplace_max_steps_and_continue():
+    """A capped solve leaves f(max_steps); stepping on and solving again agrees."""
+    say("inplace max steps")
+    c = P.single_32()
+    a, b = _pair(32, 32, "fp64", c.material, c.gx, c.gy)
+    ra = a.solve_to_tol(1e-12, 37, 5)
+    rb = b.solve_to_tol(1e-12, 37, 5)
+    assert ra[0] == rb[0] == 37 and ra[2] == rb[2]
+    a.step(3)
+    b.step(3)
+    ra = a.solve_to_tol(1e-10, 10000, 1)
+    rb = b.solve_to_tol(1e-10, 10000, 1)
+    assert ra[0] == rb[0]
+    np.testing.assert_array_equal(host(b.populations()), host(a.populations()))
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (2, 3), (33, 17)])
+def test_inplace_streaming_bit_exact(nx, ny):
+    """Streaming alone in place equals streaming with two buffers, bit for bit
+    (integer-coded populations), after odd and even step counts."""
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    say(f"inplace streaming {nx}x{ny}")
+    f0 = np.arange(8 * nx * ny, dtype=np.float64).reshape(8, ny, nx)
+    res = []
+    for inplace in (False, True):
+        s = lbm.Solver(nx, ny, "fp64", inplace=inplace)
+        if not inplace:
+            s.set_time_blocking(1)
+        s.set_populations(dev(f0))
+        out = []
+        for n in (1, 1, 3):
+            s.stream_only(n)
+            out.append(host(s.populations()))
+        res.append(out)
+    for x, y in zip(*res):
+        np.testing.assert_array_equal(y, x)
+    np.testing.assert_array_equal(res[1][-1], O.stream_only(f0, 5))
+
+
+def test_inplace_arguments():
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    s = lbm.Solver(16, 16, "fp32", inplace=True)
+    s.set_time_blocking(1)
+    with pytest.raises(lbm.LbmError):
+        s.set_time_blocking(2)
+    with pytest.raises(lbm.LbmError):
+        s.set_fused_kernel("wavefront", 16)
+    with pytest.raises(lbm.LbmError):
+        s.set_polish(1e-6)
+    with pytest.raises(ValueError):
+        lbm.Solver(16, 16, "fp32", with_polish=True, inplace=True)
