@@ -383,9 +383,9 @@ def main():
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(r32["kernel_gbs"] / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic(),
-                     "kernel": "k_stepN<float, 8, 4> (LDS tile 64 x 8 + ring 3): four fused "
-                               "steps per launch, 72 B per site-update algorithmic, 4 x 1024^2 "
-                               "site-updates per launch",
+                     "kernel": "k_stepN<float, 8, 4, 512> (LDS tile 64 x 8 + ring 3, 512 "
+                               "threads): four fused steps per launch, 72 B per site-update "
+                               "algorithmic, 4 x 1024^2 site-updates per launch",
                      "avg_launch_us": round(r32["plain_kernel_avg_us"], 3),
                      "steps_per_launch": STEPS_PER_LAUNCH,
                      "note": "the fused kernel moves the populations through HBM once per four "

@@ -454,8 +454,10 @@ static __global__ __launch_bounds__(kBlock) void k_step(StepLaunch L) {
 // to HBM.  The result is that of NS single steps, with one HBM read and one
 // HBM write of the populations per NS updates.
 //
-// Every thread keeps the same NM sites of the ring region (site e = thread +
-// a * 256, a < NM) in all NS steps, so that step 1 issues all its population
+// NT threads per workgroup (256, or 512 for the short FP32 tiles, which
+// halves each thread's share of a tile's dependent steps).  Every thread keeps
+// the same NM sites of the ring region (site e = thread + a * NT, a < NM) in
+// all NS steps, so that step 1 issues all its population
 // and force loads before it waits once, the force stays in registers, and the
 // later steps touch only LDS until the final store.  Sites past the region
 // (e >= RN) load a valid address and store nothing.
@@ -501,7 +503,7 @@ __device__ __forceinline__ void lds_gather(const S* lds, int r, typename Store<S
 // populations to LDS; returns the scaled force of the thread's sites.  Every
 // slot loads (the last slot's spare lanes re-read the region's last site), so
 // all loads are issued before the first use.
-template <typename S, int TH, int NS>
+template <typename S, int TH, int NS, int NT = kBlock>
 __device__ __forceinline__ void stepN_first(const S* __restrict__ src,
                                             const typename Store<S>::C* __restrict__ g,
                                             long long plane, int nx, int ny, int x0, int y0,
@@ -510,11 +512,11 @@ __device__ __forceinline__ void stepN_first(const S* __restrict__ src,
     using C = typename Store<S>::C;
     constexpr int R = NS - 1;
     constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
-    constexpr int NM = (RN + kBlock - 1) / kBlock;
+    constexpr int NM = (RN + NT - 1) / NT;
     C f[NM][8];
 #pragma unroll
     for (int a = 0; a < NM; ++a) {
-        const int e = min((int)threadIdx.x + a * kBlock, RN - 1);
+        const int e = min((int)threadIdx.x + a * NT, RN - 1);
         const int i = e % RW, j = e / RW;
         const int xw = wrap_coord(x0 - R + i, nx), yw = wrap_coord(y0 - R + j, ny);
         gather<S>(src, plane, nx, ny, xw, yw, f[a]);
@@ -524,7 +526,7 @@ __device__ __forceinline__ void stepN_first(const S* __restrict__ src,
     }
 #pragma unroll
     for (int a = 0; a < NM; ++a) {
-        const int e = (int)threadIdx.x + a * kBlock;
+        const int e = (int)threadIdx.x + a * NT;
         gx[a] *= k.gscale;
         gy[a] *= k.gscale;
         C ux, uy;
@@ -536,12 +538,12 @@ __device__ __forceinline__ void stepN_first(const S* __restrict__ src,
     }
 }
 
-template <typename S, int TH, int NS>
-static __global__ __launch_bounds__(kBlock) void k_stepN(StepLaunch L) {
+template <typename S, int TH, int NS, int NT = kBlock>
+static __global__ __launch_bounds__(NT) void k_stepN(StepLaunch L) {
     using C = typename Store<S>::C;
     constexpr int R = NS - 1;  // ring width of the first step
     constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
-    constexpr int NM = (RN + kBlock - 1) / kBlock;  // ring sites per thread
+    constexpr int NM = (RN + NT - 1) / NT;  // ring sites per thread
     __shared__ S lds[8 * RN];
     int last, stride, it;
     xcd_slice(L.range, last, stride, it);
@@ -559,14 +561,14 @@ static __global__ __launch_bounds__(kBlock) void k_stepN(StepLaunch L) {
         const int x0 = item.tx * kTW, y0 = item.ty * TH;
         C f[NM][8], gx[NM], gy[NM];
         // step 1: tile + ring R, HBM -> LDS
-        stepN_first<S, TH, NS>(src, g, plane, nx, ny, x0, y0, k, lds, gx, gy);
+        stepN_first<S, TH, NS, NT>(src, g, plane, nx, ny, x0, y0, k, lds, gx, gy);
         __syncthreads();
         // middle steps: ring R - m, LDS -> registers -> LDS (in place)
 #pragma unroll
         for (int m = 1; m < R; ++m) {
 #pragma unroll
             for (int a = 0; a < NM; ++a) {
-                const int e = (int)threadIdx.x + a * kBlock;
+                const int e = (int)threadIdx.x + a * NT;
                 const int i = e % RW, j = e / RW;
                 if (e < RN && i >= m && i < RW - m && j >= m && j < RH - m)
                     lds_gather<S, RW, RN>(lds, e, f[a]);
@@ -574,7 +576,7 @@ static __global__ __launch_bounds__(kBlock) void k_stepN(StepLaunch L) {
             __syncthreads();
 #pragma unroll
             for (int a = 0; a < NM; ++a) {
-                const int e = (int)threadIdx.x + a * kBlock;
+                const int e = (int)threadIdx.x + a * NT;
                 const int i = e % RW, j = e / RW;
                 if (e < RN && i >= m && i < RW - m && j >= m && j < RH - m) {
                     C ux, uy;
@@ -588,7 +590,7 @@ static __global__ __launch_bounds__(kBlock) void k_stepN(StepLaunch L) {
         // last step: the tile, LDS -> HBM
 #pragma unroll
         for (int a = 0; a < NM; ++a) {
-            const int e = (int)threadIdx.x + a * kBlock;
+            const int e = (int)threadIdx.x + a * NT;
             const int i = e % RW, j = e / RW;
             const int x = x0 + i - R, y = y0 + j - R;
             if (e < RN && i >= R && i < R + kTW && j >= R && j < R + TH && x < nx && y < ny) {
