@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-oracle-only", action="store_true",
+                    help="time the CPU oracle only (no GPU) and print its JSON")
     ap.add_argument("--large-only", default="",
                     help="comma list of precisions: run only the 8192^2 leg (for profiling)")
     ap.add_argument("--large-steps", type=int, default=10000)
@@ -321,8 +323,25 @@ def cpu_baseline(seconds: float):
                       f"{dt:.1f} s, FP64, OpenMP over rows"}
 
 
+def cpu_baseline_one_thread(seconds: float):
+    """The same oracle sample on one thread, in a child process (OpenMP reads
+    its thread count at start-up)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-oracle-only",
+                        "--cpu-seconds", str(seconds)], env=env, capture_output=True, text=True,
+                       timeout=seconds * 10 + 120)
+    if r.returncode != 0:
+        return {"error": r.stderr[-300:]}
+    rec = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value": rec["value"], "unit": rec["unit"], "cores": 1, "sample": rec["sample"]}
+
+
 def main():
     args = parse()
+    if args.cpu_oracle_only:
+        print(json.dumps(cpu_baseline(args.cpu_seconds)), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                           "(the multi-GPU decomposition is a design note, not built)"}))
@@ -449,6 +468,8 @@ def main():
         out["serving_sustained"] = serving_run(rate=sustain, window=15.0, budget=30.0)
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        log("CPU oracle baseline, one thread")
+        out["cpu_baseline"]["one_thread"] = cpu_baseline_one_thread(min(6.0, args.cpu_seconds))
         out["paper_context"] = {"mlups": 0.25, "note": "derived from ~1.6 s for ~1e3 steps of "
                                 "20x20 on a low-end notebook (Sec. 7.3.1); other hardware"}
     print(json.dumps(out), flush=True)
