@@ -29,12 +29,14 @@ DEFAULT_CACHE = os.environ.get("LBM_AUTOTUNE_CACHE",
                                             "lbm_elastic_autotune.json"))
 
 
-def candidates(nx: int, min_bx: int = 3, ny: int = 0, wavefront: bool = False) -> List[Shape]:
+def candidates(nx: int, min_bx: int = 3, ny: int = 0, wavefront: bool = False,
+               fused: bool = True) -> List[Shape]:
     """Single-step tile shapes, the fused LDS tile kernel (whose tile is fixed)
     with one workgroup per tile or a persistent grid, and (single lattices) the
-    register wavefront with a few segment heights."""
-    out = [(6, 4, k, t, 0) for t in (4, 3, 2) for k in (0, 4)]
-    if wavefront:
+    register wavefront with a few segment heights; single-step shapes only for
+    in-place solvers (fused=False)."""
+    out = [(6, 4, k, t, 0) for t in (4, 3, 2) for k in (0, 4)] if fused else []
+    if wavefront and fused:
         for rows in (32, 64, 128, 256):
             if rows <= max(ny, 32):
                 out += [(6, 4, 0, t, rows) for t in (4, 3)]
@@ -50,7 +52,7 @@ def candidates(nx: int, min_bx: int = 3, ny: int = 0, wavefront: bool = False) -
 def _apply(obj, shp: Shape):
     obj.set_time_blocking(shp[3])
     obj.set_tile(shp[0], shp[1], shp[2])
-    if hasattr(obj, "set_fused_kernel"):
+    if hasattr(obj, "set_fused_kernel") and not getattr(obj, "inplace", False):
         if shp[4] > 0:
             obj.set_fused_kernel("wavefront", shp[4])
         else:
@@ -120,14 +122,16 @@ def tune_solver(solver, precision: str, cache_path: Optional[str] = DEFAULT_CACH
                 force: bool = False) -> Shape:
     """Pick and apply the fastest launch shape for a single-lattice solver."""
     sites = solver.nx * solver.ny
-    key = _key("single", precision, sites)
+    inplace = getattr(solver, "inplace", False)
+    key = _key("single-inplace" if inplace else "single", precision, sites)
     cache = _load(cache_path) if cache_path else {}
     if not force and key in cache:
         shp = tuple(cache[key])
         _apply(solver, shp)
         return shp
     res = time_shapes(lambda s: _apply(solver, s), solver.step,
-                      candidates(solver.nx, 0, solver.ny, wavefront=True), sites)
+                      candidates(solver.nx, 0, solver.ny, wavefront=True, fused=not inplace),
+                      sites)
     shp = res[0][1]
     _apply(solver, shp)
     if cache_path:

@@ -40,3 +40,17 @@ def test_tune_batch(tmp_path):
     shp = autotune.tune_batch(b, "fp32", sum(c.nx * c.ny for c in cases),
                               cache_path=str(tmp_path / "t.json"))
     assert shp in autotune.candidates(64, 3)
+
+
+def test_tune_inplace_solver(tmp_path):
+    """In-place solvers are tuned over single-step shapes only."""
+    say("autotune in-place solver 128x96 fp32")
+    need_gpu()
+    from paper_2208_14870_amd import autotune, lbm
+    c = P.single_1024(0.3, 1, 1, n=128)
+    s = lbm.Solver(128, 128, "fp32", inplace=True)
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    shp = autotune.tune_solver(s, "fp32", cache_path=str(tmp_path / "t.json"))
+    assert shp in autotune.candidates(128, 0, 128, wavefront=True, fused=False)
+    assert shp[3] == 1 and shp[4] == 0
