@@ -113,8 +113,9 @@ STEPS_PER_LAUNCH = 4  # library default for FP32/FP64: plain steps run four per 
 
 
 def run_workload(solvers, nchunks, chunk):
-    """nchunks x (chunk steps per lattice: plain steps, then the residual check
-    pair, then displacement + error norms).  Returns timing and last metrics."""
+    """nchunks x (chunk steps per lattice: plain steps, then the two steps that end
+    in the residual check, then displacement + error norms).  Returns timing and
+    last metrics."""
     import torch
     ev = []
     last = []

@@ -135,8 +135,10 @@ struct lbm_solver {
         return hipGetLastError();
     }
 
-    // Launches for `nplain` plain steps (pairs through the fused kernel when
-    // enabled), then optionally a writeU step and a check step + finalize.
+    // Launches for `nplain` plain steps (groups of L.tb through the fused kernel
+    // when enabled, the remainder one per launch), then optionally a writeU step
+    // and a residual check (a check step, or in place a launch without a step)
+    // + finalize.
     hipError_t enqueue_seq(long long nplain, bool writeu, bool check, hipStream_t st,
                            long long& ph) {
         hipError_t e = hipSuccess;
