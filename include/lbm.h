@@ -95,7 +95,10 @@ int lbm_create(int nx, int ny, int precision, int with_polish, void *workspace,
  * and every memory location is touched by one site only, so one buffer
  * suffices and the bytes per site-update are those of lbm_step; the
  * population footprint halves (about twice the lattice per GPU).  Results are
- * identical to the two-buffer solver (bit for bit in every precision).  Same
+ * identical to the two-buffer solver bit for bit, with one qualification for
+ * FP16 storage: lbm_solve_to_tol may rescale the half storage one step earlier
+ * or later than the two-buffer solver, which changes the rounding of
+ * subnormal halves only.  Same
  * handle and entry points, with these differences: one step per launch
  * (lbm_set_time_blocking accepts only 1, lbm_set_fused_kernel returns
  * LBM_E_STATE), no polish phase, and lbm_solve_to_tol evaluates its residual
