@@ -86,6 +86,8 @@ def parse():
                     help="time the CPU oracle only (no GPU) and print its JSON")
     ap.add_argument("--large-only", default="",
                     help="comma list of precisions: run only the 8192^2 leg (for profiling)")
+    ap.add_argument("--inplace-only", action="store_true",
+                    help="run only the in-place vs two-buffer leg (for profiling)")
     ap.add_argument("--large-steps", type=int, default=10000)
     ap.add_argument("--large-warm", type=int, default=200)
     return ap.parse_args()
@@ -352,6 +354,12 @@ def main():
     lbm.load()
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
+    if args.inplace_only:
+        if args.calib_copy:
+            calib_copy()
+        print(json.dumps({"inplace_8192": inplace_run(steps=args.large_steps,
+                                                      warm=args.large_warm)}), flush=True)
+        return
     if args.large_only:
         if args.calib_copy:
             calib_copy()
