@@ -62,7 +62,7 @@ def test_batch_residual_matches_single_solver_and_oracle():
     assert r[s] == pytest.approx(want, rel=1e-9)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "fp16"])
 def test_alone_vs_mix_identical(prec):
     """A lattice gives bit-identical displacement and residual alone and in a mix."""
     say(f"batch alone vs mix {prec}")
@@ -85,6 +85,28 @@ def test_alone_vs_mix_identical(prec):
     np.testing.assert_array_equal(u1[0], u2[0])
     np.testing.assert_array_equal(u1[1], u2[1])
     assert r1[s1] == r2[ids[probe.label]]
+
+
+def test_mixed_precisions_match_single_solvers():
+    """One batch holding FP64, FP32 and FP16 lattices (each precision its own
+    launch per step) gives every lattice the displacement of a single-lattice
+    solver of the same precision, bit for bit."""
+    say("batch mixed precisions vs single solvers")
+    from paper_2208_14870_amd import lbm
+    cases = _cases()
+    precs = ["fp64", "fp32", "fp16", "fp32", "fp16", "fp64"]
+    b = _batch()
+    slots = [b.add(c.nx, c.ny, c.material.lame_lambda, c.material.lame_mu, dev(c.gx), dev(c.gy),
+                   p) for c, p in zip(cases, precs)]
+    b.step(37)
+    for c, p, sl in zip(cases, precs, slots):
+        s = lbm.Solver(c.nx, c.ny, p)
+        s.set_material(c.material.lame_lambda, c.material.lame_mu)
+        s.set_body_force(dev(c.gx), dev(c.gy))
+        s.step(37)
+        for a, t in zip(b.displacement(sl), s.displacement()):
+            np.testing.assert_array_equal(host(a), host(t), err_msg=f"{p} {c.label}")
+        s.close()
 
 
 def test_join_and_leave_mid_run():
