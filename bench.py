@@ -121,10 +121,11 @@ def run_workload(solvers, nchunks, chunk):
     import torch
     ev = []
     last = []
+    history = []  # residual of the first case after every chunk
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(nchunks):
-        for s, (ux, uy) in solvers:
+        for i, (s, (ux, uy)) in enumerate(solvers):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
@@ -133,7 +134,9 @@ def run_workload(solvers, nchunks, chunk):
             ev.append((e0, e1))
             n, r, st = s.solve_to_tol(0.0, 2, 2)  # two steps ending in the residual check
             err = s.error_norms(ux, uy)  # displacement extraction + FP64 norms
-            last.append((r, err["rel_l2"]))
+            last.append((r, err["rel_l2"], err["rel_linf"]))
+            if i == 0:
+                history.append(r)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     plain_ms = sum(a.elapsed_time(b) for a, b in ev)
@@ -141,7 +144,7 @@ def run_workload(solvers, nchunks, chunk):
     plain_launches = len(ev) * (per // STEPS_PER_LAUNCH + per % STEPS_PER_LAUNCH)
     return {"wall_s": wall, "plain_kernel_avg_us": 1e3 * plain_ms / plain_launches,
             "plain_us_per_step": 1e3 * plain_ms / (len(ev) * per),
-            "last": last[-len(solvers):]}
+            "last": last[-len(solvers):], "history": history}
 
 
 def large_lattice(steps=10000, warm=200, precs=("fp64", "fp32", "fp16")):
@@ -422,6 +425,8 @@ def main():
                              "HBM-resident figures are under large_8192"},
         "fp32_last_residual": r32["last"][0][0],
         "fp32_rel_l2_vs_manufactured": [round(x[1], 6) for x in r32["last"]],
+        "fp32_rel_linf_vs_manufactured": [round(x[2], 6) for x in r32["last"]],
+        "fp32_residual_history_case0": [float("%.4g" % r) for r in r32["history"]],
     }
     tr = out["roofline"]["traffic"]
     if tr:
