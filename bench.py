@@ -50,8 +50,9 @@ def measured_traffic():
     except (OSError, ValueError):
         return None
     h = hashlib.sha256()
-    for f in ("paper_2208_14870_amd/csrc/lbm_device.hpp", "paper_2208_14870_amd/csrc/lbm_host.hpp"):
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+    csrc = os.path.join(ROOT, "paper_2208_14870_amd", "csrc")
+    for f in sorted(x for x in os.listdir(csrc) if x.endswith(".hpp")):  # kernels + launch code
+        h.update(open(os.path.join(csrc, f), "rb").read())
     if h.hexdigest() != rec.get("source_sha256"):
         return None
     return rec["traffic_bytes_per_launch"]

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
 SOURCES = [os.path.join(CSRC, "lbm_capi.hip"), os.path.join(CSRC, "lbm_batch.hip")]
-HEADERS = [os.path.join(CSRC, "lbm_device.hpp"), os.path.join(ROOT, "include", "lbm.h")]
+HEADERS = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")) + [
+    os.path.join(ROOT, "include", "lbm.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,392 @@
+// Temporal blocking: several steps per launch through an LDS tile or a
+// register wavefront, bit-identical to single steps.
+#pragma once
+
+#include "lbm_common.hpp"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// NS fused steps per launch (temporal blocking)
+// ---------------------------------------------------------------------------
+// A workgroup owns an output tile of 64 x TH sites.  Step 1 advances the tile
+// plus a ring of NS-1 sites (periodic coordinates) from the stored field in
+// HBM and keeps the post-collision populations in LDS, rounded to the storage
+// type exactly as a store to HBM would; each middle step gathers from LDS into
+// registers, waits for the whole workgroup, collides and writes back in place
+// on a ring one site narrower; the last step advances the tile and writes it
+// to HBM.  The result is that of NS single steps, with one HBM read and one
+// HBM write of the populations per NS updates.
+//
+// NT threads per workgroup (256, or 512 for the short FP32 tiles, which
+// halves each thread's share of a tile's dependent steps).  Every thread keeps
+// the same NM sites of the ring region (site e = thread + a * NT, a < NM) in
+// all NS steps, so that step 1 issues all its population
+// and force loads before it waits once, the force stays in registers, and the
+// later steps touch only LDS until the final store.  Sites past the region
+// (e >= RN) load a valid address and store nothing.
+constexpr int kTW = 64;  // tile width of the fused kernel (the work list uses 2^6 columns)
+
+// LDS copies of the intermediate populations are held in the storage type.
+template <typename S>
+__device__ __forceinline__ typename Store<S>::C lds_ld(const S* p) {
+    return (typename Store<S>::C)(*p);
+}
+template <>
+__device__ __forceinline__ float lds_ld<__half>(const __half* p) { return __half2float(*p); }
+template <typename S>
+__device__ __forceinline__ void lds_st(S* p, typename Store<S>::C v) { *p = (S)v; }
+template <>
+__device__ __forceinline__ void lds_st<__half>(__half* p, float v) { *p = __float2half_rn(v); }
+
+__device__ __forceinline__ int wrap_coord(int v, int n) {
+    if (v < 0) v += n;
+    if (v < 0) v = ((v % n) + n) % n;
+    if (v >= n) {
+        v -= n;
+        if (v >= n) v %= n;
+    }
+    return v;
+}
+
+// Gather of the 8 populations arriving at LDS position r (row stride RW).
+template <typename S, int RW, int RN>
+__device__ __forceinline__ void lds_gather(const S* lds, int r, typename Store<S>::C f[8]) {
+    f[0] = lds_ld<S>(lds + 0 * RN + r - 1);       // c1 = ( 1, 0)
+    f[1] = lds_ld<S>(lds + 1 * RN + r - RW);      // c2 = ( 0, 1)
+    f[2] = lds_ld<S>(lds + 2 * RN + r + 1);       // c3 = (-1, 0)
+    f[3] = lds_ld<S>(lds + 3 * RN + r + RW);      // c4 = ( 0,-1)
+    f[4] = lds_ld<S>(lds + 4 * RN + r - RW - 1);  // c5 = ( 1, 1)
+    f[5] = lds_ld<S>(lds + 5 * RN + r - RW + 1);  // c6 = (-1, 1)
+    f[6] = lds_ld<S>(lds + 6 * RN + r + RW + 1);  // c7 = (-1,-1)
+    f[7] = lds_ld<S>(lds + 7 * RN + r + RW - 1);  // c8 = ( 1,-1)
+}
+
+// Step 1 of the fused kernel for one tile: gathers the ring region from the
+// stored field (periodic coordinates), collides, and writes the post-collision
+// populations to LDS; returns the scaled force of the thread's sites.  Every
+// slot loads (the last slot's spare lanes re-read the region's last site), so
+// all loads are issued before the first use.
+template <typename S, int TH, int NS, int NT = kBlock>
+__device__ __forceinline__ void stepN_first(const S* __restrict__ src,
+                                            const typename Store<S>::C* __restrict__ g,
+                                            long long plane, int nx, int ny, int x0, int y0,
+                                            const Coef<typename Store<S>::C>& k, S* lds,
+                                            typename Store<S>::C gx[], typename Store<S>::C gy[]) {
+    using C = typename Store<S>::C;
+    constexpr int R = NS - 1;
+    constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
+    constexpr int NM = (RN + NT - 1) / NT;
+    C f[NM][8];
+#pragma unroll
+    for (int a = 0; a < NM; ++a) {
+        const int e = min((int)threadIdx.x + a * NT, RN - 1);
+        const int i = e % RW, j = e / RW;
+        const int xw = wrap_coord(x0 - R + i, nx), yw = wrap_coord(y0 - R + j, ny);
+        gather<S>(src, plane, nx, ny, xw, yw, f[a]);
+        const long long sidx = (long long)yw * nx + xw;
+        gx[a] = glob(g)[sidx];
+        gy[a] = glob(g)[plane + sidx];
+    }
+#pragma unroll
+    for (int a = 0; a < NM; ++a) {
+        const int e = (int)threadIdx.x + a * NT;
+        gx[a] *= k.gscale;
+        gy[a] *= k.gscale;
+        C ux, uy;
+        collide<C, false>(f[a], gx[a], gy[a], k, ux, uy);
+        if (e < RN) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) lds_st<S>(lds + q * RN + e, f[a][q]);
+        }
+    }
+}
+
+template <typename S, int TH, int NS, int NT = kBlock>
+static __global__ __launch_bounds__(NT) void k_stepN(StepLaunch L) {
+    using C = typename Store<S>::C;
+    constexpr int R = NS - 1;  // ring width of the first step
+    constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
+    constexpr int NM = (RN + NT - 1) / NT;  // ring sites per thread
+    __shared__ S lds[8 * RN];
+    int last, stride, it;
+    xcd_slice(L.range, last, stride, it);
+    for (; it < last; it += stride) {
+        const Item item = L.items[it];
+        const SlotDesc& d = L.slots[item.slot];
+        const int nx = d.nx, ny = d.ny;
+        const long long plane = d.plane;
+        const int sel = d.cur ^ L.flip;
+        const S* __restrict__ src = reinterpret_cast<const S*>(d.buf[sel]);
+        S* __restrict__ dst = reinterpret_cast<S*>(d.buf[sel ^ 1]);
+        const C* __restrict__ g = reinterpret_cast<const C*>(d.g);
+        Coef<C> k;
+        k.load(d);
+        const int x0 = item.tx * kTW, y0 = item.ty * TH;
+        C f[NM][8], gx[NM], gy[NM];
+        // step 1: tile + ring R, HBM -> LDS
+        stepN_first<S, TH, NS, NT>(src, g, plane, nx, ny, x0, y0, k, lds, gx, gy);
+        __syncthreads();
+        // middle steps: ring R - m, LDS -> registers -> LDS (in place)
+#pragma unroll
+        for (int m = 1; m < R; ++m) {
+#pragma unroll
+            for (int a = 0; a < NM; ++a) {
+                const int e = (int)threadIdx.x + a * NT;
+                const int i = e % RW, j = e / RW;
+                if (e < RN && i >= m && i < RW - m && j >= m && j < RH - m)
+                    lds_gather<S, RW, RN>(lds, e, f[a]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < NM; ++a) {
+                const int e = (int)threadIdx.x + a * NT;
+                const int i = e % RW, j = e / RW;
+                if (e < RN && i >= m && i < RW - m && j >= m && j < RH - m) {
+                    C ux, uy;
+                    collide<C, false>(f[a], gx[a], gy[a], k, ux, uy);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) lds_st<S>(lds + q * RN + e, f[a][q]);
+                }
+            }
+            __syncthreads();
+        }
+        // last step: the tile, LDS -> HBM
+#pragma unroll
+        for (int a = 0; a < NM; ++a) {
+            const int e = (int)threadIdx.x + a * NT;
+            const int i = e % RW, j = e / RW;
+            const int x = x0 + i - R, y = y0 + j - R;
+            if (e < RN && i >= R && i < R + kTW && j >= R && j < R + TH && x < nx && y < ny) {
+                lds_gather<S, RW, RN>(lds, e, f[a]);
+                C ux, uy;
+                collide<C, false>(f[a], gx[a], gy[a], k, ux, uy);
+                const long long sidx = (long long)y * nx + x;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * plane + sidx, f[a][q]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// NS fused steps per launch, register wavefront
+// ---------------------------------------------------------------------------
+// One wave owns a strip of 64 V columns (V adjacent columns per lane): W
+// output columns plus R ring columns per side, and marches up a segment of
+// rows.  At row t it loads the stored field's row t (level 0) and advances
+// level k = 1..NS at row t - k from level k-1's rows t-k-1, t-k, t-k+1, which
+// it keeps in registers: the y neighbours are earlier rows of the same lane,
+// the x neighbours are the lane's other column or, across lanes, come through
+// a whole-wave DPP shift.  Level NS is stored.  Each level loses one valid
+// column per side, so after NS <= R levels the W middle columns hold the
+// output.  No LDS and no barrier; every intermediate level is rounded to the
+// storage type exactly as a store would round it, so the result equals NS
+// single steps bit for bit.  V = 2 (FP32, FP16) needs an even nx, so that a
+// lane's column pair stays adjacent across the periodic wrap; its ring is 4
+// columns for every NS so that pairs stay aligned.
+__device__ __forceinline__ float lane_from_left(float v) {  // lane l <- lane l-1
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_from_right(float v) {  // lane l <- lane l+1
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double lane_from_left(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_from_right(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// value as the storage type would hold it
+template <typename S>
+__device__ __forceinline__ typename Store<S>::C as_stored(typename Store<S>::C v) { return v; }
+template <>
+__device__ __forceinline__ float as_stored<__half>(float v) { return __half2float(__float2half_rn(v)); }
+
+// V consecutive storage elements as arithmetic values (one vector access).
+template <typename S, int V> struct VecIO;
+template <typename S> struct VecIO<S, 1> {
+    using C = typename Store<S>::C;
+    __device__ static __forceinline__ void ld(const S* p, C o[1]) { o[0] = Store<S>::ld(p); }
+    __device__ static __forceinline__ void st(S* p, const C v[1]) { Store<S>::st(p, v[0]); }
+};
+typedef float wf2 __attribute__((ext_vector_type(2)));
+template <> struct VecIO<float, 2> {
+    __device__ static __forceinline__ void ld(const float* p, float o[2]) {
+        const wf2 v = __builtin_nontemporal_load(glob(reinterpret_cast<const wf2*>(p)));
+        o[0] = v.x;
+        o[1] = v.y;
+    }
+    __device__ static __forceinline__ void st(float* p, const float v[2]) {
+        wf2 w;
+        w.x = v[0];
+        w.y = v[1];
+        __builtin_nontemporal_store(w, glob(reinterpret_cast<wf2*>(p)));
+    }
+};
+template <> struct VecIO<__half, 2> {
+    __device__ static __forceinline__ void ld(const __half* p, float o[2]) {
+        const unsigned u = __builtin_nontemporal_load(glob(reinterpret_cast<const unsigned*>(p)));
+        o[0] = __half2float(__ushort_as_half((unsigned short)(u & 0xffffu)));
+        o[1] = __half2float(__ushort_as_half((unsigned short)(u >> 16)));
+    }
+    __device__ static __forceinline__ void st(__half* p, const float v[2]) {
+        const unsigned u = (unsigned)__half_as_ushort(__float2half_rn(v[0])) |
+                           ((unsigned)__half_as_ushort(__float2half_rn(v[1])) << 16);
+        __builtin_nontemporal_store(u, glob(reinterpret_cast<unsigned*>(p)));
+    }
+};
+
+template <int NS, int V>
+__host__ __device__ constexpr int wave_ring() { return V == 1 ? NS : 4; }
+template <int NS, int V>
+__host__ __device__ constexpr int wave_width() { return kWave * V - 2 * wave_ring<NS, V>(); }
+
+struct WaveLaunch {
+    const SlotDesc* slots;
+    int flip;
+    int strips, segs, hs;  // strips of W output columns, segments of hs rows
+};
+
+template <typename S, int NS, int V>
+static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
+    using C = typename Store<S>::C;
+    constexpr int R = wave_ring<NS, V>();
+    constexpr int W = wave_width<NS, V>();
+    constexpr int PF = 3;  // rows loaded ahead
+    // wave index as a scalar: the row loop and the row bases stay scalar
+    const int wid = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlock / kWave) +
+                                                   (int)(threadIdx.x >> 6));
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    if (wid >= L.strips * L.segs) return;  // whole waves leave; no barrier follows
+    const SlotDesc& d = L.slots[0];
+    const int nx = d.nx, ny = d.ny;
+    const long long plane = d.plane;
+    const int sel = d.cur ^ L.flip;
+    const S* __restrict__ src = reinterpret_cast<const S*>(d.buf[sel]);
+    S* __restrict__ dst = reinterpret_cast<S*>(d.buf[sel ^ 1]);
+    const C* __restrict__ g = reinterpret_cast<const C*>(d.g);
+    Coef<C> k;
+    k.load(d);
+    const int sx = wid % L.strips, sy = wid / L.strips;
+    const int xs = sx * W, ya = sy * L.hs, yb = min(ya + L.hs, ny);
+    const int x = xs - R + V * lane;  // first column of this lane
+    const int xw = wrap_coord(x, nx);
+    const bool out_lane = lane >= R / V && lane < (R + W) / V && x < nx;
+    // loads of row t: scalar row base + per-lane byte offset of the column
+    const unsigned xs_b = (unsigned)xw * (unsigned)sizeof(S), xg_b = (unsigned)xw * (unsigned)sizeof(C);
+    auto load_row = [&](int t, C (*a)[V], C (*gg)[V]) {
+        const long long r = (long long)wrap_coord(t, ny) * nx;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            VecIO<S, V>::ld(reinterpret_cast<const S*>(
+                                reinterpret_cast<const char*>(src + (q * plane + r)) + xs_b),
+                            a[q]);
+        VecIO<C, V>::ld(reinterpret_cast<const C*>(reinterpret_cast<const char*>(g + r) + xg_b), gg[0]);
+        VecIO<C, V>::ld(reinterpret_cast<const C*>(reinterpret_cast<const char*>(g + (plane + r)) + xg_b),
+                        gg[1]);
+    };
+    C A0[6][8][V];      // level 0 rows by iteration mod 6 (three back, three ahead)
+    C Gp[6][2][V];      // force rows, same slots
+    C A[NS][3][8][V];   // levels 1..NS-1 (index 0 unused), rows mod 3
+    C G[NS + 1][2][V];  // force of rows t, t-1, ..., t-NS
+#pragma unroll
+    for (int j = 0; j <= NS; ++j)
+#pragma unroll
+        for (int c = 0; c < V; ++c) G[j][0][c] = G[j][1][c] = C(0);
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int c = 0; c < V; ++c) A0[r][q][c] = C(0);
+#pragma unroll
+    for (int lv = 0; lv < NS; ++lv)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int c = 0; c < V; ++c) A[lv][r][q][c] = C(0);
+    const int t_first = ya - NS;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) load_row(t_first + u, A0[u], Gp[u]);
+    for (int t0 = t_first; t0 < yb + NS; t0 += 6) {
+#pragma unroll
+        for (int u = 0; u < 6; ++u) {
+            const int t = t0 + u;
+            load_row(t + PF, A0[(u + PF) % 6], Gp[(u + PF) % 6]);
+#pragma unroll
+            for (int j = NS; j > 0; --j)
+#pragma unroll
+                for (int c = 0; c < V; ++c) {
+                    G[j][0][c] = G[j - 1][0][c];
+                    G[j][1][c] = G[j - 1][1][c];
+                }
+#pragma unroll
+            for (int c = 0; c < V; ++c) {
+                G[0][0][c] = Gp[u][0][c] * k.gscale;
+                G[0][1][c] = Gp[u][1][c] * k.gscale;
+            }
+#pragma unroll
+            for (int lv = 1; lv <= NS; ++lv) {
+                // level lv-1 rows t-lv+1 (this iteration), t-lv, t-lv-1
+                const C(*R0)[V] = lv == 1 ? A0[u] : A[lv - 1][u % 3];
+                const C(*R1)[V] = lv == 1 ? A0[(u + 5) % 6] : A[lv - 1][(u + 2) % 3];
+                const C(*R2)[V] = lv == 1 ? A0[(u + 4) % 6] : A[lv - 1][(u + 1) % 3];
+                // value of population q at column c - 1 / c + 1 of a row
+                auto left = [&](const C(*row)[V], int q, int c) {
+                    return c > 0 ? row[q][c - 1] : lane_from_left(row[q][V - 1]);
+                };
+                auto right = [&](const C(*row)[V], int q, int c) {
+                    return c < V - 1 ? row[q][c + 1] : lane_from_right(row[q][0]);
+                };
+                C f[V][8];
+#pragma unroll
+                for (int c = 0; c < V; ++c) {
+                    f[c][0] = left(R1, 0, c);   // c1 = ( 1, 0) from (x-1, y)
+                    f[c][1] = R2[1][c];         // c2 = ( 0, 1) from (x, y-1)
+                    f[c][2] = right(R1, 2, c);  // c3 = (-1, 0) from (x+1, y)
+                    f[c][3] = R0[3][c];         // c4 = ( 0,-1) from (x, y+1)
+                    f[c][4] = left(R2, 4, c);   // c5 = ( 1, 1) from (x-1, y-1)
+                    f[c][5] = right(R2, 5, c);  // c6 = (-1, 1) from (x+1, y-1)
+                    f[c][6] = right(R0, 6, c);  // c7 = (-1,-1) from (x+1, y+1)
+                    f[c][7] = left(R0, 7, c);   // c8 = ( 1,-1) from (x-1, y+1)
+                }
+#pragma unroll
+                for (int c = 0; c < V; ++c) {
+                    C ux, uy;
+                    collide<C, false>(f[c], G[lv][0][c], G[lv][1][c], k, ux, uy);
+                }
+                if (lv < NS) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+#pragma unroll
+                        for (int c = 0; c < V; ++c) A[lv][u % 3][q][c] = as_stored<S>(f[c][q]);
+                } else {
+                    const int y = t - NS;
+                    if (out_lane && y >= ya && y < yb) {
+                        const long long o = (long long)y * nx + x;
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            C v[V];
+#pragma unroll
+                            for (int c = 0; c < V; ++c) v[c] = f[c][q];
+                            VecIO<S, V>::st(dst + q * plane + o, v);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+}  // namespace lbm

@@ -1,0 +1,290 @@
+// Per-lattice helper kernels: extraction of u, stress and populations,
+// conversions, FP64 norms, the work list and the neutral-mode reset.
+#pragma once
+
+#include "lbm_common.hpp"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// per-lattice helpers (1 thread per site)
+// ---------------------------------------------------------------------------
+
+// u(n) = bared first moments of f(n) (read from the stored field in its
+// layout), FP64 and unscaled (Table "solution").
+template <typename S>
+static __global__ __launch_bounds__(kBlock) void k_extract_u(SlotDesc d, int sel, int layout,
+                                                             double* ux, double* uy) {
+    using C = typename Store<S>::C;
+    const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= (long long)d.nx * d.ny) return;
+    const int x = (int)(s % d.nx), y = (int)(s / d.nx);
+    C f[8];
+    load_state<S>(reinterpret_cast<const S*>(d.buf[sel]), d.plane, d.nx, d.ny, x, y, layout, f);
+    const C* g = reinterpret_cast<const C*>(d.g);
+    const double m10 = (double)((f[0] - f[2]) + ((f[4] - f[6]) - (f[5] - f[7])));
+    const double m01 = (double)((f[1] - f[3]) + ((f[4] - f[6]) + (f[5] - f[7])));
+    const double gsc = d.gscale;
+    ux[s] = (m10 + 0.5 * (double)g[s] * gsc) * d.inv_scale;
+    uy[s] = (m01 + 0.5 * (double)g[d.plane + s] * gsc) * d.inv_scale;
+}
+
+// Stress from the bared second-order moments of f(n) (Eq. compute_bared with
+// zero equilibria, Table "solution" in lattice units): sxx = -(mb_s + mb_d)/2,
+// syy = -(mb_s - mb_d)/2, sxy = -mb_11, mb = (1 - omega/2) m.
+template <typename S>
+static __global__ __launch_bounds__(kBlock) void k_extract_stress(SlotDesc d, int sel, int layout,
+                                                                  double bs, double bd, double b11,
+                                                                  double* sxx, double* syy,
+                                                                  double* sxy) {
+    using C = typename Store<S>::C;
+    const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= (long long)d.nx * d.ny) return;
+    const int x = (int)(s % d.nx), y = (int)(s / d.nx);
+    C f[8];
+    load_state<S>(reinterpret_cast<const S*>(d.buf[sel]), d.plane, d.nx, d.ny, x, y, layout, f);
+    const double h13 = (double)f[0] + (double)f[2], h24 = (double)f[1] + (double)f[3];
+    const double sac = (double)f[4] + (double)f[6], sbd = (double)f[5] + (double)f[7];
+    const double ms = (h13 + h24) + 2.0 * (sac + sbd);
+    const double md = h13 - h24;
+    const double m11 = sac - sbd;
+    const double mbs = bs * ms, mbd = bd * md, mb11 = b11 * m11;
+    sxx[s] = -0.5 * (mbs + mbd) * d.inv_scale;
+    syy[s] = -0.5 * (mbs - mbd) * d.inv_scale;
+    sxy[s] = -mb11 * d.inv_scale;
+}
+
+// Populations f(n) in the paper's order, FP64 unscaled, from the stored field.
+template <typename S>
+static __global__ __launch_bounds__(kBlock) void k_get_f(SlotDesc d, int sel, int layout,
+                                                         double* out) {
+    using C = typename Store<S>::C;
+    const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= (long long)d.nx * d.ny) return;
+    const int x = (int)(s % d.nx), y = (int)(s / d.nx);
+    C f[8];
+    load_state<S>(reinterpret_cast<const S*>(d.buf[sel]), d.plane, d.nx, d.ny, x, y, layout, f);
+    const long long N = (long long)d.nx * d.ny;  // external layout [8][ny][nx]
+    for (int q = 0; q < 8; ++q) out[q * N + s] = (double)f[q] * d.inv_scale;
+}
+
+// Load a state f(n) given in the paper's order.  kLayPull and kLaySwapped
+// store f*(n-1)(x) = f(n)(x + c_q) (the inverse of the gather), in plane q or
+// plane opp(q); kLayNatural stores f(n) itself.
+template <typename S>
+static __global__ __launch_bounds__(kBlock) void k_set_f(SlotDesc d, int sel, int layout,
+                                                         const double* in, double scale) {
+    const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= (long long)d.nx * d.ny) return;
+    const int x = (int)(s % d.nx), y = (int)(s / d.nx);
+    const int xm = (x == 0) ? d.nx - 1 : x - 1, xp = (x == d.nx - 1) ? 0 : x + 1;
+    const int ym = (y == 0) ? d.ny - 1 : y - 1, yp = (y == d.ny - 1) ? 0 : y + 1;
+    S* dst = reinterpret_cast<S*>(d.buf[sel]);
+    const long long N = (long long)d.nx * d.ny;  // external layout [8][ny][nx]
+    const int cx[8] = {1, 0, -1, 0, 1, -1, -1, 1};
+    const int cy[8] = {0, 1, 0, -1, 1, 1, -1, -1};
+    for (int q = 0; q < 8; ++q) {
+        const bool nat = layout == kLayNatural;
+        const int xs = nat ? x : (cx[q] > 0 ? xp : (cx[q] < 0 ? xm : x));
+        const int ys = nat ? y : (cy[q] > 0 ? yp : (cy[q] < 0 ? ym : y));
+        const double v = in[q * N + (long long)ys * d.nx + xs] * scale;
+        const int plane_q = layout == kLaySwapped ? opp(q) : q;
+        Store<S>::st(dst + plane_q * d.plane + s, (typename Store<S>::C)v);
+    }
+}
+
+// Convert an FP64 array to the arithmetic type (force upload).
+template <typename C>
+static __global__ __launch_bounds__(kBlock) void k_convert(const double* in, C* out, long long n) {
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = (C)in[i];
+}
+
+// out = in * factor elementwise, between storage types (promotion for the
+// FP64 polish phase, power-of-two rescaling of half storage).
+template <typename SI, typename SO>
+static __global__ __launch_bounds__(kBlock) void k_recast(const SI* in, SO* out, long long n,
+                                                   double factor) {
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double v = (double)Store<SI>::ld(in + i) * factor;
+    Store<SO>::st(out + i, (typename Store<SO>::C)v);
+}
+
+// Zero fill by a kernel (safe inside captured graphs).
+static __global__ __launch_bounds__(kBlock) void k_zero(unsigned int* p, long long nwords) {
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i < nwords) p[i] = 0u;
+}
+
+// Deterministic (fixed-order) block reduction of four values; MAXMASK bit c
+// set means entry c is reduced with max instead of +.  Result in thread 0.
+template <int MAXMASK>
+__device__ __forceinline__ void block_reduce4(double v[4], double* lds) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double w = __shfl_xor(v[c], o, kWave);
+            v[c] = ((MAXMASK >> c) & 1) ? fmax(v[c], w) : v[c] + w;
+        }
+    }
+    const int wv = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    if (l == 0)
+        for (int c = 0; c < 4; ++c) lds[4 * wv + c] = v[c];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            v[c] = ((MAXMASK >> c) & 1)
+                       ? fmax(fmax(lds[c], lds[4 + c]), fmax(lds[8 + c], lds[12 + c]))
+                       : (lds[c] + lds[4 + c]) + (lds[8 + c] + lds[12 + c]);
+    }
+    __syncthreads();
+}
+
+// Error norms against a reference field, stage 1: per block
+// (sum |e|^2, sum |ref|^2, max |e|_inf, max |ref|_inf), e = u - ref (the grid
+// norms of Sec. 7.1 before the dx weighting).
+constexpr int kErrMask = 0xC;
+static __global__ __launch_bounds__(kBlock) void k_err_norms(const double* ux, const double* uy,
+                                                      const double* rx, const double* ry,
+                                                      long long n, double* partial) {
+    __shared__ double lds[16];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock) {
+        const double ex = ux[i] - rx[i], ey = uy[i] - ry[i];
+        v[0] += ex * ex + ey * ey;
+        v[1] += rx[i] * rx[i] + ry[i] * ry[i];
+        v[2] = fmax(v[2], fmax(fabs(ex), fabs(ey)));
+        v[3] = fmax(v[3], fmax(fabs(rx[i]), fabs(ry[i])));
+    }
+    block_reduce4<kErrMask>(v, lds);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) partial[4 * blockIdx.x + c] = v[c];
+}
+
+// Force statistics, stage 1: per block (sum gx, sum gy, sum gx^2 + gy^2,
+// max |g|_inf).
+constexpr int kForceMask = 0x8;
+static __global__ __launch_bounds__(kBlock) void k_force_stats(const double* gx, const double* gy,
+                                                        long long n, double* partial) {
+    __shared__ double lds[16];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock) {
+        v[0] += gx[i];
+        v[1] += gy[i];
+        v[2] += gx[i] * gx[i] + gy[i] * gy[i];
+        v[3] = fmax(v[3], fmax(fabs(gx[i]), fabs(gy[i])));
+    }
+    block_reduce4<kForceMask>(v, lds);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) partial[4 * blockIdx.x + c] = v[c];
+}
+
+// Stage 2: one block combines the block partials in a fixed order.
+template <int MAXMASK>
+static __global__ __launch_bounds__(kBlock) void k_reduce4(const double* partial, int nparts,
+                                                    double* out) {
+    __shared__ double lds[16];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nparts; i += kBlock)
+        for (int c = 0; c < 4; ++c)
+            v[c] = ((MAXMASK >> c) & 1) ? fmax(v[c], partial[4 * i + c])
+                                         : v[c] + partial[4 * i + c];
+    block_reduce4<MAXMASK>(v, lds);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) out[c] = v[c];
+}
+
+// Write the work list of one lattice: tiles in row-major tile order.
+static __global__ __launch_bounds__(kBlock) void k_build_items(Item* items, int first, int slot,
+                                                        int tiles_x, int count) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= count) return;
+    Item it;
+    it.slot = slot;
+    it.tx = i % tiles_x;
+    it.ty = i / tiles_x;
+    it.pad_ = 0;
+    items[first + i] = it;
+}
+
+// Small device-side stores (stream-ordered, safe inside captured graphs).
+static __global__ void k_set_int(int* p, int v) { *p = v; }
+static __global__ void k_set_desc(SlotDesc* p, SlotDesc v) { *p = v; }
+
+// Neutral modes.  (1) The mean first moments: collision adds g to m10, m01 and
+// streaming permutes, so sum_x m10(f(n)) = sum_x m10(f(0)) + n sum_x gx exactly
+// (eigenvalue 1 at k = 0).  (2) The staggered first moments: for even nx,
+// J = sum_x (-1)^x m10(f(n)) obeys J(n+1) = -J(n) - sum_x (-1)^x gx for any
+// relaxation rates (streaming with c_x = +-1 flips (-1)^x), and likewise in y
+// with m01, gy: eigenvalue -1 at k = (pi, 0), (0, pi).  Neither mode is ever
+// damped, so rounding noise from narrow storage stays in them for good.  These
+// kernels measure both on the stored (post-collision) field S, whose sums
+// equal those of f(n) for the mean and J_S = J_f + G (fixed point G/2) for the
+// staggered mode, and reset them.
+//
+// Stage 1: per block two groups of four sums, unscaled FP64:
+// (sum (-1)^x m10(S), sum (-1)^y m01(S), sum (-1)^x gx, sum (-1)^y gy) and
+// (sum m10(S), sum m01(S), 0, 0).
+template <typename S>
+static __global__ __launch_bounds__(kBlock) void k_neutral_sums(SlotDesc d, int sel,
+                                                                double* partial) {
+    __shared__ double lds[16];
+    using C = typename Store<S>::C;
+    const long long N = (long long)d.nx * d.ny;
+    const S* st = reinterpret_cast<const S*>(d.buf[sel]);
+    const C* g = reinterpret_cast<const C*>(d.g);
+    const double sx = (d.nx % 2 == 0) ? 1.0 : 0.0, sy = (d.ny % 2 == 0) ? 1.0 : 0.0;
+    double v[4] = {0.0, 0.0, 0.0, 0.0}, w[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long s = (long long)blockIdx.x * kBlock + threadIdx.x; s < N;
+         s += (long long)gridDim.x * kBlock) {
+        const int x = (int)(s % d.nx), y = (int)(s / d.nx);
+        double f[8];
+        for (int q = 0; q < 8; ++q) f[q] = (double)Store<S>::ld(st + q * d.plane + s);
+        const double m10 = ((f[0] - f[2]) + ((f[4] - f[6]) - (f[5] - f[7]))) * d.inv_scale;
+        const double m01 = ((f[1] - f[3]) + ((f[4] - f[6]) + (f[5] - f[7]))) * d.inv_scale;
+        const double px = (x & 1) ? -sx : sx, py = (y & 1) ? -sy : sy;
+        v[0] += px * m10;
+        v[1] += py * m01;
+        v[2] += px * (double)g[s];
+        v[3] += py * (double)g[d.plane + s];
+        w[0] += m10;
+        w[1] += m01;
+    }
+    block_reduce4<0>(v, lds);
+    block_reduce4<0>(w, lds);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) {
+            partial[4 * blockIdx.x + c] = v[c];
+            partial[4 * (gridDim.x + blockIdx.x) + c] = w[c];
+        }
+}
+
+// Stage 2: S1 += (ex (-1)^x + mx), S3 -= (ex (-1)^x + mx),
+//          S2 += (ey (-1)^y + my), S4 -= (ey (-1)^y + my)
+// (changes only m10 / m01 of S: the staggered and the uniform parts; all
+// amounts already in storage units).
+template <typename S>
+static __global__ __launch_bounds__(kBlock) void k_neutral_fix(SlotDesc d, int sel, double ex,
+                                                               double ey, double mx, double my) {
+    using C = typename Store<S>::C;
+    const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= (long long)d.nx * d.ny) return;
+    const int x = (int)(s % d.nx), y = (int)(s / d.nx);
+    S* st = reinterpret_cast<S*>(d.buf[sel]);
+    const double px = ((x & 1) ? -ex : ex) + mx, py = ((y & 1) ? -ey : ey) + my;
+    S* p0 = st + 0 * d.plane + s;
+    S* p1 = st + 1 * d.plane + s;
+    S* p2 = st + 2 * d.plane + s;
+    S* p3 = st + 3 * d.plane + s;
+    Store<S>::st(p0, (C)((double)Store<S>::ld(p0) + px));
+    Store<S>::st(p2, (C)((double)Store<S>::ld(p2) - px));
+    Store<S>::st(p1, (C)((double)Store<S>::ld(p1) + py));
+    Store<S>::st(p3, (C)((double)Store<S>::ld(p3) - py));
+}
+
+}  // namespace lbm
