@@ -253,15 +253,21 @@ int lbm_batch_create(int max_slots, void *arena, size_t arena_bytes, void *strea
                      lbm_batch **out);
 int lbm_batch_destroy(lbm_batch *b);
 
-/* Add a lattice: material (lattice units), FP64 device force arrays [ny][nx]
- * (copied), storage precision, optional polish reservation.  The lattice
- * starts at f = 0 and joins the next step.  *slot receives its id.
- * LBM_E_WORKSPACE if the arena has no room (nothing changed). */
+/* Add a lattice: material (lattice units), FP64 device force arrays [ny][nx],
+ * storage precision, optional polish reservation.  The lattice starts at f = 0
+ * and joins the next step.  *slot receives its id.  The force is read
+ * asynchronously on the batch's stream: keep the arrays valid until that
+ * stream has run the call's work (the next lbm_batch_step returns after it;
+ * reuse ordered on the same stream is safe).  Adds and removals do not wait
+ * for the GPU: the work list is rebuilt once, before the next step.
+ * LBM_E_WORKSPACE if the arena or the work list has no room (nothing
+ * changed). */
 int lbm_batch_add(lbm_batch *b, int nx, int ny, int precision, int with_polish,
                   double lame_lambda, double lame_mu, const double *gx, const double *gy,
                   int *slot);
 
-/* Remove a lattice and return its memory to the arena. */
+/* Remove a lattice and return its memory to the arena (no wait: later work on
+ * that memory is ordered on the batch's stream after the launches reading it). */
 int lbm_batch_remove(lbm_batch *b, int slot);
 
 /* Advance every active lattice by nsteps >= 1.  With check != 0 the last two

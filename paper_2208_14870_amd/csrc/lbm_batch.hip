@@ -136,6 +136,7 @@ struct lbm_batch {
     int* d_count = nullptr;
     int* d_range = nullptr;  // 3 x {begin, end}: one range per precision
     double* d_result = nullptr;
+    double* d_stats = nullptr;  // 4 doubles per slot: sum gx, sum gy, sum |g|^2, max |g|
     Item* d_items = nullptr;
     double* d_partial = nullptr;
     SlotRow* d_rows = nullptr;
@@ -152,6 +153,14 @@ struct lbm_batch {
     int bx_log2 = 6, vy = 2;
     int blocks_per_cu = 0;  // 0: one workgroup per tile; k: persistent k per CU
     int tb = 4;             // plain steps per launch (2..4: fused multi-step kernel)
+    // fused tile height per precision, from the precision's current total sites
+    // (short tiles once few sites remain, e.g. the tail of a set of solves)
+    int th[3] = {8, 16, 12};
+    // Adds and removals only mark the work list stale; it is rebuilt once before
+    // the next launch (one host synchronisation for any number of changes).
+    bool dirty = false;
+    std::vector<char> stats_pending;  // per slot: force statistics not yet read back
+    long long items_bound = 0;        // upper bound of the work list of the active slots
     std::string err;
     std::map<std::tuple<long long, int, int, unsigned, unsigned, unsigned>, hipGraphExec_t> graphs;
 
@@ -185,12 +194,36 @@ struct lbm_batch {
         return hipGetLastError();
     }
 
+    int ensure() { return dirty ? rebuild() : LBM_OK; }
+
     // Recompute the work list: items grouped by precision, then by slot id.
     int rebuild() {
         long long total = 0;
         int nrows = 0;
         hipError_t e = hipStreamSynchronize(stream);  // staging buffer reuse
         if (e != hipSuccess) return hip_fail(e, "rebuild");
+        dirty = false;
+        // force statistics of lattices added since the last rebuild (one copy)
+        bool any = false;
+        for (int i = 0; i < max_slots; ++i) any = any || (slots[i].active && stats_pending[i]);
+        if (any) {
+            e = hipMemcpy(h_result, d_stats, 4 * max_slots * sizeof(double), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(e, "rebuild: force statistics");
+            for (int i = 0; i < max_slots; ++i) {
+                if (!slots[i].active || !stats_pending[i]) continue;
+                Lattice& L = slots[i].L;
+                L.gmax = h_result[4 * i + 3];
+                L.rebase_force(0, h_result[4 * i + 0], h_result[4 * i + 1]);
+                if (L.prec0 == LBM_FP16) L.e_scale = initial_half_exponent(L, L.gmax);
+                stats_pending[i] = 0;
+            }
+        }
+        for (int p = 0; p < 3; ++p) {
+            long long sites = 0;
+            for (int i = 0; i < max_slots; ++i)
+                if (slots[i].active && slots[i].L.prec == p) sites += slots[i].L.N;
+            th[p] = fused_th(p, sites);
+        }
         for (int p = 0; p < 3; ++p) {
             range_host[p][0] = (int)total;
             for (int i = 0; i < max_slots; ++i) {
@@ -199,7 +232,7 @@ struct lbm_batch {
                 s.L.bx_log2 = bx_log2;
                 s.L.vy = vy;
                 s.L.tb = tb;
-                s.L.th = fused_th(p, 1LL << 22);  // one tile height per precision
+                s.L.th = th[p];
                 s.first = (int)total;
                 s.count = s.L.nitems();
                 total += s.count;
@@ -243,7 +276,7 @@ struct lbm_batch {
     }
 
     // rows per thread of the tiles of one precision's lattices
-    int eff_vy(int prec) const { return tb >= 2 ? fused_th(prec, 1LL << 22) / 4 : vy; }
+    int eff_vy(int prec) const { return tb >= 2 ? th[prec] / 4 : vy; }
 
     long long launches(long long nsteps, bool check) const {
         const long long np = check ? nsteps - 2 : nsteps;
@@ -262,7 +295,7 @@ struct lbm_batch {
         long long i = 0;
         if (tb >= 2)
             for (; i + tb <= np && e == hipSuccess; i += tb, ++ph)
-                each([&](int p, unsigned g) { return launch_stepN(p, tb, fused_th(p, 1LL << 22), g, st, args(p, (int)(ph & 1))); });
+                each([&](int p, unsigned g) { return launch_stepN(p, tb, th[p], g, st, args(p, (int)(ph & 1))); });
         for (; i < np && e == hipSuccess; ++i, ++ph)
             each([&](int p, unsigned g) {
                 return launch_step(p, kPlain, false, eff_vy(p), kLayPull, g, st, args(p, (int)(ph & 1)));
@@ -328,6 +361,7 @@ int lbm_batch_create(int max_slots, void* arena, size_t arena_bytes, void* strea
     b->d_count = reinterpret_cast<int*>(take(max_slots * sizeof(int)));
     b->d_range = reinterpret_cast<int*>(take(6 * sizeof(int)));
     b->d_result = reinterpret_cast<double*>(take(4 * max_slots * sizeof(double)));
+    b->d_stats = reinterpret_cast<double*>(take(4 * max_slots * sizeof(double)));
     b->d_rows = reinterpret_cast<SlotRow*>(take((max_slots + 2) * sizeof(SlotRow)));
     b->d_red = reinterpret_cast<double*>(take((kErrBlocks * 8 + 8) * sizeof(double)));
     b->d_items = reinterpret_cast<Item*>(take(b->cap_items * sizeof(Item)));
@@ -341,6 +375,7 @@ int lbm_batch_create(int max_slots, void* arena, size_t arena_bytes, void* strea
     b->heap_off = off;
     b->arena.init(arena_bytes - off);
     b->slots.resize(max_slots);
+    b->stats_pending.assign(max_slots, 0);
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -399,8 +434,7 @@ int lbm_batch_add(lbm_batch* b, int nx, int ny, int precision, int with_polish, 
     if (id < 0) return b->fail(LBM_E_WORKSPACE, "batch_add: all slots in use");
     const long long N = (long long)nx * ny;
     const size_t need = lattice_bytes(N, precision, with_polish != 0);
-    long long items_now = b->range_host[2][1];
-    if (items_now + max_items(nx, ny) > b->cap_items)
+    if (b->items_bound + max_items(nx, ny) > b->cap_items)
         return b->fail(LBM_E_WORKSPACE, "batch_add: work list full");
     const size_t off = b->arena.alloc(need);
     if (off == SIZE_MAX) return b->fail(LBM_E_WORKSPACE, "batch_add: arena has no room");
@@ -429,36 +463,27 @@ int lbm_batch_add(lbm_batch* b, int nx, int ny, int precision, int with_polish, 
         return b->hip_fail(e, "batch_add");
     }
     if (precision == LBM_FP16 || L.polish) {
-        // sum g (the mean first moments at promotion) and the initial half
-        // scale from max |g| (blocking two-stage reduction)
+        // sum g (the mean first moments at promotion) and max |g| (the initial
+        // half scale): two-stage reduction into this slot's statistics, read
+        // back at the next rebuild
         hipLaunchKernelGGL(k_force_stats, dim3(kErrBlocks), dim3(kBlock), 0, b->stream, gx, gy, N,
                            b->d_red);
         hipLaunchKernelGGL(k_reduce4<kForceMask>, dim3(1), dim3(kBlock), 0, b->stream, b->d_red,
-                           kErrBlocks, b->d_red + 4 * kErrBlocks);
-        e = hipMemcpyAsync(b->h_result, b->d_red + 4 * kErrBlocks, 4 * 8, hipMemcpyDeviceToHost,
-                           b->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-        if (e != hipSuccess) {
+                           kErrBlocks, b->d_stats + 4 * id);
+        if ((e = hipGetLastError()) != hipSuccess) {
             b->arena.release(off, need);
             s = BSlot();
             return b->hip_fail(e, "batch_add force stats");
         }
-        L.gmax = b->h_result[3];
-        L.rebase_force(0, b->h_result[0], b->h_result[1]);
-        if (precision == LBM_FP16) L.e_scale = initial_half_exponent(L, L.gmax);
+        b->stats_pending[id] = 1;
     }
     // the next launch reads buf[cur ^ (phase & 1)] = buf[0]
     L.cur = (int)(b->phase & 1);
     s.active = true;
     s.steps = 0;
     s.checked_phase = -1;
-    int rc = b->rebuild();
-    if (rc != LBM_OK) {
-        b->arena.release(off, need);
-        s = BSlot();
-        b->rebuild();
-        return rc;
-    }
+    b->items_bound += max_items(nx, ny);
+    b->dirty = true;
     *slot = id;
     return LBM_OK;
 }
@@ -467,11 +492,15 @@ int lbm_batch_remove(lbm_batch* b, int slot) {
     if (!b) return LBM_E_ARG;
     if (slot < 0 || slot >= b->max_slots || !b->slots[slot].active)
         return b->fail(LBM_E_ARG, "batch_remove: no such slot");
-    (void)hipStreamSynchronize(b->stream);
+    // no wait: later work on this memory (a new slot's uploads) is ordered on
+    // the same stream after the launches that still read it
     BSlot& s = b->slots[slot];
+    b->items_bound -= max_items(s.L.nx, s.L.ny);
     b->arena.release(s.off, s.bytes);
     s = BSlot();
-    return b->rebuild();
+    b->stats_pending[slot] = 0;
+    b->dirty = true;
+    return LBM_OK;
 }
 
 int lbm_batch_set_tile(lbm_batch* b, int bx_log2, int rows_per_thread, int blocks_per_cu) {
@@ -501,11 +530,16 @@ int lbm_batch_step(lbm_batch* b, long long nsteps, int check) {
     if (!b) return LBM_E_ARG;
     if (nsteps < 1 || (check && nsteps < 2))
         return b->fail(LBM_E_ARG, "batch_step: nsteps >= 1 (>= 2 with check)");
+    int rc0 = b->ensure();
+    if (rc0 != LBM_OK) return rc0;
     if (b->range_host[2][1] == 0) return LBM_OK;  // nothing active
     hipError_t e;
     const int flip0 = (int)(b->phase & 1);
     if (b->launches(nsteps, check != 0) >= 4) {
-        auto key = std::make_tuple(nsteps, (check ? 1 : 0) | (b->tb << 1), flip0,
+        auto key = std::make_tuple(nsteps,
+                                   (check ? 1 : 0) | (b->tb << 1) | (b->th[0] << 4) |
+                                       (b->th[1] << 9) | (b->th[2] << 14),
+                                   flip0,
                                    b->grid_for(0), b->grid_for(1), b->grid_for(2));
         auto it = b->graphs.find(key);
         if (it == b->graphs.end()) {
@@ -566,6 +600,8 @@ int lbm_batch_promote(lbm_batch* b, int slot) {
     if (!b) return LBM_E_ARG;
     if (slot < 0 || slot >= b->max_slots || !b->slots[slot].active)
         return b->fail(LBM_E_ARG, "batch_promote: no such slot");
+    int rc0 = b->ensure();  // force statistics of a new slot are needed below
+    if (rc0 != LBM_OK) return rc0;
     BSlot& s = b->slots[slot];
     Lattice& L = s.L;
     if (L.prec == LBM_FP64) return LBM_OK;
@@ -599,6 +635,8 @@ int lbm_batch_get_displacement(lbm_batch* b, int slot, double* ux, double* uy) {
     if (!b) return LBM_E_ARG;
     if (slot < 0 || slot >= b->max_slots || !b->slots[slot].active || !ux || !uy)
         return b->fail(LBM_E_ARG, "batch_get_displacement: no such slot or NULL output");
+    int rc0 = b->ensure();  // the half scale of a new FP16 slot
+    if (rc0 != LBM_OK) return rc0;
     const BSlot& s = b->slots[slot];
     hipError_t e = extract_u(s.L.prec, s.L.desc(), b->sel(s), kLayPull, ux, uy, b->stream);
     if (e != hipSuccess) return b->hip_fail(e, "batch_get_displacement");

@@ -372,6 +372,29 @@ class Batch:
     def set_time_blocking(self, steps_per_launch: int):
         self._check(self.lib.lbm_batch_set_time_blocking(self.h, int(steps_per_launch)))
 
+    def displacements(self, slots):
+        """Displacements of several lattices as host arrays [(ux, uy), ...]:
+        one device buffer, one copy to the host."""
+        slots = list(slots)
+        if not slots:
+            return []
+        sizes = [self.shapes[sl][0] * self.shapes[sl][1] for sl in slots]
+        buf = torch.empty(2 * sum(sizes), dtype=torch.float64, device=self.device)
+        off = 0
+        base = buf.data_ptr()
+        for sl, n in zip(slots, sizes):
+            self._check(self.lib.lbm_batch_get_displacement(
+                self.h, int(sl), ctypes.c_void_p(base + 8 * off),
+                ctypes.c_void_p(base + 8 * (off + n))))
+            off += 2 * n
+        host = buf.cpu().numpy()  # waits for the extractions
+        out, off = [], 0
+        for sl, n in zip(slots, sizes):
+            shp = self.shapes[sl]
+            out.append((host[off:off + n].reshape(shp), host[off + n:off + 2 * n].reshape(shp)))
+            off += 2 * n
+        return out
+
     def displacement(self, slot: int):
         shp = self.shapes[slot]
         ux = torch.empty(shp, dtype=torch.float64, device=self.device)

@@ -91,15 +91,21 @@ class Server:
         self.active[slot] = _Active(req, case, now, g=(gx, gy))
         return True
 
-    def _retire(self, slot: int, a: _Active, steps: int, r: float, now_fn):
-        ux, uy = self.batch.displacement(slot)
-        hx, hy = ux.cpu().numpy(), uy.cpu().numpy()  # blocking copy to host
+    def _retire_all(self, done, now_fn):
+        """Retire the lattices of one chunk together: their displacements reach
+        the host in one copy (the latency ends there), then their memory
+        returns to the arena."""
+        if not done:
+            return
+        fields = self.batch.displacements([slot for slot, _, _ in done])
         t = now_fn()
-        self.results.append(Result(a.req.rid, a.req.n, a.req.t_arrival, a.t_admit, t, steps, r,
-                                   a.promoted_at, hx if self.keep else None,
-                                   hy if self.keep else None))
-        self.batch.remove(slot)
-        del self.active[slot]
+        for (slot, steps, r), (hx, hy) in zip(done, fields):
+            a = self.active[slot]
+            self.results.append(Result(a.req.rid, a.req.n, a.req.t_arrival, a.t_admit, t, steps,
+                                       r, a.promoted_at, hx if self.keep else None,
+                                       hy if self.keep else None))
+            self.batch.remove(slot)
+            del self.active[slot]
 
     def run(self, requests: List[Request], admit_window_s: float, wall_budget_s: float,
             cases: Optional[Dict[int, Case]] = None,
@@ -145,6 +151,7 @@ class Server:
                 self.batch.step(self.chunk, check=True)
                 r, steps = self.batch.residuals()
                 gpu_time += time.perf_counter() - g0
+                done = []
                 for slot in list(self.active):
                     a = self.active[slot]
                     self.site_updates += a.case.nx * a.case.ny * self.chunk
@@ -156,10 +163,10 @@ class Server:
                         continue
                     if fixed_steps is not None:
                         if steps[slot] >= fixed_steps[a.req.rid]:
-                            self._retire(slot, a, steps[slot], rs, now)
+                            done.append((slot, steps[slot], rs))
                         continue
                     if rs <= self.tol or steps[slot] >= self.max_steps:
-                        self._retire(slot, a, steps[slot], rs, now)
+                        done.append((slot, steps[slot], rs))
                         continue
                     if self.polish and a.promoted_at < 0:
                         a.nondecreasing = a.nondecreasing + 1 if rs >= a.last_r else 0
@@ -167,6 +174,7 @@ class Server:
                             self.batch.promote(slot)
                             a.promoted_at = steps[slot]
                     a.last_r = rs
+                self._retire_all(done, now)
             elif not pending and not queue:
                 break
             else:

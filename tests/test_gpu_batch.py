@@ -109,6 +109,55 @@ def test_mixed_precisions_match_single_solvers():
         s.close()
 
 
+def test_deferred_work_list():
+    """Adds and removals between steps only mark the work list stale: several of
+    them followed by one step give the same results as single solvers; reading
+    a displacement right after an add (FP16: its scale is set from the force
+    read back at the rebuild) works; a lattice not yet checked reports NaN."""
+    say("batch deferred rebuild")
+    from paper_2208_14870_amd import lbm
+    cases = _cases()
+    precs = ["fp16", "fp32", "fp64", "fp16", "fp32", "fp64"]
+    b = _batch()
+    s0 = b.add(cases[0].nx, cases[0].ny, cases[0].material.lame_lambda,
+               cases[0].material.lame_mu, dev(cases[0].gx), dev(cases[0].gy), "fp16",
+               with_polish=True)
+    got = b.displacement(s0)  # forces the rebuild before any step
+    ref = lbm.Solver(cases[0].nx, cases[0].ny, "fp16", with_polish=True)
+    ref.set_material(cases[0].material.lame_lambda, cases[0].material.lame_mu)
+    ref.set_body_force(dev(cases[0].gx), dev(cases[0].gy))
+    for a, t in zip(got, ref.displacement()):  # zero populations: half the force term
+        np.testing.assert_array_equal(host(a), host(t))
+    ref.close()
+    slots = {0: s0}
+    for i in (1, 2, 3):
+        c = cases[i]
+        slots[i] = b.add(c.nx, c.ny, c.material.lame_lambda, c.material.lame_mu, dev(c.gx),
+                         dev(c.gy), precs[i])
+    b.remove(slots.pop(2))
+    b.remove(slots.pop(3))
+    for i in (4, 5):
+        c = cases[i]
+        slots[i] = b.add(c.nx, c.ny, c.material.lame_lambda, c.material.lame_mu, dev(c.gx),
+                         dev(c.gy), precs[i])
+    b.step(20, check=True)
+    r, n = b.residuals()
+    for i, sl in slots.items():
+        assert n[sl] == 20 and np.isfinite(r[sl])
+        c = cases[i]
+        s = lbm.Solver(c.nx, c.ny, precs[i])
+        s.set_material(c.material.lame_lambda, c.material.lame_mu)
+        s.set_body_force(dev(c.gx), dev(c.gy))
+        s.step(20)
+        for a, t in zip(b.displacement(sl), s.displacement()):
+            np.testing.assert_array_equal(host(a), host(t), err_msg=f"{precs[i]} {c.label}")
+        s.close()
+    late = b.add(cases[2].nx, cases[2].ny, cases[2].material.lame_lambda,
+                 cases[2].material.lame_mu, dev(cases[2].gx), dev(cases[2].gy), "fp32")
+    r, n = b.residuals()
+    assert n[late] == 0 and np.isnan(r[late])
+
+
 def test_join_and_leave_mid_run():
     """Lattices added later and removals do not disturb the others."""
     say("batch join/leave")
