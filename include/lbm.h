@@ -198,19 +198,24 @@ int lbm_set_populations(lbm_solver *s, const double *f);
  * Results do not depend on the shape.  Used by the autotuner. */
 int lbm_set_tile(lbm_solver *s, int bx_log2, int rows_per_thread, int blocks_per_cu);
 
-/* Temporal blocking: with steps_per_launch = k in {2, 3, 4}, plain steps run k at
- * a time through one fused kernel, so populations cross HBM once per k steps.
+/* Temporal blocking: with steps_per_launch = k in 2..8, plain steps run k at a
+ * time through one fused kernel, so populations cross HBM once per k steps.
  * Results are identical to single steps.  Residual-check steps, remainders
  * and the general-rates variant run one step per launch.  Overrides the tile
- * shape of lbm_set_tile while active.  Default 4.  The fused kernel is chosen
- * with lbm_set_fused_kernel. */
+ * shape of lbm_set_tile while active.  Default by storage type and size: FP32
+ * 8 above 2^17 sites, else 4; FP16 8 up to 2^21 sites, else 4; FP64 4 (also
+ * after a polish switch).  The fused kernel follows the
+ * default of lbm_set_fused_kernel for k until the caller picks one; k > 4
+ * always runs the LDS tile kernel (the wavefront runs 2..4 steps).  Errors:
+ * LBM_E_ARG (k outside 1..8), LBM_E_STATE (k != 1 in place). */
 int lbm_set_time_blocking(lbm_solver *s, int steps_per_launch);
 
 /* Fused kernel kinds (both give identical results). */
 enum lbm_fused_kernel {
-    /* LDS tile: a workgroup advances a 64-wide tile (16 rows in FP32, 8 on
-     * lattices of up to 2^21 sites and in FP64, 12 in FP16) plus a ring of
-     * k-1 sites in LDS, then narrower rings down to the tile. */
+    /* LDS tile: a workgroup advances a 64-wide tile plus a ring of k-1 sites
+     * in LDS, then narrower rings down to the tile.  Tile rows: FP64 8; FP32
+     * 16 (8 for k <= 4 on lattices of up to 2^21 sites); FP16 12 for k <= 4,
+     * 16 above. */
     LBM_FUSED_TILE = 0,
     /* Register wavefront: a wave owns a strip of columns (one per lane, or
      * two per lane for FP32/FP16 on even widths) with a ring of k columns
@@ -222,12 +227,20 @@ enum lbm_fused_kernel {
 
 /* Select the fused kernel for steps_per_launch >= 2.  segment_rows (1..2^20)
  * is used by LBM_FUSED_WAVEFRONT only: each strip is split into segments of
- * that many rows, each recomputing 2k halo rows.  Default: the wavefront for
- * FP64 lattices of at least 2^22 sites (also after a polish switch) and for
- * even-width FP32 lattices of at least 2^25 sites, with the tallest segment of
- * 256, 128, 64 or 32 rows that still gives 18 waves per compute unit; the
- * tile kernel otherwise.  Errors: LBM_E_ARG. */
+ * that many rows, each recomputing 2k halo rows.  Default (until this is
+ * called, and again after a polish switch): for k <= 4 the wavefront on FP64
+ * lattices of more than 2^22 sites and on even-width FP32 lattices of at least
+ * 2^25 sites, with the tallest segment of 256, 128, 64 or 32 rows that still
+ * gives 18 waves per compute unit; the tile kernel otherwise.  Errors:
+ * LBM_E_ARG, LBM_E_STATE (the wavefront with steps_per_launch > 4). */
 int lbm_set_fused_kernel(lbm_solver *s, int kind, int segment_rows);
+
+/* Current launch configuration of plain steps: out[0] steps per launch;
+ * out[1] the fused kernel (LBM_FUSED_TILE, LBM_FUSED_WAVEFRONT, or -1 for one
+ * step per launch); out[2] its tile rows (tile), segment rows (wavefront) or
+ * rows per thread (one step per launch); out[3] threads per workgroup.
+ * out is a host array of 4 ints.  Errors: LBM_E_ARG. */
+int lbm_get_launch_config(const lbm_solver *s, int out[4]);
 
 /* Diagnostic: nsteps of streaming alone (no collision), for bit-exact checks
  * of the periodic index arithmetic (Eq. streaming, Sec. 6.1). */
@@ -293,8 +306,15 @@ int lbm_batch_get_displacement(lbm_batch *b, int slot, double *ux, double *uy);
 int lbm_batch_set_tile(lbm_batch *b, int bx_log2, int rows_per_thread, int blocks_per_cu);
 
 /* Temporal blocking for all lattices of the batch (see lbm_set_time_blocking,
- * 1..4); default 4. */
+ * 1..8).  Until set, each storage type takes the single-lattice default for
+ * the total sites of its lattices in the batch.  Errors: LBM_E_ARG. */
 int lbm_batch_set_time_blocking(lbm_batch *b, int steps_per_launch);
+
+/* Temporal blocking for the lattices of one storage type only (precision
+ * LBM_FP64, LBM_FP32 or LBM_FP16; steps_per_launch 1..8).  Lattices of each
+ * type run their own launch sequence, so the types may differ.  Errors:
+ * LBM_E_ARG. */
+int lbm_batch_set_time_blocking_for(lbm_batch *b, int precision, int steps_per_launch);
 
 /* Number of active lattices, and arena bytes in use / free (largest hole). */
 int lbm_batch_info(const lbm_batch *b, int *active, size_t *used_bytes, size_t *largest_free);

@@ -84,7 +84,7 @@ struct BSlot {
     Lattice L;
     size_t off = 0, bytes = 0;
     long long steps = 0;
-    long long checked_phase = -1;  // phase value right after the last check launch
+    long long checked_phase = -1;  // its precision's phase right after the last check launch
     int first = 0, count = 0;
 };
 
@@ -149,10 +149,16 @@ struct lbm_batch {
     Arena arena;
     std::vector<BSlot> slots;
     int range_host[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-    long long phase = 0;
+    // launches per precision since the descriptors were written: lattices of one
+    // storage type share a launch parity (buffer selector cur ^ (phase & 1));
+    // each type runs its own steps per launch, so each keeps its own count
+    long long phase[3] = {0, 0, 0};
     int bx_log2 = 6, vy = 2;
     int blocks_per_cu = 0;  // 0: one workgroup per tile; k: persistent k per CU
-    int tb = 4;             // plain steps per launch (2..4: fused multi-step kernel)
+    // plain steps per launch per precision (2..8: fused multi-step kernel); until
+    // set by the caller, the default for the precision's current total sites
+    int tb[3] = {4, 4, 4};
+    bool tb_auto[3] = {true, true, true};
     // fused tile height per precision, from the precision's current total sites
     // (short tiles once few sites remain, e.g. the tail of a set of solves)
     int th[3] = {8, 16, 12};
@@ -162,7 +168,7 @@ struct lbm_batch {
     std::vector<char> stats_pending;  // per slot: force statistics not yet read back
     long long items_bound = 0;        // upper bound of the work list of the active slots
     std::string err;
-    std::map<std::tuple<long long, int, int, unsigned, unsigned, unsigned>, hipGraphExec_t> graphs;
+    std::map<std::tuple<long long, int, int, int, unsigned, unsigned, unsigned>, hipGraphExec_t> graphs;
 
     int fail(int code, const std::string& m) {
         err = m;
@@ -176,7 +182,10 @@ struct lbm_batch {
         for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
         graphs.clear();
     }
-    int sel(const BSlot& s) const { return s.L.cur ^ (int)(phase & 1); }
+    int sel(const BSlot& s) const { return s.L.cur ^ (int)(phase[s.L.prec] & 1); }
+    int flips() const {
+        return (int)(phase[0] & 1) | (int)(phase[1] & 1) << 1 | (int)(phase[2] & 1) << 2;
+    }
 
     unsigned grid_for(int prec) const {
         const int n = range_host[prec][1] - range_host[prec][0];
@@ -222,7 +231,8 @@ struct lbm_batch {
             long long sites = 0;
             for (int i = 0; i < max_slots; ++i)
                 if (slots[i].active && slots[i].L.prec == p) sites += slots[i].L.N;
-            th[p] = fused_th(p, sites);
+            if (tb_auto[p]) tb[p] = default_time_blocking(p, sites);
+            th[p] = fused_th(p, tb[p], sites);
         }
         for (int p = 0; p < 3; ++p) {
             range_host[p][0] = (int)total;
@@ -231,7 +241,7 @@ struct lbm_batch {
                 if (!s.active || s.L.prec != p) continue;
                 s.L.bx_log2 = bx_log2;
                 s.L.vy = vy;
-                s.L.tb = tb;
+                s.L.tb = tb[p];
                 s.L.th = th[p];
                 s.first = (int)total;
                 s.count = s.L.nitems();
@@ -276,49 +286,45 @@ struct lbm_batch {
     }
 
     // rows per thread of the tiles of one precision's lattices
-    int eff_vy(int prec) const { return tb >= 2 ? th[prec] / 4 : vy; }
+    int eff_vy(int prec) const { return tb[prec] >= 2 ? th[prec] / 4 : vy; }
 
-    long long launches(long long nsteps, bool check) const {
+    // buffer flips of precision p in one batch_step
+    long long launches(int p, long long nsteps, bool check) const {
         const long long np = check ? nsteps - 2 : nsteps;
-        return (tb >= 2 ? np / tb + np % tb : np) + (check ? 2 : 0);
+        return (tb[p] >= 2 ? np / tb[p] + np % tb[p] : np) + (check ? 2 : 0);
     }
 
-    hipError_t enqueue(long long nsteps, bool check, hipStream_t st, long long ph) {
+    // The launches of one batch_step, precision by precision (their lattices
+    // and work-list ranges are disjoint), then one finalize over all slots.
+    hipError_t enqueue(long long nsteps, bool check, hipStream_t st) {
         hipError_t e = hipSuccess;
         const long long np = check ? nsteps - 2 : nsteps;
-        auto each = [&](auto&& fn) {
-            for (int p = 0; p < 3 && e == hipSuccess; ++p) {
-                const unsigned g = grid_for(p);
-                if (g) e = fn(p, g);
+        for (int p = 0; p < 3 && e == hipSuccess; ++p) {
+            const unsigned g = grid_for(p);
+            if (!g) continue;
+            long long ph = phase[p], i = 0;
+            if (tb[p] >= 2)
+                for (; i + tb[p] <= np && e == hipSuccess; i += tb[p], ++ph)
+                    e = launch_stepN(p, tb[p], th[p], g, st, args(p, (int)(ph & 1)));
+            for (; i < np && e == hipSuccess; ++i, ++ph)
+                e = launch_step(p, kPlain, false, eff_vy(p), kLayPull, g, st, args(p, (int)(ph & 1)));
+            if (check && e == hipSuccess) {
+                e = launch_step(p, kWriteU, false, eff_vy(p), kLayPull, g, st, args(p, (int)(ph & 1)));
+                ++ph;
+                if (e == hipSuccess)
+                    e = launch_step(p, kCheck, false, eff_vy(p), kLayPull, g, st,
+                                    args(p, (int)(ph & 1)));
             }
-        };
-        long long i = 0;
-        if (tb >= 2)
-            for (; i + tb <= np && e == hipSuccess; i += tb, ++ph)
-                each([&](int p, unsigned g) { return launch_stepN(p, tb, th[p], g, st, args(p, (int)(ph & 1))); });
-        for (; i < np && e == hipSuccess; ++i, ++ph)
-            each([&](int p, unsigned g) {
-                return launch_step(p, kPlain, false, eff_vy(p), kLayPull, g, st, args(p, (int)(ph & 1)));
-            });
+        }
         if (check && e == hipSuccess) {
-            each([&](int p, unsigned g) {
-                return launch_step(p, kWriteU, false, eff_vy(p), kLayPull, g, st, args(p, (int)(ph & 1)));
-            });
-            ++ph;
-            each([&](int p, unsigned g) {
-                return launch_step(p, kCheck, false, eff_vy(p), kLayPull, g, st, args(p, (int)(ph & 1)));
-            });
-            ++ph;
-            if (e == hipSuccess) {
-                FinalizeLaunch F;
-                F.first = d_first;
-                F.count = d_count;
-                F.partial = d_partial;
-                F.result = d_result;
-                F.nslots = max_slots;
-                hipLaunchKernelGGL(k_finalize, dim3(max_slots), dim3(kBlock), 0, st, F);
-                e = hipGetLastError();
-            }
+            FinalizeLaunch F;
+            F.first = d_first;
+            F.count = d_count;
+            F.partial = d_partial;
+            F.result = d_result;
+            F.nslots = max_slots;
+            hipLaunchKernelGGL(k_finalize, dim3(max_slots), dim3(kBlock), 0, st, F);
+            e = hipGetLastError();
         }
         return e;
     }
@@ -478,7 +484,7 @@ int lbm_batch_add(lbm_batch* b, int nx, int ny, int precision, int with_polish, 
         b->stats_pending[id] = 1;
     }
     // the next launch reads buf[cur ^ (phase & 1)] = buf[0]
-    L.cur = (int)(b->phase & 1);
+    L.cur = (int)(b->phase[precision] & 1);
     s.active = true;
     s.steps = 0;
     s.checked_phase = -1;
@@ -519,9 +525,23 @@ int lbm_batch_set_tile(lbm_batch* b, int bx_log2, int rows_per_thread, int block
 
 int lbm_batch_set_time_blocking(lbm_batch* b, int steps_per_launch) {
     if (!b) return LBM_E_ARG;
-    if (steps_per_launch < 1 || steps_per_launch > 4)
-        return b->fail(LBM_E_ARG, "batch_set_time_blocking: steps_per_launch must be in 1..4");
-    b->tb = steps_per_launch;
+    if (steps_per_launch < 1 || steps_per_launch > 8)
+        return b->fail(LBM_E_ARG, "batch_set_time_blocking: steps_per_launch must be in 1..8");
+    for (int p = 0; p < 3; ++p) {
+        b->tb[p] = steps_per_launch;
+        b->tb_auto[p] = false;
+    }
+    b->drop_graphs();
+    return b->rebuild();
+}
+
+int lbm_batch_set_time_blocking_for(lbm_batch* b, int precision, int steps_per_launch) {
+    if (!b) return LBM_E_ARG;
+    if (!valid_prec(precision) || steps_per_launch < 1 || steps_per_launch > 8)
+        return b->fail(LBM_E_ARG,
+                       "batch_set_time_blocking_for: precision LBM_FP64/FP32/FP16, steps_per_launch in 1..8");
+    b->tb[precision] = steps_per_launch;
+    b->tb_auto[precision] = false;
     b->drop_graphs();
     return b->rebuild();
 }
@@ -534,12 +554,13 @@ int lbm_batch_step(lbm_batch* b, long long nsteps, int check) {
     if (rc0 != LBM_OK) return rc0;
     if (b->range_host[2][1] == 0) return LBM_OK;  // nothing active
     hipError_t e;
-    const int flip0 = (int)(b->phase & 1);
-    if (b->launches(nsteps, check != 0) >= 4) {
-        auto key = std::make_tuple(nsteps,
-                                   (check ? 1 : 0) | (b->tb << 1) | (b->th[0] << 4) |
-                                       (b->th[1] << 9) | (b->th[2] << 14),
-                                   flip0,
+    long long nl = 0;
+    for (int p = 0; p < 3; ++p)
+        if (b->grid_for(p)) nl += b->launches(p, nsteps, check != 0);
+    if (nl >= 4) {
+        auto key = std::make_tuple(nsteps, (check ? 1 : 0) | b->flips() << 1,
+                                   b->tb[0] | b->tb[1] << 4 | b->tb[2] << 8,
+                                   b->th[0] | b->th[1] << 6 | b->th[2] << 12,
                                    b->grid_for(0), b->grid_for(1), b->grid_for(2));
         auto it = b->graphs.find(key);
         if (it == b->graphs.end()) {
@@ -547,7 +568,7 @@ int lbm_batch_step(lbm_batch* b, long long nsteps, int check) {
             hipGraph_t gr;
             if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
                 return b->hip_fail(e, "capture");
-            hipError_t le = b->enqueue(nsteps, check != 0, b->cap, b->phase);
+            hipError_t le = b->enqueue(nsteps, check != 0, b->cap);
             if ((e = hipStreamEndCapture(b->cap, &gr)) != hipSuccess) return b->hip_fail(e, "capture");
             if (le != hipSuccess) {
                 (void)hipGraphDestroy(gr);
@@ -562,14 +583,14 @@ int lbm_batch_step(lbm_batch* b, long long nsteps, int check) {
         if ((e = hipGraphLaunch(it->second, b->stream)) != hipSuccess)
             return b->hip_fail(e, "graph launch");
     } else {
-        if ((e = b->enqueue(nsteps, check != 0, b->stream, b->phase)) != hipSuccess)
+        if ((e = b->enqueue(nsteps, check != 0, b->stream)) != hipSuccess)
             return b->hip_fail(e, "batch_step");
     }
-    b->phase += b->launches(nsteps, check != 0);
+    for (int p = 0; p < 3; ++p) b->phase[p] += b->launches(p, nsteps, check != 0);
     for (auto& s : b->slots)
         if (s.active) {
             s.steps += nsteps;
-            if (check) s.checked_phase = b->phase;
+            if (check) s.checked_phase = b->phase[s.L.prec];
         }
     return LBM_OK;
 }
@@ -584,7 +605,7 @@ int lbm_batch_residuals(lbm_batch* b, double* r_host, long long* steps_host) {
     for (int i = 0; i < b->max_slots; ++i) {
         const BSlot& s = b->slots[i];
         steps_host[i] = s.active ? s.steps : -1;
-        if (!s.active || s.checked_phase != b->phase) {
+        if (!s.active || s.checked_phase != b->phase[s.L.prec]) {
             r_host[i] = NAN;
             continue;
         }
@@ -619,8 +640,11 @@ int lbm_batch_promote(lbm_batch* b, int slot) {
                            reinterpret_cast<double*>(L.mem.pbuf[0]), n, factor);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return b->hip_fail(e, "batch_promote");
+    // the last check stays current across the switch of launch parity
+    const bool checked = s.checked_phase == b->phase[L.prec];
     L.prec = LBM_FP64;
-    L.cur = (int)(b->phase & 1);
+    L.cur = (int)(b->phase[LBM_FP64] & 1);
+    s.checked_phase = checked ? b->phase[LBM_FP64] : -1;
     int rc = b->rebuild();
     if (rc != LBM_OK) return rc;
     // reset the undamped modes (staggered moments, mean) excited by the narrow phase

@@ -53,10 +53,11 @@ struct lbm_solver {
     long long steps = 0;
     double r_switch = 0.0;
     int blocks_per_cu = 0;  // 0: one workgroup per tile; k: persistent k per CU
+    bool fused_auto = true;  // fused kernel not chosen by the caller: follows the default
     std::string err;
     // captured chunks keyed by (plain steps, writeU/check kind, start parity,
     // precision, rows per thread, general path, grid)
-    std::map<std::tuple<long long, int, int, int, int, int, unsigned>, hipGraphExec_t> graphs;
+    std::map<std::tuple<long long, int, int, int, int, int, int, unsigned>, hipGraphExec_t> graphs;
 
     int fail(int code, const std::string& m) {
         err = m;
@@ -185,10 +186,11 @@ struct lbm_solver {
 
     hipError_t run_graph(long long nplain, bool writeu, bool check) {
         const int flip0 = (int)(phase & 1);
-        const int kind = (writeu ? 1 : 0) | (check ? 2 : 0) | (L.fused() ? 4 * L.tb : 0) |
-                         (L.fused() ? (L.th << 5) | (L.wave_hs << 10) : 0);
-        auto key = std::make_tuple(nplain, kind, flip0 ^ (L.cur << 1), L.prec, L.eff_vy(),
-                                   (L.general() ? 1 : 0) | (L.inplace ? 2 : 0), grid);
+        const int kind = (writeu ? 1 : 0) | (check ? 2 : 0) | (L.general() ? 4 : 0) |
+                         (L.inplace ? 8 : 0);
+        const int fused = L.fused() ? L.tb | (L.th << 4) : 0;
+        auto key = std::make_tuple(nplain, kind, flip0 ^ (L.cur << 1), L.prec, L.eff_vy(), fused,
+                                   L.fused() ? L.wave_hs : 0, grid);
         auto it = graphs.find(key);
         hipError_t e;
         if (it == graphs.end()) {
@@ -278,9 +280,9 @@ static int create_solver(int nx, int ny, int precision, int with_polish, bool in
     L.polish = with_polish != 0 && precision != LBM_FP64 && !inplace;
     L.inplace = inplace;
     default_tile(precision, nx, ny, L.bx_log2, L.vy);
-    L.tb = inplace ? 1 : default_time_blocking(precision, nx, ny);
-    L.th = fused_th(precision, (long long)nx * ny);
-    L.wave_hs = inplace ? 0 : default_wave_rows(precision, nx, ny, s->cus);
+    L.tb = inplace ? 1 : default_time_blocking(precision, (long long)nx * ny);
+    L.th = fused_th(precision, L.tb, (long long)nx * ny);
+    L.wave_hs = inplace ? 0 : default_fused_wave_rows(precision, L.tb, nx, ny, s->cus);
     char* base = reinterpret_cast<char*>(workspace);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -423,11 +425,17 @@ int lbm_set_tile(lbm_solver* s, int bx_log2, int rows_per_thread, int blocks_per
 
 int lbm_set_time_blocking(lbm_solver* s, int steps_per_launch) {
     if (!s) return LBM_E_ARG;
-    if (steps_per_launch < 1 || steps_per_launch > 4)
-        return s->fail(LBM_E_ARG, "set_time_blocking: steps_per_launch must be in 1..4");
+    if (steps_per_launch < 1 || steps_per_launch > 8)
+        return s->fail(LBM_E_ARG, "set_time_blocking: steps_per_launch must be in 1..8");
     if (s->L.inplace && steps_per_launch != 1)
         return s->fail(LBM_E_STATE, "set_time_blocking: in-place streaming runs one step per launch");
-    s->L.tb = steps_per_launch;
+    Lattice& L = s->L;
+    L.tb = steps_per_launch;
+    L.th = fused_th(L.prec, steps_per_launch, L.N);
+    if (s->fused_auto)
+        L.wave_hs = default_fused_wave_rows(L.prec, steps_per_launch, L.nx, L.ny, s->cus);
+    else if (steps_per_launch > 4)
+        L.wave_hs = 0;  // the wavefront runs 2..4 steps
     return s->sync_desc();
 }
 
@@ -437,14 +445,40 @@ int lbm_set_fused_kernel(lbm_solver* s, int kind, int segment_rows) {
         return s->fail(LBM_E_STATE, "set_fused_kernel: in-place streaming has no fused kernel");
     if (kind == LBM_FUSED_TILE) {
         s->L.wave_hs = 0;
+        s->fused_auto = false;
     } else if (kind == LBM_FUSED_WAVEFRONT) {
         if (segment_rows < 1 || segment_rows > (1 << 20))
             return s->fail(LBM_E_ARG, "set_fused_kernel: segment_rows must be in 1..2^20");
+        if (s->L.tb > 4)
+            return s->fail(LBM_E_STATE,
+                           "set_fused_kernel: the wavefront runs 2..4 steps per launch "
+                           "(set_time_blocking first)");
         s->L.wave_hs = segment_rows;
+        s->fused_auto = false;
     } else {
         return s->fail(LBM_E_ARG, "set_fused_kernel: kind must be LBM_FUSED_TILE or LBM_FUSED_WAVEFRONT");
     }
     return s->sync_desc();
+}
+
+int lbm_get_launch_config(const lbm_solver* s, int out[4]) {
+    if (!s || !out) return LBM_E_ARG;
+    const Lattice& L = s->L;
+    out[0] = L.tb;
+    if (!L.fused()) {
+        out[1] = -1;
+        out[2] = L.inplace ? 0 : L.eff_vy();
+        out[3] = kBlock;
+    } else if (L.wave_hs > 0) {
+        out[1] = LBM_FUSED_WAVEFRONT;
+        out[2] = L.wave_hs;
+        out[3] = kBlock;
+    } else {
+        out[1] = LBM_FUSED_TILE;
+        out[2] = L.th;
+        out[3] = fused_nt(L.prec, L.tb, L.th);
+    }
+    return LBM_OK;
 }
 
 int lbm_step(lbm_solver* s, long long nsteps) {
@@ -490,9 +524,10 @@ int promote_solver(lbm_solver* s) {
     L.cur = 0;
     s->phase = 0;
     default_tile(LBM_FP64, L.nx, L.ny, L.bx_log2, L.vy);
-    L.tb = default_time_blocking(LBM_FP64, L.nx, L.ny);
-    L.th = fused_th(LBM_FP64, L.N);
-    L.wave_hs = default_wave_rows(LBM_FP64, L.nx, L.ny, s->cus);
+    L.tb = default_time_blocking(LBM_FP64, L.N);
+    L.th = fused_th(LBM_FP64, L.tb, L.N);
+    L.wave_hs = default_fused_wave_rows(LBM_FP64, L.tb, L.nx, L.ny, s->cus);
+    s->fused_auto = true;
     // sync_desc folds phase into cur: phase is 0 so cur stays 0
     int rc = s->sync_desc();
     if (rc != LBM_OK) return rc;

@@ -62,22 +62,21 @@ __device__ __forceinline__ void lds_gather(const S* lds, int r, typename Store<S
     f[7] = lds_ld<S>(lds + 7 * RN + r + RW - 1);  // c8 = ( 1,-1)
 }
 
-// Step 1 of the fused kernel for one tile: gathers the ring region from the
-// stored field (periodic coordinates), collides, and writes the post-collision
-// populations to LDS; returns the scaled force of the thread's sites.  Every
-// slot loads (the last slot's spare lanes re-read the region's last site), so
-// all loads are issued before the first use.
+// Step 1 of the fused kernel for one tile, in two parts.  stepN_load issues
+// the loads of the ring region from the stored field (periodic coordinates):
+// the 8 incoming populations and the force of every slot (the last slot's
+// spare lanes re-read the region's last site), so that all loads are in
+// flight before the first use.  stepN_collide1 scales the force, collides and
+// writes the post-collision populations to LDS.
 template <typename S, int TH, int NS, int NT = kBlock>
-__device__ __forceinline__ void stepN_first(const S* __restrict__ src,
-                                            const typename Store<S>::C* __restrict__ g,
-                                            long long plane, int nx, int ny, int x0, int y0,
-                                            const Coef<typename Store<S>::C>& k, S* lds,
-                                            typename Store<S>::C gx[], typename Store<S>::C gy[]) {
-    using C = typename Store<S>::C;
+__device__ __forceinline__ void stepN_load(const S* __restrict__ src,
+                                           const typename Store<S>::C* __restrict__ g,
+                                           long long plane, int nx, int ny, int x0, int y0,
+                                           typename Store<S>::C f[][8],
+                                           typename Store<S>::C gx[], typename Store<S>::C gy[]) {
     constexpr int R = NS - 1;
     constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
     constexpr int NM = (RN + NT - 1) / NT;
-    C f[NM][8];
 #pragma unroll
     for (int a = 0; a < NM; ++a) {
         const int e = min((int)threadIdx.x + a * NT, RN - 1);
@@ -88,6 +87,17 @@ __device__ __forceinline__ void stepN_first(const S* __restrict__ src,
         gx[a] = glob(g)[sidx];
         gy[a] = glob(g)[plane + sidx];
     }
+}
+
+template <typename S, int TH, int NS, int NT = kBlock>
+__device__ __forceinline__ void stepN_collide1(typename Store<S>::C f[][8],
+                                               const Coef<typename Store<S>::C>& k, S* lds,
+                                               typename Store<S>::C gx[],
+                                               typename Store<S>::C gy[]) {
+    using C = typename Store<S>::C;
+    constexpr int R = NS - 1;
+    constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
+    constexpr int NM = (RN + NT - 1) / NT;
 #pragma unroll
     for (int a = 0; a < NM; ++a) {
         const int e = (int)threadIdx.x + a * NT;
@@ -102,6 +112,63 @@ __device__ __forceinline__ void stepN_first(const S* __restrict__ src,
     }
 }
 
+// Steps 2..NS of the fused kernel for one tile whose step 1 is in LDS: middle
+// steps on rings R-1 .. 1 (LDS -> registers -> LDS, in place), then the tile
+// from LDS to the destination field.
+template <typename S, int TH, int NS, int NT = kBlock>
+__device__ __forceinline__ void stepN_rest(S* __restrict__ dst, long long plane, int nx, int ny,
+                                           int x0, int y0, const Coef<typename Store<S>::C>& k,
+                                           S* lds, const typename Store<S>::C gx[],
+                                           const typename Store<S>::C gy[]) {
+    using C = typename Store<S>::C;
+    constexpr int R = NS - 1;
+    constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
+    constexpr int NM = (RN + NT - 1) / NT;
+    C f[NM][8];
+    // plane base pointers are wave-uniform: one 64-bit add per store
+    S* pq[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) pq[q] = dst + q * plane;
+#pragma unroll
+    for (int m = 1; m < R; ++m) {
+#pragma unroll
+        for (int a = 0; a < NM; ++a) {
+            const int e = (int)threadIdx.x + a * NT;
+            const int i = e % RW, j = e / RW;
+            if (e < RN && i >= m && i < RW - m && j >= m && j < RH - m)
+                lds_gather<S, RW, RN>(lds, e, f[a]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < NM; ++a) {
+            const int e = (int)threadIdx.x + a * NT;
+            const int i = e % RW, j = e / RW;
+            if (e < RN && i >= m && i < RW - m && j >= m && j < RH - m) {
+                C ux, uy;
+                collide<C, false>(f[a], gx[a], gy[a], k, ux, uy);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) lds_st<S>(lds + q * RN + e, f[a][q]);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < NM; ++a) {
+        const int e = (int)threadIdx.x + a * NT;
+        const int i = e % RW, j = e / RW;
+        const int x = x0 + i - R, y = y0 + j - R;
+        if (e < RN && i >= R && i < R + kTW && j >= R && j < R + TH && x < nx && y < ny) {
+            lds_gather<S, RW, RN>(lds, e, f[a]);
+            C ux, uy;
+            collide<C, false>(f[a], gx[a], gy[a], k, ux, uy);
+            const long long sidx = (long long)y * nx + x;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) Store<S>::st(pq[q] + sidx, f[a][q]);
+        }
+    }
+    __syncthreads();
+}
+
 template <typename S, int TH, int NS, int NT = kBlock>
 static __global__ __launch_bounds__(NT) void k_stepN(StepLaunch L) {
     using C = typename Store<S>::C;
@@ -114,59 +181,18 @@ static __global__ __launch_bounds__(NT) void k_stepN(StepLaunch L) {
     for (; it < last; it += stride) {
         const Item item = L.items[it];
         const SlotDesc& d = L.slots[item.slot];
-        const int nx = d.nx, ny = d.ny;
-        const long long plane = d.plane;
         const int sel = d.cur ^ L.flip;
-        const S* __restrict__ src = reinterpret_cast<const S*>(d.buf[sel]);
-        S* __restrict__ dst = reinterpret_cast<S*>(d.buf[sel ^ 1]);
-        const C* __restrict__ g = reinterpret_cast<const C*>(d.g);
         Coef<C> k;
         k.load(d);
         const int x0 = item.tx * kTW, y0 = item.ty * TH;
         C f[NM][8], gx[NM], gy[NM];
-        // step 1: tile + ring R, HBM -> LDS
-        stepN_first<S, TH, NS, NT>(src, g, plane, nx, ny, x0, y0, k, lds, gx, gy);
+        stepN_load<S, TH, NS, NT>(reinterpret_cast<const S*>(d.buf[sel]),
+                                  reinterpret_cast<const C*>(d.g), d.plane, d.nx, d.ny, x0, y0,
+                                  f, gx, gy);
+        stepN_collide1<S, TH, NS, NT>(f, k, lds, gx, gy);
         __syncthreads();
-        // middle steps: ring R - m, LDS -> registers -> LDS (in place)
-#pragma unroll
-        for (int m = 1; m < R; ++m) {
-#pragma unroll
-            for (int a = 0; a < NM; ++a) {
-                const int e = (int)threadIdx.x + a * NT;
-                const int i = e % RW, j = e / RW;
-                if (e < RN && i >= m && i < RW - m && j >= m && j < RH - m)
-                    lds_gather<S, RW, RN>(lds, e, f[a]);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int a = 0; a < NM; ++a) {
-                const int e = (int)threadIdx.x + a * NT;
-                const int i = e % RW, j = e / RW;
-                if (e < RN && i >= m && i < RW - m && j >= m && j < RH - m) {
-                    C ux, uy;
-                    collide<C, false>(f[a], gx[a], gy[a], k, ux, uy);
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) lds_st<S>(lds + q * RN + e, f[a][q]);
-                }
-            }
-            __syncthreads();
-        }
-        // last step: the tile, LDS -> HBM
-#pragma unroll
-        for (int a = 0; a < NM; ++a) {
-            const int e = (int)threadIdx.x + a * NT;
-            const int i = e % RW, j = e / RW;
-            const int x = x0 + i - R, y = y0 + j - R;
-            if (e < RN && i >= R && i < R + kTW && j >= R && j < R + TH && x < nx && y < ny) {
-                lds_gather<S, RW, RN>(lds, e, f[a]);
-                C ux, uy;
-                collide<C, false>(f[a], gx[a], gy[a], k, ux, uy);
-                const long long sidx = (long long)y * nx + x;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * plane + sidx, f[a][q]);
-            }
-        }
-        __syncthreads();
+        stepN_rest<S, TH, NS, NT>(reinterpret_cast<S*>(d.buf[sel ^ 1]), d.plane, d.nx, d.ny, x0, y0,
+                                  k, lds, gx, gy);
     }
 }
 

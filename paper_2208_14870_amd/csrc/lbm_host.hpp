@@ -123,32 +123,47 @@ inline hipError_t launch_check_state(int prec, int vy, int layout, unsigned grid
     return hipGetLastError();
 }
 
-// Tile height of the fused LDS kernel (width 64), measured on MI355X: FP64 8
-// (two workgroups per CU by LDS); FP32 16, or 8 on lattices of up to 2^21
-// sites, where more and smaller tiles balance the grid better; FP16 12.
-inline int fused_th(int prec, long long sites) {
+// Shapes of the fused LDS tile kernel (tile 64 x TH, NT threads) per storage
+// type and steps per launch, measured on MI355X.  Up to four steps: FP64 8
+// rows, FP32 8 rows with 512 threads up to 2^21 sites and 16 rows with 256
+// threads above, FP16 12 rows.  Five to eight steps: FP32 16 rows with 512
+// threads (two workgroups of 75 KB LDS per CU at eight steps), FP16 16 rows,
+// FP64 8 rows.
+inline int fused_th(int prec, int ns, long long sites) {
     if (prec == LBM_FP64) return 8;
-    if (prec == LBM_FP32) return sites <= (1LL << 21) ? 8 : 16;
-    return 12;
+    if (prec == LBM_FP32) return (ns <= 4 && sites <= (1LL << 21)) ? 8 : 16;
+    return ns <= 4 ? 12 : 16;
 }
 
-template <typename S, int TH, int NT = kBlock>
-inline void launch_stepN_t(int ns, unsigned grid, hipStream_t st, const StepLaunch& L) {
-    if (ns == 2) hipLaunchKernelGGL((k_stepN<S, TH, 2, NT>), dim3(grid), dim3(NT), 0, st, L);
-    else if (ns == 3) hipLaunchKernelGGL((k_stepN<S, TH, 3, NT>), dim3(grid), dim3(NT), 0, st, L);
-    else hipLaunchKernelGGL((k_stepN<S, TH, 4, NT>), dim3(grid), dim3(NT), 0, st, L);
+// Threads per workgroup of the fused LDS tile kernel (as launch_stepN runs it).
+inline int fused_nt(int prec, int ns, int th) {
+    if (prec == LBM_FP64) return kBlock;
+    if (prec == LBM_FP32) return (th == 8 || ns > 4) ? 512 : 256;
+    return ns > 4 ? 512 : 256;
 }
 
-// th must be a height fused_th returns for prec.  The 8-row FP32 tiles run with
-// 512 threads (measured on MI355X at 1024^2: 152 against 145 GLUPS; taller
-// tiles and the other types are faster with 256).
+template <typename S, int TH, int NT, int NS, int NSMAX>
+inline bool launch_stepN_ns(int ns, unsigned grid, hipStream_t st, const StepLaunch& L) {
+    if (ns == NS) {
+        hipLaunchKernelGGL((k_stepN<S, TH, NS, NT>), dim3(grid), dim3(NT), 0, st, L);
+        return true;
+    }
+    if constexpr (NS < NSMAX) return launch_stepN_ns<S, TH, NT, NS + 1, NSMAX>(ns, grid, st, L);
+    return false;
+}
+
+// ns in 2..8; th must be the height fused_th returns for (prec, ns).
 inline hipError_t launch_stepN(int prec, int ns, int th, unsigned grid, hipStream_t st,
                                const StepLaunch& L) {
-    if (prec == LBM_FP64 && th == 8) launch_stepN_t<double, 8>(ns, grid, st, L);
-    else if (prec == LBM_FP32 && th == 8) launch_stepN_t<float, 8, 512>(ns, grid, st, L);
-    else if (prec == LBM_FP32 && th == 16) launch_stepN_t<float, 16>(ns, grid, st, L);
-    else if (prec == LBM_FP16 && th == 12) launch_stepN_t<__half, 12>(ns, grid, st, L);
-    else return hipErrorInvalidValue;
+    bool ok = false;
+    if (prec == LBM_FP64 && th == 8) ok = launch_stepN_ns<double, 8, 256, 2, 8>(ns, grid, st, L);
+    else if (prec == LBM_FP32 && th == 8) ok = launch_stepN_ns<float, 8, 512, 2, 4>(ns, grid, st, L);
+    else if (prec == LBM_FP32 && th == 16 && ns <= 4)
+        ok = launch_stepN_ns<float, 16, 256, 2, 4>(ns, grid, st, L);
+    else if (prec == LBM_FP32 && th == 16) ok = launch_stepN_ns<float, 16, 512, 5, 8>(ns, grid, st, L);
+    else if (prec == LBM_FP16 && th == 12) ok = launch_stepN_ns<__half, 12, 256, 2, 4>(ns, grid, st, L);
+    else if (prec == LBM_FP16 && th == 16) ok = launch_stepN_ns<__half, 16, 512, 5, 8>(ns, grid, st, L);
+    if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -188,15 +203,17 @@ inline hipError_t launch_wave(int prec, int ns, int nx, int ny, int hs, const Sl
     return hipGetLastError();
 }
 
-// Default fused kernel (measured on MI355X): the register wavefront for FP64
-// lattices of at least 2^22 sites and for even-width FP32 lattices of at least
-// 2^25 sites, the LDS tile kernel otherwise (smaller lattices, FP16).  The
+// Default fused kernel at up to four steps per launch (measured on MI355X):
+// the register wavefront for FP64 lattices of more than 2^22 sites (2048^2:
+// tile 99 against 87 GLUPS; 2896^2: wavefront 106 against 97) and for
+// even-width FP32 lattices of at least 2^25 sites, the LDS tile kernel
+// otherwise (smaller lattices, FP16).  The
 // segment height is the tallest of 256, 128, 64, 32 rows that still gives
 // 18 waves per compute unit (fewer leave SIMDs idle; shorter segments
 // recompute more halo rows).  Returns the segment height, 0 for the tile kernel.
 inline int default_wave_rows(int prec, int nx, int ny, int cus) {
     const long long n = (long long)nx * ny;
-    const bool use = (prec == LBM_FP64 && n >= (1LL << 22)) ||
+    const bool use = (prec == LBM_FP64 && n > (1LL << 22)) ||
                      (prec == LBM_FP32 && n >= (1LL << 25) && nx % 2 == 0);
     if (!use) return 0;
     const long long strips = (nx + wave_width_of(4, wave_cols_per_lane(prec, nx)) - 1) /
@@ -206,13 +223,24 @@ inline int default_wave_rows(int prec, int nx, int ny, int cus) {
     return 32;
 }
 
-// Default steps per launch (measured on MI355X: four is fastest or tied for
-// every storage type at 1024^2 and 8192^2).
-inline int default_time_blocking(int prec, int nx, int ny) {
-    (void)prec;
-    (void)nx;
-    (void)ny;
+// Default steps per launch for `sites` lattice sites (of one lattice, or of
+// all lattices of one storage type in a batch), measured on MI355X: the LDS
+// tile kernel is bound by its per-launch memory phase, so deeper blocking pays
+// until LDS limits the workgroups per CU.  FP32: eight above 2^17 sites (1024^2:
+// 218 against 150 GLUPS; 8192^2: 260 against 206 for the four-step
+// wavefront), four on smaller lattices.  FP16: eight up to 2^21 sites, four
+// above (equal at 2048^2, 317 against 306 GLUPS at 8192^2).  FP64: four (its
+// LDS tile is twice as large).
+inline int default_time_blocking(int prec, long long sites) {
+    if (prec == LBM_FP32) return sites > (1LL << 17) ? 8 : 4;
+    if (prec == LBM_FP16) return sites <= (1LL << 21) ? 8 : 4;
     return 4;
+}
+
+// Default fused kernel for `ns` steps per launch: the register wavefront runs
+// two to four steps, so deeper blocking uses the tile kernel.
+inline int default_fused_wave_rows(int prec, int ns, int nx, int ny, int cus) {
+    return ns <= 4 ? default_wave_rows(prec, nx, ny, cus) : 0;
 }
 
 inline hipError_t launch_step(int prec, int mode, bool general, int vy, int layout, unsigned grid,

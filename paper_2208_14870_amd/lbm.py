@@ -70,6 +70,7 @@ def load() -> ctypes.CDLL:
         "lbm_debug_stream_only": (i, [vp, ll]),
         "lbm_set_time_blocking": (i, [vp, i]),
         "lbm_set_fused_kernel": (i, [vp, i, i]),
+        "lbm_get_launch_config": (i, [vp, pi]),
         "lbm_workspace_bytes_inplace": (sz, [i, i, i]),
         "lbm_create_inplace": (i, [i, i, i, vp, sz, vp, ctypes.POINTER(vp)]),
         "lbm_last_error": (ctypes.c_char_p, [vp]),
@@ -85,6 +86,7 @@ def load() -> ctypes.CDLL:
         "lbm_batch_set_tile": (i, [vp, i, i, i]),
         "lbm_batch_info": (i, [vp, pi, ctypes.POINTER(sz), ctypes.POINTER(sz)]),
         "lbm_batch_set_time_blocking": (i, [vp, i]),
+        "lbm_batch_set_time_blocking_for": (i, [vp, i, i]),
         "lbm_batch_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sigs.items():
@@ -243,6 +245,15 @@ class Solver:
     def set_time_blocking(self, steps_per_launch: int):
         self._check(self.lib.lbm_set_time_blocking(self.h, int(steps_per_launch)))
 
+    def launch_config(self) -> dict:
+        """Steps per launch, fused kernel ("tile", "wavefront" or "single"),
+        its rows (tile rows, segment rows, or rows per thread) and threads per
+        workgroup; see lbm_get_launch_config."""
+        out = (ctypes.c_int * 4)()
+        self._check(self.lib.lbm_get_launch_config(self.h, out))
+        kind = {0: "tile", 1: "wavefront"}.get(out[1], "single")
+        return {"steps_per_launch": out[0], "kernel": kind, "rows": out[2], "threads": out[3]}
+
     def set_fused_kernel(self, kind: str, segment_rows: int = 256):
         """kind "tile" (LDS tile kernel) or "wavefront" (register wavefront with
         segments of `segment_rows` rows); see lbm_set_fused_kernel."""
@@ -369,8 +380,13 @@ class Batch:
         self._check(self.lib.lbm_batch_set_tile(self.h, int(bx_log2), int(rows_per_thread),
                                                 int(blocks_per_cu)))
 
-    def set_time_blocking(self, steps_per_launch: int):
-        self._check(self.lib.lbm_batch_set_time_blocking(self.h, int(steps_per_launch)))
+    def set_time_blocking(self, steps_per_launch: int, precision: Optional[str] = None):
+        """Steps per launch (1..8) for every storage type, or for `precision` only."""
+        if precision is None:
+            self._check(self.lib.lbm_batch_set_time_blocking(self.h, int(steps_per_launch)))
+        else:
+            self._check(self.lib.lbm_batch_set_time_blocking_for(
+                self.h, PRECISIONS[precision], int(steps_per_launch)))
 
     def displacements(self, slots):
         """Displacements of several lattices as host arrays [(ux, uy), ...]:

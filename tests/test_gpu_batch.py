@@ -109,6 +109,45 @@ def test_mixed_precisions_match_single_solvers():
         s.close()
 
 
+def test_per_precision_time_blocking():
+    """Each storage type runs its own steps per launch (and keeps its own
+    launch parity): FP64 at 3, FP32 at 7, FP16 at 1 then 5 steps per launch,
+    with residual checks and a promotion of a polish lattice in between, give
+    every lattice the populations of a batch stepping once per launch."""
+    say("batch per-precision time blocking")
+    cases = _cases()
+    precs = ["fp64", "fp32", "fp16", "fp32", "fp16", "fp64"]
+    runs = []
+    for mixed in (False, True):
+        b = _batch()
+        slots = [b.add(c.nx, c.ny, c.material.lame_lambda, c.material.lame_mu, dev(c.gx),
+                       dev(c.gy), p, with_polish=(p != "fp64")) for c, p in zip(cases, precs)]
+        if mixed:
+            b.set_time_blocking(3, "fp64")
+            b.set_time_blocking(7, "fp32")
+            b.set_time_blocking(1, "fp16")
+        else:
+            b.set_time_blocking(1)
+        b.step(23, check=True)
+        r1, _ = b.residuals()
+        b.promote(slots[1])
+        if mixed:
+            b.set_time_blocking(5, "fp16")
+        b.step(30)
+        b.step(17, check=True)
+        r2, n2 = b.residuals()
+        u = [tuple(host(t) for t in b.displacement(sl)) for sl in slots]
+        runs.append((u, [r1[sl] for sl in slots], [r2[sl] for sl in slots], [n2[sl] for sl in slots]))
+        b.close()
+    (u0, a0, b0, n0), (u1, a1, b1, n1) = runs
+    assert n0 == n1 == [70] * len(cases)
+    for k, p in enumerate(precs):
+        for x, y in zip(u0[k], u1[k]):
+            np.testing.assert_array_equal(x, y, err_msg=f"{p} {cases[k].label}")
+        for r0, r1_ in ((a0[k], a1[k]), (b0[k], b1[k])):
+            assert np.isfinite(r0) and r1_ == pytest.approx(r0, rel=1e-12)
+
+
 def test_deferred_work_list():
     """Adds and removals between steps only mark the work list stale: several of
     them followed by one step give the same results as single solvers; reading

@@ -268,7 +268,7 @@ def test_full_size_8192_sampled(prec, tol):
     ("fp64", 64, 8, 4), ("fp32", 2, 2, 5), ("fp32", 65, 17, 9), ("fp32", 256, 48, 12),
     ("fp16", 5, 3, 5), ("fp16", 97, 31, 8), ("fp64", 1024, 1024, 6)])
 def test_time_blocking_identical_to_single_steps(prec, nx, ny, steps):
-    """Two to four steps per launch (tile + ring in LDS) give bit-identical
+    """Two to eight steps per launch (tile + ring in LDS) give bit-identical
     populations to single steps (ragged tiles, lattices smaller than the tile,
     step counts that leave remainders, checks interleaved with fused launches),
     and the FP64 result matches the oracle."""
@@ -276,7 +276,7 @@ def test_time_blocking_identical_to_single_steps(prec, nx, ny, steps):
     mat = P.Material.from_shear_poisson(0.9, 0.3)
     f0, gx, gy = _rand_state(nx, ny, 3 + nx)
     res = {}
-    for tb in (1, 2, 3, 4):
+    for tb in range(1, 9):
         s = _solver(nx, ny, prec)
         s.set_material(mat.lame_lambda, mat.lame_mu)
         s.set_body_force(dev(gx), dev(gy))
@@ -286,14 +286,47 @@ def test_time_blocking_identical_to_single_steps(prec, nx, ny, steps):
         a = host(s.populations())
         n, r, st = s.solve_to_tol(0.0, 11, 5)  # residual checks between fused launches
         res[tb] = (a, host(s.populations()), n, r)
-    for tb in (2, 3, 4):
-        np.testing.assert_array_equal(res[tb][0], res[1][0])
-        np.testing.assert_array_equal(res[tb][1], res[1][1])
+        s.close()
+    for tb in range(2, 9):
+        np.testing.assert_array_equal(res[tb][0], res[1][0], err_msg=f"{tb} steps per launch")
+        np.testing.assert_array_equal(res[tb][1], res[1][1], err_msg=f"{tb} steps per launch")
         # the residual's summation order follows the tile shape: equal to rounding
         assert res[tb][2] == res[1][2] and res[tb][3] == pytest.approx(res[1][3], rel=1e-12)
     if prec == "fp64":
         fn = O.run(f0, gx, gy, omega(mat), steps)
         assert rel_l2(res[2][0], fn) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,nx,ny,steps,bpc", [
+    ("fp32", 1024, 1024, 12, 1), ("fp32", 1024, 1024, 9, 2), ("fp32", 1000, 998, 11, 3),
+    ("fp64", 300, 200, 10, 1), ("fp64", 130, 9, 7, 2), ("fp16", 130, 90, 8, 1),
+    ("fp32", 65, 17, 9, 3), ("fp32", 3000, 40, 8, 1), ("fp64", 1024, 1024, 8, 2)])
+def test_pipelined_tile_identical_to_single_steps(prec, nx, ny, steps, bpc):
+    """Persistent fused launches (bpc workgroups per CU, fewer than the tiles:
+    each workgroup loads its next tile's step-1 inputs while it finishes the
+    current tile) give populations bit-identical to single steps, with residual
+    checks interleaved."""
+    say(f"pipelined tile {prec} {nx}x{ny} steps {steps} blocks/CU {bpc}")
+    mat = P.Material.from_shear_poisson(0.9, 0.3)
+    f0, gx, gy = _rand_state(nx, ny, 7 + nx)
+    res = {}
+    for tb in (1, 3, 4):
+        s = _solver(nx, ny, prec)
+        s.set_material(mat.lame_lambda, mat.lame_mu)
+        s.set_body_force(dev(gx), dev(gy))
+        s.set_populations(dev(f0))
+        if tb > 1:
+            s.set_tile(6, 2, bpc)
+        s.set_time_blocking(tb)
+        s.step(steps)
+        a = host(s.populations())
+        n, r, st = s.solve_to_tol(0.0, 11, 5)
+        res[tb] = (a, host(s.populations()), n, r)
+        s.close()
+    for tb in (3, 4):
+        np.testing.assert_array_equal(res[tb][0], res[1][0])
+        np.testing.assert_array_equal(res[tb][1], res[1][1])
+        assert res[tb][2] == res[1][2] and res[tb][3] == pytest.approx(res[1][3], rel=1e-12)
 
 
 @pytest.mark.parametrize("prec,nx,ny,steps,rows", [
@@ -333,6 +366,9 @@ def test_wavefront_identical_to_single_steps(prec, nx, ny, steps, rows):
 
 
 def test_fused_kernel_argument_errors():
+    """Steps per launch outside 1..8 and the wavefront beyond four steps are
+    refused; deeper blocking switches a wavefront solver to the tile kernel,
+    with results unchanged."""
     from paper_2208_14870_amd import lbm
     s = _solver(16, 16, "fp32")
     with pytest.raises(lbm.LbmError):
@@ -340,6 +376,64 @@ def test_fused_kernel_argument_errors():
     with pytest.raises(KeyError):
         s.set_fused_kernel("other", 4)
     s.set_fused_kernel("tile")
+    for bad in (0, 9):
+        with pytest.raises(lbm.LbmError):
+            s.set_time_blocking(bad)
+    s.set_time_blocking(6)
+    with pytest.raises(lbm.LbmError):
+        s.set_fused_kernel("wavefront", 16)
+    mat = P.Material.from_shear_poisson(0.9, 0.3)
+    f0, gx, gy = _rand_state(40, 24, 11)
+    out = []
+    for deep in (False, True):
+        s = _solver(40, 24, "fp32")
+        s.set_material(mat.lame_lambda, mat.lame_mu)
+        s.set_body_force(dev(gx), dev(gy))
+        s.set_populations(dev(f0))
+        s.set_time_blocking(4)
+        s.set_fused_kernel("wavefront", 8)
+        if deep:
+            s.set_time_blocking(8)  # leaves the wavefront for the tile kernel
+        s.step(16)
+        out.append(host(s.populations()))
+        s.close()
+    np.testing.assert_array_equal(out[0], out[1])
+
+
+def test_launch_config_defaults():
+    """Default plain-step launches: eight steps per launch through the LDS tile
+    (16 rows, 512 threads) for FP32 above 2^17 sites and FP16 up to 2^21, four
+    otherwise and for FP64 (the wavefront above 2^22 FP64 sites); deeper
+    blocking leaves the wavefront; one step per launch in place."""
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    cfg = lambda n, m, p, **kw: lbm.Solver(n, m, p, **kw).launch_config()
+    assert cfg(1024, 1024, "fp32") == {"steps_per_launch": 8, "kernel": "tile", "rows": 16,
+                                       "threads": 512}
+    assert cfg(96, 64, "fp16") == {"steps_per_launch": 8, "kernel": "tile", "rows": 16,
+                                   "threads": 512}
+    assert cfg(4096, 4096, "fp16") == {"steps_per_launch": 4, "kernel": "tile", "rows": 12,
+                                       "threads": 256}
+    assert cfg(256, 256, "fp32") == {"steps_per_launch": 4, "kernel": "tile", "rows": 8,
+                                     "threads": 512}
+    assert cfg(1024, 1024, "fp64") == {"steps_per_launch": 4, "kernel": "tile", "rows": 8,
+                                       "threads": 256}
+    assert cfg(2048, 2048, "fp64")["kernel"] == "tile"
+    s = lbm.Solver(2900, 2900, "fp64")
+    c = s.launch_config()
+    assert c["kernel"] == "wavefront" and c["steps_per_launch"] == 4 and c["rows"] in (32, 64, 128, 256)
+    s.set_time_blocking(6)
+    assert s.launch_config() == {"steps_per_launch": 6, "kernel": "tile", "rows": 8, "threads": 256}
+    s.set_time_blocking(3)  # default kernel again at three steps
+    assert s.launch_config()["kernel"] == "wavefront"
+    s.set_fused_kernel("tile")
+    s.set_time_blocking(4)  # the caller's choice stays
+    assert s.launch_config()["kernel"] == "tile"
+    s.set_time_blocking(1)
+    assert s.launch_config()["kernel"] == "single"
+    s.close()
+    c = cfg(256, 256, "fp32", inplace=True)
+    assert c["steps_per_launch"] == 1 and c["kernel"] == "single"
 
 
 # ---------------------------------------------------------------------------

@@ -39,7 +39,7 @@ def test_shape_sweep(prec, seed):
     for k, (nx, ny) in enumerate(_shapes(seed, 24)):
         f0, gx, gy = _state(nx, ny, seed * 1000 + k)
         steps = int(rng.integers(5, 14))
-        configs = [("single", 1, None), ("tile", int(rng.integers(2, 5)), None),
+        configs = [("single", 1, None), ("tile", int(rng.integers(2, 9)), None),
                    ("wavefront", int(rng.integers(2, 5)), int(rng.choice([1, 2, 3, 7, 16, 64]))),
                    ("inplace", 1, None)]
         ref = None
