@@ -92,20 +92,24 @@ def _store(path: str, data: Dict[str, list]):
 def time_shapes(set_shape: Callable[[Shape], None], step: Callable[[int], None],
                 shapes: Iterable[Shape], sites: int, target_ms: float = 3.0,
                 repeats: int = 3) -> List[Tuple[float, Shape]]:
-    """Returns [(microseconds per step, shape)] sorted fastest first."""
+    """Returns [(microseconds per step, shape)] sorted fastest first.  Step
+    counts are whole multiples of the shape's steps per launch, so that only
+    the shape's own launches are timed."""
     res = []
     for shp in shapes:
         set_shape(shp)
-        step(4)  # warm the shape (graph capture, caches)
+        t = max(1, shp[3])
+        k = 4 * t
+        step(k)  # warm the shape (graph capture, caches)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        step(4)
+        step(k)
         e1.record()
         torch.cuda.synchronize()
-        per = max(e0.elapsed_time(e1) / 4, 1e-4)
-        n = max(4, min(4000, int(target_ms / per)))
+        per = max(e0.elapsed_time(e1) / k, 1e-4)
+        n = max(k, min(4000, int(target_ms / per)) // t * t)
         best = float("inf")
         for _ in range(repeats):
             e0.record()
