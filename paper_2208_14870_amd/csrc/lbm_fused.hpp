@@ -12,11 +12,18 @@ namespace lbm {
 // A workgroup owns an output tile of 64 x TH sites.  Step 1 advances the tile
 // plus a ring of NS-1 sites (periodic coordinates) from the stored field in
 // HBM and keeps the post-collision populations in LDS, rounded to the storage
-// type exactly as a store to HBM would; each middle step gathers from LDS into
-// registers, waits for the whole workgroup, collides and writes back in place
-// on a ring one site narrower; the last step advances the tile and writes it
-// to HBM.  The result is that of NS single steps, with one HBM read and one
-// HBM write of the populations per NS updates.
+// type exactly as a store to HBM would; each middle step advances a ring one
+// site narrower from LDS back into LDS; the last step advances the tile and
+// writes it to HBM.  The result is that of NS single steps, with one HBM read
+// and one HBM write of the populations per NS updates.
+//
+// The LDS copy alternates between two layouts, as in-place streaming does in
+// HBM, so that within a step every LDS location a site writes is read in that
+// step by the same site only, and one barrier per step suffices.  Swapped:
+// plane opp(q) at r holds f*_q(r), the populations leaving r; step 1 and the
+// other odd steps write it at their own site.  Natural: plane q at r holds
+// f_q(r), the populations arriving at r; even steps read the swapped copy of
+// their upstream neighbours and push into it at the downstream neighbours.
 //
 // NT threads per workgroup (256, or 512 for the short FP32 tiles, which
 // halves each thread's share of a tile's dependent steps).  Every thread keeps
@@ -49,17 +56,35 @@ __device__ __forceinline__ int wrap_coord(int v, int n) {
     return v;
 }
 
-// Gather of the 8 populations arriving at LDS position r (row stride RW).
+// LDS offset of the neighbour r + c_q (row stride RW; q in the order of the
+// velocity table, 0-based).
+template <int RW>
+__device__ __forceinline__ constexpr int lds_shift(int q) {
+    return ((q == 0 || q == 4 || q == 7) ? 1 : (q == 2 || q == 5 || q == 6) ? -1 : 0) +
+           RW * ((q == 1 || q == 4 || q == 5) ? 1 : (q == 3 || q == 6 || q == 7) ? -1 : 0);
+}
+
+// The 8 populations arriving at LDS position r, from the swapped layout (the
+// upstream neighbours' post-collision values) or the natural one (own site).
 template <typename S, int RW, int RN>
-__device__ __forceinline__ void lds_gather(const S* lds, int r, typename Store<S>::C f[8]) {
-    f[0] = lds_ld<S>(lds + 0 * RN + r - 1);       // c1 = ( 1, 0)
-    f[1] = lds_ld<S>(lds + 1 * RN + r - RW);      // c2 = ( 0, 1)
-    f[2] = lds_ld<S>(lds + 2 * RN + r + 1);       // c3 = (-1, 0)
-    f[3] = lds_ld<S>(lds + 3 * RN + r + RW);      // c4 = ( 0,-1)
-    f[4] = lds_ld<S>(lds + 4 * RN + r - RW - 1);  // c5 = ( 1, 1)
-    f[5] = lds_ld<S>(lds + 5 * RN + r - RW + 1);  // c6 = (-1, 1)
-    f[6] = lds_ld<S>(lds + 6 * RN + r + RW + 1);  // c7 = (-1,-1)
-    f[7] = lds_ld<S>(lds + 7 * RN + r + RW - 1);  // c8 = ( 1,-1)
+__device__ __forceinline__ void lds_read(const S* lds, int r, bool swapped,
+                                         typename Store<S>::C f[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        f[q] = swapped ? lds_ld<S>(lds + opp(q) * RN + r - lds_shift<RW>(q))
+                       : lds_ld<S>(lds + q * RN + r);
+}
+
+// The post-collision populations of LDS position r: to its own site in the
+// swapped layout, or pushed to the downstream neighbours in the natural one.
+template <typename S, int RW, int RN>
+__device__ __forceinline__ void lds_write(S* lds, int r, bool swapped,
+                                          const typename Store<S>::C f[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        if (swapped) lds_st<S>(lds + opp(q) * RN + r, f[q]);
+        else lds_st<S>(lds + q * RN + r + lds_shift<RW>(q), f[q]);
+    }
 }
 
 // Step 1 of the fused kernel for one tile, in two parts.  stepN_load issues
@@ -105,16 +130,15 @@ __device__ __forceinline__ void stepN_collide1(typename Store<S>::C f[][8],
         gy[a] *= k.gscale;
         C ux, uy;
         collide<C, false>(f[a], gx[a], gy[a], k, ux, uy);
-        if (e < RN) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) lds_st<S>(lds + q * RN + e, f[a][q]);
-        }
+        if (e < RN) lds_write<S, RW, RN>(lds, e, true, f[a]);
     }
 }
 
 // Steps 2..NS of the fused kernel for one tile whose step 1 is in LDS: middle
-// steps on rings R-1 .. 1 (LDS -> registers -> LDS, in place), then the tile
-// from LDS to the destination field.
+// steps on rings R-1 .. 1 (LDS -> registers -> LDS), then the tile from LDS to
+// the destination field.  Step k reads the swapped layout when k is even and
+// writes the natural one (and the reverse when k is odd); one barrier after
+// each step.
 template <typename S, int TH, int NS, int NT = kBlock>
 __device__ __forceinline__ void stepN_rest(S* __restrict__ dst, long long plane, int nx, int ny,
                                            int x0, int y0, const Coef<typename Store<S>::C>& k,
@@ -124,46 +148,39 @@ __device__ __forceinline__ void stepN_rest(S* __restrict__ dst, long long plane,
     constexpr int R = NS - 1;
     constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
     constexpr int NM = (RN + NT - 1) / NT;
-    C f[NM][8];
     // plane base pointers are wave-uniform: one 64-bit add per store
     S* pq[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) pq[q] = dst + q * plane;
 #pragma unroll
     for (int m = 1; m < R; ++m) {
-#pragma unroll
-        for (int a = 0; a < NM; ++a) {
-            const int e = (int)threadIdx.x + a * NT;
-            const int i = e % RW, j = e / RW;
-            if (e < RN && i >= m && i < RW - m && j >= m && j < RH - m)
-                lds_gather<S, RW, RN>(lds, e, f[a]);
-        }
-        __syncthreads();
+        const bool even = (m & 1) != 0;  // step m + 1
 #pragma unroll
         for (int a = 0; a < NM; ++a) {
             const int e = (int)threadIdx.x + a * NT;
             const int i = e % RW, j = e / RW;
             if (e < RN && i >= m && i < RW - m && j >= m && j < RH - m) {
-                C ux, uy;
-                collide<C, false>(f[a], gx[a], gy[a], k, ux, uy);
-#pragma unroll
-                for (int q = 0; q < 8; ++q) lds_st<S>(lds + q * RN + e, f[a][q]);
+                C f[8], ux, uy;
+                lds_read<S, RW, RN>(lds, e, even, f);
+                collide<C, false>(f, gx[a], gy[a], k, ux, uy);
+                lds_write<S, RW, RN>(lds, e, !even, f);
             }
         }
         __syncthreads();
     }
+    constexpr bool last_even = (NS % 2) == 0;
 #pragma unroll
     for (int a = 0; a < NM; ++a) {
         const int e = (int)threadIdx.x + a * NT;
         const int i = e % RW, j = e / RW;
         const int x = x0 + i - R, y = y0 + j - R;
         if (e < RN && i >= R && i < R + kTW && j >= R && j < R + TH && x < nx && y < ny) {
-            lds_gather<S, RW, RN>(lds, e, f[a]);
-            C ux, uy;
-            collide<C, false>(f[a], gx[a], gy[a], k, ux, uy);
+            C f[8], ux, uy;
+            lds_read<S, RW, RN>(lds, e, last_even, f);
+            collide<C, false>(f, gx[a], gy[a], k, ux, uy);
             const long long sidx = (long long)y * nx + x;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) Store<S>::st(pq[q] + sidx, f[a][q]);
+            for (int q = 0; q < 8; ++q) Store<S>::st(pq[q] + sidx, f[q]);
         }
     }
     __syncthreads();

@@ -227,13 +227,13 @@ inline int default_wave_rows(int prec, int nx, int ny, int cus) {
 // all lattices of one storage type in a batch), measured on MI355X: the LDS
 // tile kernel is bound by its per-launch memory phase, so deeper blocking pays
 // until LDS limits the workgroups per CU.  FP32: eight above 2^17 sites (1024^2:
-// 218 against 150 GLUPS; 8192^2: 260 against 206 for the four-step
-// wavefront), four on smaller lattices.  FP16: eight up to 2^21 sites, four
-// above (equal at 2048^2, 317 against 306 GLUPS at 8192^2).  FP64: four (its
-// LDS tile is twice as large).
+// 223 against 151 GLUPS; 8192^2: 267 against 206 for the four-step
+// wavefront), four on smaller lattices.  FP16: eight up to 2^25 sites (1024^2:
+// 244 against 208; 5792^2: 307 against 304), four above (8192^2: 315 against
+// 311).  FP64: four (its LDS tile is twice as large).
 inline int default_time_blocking(int prec, long long sites) {
     if (prec == LBM_FP32) return sites > (1LL << 17) ? 8 : 4;
-    if (prec == LBM_FP16) return sites <= (1LL << 21) ? 8 : 4;
+    if (prec == LBM_FP16) return sites <= (1LL << 25) ? 8 : 4;
     return 4;
 }
 
