@@ -313,9 +313,10 @@ class Batch:
         self.device = torch.device(device)
         self.max_slots = int(max_slots)
         self._arena, ptr = _aligned_buffer(int(arena_bytes), self.device)
+        self._stream = torch.cuda.current_stream(self.device)  # the batch's launches run here
         h = ctypes.c_void_p()
         rc = self.lib.lbm_batch_create(self.max_slots, ctypes.c_void_p(ptr), int(arena_bytes),
-                                       ctypes.c_void_p(_stream_ptr(self.device)), ctypes.byref(h))
+                                       ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(h))
         if rc != 0:
             raise LbmError(rc, self.lib.lbm_batch_last_error(None).decode())
         self.h = h
@@ -390,7 +391,7 @@ class Batch:
 
     def displacements(self, slots):
         """Displacements of several lattices as host arrays [(ux, uy), ...]:
-        one device buffer, one copy to the host."""
+        one device buffer, one copy to page-locked host memory."""
         slots = list(slots)
         if not slots:
             return []
@@ -403,7 +404,13 @@ class Batch:
                 self.h, int(sl), ctypes.c_void_p(base + 8 * off),
                 ctypes.c_void_p(base + 8 * (off + n))))
             off += 2 * n
-        host = buf.cpu().numpy()  # waits for the extractions
+        # page-locked host memory (torch's caching host allocator): the copy runs
+        # at link speed instead of through a pageable staging buffer
+        pinned = torch.empty(buf.numel(), dtype=torch.float64, pin_memory=True)
+        with torch.cuda.stream(self._stream):
+            pinned.copy_(buf, non_blocking=True)
+        self._stream.synchronize()  # the extractions and the copy
+        host = pinned.numpy()
         out, off = [], 0
         for sl, n in zip(slots, sizes):
             shp = self.shapes[sl]

@@ -148,6 +148,27 @@ def test_per_precision_time_blocking():
             assert np.isfinite(r0) and r1_ == pytest.approx(r0, rel=1e-12)
 
 
+def test_displacements_of_several_slots():
+    """One copy of several lattices' displacements (page-locked host memory)
+    equals the per-slot reads, for mixed precisions and shapes."""
+    say("batch displacements of several slots")
+    cases = _cases()
+    precs = ["fp64", "fp32", "fp16", "fp32", "fp16", "fp64"]
+    b = _batch()
+    slots = [b.add(c.nx, c.ny, c.material.lame_lambda, c.material.lame_mu, dev(c.gx), dev(c.gy),
+                   p) for c, p in zip(cases, precs)]
+    b.step(21)
+    pick = [slots[4], slots[0], slots[2], slots[5]]
+    many = b.displacements(pick)
+    assert b.displacements([]) == []
+    for sl, (hx, hy) in zip(pick, many):
+        ux, uy = b.displacement(sl)
+        assert hx.shape == tuple(ux.shape) and hy.shape == tuple(uy.shape)
+        np.testing.assert_array_equal(hx, host(ux))
+        np.testing.assert_array_equal(hy, host(uy))
+    b.close()
+
+
 def test_deferred_work_list():
     """Adds and removals between steps only mark the work list stale: several of
     them followed by one step give the same results as single solvers; reading
