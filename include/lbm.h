@@ -295,7 +295,10 @@ int lbm_batch_residuals(lbm_batch *b, double *r_host, long long *steps_host);
 
 /* Switch a FP32/FP16 lattice to FP64 storage (polish phase); needs its
  * polish reservation.  Resets the undamped modes as lbm_solve_to_tol's
- * switch does.  Blocking. */
+ * switch does.  Stream-ordered, no host wait (except right after the slot's
+ * lbm_batch_add, whose force statistics it then reads back); the work list is
+ * rebuilt before the next launch.  Errors: LBM_E_ARG, LBM_E_STATE (no polish
+ * reservation). */
 int lbm_batch_promote(lbm_batch *b, int slot);
 
 /* Current displacement of one lattice (FP64 device arrays [ny][nx]). */

@@ -145,6 +145,7 @@ struct lbm_batch {
     // host
     SlotRow* h_rows = nullptr;  // pinned staging (max_slots rows + 3 ranges)
     double* h_result = nullptr;  // pinned, max(4 x max_slots, 8)
+    SlotDesc* h_desc = nullptr;  // pinned staging of the descriptors (max_slots)
     size_t heap_off = 0;
     Arena arena;
     std::vector<BSlot> slots;
@@ -197,11 +198,6 @@ struct lbm_batch {
         return g;
     }
 
-    hipError_t write_desc(int slot) {
-        hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(1), 0, stream, d_desc + slot,
-                           slots[slot].L.desc());
-        return hipGetLastError();
-    }
 
     int ensure() { return dirty ? rebuild() : LBM_OK; }
 
@@ -267,8 +263,13 @@ struct lbm_batch {
         e = hipMemcpyAsync(d_range, rng, 6 * sizeof(int), hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "rebuild");
+        // descriptors of the active slots: one copy from pinned staging (the
+        // stream was synchronised above, so the staging is free)
         for (int i = 0; i < max_slots; ++i)
-            if (slots[i].active && (e = write_desc(i)) != hipSuccess) return hip_fail(e, "desc");
+            if (slots[i].active) h_desc[i] = slots[i].L.desc();
+        e = hipMemcpyAsync(d_desc, h_desc, max_slots * sizeof(SlotDesc), hipMemcpyHostToDevice,
+                           stream);
+        if (e != hipSuccess) return hip_fail(e, "desc");
         e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hip_fail(e, "rebuild");
         return LBM_OK;
@@ -369,7 +370,7 @@ int lbm_batch_create(int max_slots, void* arena, size_t arena_bytes, void* strea
     b->d_result = reinterpret_cast<double*>(take(4 * max_slots * sizeof(double)));
     b->d_stats = reinterpret_cast<double*>(take(4 * max_slots * sizeof(double)));
     b->d_rows = reinterpret_cast<SlotRow*>(take((max_slots + 2) * sizeof(SlotRow)));
-    b->d_red = reinterpret_cast<double*>(take((kErrBlocks * 8 + 8) * sizeof(double)));
+    b->d_red = reinterpret_cast<double*>(take((kErrBlocks * 8 + 16) * sizeof(double)));
     b->d_items = reinterpret_cast<Item*>(take(b->cap_items * sizeof(Item)));
     b->d_partial = reinterpret_cast<double*>(take(b->cap_items * 3 * sizeof(double)));
     if (off > arena_bytes) {
@@ -393,12 +394,17 @@ int lbm_batch_create(int max_slots, void* arena, size_t arena_bytes, void* strea
         e = hipHostMalloc(reinterpret_cast<void**>(&b->h_result),
                           std::max(4 * max_slots, 8) * sizeof(double),
                           hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&b->h_desc), max_slots * sizeof(SlotDesc),
+                          hipHostMallocDefault);
+    if (e == hipSuccess) std::memset(b->h_desc, 0, max_slots * sizeof(SlotDesc));
     if (e == hipSuccess) e = zero_bytes(b->d_result, 4 * max_slots * sizeof(double), b->stream);
     if (e != hipSuccess) {
         g_batch_create_error = std::string("batch_create: ") + hipGetErrorString(e);
         if (b->cap) (void)hipStreamDestroy(b->cap);
         if (b->h_rows) (void)hipHostFree(b->h_rows);
         if (b->h_result) (void)hipHostFree(b->h_result);
+        if (b->h_desc) (void)hipHostFree(b->h_desc);
         delete b;
         return LBM_E_HIP;
     }
@@ -419,6 +425,7 @@ int lbm_batch_destroy(lbm_batch* b) {
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->h_rows) (void)hipHostFree(b->h_rows);
     if (b->h_result) (void)hipHostFree(b->h_result);
+    if (b->h_desc) (void)hipHostFree(b->h_desc);
     delete b;
     return LBM_OK;
 }
@@ -621,8 +628,10 @@ int lbm_batch_promote(lbm_batch* b, int slot) {
     if (!b) return LBM_E_ARG;
     if (slot < 0 || slot >= b->max_slots || !b->slots[slot].active)
         return b->fail(LBM_E_ARG, "batch_promote: no such slot");
-    int rc0 = b->ensure();  // force statistics of a new slot are needed below
-    if (rc0 != LBM_OK) return rc0;
+    if (b->stats_pending[slot]) {  // its force statistics (half scale, mean target)
+        int rc0 = b->rebuild();
+        if (rc0 != LBM_OK) return rc0;
+    }
     BSlot& s = b->slots[slot];
     Lattice& L = s.L;
     if (L.prec == LBM_FP64) return LBM_OK;
@@ -645,12 +654,11 @@ int lbm_batch_promote(lbm_batch* b, int slot) {
     L.prec = LBM_FP64;
     L.cur = (int)(b->phase[LBM_FP64] & 1);
     s.checked_phase = checked ? b->phase[LBM_FP64] : -1;
-    int rc = b->rebuild();
-    if (rc != LBM_OK) return rc;
+    b->dirty = true;  // the slot moves to the FP64 part of the work list at the next launch
     // reset the undamped modes (staggered moments, mean) excited by the narrow phase
     double target[2];
     L.mean_target(s.steps, target);
-    e = neutral_reset(LBM_FP64, L.desc(), b->sel(s), target, b->d_red, b->h_result, b->stream);
+    e = neutral_reset(LBM_FP64, L.desc(), b->sel(s), target, b->d_red, b->stream);
     if (e != hipSuccess) return b->hip_fail(e, "batch_promote: neutral modes");
     return LBM_OK;
 }

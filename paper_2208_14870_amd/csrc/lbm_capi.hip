@@ -225,7 +225,7 @@ static size_t workspace_bytes(int nx, int ny, int precision, bool polish, bool i
     const long long N = (long long)nx * ny;
     const long long mi = max_items(nx, ny);
     size_t b = al(sizeof(SlotDesc)) + 4 * al(sizeof(int)) + al(4 * 8) + al(mi * sizeof(Item)) +
-               al(mi * 3 * 8) + al((kErrBlocks * 8 + 8) * 8);
+               al(mi * 3 * 8) + al((kErrBlocks * 8 + 16) * 8);
     b += lattice_bytes(N, precision, polish, inplace);
     return b;
 }
@@ -299,7 +299,7 @@ static int create_solver(int nx, int ny, int precision, int with_polish, bool in
     s->d_result = reinterpret_cast<double*>(take(4 * 8));
     s->d_items = reinterpret_cast<Item*>(take(s->max_items_ * sizeof(Item)));
     s->d_partial = reinterpret_cast<double*>(take(s->max_items_ * 3 * 8));
-    s->d_red = reinterpret_cast<double*>(take((kErrBlocks * 8 + 8) * 8));
+    s->d_red = reinterpret_cast<double*>(take((kErrBlocks * 8 + 16) * 8));
     carve_lattice(base + off, L.N, precision, L.polish, L.mem, inplace);
     int rc = lbm_reset(s);
     if (rc != LBM_OK) {
@@ -536,7 +536,7 @@ int promote_solver(lbm_solver* s) {
     // converges to the exact trajectory's fixed point
     double target[2];
     L.mean_target(s->steps, target);
-    e = neutral_reset(LBM_FP64, L.desc(), s->sel(), target, s->d_red, s->h_result, s->stream);
+    e = neutral_reset(LBM_FP64, L.desc(), s->sel(), target, s->d_red, s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "promote: neutral modes");
     return LBM_OK;
 }

@@ -462,7 +462,7 @@ inline hipError_t zero_bytes(void* p, size_t bytes, hipStream_t st) {
 
 // Measure the neutral modes of the stored state (blocking): out[0..3] =
 // staggered sums and their force terms, out[4..5] = sum m10, sum m01.
-// scratch: 8 * kErrBlocks + 8 doubles of device memory; host: 8 pinned doubles.
+// scratch: 8 * kErrBlocks + 12 doubles of device memory; host: 8 pinned doubles.
 template <typename S>
 inline hipError_t neutral_measure_t(const SlotDesc& d, int sel, double* scratch, double* host,
                                     hipStream_t st) {
@@ -487,29 +487,31 @@ inline hipError_t neutral_measure(int prec, const SlotDesc& d, int sel, double* 
 
 // Reset the neutral modes of the stored state to their exact values: the
 // staggered moments to their fixed point and the mean first moments to
-// `mean_target` (sum_x m10, sum_x m01 of the exact trajectory).
+// `mean_target` (sum_x m10, sum_x m01 of the exact trajectory).  Stream-ordered,
+// no host wait: the corrections are computed on the device.  scratch:
+// 8 * kErrBlocks + 12 doubles of device memory.
 template <typename S>
 inline hipError_t neutral_reset_t(const SlotDesc& d, int sel, const double mean_target[2],
-                                  double* scratch, double* host, hipStream_t st) {
-    hipError_t e = neutral_measure_t<S>(d, sel, scratch, host, st);
-    if (e != hipSuccess) return e;
-    const double N = (double)d.nx * d.ny;
-    // J_S -> G/2 ; an update of eps changes J_S by 2 eps N (and the mean by 2 eps N)
-    const double ex = (d.nx % 2 == 0) ? (0.5 * host[2] - host[0]) / (2.0 * N) : 0.0;
-    const double ey = (d.ny % 2 == 0) ? (0.5 * host[3] - host[1]) / (2.0 * N) : 0.0;
-    const double mx = (mean_target[0] - host[4]) / (2.0 * N);
-    const double my = (mean_target[1] - host[5]) / (2.0 * N);
-    const double sc = 1.0 / d.inv_scale;  // into storage units
+                                  double* scratch, hipStream_t st) {
+    hipLaunchKernelGGL(k_neutral_sums<S>, dim3(kErrBlocks), dim3(kBlock), 0, st, d, sel, scratch);
+    double* out = scratch + 8 * kErrBlocks;
+    hipLaunchKernelGGL(k_reduce4<0>, dim3(1), dim3(kBlock), 0, st, scratch, kErrBlocks, out);
+    hipLaunchKernelGGL(k_reduce4<0>, dim3(1), dim3(kBlock), 0, st, scratch + 4 * kErrBlocks,
+                       kErrBlocks, out + 4);
+    double* coef = out + 8;
+    hipLaunchKernelGGL(k_neutral_coef, dim3(1), dim3(1), 0, st, out, (double)d.nx * d.ny,
+                       d.nx % 2 == 0 ? 1 : 0, d.ny % 2 == 0 ? 1 : 0, mean_target[0],
+                       mean_target[1], 1.0 / d.inv_scale, coef);
     hipLaunchKernelGGL(k_neutral_fix<S>, dim3(blocks_for((long long)d.nx * d.ny)), dim3(kBlock), 0,
-                       st, d, sel, ex * sc, ey * sc, mx * sc, my * sc);
+                       st, d, sel, coef);
     return hipGetLastError();
 }
 
 inline hipError_t neutral_reset(int prec, const SlotDesc& d, int sel, const double mean_target[2],
-                                double* scratch, double* host, hipStream_t st) {
-    if (prec == LBM_FP64) return neutral_reset_t<double>(d, sel, mean_target, scratch, host, st);
-    if (prec == LBM_FP32) return neutral_reset_t<float>(d, sel, mean_target, scratch, host, st);
-    return neutral_reset_t<__half>(d, sel, mean_target, scratch, host, st);
+                                double* scratch, hipStream_t st) {
+    if (prec == LBM_FP64) return neutral_reset_t<double>(d, sel, mean_target, scratch, st);
+    if (prec == LBM_FP32) return neutral_reset_t<float>(d, sel, mean_target, scratch, st);
+    return neutral_reset_t<__half>(d, sel, mean_target, scratch, st);
 }
 
 // Convert the FP64 force into the lattice's arithmetic type (and keep the

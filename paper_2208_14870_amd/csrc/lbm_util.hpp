@@ -264,17 +264,37 @@ static __global__ __launch_bounds__(kBlock) void k_neutral_sums(SlotDesc d, int 
         }
 }
 
+// The four corrections of stage 2 from the stage-1 sums (8 doubles, after the
+// second reduction) and the target means, in storage units (sc = 1 / inv_scale):
+// the staggered sums go to their fixed point G/2, the means to the target (an
+// update of eps changes either by 2 eps N).  One thread, on the device, so the
+// reset needs no host round trip; each operation rounds on its own.
+static __global__ void k_neutral_coef(const double* sums, double n, int evenx, int eveny,
+                                      double tx, double ty, double sc, double* coef) {
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double ex = evenx ? (0.5 * sums[2] - sums[0]) / (2.0 * n) : 0.0;
+    const double ey = eveny ? (0.5 * sums[3] - sums[1]) / (2.0 * n) : 0.0;
+    const double mx = (tx - sums[4]) / (2.0 * n);
+    const double my = (ty - sums[5]) / (2.0 * n);
+    coef[0] = ex * sc;
+    coef[1] = ey * sc;
+    coef[2] = mx * sc;
+    coef[3] = my * sc;
+}
+
 // Stage 2: S1 += (ex (-1)^x + mx), S3 -= (ex (-1)^x + mx),
 //          S2 += (ey (-1)^y + my), S4 -= (ey (-1)^y + my)
-// (changes only m10 / m01 of S: the staggered and the uniform parts; all
-// amounts already in storage units).
+// (changes only m10 / m01 of S: the staggered and the uniform parts; coef =
+// {ex, ey, mx, my} in device memory, already in storage units).
 template <typename S>
-static __global__ __launch_bounds__(kBlock) void k_neutral_fix(SlotDesc d, int sel, double ex,
-                                                               double ey, double mx, double my) {
+static __global__ __launch_bounds__(kBlock) void k_neutral_fix(SlotDesc d, int sel,
+                                                               const double* coef) {
     using C = typename Store<S>::C;
     const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (s >= (long long)d.nx * d.ny) return;
     const int x = (int)(s % d.nx), y = (int)(s / d.nx);
+    const double ex = coef[0], ey = coef[1], mx = coef[2], my = coef[3];
     S* st = reinterpret_cast<S*>(d.buf[sel]);
     const double px = ((x & 1) ? -ex : ex) + mx, py = ((y & 1) ? -ey : ey) + my;
     S* p0 = st + 0 * d.plane + s;
