@@ -39,10 +39,14 @@ PEAK_HBM_GBS = 8000.0
 BYTES_PER_SITE = {"fp64": 144, "fp32": 72, "fp16": 40}  # 8 pops in + 8 out + 2 force
 
 
-def measured_traffic():
+TRAFFIC_SOURCES = ("lbm_common.hpp", "lbm_fused.hpp")  # the headers that define the tile kernel
+
+
+def measured_traffic(kernel=None):
     """HBM bytes per launch of the headline kernel from the committed counter
     summary (FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy), or None when the
-    kernel sources changed since the counters were taken."""
+    kernel's sources changed since the counters were taken or the profiled
+    kernel (template arguments included) is not `kernel`."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_stepN_fp32_1024_traffic.json")
     try:
@@ -51,9 +55,11 @@ def measured_traffic():
         return None
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2208_14870_amd", "csrc")
-    for f in sorted(x for x in os.listdir(csrc) if x.endswith(".hpp")):  # kernels + launch code
+    for f in TRAFFIC_SOURCES:
         h.update(open(os.path.join(csrc, f), "rb").read())
     if h.hexdigest() != rec.get("source_sha256"):
+        return None
+    if kernel is not None and kernel not in rec.get("kernel", ""):
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -431,7 +437,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(r32["kernel_gbs"], 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(r32["kernel_gbs"] / PEAK_HBM_GBS, 4),
-                     "traffic": measured_traffic(),
+                     "traffic": measured_traffic(
+                         kernel_label(r32["launch_config"], "float", 1024 * 1024).split(" (")[0]),
                      "kernel": kernel_label(r32["launch_config"], "float", 1024 * 1024),
                      "avg_launch_us": round(r32["plain_kernel_avg_us"], 3),
                      "steps_per_launch": r32["steps_per_launch"],
