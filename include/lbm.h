@@ -203,8 +203,7 @@ int lbm_set_tile(lbm_solver *s, int bx_log2, int rows_per_thread, int blocks_per
  * Results are identical to single steps.  Residual-check steps, remainders
  * and the general-rates variant run one step per launch.  Overrides the tile
  * shape of lbm_set_tile while active.  Default by storage type and size: FP32
- * 8 above 2^17 sites, else 4; FP16 8 up to 2^25 sites, else 4; FP64 4 (also
- * after a polish switch).  The fused kernel follows the
+ * and FP16 8 above 2^17 sites, else 4; FP64 4 (also after a polish switch).  The fused kernel follows the
  * default of lbm_set_fused_kernel for k until the caller picks one; k > 4
  * always runs the LDS tile kernel (the wavefront runs 2..4 steps).  Errors:
  * LBM_E_ARG (k outside 1..8), LBM_E_STATE (k != 1 in place). */

@@ -433,9 +433,13 @@ int lbm_batch_destroy(lbm_batch* b) {
 int lbm_batch_add(lbm_batch* b, int nx, int ny, int precision, int with_polish, double lam,
                   double mu, const double* gx, const double* gy, int* slot) {
     if (!b) return LBM_E_ARG;
+    // the fused tile kernel addresses a plane of populations or force (in the
+    // arithmetic type; FP64 after a polish switch) with 32-bit byte offsets
+    const long long eb = (precision == LBM_FP64 || with_polish) ? 8 : 4;
     if (nx < 1 || ny < 1 || !valid_prec(precision) || !gx || !gy || !slot ||
-        (long long)nx * ny > (1LL << 31))
-        return b->fail(LBM_E_ARG, "batch_add: invalid size, precision or NULL pointer");
+        plane_of((long long)nx * ny) * eb > 0xFFFFFFFFLL)
+        return b->fail(LBM_E_ARG, "batch_add: invalid size (plane of 2^32 bytes or more), "
+                                  "precision or NULL pointer");
     Rates r;
     if (!material_rates(lam, mu, r, b->err)) return LBM_E_MATERIAL;
     int id = -1;

@@ -87,6 +87,19 @@ __device__ __forceinline__ void lds_write(S* lds, int r, bool swapped,
     }
 }
 
+// Element i of a plane through a 32-bit byte offset (planes of the tile kernel
+// hold fewer than 2^32 bytes): with a wave-uniform base each access is one
+// scalar base plus one 32-bit vector offset, instead of 64-bit address
+// arithmetic per load.
+template <typename S>
+__device__ __forceinline__ const S* at_u32(const S* base, unsigned i) {
+    return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(S));
+}
+template <typename S>
+__device__ __forceinline__ S* at_u32(S* base, unsigned i) {
+    return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(S));
+}
+
 // Step 1 of the fused kernel for one tile, in two parts.  stepN_load issues
 // the loads of the ring region from the stored field (periodic coordinates):
 // the 8 incoming populations and the force of every slot (the last slot's
@@ -102,15 +115,34 @@ __device__ __forceinline__ void stepN_load(const S* __restrict__ src,
     constexpr int R = NS - 1;
     constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
     constexpr int NM = (RN + NT - 1) / NT;
+    using C = typename Store<S>::C;
+    const S* pq[8];  // wave-uniform plane bases
+#pragma unroll
+    for (int q = 0; q < 8; ++q) pq[q] = src + q * plane;
+    const C* g1 = g + plane;
 #pragma unroll
     for (int a = 0; a < NM; ++a) {
         const int e = min((int)threadIdx.x + a * NT, RN - 1);
         const int i = e % RW, j = e / RW;
-        const int xw = wrap_coord(x0 - R + i, nx), yw = wrap_coord(y0 - R + j, ny);
-        gather<S>(src, plane, nx, ny, xw, yw, f[a]);
-        const long long sidx = (long long)yw * nx + xw;
-        gx[a] = glob(g)[sidx];
-        gy[a] = glob(g)[plane + sidx];
+        const unsigned x = (unsigned)wrap_coord(x0 - R + i, nx);
+        const unsigned y = (unsigned)wrap_coord(y0 - R + j, ny);
+        const unsigned w = (unsigned)nx;
+        const unsigned xm = (x == 0) ? w - 1 : x - 1;
+        const unsigned xp = (x == w - 1) ? 0 : x + 1;
+        const unsigned ym = (y == 0) ? (unsigned)ny - 1 : y - 1;
+        const unsigned yp = (y == (unsigned)ny - 1) ? 0 : y + 1;
+        const unsigned r0 = y * w, rm = ym * w, rp = yp * w;
+        // pull: f_q(x) = f*_q(x - c_q), velocity table order
+        f[a][0] = Store<S>::ld(at_u32(pq[0], r0 + xm));
+        f[a][1] = Store<S>::ld(at_u32(pq[1], rm + x));
+        f[a][2] = Store<S>::ld(at_u32(pq[2], r0 + xp));
+        f[a][3] = Store<S>::ld(at_u32(pq[3], rp + x));
+        f[a][4] = Store<S>::ld(at_u32(pq[4], rm + xm));
+        f[a][5] = Store<S>::ld(at_u32(pq[5], rm + xp));
+        f[a][6] = Store<S>::ld(at_u32(pq[6], rp + xp));
+        f[a][7] = Store<S>::ld(at_u32(pq[7], rp + xm));
+        gx[a] = *glob(at_u32(g, r0 + x));
+        gy[a] = *glob(at_u32(g1, r0 + x));
     }
 }
 
@@ -148,8 +180,7 @@ __device__ __forceinline__ void stepN_rest(S* __restrict__ dst, long long plane,
     constexpr int R = NS - 1;
     constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
     constexpr int NM = (RN + NT - 1) / NT;
-    // plane base pointers are wave-uniform: one 64-bit add per store
-    S* pq[8];
+    S* pq[8];  // wave-uniform plane bases
 #pragma unroll
     for (int q = 0; q < 8; ++q) pq[q] = dst + q * plane;
 #pragma unroll
@@ -178,9 +209,9 @@ __device__ __forceinline__ void stepN_rest(S* __restrict__ dst, long long plane,
             C f[8], ux, uy;
             lds_read<S, RW, RN>(lds, e, last_even, f);
             collide<C, false>(f, gx[a], gy[a], k, ux, uy);
-            const long long sidx = (long long)y * nx + x;
+            const unsigned sidx = (unsigned)y * (unsigned)nx + (unsigned)x;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) Store<S>::st(pq[q] + sidx, f[q]);
+            for (int q = 0; q < 8; ++q) Store<S>::st(at_u32(pq[q], sidx), f[q]);
         }
     }
     __syncthreads();

@@ -226,15 +226,14 @@ inline int default_wave_rows(int prec, int nx, int ny, int cus) {
 // Default steps per launch for `sites` lattice sites (of one lattice, or of
 // all lattices of one storage type in a batch), measured on MI355X: the LDS
 // tile kernel is bound by its per-launch memory phase, so deeper blocking pays
-// until LDS limits the workgroups per CU.  FP32: eight above 2^17 sites (1024^2:
-// 223 against 151 GLUPS; 8192^2: 267 against 206 for the four-step
-// wavefront), four on smaller lattices.  FP16: eight up to 2^25 sites (1024^2:
-// 244 against 208; 5792^2: 307 against 304), four above (8192^2: 315 against
-// 311).  FP64: four (its LDS tile is twice as large).
+// until LDS limits the workgroups per CU.  FP32 and FP16: eight above 2^17
+// sites (FP32 1024^2: 232 against 149 GLUPS, 8192^2: 269 against 206 for the
+// four-step wavefront; FP16 1024^2: 280 against 218, 8192^2: 361 against
+// 330), four on smaller lattices (FP32 256^2: 49 against 42).  FP64: four
+// (its LDS tile is twice as large).
 inline int default_time_blocking(int prec, long long sites) {
-    if (prec == LBM_FP32) return sites > (1LL << 17) ? 8 : 4;
-    if (prec == LBM_FP16) return sites <= (1LL << 25) ? 8 : 4;
-    return 4;
+    if (prec == LBM_FP64) return 4;
+    return sites > (1LL << 17) ? 8 : 4;
 }
 
 // Default fused kernel for `ns` steps per launch: the register wavefront runs
@@ -351,7 +350,10 @@ struct Lattice {
     int tiles_x() const { return (nx + (1 << eff_bxl()) - 1) >> eff_bxl(); }
     // The fused kernel has a tile 64 wide and th rows high; the general-rates
     // variant runs one row per thread.
-    bool fused() const { return tb >= 2 && !general() && !inplace; }
+    // The tile kernel addresses a plane (populations, and the force in the
+    // arithmetic type, which is at least as wide) with 32-bit byte offsets.
+    bool tile_fits() const { return plane * (long long)arith_bytes(prec) <= 0xFFFFFFFFLL; }
+    bool fused() const { return tb >= 2 && !general() && !inplace && (wave_hs > 0 || tile_fits()); }
     int eff_bxl() const { return fused() ? 6 : bx_log2; }
     int eff_vy() const { return fused() ? th / 4 : (general() ? 1 : vy); }
     int tile_h() const { return (kBlock >> eff_bxl()) * eff_vy(); }

@@ -402,7 +402,7 @@ def test_fused_kernel_argument_errors():
 
 def test_launch_config_defaults():
     """Default plain-step launches: eight steps per launch through the LDS tile
-    (16 rows, 512 threads) for FP32 above 2^17 sites and FP16 up to 2^25, four
+    (16 rows, 512 threads) for FP32 and FP16 above 2^17 sites, four
     otherwise and for FP64 (the wavefront above 2^22 FP64 sites); deeper
     blocking leaves the wavefront; one step per launch in place."""
     from paper_2208_14870_amd import lbm
@@ -410,10 +410,10 @@ def test_launch_config_defaults():
     cfg = lambda n, m, p, **kw: lbm.Solver(n, m, p, **kw).launch_config()
     assert cfg(1024, 1024, "fp32") == {"steps_per_launch": 8, "kernel": "tile", "rows": 16,
                                        "threads": 512}
-    assert cfg(96, 64, "fp16") == {"steps_per_launch": 8, "kernel": "tile", "rows": 16,
-                                   "threads": 512}
-    assert cfg(8192, 8192, "fp16") == {"steps_per_launch": 4, "kernel": "tile", "rows": 12,
-                                       "threads": 256}
+    assert cfg(4096, 4096, "fp16") == {"steps_per_launch": 8, "kernel": "tile", "rows": 16,
+                                       "threads": 512}
+    assert cfg(256, 256, "fp16") == {"steps_per_launch": 4, "kernel": "tile", "rows": 12,
+                                     "threads": 256}
     assert cfg(256, 256, "fp32") == {"steps_per_launch": 4, "kernel": "tile", "rows": 8,
                                      "threads": 512}
     assert cfg(1024, 1024, "fp64") == {"steps_per_launch": 4, "kernel": "tile", "rows": 8,
