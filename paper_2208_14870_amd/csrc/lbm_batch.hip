@@ -289,10 +289,16 @@ struct lbm_batch {
     // rows per thread of the tiles of one precision's lattices
     int eff_vy(int prec) const { return tb[prec] >= 2 ? th[prec] / 4 : vy; }
 
+    // Whether a remainder of r < tb[p] plain steps runs as one fused launch.
+    bool fused_rest(int p, long long r) const {
+        return tb[p] >= 2 && r >= 2 && stepN_supported(p, (int)r, th[p]);
+    }
+
     // buffer flips of precision p in one batch_step
     long long launches(int p, long long nsteps, bool check) const {
         const long long np = check ? nsteps - 2 : nsteps;
-        return (tb[p] >= 2 ? np / tb[p] + np % tb[p] : np) + (check ? 2 : 0);
+        const long long r = tb[p] >= 2 ? np % tb[p] : 0;
+        return (tb[p] >= 2 ? np / tb[p] + (fused_rest(p, r) ? 1 : r) : np) + (check ? 2 : 0);
     }
 
     // The launches of one batch_step, precision by precision (their lattices
@@ -304,9 +310,15 @@ struct lbm_batch {
             const unsigned g = grid_for(p);
             if (!g) continue;
             long long ph = phase[p], i = 0;
-            if (tb[p] >= 2)
+            if (tb[p] >= 2) {
                 for (; i + tb[p] <= np && e == hipSuccess; i += tb[p], ++ph)
                     e = launch_stepN(p, tb[p], th[p], g, st, args(p, (int)(ph & 1)));
+                if (e == hipSuccess && fused_rest(p, np - i)) {
+                    e = launch_stepN(p, (int)(np - i), th[p], g, st, args(p, (int)(ph & 1)));
+                    ++ph;
+                    i = np;
+                }
+            }
             for (; i < np && e == hipSuccess; ++i, ++ph)
                 e = launch_step(p, kPlain, false, eff_vy(p), kLayPull, g, st, args(p, (int)(ph & 1)));
             if (check && e == hipSuccess) {

@@ -116,13 +116,20 @@ struct lbm_solver {
         return e;
     }
 
-    hipError_t enqueue_fused(hipStream_t st, long long& ph) {
+    // One fused launch of ns steps (L.tb, or a shorter remainder).
+    hipError_t enqueue_fused(int ns, hipStream_t st, long long& ph) {
         hipError_t e =
             L.wave_hs > 0
-                ? launch_wave(L.prec, L.tb, L.nx, L.ny, L.wave_hs, d_desc, (int)(ph & 1), st)
-                : launch_stepN(L.prec, L.tb, L.th, grid, st, launch_args((int)(ph & 1)));
-        ++ph;  // one buffer flip for L.tb steps
+                ? launch_wave(L.prec, ns, L.nx, L.ny, L.wave_hs, d_desc, (int)(ph & 1), st)
+                : launch_stepN(L.prec, ns, L.th, grid, st, launch_args((int)(ph & 1)));
+        ++ph;  // one buffer flip for ns steps
         return e;
+    }
+
+    // Whether a remainder of r < L.tb plain steps runs as one fused launch.
+    bool fused_rest(long long r) const {
+        return L.fused() && r >= 2 &&
+               (L.wave_hs > 0 ? r <= 4 : stepN_supported(L.prec, (int)r, L.th));
     }
 
     hipError_t enqueue_finalize(hipStream_t st) {
@@ -137,15 +144,21 @@ struct lbm_solver {
     }
 
     // Launches for `nplain` plain steps (groups of L.tb through the fused kernel
-    // when enabled, the remainder one per launch), then optionally a writeU step
+    // when enabled, the remainder as one shorter fused launch where a kernel
+    // exists for it, else one per launch), then optionally a writeU step
     // and a residual check (a check step, or in place a launch without a step)
     // + finalize.
     hipError_t enqueue_seq(long long nplain, bool writeu, bool check, hipStream_t st,
                            long long& ph) {
         hipError_t e = hipSuccess;
         long long i = 0;
-        if (L.fused())
-            for (; i + L.tb <= nplain && e == hipSuccess; i += L.tb) e = enqueue_fused(st, ph);
+        if (L.fused()) {
+            for (; i + L.tb <= nplain && e == hipSuccess; i += L.tb) e = enqueue_fused(L.tb, st, ph);
+            if (e == hipSuccess && fused_rest(nplain - i)) {
+                e = enqueue_fused((int)(nplain - i), st, ph);
+                i = nplain;
+            }
+        }
         for (; i < nplain && e == hipSuccess; ++i) e = enqueue_one(kPlain, st, ph);
         if (e == hipSuccess && writeu) e = enqueue_one(kWriteU, st, ph);
         if (e == hipSuccess && check) {
@@ -163,7 +176,8 @@ struct lbm_solver {
 
     // buffer flips (launch-parity increments) of enqueue_seq
     long long launches(long long nplain, bool writeu, bool check) const {
-        const long long p = L.fused() ? nplain / L.tb + nplain % L.tb : nplain;
+        const long long r = L.fused() ? nplain % L.tb : 0;
+        const long long p = L.fused() ? nplain / L.tb + (fused_rest(r) ? 1 : r) : nplain;
         return p + (writeu ? 1 : 0) + (check && !L.inplace ? 1 : 0);
     }
 

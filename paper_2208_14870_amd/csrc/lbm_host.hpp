@@ -139,7 +139,18 @@ inline int fused_th(int prec, int ns, long long sites) {
 inline int fused_nt(int prec, int ns, int th) {
     if (prec == LBM_FP64) return kBlock;
     if (prec == LBM_FP32) return (th == 8 || ns > 4) ? 512 : 256;
-    return ns > 4 ? 512 : 256;
+    return th == 16 ? 512 : 256;
+}
+
+// Whether launch_stepN has a kernel for ns steps on tiles of th rows: every
+// tile height runs 2..4 steps, and the heights used for deeper blocking (FP64
+// 8, FP32 and FP16 16) run 2..8, so a remainder of a launch sequence can run
+// as one shorter fused launch.
+inline bool stepN_supported(int prec, int ns, int th) {
+    if (ns < 2 || ns > 8) return false;
+    if (prec == LBM_FP64) return th == 8;
+    if (prec == LBM_FP32) return th == 16 || (th == 8 && ns <= 4);
+    return th == 16 || (th == 12 && ns <= 4);
 }
 
 template <typename S, int TH, int NT, int NS, int NSMAX>
@@ -152,7 +163,8 @@ inline bool launch_stepN_ns(int ns, unsigned grid, hipStream_t st, const StepLau
     return false;
 }
 
-// ns in 2..8; th must be the height fused_th returns for (prec, ns).
+// ns in 2..8 with stepN_supported(prec, ns, th); th is the tile height of the
+// work list (fused_th for the sequence's steps per launch).
 inline hipError_t launch_stepN(int prec, int ns, int th, unsigned grid, hipStream_t st,
                                const StepLaunch& L) {
     bool ok = false;
@@ -162,7 +174,7 @@ inline hipError_t launch_stepN(int prec, int ns, int th, unsigned grid, hipStrea
         ok = launch_stepN_ns<float, 16, 256, 2, 4>(ns, grid, st, L);
     else if (prec == LBM_FP32 && th == 16) ok = launch_stepN_ns<float, 16, 512, 5, 8>(ns, grid, st, L);
     else if (prec == LBM_FP16 && th == 12) ok = launch_stepN_ns<__half, 12, 256, 2, 4>(ns, grid, st, L);
-    else if (prec == LBM_FP16 && th == 16) ok = launch_stepN_ns<__half, 16, 512, 5, 8>(ns, grid, st, L);
+    else if (prec == LBM_FP16 && th == 16) ok = launch_stepN_ns<__half, 16, 512, 2, 8>(ns, grid, st, L);
     if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }
