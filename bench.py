@@ -332,6 +332,18 @@ def serving_run(rate: float = 2000.0, window: float = 1.0, budget: float = 20.0)
     return st
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(seconds: float):
     """The FP64 CPU oracle, as it stands, on a bounded sample of the workload
     (the first 1024 x 1024 case), timed on this host's cores."""
@@ -348,7 +360,8 @@ def cpu_baseline(seconds: float):
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     return {"value": c.nx * c.ny * steps / dt / 1e6, "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "cores_visible": len(os.sched_getaffinity(0)),
             "sample": f"1024x1024, nu=0.1, mode (1,1): {steps} of the 20000 pseudo-time steps, "
                       f"{dt:.1f} s, FP64, OpenMP over rows"}
 
