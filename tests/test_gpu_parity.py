@@ -301,12 +301,11 @@ def test_time_blocking_identical_to_single_steps(prec, nx, ny, steps):
     ("fp32", 1024, 1024, 12, 1), ("fp32", 1024, 1024, 9, 2), ("fp32", 1000, 998, 11, 3),
     ("fp64", 300, 200, 10, 1), ("fp64", 130, 9, 7, 2), ("fp16", 130, 90, 8, 1),
     ("fp32", 65, 17, 9, 3), ("fp32", 3000, 40, 8, 1), ("fp64", 1024, 1024, 8, 2)])
-def test_pipelined_tile_identical_to_single_steps(prec, nx, ny, steps, bpc):
+def test_persistent_tile_identical_to_single_steps(prec, nx, ny, steps, bpc):
     """Persistent fused launches (bpc workgroups per CU, fewer than the tiles:
-    each workgroup loads its next tile's step-1 inputs while it finishes the
-    current tile) give populations bit-identical to single steps, with residual
-    checks interleaved."""
-    say(f"pipelined tile {prec} {nx}x{ny} steps {steps} blocks/CU {bpc}")
+    each workgroup walks several tiles of the work list) give populations
+    bit-identical to single steps, with residual checks interleaved."""
+    say(f"persistent tile {prec} {nx}x{ny} steps {steps} blocks/CU {bpc}")
     mat = P.Material.from_shear_poisson(0.9, 0.3)
     f0, gx, gy = _rand_state(nx, ny, 7 + nx)
     res = {}
