@@ -42,22 +42,32 @@ BYTES_PER_SITE = {"fp64": 144, "fp32": 72, "fp16": 40}  # 8 pops in + 8 out + 2 
 TRAFFIC_SOURCES = ("lbm_common.hpp", "lbm_fused.hpp")  # the headers that define the tile kernel
 
 
+def kernel_source_hash() -> str:
+    """sha256 of the tile kernel's headers with comments and whitespace removed
+    (the code the counters were taken with)."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2208_14870_amd", "csrc")
+    for f in TRAFFIC_SOURCES:
+        text = open(os.path.join(csrc, f)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel=None):
     """HBM bytes per launch of the headline kernel from the committed counter
     summary (FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy), or None when the
-    kernel's sources changed since the counters were taken or the profiled
+    kernel's code changed since the counters were taken or the profiled
     kernel (template arguments included) is not `kernel`."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "k_stepN_fp32_1024_traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2208_14870_amd", "csrc")
-    for f in TRAFFIC_SOURCES:
-        h.update(open(os.path.join(csrc, f), "rb").read())
-    if h.hexdigest() != rec.get("source_sha256"):
+    if kernel_source_hash() != rec.get("source_sha256"):
         return None
     if kernel is not None and kernel not in rec.get("kernel", ""):
         return None

@@ -25,8 +25,9 @@ namespace lbm {
 // f_q(r), the populations arriving at r; even steps read the swapped copy of
 // their upstream neighbours and push into it at the downstream neighbours.
 //
-// NT threads per workgroup (256, or 512 for the short FP32 tiles, which
-// halves each thread's share of a tile's dependent steps).  Every thread keeps
+// NT threads per workgroup: 256, or 512 for the 8-row FP32 tiles and the
+// 16-row FP32 / FP16 tiles of deeper blocking (each thread then carries fewer
+// sites of the ring region, in fewer registers).  Every thread keeps
 // the same NM sites of the ring region (site e = thread + a * NT, a < NM) in
 // all NS steps, so that step 1 issues all its population
 // and force loads before it waits once, the force stays in registers, and the
