@@ -203,7 +203,8 @@ int lbm_set_tile(lbm_solver *s, int bx_log2, int rows_per_thread, int blocks_per
  * Results are identical to single steps.  Residual-check steps, remainders
  * and the general-rates variant run one step per launch.  Overrides the tile
  * shape of lbm_set_tile while active.  Default by storage type and size: FP32
- * and FP16 8 above 2^17 sites, else 4; FP64 4 (also after a polish switch).  The fused kernel follows the
+ * and FP16 8 above 2^17 sites, else 4; FP64 5, or 4 above 2^22 sites where the
+ * wavefront is the default (also after a polish switch).  The fused kernel follows the
  * default of lbm_set_fused_kernel for k until the caller picks one; k > 4
  * always runs the LDS tile kernel (the wavefront runs 2..4 steps).  Errors:
  * LBM_E_ARG (k outside 1..8), LBM_E_STATE (k != 1 in place). */
@@ -308,8 +309,9 @@ int lbm_batch_get_displacement(lbm_batch *b, int slot, double *ux, double *uy);
 int lbm_batch_set_tile(lbm_batch *b, int bx_log2, int rows_per_thread, int blocks_per_cu);
 
 /* Temporal blocking for all lattices of the batch (see lbm_set_time_blocking,
- * 1..8).  Until set, each storage type takes the single-lattice default for
- * the total sites of its lattices in the batch.  Errors: LBM_E_ARG. */
+ * 1..8).  Until set, each storage type takes the tile kernel's default for the
+ * total sites of its lattices in the batch (FP64 5, FP32 / FP16 8 above 2^17
+ * sites).  Errors: LBM_E_ARG. */
 int lbm_batch_set_time_blocking(lbm_batch *b, int steps_per_launch);
 
 /* Temporal blocking for the lattices of one storage type only (precision

@@ -227,7 +227,7 @@ struct lbm_batch {
             long long sites = 0;
             for (int i = 0; i < max_slots; ++i)
                 if (slots[i].active && slots[i].L.prec == p) sites += slots[i].L.N;
-            if (tb_auto[p]) tb[p] = default_time_blocking(p, sites);
+            if (tb_auto[p]) tb[p] = default_time_blocking(p, sites, true);
             th[p] = fused_th(p, tb[p], sites);
         }
         for (int p = 0; p < 3; ++p) {

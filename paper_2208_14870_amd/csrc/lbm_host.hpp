@@ -124,11 +124,11 @@ inline hipError_t launch_check_state(int prec, int vy, int layout, unsigned grid
 }
 
 // Shapes of the fused LDS tile kernel (tile 64 x TH, NT threads) per storage
-// type and steps per launch, measured on MI355X.  Up to four steps: FP64 8
-// rows, FP32 8 rows with 512 threads up to 2^21 sites and 16 rows with 256
-// threads above, FP16 12 rows.  Five to eight steps: FP32 16 rows with 512
-// threads (two workgroups of 75 KB LDS per CU at eight steps), FP16 16 rows,
-// FP64 8 rows.
+// type and steps per launch, measured on MI355X.  FP64: 8 rows with 512
+// threads (1024^2, five steps: 106 against 98 GLUPS with 256).  Up to four
+// steps: FP32 8 rows with 512 threads up to 2^21 sites and 16 rows with 256
+// threads above, FP16 12 rows.  Five to eight steps: FP32 and FP16 16 rows
+// with 512 threads (two workgroups of 75 KB LDS per CU at eight steps in FP32).
 inline int fused_th(int prec, int ns, long long sites) {
     if (prec == LBM_FP64) return 8;
     if (prec == LBM_FP32) return (ns <= 4 && sites <= (1LL << 21)) ? 8 : 16;
@@ -137,7 +137,7 @@ inline int fused_th(int prec, int ns, long long sites) {
 
 // Threads per workgroup of the fused LDS tile kernel (as launch_stepN runs it).
 inline int fused_nt(int prec, int ns, int th) {
-    if (prec == LBM_FP64) return kBlock;
+    if (prec == LBM_FP64) return 512;
     if (prec == LBM_FP32) return (th == 8 || ns > 4) ? 512 : 256;
     return th == 16 ? 512 : 256;
 }
@@ -168,7 +168,7 @@ inline bool launch_stepN_ns(int ns, unsigned grid, hipStream_t st, const StepLau
 inline hipError_t launch_stepN(int prec, int ns, int th, unsigned grid, hipStream_t st,
                                const StepLaunch& L) {
     bool ok = false;
-    if (prec == LBM_FP64 && th == 8) ok = launch_stepN_ns<double, 8, 256, 2, 8>(ns, grid, st, L);
+    if (prec == LBM_FP64 && th == 8) ok = launch_stepN_ns<double, 8, 512, 2, 8>(ns, grid, st, L);
     else if (prec == LBM_FP32 && th == 8) ok = launch_stepN_ns<float, 8, 512, 2, 4>(ns, grid, st, L);
     else if (prec == LBM_FP32 && th == 16 && ns <= 4)
         ok = launch_stepN_ns<float, 16, 256, 2, 4>(ns, grid, st, L);
@@ -241,10 +241,12 @@ inline int default_wave_rows(int prec, int nx, int ny, int cus) {
 // until LDS limits the workgroups per CU.  FP32 and FP16: eight above 2^17
 // sites (FP32 1024^2: 232 against 149 GLUPS, 8192^2: 269 against 206 for the
 // four-step wavefront; FP16 1024^2: 280 against 218, 8192^2: 361 against
-// 330), four on smaller lattices (FP32 256^2: 49 against 42).  FP64: four
-// (its LDS tile is twice as large).
-inline int default_time_blocking(int prec, long long sites) {
-    if (prec == LBM_FP64) return 4;
+// 330), four on smaller lattices (FP32 256^2: 49 against 42).  FP64 (whose LDS
+// tile is twice as large): five through the tile kernel (1024^2: 106 against
+// 98 GLUPS at four), four where the register wavefront is the default (more
+// than 2^22 sites of a single lattice; a batch always runs tiles).
+inline int default_time_blocking(int prec, long long sites, bool tiles_only = false) {
+    if (prec == LBM_FP64) return (tiles_only || sites <= (1LL << 22)) ? 5 : 4;
     return sites > (1LL << 17) ? 8 : 4;
 }
 

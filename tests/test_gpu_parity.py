@@ -401,8 +401,9 @@ def test_fused_kernel_argument_errors():
 
 def test_launch_config_defaults():
     """Default plain-step launches: eight steps per launch through the LDS tile
-    (16 rows, 512 threads) for FP32 and FP16 above 2^17 sites, four
-    otherwise and for FP64 (the wavefront above 2^22 FP64 sites); deeper
+    (16 rows, 512 threads) for FP32 and FP16 above 2^17 sites, four below; FP64
+    five steps through 8-row tiles of 512 threads, or four through the
+    wavefront above 2^22 sites; deeper
     blocking leaves the wavefront; one step per launch in place."""
     from paper_2208_14870_amd import lbm
     need_gpu()
@@ -415,14 +416,14 @@ def test_launch_config_defaults():
                                      "threads": 256}
     assert cfg(256, 256, "fp32") == {"steps_per_launch": 4, "kernel": "tile", "rows": 8,
                                      "threads": 512}
-    assert cfg(1024, 1024, "fp64") == {"steps_per_launch": 4, "kernel": "tile", "rows": 8,
-                                       "threads": 256}
+    assert cfg(1024, 1024, "fp64") == {"steps_per_launch": 5, "kernel": "tile", "rows": 8,
+                                       "threads": 512}
     assert cfg(2048, 2048, "fp64")["kernel"] == "tile"
     s = lbm.Solver(2900, 2900, "fp64")
     c = s.launch_config()
     assert c["kernel"] == "wavefront" and c["steps_per_launch"] == 4 and c["rows"] in (32, 64, 128, 256)
     s.set_time_blocking(6)
-    assert s.launch_config() == {"steps_per_launch": 6, "kernel": "tile", "rows": 8, "threads": 256}
+    assert s.launch_config() == {"steps_per_launch": 6, "kernel": "tile", "rows": 8, "threads": 512}
     s.set_time_blocking(3)  # default kernel again at three steps
     assert s.launch_config()["kernel"] == "wavefront"
     s.set_fused_kernel("tile")
