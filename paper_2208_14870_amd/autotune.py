@@ -35,7 +35,7 @@ def candidates(nx: int, min_bx: int = 3, ny: int = 0, wavefront: bool = False,
     with one workgroup per tile or a persistent grid, and (single lattices) the
     register wavefront with a few segment heights; single-step shapes only for
     in-place solvers (fused=False)."""
-    out = [(6, 4, k, t, 0) for t in (8, 6, 4, 3, 2) for k in (0, 4)] if fused else []
+    out = [(6, 4, k, t, 0) for t in (8, 7, 6, 5, 4, 3, 2) for k in (0, 4)] if fused else []
     if wavefront and fused:
         for rows in (32, 64, 128, 256):
             if rows <= max(ny, 32):
@@ -67,7 +67,7 @@ def _arch() -> str:
 
 
 def _key(kind: str, precision: str, sites: int) -> str:
-    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}|v5"
+    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}|v6"
 
 
 def _load(path: str) -> Dict[str, list]:
