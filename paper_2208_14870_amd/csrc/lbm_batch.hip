@@ -140,7 +140,7 @@ struct lbm_batch {
     Item* d_items = nullptr;
     double* d_partial = nullptr;
     SlotRow* d_rows = nullptr;
-    double* d_red = nullptr;  // kErrBlocks x 8 + 8 doubles of reduction scratch
+    double* d_red = nullptr;  // kErrBlocks x 8 + 16 doubles of reduction scratch
     long long cap_items = 0;
     // host
     SlotRow* h_rows = nullptr;  // pinned staging (max_slots rows + 3 ranges)
