@@ -44,7 +44,7 @@ struct lbm_solver {
     int* d_count = nullptr;
     double* d_partial = nullptr;
     double* d_result = nullptr;
-    double* d_red = nullptr;  // kErrBlocks x 8 + 8
+    double* d_red = nullptr;  // kErrBlocks x 8 + 16
     double* h_result = nullptr;  // pinned, 8 doubles
     long long max_items_ = 0;
     int nitems = 0;
