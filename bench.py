@@ -107,6 +107,10 @@ def parse():
                     help="run only the in-place vs two-buffer leg (for profiling)")
     ap.add_argument("--large-steps", type=int, default=10000)
     ap.add_argument("--large-warm", type=int, default=200)
+    ap.add_argument("--large-tb", type=int, default=0,
+                    help="steps per launch of the 8192^2 runs (0: library default; "
+                         "4 selects the default kernel at that depth, the register "
+                         "wavefront for FP64 and FP32)")
     return ap.parse_args()
 
 
@@ -182,7 +186,7 @@ def run_workload(solvers, nchunks, chunk):
             "last": last[-len(solvers):], "history": history}
 
 
-def large_lattice(steps=10000, warm=200, precs=("fp64", "fp32", "fp16")):
+def large_lattice(steps=10000, warm=200, precs=("fp64", "fp32", "fp16"), tb=0):
     """8192 x 8192 random 16-mode load (seed 3): throughput per storage
     precision over `steps` timed steps after `warm` untimed ones, and the
     FP32 / scaled-FP16 displacement error against the FP64 run (the FP64 GPU
@@ -201,6 +205,8 @@ def large_lattice(steps=10000, warm=200, precs=("fp64", "fp32", "fp16")):
         s = lbm.Solver(8192, 8192, prec)
         s.set_material(mat.lame_lambda, mat.lame_mu)
         s.set_body_force(gx, gy)
+        if tb:
+            s.set_time_blocking(tb)
         s.step(warm)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -414,7 +420,8 @@ def main():
         if args.calib_copy:
             calib_copy()
         precs = tuple(args.large_only.split(","))
-        print(json.dumps({"large_8192": large_lattice(args.large_steps, args.large_warm, precs)}),
+        print(json.dumps({"large_8192": large_lattice(args.large_steps, args.large_warm, precs,
+                                                      args.large_tb)}),
               flush=True)
         return
     cases = build_cases(args.cases)
