@@ -348,7 +348,7 @@ struct Lattice {
         gsum[1] = sy;
     }
     int bx_log2 = 6, vy = 1;
-    int tb = 4;       // plain steps per launch (2..4: fused multi-step kernel)
+    int tb = 4;       // plain steps per launch (2..8: fused multi-step kernel)
     int th = 16;      // tile height of the fused LDS kernel (fused_th)
     int wave_hs = 0;  // > 0: fused launches use the register wavefront, segments of wave_hs rows
     int cur = 0;      // buffer with the state at flip 0
