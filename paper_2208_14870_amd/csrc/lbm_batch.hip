@@ -294,21 +294,49 @@ struct lbm_batch {
         return tb[p] >= 2 && r >= 2 && stepN_supported(p, (int)r, th[p]);
     }
 
+    // Launches of np plain steps of precision p: groups of tb[p] through the
+    // fused kernel, the remainder as one shorter fused launch or single steps.
+    long long plain_launches(int p, long long np) const {
+        if (tb[p] < 2) return np;
+        const long long r = np % tb[p];
+        return np / tb[p] + (fused_rest(p, r) ? 1 : r);
+    }
+
+    // A checked sequence of n steps of precision p: `plain` steps through the
+    // ordinary launches, then one fused launch of `span` steps whose last two
+    // steps form the residual check (span 0: a write-u step and a check step,
+    // one step per launch).  The span makes the plain part whole launches: the
+    // remainder of n (at least 2), else a full launch.
+    void check_plan(int p, long long n, long long& plain, int& span) const {
+        plain = n - 2;
+        span = 0;
+        if (tb[p] < 2) return;
+        const long long r = n % tb[p];
+        const long long k = (r >= 2) ? r : tb[p];
+        if (k > n || !stepN_supported(p, (int)k, th[p])) return;
+        plain = n - k;
+        span = (int)k;
+    }
+
     // buffer flips of precision p in one batch_step
     long long launches(int p, long long nsteps, bool check) const {
-        const long long np = check ? nsteps - 2 : nsteps;
-        const long long r = tb[p] >= 2 ? np % tb[p] : 0;
-        return (tb[p] >= 2 ? np / tb[p] + (fused_rest(p, r) ? 1 : r) : np) + (check ? 2 : 0);
+        if (!check) return plain_launches(p, nsteps);
+        long long plain;
+        int span;
+        check_plan(p, nsteps, plain, span);
+        return plain_launches(p, plain) + (span ? 1 : 2);
     }
 
     // The launches of one batch_step, precision by precision (their lattices
     // and work-list ranges are disjoint), then one finalize over all slots.
     hipError_t enqueue(long long nsteps, bool check, hipStream_t st) {
         hipError_t e = hipSuccess;
-        const long long np = check ? nsteps - 2 : nsteps;
         for (int p = 0; p < 3 && e == hipSuccess; ++p) {
             const unsigned g = grid_for(p);
             if (!g) continue;
+            long long np = nsteps;
+            int span = 0;
+            if (check) check_plan(p, nsteps, np, span);
             long long ph = phase[p], i = 0;
             if (tb[p] >= 2) {
                 for (; i + tb[p] <= np && e == hipSuccess; i += tb[p], ++ph)
@@ -321,7 +349,9 @@ struct lbm_batch {
             }
             for (; i < np && e == hipSuccess; ++i, ++ph)
                 e = launch_step(p, kPlain, false, eff_vy(p), kLayPull, g, st, args(p, (int)(ph & 1)));
-            if (check && e == hipSuccess) {
+            if (check && e == hipSuccess && span) {
+                e = launch_stepN(p, span, th[p], g, st, args(p, (int)(ph & 1)), true);
+            } else if (check && e == hipSuccess) {
                 e = launch_step(p, kWriteU, false, eff_vy(p), kLayPull, g, st, args(p, (int)(ph & 1)));
                 ++ph;
                 if (e == hipSuccess)

@@ -147,11 +147,13 @@ __device__ __forceinline__ void stepN_load(const S* __restrict__ src,
     }
 }
 
+// up[a] receives u of the step (for a check launch of two steps, u(n - 1)).
 template <typename S, int TH, int NS, int NT = kBlock>
 __device__ __forceinline__ void stepN_collide1(typename Store<S>::C f[][8],
                                                const Coef<typename Store<S>::C>& k, S* lds,
                                                typename Store<S>::C gx[],
-                                               typename Store<S>::C gy[]) {
+                                               typename Store<S>::C gy[],
+                                               typename Store<S>::C up[][2]) {
     using C = typename Store<S>::C;
     constexpr int R = NS - 1;
     constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
@@ -161,10 +163,46 @@ __device__ __forceinline__ void stepN_collide1(typename Store<S>::C f[][8],
         const int e = (int)threadIdx.x + a * NT;
         gx[a] *= k.gscale;
         gy[a] *= k.gscale;
-        C ux, uy;
-        collide<C, false>(f[a], gx[a], gy[a], k, ux, uy);
+        collide<C, false>(f[a], gx[a], gy[a], k, up[a][0], up[a][1]);
         if (e < RN) lds_write<S, RW, RN>(lds, e, true, f[a]);
     }
+}
+
+// (sum, sum, max) over the NW waves of a workgroup in a fixed order; result
+// valid in thread 0.  lds: 3 NW doubles.
+template <int NW>
+__device__ __forceinline__ void block_reduce3n(double& a, double& b, double& m, double* lds) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    m = wave_max(m);
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    if (l == 0) {
+        lds[3 * w + 0] = a;
+        lds[3 * w + 1] = b;
+        lds[3 * w + 2] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa[NW], sb[NW], sm[NW];
+#pragma unroll
+        for (int v = 0; v < NW; ++v) {
+            sa[v] = lds[3 * v];
+            sb[v] = lds[3 * v + 1];
+            sm[v] = lds[3 * v + 2];
+        }
+#pragma unroll
+        for (int h = 1; h < NW; h *= 2)
+#pragma unroll
+            for (int v = 0; v + h < NW; v += 2 * h) {
+                sa[v] += sa[v + h];
+                sb[v] += sb[v + h];
+                sm[v] = fmax(sm[v], sm[v + h]);
+            }
+        a = sa[0];
+        b = sb[0];
+        m = sm[0];
+    }
+    __syncthreads();
 }
 
 // Steps 2..NS of the fused kernel for one tile whose step 1 is in LDS: middle
@@ -172,11 +210,19 @@ __device__ __forceinline__ void stepN_collide1(typename Store<S>::C f[][8],
 // the destination field.  Step k reads the swapped layout when k is even and
 // writes the natural one (and the reverse when k is odd); one barrier after
 // each step.
-template <typename S, int TH, int NS, int NT = kBlock>
+//
+// MODE kCheck (a launch whose last two steps are the two steps of a residual
+// check): each thread keeps u(n - 1) of its tile sites from the step before
+// the last (up), and the last step stores u(n) (FP64, unscaled, into u) and
+// reduces sum |u(n) - u(n - 1)|^2, sum |u(n)|^2 and max |f*| over the tile into
+// partial[0..2], as a check step after a write-u step does.
+template <typename S, int TH, int NS, int NT = kBlock, int MODE = kPlain>
 __device__ __forceinline__ void stepN_rest(S* __restrict__ dst, long long plane, int nx, int ny,
                                            int x0, int y0, const Coef<typename Store<S>::C>& k,
                                            S* lds, const typename Store<S>::C gx[],
-                                           const typename Store<S>::C gy[]) {
+                                           const typename Store<S>::C gy[],
+                                           typename Store<S>::C up[][2], double* u,
+                                           double inv_scale, double* partial, double* red) {
     using C = typename Store<S>::C;
     constexpr int R = NS - 1;
     constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
@@ -196,11 +242,16 @@ __device__ __forceinline__ void stepN_rest(S* __restrict__ dst, long long plane,
                 lds_read<S, RW, RN>(lds, e, even, f);
                 collide<C, false>(f, gx[a], gy[a], k, ux, uy);
                 lds_write<S, RW, RN>(lds, e, !even, f);
+                if (MODE == kCheck && m == R - 1) {
+                    up[a][0] = ux;
+                    up[a][1] = uy;
+                }
             }
         }
         __syncthreads();
     }
     constexpr bool last_even = (NS % 2) == 0;
+    double dsum = 0.0, ssum = 0.0, fmaxv = 0.0;
 #pragma unroll
     for (int a = 0; a < NM; ++a) {
         const int e = (int)threadIdx.x + a * NT;
@@ -213,18 +264,43 @@ __device__ __forceinline__ void stepN_rest(S* __restrict__ dst, long long plane,
             const unsigned sidx = (unsigned)y * (unsigned)nx + (unsigned)x;
 #pragma unroll
             for (int q = 0; q < 8; ++q) Store<S>::st(at_u32(pq[q], sidx), f[q]);
+            if constexpr (MODE == kCheck) {
+                const double uxd = (double)ux * inv_scale, uyd = (double)uy * inv_scale;
+                const double dx = uxd - (double)up[a][0] * inv_scale;
+                const double dy = uyd - (double)up[a][1] * inv_scale;
+                dsum += dx * dx + dy * dy;
+                ssum += uxd * uxd + uyd * uyd;
+                double mm = 0.0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) mm = fmax(mm, (double)fabs(f[q]));
+                fmaxv = fmax(fmaxv, mm);
+                const long long s = (long long)y * nx + x;  // u planes are FP64
+                glob(u)[s] = uxd;
+                glob(u)[plane + s] = uyd;
+            }
         }
     }
     __syncthreads();
+    if constexpr (MODE == kCheck) {
+        block_reduce3n<NT / kWave>(dsum, ssum, fmaxv, red);
+        if (threadIdx.x == 0) {
+            glob(partial)[0] = dsum;
+            glob(partial)[1] = ssum;
+            glob(partial)[2] = fmaxv;
+        }
+    }
 }
 
-template <typename S, int TH, int NS, int NT = kBlock>
+// MODE kPlain (advance) or kCheck (advance; the last two steps form a
+// residual check, partials per tile as the single-step check writes them).
+template <typename S, int TH, int NS, int NT = kBlock, int MODE = kPlain>
 static __global__ __launch_bounds__(NT) void k_stepN(StepLaunch L) {
     using C = typename Store<S>::C;
     constexpr int R = NS - 1;  // ring width of the first step
     constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
     constexpr int NM = (RN + NT - 1) / NT;  // ring sites per thread
     __shared__ S lds[8 * RN];
+    __shared__ double red[3 * (NT / kWave)];
     int last, stride, it;
     xcd_slice(L.range, last, stride, it);
     for (; it < last; it += stride) {
@@ -234,14 +310,15 @@ static __global__ __launch_bounds__(NT) void k_stepN(StepLaunch L) {
         Coef<C> k;
         k.load(d);
         const int x0 = item.tx * kTW, y0 = item.ty * TH;
-        C f[NM][8], gx[NM], gy[NM];
+        C f[NM][8], gx[NM], gy[NM], up[NM][2];
         stepN_load<S, TH, NS, NT>(reinterpret_cast<const S*>(d.buf[sel]),
                                   reinterpret_cast<const C*>(d.g), d.plane, d.nx, d.ny, x0, y0,
                                   f, gx, gy);
-        stepN_collide1<S, TH, NS, NT>(f, k, lds, gx, gy);
+        stepN_collide1<S, TH, NS, NT>(f, k, lds, gx, gy, up);
         __syncthreads();
-        stepN_rest<S, TH, NS, NT>(reinterpret_cast<S*>(d.buf[sel ^ 1]), d.plane, d.nx, d.ny, x0, y0,
-                                  k, lds, gx, gy);
+        stepN_rest<S, TH, NS, NT, MODE>(reinterpret_cast<S*>(d.buf[sel ^ 1]), d.plane, d.nx, d.ny,
+                                        x0, y0, k, lds, gx, gy, up, d.u, d.inv_scale,
+                                        L.partial + 3 * it, red);
     }
 }
 

@@ -154,27 +154,36 @@ inline bool stepN_supported(int prec, int ns, int th) {
 }
 
 template <typename S, int TH, int NT, int NS, int NSMAX>
-inline bool launch_stepN_ns(int ns, unsigned grid, hipStream_t st, const StepLaunch& L) {
+inline bool launch_stepN_ns(int ns, bool check, unsigned grid, hipStream_t st, const StepLaunch& L) {
     if (ns == NS) {
-        hipLaunchKernelGGL((k_stepN<S, TH, NS, NT>), dim3(grid), dim3(NT), 0, st, L);
+        if (check) hipLaunchKernelGGL((k_stepN<S, TH, NS, NT, kCheck>), dim3(grid), dim3(NT), 0, st, L);
+        else hipLaunchKernelGGL((k_stepN<S, TH, NS, NT>), dim3(grid), dim3(NT), 0, st, L);
         return true;
     }
-    if constexpr (NS < NSMAX) return launch_stepN_ns<S, TH, NT, NS + 1, NSMAX>(ns, grid, st, L);
+    if constexpr (NS < NSMAX)
+        return launch_stepN_ns<S, TH, NT, NS + 1, NSMAX>(ns, check, grid, st, L);
     return false;
 }
 
 // ns in 2..8 with stepN_supported(prec, ns, th); th is the tile height of the
-// work list (fused_th for the sequence's steps per launch).
+// work list (fused_th for the sequence's steps per launch).  check: the last
+// two steps form a residual check (partials per tile into L.partial, u(n) into
+// the slot's u planes), replacing a write-u step and a check step.
 inline hipError_t launch_stepN(int prec, int ns, int th, unsigned grid, hipStream_t st,
-                               const StepLaunch& L) {
+                               const StepLaunch& L, bool check = false) {
     bool ok = false;
-    if (prec == LBM_FP64 && th == 8) ok = launch_stepN_ns<double, 8, 512, 2, 8>(ns, grid, st, L);
-    else if (prec == LBM_FP32 && th == 8) ok = launch_stepN_ns<float, 8, 512, 2, 4>(ns, grid, st, L);
+    if (prec == LBM_FP64 && th == 8)
+        ok = launch_stepN_ns<double, 8, 512, 2, 8>(ns, check, grid, st, L);
+    else if (prec == LBM_FP32 && th == 8)
+        ok = launch_stepN_ns<float, 8, 512, 2, 4>(ns, check, grid, st, L);
     else if (prec == LBM_FP32 && th == 16 && ns <= 4)
-        ok = launch_stepN_ns<float, 16, 256, 2, 4>(ns, grid, st, L);
-    else if (prec == LBM_FP32 && th == 16) ok = launch_stepN_ns<float, 16, 512, 5, 8>(ns, grid, st, L);
-    else if (prec == LBM_FP16 && th == 12) ok = launch_stepN_ns<__half, 12, 256, 2, 4>(ns, grid, st, L);
-    else if (prec == LBM_FP16 && th == 16) ok = launch_stepN_ns<__half, 16, 512, 2, 8>(ns, grid, st, L);
+        ok = launch_stepN_ns<float, 16, 256, 2, 4>(ns, check, grid, st, L);
+    else if (prec == LBM_FP32 && th == 16)
+        ok = launch_stepN_ns<float, 16, 512, 5, 8>(ns, check, grid, st, L);
+    else if (prec == LBM_FP16 && th == 12)
+        ok = launch_stepN_ns<__half, 12, 256, 2, 4>(ns, check, grid, st, L);
+    else if (prec == LBM_FP16 && th == 16)
+        ok = launch_stepN_ns<__half, 16, 512, 2, 8>(ns, check, grid, st, L);
     if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }

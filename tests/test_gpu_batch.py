@@ -148,6 +148,39 @@ def test_per_precision_time_blocking():
             assert np.isfinite(r0) and r1_ == pytest.approx(r0, rel=1e-12)
 
 
+@pytest.mark.parametrize("chunks", [(200, 201), (13, 9), (16, 2)])
+def test_fused_check_equals_single_step_check(chunks):
+    """A checked chunk ends in one fused launch whose last two steps form the
+    residual check (a full launch, the remainder, or a full launch after one
+    single step): displacements equal those of a batch that checks with single
+    steps, residuals equal to rounding (their summation follows the launch)."""
+    say(f"batch fused check {chunks}")
+    cases = _cases()
+    precs = ["fp32", "fp64", "fp16", "fp32", "fp64", "fp16"]
+    runs = []
+    for tb in (1, 8):
+        b = _batch()
+        slots = [b.add(c.nx, c.ny, c.material.lame_lambda, c.material.lame_mu, dev(c.gx),
+                       dev(c.gy), p) for c, p in zip(cases, precs)]
+        b.set_time_blocking(tb)
+        out = []
+        for n in chunks:
+            b.step(n, check=True)
+            r, steps = b.residuals()
+            out.append(([r[sl] for sl in slots], [steps[sl] for sl in slots]))
+        u = [tuple(host(t) for t in b.displacement(sl)) for sl in slots]
+        runs.append((out, u))
+        b.close()
+    (o1, u1), (o8, u8) = runs
+    for (r1, n1), (r8, n8) in zip(o1, o8):
+        assert n1 == n8
+        for a, b_ in zip(r1, r8):
+            assert np.isfinite(a) and b_ == pytest.approx(a, rel=1e-12, abs=1e-300)
+    for k, p in enumerate(precs):
+        for x, y in zip(u1[k], u8[k]):
+            np.testing.assert_array_equal(x, y, err_msg=f"{p} {cases[k].label}")
+
+
 def test_displacements_of_several_slots():
     """One copy of several lattices' displacements (page-locked host memory)
     equals the per-slot reads, for mixed precisions and shapes."""
