@@ -137,8 +137,8 @@ def kernel_label(cfg, ctype, sites):
     tb, rows, nt = cfg["steps_per_launch"], cfg["rows"], cfg["threads"]
     per_site = {"double": 144, "float": 72, "__half": 40}[ctype]
     side = int(round(math.sqrt(sites)))
-    if cfg["kernel"] == "tile":
-        return (f"k_stepN<{ctype}, {rows}, {tb}, {nt}> (LDS tile 64 x {rows} + ring {tb - 1}, "
+    if cfg["kernel"] == "tile":  # template arguments: type, tile rows, steps, threads, plain mode
+        return (f"k_stepN<{ctype}, {rows}, {tb}, {nt}, 0> (LDS tile 64 x {rows} + ring {tb - 1}, "
                 f"{nt} threads): {tb} fused steps per launch, {per_site} B per site-update "
                 f"algorithmic, {tb} x {side}^2 site-updates per launch")
     if cfg["kernel"] == "wavefront":
