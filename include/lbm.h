@@ -140,6 +140,15 @@ int lbm_reset(lbm_solver *s);
 /* Advance nsteps >= 0 steps of Algorithm 1 (asynchronous on the stream). */
 int lbm_step(lbm_solver *s, long long nsteps);
 
+/* Advance nsteps >= 2 steps and return (host double *residual) the steady-state
+ * residual of the last two: r(n - 1) = ||u(n - 1) - u(n - 2)||_2 / ||u(n - 1)||_2
+ * (Sec. 7.1 grid norm, FP64, R10), n = the step count after the call.  With two
+ * buffers and the LDS tile kernel the check rides on the last fused launch.
+ * Half storage is rescaled after the check as in lbm_solve_to_tol.  Blocking.
+ * Errors: LBM_E_ARG, LBM_E_STATE, LBM_E_DIVERGED (residual not finite),
+ * LBM_E_HIP. */
+int lbm_step_checked(lbm_solver *s, long long nsteps, double *residual);
+
 /* Pseudo-time stepping to steady state (blocking).  Steps and evaluates
  * r(n) = ||u(n) - u(n-1)||_2 / ||u(n)||_2 (FP64 sums over all nodes and both
  * components; 0 if both vanish) after every `check_every` >= 1 steps of this

@@ -143,23 +143,57 @@ struct lbm_solver {
         return hipGetLastError();
     }
 
-    // Launches for `nplain` plain steps (groups of L.tb through the fused kernel
-    // when enabled, the remainder as one shorter fused launch where a kernel
-    // exists for it, else one per launch), then optionally a writeU step
-    // and a residual check (a check step, or in place a launch without a step)
-    // + finalize.
+    // Steps per captured graph of plain steps: about 64, whole launches.
+    long long graph_chunk() const {
+        return L.fused() ? std::max(1, 64 / L.tb) * (long long)L.tb : 64;
+    }
+
+    // Launches of np plain steps: groups of L.tb through the fused kernel when
+    // enabled, the remainder as one shorter fused launch where a kernel exists
+    // for it, else one per launch.
+    long long plain_launches(long long np) const {
+        if (!L.fused()) return np;
+        const long long r = np % L.tb;
+        return np / L.tb + (fused_rest(r) ? 1 : r);
+    }
+
+    // Steps of the fused launch that ends a sequence of n steps whose last two
+    // are a write-u step and a check step (two buffers, LDS tile kernel): the
+    // remainder of n (at least 2), else a full launch, so that the plain part
+    // is whole launches; 0 when that launch has no kernel (the two steps then
+    // run one per launch).
+    int check_span(long long n) const {
+        if (!L.fused() || L.wave_hs > 0 || L.inplace) return 0;
+        const long long r = n % L.tb;
+        const long long k = (r >= 2) ? r : L.tb;
+        return (k <= n && stepN_supported(L.prec, (int)k, L.th)) ? (int)k : 0;
+    }
+
+    // Launches for `nplain` plain steps, then optionally a write-u step and a
+    // residual check (a check step, or in place a launch without a step) +
+    // finalize.  With two buffers and the tile kernel, the write-u step, the
+    // check step and the plain steps before them that do not fill a launch run
+    // as one fused launch whose last two steps form the check.
     hipError_t enqueue_seq(long long nplain, bool writeu, bool check, hipStream_t st,
                            long long& ph) {
         hipError_t e = hipSuccess;
+        const int span = (writeu && check) ? check_span(nplain + 2) : 0;
+        const long long np = span ? nplain + 2 - span : nplain;
         long long i = 0;
         if (L.fused()) {
-            for (; i + L.tb <= nplain && e == hipSuccess; i += L.tb) e = enqueue_fused(L.tb, st, ph);
-            if (e == hipSuccess && fused_rest(nplain - i)) {
-                e = enqueue_fused((int)(nplain - i), st, ph);
-                i = nplain;
+            for (; i + L.tb <= np && e == hipSuccess; i += L.tb) e = enqueue_fused(L.tb, st, ph);
+            if (e == hipSuccess && fused_rest(np - i)) {
+                e = enqueue_fused((int)(np - i), st, ph);
+                i = np;
             }
         }
-        for (; i < nplain && e == hipSuccess; ++i) e = enqueue_one(kPlain, st, ph);
+        for (; i < np && e == hipSuccess; ++i) e = enqueue_one(kPlain, st, ph);
+        if (e == hipSuccess && span) {
+            e = launch_stepN(L.prec, span, L.th, grid, st, launch_args((int)(ph & 1)), true);
+            ++ph;
+            if (e == hipSuccess) e = enqueue_finalize(st);
+            return e;
+        }
         if (e == hipSuccess && writeu) e = enqueue_one(kWriteU, st, ph);
         if (e == hipSuccess && check) {
             if (L.inplace) {
@@ -176,14 +210,22 @@ struct lbm_solver {
 
     // buffer flips (launch-parity increments) of enqueue_seq
     long long launches(long long nplain, bool writeu, bool check) const {
-        const long long r = L.fused() ? nplain % L.tb : 0;
-        const long long p = L.fused() ? nplain / L.tb + (fused_rest(r) ? 1 : r) : nplain;
-        return p + (writeu ? 1 : 0) + (check && !L.inplace ? 1 : 0);
+        const int span = (writeu && check) ? check_span(nplain + 2) : 0;
+        if (span) return plain_launches(nplain + 2 - span) + 1;
+        return plain_launches(nplain) + (writeu ? 1 : 0) + (check && !L.inplace ? 1 : 0);
+    }
+
+    // Steps of the launch that ends enqueue_chunk(nplain, writeu, true) (the
+    // check launch): a fused check launch's span, else 1.
+    int check_launch_steps(long long nplain, bool writeu) const {
+        const long long rest = nplain % graph_chunk();
+        const int span = writeu ? check_span(rest + 2) : 0;
+        return span ? span : 1;
     }
 
     // Enqueue a chunk; long runs are replayed from captured graphs.
     hipError_t enqueue_chunk(long long nplain, bool writeu, bool check) {
-        const long long kGraphChunk = 64;
+        const long long kGraphChunk = graph_chunk();
         hipError_t e;
         while (nplain >= kGraphChunk) {
             if ((e = run_graph(kGraphChunk, false, false)) != hipSuccess) return e;
@@ -611,6 +653,7 @@ int lbm_solve_to_tol(lbm_solver* s, double tol, long long max_steps, int check_e
                                          : !(have_prev_u && j - 1 == n - 1);
         const long long nplain =
             inplace ? (j - n - (need_writeu ? 1 : 0)) : (need_writeu ? (j - 1 - n) : 0);
+        const int span = s->check_launch_steps(nplain, need_writeu);
         hipError_t e = s->enqueue_chunk(nplain, need_writeu, true);
         if (e == hipSuccess)
             e = hipMemcpyAsync(s->h_result, s->d_result, 4 * 8, hipMemcpyDeviceToHost, s->stream);
@@ -631,9 +674,16 @@ int lbm_solve_to_tol(lbm_solver* s, double tol, long long max_steps, int check_e
         }
         if (r <= tol || j == max_steps) {
             if (!inplace) {
-                // the check launch advanced to j + 1; its source buffer still holds f(j)
+                // the check launch advanced to j + 1 and its source buffer still
+                // holds the state it started from, f(j + 1 - span): take the
+                // launch back and advance the span - 1 steps to f(j) again
                 s->phase -= 1;
-                s->steps -= 1;
+                s->steps -= span;
+                if (span > 1) {
+                    hipError_t e2 = s->enqueue_chunk(span - 1, false, false);
+                    if (e2 != hipSuccess) return s->hip_fail(e2, "solve_to_tol");
+                    s->steps += span - 1;
+                }
             }
             n = j;
             *steps_done = n;
@@ -654,6 +704,41 @@ int lbm_solve_to_tol(lbm_solver* s, double tol, long long max_steps, int check_e
         }
         r_last = r;
     }
+}
+
+int lbm_step_checked(lbm_solver* s, long long nsteps, double* residual) {
+    if (!s) return LBM_E_ARG;
+    if (nsteps < 2 || !residual)
+        return s->fail(LBM_E_ARG, "step_checked: need nsteps >= 2 and a residual output");
+    if (!s->L.has_material || !s->L.has_force)
+        return s->fail(LBM_E_STATE, "step_checked: material and body force must be set first");
+    *residual = NAN;
+    // two buffers: nsteps - 2 plain steps, a write-u step and the check step;
+    // in place: the check launch does not step, so one plain step follows it
+    hipError_t e = s->enqueue_chunk(nsteps - 2, true, true);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->h_result, s->d_result, 4 * 8, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "step_checked");
+    s->steps += s->L.inplace ? nsteps - 1 : nsteps;
+    const double d2 = s->h_result[0], u2 = s->h_result[1], fm = s->h_result[2];
+    double r = (u2 == 0.0) ? (d2 == 0.0 ? 0.0 : INFINITY) : std::sqrt(d2 / u2);
+    if (d2 != d2 || u2 != u2 || !std::isfinite(u2) || !std::isfinite(fm)) r = NAN;
+    *residual = r;
+    if (!std::isfinite(r) && !(u2 == 0.0 && d2 != 0.0)) {
+        s->err = "step_checked: residual is not finite (diverged)";
+        return LBM_E_DIVERGED;
+    }
+    if (s->L.prec == LBM_FP16) {
+        int rc = rescale_half(s, fm);
+        if (rc != LBM_OK) return rc;
+    }
+    if (s->L.inplace) {
+        if ((e = s->enqueue_chunk(1, false, false)) != hipSuccess)
+            return s->hip_fail(e, "step_checked");
+        s->steps += 1;
+    }
+    return LBM_OK;
 }
 
 int lbm_get_displacement(lbm_solver* s, double* ux, double* uy) {

@@ -57,6 +57,7 @@ def load() -> ctypes.CDLL:
         "lbm_set_body_force": (i, [vp, vp, vp]),
         "lbm_reset": (i, [vp]),
         "lbm_step": (i, [vp, ll]),
+        "lbm_step_checked": (i, [vp, ll, pd]),
         "lbm_solve_to_tol": (i, [vp, d, ll, i, pll, pd]),
         "lbm_set_polish": (i, [vp, d]),
         "lbm_current_precision": (i, [vp]),
@@ -217,6 +218,13 @@ class Solver:
 
     def step(self, nsteps: int):
         self._check(self.lib.lbm_step(self.h, int(nsteps)))
+
+    def step_checked(self, nsteps: int) -> float:
+        """Advance nsteps >= 2 steps; returns the residual r(n - 1) of the last
+        two steps' displacements (see lbm_step_checked)."""
+        r = ctypes.c_double(0.0)
+        self._check(self.lib.lbm_step_checked(self.h, int(nsteps), ctypes.byref(r)))
+        return r.value
 
     def solve_to_tol(self, tol: float, max_steps: int, check_every: int = 1):
         """Returns (steps_done, residual, status) with status 0 converged, 1 not."""

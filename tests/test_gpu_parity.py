@@ -127,6 +127,46 @@ def test_fp64_check_interval_matches_oracle(K):
     assert rel_l2(ux, ox, uy, oy) <= 1e-12
 
 
+@pytest.mark.parametrize("prec,nx,ny,n,tb", [
+    ("fp64", 48, 48, 30, 5), ("fp64", 48, 48, 30, 1), ("fp64", 33, 17, 9, 4),
+    ("fp32", 70, 40, 18, 8), ("fp32", 70, 40, 17, 8), ("fp64", 24, 24, 2, 8),
+    ("fp16", 64, 64, 21, 8)])
+def test_step_checked(prec, nx, ny, n, tb):
+    """step_checked(n) advances n steps (f(n) as n plain steps, bit for bit) and
+    returns r(n - 1) of the oracle (FP64: to 1e-9; the check may ride on the last
+    fused launch of any span)."""
+    say(f"step_checked {prec} {nx}x{ny} n {n} tb {tb}")
+    from paper_2208_14870_amd import lbm
+    mat = P.Material.from_shear_poisson(0.9, 0.3)
+    f0, gx, gy = _rand_state(nx, ny, 13 + nx)
+    out = []
+    for checked in (True, False):
+        s = _solver(nx, ny, prec)
+        s.set_material(mat.lame_lambda, mat.lame_mu)
+        s.set_body_force(dev(gx), dev(gy))
+        s.set_populations(dev(f0))
+        s.set_time_blocking(tb)
+        r = s.step_checked(n) if checked else s.step(n)
+        assert s.steps_done == n
+        out.append((r, host(s.populations())))
+        s.close()
+    if prec == "fp16":
+        # the half-storage rescale after the check is exact for normal halves
+        # and moves subnormal ones by at most half their spacing
+        np.testing.assert_allclose(out[0][1], out[1][1], rtol=0, atol=1e-10)
+    else:
+        np.testing.assert_array_equal(out[0][1], out[1][1])
+    assert np.isfinite(out[0][0])
+    if prec == "fp64":
+        f = O.run(f0, gx, gy, omega(mat), n - 2)
+        ua = O.displacement(f, gx, gy)
+        f = O.run(f, gx, gy, omega(mat), 1)
+        ub = O.displacement(f, gx, gy)
+        assert out[0][0] == pytest.approx(O.residual(ub[0], ub[1], ua[0], ua[1]), rel=1e-9)
+    with pytest.raises(lbm.LbmError):
+        _solver(8, 8, prec).step_checked(1)
+
+
 def test_fp64_max_steps_not_converged():
     say("fp64 max_steps")
     c = P.single_32()
