@@ -115,6 +115,7 @@ def test_per_precision_time_blocking():
     with residual checks and a promotion of a polish lattice in between, give
     every lattice the populations of a batch stepping once per launch."""
     say("batch per-precision time blocking")
+    from paper_2208_14870_amd import lbm
     cases = _cases()
     precs = ["fp64", "fp32", "fp16", "fp32", "fp16", "fp64"]
     runs = []
@@ -126,6 +127,11 @@ def test_per_precision_time_blocking():
             b.set_time_blocking(3, "fp64")
             b.set_time_blocking(7, "fp32")
             b.set_time_blocking(1, "fp16")
+            for bad in (0, 9):
+                with pytest.raises(lbm.LbmError):
+                    b.set_time_blocking(bad, "fp32")
+            with pytest.raises(KeyError):
+                b.set_time_blocking(4, "bf16")
         else:
             b.set_time_blocking(1)
         b.step(23, check=True)

@@ -89,6 +89,24 @@ def test_inplace_solve_to_tol(prec, K):
         assert ra[0] == 113 or K > 1  # the oracle's stop step at K = 1
 
 
+@pytest.mark.parametrize("prec,n", [("fp64", 2), ("fp64", 17), ("fp32", 40)])
+def test_inplace_step_checked(prec, n):
+    """step_checked in place (its check launch does not step, a plain step
+    follows it) leaves the state of the two-buffer solver and returns its
+    residual r(n - 1)."""
+    say(f"inplace step_checked {prec} n {n}")
+    c = P.single_32()
+    rng = np.random.default_rng(5)
+    f0 = rng.standard_normal((8, 32, 32)) * 1e-3
+    a, b = _pair(32, 32, prec, c.material, c.gx, c.gy, f0=f0)
+    a.set_time_blocking(8 if prec == "fp32" else 5)
+    ra = a.step_checked(n)
+    rb = b.step_checked(n)
+    assert a.steps_done == b.steps_done == n
+    assert rb == pytest.approx(ra, rel=1e-12)
+    np.testing.assert_array_equal(host(b.populations()), host(a.populations()))
+
+
 def test_inplace_max_steps_and_continue():
     """A capped solve leaves f(max_steps); stepping on and solving again agrees."""
     say("inplace max steps")
