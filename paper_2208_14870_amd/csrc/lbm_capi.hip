@@ -88,7 +88,8 @@ struct lbm_solver {
         hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, stream, d_first, 0);
         hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, stream, d_count, nitems);
         hipLaunchKernelGGL(k_build_items, dim3(blocks_for(nitems)), dim3(kBlock), 0, stream,
-                           d_items, 0, 0, d.tiles_x, nitems);
+                           d_items, 0, 0, d.tiles_x, nitems,
+                           (L.fused() && L.wave_hs == 0) ? kItemBand : 0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "descriptor upload");
         unsigned g = (unsigned)((nitems + 7) / 8 * 8);

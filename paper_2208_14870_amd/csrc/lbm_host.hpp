@@ -18,6 +18,10 @@ using namespace lbm;
 
 
 constexpr size_t kAlign = 256;
+// Tiles per vertical band of a single lattice's work list for the fused tile
+// kernel (single steps stream best in row-major order: 8192^2 FP32 81 against
+// 76 GLUPS).
+constexpr int kItemBand = 8;
 inline size_t al(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 inline size_t elem_bytes(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2); }

@@ -199,15 +199,29 @@ static __global__ __launch_bounds__(kBlock) void k_reduce4(const double* partial
         for (int c = 0; c < 4; ++c) out[c] = v[c];
 }
 
-// Write the work list of one lattice: tiles in row-major tile order.
+// Write the work list of one lattice: tiles in vertical bands `band` tiles
+// wide, each band row by row (band >= tiles_x: row-major order).  Each XCD
+// walks a contiguous slice of the list, so a tile's neighbours above and
+// below (whose rings overlap its own) run shortly before and after it on the
+// same XCD and find those rows in its L2 (measured on MI355X with bands of 8
+// tiles: 8192^2 FP32 286 against 271 GLUPS, 2048^2 FP64 119 against 111).
 static __global__ __launch_bounds__(kBlock) void k_build_items(Item* items, int first, int slot,
-                                                        int tiles_x, int count) {
+                                                        int tiles_x, int count, int band) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= count) return;
     Item it;
     it.slot = slot;
-    it.tx = i % tiles_x;
-    it.ty = i / tiles_x;
+    if (band <= 0 || band >= tiles_x) {
+        it.tx = i % tiles_x;
+        it.ty = i / tiles_x;
+    } else {
+        const int tiles_y = count / tiles_x;
+        const int per = band * tiles_y;  // items of a full band
+        const int b = i / per, j = i - b * per;
+        const int w = min(band, tiles_x - b * band);  // the last band may be narrower
+        it.ty = j / w;
+        it.tx = b * band + j % w;
+    }
     it.pad_ = 0;
     items[first + i] = it;
 }
