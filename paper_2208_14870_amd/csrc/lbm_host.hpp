@@ -82,8 +82,10 @@ inline hipError_t launch_step_l(bool general, int vy, unsigned grid, hipStream_t
         hipLaunchKernelGGL((k_step<S, MODE, false, 2, LAY>), dim3(grid), dim3(kBlock), 0, st, L);
     } else if (vy == 3) {
         hipLaunchKernelGGL((k_step<S, MODE, false, 3, LAY>), dim3(grid), dim3(kBlock), 0, st, L);
-    } else {
+    } else if (vy == 4) {
         hipLaunchKernelGGL((k_step<S, MODE, false, 4, LAY>), dim3(grid), dim3(kBlock), 0, st, L);
+    } else {
+        return hipErrorInvalidValue;  // rows per thread outside 1..4
     }
     return hipGetLastError();
 }
@@ -108,23 +110,25 @@ inline hipError_t launch_step_s(int mode, bool general, int vy, int layout, unsi
 
 // Non-advancing residual check of an in-place lattice (layout natural or swapped).
 template <typename S, int LAY>
-inline void launch_check_state_l(int vy, unsigned grid, hipStream_t st, const StepLaunch& L) {
+inline hipError_t launch_check_state_l(int vy, unsigned grid, hipStream_t st, const StepLaunch& L) {
     if (vy == 1) hipLaunchKernelGGL((k_check_state<S, LAY, 1>), dim3(grid), dim3(kBlock), 0, st, L);
     else if (vy == 2) hipLaunchKernelGGL((k_check_state<S, LAY, 2>), dim3(grid), dim3(kBlock), 0, st, L);
     else if (vy == 3) hipLaunchKernelGGL((k_check_state<S, LAY, 3>), dim3(grid), dim3(kBlock), 0, st, L);
-    else hipLaunchKernelGGL((k_check_state<S, LAY, 4>), dim3(grid), dim3(kBlock), 0, st, L);
+    else if (vy == 4) hipLaunchKernelGGL((k_check_state<S, LAY, 4>), dim3(grid), dim3(kBlock), 0, st, L);
+    else return hipErrorInvalidValue;  // rows per thread outside 1..4
+    return hipGetLastError();
 }
 template <typename S>
-inline void launch_check_state_s(int vy, int layout, unsigned grid, hipStream_t st, const StepLaunch& L) {
-    if (layout == kLaySwapped) launch_check_state_l<S, kLaySwapped>(vy, grid, st, L);
-    else launch_check_state_l<S, kLayNatural>(vy, grid, st, L);
+inline hipError_t launch_check_state_s(int vy, int layout, unsigned grid, hipStream_t st,
+                                       const StepLaunch& L) {
+    if (layout == kLaySwapped) return launch_check_state_l<S, kLaySwapped>(vy, grid, st, L);
+    return launch_check_state_l<S, kLayNatural>(vy, grid, st, L);
 }
 inline hipError_t launch_check_state(int prec, int vy, int layout, unsigned grid, hipStream_t st,
                                      const StepLaunch& L) {
-    if (prec == LBM_FP64) launch_check_state_s<double>(vy, layout, grid, st, L);
-    else if (prec == LBM_FP32) launch_check_state_s<float>(vy, layout, grid, st, L);
-    else launch_check_state_s<__half>(vy, layout, grid, st, L);
-    return hipGetLastError();
+    if (prec == LBM_FP64) return launch_check_state_s<double>(vy, layout, grid, st, L);
+    if (prec == LBM_FP32) return launch_check_state_s<float>(vy, layout, grid, st, L);
+    return launch_check_state_s<__half>(vy, layout, grid, st, L);
 }
 
 // Shapes of the fused LDS tile kernel (tile 64 x TH, NT threads) per storage
