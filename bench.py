@@ -11,9 +11,12 @@ manufactured solution; the default 20 steps make the 20k pseudo-time steps of
 the configuration.  `value` is whole-job MLUPS (site updates per second).
 
 Also reported on the same JSON line:
-  roofline      -- plain step kernel of the headline run: algorithmic bytes
-                   (72 B per FP32 site update) / average launch duration from
-                   HIP events on the library's stream, against 8 TB/s;
+  roofline      -- dominant kernel of the headline run (the fused tile
+                   kernel, several steps per launch): algorithmic bytes (72 B
+                   per FP32 site update x sites x steps per launch) / average
+                   launch duration from HIP events on the library's stream,
+                   against 8 TB/s, plus the HBM bytes per launch that the
+                   committed rocprofv3 counter summary measured;
   fp64          -- the same workload with FP64 storage;
   large_8192    -- 8192 x 8192 FP64 / FP32 / scaled-FP16 step throughput (the
                    working set exceeds the 256 MB last-level cache) and the
