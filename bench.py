@@ -134,6 +134,10 @@ def parse():
                     help="comma list of precisions: run only the 8192^2 leg (for profiling)")
     ap.add_argument("--inplace-only", action="store_true",
                     help="run only the in-place vs two-buffer leg (for profiling)")
+    ap.add_argument("--batch-only", default="",
+                    help="comma list of precisions: run only the 512-lattice batch leg "
+                         "(for profiling)")
+    ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--large-steps", type=int, default=10000)
     ap.add_argument("--large-warm", type=int, default=200)
     ap.add_argument("--large-tb", type=int, default=0,
@@ -445,6 +449,12 @@ def main():
             calib_copy()
         print(json.dumps({"inplace_8192": inplace_run(steps=args.large_steps,
                                                       warm=args.large_warm)}), flush=True)
+        return
+    if args.batch_only:
+        if args.calib_copy:
+            calib_copy()
+        print(json.dumps({"batch": {p: batch_run(p, steps=args.batch_steps)
+                                    for p in args.batch_only.split(",")}}), flush=True)
         return
     if args.large_only:
         if args.calib_copy:
