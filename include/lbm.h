@@ -196,7 +196,10 @@ int lbm_error_norms(lbm_solver *s, const double *ux_ref, const double *uy_ref, d
 /* Checkpoint / restart: the pre-collision populations f(n) as FP64 device
  * arrays [8][ny][nx] (paper order, unscaled).  set leaves the step count
  * unchanged and is blocking (it records the mean first moments of the given
- * state for the polish switch). */
+ * state for the polish switch).  With half storage, set first picks the
+ * power-of-two scale so that the state's max |f| maps to 2^12 (never finer
+ * than the force's steady-state bound), so that no state overflows the half
+ * range; LBM_E_ARG for a non-finite state. */
 int lbm_get_populations(lbm_solver *s, double *f);
 int lbm_set_populations(lbm_solver *s, const double *f);
 

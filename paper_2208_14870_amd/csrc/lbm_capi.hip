@@ -803,6 +803,32 @@ int lbm_get_populations(lbm_solver* s, double* f) {
 int lbm_set_populations(lbm_solver* s, const double* f) {
     if (!s) return LBM_E_ARG;
     if (!f) return s->fail(LBM_E_ARG, "set_populations: NULL input");
+    if (s->L.prec == LBM_FP16) {
+        // Half storage: choose the power-of-two scale for the given state, so
+        // that its max |f| maps to 2^12 (the middle of the window the checked
+        // rescale keeps), and never finer than the force's steady-state bound.
+        // Otherwise a state far above that bound would overflow the half range.
+        Lattice& L = s->L;
+        const long long h = 4 * L.N;  // the eight planes as two halves
+        hipLaunchKernelGGL(k_force_stats, dim3(kErrBlocks), dim3(kBlock), 0, s->stream, f, f + h,
+                           h, s->d_red);
+        hipLaunchKernelGGL(k_reduce4<kForceMask>, dim3(1), dim3(kBlock), 0, s->stream, s->d_red,
+                           kErrBlocks, s->d_red + 4 * kErrBlocks);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->h_result, s->d_red + 4 * kErrBlocks, 4 * 8,
+                               hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return s->hip_fail(e, "set_populations: max |f|");
+        const double fmax = s->h_result[3];
+        if (!std::isfinite(fmax)) return s->fail(LBM_E_ARG, "set_populations: non-finite input");
+        int es = (L.has_force && L.has_material) ? initial_half_exponent(L, L.gmax) : -100;
+        if (fmax > 0.0) es = std::max(es, (int)std::ceil(std::log2(fmax / 4096.0)));
+        if (es == -100 && !(fmax > 0.0)) es = L.e_scale;  // nothing to fit
+        L.e_scale = std::max(-100, std::min(100, es));
+        const int rc = s->sync_desc();
+        if (rc != LBM_OK) return rc;
+    }
     const SlotDesc d = s->L.desc();
     const double sc = d.gscale;
     hipError_t e;

@@ -536,6 +536,49 @@ def test_fp16_error_vs_oracle():
     assert err <= 5e-2
 
 
+@pytest.mark.parametrize("n,scale", [(8, 1e-3), (5, 1e-3), (64, 1.0)])
+def test_fp16_set_populations_fits_the_state(n, scale):
+    """Half storage picks its power-of-two scale from a state set by the caller:
+    a state far above the force's steady-state bound (tiny lattice, large
+    populations) neither overflows the half range nor loses its digits; 30
+    steps without a check stay finite and within half rounding of the FP64
+    oracle."""
+    say(f"fp16 set_populations {n}x{n} scale {scale}")
+    f0, gx, gy = _rand_state(n, n, 11, scale)
+    gx, gy = gx * 1e-2, gy * 1e-2
+    mat = P.Material.from_shear_poisson(1.0, 0.3)
+    s = _solver(n, n, "fp16")
+    s.set_material(mat.lame_lambda, mat.lame_mu)
+    s.set_body_force(dev(gx), dev(gy))
+    s.set_populations(dev(f0))
+    back = host(s.populations())
+    assert np.all(np.isfinite(back))
+    assert rel_l2(back, f0) <= 1e-3  # stored within half rounding
+    s.step(30)
+    got = host(s.populations())
+    want = O.run(f0, gx, gy, omega(mat), 30)
+    err = rel_l2(got, want)
+    say(f"  rel err vs fp64 oracle after 30 steps: {err:.3e}")
+    assert np.all(np.isfinite(got)) and err <= 3e-3
+
+
+def test_fp16_zero_state_keeps_the_force_scale():
+    """Setting an all-zero state leaves the scale the force chose: the run is
+    bit-identical to a fresh solver's."""
+    say("fp16 zero state")
+    c = P.single_1024(0.3, 1, 1, n=64)
+    out = []
+    for set_zero in (False, True):
+        s = _solver(64, 64, "fp16")
+        s.set_material(c.material.lame_lambda, c.material.lame_mu)
+        s.set_body_force(dev(c.gx), dev(c.gy))
+        if set_zero:
+            s.set_populations(dev(np.zeros((8, 64, 64))))
+        s.step(50)
+        out.append(host(s.populations()))
+    assert np.array_equal(out[0], out[1])
+
+
 def test_fp32_polish_reaches_fp64_tolerance():
     """FP32 storage with the FP64 polish phase reaches r <= 1e-11 and then agrees
     with the FP64 steady state to the residual's stopping error."""
