@@ -1,0 +1,152 @@
+"""Seeded random configurations of the whole solver surface.
+
+Single lattices: random shapes (1..300 per side), storage types, fused kernels
+(LDS tile at 2..8 steps per launch, register wavefront at 2..4 with random
+segment heights, in-place streaming), random step counts and residual-checked
+runs, each against the same lattice stepped once per launch: populations and
+displacement bit-identical, the checked residual equal to rounding of its
+reduction order (the partial sums follow the tile shape), and FP64 within 1e-12
+of the oracle on small lattices.
+
+Batches: random mixes of lattices with a depth per storage type, plain and
+checked chunks, removals and late additions; every lattice still resident
+equals a solo solver stepped as many steps (bit-identical; half storage to
+1e-9 of max |u|, since checks rescale it and subnormal halves round apart).
+"""
+import json
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2208_14870_amd import problem as P
+from gpu_common import dev, host, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _side(rng):
+    r = rng.random()
+    if r < 0.25:
+        return int(rng.integers(1, 9))
+    if r < 0.7:
+        return int(rng.integers(9, 140))
+    return int(rng.integers(140, 300))
+
+
+def _material(rng):
+    return P.Material.from_shear_poisson(float(rng.uniform(0.2, 2.0)), float(rng.uniform(0.05, 0.45)))
+
+
+def _load(rng, nx, ny, scale=1e-5):
+    gx = P.remove_mean(rng.standard_normal((ny, nx)) * scale)
+    gy = P.remove_mean(rng.standard_normal((ny, nx)) * scale)
+    return gx, gy
+
+
+def _run_single(lbm, cfg, mat, f0, gx, gy, reference):
+    nx, ny = cfg["nx"], cfg["ny"]
+    s = lbm.Solver(nx, ny, cfg["prec"], inplace=(not reference and cfg["kind"] == "inplace"))
+    s.set_material(mat.lame_lambda, mat.lame_mu)
+    s.set_body_force(dev(gx), dev(gy))
+    if reference or cfg["kind"] == "inplace":
+        s.set_time_blocking(1)
+    else:
+        s.set_time_blocking(cfg["tb"])
+        s.set_fused_kernel("tile" if cfg["kind"] == "tile" else "wavefront", cfg["seg"])
+    s.set_populations(dev(f0))
+    r = s.step_checked(cfg["steps"]) if cfg["checked"] else None
+    if not cfg["checked"]:
+        s.step(cfg["steps"])
+    f = host(s.populations())
+    ux, uy = (host(t) for t in s.displacement())
+    s.close()
+    return f, ux, uy, r
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_random_single_lattices(seed):
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    rng = np.random.default_rng(seed)
+    for case in range(100):
+        nx, ny = _side(rng), _side(rng)
+        kind = str(rng.choice(["tile", "tile", "wavefront", "inplace"]))
+        tb = {"tile": int(rng.integers(2, 9)), "wavefront": int(rng.integers(2, 5)), "inplace": 1}[kind]
+        steps = int(rng.integers(1, 40))
+        cfg = dict(case=case, nx=nx, ny=ny, prec=str(rng.choice(["fp64", "fp32", "fp16"])),
+                   kind=kind, tb=tb, seg=int(rng.choice([1, 3, 8, 17, 64, 256])), steps=steps,
+                   checked=bool(rng.random() < 0.3) and steps >= 2 and kind != "inplace")
+        say("case " + json.dumps(cfg))
+        mat = _material(rng)
+        f0 = rng.standard_normal((8, ny, nx)) * 1e-3
+        gx, gy = _load(rng, nx, ny)
+        fa, uxa, uya, ra = _run_single(lbm, cfg, mat, f0, gx, gy, reference=True)
+        fb, uxb, uyb, rb = _run_single(lbm, cfg, mat, f0, gx, gy, reference=False)
+        assert np.all(np.isfinite(fb))
+        assert np.array_equal(fa, fb) and np.array_equal(uxa, uxb) and np.array_equal(uya, uyb)
+        if cfg["checked"]:
+            assert abs(ra - rb) <= 1e-12 * max(abs(ra), abs(rb), 1e-300)
+        if cfg["prec"] == "fp64" and nx * ny <= 6000:
+            fo = O.run(f0, gx, gy, O.omega_vector(mat.lame_lambda, mat.lame_mu), steps)
+            assert np.sqrt(np.sum((fb - fo) ** 2) / np.sum(fo ** 2)) <= 1e-12
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_random_batches(seed):
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    rng = np.random.default_rng(1000 + seed)
+    compared = 0
+    for trial in range(20):
+        b = lbm.Batch(64, 256 << 20)
+        tbs = {p: int(rng.integers(1, 9)) for p in ("fp64", "fp32", "fp16")}
+        for p, k in tbs.items():
+            b.set_time_blocking(k, p)
+        lat = {}
+
+        def add():
+            nx = int(rng.choice([rng.integers(1, 9), rng.integers(9, 200)]))
+            ny = int(rng.choice([rng.integers(1, 9), rng.integers(9, 200)]))
+            prec = str(rng.choice(["fp64", "fp32", "fp16"]))
+            mat = _material(rng)
+            gx, gy = _load(rng, nx, ny)
+            slot = b.add(nx, ny, mat.lame_lambda, mat.lame_mu, dev(gx), dev(gy), prec)
+            assert slot is not None
+            lat[slot] = (nx, ny, prec, mat, gx, gy)
+
+        for _ in range(int(rng.integers(1, 12))):
+            add()
+        plan = []
+        for _ in range(int(rng.integers(1, 4))):
+            check = bool(rng.random() < 0.5)
+            chunk = int(rng.integers(2 if check else 1, 30))
+            plan.append((chunk, check))
+            b.step(chunk, check=check)
+            if rng.random() < 0.3 and lat:
+                victim = int(rng.choice(list(lat)))
+                b.remove(victim)
+                del lat[victim]
+            if rng.random() < 0.3:
+                add()
+        _, steps = b.residuals()
+        say(f"trial {trial} depths {tbs} plan {plan} lattices "
+            + str([(sl, v[0], v[1], v[2], int(steps[sl])) for sl, v in lat.items()]))
+        for slot, (nx, ny, prec, mat, gx, gy) in lat.items():
+            bx, by = (host(t) for t in b.displacement(slot))
+            s = lbm.Solver(nx, ny, prec)
+            s.set_material(mat.lame_lambda, mat.lame_mu)
+            s.set_body_force(dev(gx), dev(gy))
+            s.set_time_blocking(1)
+            s.step(int(steps[slot]))
+            sx, sy = (host(t) for t in s.displacement())
+            s.close()
+            if prec == "fp16":
+                sc = max(np.max(np.abs(sx)), np.max(np.abs(sy)), 1e-300)
+                assert np.max(np.abs(bx - sx)) <= 1e-9 * sc and np.max(np.abs(by - sy)) <= 1e-9 * sc
+            else:
+                assert np.array_equal(bx, sx) and np.array_equal(by, sy)
+            compared += 1
+        b.close()
+    say(f"lattices compared: {compared}")
+    assert compared > 0
