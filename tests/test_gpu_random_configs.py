@@ -8,6 +8,9 @@ displacement bit-identical, the checked residual equal to rounding of its
 reduction order (the partial sums follow the tile shape), and FP64 within 1e-12
 of the oracle on small lattices.
 
+Solves: solve_to_tol under random check intervals and depths, with and
+without the FP64 polish, gives the same stop step and state as single steps.
+
 Batches: random mixes of lattices with a depth per storage type, plain and
 checked chunks, removals and late additions; every lattice still resident
 equals a solo solver stepped as many steps (bit-identical; half storage to
@@ -150,3 +153,55 @@ def test_random_batches(seed):
         b.close()
     say(f"lattices compared: {compared}")
     assert compared > 0
+
+
+def test_random_solves():
+    """solve_to_tol under random check intervals, depths and kernels (FP32 and
+    FP16 with or without the FP64 polish, in place where there is no polish):
+    the same stop step, status, final storage type and residual (to 1e-9) as
+    single steps, and the same displacement (FP16 to 1e-9 of max |u|)."""
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    rng = np.random.default_rng(77)
+    for case in range(30):
+        nx, ny = int(rng.integers(3, 70)), int(rng.integers(3, 70))
+        prec = str(rng.choice(["fp64", "fp32", "fp16"]))
+        polish = prec != "fp64" and bool(rng.random() < 0.7)
+        kind = str(rng.choice(["tile", "wavefront"] if polish else ["tile", "tile", "wavefront", "inplace"]))
+        tb = {"tile": int(rng.integers(2, 9)), "wavefront": int(rng.integers(2, 5)), "inplace": 1}[kind]
+        K = int(rng.choice([1, 2, 3, 7, 50, 100, 333]))
+        tol = float(rng.choice([1e-6, 1e-8, 1e-10])) if (prec == "fp64" or polish) else 1e-5
+        mat = _material(rng)
+        kx, ky = int(rng.integers(1, 3)), int(rng.integers(0, 3))
+        x = (np.arange(nx) + 0.5) / nx
+        y = (np.arange(ny) + 0.5) / ny
+        gx = P.remove_mean(1e-4 * np.sin(2 * np.pi * (kx * x[None, :] + ky * y[:, None])))
+        gy = P.remove_mean(1e-4 * np.cos(2 * np.pi * (kx * x[None, :] - ky * y[:, None])))
+        seg = int(rng.choice([1, 8, 64]))
+        say("solve " + json.dumps(dict(case=case, nx=nx, ny=ny, prec=prec, polish=polish, kind=kind,
+                                        tb=tb, K=K, tol=tol)))
+        out = []
+        for reference in (True, False):
+            s = lbm.Solver(nx, ny, prec, with_polish=polish,
+                           inplace=(not reference and kind == "inplace"))
+            s.set_material(mat.lame_lambda, mat.lame_mu)
+            s.set_body_force(dev(gx), dev(gy))
+            if polish:
+                s.set_polish(1e-5)
+            if reference or kind == "inplace":
+                s.set_time_blocking(1)
+            else:
+                s.set_time_blocking(tb)
+                s.set_fused_kernel("tile" if kind == "tile" else "wavefront", seg)
+            n, r, status = s.solve_to_tol(tol, 20000, K)
+            ux, uy = (host(t) for t in s.displacement())
+            out.append((n, r, status, s.current_precision, ux, uy))
+            s.close()
+        (na, ra, sa, pa, uxa, uya), (nb, rb, sb, pb, uxb, uyb) = out
+        assert (na, sa, pa) == (nb, sb, pb)
+        assert abs(ra - rb) <= 1e-9 * max(abs(ra), 1e-300)
+        if prec == "fp16":
+            sc = max(np.max(np.abs(uxa)), np.max(np.abs(uya)), 1e-300)
+            assert np.max(np.abs(uxa - uxb)) <= 1e-9 * sc and np.max(np.abs(uya - uyb)) <= 1e-9 * sc
+        else:
+            assert np.array_equal(uxa, uxb) and np.array_equal(uya, uyb)
