@@ -138,6 +138,8 @@ def parse():
                     help="comma list of precisions: run only the 512-lattice batch leg "
                          "(for profiling)")
     ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the two serving legs (overloaded, then sustained)")
     ap.add_argument("--large-steps", type=int, default=10000)
     ap.add_argument("--large-warm", type=int, default=200)
     ap.add_argument("--large-tb", type=int, default=0,
@@ -375,11 +377,41 @@ def serving_run(rate: float = 2000.0, window: float = 1.0, budget: float = 20.0)
     arena = min(64 << 30, int(free * 0.5))
     srv = Server(arena, max_slots=4096, chunk=200, tol=1e-8, r_switch=1e-6)
     st = srv.run(reqs, window, budget)
+    # steps to tolerance grow like n^2 (the slowest mode relaxes at ~mu (2 pi/n)^2
+    # per step): c = median of steps / n^2 over the completed requests.  This errs
+    # high (small lattices retire at whole chunks), which offsets the lower
+    # throughput of a lightly loaded server (few resident lattices fill the GPU
+    # less, and the FP64 polish of a large lattice dominates)
+    fit = sorted(r.steps / float(r.n) ** 2 for r in srv.results)
+    st["steps_per_n2"] = fit[len(fit) // 2] if fit else None
     srv.close()
     st["offered_rate_hz"] = rate
     st["admission_window_s"] = window
     st["arena_bytes"] = arena
     return st
+
+
+def serving_legs():
+    """The overloaded serving run (Poisson 2000 req/s for 1 s), then a run at
+    0.8x the capacity estimated from work: site-updates per request ~ c n^4
+    (steps to tolerance grow like n^2), with n = 64 * 32^U, U ~ U[0, 1), so
+    E[n^4] = 64^4 (32^4 - 1) / (4 ln 32); capacity = GLUPS while busy / (c E[n^4]).
+    The completion rate of the overloaded run would overstate it, since that
+    run completes the small requests first."""
+    log("serving: Poisson 2000 req/s, sides 64..2048, tol 1e-8")
+    sv = serving_run()
+    e_n4 = 64.0 ** 4 * (32.0 ** 4 - 1.0) / (4.0 * math.log(32.0))
+    if sv.get("steps_per_n2") and sv["mlups_while_busy"] > 0:
+        capacity = sv["mlups_while_busy"] * 1e6 / (sv["steps_per_n2"] * e_n4)
+    else:
+        capacity = sv["solves_per_s"]
+    sustain = max(0.05, 0.8 * capacity)
+    log(f"serving at 0.8x the work-based capacity ({sustain:.2f} req/s)")
+    ss = serving_run(rate=sustain, window=15.0, budget=45.0)
+    ss["capacity_req_s"] = capacity
+    ss["capacity_model"] = ("GLUPS while busy / (c E[n^4]), c = median steps / n^2 of the "
+                            "completed requests of the overloaded run")
+    return sv, ss
 
 
 def cpu_model() -> str:
@@ -449,6 +481,10 @@ def main():
             calib_copy()
         print(json.dumps({"inplace_8192": inplace_run(steps=args.large_steps,
                                                       warm=args.large_warm)}), flush=True)
+        return
+    if args.serving_only:
+        sv, ss = serving_legs()
+        print(json.dumps({"serving": sv, "serving_sustained": ss}), flush=True)
         return
     if args.batch_only:
         if args.calib_copy:
@@ -570,11 +606,7 @@ def main():
             "fp32": dict({k: s32[k] for k in keys}, **err_vs_fp64(res32)),
             "fp32_polish_at_1e-5": dict({k: sp[k] for k in keys}, **err_vs_fp64(resp)),
             "fp64": {k: s64[k] for k in keys}}
-        log("serving: Poisson 2000 req/s, sides 64..2048, tol 1e-8")
-        out["serving"] = serving_run()
-        sustain = max(0.5, 0.8 * out["serving"]["solves_per_s"])
-        log(f"serving at 0.8x the measured completion rate ({sustain:.1f} req/s)")
-        out["serving_sustained"] = serving_run(rate=sustain, window=15.0, budget=30.0)
+        out["serving"], out["serving_sustained"] = serving_legs()
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
         log("CPU oracle baseline, one thread")
