@@ -138,6 +138,9 @@ def parse():
                     help="comma list of precisions: run only the 512-lattice batch leg "
                          "(for profiling)")
     ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--comparator-only", action="store_true",
+                    help="run only the FP64-storage comparator of the headline workload "
+                         "(for profiling)")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the two serving legs (overloaded, then sustained)")
     ap.add_argument("--large-steps", type=int, default=10000)
@@ -519,6 +522,17 @@ def main():
             s.close()
         return res, u
 
+    if args.comparator_only:
+        if args.calib_copy:
+            calib_copy()
+        r64, _ = measure("fp64")
+        print(json.dumps({"fp64": {"mlups": round(r64["mlups"], 1),
+                                   "avg_launch_us": round(r64["plain_kernel_avg_us"], 3),
+                                   "steps_per_launch": r64["steps_per_launch"],
+                                   "launch_config": r64["launch_config"],
+                                   "kernel": kernel_label(r64["launch_config"], "double",
+                                                          1024 * 1024)}}), flush=True)
+        return
     log("headline: 1024x1024 FP32")
     r32, u32 = measure("fp32")
     out = {
