@@ -35,6 +35,28 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+CONSUMER_SRC = os.path.join(ROOT, "tests", "capi_consumer.c")
+CONSUMER = os.path.join(ROOT, "tests", "capi_consumer")
+
+
+def build_c_consumer(verbose: bool = True) -> str:
+    """Compile the plain C consumer of the ABI used by the tests (gcc, linked
+    against liblbm.so and the HIP runtime, found through rpath)."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    tmp = CONSUMER + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-D__HIP_PLATFORM_AMD__",
+           "-I" + os.path.join(rocm, "include"), "-I" + os.path.join(ROOT, "include"),
+           CONSUMER_SRC, "-o", tmp, "-L" + PKG, "-llbm", "-L" + os.path.join(rocm, "lib"),
+           "-lamdhip64", "-Wl,-rpath,$ORIGIN/../paper_2208_14870_amd",
+           "-Wl,-rpath," + os.path.join(rocm, "lib")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, CONSUMER)
+    return CONSUMER
+
+
 if __name__ == "__main__":
     build()
+    build_c_consumer()
     sys.exit(0)

@@ -1,0 +1,45 @@
+"""The library used from plain C (tests/capi_consumer.c, built by build()): the
+32 x 32 manufactured problem solved to tolerance through include/lbm.h with
+device memory from the HIP runtime, no Python binding and no torch, against
+the oracle."""
+import json
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2208_14870_amd import problem as P
+from gpu_common import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+EXE = os.path.join(HERE, "capi_consumer")
+
+
+@pytest.mark.parametrize("precision,tol,bar", [(0, 1e-10, 1e-12), (1, 1e-6, 1e-5)])
+def test_c_consumer_solves_to_tolerance(tmp_path, precision, tol, bar):
+    need_gpu()
+    assert os.path.exists(EXE), "C consumer not built (run __graft_entry__.build())"
+    case = P.single_32()
+    mat = case.material
+    fin, fout = str(tmp_path / "force.bin"), str(tmp_path / "u.bin")
+    np.concatenate([case.gx.ravel(), case.gy.ravel()]).astype(np.float64).tofile(fin)
+    say(f"C consumer, precision {precision}, tol {tol}")
+    r = subprocess.run([EXE, "32", "32", repr(mat.lame_lambda), repr(mat.lame_mu), str(precision),
+                        repr(tol), "10000", "1", fin, fout],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    rec = json.loads(r.stdout.strip().splitlines()[-1])
+    u = np.fromfile(fout, dtype=np.float64).reshape(2, 32, 32)
+    om = O.omega_vector(mat.lame_lambda, mat.lame_mu)
+    f, n, res, st = O.solve_to_tol(O.zero_state(32, 32), case.gx, case.gy, om, tol, 10000, 1)
+    ox, oy = O.displacement(f, case.gx, case.gy)
+    err = np.sqrt(np.sum((u[0] - ox) ** 2 + (u[1] - oy) ** 2) / np.sum(ox ** 2 + oy ** 2))
+    say(f"  C: steps {rec['steps']} r {rec['residual']:.3e} | oracle steps {n} | rel diff {err:.2e}")
+    assert rec["status"] == 0 and st == 0
+    if precision == 0:
+        assert rec["steps"] == n
+    assert err <= bar
