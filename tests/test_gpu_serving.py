@@ -75,3 +75,33 @@ def test_serving_admission_respects_footprint():
     assert stats["completed"] == len(reqs)
     # arrival order is kept except for backfilling
     assert all(x.latency >= 0 for x in srv.results)
+
+
+def test_serving_retires_a_diverging_request():
+    """A request whose material is linearly unstable (Sec. 7.3.5: nu = -0.4,
+    E~ = 0.082, Gaussian-hill load) grows until its residual is no longer
+    finite; the server then retires it as failed and frees its slot, while the
+    requests beside it finish exactly as they do alone."""
+    say("serving with one diverging request")
+    reqs = [P.Request(0, 0.0, 64, 0.3, 77), P.Request(1, 0.0, 48, 0.0, 0),
+            P.Request(2, 0.0, 72, 0.2, 78)]
+    cases = {0: reqs[0].case(), 2: reqs[2].case(),
+             1: P.gaussian_hill_case(48, P.Material.from_young_poisson(0.082, -0.4))}
+    from paper_2208_14870_amd.serving import Server
+    need_gpu()
+    srv = Server(1 << 30, max_slots=16, chunk=1000, tol=1e-8, keep_results=True)
+    stats = srv.run(reqs, admit_window_s=1.0, wall_budget_s=90.0, cases=cases)
+    active, _, _ = srv.batch.info()
+    srv.close()
+    say(f"  {stats['completed']} completed, failed {srv.failed}, backlog {stats['backlog']}")
+    assert srv.failed == [1] and stats["completed"] == 2 and stats["backlog"] == 0
+    assert active == 0
+    for rid in (0, 2):
+        alone = Server(1 << 30, max_slots=16, chunk=1000, tol=1e-8, keep_results=True)
+        alone.run([reqs[rid]], 1.0, 60.0, cases=cases)
+        alone.close()
+        a = alone.results[0]
+        m = [r for r in srv.results if r.rid == rid][0]
+        assert a.steps == m.steps and a.residual == m.residual
+        np.testing.assert_array_equal(a.ux, m.ux)
+        np.testing.assert_array_equal(a.uy, m.uy)
