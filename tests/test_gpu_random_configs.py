@@ -11,6 +11,9 @@ of the oracle on small lattices.
 Solves: solve_to_tol under random check intervals and depths, with and
 without the FP64 polish, gives the same stop step and state as single steps.
 
+Outputs: populations, displacement, stress and error norms after random step
+counts (two buffers or in place) against the oracle and numpy.
+
 Batches: random mixes of lattices with a depth per storage type, plain and
 checked chunks, removals and late additions; every lattice still resident
 equals a solo solver stepped as many steps (bit-identical; half storage to
@@ -205,3 +208,56 @@ def test_random_solves():
             assert np.max(np.abs(uxa - uxb)) <= 1e-9 * sc and np.max(np.abs(uya - uyb)) <= 1e-9 * sc
         else:
             assert np.array_equal(uxa, uxb) and np.array_equal(uya, uyb)
+
+
+def test_random_outputs_against_the_oracle():
+    """Populations, displacement and stress after random step counts (two
+    buffers at 1..8 steps per launch, or in place at odd and even counts) from
+    random states, against the oracle: FP64 1e-12, FP32 2e-6 (populations) /
+    2e-5, FP16 3e-3 / 3e-2 relative; error norms against numpy to 1e-12."""
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    rng = np.random.default_rng(7)
+    for case in range(40):
+        nx, ny = int(rng.integers(1, 90)), int(rng.integers(1, 90))
+        prec = str(rng.choice(["fp64", "fp32", "fp16"]))
+        inplace = bool(rng.random() < 0.4)
+        tb = 1 if inplace else int(rng.integers(1, 9))
+        steps = int(rng.integers(0, 12))
+        say("outputs " + json.dumps(dict(case=case, nx=nx, ny=ny, prec=prec, inplace=inplace,
+                                          tb=tb, steps=steps)))
+        mat = _material(rng)
+        f0 = rng.standard_normal((8, ny, nx)) * 1e-3
+        gx, gy = _load(rng, nx, ny)
+        s = lbm.Solver(nx, ny, prec, inplace=inplace)
+        s.set_material(mat.lame_lambda, mat.lame_mu)
+        s.set_body_force(dev(gx), dev(gy))
+        s.set_time_blocking(tb)
+        s.set_populations(dev(f0))
+        if steps:
+            s.step(steps)
+        f = host(s.populations())
+        ux, uy = (host(t) for t in s.displacement())
+        sig = np.stack([host(t) for t in s.stress()])
+        rx, ry = rng.standard_normal((ny, nx)), rng.standard_normal((ny, nx))
+        norms = s.error_norms(dev(rx), dev(ry))
+        s.close()
+        om = O.omega_vector(mat.lame_lambda, mat.lame_mu)
+        fo = O.run(f0, gx, gy, om, steps) if steps else f0
+        oux, ouy = O.displacement(fo, gx, gy)
+        osig = np.stack(O.stress(fo, om))
+
+        def rel(a, b):
+            return float(np.sqrt(np.sum((a - b) ** 2) / max(np.sum(b ** 2), 1e-300)))
+
+        tol = {"fp64": 1e-12, "fp32": 2e-6, "fp16": 3e-3}[prec]
+        assert rel(f, fo) <= tol
+        assert rel(np.stack([ux, uy]), np.stack([oux, ouy])) <= 10 * tol
+        assert rel(sig, osig) <= 10 * tol
+        ex, ey = ux - rx, uy - ry
+        want = (float(np.sum(ex ** 2 + ey ** 2)), float(np.sum(rx ** 2 + ry ** 2)),
+                float(max(np.max(np.abs(ex)), np.max(np.abs(ey)))),
+                float(max(np.max(np.abs(rx)), np.max(np.abs(ry)))))
+        got = (norms["sum_e2"], norms["sum_ref2"], norms["max_e"], norms["max_ref"])
+        for g, w in zip(got, want):
+            assert abs(g - w) <= 1e-12 * w
