@@ -199,7 +199,10 @@ int lbm_error_norms(lbm_solver *s, const double *ux_ref, const double *uy_ref, d
  * state for the polish switch).  With half storage, set first picks the
  * power-of-two scale so that the state's max |f| maps to 2^12 (never finer
  * than the force's steady-state bound), so that no state overflows the half
- * range; LBM_E_ARG for a non-finite state. */
+ * range; LBM_E_ARG for a non-finite state.  State, force and material may be
+ * set in any order before the first step: a force or material set later that
+ * needs a coarser scale rescales the stored state by that power of two.
+ * lbm_reset returns to the scale of a freshly created solver. */
 int lbm_get_populations(lbm_solver *s, double *f);
 int lbm_set_populations(lbm_solver *s, const double *f);
 

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -54,6 +55,9 @@ struct lbm_solver {
     double r_switch = 0.0;
     int blocks_per_cu = 0;  // 0: one workgroup per tile; k: persistent k per CU
     bool fused_auto = true;  // fused kernel not chosen by the caller: follows the default
+    // half storage: a state set by lbm_set_populations and the exponent it needs
+    bool user_state = false;
+    int e_user = INT_MIN;  // INT_MIN: the state sets no bound (all zero)
     std::string err;
     // captured chunks keyed by (plain steps, writeU/check kind, start parity,
     // precision, rows per thread, general path, grid)
@@ -390,6 +394,11 @@ int lbm_destroy(lbm_solver* s) {
     return LBM_OK;
 }
 
+namespace {
+int half_exponent(const lbm_solver* s);
+int set_half_exponent(lbm_solver* s, int e_new);
+}  // namespace
+
 int lbm_reset(lbm_solver* s) {
     if (!s) return LBM_E_ARG;
     Lattice& L = s->L;
@@ -402,6 +411,9 @@ int lbm_reset(lbm_solver* s) {
     hipError_t e = zero_bytes(L.mem.buf[0], 8 * L.plane * elem_bytes(L.prec0), s->stream);
     if (e == hipSuccess) e = zero_bytes(L.mem.u, 2 * L.plane * 8, s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "lbm_reset");
+    // f = 0 again: half storage takes the exponent a fresh solver would
+    s->user_state = false;
+    if (L.prec0 == LBM_FP16) L.e_scale = half_exponent(s);
     return s->sync_desc();
 }
 
@@ -413,8 +425,7 @@ int lbm_set_material(lbm_solver* s, double lame_lambda, double lame_mu) {
     s->L.lam = lame_lambda;
     s->L.mu = lame_mu;
     s->L.has_material = true;
-    if (s->L.prec0 == LBM_FP16 && s->L.has_force && s->steps == 0)
-        s->L.e_scale = initial_half_exponent(s->L, s->L.gmax);
+    if (s->L.prec0 == LBM_FP16 && s->steps == 0) return set_half_exponent(s, half_exponent(s));
     return s->sync_desc();
 }
 
@@ -455,8 +466,8 @@ int lbm_set_body_force(lbm_solver* s, const double* gx, const double* gy) {
     L.has_force = true;
     L.gmax = gmax;
     L.rebase_force(s->steps, sx, sy);
-    if (L.prec0 == LBM_FP16 && s->steps == 0) L.e_scale = initial_half_exponent(L, gmax);
-    int rc = s->sync_desc();
+    int rc = (L.prec0 == LBM_FP16 && s->steps == 0) ? set_half_exponent(s, half_exponent(s))
+                                                      : s->sync_desc();
     if (rc != LBM_OK) return rc;
     const double N = (double)L.N;
     const double rms = std::sqrt(s2 / (2.0 * N));
@@ -596,6 +607,37 @@ int promote_solver(lbm_solver* s) {
     e = neutral_reset(LBM_FP64, L.desc(), s->sel(), target, s->d_red, s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "promote: neutral modes");
     return LBM_OK;
+}
+
+// Half storage: the power-of-two exponent for the current state.  From f = 0
+// (creation, reset) the force's steady-state bound alone (a zero force sets
+// no bound); after lbm_set_populations the larger of that and the exponent
+// that maps the given state's max |f| to 2^12.
+int half_exponent(const lbm_solver* s) {
+    const Lattice& L = s->L;
+    const int ef = (L.has_force && L.has_material && L.gmax > 0.0)
+                       ? initial_half_exponent(L, L.gmax) : INT_MIN;
+    const int e = s->user_state ? std::max(ef, s->e_user) : ef;
+    return (e == INT_MIN) ? 0 : std::max(-100, std::min(100, e));
+}
+
+// Change the half-storage exponent before any step; a state set by the caller
+// is rescaled by the power of two (exact for normal halves), so that it keeps
+// its values.
+int set_half_exponent(lbm_solver* s, int e_new) {
+    Lattice& L = s->L;
+    e_new = std::max(-100, std::min(100, e_new));
+    if (L.prec != LBM_FP16 || e_new == L.e_scale) return LBM_OK;
+    if (s->user_state) {
+        __half* p = reinterpret_cast<__half*>(L.mem.buf[s->sel()]);
+        const long long n = 8 * L.plane;
+        hipLaunchKernelGGL((k_recast<__half, __half>), dim3(blocks_for(n)), dim3(kBlock), 0,
+                           s->stream, p, p, n, std::ldexp(1.0, L.e_scale - e_new));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return s->hip_fail(e, "half rescale");
+    }
+    L.e_scale = e_new;
+    return s->sync_desc();
 }
 
 // Rescale half storage so that max |stored| stays within [2^10, 2^14].
@@ -822,10 +864,10 @@ int lbm_set_populations(lbm_solver* s, const double* f) {
         if (e != hipSuccess) return s->hip_fail(e, "set_populations: max |f|");
         const double fmax = s->h_result[3];
         if (!std::isfinite(fmax)) return s->fail(LBM_E_ARG, "set_populations: non-finite input");
-        int es = (L.has_force && L.has_material) ? initial_half_exponent(L, L.gmax) : -100;
-        if (fmax > 0.0) es = std::max(es, (int)std::ceil(std::log2(fmax / 4096.0)));
-        if (es == -100 && !(fmax > 0.0)) es = L.e_scale;  // nothing to fit
-        L.e_scale = std::max(-100, std::min(100, es));
+        // the old state is overwritten below: set the exponent without rescaling it
+        s->user_state = true;
+        s->e_user = (fmax > 0.0) ? (int)std::ceil(std::log2(fmax / 4096.0)) : INT_MIN;
+        L.e_scale = half_exponent(s);
         const int rc = s->sync_desc();
         if (rc != LBM_OK) return rc;
     }

@@ -562,6 +562,82 @@ def test_fp16_set_populations_fits_the_state(n, scale):
     assert np.all(np.isfinite(got)) and err <= 3e-3
 
 
+@pytest.mark.parametrize("order", ["pops_force_material", "material_pops_force", "force_material_pops"])
+def test_fp16_set_calls_in_any_order(order):
+    """Half storage: the state, force and material may be set in any order
+    before the first step.  When a later force or material raises the scale's
+    exponent, the stored state is rescaled by that power of two instead of
+    being read at the wrong scale; results agree with the usual order to
+    subnormal-half rounding and with the FP64 oracle to half rounding."""
+    say(f"fp16 set order {order}")
+    n = 24
+    f0, gx, gy = _rand_state(n, n, 21, 1e-4)
+    gx, gy = gx * 100.0, gy * 100.0  # a force whose bound dominates the state's
+    mat = P.Material.from_shear_poisson(1.0, 0.3)
+    out = []
+    for o in (order, "force_material_pops"):
+        s = _solver(n, n, "fp16")
+        for step in o.split("_"):
+            if step == "pops":
+                s.set_populations(dev(f0))
+            elif step == "force":
+                s.set_body_force(dev(gx), dev(gy))
+            else:
+                s.set_material(mat.lame_lambda, mat.lame_mu)
+        s.step(20)
+        out.append(host(s.populations()))
+        s.close()
+    want = O.run(f0, gx, gy, omega(mat), 20)
+    scale = np.max(np.abs(want))
+    say(f"  max diff between orders {np.max(np.abs(out[0] - out[1])) / scale:.2e}, "
+        f"rel err vs oracle {rel_l2(out[0], want):.2e}")
+    assert np.max(np.abs(out[0] - out[1])) <= 1e-9 * scale
+    assert rel_l2(out[0], want) <= 3e-3
+
+
+def test_fp16_small_state_without_force_keeps_its_digits():
+    """A zero force sets no bound on the half scale: a small state keeps its
+    own scale (no subnormal halves)."""
+    say("fp16 small state, zero force")
+    n = 16
+    f0, _, _ = _rand_state(n, n, 22, 1e-6)
+    z = np.zeros((n, n))
+    mat = P.Material.from_shear_poisson(1.0, 0.3)
+    s = _solver(n, n, "fp16")
+    s.set_material(mat.lame_lambda, mat.lame_mu)
+    s.set_body_force(dev(z), dev(z))
+    s.set_populations(dev(f0))
+    back = host(s.populations())
+    s.step(10)
+    got = host(s.populations())
+    s.close()
+    assert rel_l2(back, f0) <= 1e-3
+    assert rel_l2(got, O.run(f0, z, z, omega(mat), 10)) <= 3e-3
+
+
+def test_fp16_reset_is_a_fresh_solver():
+    """After checked runs that rescale half storage, reset gives the exponent a
+    fresh solver starts with: the next run is bit-identical to a fresh one."""
+    say("fp16 reset")
+    c = P.single_1024(0.3, 1, 1, n=64)
+    runs = []
+    s = _solver(64, 64, "fp16")
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    s.solve_to_tol(1e-4, 3000, 50)
+    s.reset()
+    s.step(200)
+    runs.append(host(s.populations()))
+    s.close()
+    s = _solver(64, 64, "fp16")
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    s.step(200)
+    runs.append(host(s.populations()))
+    s.close()
+    assert np.array_equal(runs[0], runs[1])
+
+
 def test_fp16_zero_state_keeps_the_force_scale():
     """Setting an all-zero state leaves the scale the force chose: the run is
     bit-identical to a fresh solver's."""
