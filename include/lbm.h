@@ -201,8 +201,10 @@ int lbm_error_norms(lbm_solver *s, const double *ux_ref, const double *uy_ref, d
  * than the force's steady-state bound), so that no state overflows the half
  * range; LBM_E_ARG for a non-finite state.  State, force and material may be
  * set in any order before the first step: a force or material set later that
- * needs a coarser scale rescales the stored state by that power of two.
- * lbm_reset returns to the scale of a freshly created solver. */
+ * needs a coarser scale rescales the stored state by that power of two; after
+ * the first step a new force or material only coarsens the scale (rescaling
+ * the live state), so plain steps do not overflow before the next checked
+ * rescale.  lbm_reset returns to the scale of a freshly created solver. */
 int lbm_get_populations(lbm_solver *s, double *f);
 int lbm_set_populations(lbm_solver *s, const double *f);
 

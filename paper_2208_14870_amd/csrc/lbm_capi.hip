@@ -397,6 +397,7 @@ int lbm_destroy(lbm_solver* s) {
 namespace {
 int half_exponent(const lbm_solver* s);
 int set_half_exponent(lbm_solver* s, int e_new);
+int refit_half(lbm_solver* s);
 }  // namespace
 
 int lbm_reset(lbm_solver* s) {
@@ -425,8 +426,7 @@ int lbm_set_material(lbm_solver* s, double lame_lambda, double lame_mu) {
     s->L.lam = lame_lambda;
     s->L.mu = lame_mu;
     s->L.has_material = true;
-    if (s->L.prec0 == LBM_FP16 && s->steps == 0) return set_half_exponent(s, half_exponent(s));
-    return s->sync_desc();
+    return refit_half(s);
 }
 
 int lbm_set_rates(lbm_solver* s, double theta, double w12, double w21, double w22) {
@@ -466,8 +466,7 @@ int lbm_set_body_force(lbm_solver* s, const double* gx, const double* gy) {
     L.has_force = true;
     L.gmax = gmax;
     L.rebase_force(s->steps, sx, sy);
-    int rc = (L.prec0 == LBM_FP16 && s->steps == 0) ? set_half_exponent(s, half_exponent(s))
-                                                      : s->sync_desc();
+    int rc = refit_half(s);
     if (rc != LBM_OK) return rc;
     const double N = (double)L.N;
     const double rms = std::sqrt(s2 / (2.0 * N));
@@ -621,14 +620,14 @@ int half_exponent(const lbm_solver* s) {
     return (e == INT_MIN) ? 0 : std::max(-100, std::min(100, e));
 }
 
-// Change the half-storage exponent before any step; a state set by the caller
-// is rescaled by the power of two (exact for normal halves), so that it keeps
-// its values.
+// Change the half-storage exponent.  A live state (set by the caller, or any
+// state after the first step) is rescaled by the power of two (exact for
+// normal halves), so that it keeps its values.
 int set_half_exponent(lbm_solver* s, int e_new) {
     Lattice& L = s->L;
     e_new = std::max(-100, std::min(100, e_new));
     if (L.prec != LBM_FP16 || e_new == L.e_scale) return LBM_OK;
-    if (s->user_state) {
+    if (s->user_state || s->steps > 0) {
         __half* p = reinterpret_cast<__half*>(L.mem.buf[s->sel()]);
         const long long n = 8 * L.plane;
         hipLaunchKernelGGL((k_recast<__half, __half>), dim3(blocks_for(n)), dim3(kBlock), 0,
@@ -638,6 +637,17 @@ int set_half_exponent(lbm_solver* s, int e_new) {
     }
     L.e_scale = e_new;
     return s->sync_desc();
+}
+
+// After a new force or material: before the first step the exponent follows
+// half_exponent; later the scale only coarsens (a larger steady-state bound
+// would otherwise overflow the half range before the next checked rescale).
+int refit_half(lbm_solver* s) {
+    const Lattice& L = s->L;
+    if (L.prec != LBM_FP16) return s->sync_desc();
+    const int e = half_exponent(s);
+    if (s->steps == 0) return set_half_exponent(s, e);
+    return e > L.e_scale ? set_half_exponent(s, e) : s->sync_desc();
 }
 
 // Rescale half storage so that max |stored| stays within [2^10, 2^14].

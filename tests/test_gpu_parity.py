@@ -638,6 +638,28 @@ def test_fp16_reset_is_a_fresh_solver():
     assert np.array_equal(runs[0], runs[1])
 
 
+def test_fp16_force_raised_mid_run():
+    """Half storage: a force 100 times larger set after 100 steps coarsens the
+    scale (the live state is rescaled by the power of two), so 400 plain steps
+    without a check stay finite and within half rounding of the oracle."""
+    say("fp16 force raised mid-run")
+    c = P.single_1024(0.3, 1, 1, n=32)
+    om = omega(c.material)
+    s = _solver(32, 32, "fp16")
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    s.set_body_force(dev(c.gx), dev(c.gy))
+    s.step(100)
+    s.set_body_force(dev(100.0 * c.gx), dev(100.0 * c.gy))
+    s.step(400)
+    got = host(s.populations())
+    s.close()
+    f = O.run(O.zero_state(32, 32), c.gx, c.gy, om, 100)
+    want = O.run(f, 100.0 * c.gx, 100.0 * c.gy, om, 400)
+    err = rel_l2(got, want)
+    say(f"  rel err vs oracle {err:.2e}")
+    assert np.all(np.isfinite(got)) and err <= 3e-3
+
+
 def test_fp16_zero_state_keeps_the_force_scale():
     """Setting an all-zero state leaves the scale the force chose: the run is
     bit-identical to a fresh solver's."""
