@@ -99,3 +99,104 @@ def stable_young_range(nu: float, young: Iterable[float]) -> list:
         if is_stable(lam, mu):
             out.append(E)
     return out
+
+
+# ---------------------------------------------------------------------------
+# accuracy and convergence of one Fourier mode (planning advisor)
+# ---------------------------------------------------------------------------
+
+def forcing_operator(theta: float = 1.0 / 3.0, w12: float = 1.0, w21: float = 1.0) -> np.ndarray:
+    """Populations one collision adds for a force g (8 x 2): the first moments gain
+    g (half before the equilibria, half after: Eqs. coll10, coll10post) and the
+    third-order moments m12, m21 relax towards theta times the bared first
+    moments, so they gain w12 theta g/2 and w21 theta g/2."""
+    G = np.zeros((8, 2))
+    G[0, 0] = G[1, 1] = 1.0
+    G[5, 0] = w12 * theta / 2.0
+    G[6, 1] = w21 * theta / 2.0
+    return np.linalg.solve(moment_matrix(), G)
+
+
+def steady_response(lame_lambda: float, lame_mu: float, kx: float, ky: float,
+                    theta: float = 1.0 / 3.0, w12: float = 1.0, w21: float = 1.0,
+                    w22: float = 1.0) -> np.ndarray:
+    """The scheme's exact steady state for one load mode g = g_hat exp(i k.x),
+    k != 0, as the 2 x 2 map g_hat -> u_hat: the populations after the
+    collision-and-stream step satisfy f = D(A f + B g) with D = diag(exp(-i k.c)),
+    so f = (I - D A)^-1 D B g, and u = (M f)[10, 01] + g/2 (the bared first
+    moments)."""
+    A = collision_operator(lame_lambda, lame_mu, theta=theta, w12=w12, w21=w21, w22=w22)
+    D = np.diag(np.exp(-1j * (C[:, 0] * kx + C[:, 1] * ky)))
+    B = forcing_operator(theta, w12, w21)
+    F = np.linalg.solve(np.eye(8) - D @ A, D @ B)
+    return (moment_matrix() @ F)[:2] + 0.5 * np.eye(2)
+
+
+def continuum_response(lame_lambda: float, lame_mu: float, kx: float, ky: float) -> np.ndarray:
+    """Steady state of mu lap u + K grad div u + g = 0 (lattice units) for one
+    mode: (mu |k|^2 I + K k k^T)^-1."""
+    K = lame_lambda + lame_mu
+    k = np.array([kx, ky])
+    return np.linalg.inv(lame_mu * (k @ k) * np.eye(2) + K * np.outer(k, k))
+
+
+def mode_error(lame_lambda: float, lame_mu: float, kx: float, ky: float, **kw) -> float:
+    """Relative discretisation error of the steady state for one load mode: the
+    spectral norm of (discrete - continuum response) over that of the continuum
+    response.  Second order: it falls by 4 when k halves."""
+    Rd = steady_response(lame_lambda, lame_mu, kx, ky, **kw)
+    Rc = continuum_response(lame_lambda, lame_mu, kx, ky)
+    return float(np.linalg.norm(Rd - Rc, 2) / np.linalg.norm(Rc, 2))
+
+
+def slowest_decay(lame_lambda: float, lame_mu: float, nx: int, ny: int,
+                  **kw) -> Tuple[float, Tuple[float, float]]:
+    """Largest |eigenvalue| of L(k) over the smooth wavevectors of an nx x ny
+    lattice (both components, folded into [-pi, pi), at most pi/2 in size), and
+    its k: the slowest decay of a smooth load's response.  k = 0, the mean, never
+    decays and is left out.  (Wavevectors next to the staggered ones with a
+    component pi, whose eigenvalue -1 never decays either, mirror the smooth
+    ones' slowest |eigenvalue|; a smooth load from f = 0 does not excite them.)"""
+    A = collision_operator(lame_lambda, lame_mu, **kw)
+    best, arg = 0.0, (0.0, 0.0)
+    for kx, ky in lattice_grid(nx, ny):
+        fx = kx - 2 * math.pi if kx >= math.pi else kx
+        fy = ky - 2 * math.pi if ky >= math.pi else ky
+        if (fx == 0.0 and fy == 0.0) or abs(fx) > math.pi / 2 or abs(fy) > math.pi / 2:
+            continue
+        r = float(np.max(np.abs(np.linalg.eigvals(amplification(A, fx, fy)))))
+        if r > best:
+            best, arg = r, (fx, fy)
+    return best, arg
+
+
+def predicted_steps(rho: float, tol: float) -> int:
+    """Steps until the residual ||u(n) - u(n-1)|| / ||u(n)|| of a mode decaying as
+    rho^n from f = 0 falls to tol: u(n) = u(1 - rho^n), so the residual is about
+    (1 - rho) rho^(n-1) (an estimate: the load's other modes decay faster)."""
+    if not (0.0 < rho < 1.0):
+        return 0 if rho <= 0.0 else -1
+    return int(math.ceil(1.0 + math.log(tol / (1.0 - rho)) / math.log(rho)))
+
+
+def advise(nu: float, n: int, young: Optional[Iterable[float]] = None, tol: float = 1e-8,
+           max_error: Optional[float] = None) -> Tuple[list, Optional[dict]]:
+    """Choice of the dimensionless Young's modulus (Eq. scalingE: the ratio of time
+    step to damping for a given physical E) for an n x n lattice at Poisson ratio
+    nu.  For each candidate: stability on the paper's grid, the steps to reach tol
+    for the slowest decaying lattice mode, and the steady-state error of the lowest
+    diagonal load mode k = 2 pi (1, 1)/n.  Returns (rows, the stable row with the
+    fewest steps whose error is at most max_error, or None)."""
+    young = np.geomspace(0.01, 10.0, 25) if young is None else young
+    rows = []
+    for E in young:
+        lam, mu = E * nu / (1 - nu * nu), E / (2 * (1 + nu))
+        stable = is_stable(lam, mu)
+        rho, _ = slowest_decay(lam, mu, n, n)
+        k = 2 * math.pi / n
+        rows.append({"young": float(E), "lame_lambda": lam, "lame_mu": mu, "stable": stable,
+                     "rho": rho, "steps": predicted_steps(rho, tol),
+                     "error_k11": mode_error(lam, mu, k, k)})
+    ok = [r for r in rows if r["stable"] and r["steps"] > 0 and
+          (max_error is None or r["error_k11"] <= max_error)]
+    return rows, (min(ok, key=lambda r: r["steps"]) if ok else None)
