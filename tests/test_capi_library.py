@@ -73,3 +73,16 @@ def test_binding_has_no_cpu_fallback():
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError):
         lbm.Solver(8, 8)
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """A missing liblbm.so is an error naming the build step, never a fallback."""
+    from paper_2208_14870_amd import lbm
+    monkeypatch.setattr(lbm, "_lib", None)
+    monkeypatch.setattr(lbm, "LIB_PATH", str(tmp_path / "liblbm.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        lbm.load()
+    with pytest.raises(RuntimeError, match="not built"):
+        lbm.Solver(8, 8)
+    with pytest.raises(RuntimeError, match="not built"):
+        lbm.Batch(4, 1 << 20)
