@@ -221,9 +221,11 @@ int lbm_set_tile(lbm_solver *s, int bx_log2, int rows_per_thread, int blocks_per
  * and the general-rates variant run one step per launch.  Overrides the tile
  * shape of lbm_set_tile while active.  Default by storage type and size: FP32
  * and FP16 8 above 2^17 sites, else 4; FP64 5, or 4 above 2^22 sites where the
- * wavefront is the default (also after a polish switch).  The fused kernel follows the
- * default of lbm_set_fused_kernel for k until the caller picks one; k > 4
- * always runs the LDS tile kernel (the wavefront runs 2..4 steps).  Errors:
+ * wavefront is the default (also after a polish switch); 4 (the wavefront) for
+ * lattices beyond the tile kernel's plane limit (see lbm_set_fused_kernel).  The
+ * fused kernel follows the default of lbm_set_fused_kernel for k until the
+ * caller picks one; k > 4 always runs the LDS tile kernel (the wavefront runs
+ * 2..4 steps), or single steps beyond its plane limit.  Errors:
  * LBM_E_ARG (k outside 1..8), LBM_E_STATE (k != 1 in place). */
 int lbm_set_time_blocking(lbm_solver *s, int steps_per_launch);
 
@@ -248,7 +250,11 @@ enum lbm_fused_kernel {
  * called, and again after a polish switch): for k <= 4 the wavefront on FP64
  * lattices of more than 2^22 sites and on even-width FP32 lattices of at least
  * 2^25 sites, with the tallest segment of 256, 128, 64 or 32 rows that still
- * gives 18 waves per compute unit; the tile kernel otherwise.  Errors:
+ * gives 18 waves per compute unit; the tile kernel otherwise.  The tile kernel
+ * addresses a plane with 32-bit byte offsets, so a lattice whose planes hold
+ * 2^32 bytes or more in the arithmetic type (above 2^30 FP32/FP16 or 2^29 FP64
+ * sites) defaults to the wavefront at four steps per launch whatever its
+ * width; at more than four steps it runs single steps.  Errors:
  * LBM_E_ARG, LBM_E_STATE (the wavefront with steps_per_launch > 4). */
 int lbm_set_fused_kernel(lbm_solver *s, int kind, int segment_rows);
 

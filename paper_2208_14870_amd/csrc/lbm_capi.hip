@@ -342,8 +342,11 @@ static int create_solver(int nx, int ny, int precision, int with_polish, bool in
     L.inplace = inplace;
     default_tile(precision, nx, ny, L.bx_log2, L.vy);
     L.tb = inplace ? 1 : default_time_blocking(precision, (long long)nx * ny);
+    // planes beyond the tile kernel's 32-bit offsets: the wavefront at four steps
+    if (!L.tile_fits()) L.tb = std::min(L.tb, 4);
     L.th = fused_th(precision, L.tb, (long long)nx * ny);
-    L.wave_hs = inplace ? 0 : default_fused_wave_rows(precision, L.tb, nx, ny, s->cus);
+    L.wave_hs = inplace ? 0 : default_fused_wave_rows(precision, L.tb, nx, ny, s->cus,
+                                                      !L.tile_fits());
     char* base = reinterpret_cast<char*>(workspace);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -500,7 +503,8 @@ int lbm_set_time_blocking(lbm_solver* s, int steps_per_launch) {
     L.tb = steps_per_launch;
     L.th = fused_th(L.prec, steps_per_launch, L.N);
     if (s->fused_auto)
-        L.wave_hs = default_fused_wave_rows(L.prec, steps_per_launch, L.nx, L.ny, s->cus);
+        L.wave_hs = default_fused_wave_rows(L.prec, steps_per_launch, L.nx, L.ny, s->cus,
+                                            !L.tile_fits());
     else if (steps_per_launch > 4)
         L.wave_hs = 0;  // the wavefront runs 2..4 steps
     return s->sync_desc();
@@ -592,8 +596,9 @@ int promote_solver(lbm_solver* s) {
     s->phase = 0;
     default_tile(LBM_FP64, L.nx, L.ny, L.bx_log2, L.vy);
     L.tb = default_time_blocking(LBM_FP64, L.N);
+    if (!L.tile_fits()) L.tb = std::min(L.tb, 4);
     L.th = fused_th(LBM_FP64, L.tb, L.N);
-    L.wave_hs = default_fused_wave_rows(LBM_FP64, L.tb, L.nx, L.ny, s->cus);
+    L.wave_hs = default_fused_wave_rows(LBM_FP64, L.tb, L.nx, L.ny, s->cus, !L.tile_fits());
     s->fused_auto = true;
     // sync_desc folds phase into cur: phase is 0 so cur stays 0
     int rc = s->sync_desc();

@@ -240,9 +240,11 @@ inline hipError_t launch_wave(int prec, int ns, int nx, int ny, int hs, const Sl
 // segment height is the tallest of 256, 128, 64, 32 rows that still gives
 // 18 waves per compute unit (fewer leave SIMDs idle; shorter segments
 // recompute more halo rows).  Returns the segment height, 0 for the tile kernel.
-inline int default_wave_rows(int prec, int nx, int ny, int cus) {
+// `beyond_tile`: the lattice's planes exceed what the tile kernel addresses
+// (2^32 bytes in the arithmetic type), so the wavefront is the only fused kernel.
+inline int default_wave_rows(int prec, int nx, int ny, int cus, bool beyond_tile = false) {
     const long long n = (long long)nx * ny;
-    const bool use = (prec == LBM_FP64 && n > (1LL << 22)) ||
+    const bool use = beyond_tile || (prec == LBM_FP64 && n > (1LL << 22)) ||
                      (prec == LBM_FP32 && n >= (1LL << 25) && nx % 2 == 0);
     if (!use) return 0;
     const long long strips = (nx + wave_width_of(4, wave_cols_per_lane(prec, nx)) - 1) /
@@ -269,8 +271,9 @@ inline int default_time_blocking(int prec, long long sites, bool tiles_only = fa
 
 // Default fused kernel for `ns` steps per launch: the register wavefront runs
 // two to four steps, so deeper blocking uses the tile kernel.
-inline int default_fused_wave_rows(int prec, int ns, int nx, int ny, int cus) {
-    return ns <= 4 ? default_wave_rows(prec, nx, ny, cus) : 0;
+inline int default_fused_wave_rows(int prec, int ns, int nx, int ny, int cus,
+                                   bool beyond_tile = false) {
+    return ns <= 4 ? default_wave_rows(prec, nx, ny, cus, beyond_tile) : 0;
 }
 
 inline hipError_t launch_step(int prec, int mode, bool general, int vy, int layout, unsigned grid,

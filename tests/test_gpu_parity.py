@@ -303,6 +303,63 @@ def test_full_size_8192_sampled(prec, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("kind,nx", [("default", 36000), ("default", 35999), ("single", 36000)])
+def test_beyond_the_tile_kernel_limit(kind, nx):
+    """About 1.08e9 FP32 sites, above the 2^30 whose planes the tile kernel
+    addresses with 32-bit offsets: by default such lattices run the register
+    wavefront at four steps (two columns per lane on even widths, one on odd),
+    which like single steps addresses the planes with 64-bit offsets.
+    Displacement after 6 steps from f = 0 at sampled sites (corners and edges
+    included) against the oracle on light-cone windows of the same force values."""
+    import torch
+    need_gpu()
+    ny, steps = 30000, 6
+    say(f"{nx}x{ny} fp32 {kind}")
+    two_pi = 2.0 * np.pi
+    x = torch.arange(nx, dtype=torch.float64, device="cuda") + 0.5
+    y = torch.arange(ny, dtype=torch.float64, device="cuda") + 0.5
+    gx = 1e-4 * torch.outer(torch.cos(two_pi * 2 * y / ny), torch.sin(two_pi * 3 * x / nx))
+    gy = 1e-4 * torch.outer(torch.sin(two_pi * 1 * y / ny), torch.cos(two_pi * 2 * x / nx))
+    del x, y
+    mat = P.Material.from_shear_poisson(1.0, 0.3)
+    s = _solver(nx, ny, "fp32")
+    s.set_material(mat.lame_lambda, mat.lame_mu)
+    s.set_body_force(gx, gy)
+    if kind == "single":
+        s.set_time_blocking(1)
+    cfg = s.launch_config()
+    say(f"  launch config {cfg}")
+    if kind == "default":
+        assert cfg["kernel"] == "wavefront" and cfg["steps_per_launch"] == 4
+    else:
+        assert cfg["kernel"] == "single"
+    s.step(steps)
+    ux, uy = s.displacement()
+    rng = np.random.default_rng(3)
+    sites = [(0, 0), (0, nx - 1), (ny - 1, 0), (ny - 1, nx - 1), (ny // 2, 0), (0, nx // 2)]
+    sites += [(int(rng.integers(0, ny)), int(rng.integers(0, nx))) for _ in range(14)]
+    iy = torch.tensor([p[0] for p in sites], device="cuda")
+    ix = torch.tensor([p[1] for p in sites], device="cuda")
+    got = np.stack([host(ux[iy, ix]), host(uy[iy, ix])], axis=1)
+    om = omega(mat)
+    halo = steps + 2
+    want = []
+    for (py, px) in sites:
+        ys = torch.tensor((np.arange(py - halo, py + halo + 1)) % ny, device="cuda")
+        xs = torch.tensor((np.arange(px - halo, px + halo + 1)) % nx, device="cuda")
+        wx, wy = host(gx[ys][:, xs]), host(gy[ys][:, xs])
+        f = O.run(O.zero_state(2 * halo + 1, 2 * halo + 1), wx, wy, om, steps)
+        ox, oy = O.displacement(f, wx, wy)
+        want.append((ox[halo, halo], oy[halo, halo]))
+    want = np.array(want)
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    say(f"  max rel err at {len(sites)} sites: {err:.2e}")
+    s.close()
+    del s, gx, gy, ux, uy
+    torch.cuda.empty_cache()
+    assert err <= 1e-5
+
+
 @pytest.mark.parametrize("prec,nx,ny,steps", [
     ("fp64", 1, 1, 6), ("fp64", 3, 5, 7), ("fp64", 67, 33, 21), ("fp64", 130, 9, 10),
     ("fp64", 64, 8, 4), ("fp32", 2, 2, 5), ("fp32", 65, 17, 9), ("fp32", 256, 48, 12),
