@@ -141,6 +141,8 @@ def parse():
     ap.add_argument("--comparator-only", action="store_true",
                     help="run only the FP64-storage comparator of the headline workload "
                          "(for profiling)")
+    ap.add_argument("--small-only", action="store_true",
+                    help="run only the 32 x 32 launch-bound solve leg")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the two serving legs (overloaded, then sustained)")
     ap.add_argument("--large-steps", type=int, default=10000)
@@ -223,6 +225,42 @@ def run_workload(solvers, nchunks, chunk):
             "plain_us_per_step": 1e3 * plain_ms / (len(ev) * fused),
             "steps_per_launch": tb, "launch_config": solvers[0][0].launch_config(),
             "last": last[-len(solvers):], "history": history}
+
+
+def small_32(reps: int = 20):
+    """The 32 x 32 FP64 manufactured workload (nu = 0.3, mu = 1, mode (1, 1)) solved
+    to r <= 1e-10 with a check every step: launch-bound (147 KB per step), so it is
+    timed per solve and per step rather than against a roofline (its stop step and
+    displacement against the oracle are the smoke check's and the tests').  It runs
+    as one workgroup that keeps the state in LDS (lbm_set_small_solve)."""
+    import numpy as np
+    import torch
+    from paper_2208_14870_amd import lbm, problem as P
+    case = P.single_32()
+    mat = case.material
+    gx, gy = torch.from_numpy(case.gx).cuda(), torch.from_numpy(case.gy).cuda()
+    s = lbm.Solver(32, 32, "fp64")
+    s.set_material(mat.lame_lambda, mat.lame_mu)
+    s.set_body_force(gx, gy)
+    times, n, r = [], 0, 0.0
+    for _ in range(reps + 1):
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n, r, _ = s.solve_to_tol(1e-10, 10000, 1)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ux, uy = (t.cpu().numpy() for t in s.displacement())
+    s.close()
+    ex = np.sqrt(np.sum((ux - case.ux_exact) ** 2 + (uy - case.uy_exact) ** 2) /
+                 np.sum(case.ux_exact ** 2 + case.uy_exact ** 2))
+    med = sorted(times[1:])[len(times[1:]) // 2]
+    return {"lattice": [32, 32], "storage": "fp64", "tol": 1e-10, "check_every": 1,
+            "steps": int(n), "residual": r,
+            "solve_ms_median": round(1e3 * med, 3), "us_per_step": round(1e6 * med / n, 2),
+            "rel_l2_vs_manufactured": float(ex),
+            "path": "one workgroup: state in LDS, residual and stop on the device",
+            "note": "a check every step; launch-per-check solve: 2.19 ms (19.4 us per step)"}
 
 
 def large_lattice(steps=10000, warm=200, precs=("fp64", "fp32", "fp16"), tb=0):
@@ -485,6 +523,9 @@ def main():
         print(json.dumps({"inplace_8192": inplace_run(steps=args.large_steps,
                                                       warm=args.large_warm)}), flush=True)
         return
+    if args.small_only:
+        print(json.dumps({"small_32": small_32()}), flush=True)
+        return
     if args.serving_only:
         sv, ss = serving_legs()
         print(json.dumps({"serving": sv, "serving_sustained": ss}), flush=True)
@@ -592,6 +633,8 @@ def main():
         out["fp32_rel_l2_vs_fp64"] = math.sqrt(num / den)
         log("8192x8192 random load: FP64 / FP32 / FP16, 200 + 10000 steps")
         out["hbm_copy"] = copy_bandwidth()
+        log("32x32 FP64 to r <= 1e-10, a check every step")
+        out["small_32"] = small_32()
         out["large_8192"] = large_lattice()
         log("in-place streaming vs two buffers, 8192x8192, one step per launch")
         out["inplace_8192"] = inplace_run()

@@ -55,6 +55,8 @@ struct lbm_solver {
     double r_switch = 0.0;
     int blocks_per_cu = 0;  // 0: one workgroup per tile; k: persistent k per CU
     bool fused_auto = true;  // fused kernel not chosen by the caller: follows the default
+    // steps per launch of the one-workgroup solve of small lattices (0: off)
+    long long small_budget = 65536;
     // half storage: a state set by lbm_set_populations and the exponent it needs
     bool user_state = false;
     int e_user = INT_MIN;  // INT_MIN: the state sets no bound (all zero)
@@ -675,6 +677,63 @@ int rescale_half(lbm_solver* s, double fmax_stored) {
 }
 }  // namespace
 
+namespace {
+// Whether lbm_solve_to_tol runs as one-workgroup launches: two buffers, a lattice
+// whose two population buffers fit in LDS, FP64 storage or FP32 without a polish
+// switch (half storage rescales between checks on the host).
+bool small_solve_ok(const lbm_solver* s) {
+    const Lattice& L = s->L;
+    if (s->small_budget <= 0 || L.inplace || L.N > small_max_sites(L.prec)) return false;
+    return L.prec == LBM_FP64 || (L.prec == LBM_FP32 && !(s->r_switch > 0.0));
+}
+
+int solve_small(lbm_solver* s, double tol, long long max_steps, long long K,
+                long long* steps_done, double* residual) {
+    Lattice& L = s->L;
+    SmallLaunch P;
+    P.d = L.desc();
+    P.sel = s->sel();
+    P.check = K;
+    P.max_steps = max_steps;
+    P.tol = tol;
+    P.out = s->d_result;
+    long long m = 0;
+    double r = NAN;
+    while (true) {
+        P.m0 = m;
+        P.have_prev = m > 0;
+        P.budget = s->small_budget;
+        P.r_in = r;
+        hipError_t e = launch_solve_small(L.prec, L.general(), s->stream, P);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->h_result, s->d_result, 3 * 8, hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return s->hip_fail(e, "solve_to_tol");
+        const long long m_new = (long long)s->h_result[0];
+        const int outcome = (int)s->h_result[2];
+        r = s->h_result[1];
+        s->steps += m_new - m;
+        m = m_new;
+        *steps_done = m;
+        *residual = r;
+        if (outcome == kSmallConverged) return LBM_OK;
+        if (outcome == kSmallLimit) return LBM_NOT_CONVERGED;
+        if (outcome == kSmallDiverged) {
+            s->err = "solve_to_tol: residual is not finite (diverged)";
+            return LBM_E_DIVERGED;
+        }
+    }
+}
+}  // namespace
+
+int lbm_set_small_solve(lbm_solver* s, long long steps_per_launch) {
+    if (!s) return LBM_E_ARG;
+    if (steps_per_launch < 0)
+        return s->fail(LBM_E_ARG, "set_small_solve: steps_per_launch must be >= 0");
+    s->small_budget = steps_per_launch;
+    return LBM_OK;
+}
+
 int lbm_solve_to_tol(lbm_solver* s, double tol, long long max_steps, int check_every,
                      long long* steps_done, double* residual) {
     if (!s) return LBM_E_ARG;
@@ -682,6 +741,7 @@ int lbm_solve_to_tol(lbm_solver* s, double tol, long long max_steps, int check_e
         return s->fail(LBM_E_ARG, "solve_to_tol: need tol >= 0, max_steps >= 0, check_every >= 1");
     if (!s->L.has_material || !s->L.has_force)
         return s->fail(LBM_E_STATE, "solve_to_tol: material and body force must be set first");
+    if (small_solve_ok(s)) return solve_small(s, tol, max_steps, check_every, steps_done, residual);
     const long long K = check_every;
     long long n = 0;             // steps taken by this call
     bool have_prev_u = false;    // u buffer holds u(n - 1)

@@ -196,6 +196,28 @@ inline hipError_t launch_stepN(int prec, int ns, int th, unsigned grid, hipStrea
     return hipGetLastError();
 }
 
+// Whole solves of small lattices in one workgroup (k_solve_small): the largest
+// lattices whose two population buffers fit in LDS.
+constexpr int kSmallMax64 = 1152, kSmallMax32 = 2304;
+
+inline int small_max_sites(int prec) {
+    return prec == LBM_FP64 ? kSmallMax64 : prec == LBM_FP32 ? kSmallMax32 : 0;
+}
+
+inline hipError_t launch_solve_small(int prec, bool general, hipStream_t st, const SmallLaunch& P) {
+    if (prec == LBM_FP64 && general)
+        hipLaunchKernelGGL((k_solve_small<double, kSmallMax64, true>), dim3(1), dim3(kSmallThreads), 0, st, P);
+    else if (prec == LBM_FP64)
+        hipLaunchKernelGGL((k_solve_small<double, kSmallMax64, false>), dim3(1), dim3(kSmallThreads), 0, st, P);
+    else if (prec == LBM_FP32 && general)
+        hipLaunchKernelGGL((k_solve_small<float, kSmallMax32, true>), dim3(1), dim3(kSmallThreads), 0, st, P);
+    else if (prec == LBM_FP32)
+        hipLaunchKernelGGL((k_solve_small<float, kSmallMax32, false>), dim3(1), dim3(kSmallThreads), 0, st, P);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 // Register-wavefront launch of `ns` plain steps on slot 0 (single lattice),
 // segments of hs rows; two columns per lane for FP32/FP16 on even-width lattices.
 template <typename S, int V>

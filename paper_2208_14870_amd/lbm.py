@@ -60,6 +60,7 @@ def load() -> ctypes.CDLL:
         "lbm_step_checked": (i, [vp, ll, pd]),
         "lbm_solve_to_tol": (i, [vp, d, ll, i, pll, pd]),
         "lbm_set_polish": (i, [vp, d]),
+        "lbm_set_small_solve": (i, [vp, ll]),
         "lbm_current_precision": (i, [vp]),
         "lbm_steps_done": (ll, [vp]),
         "lbm_get_displacement": (i, [vp, vp, vp]),
@@ -237,6 +238,11 @@ class Solver:
 
     def set_polish(self, r_switch: float):
         self._check(self.lib.lbm_set_polish(self.h, float(r_switch)))
+
+    def set_small_solve(self, steps_per_launch: int):
+        """Steps per launch of the one-workgroup solve of small lattices in
+        solve_to_tol (0: off); see lbm_set_small_solve."""
+        self._check(self.lib.lbm_set_small_solve(self.h, int(steps_per_launch)))
 
     @property
     def current_precision(self) -> int:
