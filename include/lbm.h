@@ -160,7 +160,9 @@ int lbm_step_checked(lbm_solver *s, long long nsteps, double *residual);
  * decreasing, resets the two undamped modes that narrow storage leaves
  * rounding noise in (the staggered first moments at k = (pi,0), (0,pi) to
  * their fixed point, the mean first moments to their exact value: the
- * initial sums plus steps * sum g), and continues in FP64.  Errors: LBM_E_ARG, LBM_E_STATE (no
+ * initial sums plus steps * sum g), and continues in FP64.  Small lattices
+ * (see lbm_set_small_solve) run the whole call in one workgroup on the device
+ * with the same steps, states and outcome.  Errors: LBM_E_ARG, LBM_E_STATE (no
  * force), LBM_E_DIVERGED (non-finite residual; state left readable),
  * LBM_E_HIP. */
 int lbm_solve_to_tol(lbm_solver *s, double tol, long long max_steps, int check_every,
