@@ -143,10 +143,11 @@ static __global__ __launch_bounds__(kSmallThreads) void k_solve_small(SmallLaunc
                 r_shared = rr;
             }
             __syncthreads();
+            // flag and r_shared are next written at the next check, after the
+            // barrier that ends this step and those of the next reduction
             decision = flag & 15;
             outcome = flag >> 4;
             r = r_shared;
-            __syncthreads();  // flag and r_shared are rewritten at the next check
             if (decision == 1) break;
         }
 #pragma unroll
