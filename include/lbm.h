@@ -175,11 +175,12 @@ int lbm_set_polish(lbm_solver *s, double r_switch);
 
 /* Whole solves of small lattices on the device (lbm_solve_to_tol).  A residual
  * check every K steps makes a small lattice's solve launch-bound, so a
- * two-buffer lattice of at most 1152 FP64 or 2304 FP32 sites (FP32 without a
- * polish switch) runs as one workgroup that keeps both population buffers in
- * LDS, evaluates the residual of Sec. 2.1 at the check steps and stops on the
- * device by the rules of lbm_solve_to_tol, at most `steps_per_launch` steps per
- * launch (the host resumes it).  States and stop steps equal those of the
+ * two-buffer lattice of at most 1152 FP64 or 2304 FP32 sites (1152 for FP32
+ * with a polish switch) runs as one workgroup that keeps both population
+ * buffers in LDS, evaluates the residual of Sec. 2.1 at the check steps and
+ * stops on the device by the rules of lbm_solve_to_tol, at most
+ * `steps_per_launch` steps per launch (the host resumes it, and performs the
+ * FP64 switch where the device finds it due).  States and stop steps equal those of the
  * launch-per-check solve (the residual's FP64 sums run in another order).
  * steps_per_launch = 0 turns this off; the default is 65536.  Errors: LBM_E_ARG
  * (negative). */

@@ -679,12 +679,14 @@ int rescale_half(lbm_solver* s, double fmax_stored) {
 
 namespace {
 // Whether lbm_solve_to_tol runs as one-workgroup launches: two buffers, a lattice
-// whose two population buffers fit in LDS, FP64 storage or FP32 without a polish
-// switch (half storage rescales between checks on the host).
+// whose two population buffers fit in LDS, FP64 or FP32 storage (half storage
+// rescales between checks on the host); FP32 with a polish switch only if the
+// FP64 state it switches to fits as well.
 bool small_solve_ok(const lbm_solver* s) {
     const Lattice& L = s->L;
     if (s->small_budget <= 0 || L.inplace || L.N > small_max_sites(L.prec)) return false;
-    return L.prec == LBM_FP64 || (L.prec == LBM_FP32 && !(s->r_switch > 0.0));
+    if (L.prec == LBM_FP64) return true;
+    return L.prec == LBM_FP32 && (!(s->r_switch > 0.0) || L.N <= small_max_sites(LBM_FP64));
 }
 
 int solve_small(lbm_solver* s, double tol, long long max_steps, long long K,
@@ -699,19 +701,24 @@ int solve_small(lbm_solver* s, double tol, long long max_steps, long long K,
     P.out = s->d_result;
     long long m = 0;
     double r = NAN;
+    int nondec = 0;
     while (true) {
         P.m0 = m;
         P.have_prev = m > 0;
         P.budget = s->small_budget;
         P.r_in = r;
+        P.r_switch = (L.prec != LBM_FP64) ? s->r_switch : 0.0;
+        P.nondec_in = nondec;
+        P.pad_ = 0;
         hipError_t e = launch_solve_small(L.prec, L.general(), s->stream, P);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(s->h_result, s->d_result, 3 * 8, hipMemcpyDeviceToHost, s->stream);
+            e = hipMemcpyAsync(s->h_result, s->d_result, 4 * 8, hipMemcpyDeviceToHost, s->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
         if (e != hipSuccess) return s->hip_fail(e, "solve_to_tol");
         const long long m_new = (long long)s->h_result[0];
         const int outcome = (int)s->h_result[2];
         r = s->h_result[1];
+        nondec = (int)s->h_result[3];
         s->steps += m_new - m;
         m = m_new;
         *steps_done = m;
@@ -721,6 +728,12 @@ int solve_small(lbm_solver* s, double tol, long long max_steps, long long K,
         if (outcome == kSmallDiverged) {
             s->err = "solve_to_tol: residual is not finite (diverged)";
             return LBM_E_DIVERGED;
+        }
+        if (outcome == kSmallSwitch) {  // narrow storage to FP64, then on in FP64
+            const int rc = promote_solver(s);
+            if (rc != LBM_OK) return rc;
+            P.d = L.desc();
+            P.sel = s->sel();
         }
     }
 }

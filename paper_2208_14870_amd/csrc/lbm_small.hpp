@@ -6,7 +6,8 @@
 // fit in LDS runs instead in one workgroup that keeps the state in LDS, steps,
 // evaluates the steady-state residual of Sec. 2.1 at the check steps with the
 // same FP64 sums as the check kernels, and decides on the device when to stop,
-// with the stopping rules of lbm_solve_to_tol.  The collision is the one every
+// with the stopping rules of lbm_solve_to_tol (and the FP64 switch of narrow
+// storage, which the host then performs).  The collision is the one every
 // kernel uses, so the states are those of single steps bit for bit; the
 // residual's sums run in another order (rounding only).
 #pragma once
@@ -28,11 +29,15 @@ struct SmallLaunch {
     long long max_steps;  // the solve's limit
     double tol;
     double r_in;          // the solve's last residual so far (NaN: none)
-    double* out;          // steps after the launch, last residual, outcome
+    double r_switch;      // > 0: narrow storage switches to FP64 (lbm_set_polish)
+    int nondec_in;        // checks in a row whose residual did not decrease
+    int pad_;
+    double* out;          // steps after the launch, last residual, outcome, nondec
 };
 
 // Outcome codes in out[2].
-constexpr int kSmallConverged = 0, kSmallLimit = 1, kSmallDiverged = 2, kSmallBudget = 3;
+constexpr int kSmallConverged = 0, kSmallLimit = 1, kSmallDiverged = 2, kSmallBudget = 3,
+              kSmallSwitch = 4;
 
 // One solve (or a budget of its steps) of an nx x ny lattice, nx * ny <= NMAX.
 // The state at solve step m is the post-collision field f*(m - 1) (as stored in
@@ -83,6 +88,7 @@ static __global__ __launch_bounds__(kSmallThreads) void k_solve_small(SmallLaunc
     long long m = P.m0;
     const long long mend = P.max_steps - P.m0 > P.budget ? P.m0 + P.budget : P.max_steps;
     double r = P.r_in;
+    int nondec = P.nondec_in;
     int outcome = kSmallBudget;
     while (true) {
         const bool check = m >= P.check && m % P.check == 0;
@@ -138,6 +144,14 @@ static __global__ __launch_bounds__(kSmallThreads) void k_solve_small(SmallLaunc
                 } else if (m >= P.max_steps) {
                     dec = 1;
                     oc = kSmallLimit;
+                } else if (P.r_switch > 0.0) {
+                    // the switch of lbm_set_polish, after this step as between
+                    // launches of the launch-per-check solve
+                    nondec = (rr >= r) ? nondec + 1 : 0;
+                    if (rr <= P.r_switch || nondec >= 2) {
+                        dec = 2;
+                        oc = kSmallSwitch;
+                    }
                 }
                 flag = dec | (oc << 4);
                 r_shared = rr;
@@ -179,6 +193,7 @@ static __global__ __launch_bounds__(kSmallThreads) void k_solve_small(SmallLaunc
         glob(P.out)[0] = (double)m;
         glob(P.out)[1] = r;
         glob(P.out)[2] = (double)outcome;
+        glob(P.out)[3] = (double)nondec;
     }
 }
 

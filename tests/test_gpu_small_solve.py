@@ -13,12 +13,14 @@ from gpu_common import dev, host, need_gpu, say
 pytestmark = pytest.mark.gpu
 
 
-def _solve(lbm, n1, n2, prec, mat, gx, gy, rates, tol, max_steps, K, budget):
-    s = lbm.Solver(n1, n2, prec)
+def _solve(lbm, n1, n2, prec, mat, gx, gy, rates, tol, max_steps, K, budget, r_switch=0.0):
+    s = lbm.Solver(n1, n2, prec, with_polish=r_switch > 0.0)
     s.set_material(mat.lame_lambda, mat.lame_mu)
     if rates:
         s.set_rates(*rates)
     s.set_body_force(dev(gx), dev(gy))
+    if r_switch > 0.0:
+        s.set_polish(r_switch)
     s.set_small_solve(budget)
     try:
         n, r, status = s.solve_to_tol(tol, max_steps, K)
@@ -26,7 +28,7 @@ def _solve(lbm, n1, n2, prec, mat, gx, gy, rates, tol, max_steps, K, budget):
         n, r, status = s.steps_done, float("nan"), -5
     f = host(s.populations())
     ux, uy = (host(t) for t in s.displacement())
-    done = s.steps_done
+    done = (s.steps_done, s.current_precision)
     s.close()
     return n, r, status, f, ux, uy, done
 
@@ -57,10 +59,43 @@ def test_random_small_solves_equal_the_launch_per_check_solve():
                                         tol=tol, K=K, max_steps=max_steps, budget=budget)))
         a = _solve(lbm, nx, ny, prec, mat, gx, gy, rates, tol, max_steps, K, budget)
         b = _solve(lbm, nx, ny, prec, mat, gx, gy, rates, tol, max_steps, K, 0)
-        assert a[0] == b[0] and a[2] == b[2] and a[6] == b[6], (a[0], b[0], a[2], b[2])
-        assert (np.isnan(a[1]) and np.isnan(b[1])) or abs(a[1] - b[1]) <= 1e-9 * abs(b[1])
-        for u, v in zip(a[3:6], b[3:6]):
-            assert np.array_equal(u, v)
+        _same(a, b)
+
+
+def _same(a, b):
+    assert a[0] == b[0] and a[2] == b[2] and a[6] == b[6], (a[0], b[0], a[2], b[2], a[6], b[6])
+    assert (np.isnan(a[1]) and np.isnan(b[1])) or abs(a[1] - b[1]) <= 1e-9 * abs(b[1])
+    for u, v in zip(a[3:6], b[3:6]):
+        assert np.array_equal(u, v, equal_nan=True)
+
+
+def test_small_solves_with_the_fp64_switch():
+    """FP32 storage with a polish threshold: the device finds the switch due (r <=
+    r_switch or two checks without decrease), the host switches to FP64 and the
+    solve goes on in one workgroup; same steps, switch and final state as the
+    launch-per-check solve."""
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    rng = np.random.default_rng(32)
+    for case in range(16):
+        while True:
+            nx, ny = int(rng.integers(2, 40)), int(rng.integers(2, 40))
+            if nx * ny <= 1152:
+                break
+        mat = P.Material.from_shear_poisson(float(rng.uniform(0.3, 1.5)), float(rng.uniform(0.05, 0.45)))
+        x = (np.arange(nx) + 0.5) / nx
+        y = (np.arange(ny) + 0.5) / ny
+        gx = P.remove_mean(1e-4 * np.sin(2 * np.pi * (x[None, :] + y[:, None])))
+        gy = P.remove_mean(1e-4 * np.cos(2 * np.pi * (x[None, :] - 2 * y[:, None])))
+        K = int(rng.choice([1, 3, 20, 50]))
+        r_switch = float(rng.choice([1e-4, 1e-6, 1e-7]))
+        budget = int(rng.choice([1, 9, 65536]))
+        say("small polish " + json.dumps(dict(case=case, nx=nx, ny=ny, K=K, r_switch=r_switch,
+                                               budget=budget)))
+        a = _solve(lbm, nx, ny, "fp32", mat, gx, gy, None, 1e-11, 30000, K, budget, r_switch)
+        b = _solve(lbm, nx, ny, "fp32", mat, gx, gy, None, 1e-11, 30000, K, 0, r_switch)
+        _same(a, b)
+        assert a[6][1] == 0  # ended in FP64
 
 
 def test_small_solve_divergence():
