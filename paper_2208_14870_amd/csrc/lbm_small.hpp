@@ -46,7 +46,9 @@ constexpr int kSmallConverged = 0, kSmallLimit = 1, kSmallDiverged = 2, kSmallBu
 // the latter kept per site from the step before (or read from d.u at the start
 // of a launch).  Stopping as lbm_solve_to_tol does: r <= tol or the limit at a
 // check step keeps the state of step m; a residual that is not finite ends after
-// step m + 1; the limit between checks keeps the state of the limit.
+// step m + 1; the limit between checks keeps the state of the limit.  With a
+// switch threshold (narrow storage, lbm_set_polish), a check that finds the FP64
+// switch due also ends the launch after step m + 1, and the host switches.
 template <typename S, int NMAX, bool GENERAL>
 static __global__ __launch_bounds__(kSmallThreads) void k_solve_small(SmallLaunch P) {
     using C = typename Store<S>::C;
