@@ -50,18 +50,26 @@ typedef struct lbm_batch lbm_batch;
 /* Storage precision of the populations. */
 enum lbm_precision { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16 = 2 };
 
-/* Status codes: 0 ok, > 0 informational, < 0 error. */
+/* Status codes: 0 ok, > 0 informational, < 0 error.  The informational
+ * codes of lbm_set_body_force are bits and may be combined (2 | 4 = 6). */
 enum lbm_status {
     LBM_OK = 0,
     LBM_NOT_CONVERGED = 1,   /* solve stopped at max_steps above tolerance            */
-    LBM_W_NONZERO_MEAN = 2,  /* force accepted, but its mean is not zero: no steady
-                                state exists (the mean of u is conserved, Sec. 7.2)   */
+    LBM_W_MEAN_REMOVED = 2,  /* force accepted with its non-zero mean subtracted: the
+                                mean of u is conserved, so a load with a mean has no
+                                steady state (Sec. 7.2)                                */
+    LBM_W_STAGGERED_LOAD = 4, /* force accepted, but it has a component at k = (pi, 0)
+                                or (0, pi) (sum (-1)^x gx or sum (-1)^y gy is not at
+                                rounding level, even nx or ny): the staggered first
+                                moment then oscillates for good, so the iteration
+                                from f = 0 does not reach a steady state            */
     LBM_E_ARG = -1,          /* invalid argument (null pointer, size, tolerance)       */
     LBM_E_MATERIAL = -2,     /* mu <= 0, lambda + mu <= 0, non-finite, or theta,
                                 omega outside the admissible range                    */
     LBM_E_WORKSPACE = -3,    /* workspace / arena too small, or no room for a lattice */
     LBM_E_HIP = -4,          /* a HIP runtime call failed                              */
-    LBM_E_DIVERGED = -5,     /* residual or populations became non-finite              */
+    LBM_E_DIVERGED = -5,     /* residual or populations became non-finite, or the
+                                update norm kept rising (lbm_set_divergence_guard)    */
     LBM_E_STATE = -6         /* call not valid in the current state (e.g. no force)   */
 };
 
@@ -128,9 +136,14 @@ int lbm_set_material(lbm_solver *s, double lame_lambda, double lame_mu);
 int lbm_set_rates(lbm_solver *s, double theta, double omega12, double omega21, double omega22);
 
 /* Body force g (per-step force in lattice units), FP64 device arrays
- * [ny][nx].  Copied into the workspace (converted to the arithmetic type).
- * Returns LBM_W_NONZERO_MEAN (force accepted unchanged) if
- * |mean| > 1e-12 * rms for either component.  Errors: LBM_E_ARG, LBM_E_HIP. */
+ * [ny][nx].  The force's FP64 statistics are formed first (a two-stage
+ * reduction in a fixed order); a non-finite force returns LBM_E_ARG and leaves
+ * the previous force in place.  Otherwise the force is copied into the
+ * workspace (in the arithmetic type) with its FP64 mean subtracted from a
+ * component whose |mean| exceeds 1e-12 * rms of the force (LBM_W_MEAN_REMOVED;
+ * a smaller mean is at the rounding level of the sum and is left as given).
+ * Returns the OR of LBM_W_MEAN_REMOVED and LBM_W_STAGGERED_LOAD (see the
+ * status codes), or LBM_OK.  Blocking.  Errors: LBM_E_ARG, LBM_E_HIP. */
 int lbm_set_body_force(lbm_solver *s, const double *gx, const double *gy);
 
 /* f := 0 (u0 = 0 initialisation at equilibrium, Sec. 6.2), step count := 0,
@@ -158,13 +171,17 @@ int lbm_step_checked(lbm_solver *s, long long nsteps, double *residual);
  * r evaluated (NaN if none).  With a polish threshold set (lbm_set_polish), an
  * FP32/FP16 solver switches to FP64 storage once r <= r_switch or r stops
  * decreasing, resets the two undamped modes that narrow storage leaves
- * rounding noise in (the staggered first moments at k = (pi,0), (0,pi) to
- * their fixed point, the mean first moments to their exact value: the
- * initial sums plus steps * sum g), and continues in FP64.  Small lattices
- * (see lbm_set_small_solve) run the whole call in one workgroup on the device
- * with the same steps, states and outcome.  Errors: LBM_E_ARG, LBM_E_STATE (no
- * force), LBM_E_DIVERGED (non-finite residual; state left readable),
- * LBM_E_HIP. */
+ * rounding noise in to the values of the exact trajectory, and continues in
+ * FP64: the staggered first moments at k = (pi,0), (0,pi), which oscillate
+ * with period two about -G/2 (G = sum (-1)^x gx, likewise in y) with the
+ * amplitude set by the initial state, and the mean first moments (the initial
+ * sums plus steps * sum g).  The FP64 phase therefore follows the FP64
+ * solver's trajectory: a load with a staggered component (LBM_W_STAGGERED_LOAD)
+ * stays unconverged in both.  Small lattices (see lbm_set_small_solve) run the
+ * whole call in one workgroup on the device with the same steps, states and
+ * outcome.  Errors: LBM_E_ARG, LBM_E_STATE (no force), LBM_E_DIVERGED
+ * (non-finite residual, or the rise rule of lbm_set_divergence_guard; the
+ * state f(n) of that check step is left readable), LBM_E_HIP. */
 int lbm_solve_to_tol(lbm_solver *s, double tol, long long max_steps, int check_every,
                      long long *steps_done, double *residual);
 
@@ -185,6 +202,20 @@ int lbm_set_polish(lbm_solver *s, double r_switch);
  * steps_per_launch = 0 turns this off; the default is 65536.  Errors: LBM_E_ARG
  * (negative). */
 int lbm_set_small_solve(lbm_solver *s, long long steps_per_launch);
+
+/* Divergence guard of lbm_solve_to_tol (both the launch-per-check and the
+ * one-workgroup paths).  With a material outside the stability region of
+ * Sec. 5 (e.g. nu = -0.4, E = 0.082, Sec. 7.3.5) the unstable modes grow
+ * geometrically, and with them the update norm d(n) = ||u(n) - u(n-1)||_2 (the
+ * residual's numerator), long before any value overflows; in a stable solve d
+ * decays.  The solve stops with LBM_E_DIVERGED when d rose at each of `checks`
+ * consecutive checks and is at least twice the largest d of the 32 checks
+ * before that run of rises (a decaying oscillation climbs from its dips, but
+ * not above its earlier peaks); a non-finite residual always stops it.  The
+ * state of the check step that fired (f(n), n = *steps_done) is left
+ * readable.  checks = 0 turns the rise rule off; default 8.  The rule restarts
+ * at the FP64 switch of the polish phase.  Errors: LBM_E_ARG (negative). */
+int lbm_set_divergence_guard(lbm_solver *s, int checks);
 
 /* Current storage precision (changes to LBM_FP64 after a polish switch). */
 int lbm_current_precision(const lbm_solver *s);
@@ -310,12 +341,21 @@ int lbm_batch_destroy(lbm_batch *b);
  * asynchronously on the batch's stream: keep the arrays valid until that
  * stream has run the call's work (the next lbm_batch_step returns after it;
  * reuse ordered on the same stream is safe).  Adds and removals do not wait
- * for the GPU: the work list is rebuilt once, before the next step.
- * LBM_E_WORKSPACE if the arena or the work list has no room (nothing
- * changed). */
+ * for the GPU: the work list is rebuilt once, before the next step.  The
+ * force is mean-projected on the device by the rule of lbm_set_body_force (the
+ * statistics are formed on the stream before the copy, so a solo solver and a
+ * batch slot hold the same force bit for bit); since the call does not wait,
+ * its warnings are read with lbm_batch_force_warnings.  LBM_E_WORKSPACE if the
+ * arena or the work list has no room (nothing changed). */
 int lbm_batch_add(lbm_batch *b, int nx, int ny, int precision, int with_polish,
                   double lame_lambda, double lame_mu, const double *gx, const double *gy,
                   int *slot);
+
+/* Warning bits of a slot's force, as lbm_set_body_force returns them
+ * (LBM_W_MEAN_REMOVED | LBM_W_STAGGERED_LOAD, or 0).  Blocking when the slot
+ * was added since the last step (it reads the force statistics back).
+ * Errors: LBM_E_ARG (no such slot), LBM_E_HIP. */
+int lbm_batch_force_warnings(lbm_batch *b, int slot);
 
 /* Remove a lattice and return its memory to the arena (no wait: later work on
  * that memory is ordered on the batch's stream after the launches reading it). */
@@ -330,6 +370,17 @@ int lbm_batch_step(lbm_batch *b, long long nsteps, int check);
 /* Blocking: residual of the last checked chunk and step count per slot,
  * written for slots 0..max_slots-1 (NaN / -1 for unused slots). */
 int lbm_batch_residuals(lbm_batch *b, double *r_host, long long *steps_host);
+
+/* Divergence flags per slot (host int array of max_slots): 1 when a slot's
+ * residual, over the checks read by lbm_batch_residuals (each check counted
+ * once), became non-finite or its update norm tripped the rise rule of
+ * lbm_set_divergence_guard; 0 otherwise and for unused slots.  The rule
+ * restarts at lbm_batch_promote.  Not blocking. */
+int lbm_batch_diverged(lbm_batch *b, int *flags_host);
+
+/* Rise rule of the batch's divergence guard (see lbm_set_divergence_guard):
+ * checks in a row, 0 = off; default 8.  Errors: LBM_E_ARG. */
+int lbm_batch_set_divergence_guard(lbm_batch *b, int checks);
 
 /* Switch a FP32/FP16 lattice to FP64 storage (polish phase); needs its
  * polish reservation.  Resets the undamped modes as lbm_solve_to_tol's

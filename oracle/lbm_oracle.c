@@ -307,10 +307,18 @@ double oracle_residual(long n, const double *ux, const double *uy, const double 
  * r(n) <= tol, or when n reaches max_steps.  f holds f(n) on return.
  * *steps_out = n, *r_out = last residual evaluated (NAN if none).
  * Returns 0 on convergence, 1 if max_steps was reached, -1 on allocation
- * failure, -2 if a non-finite residual was seen (divergence). */
+ * failure, -2 on divergence: a non-finite residual, or (rise_checks > 0) an
+ * update norm d(n) = ||u(n) - u(n-1)||_2 (the residual's numerator) that rose
+ * at each of rise_checks checks in a row and is at least twice the largest of
+ * the 32 update norms before those rises.  The paper gives no divergence rule;
+ * the rise rule is the solve's stop policy for materials outside the stable
+ * region of Sec. 5, checked after the tolerance and the step limit.  (Under an
+ * instability d grows geometrically without end, while r saturates once the
+ * unstable modes dominate u; a decaying oscillation makes d climb from its
+ * dips for several checks, but never above its earlier peaks.) */
 int oracle_solve_to_tol(int nx, int ny, double *f, const double *gx, const double *gy,
                         const double omega[8], double theta, double tol, long max_steps,
-                        int check_every, long *steps_out, double *r_out) {
+                        int check_every, int rise_checks, long *steps_out, double *r_out) {
     long ns = (long)nx * ny;
     double *fs = (double *)malloc((size_t)8 * ns * sizeof(double));
     double *u = (double *)malloc((size_t)4 * ns * sizeof(double));
@@ -319,6 +327,9 @@ int oracle_solve_to_tol(int nx, int ny, double *f, const double *gx, const doubl
     if (check_every < 1) check_every = 1;
     long n = 0;
     int status = 1;
+    double d_prev = NAN, d_before_rises = NAN;
+    double hist[32];
+    int rises = 0, nhist = 0;
     *r_out = NAN;
     while (n < max_steps) {
         if ((n + 1) % check_every == 0)
@@ -332,6 +343,30 @@ int oracle_solve_to_tol(int nx, int ny, double *f, const double *gx, const doubl
             *r_out = r;
             if (!isfinite(r)) { status = -2; break; }
             if (r <= tol) { status = 0; break; }
+            if (n >= max_steps) break;
+            double d = 0.0;
+            for (long i = 0; i < ns; ++i) {
+                double ex = ux[i] - uxp[i], ey = uy[i] - uyp[i];
+                d += ex * ex + ey * ey;
+            }
+            d = sqrt(d);
+            if (d > d_prev) {
+                if (rises == 0) {
+                    d_before_rises = hist[0];
+                    for (int h = 1; h < nhist && h < 32; ++h)
+                        if (hist[h] > d_before_rises) d_before_rises = hist[h];
+                }
+                ++rises;
+            } else {
+                rises = 0;
+            }
+            hist[nhist % 32] = d;
+            ++nhist;
+            d_prev = d;
+            if (rise_checks > 0 && rises >= rise_checks && d >= 2.0 * d_before_rises) {
+                status = -2;
+                break;
+            }
         }
     }
     *steps_out = n;

@@ -67,7 +67,7 @@ def _load():
         lib.oracle_stress.argtypes = [i, i, dp, dp, dp, dp, dp]
         lib.oracle_residual.argtypes = [l, dp, dp, dp, dp]
         lib.oracle_residual.restype = d
-        lib.oracle_solve_to_tol.argtypes = [i, i, dp, dp, dp, dp, d, d, l, i,
+        lib.oracle_solve_to_tol.argtypes = [i, i, dp, dp, dp, dp, d, d, l, i, i,
                                             ctypes.POINTER(l), dp]
         lib.oracle_solve_to_tol.restype = i
         lib.oracle_stream_only.argtypes = [i, i, dp, l]
@@ -209,15 +209,19 @@ def residual(ux, uy, uxp, uyp) -> float:
 
 
 def solve_to_tol(f, gx, gy, omega, tol: float, max_steps: int, check_every: int = 1,
-                 theta: float = THETA):
-    """Returns (f(n), n, r(n), status) with status 0 converged, 1 max_steps, -2 diverged."""
+                 theta: float = THETA, rise_checks: int = 0):
+    """Returns (f(n), n, r(n), status) with status 0 converged, 1 max_steps, -2
+    diverged (a non-finite residual, or with rise_checks > 0 an update norm
+    ||u(n) - u(n-1)|| that rose at rise_checks checks in a row to at least
+    twice the largest of the 32 update norms before those rises)."""
     f = _f64(f).copy()
     ny, nx = f.shape[1:]
     n = ctypes.c_long(0)
     r = ctypes.c_double(0.0)
     st = _load().oracle_solve_to_tol(nx, ny, _p(f), _p(_f64(gx)), _p(_f64(gy)),
                                      _p(_f64(omega)), theta, tol, int(max_steps),
-                                     int(check_every), ctypes.byref(n), ctypes.byref(r))
+                                     int(check_every), int(rise_checks), ctypes.byref(n),
+                                     ctypes.byref(r))
     if st == -1:
         raise MemoryError("oracle_solve_to_tol")
     return f, n.value, r.value, st

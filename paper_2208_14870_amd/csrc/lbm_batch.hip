@@ -86,6 +86,13 @@ struct BSlot {
     long long steps = 0;
     long long checked_phase = -1;  // its precision's phase right after the last check launch
     int first = 0, count = 0;
+    int warn = 0;  // warning bits of its force (lbm_batch_force_warnings)
+    // divergence guard over its checked chunks (fed once per check by
+    // lbm_batch_residuals), and the check it was last fed
+    RiseGuard guard;
+    long long guard_fed = -1;
+    bool diverged = false;
+    BSlot() { guard.clear(); }
 };
 
 // Work-list entry per slot, uploaded to build the items on the device.
@@ -144,7 +151,7 @@ struct lbm_batch {
     long long cap_items = 0;
     // host
     SlotRow* h_rows = nullptr;  // pinned staging (max_slots rows + 3 ranges)
-    double* h_result = nullptr;  // pinned, max(4 x max_slots, 8)
+    double* h_result = nullptr;  // pinned, max(8 x max_slots, 8)
     SlotDesc* h_desc = nullptr;  // pinned staging of the descriptors (max_slots)
     size_t heap_off = 0;
     Arena arena;
@@ -168,6 +175,7 @@ struct lbm_batch {
     bool dirty = false;
     std::vector<char> stats_pending;  // per slot: force statistics not yet read back
     long long items_bound = 0;        // upper bound of the work list of the active slots
+    int guard_checks = 8;             // divergence guard of every slot (0: rise rule off)
     std::string err;
     std::map<std::tuple<long long, int, int, int, unsigned, unsigned, unsigned>, hipGraphExec_t> graphs;
 
@@ -212,13 +220,15 @@ struct lbm_batch {
         bool any = false;
         for (int i = 0; i < max_slots; ++i) any = any || (slots[i].active && stats_pending[i]);
         if (any) {
-            e = hipMemcpy(h_result, d_stats, 4 * max_slots * sizeof(double), hipMemcpyDeviceToHost);
+            e = hipMemcpy(h_result, d_stats, 8 * max_slots * sizeof(double), hipMemcpyDeviceToHost);
             if (e != hipSuccess) return hip_fail(e, "rebuild: force statistics");
             for (int i = 0; i < max_slots; ++i) {
                 if (!slots[i].active || !stats_pending[i]) continue;
                 Lattice& L = slots[i].L;
-                L.gmax = h_result[4 * i + 3];
-                L.rebase_force(0, h_result[4 * i + 0], h_result[4 * i + 1]);
+                // the force as lbm_set_body_force records it (mean removal,
+                // neutral-mode targets, half scale) and its warnings
+                record_force(L, h_result + 8 * i, 0);
+                slots[i].warn = force_warnings(h_result + 8 * i, L.N);
                 if (L.prec0 == LBM_FP16) L.e_scale = initial_half_exponent(L, L.gmax);
                 stats_pending[i] = 0;
             }
@@ -410,7 +420,7 @@ int lbm_batch_create(int max_slots, void* arena, size_t arena_bytes, void* strea
     b->d_count = reinterpret_cast<int*>(take(max_slots * sizeof(int)));
     b->d_range = reinterpret_cast<int*>(take(6 * sizeof(int)));
     b->d_result = reinterpret_cast<double*>(take(4 * max_slots * sizeof(double)));
-    b->d_stats = reinterpret_cast<double*>(take(4 * max_slots * sizeof(double)));
+    b->d_stats = reinterpret_cast<double*>(take(8 * max_slots * sizeof(double)));
     b->d_rows = reinterpret_cast<SlotRow*>(take((max_slots + 2) * sizeof(SlotRow)));
     b->d_red = reinterpret_cast<double*>(take((kErrBlocks * 8 + 16) * sizeof(double)));
     b->d_items = reinterpret_cast<Item*>(take(b->cap_items * sizeof(Item)));
@@ -434,7 +444,7 @@ int lbm_batch_create(int max_slots, void* arena, size_t arena_bytes, void* strea
                           hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&b->h_result),
-                          std::max(4 * max_slots, 8) * sizeof(double),
+                          std::max(8 * max_slots, 8) * sizeof(double),
                           hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&b->h_desc), max_slots * sizeof(SlotDesc),
@@ -513,7 +523,11 @@ int lbm_batch_add(lbm_batch* b, int nx, int ny, int precision, int with_polish, 
     L.mu = mu;
     L.has_material = L.has_force = true;
     carve_lattice(b->base + b->heap_off + off, N, precision, L.polish, L.mem);
-    hipError_t e = upload_force(L, gx, gy, b->stream);
+    // force statistics into this slot's entry (read back at the next rebuild),
+    // then the mean-projected copy, which reads them in stream order
+    double* st = b->d_stats + 8 * id;
+    hipError_t e = force_stats(gx, gy, nx, ny, b->d_red, st, b->stream);
+    if (e == hipSuccess) e = upload_force(L, gx, gy, st, b->stream);
     if (e == hipSuccess) e = zero_bytes(L.mem.buf[0], 8 * L.plane * elem_bytes(precision), b->stream);
     if (e == hipSuccess) e = zero_bytes(L.mem.u, 2 * L.plane * 8, b->stream);
     if (e != hipSuccess) {
@@ -521,21 +535,7 @@ int lbm_batch_add(lbm_batch* b, int nx, int ny, int precision, int with_polish, 
         s = BSlot();
         return b->hip_fail(e, "batch_add");
     }
-    if (precision == LBM_FP16 || L.polish) {
-        // sum g (the mean first moments at promotion) and max |g| (the initial
-        // half scale): two-stage reduction into this slot's statistics, read
-        // back at the next rebuild
-        hipLaunchKernelGGL(k_force_stats, dim3(kErrBlocks), dim3(kBlock), 0, b->stream, gx, gy, N,
-                           b->d_red);
-        hipLaunchKernelGGL(k_reduce4<kForceMask>, dim3(1), dim3(kBlock), 0, b->stream, b->d_red,
-                           kErrBlocks, b->d_stats + 4 * id);
-        if ((e = hipGetLastError()) != hipSuccess) {
-            b->arena.release(off, need);
-            s = BSlot();
-            return b->hip_fail(e, "batch_add force stats");
-        }
-        b->stats_pending[id] = 1;
-    }
+    b->stats_pending[id] = 1;
     // the next launch reads buf[cur ^ (phase & 1)] = buf[0]
     L.cur = (int)(b->phase[precision] & 1);
     s.active = true;
@@ -545,6 +545,17 @@ int lbm_batch_add(lbm_batch* b, int nx, int ny, int precision, int with_polish, 
     b->dirty = true;
     *slot = id;
     return LBM_OK;
+}
+
+int lbm_batch_force_warnings(lbm_batch* b, int slot) {
+    if (!b) return LBM_E_ARG;
+    if (slot < 0 || slot >= b->max_slots || !b->slots[slot].active)
+        return b->fail(LBM_E_ARG, "batch_force_warnings: no such slot");
+    if (b->stats_pending[slot]) {  // read its force statistics back
+        int rc = b->rebuild();
+        if (rc != LBM_OK) return rc;
+    }
+    return b->slots[slot].warn;
 }
 
 int lbm_batch_remove(lbm_batch* b, int slot) {
@@ -666,7 +677,29 @@ int lbm_batch_residuals(lbm_batch* b, double* r_host, long long* steps_host) {
         double r = (u2 == 0.0) ? (d2 == 0.0 ? 0.0 : INFINITY) : std::sqrt(d2 / u2);
         if (d2 != d2 || u2 != u2 || !std::isfinite(u2)) r = NAN;
         r_host[i] = r;
+        // each check feeds the slot's divergence guard once
+        BSlot& sl = b->slots[i];
+        if (sl.guard_fed != s.checked_phase) {
+            sl.guard_fed = s.checked_phase;
+            const bool bad = !std::isfinite(r) && !(u2 == 0.0 && d2 != 0.0);
+            if (bad || sl.guard.update(std::sqrt(d2), b->guard_checks)) sl.diverged = true;
+        }
     }
+    return LBM_OK;
+}
+
+int lbm_batch_diverged(lbm_batch* b, int* flags_host) {
+    if (!b) return LBM_E_ARG;
+    if (!flags_host) return b->fail(LBM_E_ARG, "batch_diverged: NULL output");
+    for (int i = 0; i < b->max_slots; ++i)
+        flags_host[i] = (b->slots[i].active && b->slots[i].diverged) ? 1 : 0;
+    return LBM_OK;
+}
+
+int lbm_batch_set_divergence_guard(lbm_batch* b, int checks) {
+    if (!b) return LBM_E_ARG;
+    if (checks < 0) return b->fail(LBM_E_ARG, "batch_set_divergence_guard: checks must be >= 0");
+    b->guard_checks = checks;
     return LBM_OK;
 }
 
@@ -701,10 +734,13 @@ int lbm_batch_promote(lbm_batch* b, int slot) {
     L.cur = (int)(b->phase[LBM_FP64] & 1);
     s.checked_phase = checked ? b->phase[LBM_FP64] : -1;
     b->dirty = true;  // the slot moves to the FP64 part of the work list at the next launch
+    s.guard.clear();  // the FP64 phase starts a new residual history
+    s.guard_fed = s.checked_phase;
     // reset the undamped modes (staggered moments, mean) excited by the narrow phase
-    double target[2];
+    double target[2], stag[2];
     L.mean_target(s.steps, target);
-    e = neutral_reset(LBM_FP64, L.desc(), b->sel(s), target, b->d_red, b->stream);
+    L.stag_target_stored(s.steps, stag);
+    e = neutral_reset(LBM_FP64, L.desc(), b->sel(s), target, stag, b->d_red, b->stream);
     if (e != hipSuccess) return b->hip_fail(e, "batch_promote: neutral modes");
     return LBM_OK;
 }

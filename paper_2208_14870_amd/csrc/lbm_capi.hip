@@ -45,6 +45,7 @@ struct lbm_solver {
     int* d_count = nullptr;
     double* d_partial = nullptr;
     double* d_result = nullptr;
+    RiseGuard* d_guard = nullptr;  // divergence guard of the one-workgroup solve
     double* d_red = nullptr;  // kErrBlocks x 8 + 16
     double* h_result = nullptr;  // pinned, 8 doubles
     long long max_items_ = 0;
@@ -57,6 +58,8 @@ struct lbm_solver {
     bool fused_auto = true;  // fused kernel not chosen by the caller: follows the default
     // steps per launch of the one-workgroup solve of small lattices (0: off)
     long long small_budget = 65536;
+    // divergence guard of lbm_solve_to_tol: rises of the residual in a row (0: off)
+    int guard_checks = 8;
     // half storage: a state set by lbm_set_populations and the exponent it needs
     bool user_state = false;
     int e_user = INT_MIN;  // INT_MIN: the state sets no bound (all zero)
@@ -287,7 +290,8 @@ static size_t workspace_bytes(int nx, int ny, int precision, bool polish, bool i
     if (nx < 1 || ny < 1 || !valid_prec(precision)) return 0;
     const long long N = (long long)nx * ny;
     const long long mi = max_items(nx, ny);
-    size_t b = al(sizeof(SlotDesc)) + 4 * al(sizeof(int)) + al(4 * 8) + al(mi * sizeof(Item)) +
+    size_t b = al(sizeof(SlotDesc)) + 4 * al(sizeof(int)) + al(4 * 8) + al(sizeof(RiseGuard)) +
+               al(mi * sizeof(Item)) +
                al(mi * 3 * 8) + al((kErrBlocks * 8 + 16) * 8);
     b += lattice_bytes(N, precision, polish, inplace);
     return b;
@@ -363,6 +367,7 @@ static int create_solver(int nx, int ny, int precision, int with_polish, bool in
     s->d_count = reinterpret_cast<int*>(take(sizeof(int)));
     take(sizeof(int));
     s->d_result = reinterpret_cast<double*>(take(4 * 8));
+    s->d_guard = reinterpret_cast<RiseGuard*>(take(sizeof(RiseGuard)));
     s->d_items = reinterpret_cast<Item*>(take(s->max_items_ * sizeof(Item)));
     s->d_partial = reinterpret_cast<double*>(take(s->max_items_ * 3 * 8));
     s->d_red = reinterpret_cast<double*>(take((kErrBlocks * 8 + 16) * 8));
@@ -414,6 +419,8 @@ int lbm_reset(lbm_solver* s) {
     s->steps = 0;
     L.mbase[0] = L.mbase[1] = 0.0;
     L.mbase_steps = 0;
+    const double j0[2] = {0.0, 0.0};  // f = 0: no staggered moment
+    L.set_stagger_state(0, j0);
     hipError_t e = zero_bytes(L.mem.buf[0], 8 * L.plane * elem_bytes(L.prec0), s->stream);
     if (e == hipSuccess) e = zero_bytes(L.mem.u, 2 * L.plane * 8, s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "lbm_reset");
@@ -453,33 +460,33 @@ int lbm_set_body_force(lbm_solver* s, const double* gx, const double* gy) {
     if (!s) return LBM_E_ARG;
     if (!gx || !gy) return s->fail(LBM_E_ARG, "set_body_force: NULL force");
     Lattice& L = s->L;
-    hipError_t e = upload_force(L, gx, gy, s->stream);
-    if (e != hipSuccess) return s->hip_fail(e, "set_body_force");
-    // mean / rms / max of the force (two-stage FP64 reduction)
-    hipLaunchKernelGGL(k_force_stats, dim3(kErrBlocks), dim3(kBlock), 0, s->stream, gx, gy, L.N,
-                       s->d_red);
-    hipLaunchKernelGGL(k_reduce4<kForceMask>, dim3(1), dim3(kBlock), 0, s->stream, s->d_red,
-                       kErrBlocks, s->d_red + 4 * kErrBlocks);
-    if ((e = hipGetLastError()) != hipSuccess) return s->hip_fail(e, "force stats");
-    if ((e = hipMemcpyAsync(s->h_result, s->d_red + 4 * kErrBlocks, 4 * 8,
-                            hipMemcpyDeviceToHost, s->stream)) != hipSuccess ||
-        (e = hipStreamSynchronize(s->stream)) != hipSuccess)
-        return s->hip_fail(e, "force stats");
-    const double sx = s->h_result[0], sy = s->h_result[1], s2 = s->h_result[2],
-                 gmax = s->h_result[3];
-    if (!std::isfinite(s2)) return s->fail(LBM_E_ARG, "set_body_force: non-finite force");
+    // statistics of the caller's arrays before anything is overwritten, so
+    // that a rejected force leaves the previous one in place
+    double* stats = s->d_red + 8 * kErrBlocks;
+    hipError_t e = force_stats(gx, gy, L.nx, L.ny, s->d_red, stats, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->h_result, stats, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                           s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "set_body_force: force statistics");
+    double st[8];
+    std::memcpy(st, s->h_result, sizeof(st));
+    if (!std::isfinite(st[0]) || !std::isfinite(st[1]) || !std::isfinite(st[2]))
+        return s->fail(LBM_E_ARG, "set_body_force: non-finite force (previous force kept)");
+    // mean-projected copy (the kernel reads the statistics in stream order)
+    if ((e = upload_force(L, gx, gy, stats, s->stream)) != hipSuccess)
+        return s->hip_fail(e, "set_body_force");
     L.has_force = true;
-    L.gmax = gmax;
-    L.rebase_force(s->steps, sx, sy);
+    record_force(L, st, s->steps);
     int rc = refit_half(s);
     if (rc != LBM_OK) return rc;
-    const double N = (double)L.N;
-    const double rms = std::sqrt(s2 / (2.0 * N));
-    if (std::fabs(sx / N) > 1e-12 * rms || std::fabs(sy / N) > 1e-12 * rms) {
-        s->err = "body force has a non-zero mean: no steady state (mean of u grows)";
-        return LBM_W_NONZERO_MEAN;
-    }
-    return LBM_OK;
+    const int w = force_warnings(st, L.N);
+    if (w & LBM_W_MEAN_REMOVED)
+        s->err = "body force had a non-zero mean: removed (the mean of u is conserved)";
+    if (w & LBM_W_STAGGERED_LOAD)
+        s->err = "body force has a k = (pi,0) or (0,pi) component: the staggered first moment "
+                 "oscillates for good, no steady state is reached";
+    return w;
 }
 
 int lbm_set_tile(lbm_solver* s, int bx_log2, int rows_per_thread, int blocks_per_cu) {
@@ -608,9 +615,10 @@ int promote_solver(lbm_solver* s) {
     // the narrow phase leaves rounding noise in the undamped modes (the
     // staggered moments and the mean); reset them so that the FP64 phase
     // converges to the exact trajectory's fixed point
-    double target[2];
+    double target[2], stag[2];
     L.mean_target(s->steps, target);
-    e = neutral_reset(LBM_FP64, L.desc(), s->sel(), target, s->d_red, s->stream);
+    L.stag_target_stored(s->steps, stag);
+    e = neutral_reset(LBM_FP64, L.desc(), s->sel(), target, stag, s->d_red, s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "promote: neutral modes");
     return LBM_OK;
 }
@@ -699,6 +707,9 @@ int solve_small(lbm_solver* s, double tol, long long max_steps, long long K,
     P.max_steps = max_steps;
     P.tol = tol;
     P.out = s->d_result;
+    P.guard_checks = s->guard_checks;
+    P.guard = s->d_guard;
+    hipLaunchKernelGGL(k_guard_clear, dim3(1), dim3(1), 0, s->stream, s->d_guard);
     long long m = 0;
     double r = NAN;
     int nondec = 0;
@@ -709,7 +720,6 @@ int solve_small(lbm_solver* s, double tol, long long max_steps, long long K,
         P.r_in = r;
         P.r_switch = (L.prec != LBM_FP64) ? s->r_switch : 0.0;
         P.nondec_in = nondec;
-        P.pad_ = 0;
         hipError_t e = launch_solve_small(L.prec, L.general(), s->stream, P);
         if (e == hipSuccess)
             e = hipMemcpyAsync(s->h_result, s->d_result, 4 * 8, hipMemcpyDeviceToHost, s->stream);
@@ -726,7 +736,8 @@ int solve_small(lbm_solver* s, double tol, long long max_steps, long long K,
         if (outcome == kSmallConverged) return LBM_OK;
         if (outcome == kSmallLimit) return LBM_NOT_CONVERGED;
         if (outcome == kSmallDiverged) {
-            s->err = "solve_to_tol: residual is not finite (diverged)";
+            s->err = std::isfinite(r) ? "solve_to_tol: the update norm kept rising (diverged)"
+                                      : "solve_to_tol: residual is not finite (diverged)";
             return LBM_E_DIVERGED;
         }
         if (outcome == kSmallSwitch) {  // narrow storage to FP64, then on in FP64
@@ -734,10 +745,19 @@ int solve_small(lbm_solver* s, double tol, long long max_steps, long long K,
             if (rc != LBM_OK) return rc;
             P.d = L.desc();
             P.sel = s->sel();
+            // the FP64 phase starts a new residual history
+            hipLaunchKernelGGL(k_guard_clear, dim3(1), dim3(1), 0, s->stream, s->d_guard);
         }
     }
 }
 }  // namespace
+
+int lbm_set_divergence_guard(lbm_solver* s, int checks) {
+    if (!s) return LBM_E_ARG;
+    if (checks < 0) return s->fail(LBM_E_ARG, "set_divergence_guard: checks must be >= 0");
+    s->guard_checks = checks;
+    return LBM_OK;
+}
 
 int lbm_set_small_solve(lbm_solver* s, long long steps_per_launch) {
     if (!s) return LBM_E_ARG;
@@ -760,6 +780,8 @@ int lbm_solve_to_tol(lbm_solver* s, double tol, long long max_steps, int check_e
     bool have_prev_u = false;    // u buffer holds u(n - 1)
     double r = NAN, r_last = INFINITY;
     int nondecreasing = 0;
+    RiseGuard guard;
+    guard.clear();
     *residual = NAN;
     *steps_done = 0;
     const bool inplace = s->L.inplace;
@@ -798,12 +820,12 @@ int lbm_solve_to_tol(lbm_solver* s, double tol, long long max_steps, int check_e
         s->steps += after - n;
         n = after;
         have_prev_u = true;
-        if (!std::isfinite(r) && !(u2 == 0.0 && d2 != 0.0)) {
-            *steps_done = n;
-            s->err = "solve_to_tol: residual is not finite (diverged)";
-            return LBM_E_DIVERGED;
-        }
-        if (r <= tol || j == max_steps) {
+        // stop rules, in the order of the one-workgroup solve: a non-finite
+        // residual, the tolerance, the limit, the divergence guard
+        bool diverged = !std::isfinite(r) && !(u2 == 0.0 && d2 != 0.0);
+        bool stop = diverged || r <= tol || j == max_steps;
+        if (!stop && guard.update(std::sqrt(d2), s->guard_checks)) diverged = stop = true;
+        if (stop) {
             if (!inplace) {
                 // the check launch advanced to j + 1 and its source buffer still
                 // holds the state it started from, f(j + 1 - span): take the
@@ -818,6 +840,11 @@ int lbm_solve_to_tol(lbm_solver* s, double tol, long long max_steps, int check_e
             }
             n = j;
             *steps_done = n;
+            if (diverged) {
+                s->err = std::isfinite(r) ? "solve_to_tol: the update norm kept rising (diverged)"
+                                          : "solve_to_tol: residual is not finite (diverged)";
+                return LBM_E_DIVERGED;
+            }
             return (r <= tol) ? LBM_OK : LBM_NOT_CONVERGED;
         }
         // precision management between chunks
@@ -831,6 +858,7 @@ int lbm_solve_to_tol(lbm_solver* s, double tol, long long max_steps, int check_e
                 int rc = promote_solver(s);
                 if (rc != LBM_OK) return rc;
                 have_prev_u = true;  // u buffer (FP64, unscaled) is unaffected
+                guard.clear();       // the FP64 phase starts a new residual history
             }
         }
         r_last = r;
@@ -965,13 +993,18 @@ int lbm_set_populations(lbm_solver* s, const double* f) {
     if (s->L.prec == LBM_FP64) e = launch_set_f<double>(d, s->sel(), s->L.layout(s->sel()), f, sc, s->stream);
     else if (s->L.prec == LBM_FP32) e = launch_set_f<float>(d, s->sel(), s->L.layout(s->sel()), f, sc, s->stream);
     else e = launch_set_f<__half>(d, s->sel(), s->L.layout(s->sel()), f, sc, s->stream);
-    if (e == hipSuccess && !s->L.inplace)  // in place: no polish switch, no mean target
+    if (e == hipSuccess && !s->L.inplace)  // in place: no polish switch, no targets
         e = neutral_measure(s->L.prec, d, s->sel(), s->d_red, s->h_result, s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "set_populations");
-    // the mean first moments of the given state start the exact trajectory
-    s->L.mbase[0] = s->h_result[4];
-    s->L.mbase[1] = s->h_result[5];
-    s->L.mbase_steps = s->steps;
+    if (!s->L.inplace) {
+        // the given state starts the exact trajectory: its mean first moments,
+        // and its staggered ones (the stored field's staggered sums are -J)
+        s->L.mbase[0] = s->h_result[4];
+        s->L.mbase[1] = s->h_result[5];
+        s->L.mbase_steps = s->steps;
+        const double j[2] = {-s->h_result[0], -s->h_result[1]};
+        s->L.set_stagger_state(s->steps, j);
+    }
     return LBM_OK;
 }
 
@@ -987,6 +1020,7 @@ int lbm_debug_stream_only(lbm_solver* s, long long nsteps) {
         ++s->phase;
     }
     if (e != hipSuccess) return s->hip_fail(e, "debug_stream_only");
+    s->L.stream_only_stagger(s->steps, nsteps);  // streaming alone flips J
     s->steps += nsteps;
     s->L.mbase_steps += nsteps;  // streaming alone adds no force
     return LBM_OK;

@@ -346,6 +346,70 @@ struct StepLaunch {
     int rows;           // rows per thread of the tiles (the step kernel takes it as VY)
 };
 
+// ---------------------------------------------------------------------------
+// host/device policies shared by every solve path
+// ---------------------------------------------------------------------------
+
+// Mean projection of a body force.  The mean of u is conserved by the scheme
+// (collision adds g to the first moments, streaming permutes), so a steady
+// state needs a zero-mean load (Sec. 7.2).  From the FP64 sums
+// st = {sum gx, sum gy, sum gx^2 + gy^2} over n sites, a component's mean is
+// removed when it exceeds 1e-12 times the rms of the force; a smaller mean is
+// at the level of the sum's own rounding and the force is taken as given.
+// Host and device evaluate this with the same correctly rounded operations, so
+// they take the same decision.
+__host__ __device__ inline void force_mean_shift(const double* st, double n, double shift[2]) {
+#pragma clang fp contract(off)
+    const double ms = st[2] / (2.0 * n);  // mean square of the components
+    for (int c = 0; c < 2; ++c) {
+        const double m = st[c] / n;
+        shift[c] = (m * m > 1e-24 * ms) ? m : 0.0;
+    }
+}
+
+// Divergence guard of the pseudo-time iteration, fed at every check with the
+// update norm d = ||u(n) - u(n-1)||_2 (the residual's numerator).  With a
+// material outside the stability region of Sec. 5 the unstable modes grow
+// geometrically, and so does d, without end (the ratio r = d / ||u|| rises
+// too, but saturates once they dominate u); d grows by decades long before
+// any value overflows.  In a stable solve d decays.  The guard fires when d
+// rose at each of at least M consecutive checks and is at least twice the
+// largest d of the kWindow checks before that run of rises.  A decaying
+// oscillation (a complex pair of eigenvalues) also makes d climb from its dips
+// for several checks, but not above its earlier peaks; the factor keeps
+// rounding noise at a precision floor from firing it.
+struct RiseGuard {
+    static constexpr int kWindow = 32;
+    double hist[kWindow];  // the last update norms, a ring
+    double prev;           // d of the previous check (NaN: none)
+    double base;           // the largest d of the window before the current run
+    int run;               // checks in a row whose d rose
+    int count, pos;        // values in the ring, next slot
+    int pad_;
+    __host__ __device__ void clear() {
+        prev = __builtin_nan("");
+        base = __builtin_nan("");
+        run = count = pos = pad_ = 0;
+    }
+    __host__ __device__ bool update(double d, int M) {
+        if (d > prev) {
+            if (run == 0) {
+                base = hist[0];
+                for (int h = 1; h < count; ++h)
+                    if (hist[h] > base) base = hist[h];
+            }
+            ++run;
+        } else {
+            run = 0;
+        }
+        hist[pos] = d;
+        pos = (pos + 1) % kWindow;
+        if (count < kWindow) ++count;
+        prev = d;
+        return M > 0 && run >= M && d >= 2.0 * base;
+    }
+};
+
 // Blocks are spread over the 8 XCDs round-robin by the hardware; item ranges
 // are assigned so that each XCD walks one contiguous slice of the work list
 // (neighbouring tiles share cache lines of the shifted rows in one L2).

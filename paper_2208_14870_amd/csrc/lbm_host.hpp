@@ -389,6 +389,46 @@ struct Lattice {
         gsum[0] = sx;
         gsum[1] = sy;
     }
+    // The staggered first moments of the exact trajectory (even nx: Jx =
+    // sum_x (-1)^x m10 of f(n); even ny: Jy with (-1)^y m01): J(n) = -G/2 +
+    // (-1)^(n - jbase_steps) jamp with G = gstag, the staggered sums of the
+    // FP64 force.  From f = 0, jamp = G/2: J alternates between 0 and -G.
+    double gstag[2] = {0, 0};
+    double jamp[2] = {0, 0};
+    long long jbase_steps = 0;
+    void stag_value(long long steps, double out[2]) const {
+        const double sg = ((steps - jbase_steps) & 1) ? -1.0 : 1.0;
+        for (int c = 0; c < 2; ++c) out[c] = -0.5 * gstag[c] + sg * jamp[c];
+    }
+    // the staggered sums of the stored field S = f*(n-1) are -J(n)
+    void stag_target_stored(long long steps, double out[2]) const {
+        stag_value(steps, out);
+        out[0] = -out[0];
+        out[1] = -out[1];
+    }
+    // a new force from step `steps` on (J itself is a property of the state)
+    void rebase_stagger(long long steps, double gx_stag, double gy_stag) {
+        double j[2];
+        stag_value(steps, j);
+        gstag[0] = gx_stag;
+        gstag[1] = gy_stag;
+        set_stagger_state(steps, j);
+    }
+    // the state at step `steps` has staggered moments j (f = 0: j = 0)
+    void set_stagger_state(long long steps, const double j[2]) {
+        for (int c = 0; c < 2; ++c) jamp[c] = j[c] + 0.5 * gstag[c];
+        jbase_steps = steps;
+    }
+    // k steps of streaming alone (no collision) flip J k times
+    void stream_only_stagger(long long steps, long long k) {
+        double j[2];
+        stag_value(steps, j);
+        if (k & 1) {
+            j[0] = -j[0];
+            j[1] = -j[1];
+        }
+        set_stagger_state(steps + k, j);
+    }
     int bx_log2 = 6, vy = 1;
     int tb = 4;       // plain steps per launch (2..8: fused multi-step kernel)
     int th = 16;      // tile height of the fused LDS kernel (fused_th)
@@ -544,13 +584,14 @@ inline hipError_t neutral_measure(int prec, const SlotDesc& d, int sel, double* 
 }
 
 // Reset the neutral modes of the stored state to their exact values: the
-// staggered moments to their fixed point and the mean first moments to
-// `mean_target` (sum_x m10, sum_x m01 of the exact trajectory).  Stream-ordered,
-// no host wait: the corrections are computed on the device.  scratch:
+// staggered sums of the stored field to `stag_target` and the mean first
+// moments to `mean_target` (sum_x m10, sum_x m01), both of the exact trajectory
+// (Lattice::stag_target_stored, Lattice::mean_target).  Stream-ordered, no
+// host wait: the corrections are computed on the device.  scratch:
 // 8 * kErrBlocks + 12 doubles of device memory.
 template <typename S>
 inline hipError_t neutral_reset_t(const SlotDesc& d, int sel, const double mean_target[2],
-                                  double* scratch, hipStream_t st) {
+                                  const double stag_target[2], double* scratch, hipStream_t st) {
     hipLaunchKernelGGL(k_neutral_sums<S>, dim3(kErrBlocks), dim3(kBlock), 0, st, d, sel, scratch);
     double* out = scratch + 8 * kErrBlocks;
     hipLaunchKernelGGL(k_reduce4<0>, dim3(1), dim3(kBlock), 0, st, scratch, kErrBlocks, out);
@@ -559,44 +600,73 @@ inline hipError_t neutral_reset_t(const SlotDesc& d, int sel, const double mean_
     double* coef = out + 8;
     hipLaunchKernelGGL(k_neutral_coef, dim3(1), dim3(1), 0, st, out, (double)d.nx * d.ny,
                        d.nx % 2 == 0 ? 1 : 0, d.ny % 2 == 0 ? 1 : 0, mean_target[0],
-                       mean_target[1], 1.0 / d.inv_scale, coef);
+                       mean_target[1], stag_target[0], stag_target[1], 1.0 / d.inv_scale, coef);
     hipLaunchKernelGGL(k_neutral_fix<S>, dim3(blocks_for((long long)d.nx * d.ny)), dim3(kBlock), 0,
                        st, d, sel, coef);
     return hipGetLastError();
 }
 
 inline hipError_t neutral_reset(int prec, const SlotDesc& d, int sel, const double mean_target[2],
-                                double* scratch, hipStream_t st) {
-    if (prec == LBM_FP64) return neutral_reset_t<double>(d, sel, mean_target, scratch, st);
-    if (prec == LBM_FP32) return neutral_reset_t<float>(d, sel, mean_target, scratch, st);
-    return neutral_reset_t<__half>(d, sel, mean_target, scratch, st);
+                                const double stag_target[2], double* scratch, hipStream_t st) {
+    if (prec == LBM_FP64) return neutral_reset_t<double>(d, sel, mean_target, stag_target, scratch, st);
+    if (prec == LBM_FP32) return neutral_reset_t<float>(d, sel, mean_target, stag_target, scratch, st);
+    return neutral_reset_t<__half>(d, sel, mean_target, stag_target, scratch, st);
 }
 
-// Convert the FP64 force into the lattice's arithmetic type (and keep the
-// FP64 copy for the polish phase).
-inline hipError_t upload_force(const Lattice& L, const double* gx, const double* gy, hipStream_t st) {
-    hipError_t e;
+// Statistics of a force given as FP64 device arrays (two-stage reduction in
+// a fixed order): stats[0..7] = sum gx, sum gy, sum gx^2 + gy^2, max |g|, the
+// staggered sums (even nx / ny, else 0), 0, 0.  scratch: 8 * kErrBlocks
+// doubles; stats: 8 doubles of device memory.  Stream-ordered.
+inline hipError_t force_stats(const double* gx, const double* gy, int nx, int ny, double* scratch,
+                              double* stats, hipStream_t st) {
+    hipLaunchKernelGGL(k_force_stats8, dim3(kErrBlocks), dim3(kBlock), 0, st, gx, gy, nx, ny,
+                       scratch);
+    hipLaunchKernelGGL(k_reduce4<kForceMask>, dim3(1), dim3(kBlock), 0, st, scratch, kErrBlocks,
+                       stats);
+    hipLaunchKernelGGL(k_reduce4<0>, dim3(1), dim3(kBlock), 0, st, scratch + 4 * kErrBlocks,
+                       kErrBlocks, stats + 4);
+    return hipGetLastError();
+}
+
+// Warning bits of a force from its statistics (host): LBM_W_MEAN_REMOVED when
+// force_mean_shift removes a mean, LBM_W_STAGGERED_LOAD when a staggered sum
+// exceeds 1e-12 N rms (a load with a k = (pi, 0) or (0, pi) component: the
+// staggered first moment then oscillates for good and the iteration from
+// f = 0 has no steady state).
+inline int force_warnings(const double* stats, long long N) {
+    double shift[2];
+    const double n = (double)N;
+    force_mean_shift(stats, n, shift);
+    int w = (shift[0] != 0.0 || shift[1] != 0.0) ? LBM_W_MEAN_REMOVED : 0;
+    const double lim = 1e-24 * n * (0.5 * stats[2]);  // (1e-12 N rms)^2
+    if (stats[4] * stats[4] > lim || stats[5] * stats[5] > lim) w |= LBM_W_STAGGERED_LOAD;
+    return w;
+}
+
+// Mean-projected copy of the FP64 force into the lattice's arithmetic type
+// (and the FP64 copy for the polish phase); stats: the force's statistics in
+// device memory (force_stats), read by the kernel in stream order.
+inline hipError_t upload_force(const Lattice& L, const double* gx, const double* gy,
+                               const double* stats, hipStream_t st) {
     const long long N = L.N, P = L.plane;
-    if (L.prec0 == LBM_FP64) {
-        double* g = reinterpret_cast<double*>(L.mem.g);
-        if ((e = hipMemcpyAsync(g, gx, N * 8, hipMemcpyDeviceToDevice, st)) != hipSuccess) return e;
-        if ((e = hipMemcpyAsync(g + P, gy, N * 8, hipMemcpyDeviceToDevice, st)) != hipSuccess)
-            return e;
-    } else {
-        float* g = reinterpret_cast<float*>(L.mem.g);
-        hipLaunchKernelGGL(k_convert<float>, dim3(blocks_for(N)), dim3(kBlock), 0, st, gx, g, N);
-        hipLaunchKernelGGL(k_convert<float>, dim3(blocks_for(N)), dim3(kBlock), 0, st, gy, g + P,
-                           N);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (L.mem.pg) {
-            if ((e = hipMemcpyAsync(L.mem.pg, gx, N * 8, hipMemcpyDeviceToDevice, st)) != hipSuccess)
-                return e;
-            if ((e = hipMemcpyAsync(L.mem.pg + P, gy, N * 8, hipMemcpyDeviceToDevice, st)) !=
-                hipSuccess)
-                return e;
-        }
-    }
-    return hipSuccess;
+    if (L.prec0 == LBM_FP64)
+        hipLaunchKernelGGL(k_force_upload<double>, dim3(blocks_for(N)), dim3(kBlock), 0, st, gx, gy,
+                           N, P, stats, reinterpret_cast<double*>(L.mem.g), (double*)nullptr);
+    else
+        hipLaunchKernelGGL(k_force_upload<float>, dim3(blocks_for(N)), dim3(kBlock), 0, st, gx, gy,
+                           N, P, stats, reinterpret_cast<float*>(L.mem.g), L.mem.pg);
+    return hipGetLastError();
+}
+
+// The host's record of a force just uploaded (stats on the host): max |g| for
+// the half scale, and the sums that drive the neutral modes of the exact
+// trajectory from step `steps` on (a removed mean leaves a zero sum).
+inline void record_force(Lattice& L, const double* stats, long long steps) {
+    double shift[2];
+    force_mean_shift(stats, (double)L.N, shift);
+    L.gmax = stats[3] + std::max(std::fabs(shift[0]), std::fabs(shift[1]));
+    L.rebase_force(steps, shift[0] != 0.0 ? 0.0 : stats[0], shift[1] != 0.0 ? 0.0 : stats[1]);
+    L.rebase_stagger(steps, stats[4], stats[5]);
 }
 
 // Initial power-of-two scale for half storage: the steady state of a load g

@@ -31,9 +31,15 @@ struct SmallLaunch {
     double r_in;          // the solve's last residual so far (NaN: none)
     double r_switch;      // > 0: narrow storage switches to FP64 (lbm_set_polish)
     int nondec_in;        // checks in a row whose residual did not decrease
-    int pad_;
+    int guard_checks;     // divergence guard: rises in a row that stop the solve (0: off)
+    RiseGuard* guard;     // the guard's state (device memory, kept across launches)
     double* out;          // steps after the launch, last residual, outcome, nondec
 };
+
+// Clear a divergence guard in device memory (start of a solve, FP64 switch).
+static __global__ void k_guard_clear(RiseGuard* g) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) g->clear();
+}
 
 // Outcome codes in out[2].
 constexpr int kSmallConverged = 0, kSmallLimit = 1, kSmallDiverged = 2, kSmallBudget = 3,
@@ -44,11 +50,11 @@ constexpr int kSmallConverged = 0, kSmallLimit = 1, kSmallDiverged = 2, kSmallBu
 // HBM).  A step pulls f(m) from it, forms u(m) while colliding and writes f*(m)
 // to the other LDS buffer.  At a check step m the residual uses u(m) and u(m-1),
 // the latter kept per site from the step before (or read from d.u at the start
-// of a launch).  Stopping as lbm_solve_to_tol does: r <= tol or the limit at a
-// check step keeps the state of step m; a residual that is not finite ends after
-// step m + 1; the limit between checks keeps the state of the limit.  With a
-// switch threshold (narrow storage, lbm_set_polish), a check that finds the FP64
-// switch due also ends the launch after step m + 1, and the host switches.
+// of a launch).  Stopping as lbm_solve_to_tol does: a residual that is not
+// finite, r <= tol, the limit, or the divergence guard at a check step keeps
+// the state of step m; the limit between checks keeps the state of the limit.
+// With a switch threshold (narrow storage, lbm_set_polish), a check that finds
+// the FP64 switch due ends the launch after step m + 1, and the host switches.
 template <typename S, int NMAX, bool GENERAL>
 static __global__ __launch_bounds__(kSmallThreads) void k_solve_small(SmallLaunch P) {
     using C = typename Store<S>::C;
@@ -58,6 +64,7 @@ static __global__ __launch_bounds__(kSmallThreads) void k_solve_small(SmallLaunc
     __shared__ double red[3 * NW];
     __shared__ int flag;
     __shared__ double r_shared;
+    __shared__ RiseGuard guard;  // updated by thread 0 only
     const SlotDesc& d = P.d;
     const int nx = d.nx, ny = d.ny, N = nx * ny;
     const long long plane = d.plane;
@@ -91,6 +98,7 @@ static __global__ __launch_bounds__(kSmallThreads) void k_solve_small(SmallLaunc
     const long long mend = P.max_steps - P.m0 > P.budget ? P.m0 + P.budget : P.max_steps;
     double r = P.r_in;
     int nondec = P.nondec_in;
+    if (threadIdx.x == 0) guard = *P.guard;
     int outcome = kSmallBudget;
     while (true) {
         const bool check = m >= P.check && m % P.check == 0;
@@ -138,7 +146,7 @@ static __global__ __launch_bounds__(kSmallThreads) void k_solve_small(SmallLaunc
                 if (dsum != dsum || ssum != ssum || !isfinite(ssum)) rr = NAN;
                 int dec = 0, oc = kSmallBudget;
                 if (!isfinite(rr) && !(ssum == 0.0 && dsum != 0.0)) {
-                    dec = 2;
+                    dec = 1;
                     oc = kSmallDiverged;
                 } else if (rr <= P.tol) {
                     dec = 1;
@@ -146,6 +154,9 @@ static __global__ __launch_bounds__(kSmallThreads) void k_solve_small(SmallLaunc
                 } else if (m >= P.max_steps) {
                     dec = 1;
                     oc = kSmallLimit;
+                } else if (guard.update(sqrt(dsum), P.guard_checks)) {
+                    dec = 1;
+                    oc = kSmallDiverged;
                 } else if (P.r_switch > 0.0) {
                     // the switch of lbm_set_polish, after this step as between
                     // launches of the launch-per-check solve
@@ -196,6 +207,7 @@ static __global__ __launch_bounds__(kSmallThreads) void k_solve_small(SmallLaunc
         glob(P.out)[1] = r;
         glob(P.out)[2] = (double)outcome;
         glob(P.out)[3] = (double)nondec;
+        *P.guard = guard;
     }
 }
 

@@ -184,6 +184,60 @@ static __global__ __launch_bounds__(kBlock) void k_force_stats(const double* gx,
         for (int c = 0; c < 4; ++c) partial[4 * blockIdx.x + c] = v[c];
 }
 
+// Statistics of a body force given as FP64 arrays [ny][nx], stage 1: per block
+// two groups of four, (sum gx, sum gy, sum gx^2 + gy^2, max |g|_inf) into
+// partial[4 b ..] and (sum (-1)^x gx for even nx, sum (-1)^y gy for even ny,
+// 0, 0) into partial[4 (gridDim + b) ..].  The staggered sums drive the
+// undamped modes at k = (pi, 0), (0, pi) (see k_neutral_sums).
+static __global__ __launch_bounds__(kBlock) void k_force_stats8(const double* gx, const double* gy,
+                                                                int nx, int ny, double* partial) {
+    __shared__ double lds[16];
+    const long long n = (long long)nx * ny;
+    const double sx = (nx % 2 == 0) ? 1.0 : 0.0, sy = (ny % 2 == 0) ? 1.0 : 0.0;
+    double v[4] = {0.0, 0.0, 0.0, 0.0}, w[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock) {
+        const int x = (int)(i % nx), y = (int)(i / nx);
+        v[0] += gx[i];
+        v[1] += gy[i];
+        v[2] += gx[i] * gx[i] + gy[i] * gy[i];
+        v[3] = fmax(v[3], fmax(fabs(gx[i]), fabs(gy[i])));
+        w[0] += ((x & 1) ? -sx : sx) * gx[i];
+        w[1] += ((y & 1) ? -sy : sy) * gy[i];
+    }
+    block_reduce4<kForceMask>(v, lds);
+    block_reduce4<0>(w, lds);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) {
+            partial[4 * blockIdx.x + c] = v[c];
+            partial[4 * (gridDim.x + blockIdx.x) + c] = w[c];
+        }
+}
+
+// Internal copy of a body force: out = g - shift in the arithmetic type C
+// (planes [2][plane]), and optionally the FP64 copy out64 (the polish state's
+// force), with the shift of force_mean_shift taken from the device statistics
+// st (8 doubles of k_force_stats8 after stage 2).  A zero shift copies g bit
+// for bit.
+template <typename C>
+static __global__ __launch_bounds__(kBlock) void k_force_upload(const double* gx, const double* gy,
+                                                                long long n, long long plane,
+                                                                const double* st, C* out,
+                                                                double* out64) {
+#pragma clang fp contract(off)
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double shift[2];
+    force_mean_shift(st, (double)n, shift);
+    const double vx = gx[i] - shift[0], vy = gy[i] - shift[1];
+    out[i] = (C)vx;
+    out[plane + i] = (C)vy;
+    if (out64) {
+        out64[i] = vx;
+        out64[plane + i] = vy;
+    }
+}
+
 // Stage 2: one block combines the block partials in a fixed order.
 template <int MAXMASK>
 static __global__ __launch_bounds__(kBlock) void k_reduce4(const double* partial, int nparts,
@@ -235,11 +289,13 @@ static __global__ void k_set_desc(SlotDesc* p, SlotDesc v) { *p = v; }
 // (eigenvalue 1 at k = 0).  (2) The staggered first moments: for even nx,
 // J = sum_x (-1)^x m10(f(n)) obeys J(n+1) = -J(n) - sum_x (-1)^x gx for any
 // relaxation rates (streaming with c_x = +-1 flips (-1)^x), and likewise in y
-// with m01, gy: eigenvalue -1 at k = (pi, 0), (0, pi).  Neither mode is ever
-// damped, so rounding noise from narrow storage stays in them for good.  These
-// kernels measure both on the stored (post-collision) field S, whose sums
-// equal those of f(n) for the mean and J_S = J_f + G (fixed point G/2) for the
-// staggered mode, and reset them.
+// with m01, gy: eigenvalue -1 at k = (pi, 0), (0, pi), so that
+// J(n) = -G/2 + (-1)^(n - n0) (J(n0) + G/2) oscillates about -G/2 with a
+// constant amplitude.  Neither mode is ever damped, so rounding noise from
+// narrow storage stays in them for good.  These kernels measure both on the
+// stored (post-collision) field S = f*(n-1), whose sums equal those of f(n)
+// for the mean and J_S = J(n-1) + G = -J(n) for the staggered mode, and reset
+// them to the exact trajectory's values (tracked on the host).
 //
 // Stage 1: per block two groups of four sums, unscaled FP64:
 // (sum (-1)^x m10(S), sum (-1)^y m01(S), sum (-1)^x gx, sum (-1)^y gy) and
@@ -279,16 +335,18 @@ static __global__ __launch_bounds__(kBlock) void k_neutral_sums(SlotDesc d, int 
 }
 
 // The four corrections of stage 2 from the stage-1 sums (8 doubles, after the
-// second reduction) and the target means, in storage units (sc = 1 / inv_scale):
-// the staggered sums go to their fixed point G/2, the means to the target (an
-// update of eps changes either by 2 eps N).  One thread, on the device, so the
-// reset needs no host round trip; each operation rounds on its own.
+// second reduction) and the targets, in storage units (sc = 1 / inv_scale):
+// the staggered sums of the stored field go to (jx, jy) and the means to
+// (tx, ty), the values of the exact trajectory (an update of eps changes
+// either by 2 eps N).  One thread, on the device, so the reset needs no host
+// round trip; each operation rounds on its own.
 static __global__ void k_neutral_coef(const double* sums, double n, int evenx, int eveny,
-                                      double tx, double ty, double sc, double* coef) {
+                                      double tx, double ty, double jx, double jy, double sc,
+                                      double* coef) {
 #pragma clang fp contract(off)
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double ex = evenx ? (0.5 * sums[2] - sums[0]) / (2.0 * n) : 0.0;
-    const double ey = eveny ? (0.5 * sums[3] - sums[1]) / (2.0 * n) : 0.0;
+    const double ex = evenx ? (jx - sums[0]) / (2.0 * n) : 0.0;
+    const double ey = eveny ? (jy - sums[1]) / (2.0 * n) : 0.0;
     const double mx = (tx - sums[4]) / (2.0 * n);
     const double my = (ty - sums[5]) / (2.0 * n);
     coef[0] = ex * sc;

@@ -20,8 +20,11 @@ LIB_PATH = os.path.join(PKG, "liblbm.so")
 
 FP64, FP32, FP16 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16}
-STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "W_NONZERO_MEAN", -1: "E_ARG", -2: "E_MATERIAL",
+STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "W_MEAN_REMOVED", 4: "W_STAGGERED_LOAD",
+          6: "W_MEAN_REMOVED|W_STAGGERED_LOAD", -1: "E_ARG", -2: "E_MATERIAL",
           -3: "E_WORKSPACE", -4: "E_HIP", -5: "E_DIVERGED", -6: "E_STATE"}
+W_MEAN_REMOVED, W_STAGGERED_LOAD = 2, 4
+FORCE_WARNINGS = (0, 2, 4, 6)
 
 
 class LbmError(RuntimeError):
@@ -61,6 +64,7 @@ def load() -> ctypes.CDLL:
         "lbm_solve_to_tol": (i, [vp, d, ll, i, pll, pd]),
         "lbm_set_polish": (i, [vp, d]),
         "lbm_set_small_solve": (i, [vp, ll]),
+        "lbm_set_divergence_guard": (i, [vp, i]),
         "lbm_current_precision": (i, [vp]),
         "lbm_steps_done": (ll, [vp]),
         "lbm_get_displacement": (i, [vp, vp, vp]),
@@ -83,6 +87,9 @@ def load() -> ctypes.CDLL:
         "lbm_batch_remove": (i, [vp, i]),
         "lbm_batch_step": (i, [vp, ll, i]),
         "lbm_batch_residuals": (i, [vp, pd, pll]),
+        "lbm_batch_diverged": (i, [vp, pi]),
+        "lbm_batch_set_divergence_guard": (i, [vp, i]),
+        "lbm_batch_force_warnings": (i, [vp, i]),
         "lbm_batch_promote": (i, [vp, i]),
         "lbm_batch_get_displacement": (i, [vp, i, vp, vp]),
         "lbm_batch_set_tile": (i, [vp, i, i, i]),
@@ -206,13 +213,15 @@ class Solver:
         self._check(self.lib.lbm_set_rates(self.h, theta, w12, w21, w22))
 
     def set_body_force(self, gx: torch.Tensor, gy: torch.Tensor) -> int:
+        """Returns the warning bits of lbm_set_body_force (W_MEAN_REMOVED,
+        W_STAGGERED_LOAD) or 0."""
         shp = (self.ny, self.nx)
         gx = _dev_f64(gx, shp, "gx")
         gy = _dev_f64(gy, shp, "gy")
         self._keep = [gx, gy]
         return self._check(self.lib.lbm_set_body_force(self.h, ctypes.c_void_p(gx.data_ptr()),
                                                        ctypes.c_void_p(gy.data_ptr())),
-                           allow=(0, 2))
+                           allow=FORCE_WARNINGS)
 
     def reset(self):
         self._check(self.lib.lbm_reset(self.h))
@@ -238,6 +247,11 @@ class Solver:
 
     def set_polish(self, r_switch: float):
         self._check(self.lib.lbm_set_polish(self.h, float(r_switch)))
+
+    def set_divergence_guard(self, checks: int):
+        """Rises of the update norm in a row that stop solve_to_tol (0: off);
+        see lbm_set_divergence_guard."""
+        self._check(self.lib.lbm_set_divergence_guard(self.h, int(checks)))
 
     def set_small_solve(self, steps_per_launch: int):
         """Steps per launch of the one-workgroup solve of small lattices in
@@ -369,7 +383,7 @@ class Batch:
                                     ctypes.byref(slot))
         if rc == -3:
             return None
-        self._check(rc, allow=(0, 2))
+        self._check(rc)
         self.shapes[slot.value] = (ny, nx)
         self._keep[slot.value] = (gx, gy)
         return slot.value
@@ -387,6 +401,24 @@ class Batch:
         n = (ctypes.c_longlong * self.max_slots)()
         self._check(self.lib.lbm_batch_residuals(self.h, r, n))
         return list(r), list(n)
+
+    def diverged(self):
+        """Per slot: True once its residual, over the checks read by
+        residuals(), became non-finite or its update norm kept rising
+        (lbm_batch_diverged)."""
+        f = (ctypes.c_int * self.max_slots)()
+        self._check(self.lib.lbm_batch_diverged(self.h, f))
+        return [bool(v) for v in f]
+
+    def set_divergence_guard(self, checks: int):
+        self._check(self.lib.lbm_batch_set_divergence_guard(self.h, int(checks)))
+
+    def force_warnings(self, slot: int) -> int:
+        """Warning bits of a slot's force (lbm_batch_force_warnings)."""
+        rc = self.lib.lbm_batch_force_warnings(self.h, int(slot))
+        if rc < 0:
+            self._check(rc)
+        return rc
 
     def promote(self, slot: int):
         self._check(self.lib.lbm_batch_promote(self.h, int(slot)))

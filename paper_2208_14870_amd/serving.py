@@ -8,7 +8,9 @@ lattice advances in the same persistent step launches.  After each chunk of
 `chunk` steps the FP64 residual of every lattice is read; a lattice in FP32
 switches to FP64 storage once its residual reaches `r_switch` or stops
 decreasing, and retires when r <= tol: its displacement is copied to the host
-and its memory returns to the arena.  Latency = result on host - arrival.
+and its memory returns to the arena.  A lattice whose residual becomes
+non-finite or whose update norm keeps rising (the library's divergence
+guard) is retired as failed.  Latency = result on host - arrival.
 
 Each lattice steps whole chunks from its admission on, with its own promote
 and retire decisions taken only from its own residuals, so its result is
@@ -150,13 +152,15 @@ class Server:
                 g0 = time.perf_counter()
                 self.batch.step(self.chunk, check=True)
                 r, steps = self.batch.residuals()
+                diverged = self.batch.diverged()
                 gpu_time += time.perf_counter() - g0
                 done = []
                 for slot in list(self.active):
                     a = self.active[slot]
                     self.site_updates += a.case.nx * a.case.ny * self.chunk
                     rs = r[slot]
-                    if not np.isfinite(rs):
+                    # a converged residual wins over the guard (as in solve_to_tol)
+                    if diverged[slot] and not rs <= self.tol:
                         self.failed.append(a.req.rid)
                         self.batch.remove(slot)
                         del self.active[slot]

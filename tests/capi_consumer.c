@@ -5,7 +5,8 @@
  * usage: capi_consumer nx ny lambda mu precision tol max_steps check_every
  *                      force.bin displacement.bin
  * force.bin: gx then gy, FP64, [ny][nx] each (x fastest); displacement.bin
- * receives ux then uy in the same layout.  Prints one JSON line; exit status 0
+ * receives ux then uy in the same layout.  Prints one JSON line (solve status,
+ * the warning bits of lbm_set_body_force, steps, residual); exit status 0
  * on success (converged or not), 1 on a library or HIP error, 2 on bad usage. */
 #include <stdio.h>
 #include <stdlib.h>
@@ -61,9 +62,14 @@ int main(int argc, char **argv) {
         return 1;
     }
     rc = lbm_set_material(s, lam, mu);
+    int force_status = 0;
     if (rc == LBM_OK) {
         rc = lbm_set_body_force(s, d_g, d_g + n);
-        if (rc > 0) rc = LBM_OK;  /* informational (a force with a non-zero mean) */
+        /* informational bits: LBM_W_MEAN_REMOVED, LBM_W_STAGGERED_LOAD */
+        if (rc > 0) {
+            force_status = rc;
+            rc = LBM_OK;
+        }
     }
     long long steps = 0;
     double residual = 0.0;
@@ -88,7 +94,8 @@ int main(int argc, char **argv) {
         return 1;
     }
     fclose(fout);
-    printf("{\"status\": %d, \"steps\": %lld, \"residual\": %.17g}\n", status, steps, residual);
+    printf("{\"status\": %d, \"force_status\": %d, \"steps\": %lld, \"residual\": %.17g}\n",
+           status, force_status, steps, residual);
     hipFree(d_u);
     hipFree(d_g);
     hipFree(d_ws);

@@ -4,7 +4,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2208_14870_amd import problem as P
-from gpu_common import dev, host, need_gpu, omega, rel_l2, say
+from gpu_common import assert_elementwise, dev, host, need_gpu, omega, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 
@@ -40,7 +40,7 @@ def test_batch_fp64_matches_oracle():
         f = O.run(O.zero_state(c.nx, c.ny), c.gx, c.gy, omega(c.material), 40)
         ox, oy = O.displacement(f, c.gx, c.gy)
         ux, uy = (host(t) for t in b.displacement(s))
-        assert rel_l2(ux, ox, uy, oy) <= 1e-12, c.label
+        assert_elementwise((ux, uy), (ox, oy), 1e-12, c.label)
 
 
 def test_batch_residual_matches_single_solver_and_oracle():
@@ -276,7 +276,7 @@ def test_join_and_leave_mid_run():
         f = O.run(O.zero_state(case.nx, case.ny), case.gx, case.gy, omega(case.material), n)
         ox, oy = O.displacement(f, case.gx, case.gy)
         ux, uy = (host(t) for t in b.displacement(slot))
-        assert rel_l2(ux, ox, uy, oy) <= 1e-12
+        assert_elementwise((ux, uy), (ox, oy), 1e-12, "u")
 
 
 def test_promote_to_fp64():
@@ -317,3 +317,70 @@ def test_arena_admission():
     b.remove(got[0])
     assert b.add(256, 256, c.material.lame_lambda, c.material.lame_mu, dev(c.gx), dev(c.gy),
                  "fp32") is not None
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_force_projection_equals_solo(prec):
+    """A batch slot mean-projects its force on the device by the rule of
+    lbm_set_body_force: its populations equal a solo solver's given the same
+    force bit for bit, and lbm_batch_force_warnings reports the same bits."""
+    from paper_2208_14870_amd import lbm
+    c = _cases()[3]  # 128 x 40
+    gx = c.gx + 0.4 * np.sqrt(np.mean(c.gx ** 2))
+    gy = c.gy + 0.05e-3 * (-1.0) ** np.arange(c.ny)[:, None]  # a (0, pi) component
+    say(f"batch force projection {prec}")
+    b = _batch()
+    slot = b.add(c.nx, c.ny, c.material.lame_lambda, c.material.lame_mu, dev(gx), dev(gy), prec)
+    other = b.add(64, 64, c.material.lame_lambda, c.material.lame_mu,
+                  dev(np.zeros((64, 64))), dev(np.zeros((64, 64))), prec)
+    assert b.force_warnings(slot) == lbm.W_MEAN_REMOVED | lbm.W_STAGGERED_LOAD
+    assert b.force_warnings(other) == 0
+    b.step(37)
+    s = lbm.Solver(c.nx, c.ny, prec)
+    s.set_material(c.material.lame_lambda, c.material.lame_mu)
+    assert s.set_body_force(dev(gx), dev(gy)) == lbm.W_MEAN_REMOVED | lbm.W_STAGGERED_LOAD
+    s.step(37)
+    ua = [host(t) for t in b.displacement(slot)]
+    ub = [host(t) for t in s.displacement()]
+    assert all(np.array_equal(a, bb) for a, bb in zip(ua, ub))
+    if prec == "fp64":
+        px = gx - gx.mean()
+        f = O.run(O.zero_state(c.nx, c.ny), px, gy - gy.mean(), omega(c.material), 37)
+        assert_elementwise(tuple(ua), O.displacement(f, px, gy - gy.mean()), 1e-12, "u")
+    s.close()
+    b.close()
+
+
+def test_batch_divergence_flag():
+    """The batch's divergence guard: an unstable lattice (Sec. 7.3.5) is flagged
+    after its update norm kept rising over checked chunks, its neighbour is not,
+    and the neighbour's state equals a batch without the unstable lattice."""
+    from paper_2208_14870_amd import lbm
+    say("batch divergence flag")
+    bad = P.gaussian_hill_case(32, P.Material.from_young_poisson(0.082, -0.4))
+    good = _cases()[0]
+    b = _batch()
+    sb = b.add(32, 32, bad.material.lame_lambda, bad.material.lame_mu, dev(bad.gx), dev(bad.gy),
+               "fp64")
+    sg = b.add(good.nx, good.ny, good.material.lame_lambda, good.material.lame_mu,
+               dev(good.gx), dev(good.gy), "fp64")
+    ref = _batch()
+    rg = ref.add(good.nx, good.ny, good.material.lame_lambda, good.material.lame_mu,
+                 dev(good.gx), dev(good.gy), "fp64")
+    flagged_at = None
+    for chunk in range(60):
+        b.step(20, check=True)
+        ref.step(20, check=True)
+        b.residuals()
+        flags = b.diverged()
+        assert not flags[sg]
+        if flags[sb] and flagged_at is None:
+            flagged_at = (chunk + 1) * 20
+            break
+    say(f"  flagged after {flagged_at} steps")
+    assert flagged_at is not None and flagged_at <= 1200
+    ua = [host(t) for t in b.displacement(sg)]
+    ub = [host(t) for t in ref.displacement(rg)]
+    assert all(np.array_equal(a, bb) for a, bb in zip(ua, ub))
+    b.close()
+    ref.close()

@@ -11,7 +11,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2208_14870_amd import problem as P
-from gpu_common import need_gpu, say
+from gpu_common import assert_elementwise, need_gpu, say
 
 pytestmark = pytest.mark.gpu
 
@@ -39,7 +39,35 @@ def test_c_consumer_solves_to_tolerance(tmp_path, precision, tol, bar):
     ox, oy = O.displacement(f, case.gx, case.gy)
     err = np.sqrt(np.sum((u[0] - ox) ** 2 + (u[1] - oy) ** 2) / np.sum(ox ** 2 + oy ** 2))
     say(f"  C: steps {rec['steps']} r {rec['residual']:.3e} | oracle steps {n} | rel diff {err:.2e}")
-    assert rec["status"] == 0 and st == 0
+    assert rec["status"] == 0 and st == 0 and rec["force_status"] == 0
     if precision == 0:
         assert rec["steps"] == n
     assert err <= bar
+
+
+def test_c_consumer_mean_removed(tmp_path):
+    """A force with a non-zero mean: the library subtracts the FP64 mean
+    (LBM_W_MEAN_REMOVED) and solves the mean-free problem, which the oracle
+    solves from the numpy-projected force."""
+    need_gpu()
+    assert os.path.exists(EXE), "C consumer not built (run __graft_entry__.build())"
+    case = P.single_32()
+    mat = case.material
+    gx = case.gx + 0.3 * np.sqrt(np.mean(case.gx ** 2))
+    gy = case.gy - 0.1 * np.sqrt(np.mean(case.gy ** 2))
+    fin, fout = str(tmp_path / "force.bin"), str(tmp_path / "u.bin")
+    np.concatenate([gx.ravel(), gy.ravel()]).astype(np.float64).tofile(fin)
+    say("C consumer, force with a mean")
+    r = subprocess.run([EXE, "32", "32", repr(mat.lame_lambda), repr(mat.lame_mu), "0",
+                        "1e-10", "10000", "1", fin, fout],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    rec = json.loads(r.stdout.strip().splitlines()[-1])
+    assert rec["force_status"] == 2 and rec["status"] == 0
+    u = np.fromfile(fout, dtype=np.float64).reshape(2, 32, 32)
+    px, py = gx - gx.mean(), gy - gy.mean()
+    om = O.omega_vector(mat.lame_lambda, mat.lame_mu)
+    f, n, res, st = O.solve_to_tol(O.zero_state(32, 32), px, py, om, 1e-10, 10000, 1)
+    ox, oy = O.displacement(f, px, py)
+    assert st == 0 and rec["steps"] == n
+    assert_elementwise((u[0], u[1]), (ox, oy), 1e-12, "u")

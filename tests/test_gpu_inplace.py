@@ -5,7 +5,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2208_14870_amd import problem as P
-from gpu_common import dev, host, need_gpu, omega, rel_l2, say
+from gpu_common import assert_elementwise, dev, host, need_gpu, omega, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 
@@ -58,7 +58,7 @@ def test_inplace_identical_to_two_buffers(prec, nx, ny):
             np.testing.assert_array_equal(host(tb), host(ta))
     if prec == "fp64" and nx * ny <= 5000:
         fn = O.run(f0, gx, gy, omega(mat), done)
-        assert rel_l2(host(b.populations()), fn) <= 1e-12
+        assert_elementwise(host(b.populations()), fn, 1e-12, "f")
 
 
 def test_inplace_general_rates():

@@ -411,3 +411,101 @@ def test_neutral_modes_in_spectrum():
                 found.append((a, b))
                 assert np.min(np.abs(ev + 1)) < 1e-12
     assert sorted(found) == [(0, n // 2), (n // 2, 0)]
+
+
+def _staggered_load(n=16, amp=1e-3):
+    """Zero-mean load on an n x n lattice (n even) with a smooth part and a
+    k = (pi, 0) component in gx: G = sum_x (-1)^x gx = n^2 * amp * 0.2."""
+    x = np.arange(n) + 0.5
+    X, Y = np.meshgrid(x, x)
+    gx = amp * (np.sin(2 * np.pi * X / n) * np.cos(2 * np.pi * Y / n)
+                + 0.2 * (-1.0) ** np.arange(n)[None, :])
+    gy = amp * np.cos(2 * np.pi * X / n) * np.sin(2 * np.pi * Y / n)
+    return gx - gx.mean(), gy - gy.mean()
+
+
+def test_staggered_load_oscillates_for_good():
+    """A zero-mean load with a k = (pi, 0) component (G != 0) has no steady state
+    from f = 0: the staggered first moment J(n) = sum_x (-1)^x m10(f(n)) obeys
+    J(n + 1) = -J(n) - G, so from J(0) = 0 it alternates exactly between 0 and
+    -G (the closed form -G/2 + (-1)^n G/2), while every damped mode converges;
+    the residual therefore settles at a floor and the solve never converges."""
+    n = 16
+    gx, gy = _staggered_load(n)
+    px = (-1.0) ** np.arange(n)[None, :]
+    G = float(np.sum(px * gx))
+    assert abs(G) > 1e-3  # a real staggered component
+    mat = P.Material.from_shear_poisson(1.0, 0.3)
+    om = _omega(mat)
+    M = S.printed_M()
+    f = O.zero_state(n, n)
+    for step in (1, 2, 7, 40, 41, 300, 301):
+        fn = O.run(f, gx, gy, om, step)
+        J = float(np.sum(px * np.einsum("j,jyx->yx", M[0], fn)))
+        want = -0.5 * G + (-1.0) ** step * 0.5 * G
+        assert abs(J - want) <= 1e-12 * abs(G), (step, J, want)
+    _, steps, r, st = O.solve_to_tol(O.zero_state(n, n), gx, gy, om, 1e-8, 20000, 1)
+    assert st == 1 and steps == 20000
+    # the floor: u(n) - u(n-1) keeps the staggered oscillation (|J| changes by
+    # |G| every step), a fixed fraction of |u|
+    assert 1e-3 < r < 1.0
+    # without the staggered component the same problem converges
+    sx, sy = _staggered_load(n)
+    sx = sx - 0.2e-3 * (-1.0) ** np.arange(n)[None, :]
+    _, steps2, r2, st2 = O.solve_to_tol(O.zero_state(n, n), sx, sy, om, 1e-8, 20000, 1)
+    assert st2 == 0 and r2 <= 1e-8
+
+
+def test_divergence_rule_fires_on_unstable_material():
+    """Sec. 7.3.5: the Gaussian hill at nu = -0.4, E~ = 0.082 (unstable, rho ~ 1.01)
+    is stopped by the rise rule on the update norm within a few thousand steps
+    (the populations would take ~7e4 steps to overflow), at several check
+    intervals, also at coarse checks where the residual ratio has saturated
+    near 2 before its rises add up; the stable E~ = 0.3 run converges with the
+    rule on."""
+    for n, K, limit in ((48, 1, 2500), (48, 7, 2500), (32, 1, 1000), (32, 64, 1500),
+                        (32, 500, 6000)):
+        c = P.gaussian_hill_case(n, P.Material.from_young_poisson(0.082, -0.4))
+        _, steps, r, st = O.solve_to_tol(O.zero_state(n, n), c.gx, c.gy, _omega(c.material),
+                                         1e-12, 100000, K, rise_checks=8)
+        assert st == -2 and np.isfinite(r) and steps % K == 0 and steps <= limit, (n, K, steps)
+    c = P.gaussian_hill_case(32, P.Material.from_young_poisson(0.3, -0.4))
+    _, steps, r, st = O.solve_to_tol(O.zero_state(32, 32), c.gx, c.gy, _omega(c.material),
+                                     1e-10, 100000, 1, rise_checks=8)
+    assert st == 0 and r <= 1e-10
+
+
+def test_divergence_rule_ignores_decaying_oscillation():
+    """A stable solve whose update is led by a decaying complex pair: the update
+    norm (and r) dips where the pair's two terms cancel and then climbs
+    ten-fold over several checks, but never above its earlier peaks.  A rule
+    that compared against the dip would stop this solve at step 193; the
+    rule's window of 32 earlier checks does not.  (Found by a seeded sweep of
+    random stable solves.)"""
+    n = 32
+    mat = P.Material.from_young_poisson(2.5733447287342703, -0.3)
+    modes = [(-1, -1, 0.5209762924222331, 0.1464832959825571, 0.5731240586374448, 5.262281775239881),
+             (-2, 2, 0.3839972559516547, -0.07175991874001672, 1.5768124413604954, 5.901201410252297),
+             (3, 2, -0.4444125971879807, -0.2859994036120117, 3.913310535457861, 1.2228780623519049),
+             (1, 2, 0.3669982417671297, 0.9609801985527886, 4.9043925182934185, 6.140801318865113)]
+    X, Y = np.meshgrid(np.arange(n) + 0.5, np.arange(n) + 0.5)
+    gx = np.zeros((n, n))
+    gy = np.zeros((n, n))
+    for a, b, cx, cy, p0, p1 in modes:
+        gx += cx * np.cos(2 * np.pi * (a * X + b * Y) / n + p0)
+        gy += cy * np.cos(2 * np.pi * (a * X + b * Y) / n + p1)
+    gx = 1e-3 * (gx - gx.mean())
+    gy = 1e-3 * (gy - gy.mean())
+    om = _omega(mat)
+    # the residual history does climb ~3x within 8 checks after a dip near step 186
+    f = O.run(O.zero_state(n, n), gx, gy, om, 185)
+    r = []
+    for _ in range(8):
+        u0 = O.displacement(f, gx, gy)
+        f = O.run(f, gx, gy, om, 1)
+        u1 = O.displacement(f, gx, gy)
+        r.append(O.residual(u1[0], u1[1], u0[0], u0[1]))
+    assert r[-1] > 2.0 * r[0] and all(b > a for a, b in zip(r[1:], r[2:]))
+    _, steps, rr, st = O.solve_to_tol(O.zero_state(n, n), gx, gy, om, 1e-13, 4000, 1,
+                                      rise_checks=8)
+    assert st == 0 and rr <= 1e-13
