@@ -239,6 +239,23 @@ int lbm_get_stress(lbm_solver *s, double *sxx, double *syy, double *sxy);
  * grid norms of Sec. 7.1 before the dx weighting.  Blocking. */
 int lbm_error_norms(lbm_solver *s, const double *ux_ref, const double *uy_ref, double out[4]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the error
+ * norms of lbm_error_norms for displacement fields given directly (ux, uy,
+ * e.g. from lbm_get_displacement), with no solver handle.  Allocates nothing
+ * and does not wait: two kernels on `stream` (a hipStream_t, NULL = null
+ * stream) write out[4] (caller-owned FP64 device memory) = { sum |e_i|_2^2,
+ * sum |ref_i|_2^2, max |e_i|_inf, max |ref_i|_inf }, e = u - ref, the same
+ * values lbm_error_norms returns for the same fields.  The reduction's partials
+ * live in a static device array of 32 KiB per GPU (held until the process
+ * ends), shared by every call on that GPU: calls that overlap on one GPU race.
+ * Limit: nx * ny <= 2^31 (LBM_E_ARG beyond; the scratch does not grow with the
+ * lattice).  Errors: LBM_E_ARG (sizes, NULL pointers), LBM_E_HIP; messages
+ * through lbm_last_error(NULL). */
+int lbm_error_norms_noalloc(int nx, int ny, const double *ux, const double *uy,
+                            const double *ux_ref, const double *uy_ref, double *out,
+                            void *stream);
+
 /* Checkpoint / restart: the pre-collision populations f(n) as FP64 device
  * arrays [8][ny][nx] (paper order, unscaled).  set leaves the step count
  * unchanged and is blocking (it records the mean first moments of the given

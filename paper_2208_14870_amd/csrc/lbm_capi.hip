@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -25,8 +26,40 @@
 using namespace lbm;
 using namespace lbm_host;
 
+// Scratch of lbm_error_norms_noalloc: the block partials of its two-stage
+// reduction, kErrBlocks x 4 doubles (32 KiB), in a static device array so that
+// the call allocates nothing.  Each GPU holds its own copy at its own address
+// until the process ends; host code uses that address (noalloc_scratch), never
+// the array's name.  Every call on a GPU shares the GPU's copy: calls that
+// overlap on one GPU race.
+constexpr long long kNoAllocScratchDoubles = 4LL * kErrBlocks;
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
 namespace {
 thread_local std::string g_create_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's scratch, looked up once per device with
+// that device current; nullptr (and *e set) on failure.
+double* noalloc_scratch(hipError_t* e) {
+    int dev = 0;
+    if ((*e = hipGetDevice(&dev)) != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        *e = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if ((*e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = reinterpret_cast<double*>(p);
+    }
+    *e = hipSuccess;
+    return g_scratch_ptr[dev];
+}
 }  // namespace
 
 // ===========================================================================
@@ -943,6 +976,36 @@ int lbm_error_norms(lbm_solver* s, const double* ux_ref, const double* uy_ref, d
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "error_norms");
     for (int c = 0; c < 4; ++c) out[c] = s->h_result[c];
+    return LBM_OK;
+}
+
+int lbm_error_norms_noalloc(int nx, int ny, const double* ux, const double* uy,
+                            const double* ux_ref, const double* uy_ref, double* out,
+                            void* stream) {
+    if (nx < 1 || ny < 1 || (long long)nx * ny > (1LL << 31)) {
+        g_create_error = "error_norms_noalloc: need 1 <= nx, ny and nx * ny <= 2^31";
+        return LBM_E_ARG;
+    }
+    if (!ux || !uy || !ux_ref || !uy_ref || !out) {
+        g_create_error = "error_norms_noalloc: NULL argument";
+        return LBM_E_ARG;
+    }
+    hipError_t e;
+    double* part = noalloc_scratch(&e);
+    if (!part) {
+        g_create_error = std::string("error_norms_noalloc: scratch address: ") + hipGetErrorString(e);
+        return LBM_E_HIP;
+    }
+    // the kernels of lbm_error_norms: every block writes its four partials, so
+    // nothing in the scratch needs clearing
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_err_norms, dim3(kErrBlocks), dim3(kBlock), 0, st, ux, uy, ux_ref, uy_ref,
+                       (long long)nx * ny, part);
+    hipLaunchKernelGGL(k_reduce4<kErrMask>, dim3(1), dim3(kBlock), 0, st, part, kErrBlocks, out);
+    if ((e = hipGetLastError()) != hipSuccess) {
+        g_create_error = std::string("error_norms_noalloc: ") + hipGetErrorString(e);
+        return LBM_E_HIP;
+    }
     return LBM_OK;
 }
 

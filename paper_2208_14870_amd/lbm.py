@@ -70,6 +70,7 @@ def load() -> ctypes.CDLL:
         "lbm_get_displacement": (i, [vp, vp, vp]),
         "lbm_get_stress": (i, [vp, vp, vp, vp]),
         "lbm_error_norms": (i, [vp, vp, vp, pd]),
+        "lbm_error_norms_noalloc": (i, [i, i, vp, vp, vp, vp, vp, vp]),
         "lbm_get_populations": (i, [vp, vp]),
         "lbm_set_populations": (i, [vp, vp]),
         "lbm_set_tile": (i, [vp, i, i, i]),
@@ -128,6 +129,23 @@ def _aligned_buffer(nbytes: int, device) -> Tuple[torch.Tensor, int]:
     buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
     addr = buf.data_ptr()
     return buf, (addr + 255) // 256 * 256
+
+
+def error_norms_noalloc(ux: torch.Tensor, uy: torch.Tensor, ux_ref: torch.Tensor,
+                       uy_ref: torch.Tensor, out: torch.Tensor) -> None:
+    """lbm_error_norms_noalloc: out (4 float64 on the device) = sum |e|^2,
+    sum |ref|^2, max |e|, max |ref| with e = u - ref, enqueued on the current
+    stream; allocates nothing."""
+    lib = load()
+    ny, nx = ux.shape
+    fields = [_dev_f64(t, (ny, nx), n) for t, n in
+              ((ux, "ux"), (uy, "uy"), (ux_ref, "ux_ref"), (uy_ref, "uy_ref"))]
+    out = _dev_f64(out, (4,), "out")
+    rc = lib.lbm_error_norms_noalloc(nx, ny, *[ctypes.c_void_p(t.data_ptr()) for t in fields],
+                                     ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.c_void_p(_stream_ptr(out.device)))
+    if rc != 0:
+        raise LbmError(rc, lib.lbm_last_error(None).decode())
 
 
 class Solver:
