@@ -161,8 +161,12 @@ __device__ __forceinline__ void bared_u(const C f[8], C gx, C gy, C& ux, C& uy) 
     uy = ((f[1] - f[3]) + (p + q)) + C(0.5) * gy;
 }
 
+// The collision with the force given as its half and quarter (hgx = gx/2,
+// qgx = hgx/2, formed by the caller with exactly these two products, so that
+// kernels that keep them per site across steps round as collide() does).
 template <typename C, bool GENERAL>
-__device__ __forceinline__ void collide(C f[8], C gx, C gy, const Coef<C>& k, C& ux, C& uy) {
+__device__ __forceinline__ void collide_h(C f[8], C hgx, C hgy, C qgx, C qgy, const Coef<C>& k,
+                                          C& ux, C& uy) {
 #pragma clang fp contract(off)
     const C p = f[4] - f[6];   // f5 - f7
     const C q = f[5] - f[7];   // f6 - f8
@@ -175,17 +179,16 @@ __device__ __forceinline__ void collide(C f[8], C gx, C gy, const Coef<C>& k, C&
     const C m10 = (f[0] - f[2]) + m12;
     const C m01 = (f[1] - f[3]) + m21;
     const C m11 = sac - sbd;
-    const C ms = (h13 + h24) + C(2) * (sac + sbd);
+    const C ms = fmac(C(2), sac + sbd, h13 + h24);  // (h13 + h24) + 2 (sac + sbd): 2x is exact
     const C md = h13 - h24;
-    const C hgx = C(0.5) * gx, hgy = C(0.5) * gy;
     ux = m10 + hgx;
     uy = m01 + hgy;
     if constexpr (!GENERAL) {
         const C dd = k.cd * md;
         const C a = fmac(k.cs, ms, dd);
         const C b = fmac(k.cs, ms, -dd);
-        const C ex = fmac(k.hth, ux, C(0.5) * hgx);
-        const C ey = fmac(k.hth, uy, C(0.5) * hgy);
+        const C ex = fmac(k.hth, ux, qgx);
+        const C ey = fmac(k.hth, uy, qgy);
         const C s = k.c11 * m11;
         const C t1 = k.tq * (ux + uy);
         const C t2 = k.tq * (ux - uy);
@@ -218,6 +221,13 @@ __device__ __forceinline__ void collide(C f[8], C gx, C gy, const Coef<C>& k, C&
         f[6] = C(0.25) * ((s22 + s11) - (s12 + s21));
         f[7] = C(0.25) * ((s22 - s11) + (s12 - s21));
     }
+}
+
+template <typename C, bool GENERAL>
+__device__ __forceinline__ void collide(C f[8], C gx, C gy, const Coef<C>& k, C& ux, C& uy) {
+#pragma clang fp contract(off)
+    const C hgx = C(0.5) * gx, hgy = C(0.5) * gy;
+    collide_h<C, GENERAL>(f, hgx, hgy, C(0.5) * hgx, C(0.5) * hgy, k, ux, uy);
 }
 
 // ---------------------------------------------------------------------------

@@ -2,6 +2,8 @@
 // register wavefront, bit-identical to single steps.
 #pragma once
 
+#include <type_traits>
+
 #include "lbm_common.hpp"
 
 namespace lbm {
@@ -101,39 +103,95 @@ __device__ __forceinline__ S* at_u32(S* base, unsigned i) {
     return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(S));
 }
 
+// The slots of a thread in the region of the fused kernel, fixed for the whole
+// launch: slot a is region site e = threadIdx.x + a NT, at column i and row j of
+// the region, and lvl = min(i, RW-1-i, j, RH-1-j) is its distance to the
+// region's edge.  Step s (1-based) advances the region shrunk by s-1 sites on
+// every side, i.e. the slots with lvl >= s-1, and the last step's tile is
+// lvl >= R.  Spare slots (e >= RN) have lvl = -1 and the coordinates of the
+// region's last site (a valid address).  Computed once per launch, so that no
+// step divides or compares coordinates again, and packed into one register per
+// slot (i in bits 0-7, j in bits 8-15, lvl + 1 from bit 16), so that "lvl >= m"
+// is one unsigned compare against a constant.
+template <int TH, int NS, int NT>
+struct SlotGeo {
+    static constexpr int R = NS - 1;
+    static constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
+    static constexpr int NM = (RN + NT - 1) / NT;
+    static_assert(RW < 256 && RH < 256, "region coordinates must fit 8 bits");
+    unsigned p[NM];
+    __device__ __forceinline__ void init() {
+#pragma unroll
+        for (int a = 0; a < NM; ++a) {
+            const int e0 = (int)threadIdx.x + a * NT;
+            const int e = min(e0, RN - 1);
+            const int ii = e % RW, jj = e / RW;
+            const int lv = e0 < RN ? min(min(ii, RW - 1 - ii), min(jj, RH - 1 - jj)) : -1;
+            p[a] = (unsigned)ii | ((unsigned)jj << 8) | ((unsigned)(lv + 1) << 16);
+        }
+    }
+    __device__ __forceinline__ int i(int a) const { return (int)(p[a] & 0xffu); }
+    __device__ __forceinline__ int j(int a) const { return (int)((p[a] >> 8) & 0xffu); }
+    // lvl >= m (m >= 0)
+    __device__ __forceinline__ bool active(int a, int m) const {
+        return p[a] >= ((unsigned)(m + 1) << 16);
+    }
+};
+
 // Step 1 of the fused kernel for one tile, in two parts.  stepN_load issues
 // the loads of the ring region from the stored field (periodic coordinates):
-// the 8 incoming populations and the force of every slot (the last slot's
-// spare lanes re-read the region's last site), so that all loads are in
-// flight before the first use.  stepN_collide1 scales the force, collides and
-// writes the post-collision populations to LDS.
+// the 8 incoming populations and the force of every slot, so that all loads
+// are in flight before the first use.  A tile whose region and its pull halo
+// lie inside the lattice (almost every tile of a large lattice) forms its
+// addresses without the periodic wrap; the others wrap every coordinate.
+// stepN_collide1 scales the force, collides and writes the post-collision
+// populations to LDS.
 template <typename S, int TH, int NS, int NT = kBlock>
 __device__ __forceinline__ void stepN_load(const S* __restrict__ src,
                                            const typename Store<S>::C* __restrict__ g,
                                            long long plane, int nx, int ny, int x0, int y0,
+                                           const SlotGeo<TH, NS, NT>& geo,
                                            typename Store<S>::C f[][8],
                                            typename Store<S>::C gx[], typename Store<S>::C gy[]) {
-    constexpr int R = NS - 1;
-    constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
-    constexpr int NM = (RN + NT - 1) / NT;
+    using Geo = SlotGeo<TH, NS, NT>;
+    constexpr int R = Geo::R, NM = Geo::NM;
     using C = typename Store<S>::C;
     const S* pq[8];  // wave-uniform plane bases
 #pragma unroll
     for (int q = 0; q < 8; ++q) pq[q] = src + q * plane;
     const C* g1 = g + plane;
+    const unsigned w = (unsigned)nx;
+    const bool interior = x0 - R >= 1 && x0 + kTW + R <= nx - 1 && y0 - R >= 1 &&
+                          y0 + TH + R <= ny - 1;  // wave-uniform
+    if (interior) {
+        const unsigned base = (unsigned)(y0 - R) * w + (unsigned)(x0 - R);
+#pragma unroll
+        for (int a = 0; a < NM; ++a) {
+            const unsigned c = base + (unsigned)geo.j(a) * w + (unsigned)geo.i(a);
+            const unsigned cm = c - w, cp = c + w;
+            // pull: f_q(x) = f*_q(x - c_q), velocity table order
+            f[a][0] = Store<S>::ld(at_u32(pq[0], c - 1));
+            f[a][1] = Store<S>::ld(at_u32(pq[1], cm));
+            f[a][2] = Store<S>::ld(at_u32(pq[2], c + 1));
+            f[a][3] = Store<S>::ld(at_u32(pq[3], cp));
+            f[a][4] = Store<S>::ld(at_u32(pq[4], cm - 1));
+            f[a][5] = Store<S>::ld(at_u32(pq[5], cm + 1));
+            f[a][6] = Store<S>::ld(at_u32(pq[6], cp + 1));
+            f[a][7] = Store<S>::ld(at_u32(pq[7], cp - 1));
+            gx[a] = *glob(at_u32(g, c));
+            gy[a] = *glob(at_u32(g1, c));
+        }
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < NM; ++a) {
-        const int e = min((int)threadIdx.x + a * NT, RN - 1);
-        const int i = e % RW, j = e / RW;
-        const unsigned x = (unsigned)wrap_coord(x0 - R + i, nx);
-        const unsigned y = (unsigned)wrap_coord(y0 - R + j, ny);
-        const unsigned w = (unsigned)nx;
+        const unsigned x = (unsigned)wrap_coord(x0 - R + geo.i(a), nx);
+        const unsigned y = (unsigned)wrap_coord(y0 - R + geo.j(a), ny);
         const unsigned xm = (x == 0) ? w - 1 : x - 1;
         const unsigned xp = (x == w - 1) ? 0 : x + 1;
         const unsigned ym = (y == 0) ? (unsigned)ny - 1 : y - 1;
         const unsigned yp = (y == (unsigned)ny - 1) ? 0 : y + 1;
         const unsigned r0 = y * w, rm = ym * w, rp = yp * w;
-        // pull: f_q(x) = f*_q(x - c_q), velocity table order
         f[a][0] = Store<S>::ld(at_u32(pq[0], r0 + xm));
         f[a][1] = Store<S>::ld(at_u32(pq[1], rm + x));
         f[a][2] = Store<S>::ld(at_u32(pq[2], r0 + xp));
@@ -147,24 +205,50 @@ __device__ __forceinline__ void stepN_load(const S* __restrict__ src,
     }
 }
 
-// up[a] receives u of the step (for a check launch of two steps, u(n - 1)).
+// Whether the tile kernel keeps the quarter force of every slot in registers
+// (FP32 / FP64: LDS, not registers, limits their workgroups per CU) or forms it
+// at each collision (half storage: four more registers per thread would cost a
+// workgroup per CU).  Either way it is the same product of the half force.
+template <typename S>
+constexpr bool kKeepQuarter = !std::is_same<S, __half>::value;
+
+// The quarter force of slot a for a collision.
+template <typename S, typename C>
+__device__ __forceinline__ C quarter(const C hq[][2], const C qg[][2], int a, int c) {
+#pragma clang fp contract(off)
+    if constexpr (kKeepQuarter<S>) return qg[a][c];
+    else return C(0.5) * hq[a][c];
+}
+
+// Scales the force of every slot and keeps its half (hg) and, where registers
+// allow, its quarter (qg): the products collide() forms, taken once per tile.
+// Collides and writes step 1 to LDS; up[a] receives u of the step (for a check
+// launch of two steps, u(n - 1)).
 template <typename S, int TH, int NS, int NT = kBlock>
 __device__ __forceinline__ void stepN_collide1(typename Store<S>::C f[][8],
                                                const Coef<typename Store<S>::C>& k, S* lds,
-                                               typename Store<S>::C gx[],
-                                               typename Store<S>::C gy[],
+                                               const SlotGeo<TH, NS, NT>& geo,
+                                               const typename Store<S>::C gx[],
+                                               const typename Store<S>::C gy[],
+                                               typename Store<S>::C hg[][2],
+                                               typename Store<S>::C qg[][2],
                                                typename Store<S>::C up[][2]) {
+#pragma clang fp contract(off)
     using C = typename Store<S>::C;
-    constexpr int R = NS - 1;
-    constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
-    constexpr int NM = (RN + NT - 1) / NT;
+    using Geo = SlotGeo<TH, NS, NT>;
+    constexpr int RW = Geo::RW, RN = Geo::RN, NM = Geo::NM;
 #pragma unroll
     for (int a = 0; a < NM; ++a) {
         const int e = (int)threadIdx.x + a * NT;
-        gx[a] *= k.gscale;
-        gy[a] *= k.gscale;
-        collide<C, false>(f[a], gx[a], gy[a], k, up[a][0], up[a][1]);
-        if (e < RN) lds_write<S, RW, RN>(lds, e, true, f[a]);
+        hg[a][0] = C(0.5) * (gx[a] * k.gscale);
+        hg[a][1] = C(0.5) * (gy[a] * k.gscale);
+        if constexpr (kKeepQuarter<S>) {
+            qg[a][0] = C(0.5) * hg[a][0];
+            qg[a][1] = C(0.5) * hg[a][1];
+        }
+        collide_h<C, false>(f[a], hg[a][0], hg[a][1], quarter<S>(hg, qg, a, 0),
+                            quarter<S>(hg, qg, a, 1), k, up[a][0], up[a][1]);
+        if (geo.active(a, 0)) lds_write<S, RW, RN>(lds, e, true, f[a]);
     }
 }
 
@@ -219,14 +303,14 @@ __device__ __forceinline__ void block_reduce3n(double& a, double& b, double& m, 
 template <typename S, int TH, int NS, int NT = kBlock, int MODE = kPlain>
 __device__ __forceinline__ void stepN_rest(S* __restrict__ dst, long long plane, int nx, int ny,
                                            int x0, int y0, const Coef<typename Store<S>::C>& k,
-                                           S* lds, const typename Store<S>::C gx[],
-                                           const typename Store<S>::C gy[],
+                                           S* lds, const SlotGeo<TH, NS, NT>& geo,
+                                           const typename Store<S>::C hg[][2],
+                                           const typename Store<S>::C qg[][2],
                                            typename Store<S>::C up[][2], double* u,
                                            double inv_scale, double* partial, double* red) {
     using C = typename Store<S>::C;
-    constexpr int R = NS - 1;
-    constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
-    constexpr int NM = (RN + NT - 1) / NT;
+    using Geo = SlotGeo<TH, NS, NT>;
+    constexpr int R = Geo::R, RW = Geo::RW, RN = Geo::RN, NM = Geo::NM;
     S* pq[8];  // wave-uniform plane bases
 #pragma unroll
     for (int q = 0; q < 8; ++q) pq[q] = dst + q * plane;
@@ -236,11 +320,11 @@ __device__ __forceinline__ void stepN_rest(S* __restrict__ dst, long long plane,
 #pragma unroll
         for (int a = 0; a < NM; ++a) {
             const int e = (int)threadIdx.x + a * NT;
-            const int i = e % RW, j = e / RW;
-            if (e < RN && i >= m && i < RW - m && j >= m && j < RH - m) {
+            if (geo.active(a, m)) {
                 C f[8], ux, uy;
                 lds_read<S, RW, RN>(lds, e, even, f);
-                collide<C, false>(f, gx[a], gy[a], k, ux, uy);
+                collide_h<C, false>(f, hg[a][0], hg[a][1], quarter<S>(hg, qg, a, 0),
+                                    quarter<S>(hg, qg, a, 1), k, ux, uy);
                 lds_write<S, RW, RN>(lds, e, !even, f);
                 if (MODE == kCheck && m == R - 1) {
                     up[a][0] = ux;
@@ -255,12 +339,12 @@ __device__ __forceinline__ void stepN_rest(S* __restrict__ dst, long long plane,
 #pragma unroll
     for (int a = 0; a < NM; ++a) {
         const int e = (int)threadIdx.x + a * NT;
-        const int i = e % RW, j = e / RW;
-        const int x = x0 + i - R, y = y0 + j - R;
-        if (e < RN && i >= R && i < R + kTW && j >= R && j < R + TH && x < nx && y < ny) {
+        const int x = x0 + geo.i(a) - R, y = y0 + geo.j(a) - R;
+        if (geo.active(a, R) && x < nx && y < ny) {  // the tile, inside the lattice
             C f[8], ux, uy;
             lds_read<S, RW, RN>(lds, e, last_even, f);
-            collide<C, false>(f, gx[a], gy[a], k, ux, uy);
+            collide_h<C, false>(f, hg[a][0], hg[a][1], quarter<S>(hg, qg, a, 0),
+                                quarter<S>(hg, qg, a, 1), k, ux, uy);
             const unsigned sidx = (unsigned)y * (unsigned)nx + (unsigned)x;
 #pragma unroll
             for (int q = 0; q < 8; ++q) Store<S>::st(at_u32(pq[q], sidx), f[q]);
@@ -296,11 +380,12 @@ __device__ __forceinline__ void stepN_rest(S* __restrict__ dst, long long plane,
 template <typename S, int TH, int NS, int NT = kBlock, int MODE = kPlain>
 static __global__ __launch_bounds__(NT) void k_stepN(StepLaunch L) {
     using C = typename Store<S>::C;
-    constexpr int R = NS - 1;  // ring width of the first step
-    constexpr int RW = kTW + 2 * R, RH = TH + 2 * R, RN = RW * RH;
-    constexpr int NM = (RN + NT - 1) / NT;  // ring sites per thread
+    using Geo = SlotGeo<TH, NS, NT>;
+    constexpr int RN = Geo::RN, NM = Geo::NM;
     __shared__ S lds[8 * RN];
     __shared__ double red[3 * (NT / kWave)];
+    Geo geo;
+    geo.init();
     int last, stride, it;
     xcd_slice(L.range, last, stride, it);
     for (; it < last; it += stride) {
@@ -310,14 +395,14 @@ static __global__ __launch_bounds__(NT) void k_stepN(StepLaunch L) {
         Coef<C> k;
         k.load(d);
         const int x0 = item.tx * kTW, y0 = item.ty * TH;
-        C f[NM][8], gx[NM], gy[NM], up[NM][2];
+        C f[NM][8], gx[NM], gy[NM], hg[NM][2], qg[kKeepQuarter<S> ? NM : 1][2], up[NM][2];
         stepN_load<S, TH, NS, NT>(reinterpret_cast<const S*>(d.buf[sel]),
                                   reinterpret_cast<const C*>(d.g), d.plane, d.nx, d.ny, x0, y0,
-                                  f, gx, gy);
-        stepN_collide1<S, TH, NS, NT>(f, k, lds, gx, gy, up);
+                                  geo, f, gx, gy);
+        stepN_collide1<S, TH, NS, NT>(f, k, lds, geo, gx, gy, hg, qg, up);
         __syncthreads();
         stepN_rest<S, TH, NS, NT, MODE>(reinterpret_cast<S*>(d.buf[sel ^ 1]), d.plane, d.nx, d.ny,
-                                        x0, y0, k, lds, gx, gy, up, d.u, d.inv_scale,
+                                        x0, y0, k, lds, geo, hg, qg, up, d.u, d.inv_scale,
                                         L.partial + 3 * it, red);
     }
 }
