@@ -292,6 +292,14 @@ int lbm_set_tile(lbm_solver *s, int bx_log2, int rows_per_thread, int blocks_per
  * LBM_E_ARG (k outside 1..8), LBM_E_STATE (k != 1 in place). */
 int lbm_set_time_blocking(lbm_solver *s, int steps_per_launch);
 
+/* Tile height of the LDS tile kernel (the tile is 64 columns wide): rows in
+ * {8, 12, 16, 24}, where a kernel exists for the storage type and steps per
+ * launch (FP64 8; FP32 16 and 24 at any depth, 8 up to four steps; FP16 16 at
+ * any depth, 12 up to four); 0 restores the default of lbm_set_time_blocking.
+ * A later change of the steps per launch keeps the choice where a kernel
+ * exists for it.  Results do not depend on it.  Errors: LBM_E_ARG. */
+int lbm_set_tile_rows(lbm_solver *s, int rows);
+
 /* Fused kernel kinds (both give identical results). */
 enum lbm_fused_kernel {
     /* LDS tile: a workgroup advances a 64-wide tile plus a ring of k-1 sites

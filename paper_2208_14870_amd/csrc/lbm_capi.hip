@@ -543,12 +543,25 @@ int lbm_set_time_blocking(lbm_solver* s, int steps_per_launch) {
         return s->fail(LBM_E_STATE, "set_time_blocking: in-place streaming runs one step per launch");
     Lattice& L = s->L;
     L.tb = steps_per_launch;
-    L.th = fused_th(L.prec, steps_per_launch, L.N);
+    L.th = fused_th(L.prec, steps_per_launch, L.N, L.th_user);
     if (s->fused_auto)
         L.wave_hs = default_fused_wave_rows(L.prec, steps_per_launch, L.nx, L.ny, s->cus,
                                             !L.tile_fits());
     else if (steps_per_launch > 4)
         L.wave_hs = 0;  // the wavefront runs 2..4 steps
+    return s->sync_desc();
+}
+
+int lbm_set_tile_rows(lbm_solver* s, int rows) {
+    if (!s) return LBM_E_ARG;
+    Lattice& L = s->L;
+    if (rows != 0 && !(rows == 8 || rows == 12 || rows == 16 || rows == 24))
+        return s->fail(LBM_E_ARG, "set_tile_rows: rows must be 0, 8, 12, 16 or 24");
+    if (rows != 0 && L.fused() && L.wave_hs == 0 && !stepN_supported(L.prec, L.tb, rows))
+        return s->fail(LBM_E_ARG, "set_tile_rows: no tile kernel of that height for this "
+                                  "storage type and steps per launch");
+    L.th_user = rows;
+    L.th = fused_th(L.prec, L.tb, L.N, rows);
     return s->sync_desc();
 }
 

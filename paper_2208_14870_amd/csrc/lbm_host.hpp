@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "lbm.h"
 #include "lbm_device.hpp"
@@ -84,6 +85,10 @@ inline hipError_t launch_step_l(bool general, int vy, unsigned grid, hipStream_t
         hipLaunchKernelGGL((k_step<S, MODE, false, 3, LAY>), dim3(grid), dim3(kBlock), 0, st, L);
     } else if (vy == 4) {
         hipLaunchKernelGGL((k_step<S, MODE, false, 4, LAY>), dim3(grid), dim3(kBlock), 0, st, L);
+    } else if constexpr (std::is_same<S, float>::value && LAY == kLayPull) {
+        // the work list of the 24-row FP32 tile (single steps between its launches)
+        if (vy != 6) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_step<S, MODE, false, 6, LAY>), dim3(grid), dim3(kBlock), 0, st, L);
     } else {
         return hipErrorInvalidValue;  // rows per thread outside 1..4
     }
@@ -131,13 +136,27 @@ inline hipError_t launch_check_state(int prec, int vy, int layout, unsigned grid
     return launch_check_state_s<__half>(vy, layout, grid, st, L);
 }
 
+// Whether launch_stepN has a kernel for ns steps on tiles of th rows: every
+// tile height runs 2..4 steps, and the heights used for deeper blocking (FP64
+// 8, FP32 16 and 24, FP16 16) run 2..8, so a remainder of a launch sequence
+// can run as one shorter fused launch.
+inline bool stepN_supported(int prec, int ns, int th) {
+    if (ns < 2 || ns > 8) return false;
+    if (prec == LBM_FP64) return th == 8;
+    if (prec == LBM_FP32) return th == 16 || th == 24 || (th == 8 && ns <= 4);
+    return th == 16 || (th == 12 && ns <= 4);
+}
+
 // Shapes of the fused LDS tile kernel (tile 64 x TH, NT threads) per storage
 // type and steps per launch, measured on MI355X.  FP64: 8 rows with 512
 // threads (1024^2, five steps: 106 against 98 GLUPS with 256).  Up to four
 // steps: FP32 8 rows with 512 threads up to 2^21 sites and 16 rows with 256
 // threads above, FP16 12 rows.  Five to eight steps: FP32 and FP16 16 rows
 // with 512 threads (two workgroups of 75 KB LDS per CU at eight steps in FP32).
-inline int fused_th(int prec, int ns, long long sites) {
+// A tile height chosen by the caller (`rows`, lbm_set_tile_rows) is taken when
+// a kernel exists for it at `ns` steps.
+inline int fused_th(int prec, int ns, long long sites, int rows = 0) {
+    if (rows > 0 && stepN_supported(prec, ns, rows)) return rows;
     if (prec == LBM_FP64) return 8;
     if (prec == LBM_FP32) return (ns <= 4 && sites <= (1LL << 21)) ? 8 : 16;
     return ns <= 4 ? 12 : 16;
@@ -146,19 +165,8 @@ inline int fused_th(int prec, int ns, long long sites) {
 // Threads per workgroup of the fused LDS tile kernel (as launch_stepN runs it).
 inline int fused_nt(int prec, int ns, int th) {
     if (prec == LBM_FP64) return 512;
-    if (prec == LBM_FP32) return (th == 8 || ns > 4) ? 512 : 256;
+    if (prec == LBM_FP32) return (th == 8 || th == 24 || ns > 4) ? 512 : 256;
     return th == 16 ? 512 : 256;
-}
-
-// Whether launch_stepN has a kernel for ns steps on tiles of th rows: every
-// tile height runs 2..4 steps, and the heights used for deeper blocking (FP64
-// 8, FP32 and FP16 16) run 2..8, so a remainder of a launch sequence can run
-// as one shorter fused launch.
-inline bool stepN_supported(int prec, int ns, int th) {
-    if (ns < 2 || ns > 8) return false;
-    if (prec == LBM_FP64) return th == 8;
-    if (prec == LBM_FP32) return th == 16 || (th == 8 && ns <= 4);
-    return th == 16 || (th == 12 && ns <= 4);
 }
 
 template <typename S, int TH, int NT, int NS, int NSMAX>
@@ -188,6 +196,8 @@ inline hipError_t launch_stepN(int prec, int ns, int th, unsigned grid, hipStrea
         ok = launch_stepN_ns<float, 16, 256, 2, 4>(ns, check, grid, st, L);
     else if (prec == LBM_FP32 && th == 16)
         ok = launch_stepN_ns<float, 16, 512, 5, 8>(ns, check, grid, st, L);
+    else if (prec == LBM_FP32 && th == 24)
+        ok = launch_stepN_ns<float, 24, 512, 2, 8>(ns, check, grid, st, L);
     else if (prec == LBM_FP16 && th == 12)
         ok = launch_stepN_ns<__half, 12, 256, 2, 4>(ns, check, grid, st, L);
     else if (prec == LBM_FP16 && th == 16)
@@ -432,6 +442,7 @@ struct Lattice {
     int bx_log2 = 6, vy = 1;
     int tb = 4;       // plain steps per launch (2..8: fused multi-step kernel)
     int th = 16;      // tile height of the fused LDS kernel (fused_th)
+    int th_user = 0;  // tile height chosen by the caller (0: the default)
     int wave_hs = 0;  // > 0: fused launches use the register wavefront, segments of wave_hs rows
     int cur = 0;      // buffer with the state at flip 0
     bool inplace = false;  // one buffer, in-place streaming (layout alternates per step)

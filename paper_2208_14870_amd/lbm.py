@@ -77,6 +77,7 @@ def load() -> ctypes.CDLL:
         "lbm_debug_stream_only": (i, [vp, ll]),
         "lbm_set_time_blocking": (i, [vp, i]),
         "lbm_set_fused_kernel": (i, [vp, i, i]),
+        "lbm_set_tile_rows": (i, [vp, i]),
         "lbm_get_launch_config": (i, [vp, pi]),
         "lbm_workspace_bytes_inplace": (sz, [i, i, i]),
         "lbm_create_inplace": (i, [i, i, i, vp, sz, vp, ctypes.POINTER(vp)]),
@@ -299,6 +300,10 @@ class Solver:
         self._check(self.lib.lbm_get_launch_config(self.h, out))
         kind = {0: "tile", 1: "wavefront"}.get(out[1], "single")
         return {"steps_per_launch": out[0], "kernel": kind, "rows": out[2], "threads": out[3]}
+
+    def set_tile_rows(self, rows: int):
+        """Tile height of the LDS tile kernel (0: default); see lbm_set_tile_rows."""
+        self._check(self.lib.lbm_set_tile_rows(self.h, int(rows)))
 
     def set_fused_kernel(self, kind: str, segment_rows: int = 256):
         """kind "tile" (LDS tile kernel) or "wavefront" (register wavefront with

@@ -397,6 +397,51 @@ def test_time_blocking_identical_to_single_steps(prec, nx, ny, steps):
         assert_elementwise(res[2][0], fn, 1e-12, "f")
 
 
+@pytest.mark.parametrize("nx,ny,steps", [(3, 5, 9), (65, 17, 11), (200, 70, 13), (130, 49, 17)])
+def test_tile_rows_24_identical_to_single_steps(nx, ny, steps):
+    """The 24-row FP32 tile (lbm_set_tile_rows) at two to eight steps per launch:
+    populations bit-identical to single steps, with the remainder steps (six
+    rows per thread on the same work list) and the fused residual check of
+    solve_to_tol between its launches."""
+    say(f"tile rows 24 fp32 {nx}x{ny} steps {steps}")
+    mat = P.Material.from_shear_poisson(0.9, 0.3)
+    f0, gx, gy = _rand_state(nx, ny, 11 + nx)
+    res = {}
+    for tb in range(1, 9):
+        s = _solver(nx, ny, "fp32")
+        s.set_material(mat.lame_lambda, mat.lame_mu)
+        s.set_body_force(dev(gx), dev(gy))
+        s.set_populations(dev(f0))
+        s.set_time_blocking(tb)
+        if tb > 1:
+            s.set_fused_kernel("tile", 256)
+            s.set_tile_rows(24)
+            cfg = s.launch_config()
+            assert cfg["rows"] == 24 and cfg["kernel"] == "tile", cfg
+        s.step(steps)
+        a = host(s.populations())
+        n, r, st = s.solve_to_tol(0.0, 11, 5)
+        res[tb] = (a, host(s.populations()), n, r)
+        s.close()
+    for tb in range(2, 9):
+        np.testing.assert_array_equal(res[tb][0], res[1][0], err_msg=f"{tb} steps per launch")
+        np.testing.assert_array_equal(res[tb][1], res[1][1], err_msg=f"{tb} steps per launch")
+        assert res[tb][2] == res[1][2] and res[tb][3] == pytest.approx(res[1][3], rel=1e-12)
+
+
+def test_tile_rows_argument_errors():
+    from paper_2208_14870_amd import lbm
+    s = _solver(64, 64, "fp64")
+    s.set_time_blocking(5)
+    with pytest.raises(lbm.LbmError):
+        s.set_tile_rows(24)  # no FP64 kernel of that height
+    with pytest.raises(lbm.LbmError):
+        s.set_tile_rows(20)
+    s.set_tile_rows(0)
+    assert s.launch_config()["rows"] == 8
+    s.close()
+
+
 @pytest.mark.parametrize("prec,nx,ny,steps,bpc", [
     ("fp32", 1024, 1024, 12, 1), ("fp32", 1024, 1024, 9, 2), ("fp32", 1000, 998, 11, 3),
     ("fp64", 300, 200, 10, 1), ("fp64", 130, 9, 7, 2), ("fp16", 130, 90, 8, 1),
