@@ -12,11 +12,18 @@ the configuration.  `value` is whole-job MLUPS (site updates per second).
 
 Also reported on the same JSON line:
   roofline      -- dominant kernel of the headline run (the fused tile
-                   kernel, several steps per launch): algorithmic bytes (72 B
-                   per FP32 site update x sites x steps per launch) / average
-                   launch duration from HIP events on the library's stream,
-                   against 8 TB/s, plus the HBM bytes per launch that the
-                   committed rocprofv3 counter summary measured;
+                   kernel, several steps per launch).  A launch moves each
+                   site's populations and force through HBM once, whatever
+                   the number of fused steps: its minimum bytes are 72 B per
+                   site (FP32: 8 populations read and written, 2 force values
+                   read).  achieved = minimum bytes per launch / average launch
+                   duration (HIP events on the library's stream), frac =
+                   achieved / 8 TB/s; traffic (and traffic_frac) = the HBM bytes
+                   per launch of the committed rocprofv3 counters; valu_frac =
+                   the committed VALU instruction count x 64 lanes / duration /
+                   the chip's VALU issue rate; effective_gbs = the one-step byte
+                   model (72 B per site-update x steps per launch), which passes
+                   8 TB/s because the populations cross HBM once per launch;
   fp64          -- the same workload with FP64 storage;
   large_8192    -- 8192 x 8192 FP64 / FP32 / scaled-FP16 step throughput (the
                    working set exceeds the 256 MB last-level cache) and the
@@ -40,6 +47,10 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_SITE = {"fp64": 144, "fp32": 72, "fp16": 40}  # 8 pops in + 8 out + 2 force
+# VALU issue rate of MI355X in lane-instructions per second: 256 compute units x
+# 4 SIMDs, each issuing a wave64 VALU instruction over 4 cycles on 16 lanes, at
+# 2.4 GHz (packed FP32 is not used)
+PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
 TRAFFIC_SOURCES = ("lbm_common.hpp", "lbm_fused.hpp")  # the headers that define the tile kernel
@@ -60,12 +71,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel=None):
-    """HBM bytes per launch of the headline kernel from the committed counter
-    summary (FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy), or None when the
-    kernel's code changed since the counters were taken or the profiled
-    kernel (template arguments included) is not `kernel`."""
-    path = os.path.join(ROOT, "profiles", "k_stepN_fp32_1024_traffic.json")
+def measured_counters(name, kernel=None):
+    """The committed counter record profiles/<name>.json (HBM bytes per launch
+    from FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy, VALU instructions per
+    launch), or None when the kernel's code changed since the counters were
+    taken or the profiled kernel (template arguments included) is not
+    `kernel`."""
+    path = os.path.join(ROOT, "profiles", name + ".json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
@@ -74,7 +86,38 @@ def measured_traffic(kernel=None):
         return None
     if kernel is not None and kernel not in rec.get("kernel", ""):
         return None
-    return rec["traffic_bytes_per_launch"]
+    return rec
+
+
+def roofline(prec, sites, avg_launch_us, steps_per_launch, kernel, counters=None, note=""):
+    """Roofline fields of one fused launch over `sites` sites (see the module
+    docstring): minimum HBM bytes per launch against 8 TB/s, and the committed
+    counters' traffic and VALU issue against their ceilings."""
+    t = avg_launch_us * 1e-6
+    min_bytes = BYTES_PER_SITE[prec] * sites
+    achieved = min_bytes / t / 1e9
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "traffic_frac": None,
+           "valu_frac": None, "min_bytes_per_launch": min_bytes,
+           "site_updates_per_launch": sites * steps_per_launch,
+           "effective_gbs": round(BYTES_PER_SITE[prec] * sites * steps_per_launch / t / 1e9, 1),
+           "avg_launch_us": round(avg_launch_us, 3), "steps_per_launch": steps_per_launch,
+           "kernel": kernel}
+    rec = measured_counters(counters, kernel.split(" (")[0]) if counters else None
+    if rec:
+        tr = rec.get("traffic_bytes_per_launch")
+        if tr:
+            out["traffic"] = round(tr)
+            out["traffic_frac"] = round(tr / t / (PEAK_HBM_GBS * 1e9), 4)
+            out["traffic_over_min"] = round(tr / min_bytes, 3)
+        valu = rec.get("valu_insts_per_launch")
+        if valu:
+            out["valu_frac"] = round(64 * valu / t / PEAK_VALU_LANE_OPS, 4)
+            out["valu_lane_insts_per_update"] = round(64 * valu / (sites * steps_per_launch), 2)
+        out["counters"] = "profiles/" + counters + ".json"
+    if note:
+        out["note"] = note
+    return out
 
 
 def calib_copy():
@@ -299,10 +342,15 @@ def large_lattice(steps=10000, warm=200, precs=("fp64", "fp32", "fp16"), tb=0):
         del ux, uy
         s.close()
         del s
-        gbs = BYTES_PER_SITE[prec] * sites / (us * 1e-6) / 1e9
+        tbl = cfg["steps_per_launch"]
+        launches = steps // tbl + (1 if steps % tbl else 0)
+        ctype = {"fp64": "double", "fp32": "float", "fp16": "__half"}[prec]
         out[prec] = {"mlups": round(sites / us, 1), "us_per_step": round(us, 2),
-                     "gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4),
-                     "launch_config": cfg}
+                     "launch_config": cfg,
+                     "roofline": roofline(prec, sites, us * steps / launches, tbl,
+                                          kernel_label(cfg, ctype, sites),
+                                          f"k_stepN_{prec}_8192_counters"
+                                          if cfg["kernel"] == "tile" else None)}
     rx, ry = u.get("fp64", (None, None))
     den = float(torch.sum(rx ** 2) + torch.sum(ry ** 2)) if rx is not None else 0.0
     for prec in (p for p in ("fp32", "fp16") if p in u and rx is not None):
@@ -380,10 +428,21 @@ def batch_run(prec: str, nlat: int = 512, steps: int = 2000, chunk: int = 100):
     n = steps // chunk * chunk
     us = 1e3 * e0.elapsed_time(e1) / n
     b.close()
-    gbs = BYTES_PER_SITE[prec] * sites / (us * 1e-6) / 1e9
+    # population passes per chunk: fused launches of shape[3] steps (the last
+    # carrying the residual check); approximate for the check's own split
+    tb = max(1, int(shape[3])) if len(shape) > 3 else 1
+    passes = math.ceil(chunk / tb)
+    min_bytes = BYTES_PER_SITE[prec] * sites
+    achieved = min_bytes * passes / chunk / (us * 1e-6) / 1e9
     return {"lattices": nlat, "sites": sites, "steps": n, "mlups": sites * n / wall / 1e6,
-            "us_per_step": round(us, 2), "gbs": round(gbs, 1),
-            "frac": round(gbs / PEAK_HBM_GBS, 4), "tile": list(shape)}
+            "us_per_step": round(us, 2), "tile": list(shape),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                         "min_bytes_per_pass": min_bytes, "passes_per_chunk": passes,
+                         "effective_gbs": round(BYTES_PER_SITE[prec] * sites / (us * 1e-6) / 1e9, 1),
+                         "note": f"{passes} population passes per {chunk}-step chunk "
+                                 f"({tb} steps per fused launch); minimum bytes per pass = "
+                                 f"{BYTES_PER_SITE[prec]} B per site"}}
 
 
 def batch_solves(prec: str, nlat: int = 512, tol: float = 1e-6, chunk: int = 200,
@@ -407,16 +466,18 @@ def batch_solves(prec: str, nlat: int = 512, tol: float = 1e-6, chunk: int = 200
     return st, res
 
 
-def serving_run(rate: float = 2000.0, window: float = 1.0, budget: float = 20.0):
+def serving_run(rate: float = 2000.0, window: float = 1.0, budget: float = 20.0,
+                policy: str = "fifo"):
     """Poisson arrivals (seed 5), sides log-uniform 64..2048, 8-mode loads, tol 1e-8,
-    FP32 storage with FP64 polish, admission by arena footprint."""
+    FP32 storage with FP64 polish, admission by arena footprint in the order of
+    `policy` (arrival order, or highest response ratio next)."""
     import torch
     from paper_2208_14870_amd import problem as P
     from paper_2208_14870_amd.serving import Server
     reqs = P.request_stream(rate, window, seed=5)
     free, _ = torch.cuda.mem_get_info()
     arena = min(64 << 30, int(free * 0.5))
-    srv = Server(arena, max_slots=4096, chunk=200, tol=1e-8, r_switch=1e-6)
+    srv = Server(arena, max_slots=4096, chunk=200, tol=1e-8, r_switch=1e-6, policy=policy)
     st = srv.run(reqs, window, budget)
     # steps to tolerance grow like n^2 (the slowest mode relaxes at ~mu (2 pi/n)^2
     # per step): c = median of steps / n^2 over the completed requests.  This errs
@@ -438,8 +499,9 @@ def serving_legs():
     (steps to tolerance grow like n^2), with n = 64 * 32^U, U ~ U[0, 1), so
     E[n^4] = 64^4 (32^4 - 1) / (4 ln 32); capacity = GLUPS while busy / (c E[n^4]).
     The completion rate of the overloaded run would overstate it, since that
-    run completes the small requests first."""
-    log("serving: Poisson 2000 req/s, sides 64..2048, tol 1e-8")
+    run completes the small requests first.  Each run is made with admission
+    in arrival order and with highest response ratio next, at the same rates."""
+    log("serving: Poisson 2000 req/s, sides 64..2048, tol 1e-8 (arrival order)")
     sv = serving_run()
     e_n4 = 64.0 ** 4 * (32.0 ** 4 - 1.0) / (4.0 * math.log(32.0))
     if sv.get("steps_per_n2") and sv["mlups_while_busy"] > 0:
@@ -447,12 +509,16 @@ def serving_legs():
     else:
         capacity = sv["solves_per_s"]
     sustain = max(0.05, 0.8 * capacity)
-    log(f"serving at 0.8x the work-based capacity ({sustain:.2f} req/s)")
+    log("serving: Poisson 2000 req/s (highest response ratio next)")
+    sh = serving_run(policy="hrrn")
+    log(f"serving at 0.8x the work-based capacity ({sustain:.2f} req/s), both policies")
     ss = serving_run(rate=sustain, window=15.0, budget=45.0)
-    ss["capacity_req_s"] = capacity
-    ss["capacity_model"] = ("GLUPS while busy / (c E[n^4]), c = median steps / n^2 of the "
-                            "completed requests of the overloaded run")
-    return sv, ss
+    ssh = serving_run(rate=sustain, window=15.0, budget=45.0, policy="hrrn")
+    for rec in (ss, ssh):
+        rec["capacity_req_s"] = capacity
+        rec["capacity_model"] = ("GLUPS while busy / (c E[n^4]), c = median steps / n^2 of "
+                                 "the completed requests of the overloaded run")
+    return sv, ss, sh, ssh
 
 
 def cpu_model() -> str:
@@ -527,8 +593,9 @@ def main():
         print(json.dumps({"small_32": small_32()}), flush=True)
         return
     if args.serving_only:
-        sv, ss = serving_legs()
-        print(json.dumps({"serving": sv, "serving_sustained": ss}), flush=True)
+        sv, ss, sh, ssh = serving_legs()
+        print(json.dumps({"serving": sv, "serving_sustained": ss, "serving_hrrn": sh,
+                          "serving_sustained_hrrn": ssh}), flush=True)
         return
     if args.batch_only:
         if args.calib_copy:
@@ -556,8 +623,6 @@ def main():
         res = run_workload(solvers, args.steps, args.chunk)
         updates = nsites * args.chunk * args.steps * len(solvers)
         res["mlups"] = updates / res["wall_s"] / 1e6
-        # algorithmic bytes per site-update x site-updates, over the plain-step time
-        res["kernel_gbs"] = BYTES_PER_SITE[prec] * nsites / (res["plain_us_per_step"] * 1e-6) / 1e9
         u = [s.displacement() for s, _ in solvers]
         for s, _ in solvers:
             s.close()
@@ -595,27 +660,18 @@ def main():
                                f"residual + displacement + error norms every {args.chunk}",
                    "lattice": [1024, 1024], "cases": len(cases), "chunk": args.chunk,
                    "storage": "fp32", "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(r32["kernel_gbs"], 1),
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(r32["kernel_gbs"] / PEAK_HBM_GBS, 4),
-                     "traffic": measured_traffic(
-                         kernel_label(r32["launch_config"], "float", 1024 * 1024).split(" (")[0]),
-                     "kernel": kernel_label(r32["launch_config"], "float", 1024 * 1024),
-                     "avg_launch_us": round(r32["plain_kernel_avg_us"], 3),
-                     "steps_per_launch": r32["steps_per_launch"],
-                     "note": "the fused kernel moves the populations through HBM once per "
-                             f"{r32['steps_per_launch']} steps, so frac can pass 1; "
-                             "1024^2 (~72 MB) also fits the 256 MB last-level cache; the "
-                             "HBM-resident figures are under large_8192"},
+        "roofline": roofline("fp32", nsites, r32["plain_kernel_avg_us"], r32["steps_per_launch"],
+                             kernel_label(r32["launch_config"], "float", nsites),
+                             "k_stepN_fp32_1024_counters",
+                             note="1024^2 FP32 (~72 MB of populations and force) fits the "
+                                  "256 MB last-level cache: frac is against HBM's peak, the "
+                                  "bytes need not come from HBM; the HBM-resident figures "
+                                  "are under large_8192"),
         "fp32_last_residual": r32["last"][0][0],
         "fp32_rel_l2_vs_manufactured": [round(x[1], 6) for x in r32["last"]],
         "fp32_rel_linf_vs_manufactured": [round(x[2], 6) for x in r32["last"]],
         "fp32_residual_history_case0": [float("%.4g" % r) for r in r32["history"]],
     }
-    tr = out["roofline"]["traffic"]
-    if tr:
-        # measured HBM bytes per launch over the same launch duration
-        out["roofline"]["measured_hbm_gbs"] = round(tr / (r32["plain_kernel_avg_us"] * 1e-6) / 1e9, 1)
     if args.calib_copy:
         calib_copy()
     if not args.no_extras:
@@ -625,10 +681,10 @@ def main():
                   for (a, c), (b, d) in zip(u32, u64))
         den = sum(float(torch.sum(b ** 2) + torch.sum(d ** 2)) for (b, d) in u64)
         out["fp64"] = {"mlups": round(r64["mlups"], 1),
-                       "kernel_gbs": round(r64["kernel_gbs"], 1),
-                       "frac": round(r64["kernel_gbs"] / PEAK_HBM_GBS, 4),
-                       "avg_launch_us": round(r64["plain_kernel_avg_us"], 3),
-                       "kernel": kernel_label(r64["launch_config"], "double", 1024 * 1024)}
+                       "roofline": roofline("fp64", nsites, r64["plain_kernel_avg_us"],
+                                            r64["steps_per_launch"],
+                                            kernel_label(r64["launch_config"], "double", nsites),
+                                            "k_stepN_fp64_1024_counters")}
         out["fp32_speedup_over_fp64"] = round(r32["mlups"] / r64["mlups"], 3)
         out["fp32_rel_l2_vs_fp64"] = math.sqrt(num / den)
         log("8192x8192 random load: FP64 / FP32 / FP16, 200 + 10000 steps")
@@ -663,7 +719,8 @@ def main():
             "fp32": dict({k: s32[k] for k in keys}, **err_vs_fp64(res32)),
             "fp32_polish_at_1e-5": dict({k: sp[k] for k in keys}, **err_vs_fp64(resp)),
             "fp64": {k: s64[k] for k in keys}}
-        out["serving"], out["serving_sustained"] = serving_legs()
+        (out["serving"], out["serving_sustained"], out["serving_hrrn"],
+         out["serving_sustained_hrrn"]) = serving_legs()
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
         log("CPU oracle baseline, one thread")

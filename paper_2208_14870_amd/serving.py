@@ -12,10 +12,18 @@ and its memory returns to the arena.  A lattice whose residual becomes
 non-finite or whose update norm keeps rising (the library's divergence
 guard) is retired as failed.  Latency = result on host - arrival.
 
+Admission order (`policy`): "fifo" takes waiting requests in arrival order,
+backfilling smaller ones that fit when the next does not; "hrrn" (highest
+response ratio next) takes them in decreasing (wait + S) / S, where S is the
+request's predicted service time: the site-updates its solve needs (steps of
+its slowest smooth mode to reach the tolerance, times n^2) over the measured
+update rate.  Small solves go first, as in shortest-job-first, and a waiting
+request's ratio grows with its wait, so a large one is not starved.
+
 Each lattice steps whole chunks from its admission on, with its own promote
 and retire decisions taken only from its own residuals, so its result is
 the same alone and in any mix (the per-site arithmetic and the per-lattice
-reduction order do not depend on the other lattices).
+reduction order do not depend on the other lattices), whatever the policy.
 """
 from __future__ import annotations
 
@@ -24,11 +32,42 @@ import time
 from collections import deque
 from typing import Dict, List, Optional
 
+import math
+
 import numpy as np
 import torch
 
-from . import lbm
-from .problem import Case, Request
+from . import lbm, stability
+from .problem import Case, Material, Request
+
+
+def predicted_work(n: int, lame_lambda: float, lame_mu: float, tol: float) -> float:
+    """Site-updates an n x n solve from f = 0 needs to reach the residual tol:
+    the steps of the slowest smooth mode, the shear mode at the lowest
+    wavenumber 2 pi / n (stability.predicted_steps of its |eigenvalue|), times
+    n^2.  An estimate: the load's other modes decay faster."""
+    A = stability.collision_operator(lame_lambda, lame_mu)
+    k = 2.0 * math.pi / n
+    rho = max(float(np.max(np.abs(np.linalg.eigvals(stability.amplification(A, k, 0.0))))),
+              float(np.max(np.abs(np.linalg.eigvals(stability.amplification(A, 0.0, k))))))
+    steps = stability.predicted_steps(rho, tol)
+    return float(max(steps, 1)) * n * n
+
+
+def admission_order(waiting, now: float, rate: float, policy: str):
+    """The order in which waiting requests are offered a slot: `waiting` is a
+    list of (request, predicted site-updates); "fifo" keeps arrival order,
+    "hrrn" sorts by decreasing response ratio (now - t_arrival + S) / S with
+    S = work / rate (seconds of GPU time), ties in arrival order."""
+    if policy == "fifo":
+        return sorted(waiting, key=lambda rw: (rw[0].t_arrival, rw[0].rid))
+    if policy != "hrrn":
+        raise ValueError(f"unknown admission policy {policy!r}")
+
+    def ratio(rw):
+        svc = rw[1] / rate
+        return (now - rw[0].t_arrival + svc) / svc
+    return sorted(waiting, key=lambda rw: (-ratio(rw), rw[0].t_arrival, rw[0].rid))
 
 
 @dataclasses.dataclass
@@ -64,7 +103,7 @@ class Server:
     def __init__(self, arena_bytes: int, max_slots: int = 1024, chunk: int = 200,
                  tol: float = 1e-8, r_switch: float = 1e-6, precision: str = "fp32",
                  polish: bool = True, max_steps: int = 10 ** 8, keep_results: bool = False,
-                 tile: Optional[tuple] = None):
+                 tile: Optional[tuple] = None, policy: str = "fifo"):
         self.batch = lbm.Batch(max_slots, arena_bytes)
         if tile is not None:
             self.batch.set_tile(*tile)
@@ -79,6 +118,9 @@ class Server:
         self.results: List[Result] = []
         self.failed: List[int] = []
         self.site_updates = 0
+        admission_order([], 0.0, 1.0, policy)  # rejects an unknown policy
+        self.policy = policy
+        self.work: Dict[int, float] = {}  # predicted site-updates per request id
 
     def footprint(self, n: int) -> int:
         return lbm.Batch.slot_bytes(n, n, self.precision, self.polish)
@@ -130,8 +172,18 @@ class Server:
         while True:
             t = now()
             while pending and pending[0].t_arrival <= t:
-                queue.append(pending.popleft())
-            # admission: arrival order, backfilling smaller requests that fit
+                req = pending.popleft()
+                if self.policy != "fifo":
+                    mat = cases[req.rid].material if cases is not None else \
+                        Material.from_shear_poisson(1.0, req.nu)
+                    self.work[req.rid] = predicted_work(req.n, mat.lame_lambda, mat.lame_mu,
+                                                        self.tol)
+                queue.append(req)
+            # admission in the policy's order, backfilling requests that fit
+            if self.policy != "fifo" and queue:
+                rate = self.site_updates / gpu_time if gpu_time > 0 else 2e11
+                queue = deque(r for r, _ in admission_order(
+                    [(r, self.work[r.rid]) for r in queue], t, rate, self.policy))
             skipped = deque()
             _, _, largest = self.batch.info()
             while queue:
@@ -198,6 +250,7 @@ class Server:
             "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
             "gpu_busy_s": gpu_time,
+            "policy": self.policy,
             "mlups_while_busy": self.site_updates / gpu_time / 1e6 if gpu_time > 0 else 0.0,
         }
 

@@ -29,4 +29,7 @@ def test_headline_bench_line(monkeypatch, capsys):
     assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == bench.PEAK_HBM_GBS
     assert rf["achieved"] > 0 and abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-3
     assert rf["steps_per_launch"] >= 1 and rf["avg_launch_us"] > 0
-    assert "traffic" in rf
+    assert "traffic" in rf and "traffic_frac" in rf and "valu_frac" in rf
+    # a fraction of a real ceiling: the launch's own minimum bytes over its duration
+    assert rf["min_bytes_per_launch"] == 72 * 1024 * 1024 and 0 < rf["frac"] <= 1.0
+    assert rf["effective_gbs"] == pytest.approx(rf["achieved"] * rf["steps_per_launch"], rel=1e-3)

@@ -23,11 +23,14 @@ def _server(arena=1 << 30, **kw):
     return Server(arena, max_slots=64, chunk=100, tol=1e-8, keep_results=True, **kw)
 
 
-def test_serving_completes_and_alone_equals_mix():
-    say("serving mix of 10 + 3 alone")
+@pytest.mark.parametrize("policy", ["fifo", "hrrn"])
+def test_serving_completes_and_alone_equals_mix(policy):
+    """Every request completes, and each result equals the same request served
+    alone, whatever the admission order."""
+    say(f"serving mix of 10 + 3 alone ({policy})")
     reqs = _requests()
     cases = {r.rid: r.case() for r in reqs}
-    srv = _server()
+    srv = _server(policy=policy)
     stats = srv.run(reqs, admit_window_s=10.0, wall_budget_s=60.0, cases=cases)
     srv.close()
     assert stats["completed"] == len(reqs) and stats["backlog"] == 0 and stats["failed"] == 0
@@ -63,13 +66,14 @@ def test_serving_result_matches_oracle():
     assert err <= 1e-6
 
 
-def test_serving_admission_respects_footprint():
+@pytest.mark.parametrize("policy", ["fifo", "hrrn"])
+def test_serving_admission_respects_footprint(policy):
     """An arena that holds only a few lattices at once still serves everything."""
-    say("serving small arena")
+    say(f"serving small arena ({policy})")
     from paper_2208_14870_amd import lbm
     reqs = _requests()
     per = lbm.Batch.slot_bytes(144, 144, "fp32", True)
-    srv = _server(arena=3 * per + (8 << 20))
+    srv = _server(arena=3 * per + (8 << 20), policy=policy)
     stats = srv.run(reqs, 10.0, 60.0, cases={r.rid: r.case() for r in reqs})
     srv.close()
     assert stats["completed"] == len(reqs)
@@ -79,9 +83,9 @@ def test_serving_admission_respects_footprint():
 
 def test_serving_retires_a_diverging_request():
     """A request whose material is linearly unstable (Sec. 7.3.5: nu = -0.4,
-    E~ = 0.082, Gaussian-hill load) grows until its residual is no longer
-    finite; the server then retires it as failed and frees its slot, while the
-    requests beside it finish exactly as they do alone."""
+    E~ = 0.082, Gaussian-hill load) grows until the batch's divergence guard
+    flags it; the server then retires it as failed and frees its slot, while
+    the requests beside it finish exactly as they do alone."""
     say("serving with one diverging request")
     reqs = [P.Request(0, 0.0, 64, 0.3, 77), P.Request(1, 0.0, 48, 0.0, 0),
             P.Request(2, 0.0, 72, 0.2, 78)]
