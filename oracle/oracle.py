@@ -15,6 +15,10 @@ numpy formula that cites the passage it follows:
 * ``stress``          -- Eq. compute_bared + Table "solution" (lattice units)
 * ``solve_to_tol``    -- pseudo-time stepping until ||u(n)-u(n-1)||/||u(n)|| <= tol
 * ``error_norms``     -- grid norms of Sec. 7.1 (L2 with dx^2 weight, Linf)
+* ``leading_error_constants`` -- C1..C5, D1..D3 of Eq. leadingCoefficients (App. B)
+* ``fourth_order_rates`` -- tau_12 = tau_21 of App. C and tau_22 from C1 = 0
+* ``corrected_force``  -- Eqs. force_correction_x/y (improved scheme, Sec. 4)
+* ``error_estimates``  -- R1, R2 of Eq. rss_estimate
 
 State layout: ``f[q, y, x]`` float64, q = 0..7 for populations 1..8 of the
 one-index table of Sec. 5, x fastest.
@@ -250,3 +254,141 @@ def error_norms(ux, uy, ux_ref, uy_ref, dx: float = 1.0) -> dict:
         "rel_linf": linf / ref_l2 if ref_l2 > 0 else float("nan"),
         "rel_l2_plain": np.sqrt(e2 / r2) if r2 > 0 else float("nan"),
     }
+
+
+# ---------------------------------------------------------------------------
+# leading-order error, improved scheme and fourth-order rates (Sec. 4, App. B, C)
+# ---------------------------------------------------------------------------
+
+def young_poisson(lame_lambda: float, lame_mu: float):
+    """Dimensionless Young's modulus and Poisson ratio of the 2D relations
+    (Eq. material_relations): K = lambda + mu, E = 4 K mu / (K + mu),
+    nu = (K - mu) / (K + mu)."""
+    K = lame_lambda + lame_mu
+    return 4.0 * K * lame_mu / (K + lame_mu), (K - lame_mu) / (K + lame_mu)
+
+
+def tau_of(omega: float) -> float:
+    """Eq. relaxation_rate: tau = 1/omega - 1/2."""
+    return 1.0 / omega - 0.5
+
+
+def leading_error_constants(young: float, nu: float, theta: float = THETA, tau12: float = 0.5,
+                            tau21: float = 0.5, tau22: float = 0.5) -> dict:
+    """C1..C5 and D1..D3 of the body-force term r_x^(4) of the leading-order
+    error equation (Eqs. ux_order2 / leadingCoefficients) from the expressions
+    of App. B, with the second-order relaxation times replaced by (E, nu).
+
+    Four readings, each fixed by the exact one-mode response of the scheme
+    (the quartic part of the logarithm of its slow 2 x 2 block and the
+    quadratic part of its effective forcing, both to 1e-12 relative for theta
+    in (0, 1), tau_12 != tau_21 and nu < 0):
+      1. sign: the printed constants are the negatives of the coefficients in
+         Eq. ux_order2, so every constant below carries a leading minus;
+      2. D1: its tau_12 term has the denominator (1 - theta^2)(1 - nu^2)
+         (printed with (1 - nu^2)^2);
+      3. D2: its tau_21 term has the denominator (1 - theta^2)(1 - nu^2)
+         (printed with (1 - nu^2)^2);
+      4. C2: its E^3 term has the denominator 8 theta (1 - theta^2)(1 - nu^2)^3
+         (printed without theta).
+    The x row; the y row follows with tau_12 and tau_21 exchanged."""
+    E, v, th = float(young), float(nu), float(theta)
+    t12, t21, t22 = float(tau12), float(tau21), float(tau22)
+    a = 1.0 - th * th
+    b = 1.0 - v * v
+    q = th * th * (1.0 + v) + v - 2.0 * th - 1.0   # a factor shared by several terms
+    C1 = ((v * v - 2.0 * th * v + 1.0) / (a * b ** 3) * E ** 3
+          + th * (v - th) * t12 / (a * b * b) * E * E
+          + (-1.0 + th * th + 12.0 * th * (th - v) * t12 * t22) / (12.0 * a * b) * E)
+    C2 = (((1.0 - v) ** 3 + 4.0 * th * (v ** 3 - v * v + 3.0 * v + 1.0)
+           + th * th * (5.0 * v ** 3 - 15.0 * v * v - v - 5.0)) / (8.0 * th * a * b ** 3) * E ** 3
+          + (2.0 * th * ((1.0 - v) * v + th * th * (1.0 + v) - th * (1.0 + v * v)) * t12
+             + (1.0 - th) * (1.0 - v) * (1.0 + 2.0 * th - v - th * th * (1.0 + v)) * t21)
+          / (-4.0 * th * a * b * b) * E * E
+          + ((2.0 * th * th - 3.0 * th + 1.0) * (1.0 + 3.0 * th * (1.0 - v) - 5.0 * v)
+             + 24.0 * th * (th - v) * t12 * t22) / (24.0 * a * b) * E)
+    C3 = (((1.0 - v) ** 2 * (3.0 + v) + 4.0 * th * (-v ** 3 + 3.0 * v * v + v + 1.0)
+           - th * th * (5.0 * v ** 3 - 3.0 * v * v + 7.0 * v + 7.0)) / (8.0 * th * a * b ** 3) * E ** 3
+          + (-2.0 * (1.0 - th) * th * (v - 2.0 * th - 1.0) * (1.0 - v) * t12
+             - ((1.0 + th) * (1.0 - v) ** 2 + th ** 3 * (1.0 + v) ** 2
+                + th * th * (v * v - 2.0 * v - 3.0)) * t21) / (4.0 * th * a * b * b) * E * E
+          + ((1.0 - th) * (1.0 - v - th * (1.0 + v) - 2.0 * th * th * (2.0 + v))
+             - 4.0 * a * (1.0 - v) * t12 * t22 + 4.0 * q * t21 * t22) / (8.0 * a * b) * E
+          + th * t22 / 4.0)
+    C4 = ((16.0 * th * v + (1.0 - v) ** 2 * (3.0 + v)
+           - th * th * (v ** 3 + 9.0 * v * v - 5.0 * v + 11.0)) / (8.0 * th * a * b ** 3) * E ** 3
+          + (a * (1.0 - v) * (th * v + v + th - 1.0) * t12 - 2.0 * th * q * t21)
+          / (4.0 * th * a * b * b) * E * E
+          + (a * (2.0 * (2.0 - v) - 3.0 * th * (5.0 + v)) - 12.0 * a * (1.0 - v) * t12 * t22
+             + 12.0 * q * t21 * t22) / (24.0 * a * b) * E
+          + th * t22 / 4.0)
+    C5 = (E ** 3 / (8.0 * th * (1.0 + v) ** 3) - (1.0 - th) * t12 / (4.0 * th * (1.0 + v) ** 2) * E * E
+          - (3.0 * th - 2.0) / (24.0 * (1.0 + v)) * E)
+    D1 = ((v * v - 2.0 * th * v + 1.0) / (a * b * b) * E * E + th * (v - th) * t12 / (a * b) * E
+          - 0.25)
+    D2 = (((1.0 - v) ** 2 + 8.0 * th * v - th * th * (5.0 * v * v - 2.0 * v + 5.0))
+          / (4.0 * th * a * b * b) * E * E - q * t21 / (2.0 * a * b) * E - th / 2.0)
+    D3 = E * E / (4.0 * th * (1.0 + v) ** 2) + t12 / (2.0 * (1.0 + v)) * E - th / 4.0
+    printed = {"C1": C1, "C2": C2, "C3": C3, "C4": C4, "C5": C5, "D1": D1, "D2": D2, "D3": D3}
+    return {k: -val for k, val in printed.items()}
+
+
+def material_error_constants(lame_lambda: float, lame_mu: float, theta: float = THETA,
+                             w12: float = 1.0, w21: float = 1.0, w22: float = 1.0):
+    """(x-row constants, y-row constants) for a material and rates."""
+    E, v = young_poisson(lame_lambda, lame_mu)
+    t12, t21, t22 = tau_of(w12), tau_of(w21), tau_of(w22)
+    return (leading_error_constants(E, v, theta, t12, t21, t22),
+            leading_error_constants(E, v, theta, t21, t12, t22))
+
+
+def error_estimates(consts: dict):
+    """Eq. rss_estimate: R1 = |C|_2 (error left after the force correction),
+    R2 = |(C, D)|_2 (without it)."""
+    c = sum(consts["C%d" % i] ** 2 for i in range(1, 6))
+    d = sum(consts["D%d" % i] ** 2 for i in range(1, 4))
+    return float(np.sqrt(c)), float(np.sqrt(c + d))
+
+
+def fourth_order_rates(lame_lambda: float, lame_mu: float, theta: float = THETA):
+    """(omega_12, omega_21, omega_22) of the fourth-order special case (Sec.
+    7.3.3): tau_12 = tau_21 from App. C, which makes C5 = 0; tau_22 as the
+    root of C1 = 0, which is affine in tau_22 (App. C's printed tau_22 does
+    not make C1 vanish; reading adopted: the condition C1 = 0 it is meant to
+    satisfy)."""
+    E, v = young_poisson(lame_lambda, lame_mu)
+    t11 = lame_mu / theta
+    t12 = (2.0 - 3.0 * theta + 12.0 * theta * t11 * t11) / (12.0 * (1.0 - theta) * t11)
+    c0 = leading_error_constants(E, v, theta, t12, t12, 0.0)["C1"]
+    c1 = leading_error_constants(E, v, theta, t12, t12, 1.0)["C1"]
+    t22 = -c0 / (c1 - c0)
+    return 1.0 / (t12 + 0.5), 1.0 / (t12 + 0.5), 1.0 / (t22 + 0.5)
+
+
+def central_second_derivatives(g) -> np.ndarray:
+    """Second-order central differences on the periodic lattice (unit
+    spacing): planes (d_xx, d_xy, d_yy) of a field [ny][nx]."""
+    g = _f64(g)
+    xp, xm = np.roll(g, -1, axis=1), np.roll(g, 1, axis=1)
+    yp, ym = np.roll(g, -1, axis=0), np.roll(g, 1, axis=0)
+    dxx = xp - 2.0 * g + xm
+    dyy = yp - 2.0 * g + ym
+    pp = np.roll(xp, -1, axis=0)   # g(x+1, y+1)
+    mp_ = np.roll(xm, -1, axis=0)  # g(x-1, y+1)
+    pm = np.roll(xp, 1, axis=0)    # g(x+1, y-1)
+    mm = np.roll(xm, 1, axis=0)    # g(x-1, y-1)
+    dxy = ((pp - mp_) - (pm - mm)) * 0.25
+    return np.stack([dxx, dxy, dyy])
+
+
+def corrected_force(gx, gy, d2gx, d2gy, consts_x: dict, consts_y: dict):
+    """Eqs. force_correction_x/y in lattice units:
+    gx' = gx - (D1 d_xx gx + D2 d_xy gy + D3 d_yy gx),
+    gy' = gy - (D3' d_xx gy + D2' d_xy gx + D1' d_yy gy),
+    with d2gx = (d_xx gx, d_xy gx, d_yy gx), d2gy likewise, the x-row
+    constants D and the y-row constants D' (equal when tau_12 = tau_21)."""
+    cx, cy = consts_x, consts_y
+    gx, gy = _f64(gx), _f64(gy)
+    hx = gx - ((cx["D1"] * d2gx[0] + cx["D2"] * d2gy[1]) + cx["D3"] * d2gx[2])
+    hy = gy - ((cy["D3"] * d2gy[0] + cy["D2"] * d2gx[1]) + cy["D1"] * d2gy[2])
+    return hx, hy

@@ -93,6 +93,17 @@ class PlaneWaveField:
             out.append(cy @ ax.real - sy @ ax.imag)
         return out[0], out[1]
 
+    def second_derivatives(self, nx: int, ny: int) -> Tuple[np.ndarray, np.ndarray]:
+        """Analytic second derivatives at the nodes: for each component the
+        planes (d_xx, d_xy, d_yy), shape (3, ny, nx) each (d_x of a mode is
+        i k_x, so d_xx -> -k_x^2, d_xy -> -k_x k_y, d_yy -> -k_y^2)."""
+        planes = ([], [])
+        for fac in (-self.k[:, 0] ** 2, -self.k[:, 0] * self.k[:, 1], -self.k[:, 1] ** 2):
+            vx, vy = PlaneWaveField(self.k, self.amp * fac[:, None]).evaluate(nx, ny)
+            planes[0].append(vx)
+            planes[1].append(vy)
+        return np.stack(planes[0]), np.stack(planes[1])
+
     def scaled(self, s: float) -> "PlaneWaveField":
         return PlaneWaveField(self.k.copy(), self.amp * s)
 
@@ -160,6 +171,10 @@ class Case:
     ux_exact: np.ndarray | None = None  # continuum solution at the nodes, if known
     uy_exact: np.ndarray | None = None
     label: str = ""
+    # analytic second derivatives of the load, planes (d_xx, d_xy, d_yy) per
+    # component, when known (input of the improved scheme's force correction)
+    d2gx: np.ndarray | None = None
+    d2gy: np.ndarray | None = None
 
 
 def manufactured_case(n: int, mat: Material, u: PlaneWaveField, label: str = "",
@@ -168,7 +183,8 @@ def manufactured_case(n: int, mat: Material, u: PlaneWaveField, label: str = "",
     b = body_force_of(u, mat)
     gx, gy = b.evaluate(n, ny)
     ux, uy = u.evaluate(n, ny)
-    return Case(n, ny, mat, remove_mean(gx), remove_mean(gy), ux, uy, label)
+    d2gx, d2gy = b.second_derivatives(n, ny)
+    return Case(n, ny, mat, remove_mean(gx), remove_mean(gy), ux, uy, label, d2gx, d2gy)
 
 
 def sin_cos_solution(n: int, amp: float, kx: int = 1, ky: int = 1) -> PlaneWaveField:
@@ -205,6 +221,29 @@ def paper_e1(n: int) -> Case:
     a = 2.0 * math.pi / n
     u = trig_product((9e-4, 7e-4), ("c", "s"), ("s", "c"), a, a)
     return manufactured_case(n, mat, u, f"paper-e1-{n}")
+
+
+def paper_e2(n: int) -> Case:
+    """The convergence study of the improved scheme (Sec. 7.3.2): the load of
+    the first study at nu = 0.8, E~ = 0.085 (with its analytic second
+    derivatives for the force correction)."""
+    mat = Material.from_young_poisson(0.085, 0.8)
+    a = 2.0 * math.pi / n
+    u = trig_product((9e-4, 7e-4), ("c", "s"), ("s", "c"), a, a)
+    return manufactured_case(n, mat, u, f"paper-e2-{n}")
+
+
+def paper_e3(n: int, young: float = 0.085, nu: float = 0.8) -> Case:
+    """The special case with no mixed derivatives (Sec. 7.3.3):
+    u/U = (9e-4 (cos(2 pi x~) + sin(2 pi y~)), 7e-4 (sin(2 pi x~) + cos(2 pi y~))).
+    The paper does not state the material; the improved scheme's nu = 0.8,
+    E~ = 0.085 by default."""
+    mat = Material.from_young_poisson(young, nu)
+    a = 2.0 * math.pi / n
+    # cos -> amplitude 1, sin -> -i (Re(A e^{i k.x}))
+    u = PlaneWaveField(np.array([[a, 0.0], [0.0, a]]),
+                       np.array([[9e-4, -7e-4j], [-9e-4j, 7e-4]], complex))
+    return manufactured_case(n, mat, u, f"paper-e3-{n}")
 
 
 def gaussian_hill_case(n: int, mat: Material,
