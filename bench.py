@@ -184,6 +184,8 @@ def parse():
     ap.add_argument("--comparator-only", action="store_true",
                     help="run only the FP64-storage comparator of the headline workload "
                          "(for profiling)")
+    ap.add_argument("--accuracy-only", action="store_true",
+                    help="only the three convergence studies of the paper (FP64 solves)")
     ap.add_argument("--small-only", action="store_true",
                     help="run only the 32 x 32 launch-bound solve leg")
     ap.add_argument("--serving-only", action="store_true",
@@ -268,6 +270,75 @@ def run_workload(solvers, nchunks, chunk):
             "plain_us_per_step": 1e3 * plain_ms / (len(ev) * fused),
             "steps_per_launch": tb, "launch_config": solvers[0][0].launch_config(),
             "last": last[-len(solvers):], "history": history}
+
+
+def stress_error(solver, case):
+    """Stress of the solver's current state (lbm_get_stress, lattice units)
+    against the continuum stress of the case's manufactured solution: (relative
+    L2 over the three components with sxy counted twice, max |e| / max |exact|)."""
+    import numpy as np
+    from paper_2208_14870_amd import problem as P
+    got = [t.cpu().numpy() for t in solver.stress()]
+    want = P.stress_of(case.u_field, case.material, case.nx, case.ny)
+    wts = (1.0, 1.0, 2.0)
+    num = sum(w * float(np.sum((a - b) ** 2)) for w, a, b in zip(wts, got, want))
+    den = sum(w * float(np.sum(b ** 2)) for w, b in zip(wts, want))
+    linf = max(float(np.max(np.abs(a - b))) for a, b in zip(got, want))
+    return math.sqrt(num / den), linf / max(float(np.max(np.abs(b))) for b in want)
+
+
+def accuracy_studies(sizes=(20, 40, 80, 160), tol=1e-12):
+    """The paper's three convergence studies solved on the GPU in FP64 to
+    r <= tol (a check every 100 steps): the standard scheme (Sec. 7.3.1,
+    nu = 0.8, E = 0.11), the improved scheme with the analytic force correction
+    (Sec. 7.3.2, E = 0.085) and the special case with the fourth-order rates
+    (Sec. 7.3.3).  Relative errors of displacement and stress against the
+    manufactured solution (L2 ratio and max |e| / max |exact|) and the observed
+    orders per halving."""
+    import numpy as np
+    import torch
+    from paper_2208_14870_amd import lbm, problem as P
+    out = {}
+    for name, make in (("standard_e1", P.paper_e1), ("improved_e2", P.paper_e2),
+                       ("fourth_order_e3", P.paper_e3)):
+        rows = []
+        for n in sizes:
+            c = make(n)
+            m = c.material
+            s = lbm.Solver(n, n, "fp64")
+            s.set_material(m.lame_lambda, m.lame_mu)
+            dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+            if name == "standard_e1":
+                s.set_body_force(dev(c.gx), dev(c.gy))
+            else:
+                if name == "fourth_order_e3":
+                    w12, w22 = lbm.fourth_order_rates(m.lame_lambda, m.lame_mu)
+                    s.set_rates(1.0 / 3.0, w12, w12, w22)
+                s.set_body_force_corrected(dev(c.gx), dev(c.gy),
+                                           dev(np.concatenate([c.d2gx, c.d2gy])))
+            t0 = time.perf_counter()
+            steps, r, st = s.solve_to_tol(tol, 10 ** 7, 100)
+            wall = time.perf_counter() - t0
+            ux, uy = (t.cpu().numpy() for t in s.displacement())
+            num = float(np.sum((ux - c.ux_exact) ** 2 + (uy - c.uy_exact) ** 2))
+            den = float(np.sum(c.ux_exact ** 2 + c.uy_exact ** 2))
+            ref = max(float(np.max(np.abs(c.ux_exact))), float(np.max(np.abs(c.uy_exact))))
+            dl2 = math.sqrt(num / den)
+            dinf = max(float(np.max(np.abs(ux - c.ux_exact))),
+                       float(np.max(np.abs(uy - c.uy_exact)))) / ref
+            sl2, sinf = stress_error(s, c)
+            s.close()
+            rows.append({"n": n, "status": st, "steps": steps, "solve_s": round(wall, 3),
+                         "disp_rel_l2": dl2, "disp_rel_linf": dinf,
+                         "stress_rel_l2": sl2, "stress_rel_linf": sinf})
+        for a, b in zip(rows, rows[1:]):
+            b["orders"] = {k: round(math.log2(a[k] / b[k]), 3) for k in
+                           ("disp_rel_l2", "disp_rel_linf", "stress_rel_l2", "stress_rel_linf")}
+        out[name] = rows
+    e1, e2 = out["standard_e1"], out["improved_e2"]
+    out["improved_over_standard_disp_linf"] = [round(a["disp_rel_linf"] / b["disp_rel_linf"], 2)
+                                               for a, b in zip(e1, e2)]
+    return out
 
 
 def small_32(reps: int = 20):
@@ -592,6 +663,9 @@ def main():
     if args.small_only:
         print(json.dumps({"small_32": small_32()}), flush=True)
         return
+    if args.accuracy_only:
+        print(json.dumps({"accuracy": accuracy_studies()}), flush=True)
+        return
     if args.serving_only:
         sv, ss, sh, ssh = serving_legs()
         print(json.dumps({"serving": sv, "serving_sustained": ss, "serving_hrrn": sh,
@@ -624,6 +698,7 @@ def main():
         updates = nsites * args.chunk * args.steps * len(solvers)
         res["mlups"] = updates / res["wall_s"] / 1e6
         u = [s.displacement() for s, _ in solvers]
+        res["stress_rel_l2"] = [stress_error(s, c)[0] for (s, _), c in zip(solvers, cases)]
         for s, _ in solvers:
             s.close()
         return res, u
@@ -671,6 +746,7 @@ def main():
         "fp32_rel_l2_vs_manufactured": [round(x[1], 6) for x in r32["last"]],
         "fp32_rel_linf_vs_manufactured": [round(x[2], 6) for x in r32["last"]],
         "fp32_residual_history_case0": [float("%.4g" % r) for r in r32["history"]],
+        "fp32_stress_rel_l2_vs_manufactured": [round(x, 6) for x in r32["stress_rel_l2"]],
     }
     if args.calib_copy:
         calib_copy()
@@ -691,6 +767,8 @@ def main():
         out["hbm_copy"] = copy_bandwidth()
         log("32x32 FP64 to r <= 1e-10, a check every step")
         out["small_32"] = small_32()
+        log("accuracy: the paper's three convergence studies (FP64, 20..160 nodes)")
+        out["accuracy"] = accuracy_studies()
         out["large_8192"] = large_lattice()
         log("in-place streaming vs two buffers, 8192x8192, one step per launch")
         out["inplace_8192"] = inplace_run()

@@ -146,6 +146,53 @@ int lbm_set_rates(lbm_solver *s, double theta, double omega12, double omega21, d
  * status codes), or LBM_OK.  Blocking.  Errors: LBM_E_ARG, LBM_E_HIP. */
 int lbm_set_body_force(lbm_solver *s, const double *gx, const double *gy);
 
+/* Body force with the leading-order correction of the improved scheme
+ * (Sec. 4, Eqs. force_correction_x/y; used in Sec. 7.3.2 and 7.3.3): the
+ * library takes in
+ *   gx' = gx - (D1 d_xx gx + D2 d_xy gy + D3 d_yy gx),
+ *   gy' = gy - (D3' d_xx gy + D2' d_xy gx + D1' d_yy gy)
+ * in place of (gx, gy), with D1..D3 the constants of the leading-order error
+ * (lbm_leading_error_constants) of the solver's current material and rates
+ * (D' = the y row's, equal to D when omega_12 = omega_21).  Set the material
+ * and rates first: a later change does not update the correction.
+ * gx, gy: FP64 device arrays [ny][nx] as for lbm_set_body_force.
+ * d2g: NULL, or an FP64 device array [6][ny][nx] with the planes d_xx gx,
+ * d_xy gx, d_yy gx, d_xx gy, d_xy gy, d_yy gy (second derivatives of the
+ * per-step force in lattice units, e.g. analytic ones as the paper assumes);
+ * NULL takes the second-order central differences of g on the periodic
+ * lattice, d_xx g = g(x+1) - 2 g(x) + g(x-1), d_xy g = (g(x+1,y+1) -
+ * g(x-1,y+1) - g(x+1,y-1) + g(x-1,y-1)) / 4, which changes the result only at
+ * O(k^4) relative.  The corrected force is then treated exactly as by
+ * lbm_set_body_force (statistics, mean removal, warnings).  Caller keeps
+ * ownership; read in stream order, blocking.  Errors: LBM_E_ARG, LBM_E_STATE
+ * (no material), LBM_E_MATERIAL (constants not finite), LBM_E_HIP. */
+int lbm_set_body_force_corrected(lbm_solver *s, const double *gx, const double *gy,
+                                 const double *d2g);
+
+/* Constants of the leading-order error (Sec. 4, Eq. leadingCoefficients,
+ * App. B) for a material (lattice units) and the free rates, host only (no
+ * GPU call):  out[0..4] = C1..C5, out[5..7] = D1..D3 (x row; the y row is the
+ * same call with omega12 and omega21 exchanged), out[8] = R1, out[9] = R2
+ * (Eq. rss_estimate).  Sign: the coefficients of r_x^(4) in Eq. ux_order2.
+ * App. B's printed constants are the negatives of these, and three of its
+ * terms differ (the tau terms of D1 and D2 are over (1-theta^2)(1-nu^2); the
+ * E^3 term of C2 is over 8 theta (1-theta^2)(1-nu^2)^3): these values are the
+ * ones the exact scheme has.  Errors: LBM_E_ARG (NULL out), LBM_E_MATERIAL
+ * (inadmissible material, theta outside (0, 1), omega outside (0, 2), or a
+ * constant not finite). */
+int lbm_leading_error_constants(double lame_lambda, double lame_mu, double theta,
+                                double omega12, double omega21, double omega22, double out[10]);
+
+/* Rates of the fourth-order special case (Sec. 7.3.3, App. C), host only:
+ * out[0] = omega_12 = omega_21 from App. C's tau_12 (which cancels C5),
+ * out[1] = omega_22 from the root of C1 = 0 (App. C's printed tau_22 does not
+ * cancel C1).  Use with lbm_set_rates(theta, out[0], out[0], out[1]) and
+ * lbm_set_body_force_corrected; fourth order holds for loads without mixed
+ * derivatives.  Finite-k stability is not checked (Sec. 7.3.3: these rates
+ * are unstable for many materials).  Errors: LBM_E_ARG, LBM_E_MATERIAL
+ * (inadmissible material, no root, or a rate outside (0, 2)). */
+int lbm_fourth_order_rates(double lame_lambda, double lame_mu, double theta, double out[2]);
+
 /* f := 0 (u0 = 0 initialisation at equilibrium, Sec. 6.2), step count := 0,
  * back to the creation precision. */
 int lbm_reset(lbm_solver *s);

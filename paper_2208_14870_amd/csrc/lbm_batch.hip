@@ -526,8 +526,9 @@ int lbm_batch_add(lbm_batch* b, int nx, int ny, int precision, int with_polish, 
     // force statistics into this slot's entry (read back at the next rebuild),
     // then the mean-projected copy, which reads them in stream order
     double* st = b->d_stats + 8 * id;
-    hipError_t e = force_stats(gx, gy, nx, ny, b->d_red, st, b->stream);
-    if (e == hipSuccess) e = upload_force(L, gx, gy, st, b->stream);
+    const ForceSrc src = raw_force(gx, gy, nx, ny);
+    hipError_t e = force_stats(src, b->d_red, st, b->stream);
+    if (e == hipSuccess) e = upload_force(L, src, st, b->stream);
     if (e == hipSuccess) e = zero_bytes(L.mem.buf[0], 8 * L.plane * elem_bytes(precision), b->stream);
     if (e == hipSuccess) e = zero_bytes(L.mem.u, 2 * L.plane * 8, b->stream);
     if (e != hipSuccess) {

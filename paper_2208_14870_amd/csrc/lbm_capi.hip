@@ -489,26 +489,25 @@ int lbm_set_rates(lbm_solver* s, double theta, double w12, double w21, double w2
     return s->sync_desc();
 }
 
-int lbm_set_body_force(lbm_solver* s, const double* gx, const double* gy) {
-    if (!s) return LBM_E_ARG;
-    if (!gx || !gy) return s->fail(LBM_E_ARG, "set_body_force: NULL force");
+namespace {
+// The force from a source (raw or corrected): statistics of the source
+// before anything is overwritten, so that a rejected force leaves the
+// previous one in place; then the mean-projected copy.
+int set_force(lbm_solver* s, const ForceSrc& src, const char* what) {
     Lattice& L = s->L;
-    // statistics of the caller's arrays before anything is overwritten, so
-    // that a rejected force leaves the previous one in place
     double* stats = s->d_red + 8 * kErrBlocks;
-    hipError_t e = force_stats(gx, gy, L.nx, L.ny, s->d_red, stats, s->stream);
+    hipError_t e = force_stats(src, s->d_red, stats, s->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->h_result, stats, 8 * sizeof(double), hipMemcpyDeviceToHost,
                            s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (e != hipSuccess) return s->hip_fail(e, "set_body_force: force statistics");
+    if (e != hipSuccess) return s->hip_fail(e, (std::string(what) + ": force statistics").c_str());
     double st[8];
     std::memcpy(st, s->h_result, sizeof(st));
     if (!std::isfinite(st[0]) || !std::isfinite(st[1]) || !std::isfinite(st[2]))
-        return s->fail(LBM_E_ARG, "set_body_force: non-finite force (previous force kept)");
+        return s->fail(LBM_E_ARG, std::string(what) + ": non-finite force (previous force kept)");
     // mean-projected copy (the kernel reads the statistics in stream order)
-    if ((e = upload_force(L, gx, gy, stats, s->stream)) != hipSuccess)
-        return s->hip_fail(e, "set_body_force");
+    if ((e = upload_force(L, src, stats, s->stream)) != hipSuccess) return s->hip_fail(e, what);
     L.has_force = true;
     record_force(L, st, s->steps);
     int rc = refit_half(s);
@@ -520,6 +519,84 @@ int lbm_set_body_force(lbm_solver* s, const double* gx, const double* gy) {
         s->err = "body force has a k = (pi,0) or (0,pi) component: the staggered first moment "
                  "oscillates for good, no steady state is reached";
     return w;
+}
+}  // namespace
+
+int lbm_set_body_force(lbm_solver* s, const double* gx, const double* gy) {
+    if (!s) return LBM_E_ARG;
+    if (!gx || !gy) return s->fail(LBM_E_ARG, "set_body_force: NULL force");
+    return set_force(s, raw_force(gx, gy, s->L.nx, s->L.ny), "set_body_force");
+}
+
+int lbm_set_body_force_corrected(lbm_solver* s, const double* gx, const double* gy,
+                                 const double* d2g) {
+    if (!s) return LBM_E_ARG;
+    if (!gx || !gy) return s->fail(LBM_E_ARG, "set_body_force_corrected: NULL force");
+    Lattice& L = s->L;
+    if (!L.has_material)
+        return s->fail(LBM_E_STATE, "set_body_force_corrected: set the material first");
+    const Rates& r = L.rates;
+    double E, nu;
+    young_poisson(L.lam, L.mu, E, nu);
+    const double t12 = 1.0 / r.w12 - 0.5, t21 = 1.0 / r.w21 - 0.5, t22 = 1.0 / r.w22 - 0.5;
+    const ErrorConstants kx = error_constants(E, nu, r.theta, t12, t21, t22);
+    const ErrorConstants ky = error_constants(E, nu, r.theta, t21, t12, t22);
+    ForceSrc src = raw_force(gx, gy, L.nx, L.ny);
+    src.mode = d2g ? ForceSrc::kGiven : ForceSrc::kCentral;
+    src.d2 = d2g;
+    for (int i = 0; i < 3; ++i) {
+        src.cx[i] = kx.D[i];
+        src.cy[i] = ky.D[i];
+    }
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(src.cx[i]) || !std::isfinite(src.cy[i]))
+            return s->fail(LBM_E_MATERIAL, "set_body_force_corrected: constants not finite "
+                                           "(nu = 1 or theta = 0)");
+    return set_force(s, src, "set_body_force_corrected");
+}
+
+int lbm_leading_error_constants(double lame_lambda, double lame_mu, double theta, double omega12,
+                                double omega21, double omega22, double out[10]) {
+    if (!out) return LBM_E_ARG;
+    Rates r;
+    r.theta = theta;
+    std::string err;
+    auto ok = [](double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; };
+    if (!(theta > 0.0 && theta < 1.0) || !ok(omega12) || !ok(omega21) || !ok(omega22) ||
+        !material_rates(lame_lambda, lame_mu, r, err))
+        return LBM_E_MATERIAL;
+    double E, nu;
+    young_poisson(lame_lambda, lame_mu, E, nu);
+    const ErrorConstants k = error_constants(E, nu, theta, 1.0 / omega12 - 0.5,
+                                             1.0 / omega21 - 0.5, 1.0 / omega22 - 0.5);
+    double c2 = 0.0, d2 = 0.0;
+    for (int i = 0; i < 5; ++i) {
+        out[i] = k.C[i];
+        c2 += k.C[i] * k.C[i];
+    }
+    for (int i = 0; i < 3; ++i) {
+        out[5 + i] = k.D[i];
+        d2 += k.D[i] * k.D[i];
+    }
+    out[8] = std::sqrt(c2);
+    out[9] = std::sqrt(c2 + d2);
+    for (int i = 0; i < 10; ++i)
+        if (!std::isfinite(out[i])) return LBM_E_MATERIAL;
+    return LBM_OK;
+}
+
+int lbm_fourth_order_rates(double lame_lambda, double lame_mu, double theta, double out[2]) {
+    if (!out) return LBM_E_ARG;
+    Rates r;
+    r.theta = theta;
+    std::string err;
+    if (!(theta > 0.0 && theta < 1.0) || !material_rates(lame_lambda, lame_mu, r, err))
+        return LBM_E_MATERIAL;
+    double w12 = 0.0, w22 = 0.0;
+    if (!fourth_order_rates(lame_lambda, lame_mu, theta, w12, w22)) return LBM_E_MATERIAL;
+    out[0] = w12;
+    out[1] = w22;
+    return LBM_OK;
 }
 
 int lbm_set_tile(lbm_solver* s, int bx_log2, int rows_per_thread, int blocks_per_cu) {

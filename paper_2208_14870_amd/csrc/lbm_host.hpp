@@ -53,6 +53,96 @@ inline bool material_rates(double lam, double mu, Rates& r, std::string& err) {
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// leading-order error of the scheme (Sec. 4, App. B) and the rates of the
+// fourth-order special case (App. C)
+// ---------------------------------------------------------------------------
+
+// r_x^(4) = C1 d_xxxx u0x + C2 d_xxxy u0y + C3 d_xxyy u0x + C4 d_xyyy u0y
+//         + C5 d_yyyy u0x + D1 d_xx gx + D2 d_xy gy + D3 d_yy gx
+// (Eq. leadingCoefficients), in the sign of Eq. ux_order2.  App. B lists the
+// constants as functions of the dimensionless Young's modulus E and Poisson
+// ratio nu (second-order relaxation times eliminated) and of theta, tau_12,
+// tau_21, tau_22.  Matched against the symbols of the exact one-step operator
+// (quartic part of the log of its slow two-mode block, quadratic part of its
+// effective forcing), the printed list needs four changes, applied here:
+// every constant changes sign; the tau terms of D1 and D2 are over
+// (1 - theta^2)(1 - nu^2), not (1 - theta^2)(1 - nu^2)^2; the E^3 term of C2
+// is over 8 theta (1 - theta^2)(1 - nu^2)^3.  The y row is the x row with
+// tau_12 and tau_21 exchanged.
+struct ErrorConstants {
+    double C[5];
+    double D[3];
+};
+
+inline ErrorConstants error_constants(double E, double nu, double th, double t12, double t21,
+                                      double t22) {
+    const double a = 1.0 - th * th, b = 1.0 - nu * nu;
+    const double E2 = E * E, E3 = E2 * E, n2 = nu * nu, n3 = n2 * nu, th2 = th * th;
+    const double b2 = b * b, b3 = b2 * b, om = 1.0 - nu, op = 1.0 + nu;
+    const double q = th2 * op + nu - 2.0 * th - 1.0;
+    double c[5], d[3];  // as printed (before the sign change)
+    c[0] = (n2 - 2.0 * th * nu + 1.0) * E3 / (a * b3) + th * (nu - th) * t12 * E2 / (a * b2) +
+           (th2 - 1.0 + 12.0 * th * (th - nu) * t12 * t22) * E / (12.0 * a * b);
+    c[1] = (om * om * om + 4.0 * th * (n3 - n2 + 3.0 * nu + 1.0) +
+            th2 * (5.0 * n3 - 15.0 * n2 - nu - 5.0)) * E3 / (8.0 * th * a * b3) -
+           (2.0 * th * (om * nu + th2 * op - th * (1.0 + n2)) * t12 +
+            (1.0 - th) * om * (1.0 + 2.0 * th - nu - th2 * op) * t21) * E2 / (4.0 * th * a * b2) +
+           ((2.0 * th2 - 3.0 * th + 1.0) * (1.0 + 3.0 * th * om - 5.0 * nu) +
+            24.0 * th * (th - nu) * t12 * t22) * E / (24.0 * a * b);
+    c[2] = (om * om * (3.0 + nu) + 4.0 * th * (-n3 + 3.0 * n2 + nu + 1.0) -
+            th2 * (5.0 * n3 - 3.0 * n2 + 7.0 * nu + 7.0)) * E3 / (8.0 * th * a * b3) +
+           (-2.0 * (1.0 - th) * th * (nu - 2.0 * th - 1.0) * om * t12 -
+            ((1.0 + th) * om * om + th2 * th * op * op + th2 * (n2 - 2.0 * nu - 3.0)) * t21) * E2 /
+               (4.0 * th * a * b2) +
+           ((1.0 - th) * (om - th * op - 2.0 * th2 * (2.0 + nu)) - 4.0 * a * om * t12 * t22 +
+            4.0 * q * t21 * t22) * E / (8.0 * a * b) +
+           0.25 * th * t22;
+    c[3] = (16.0 * th * nu + om * om * (3.0 + nu) - th2 * (n3 + 9.0 * n2 - 5.0 * nu + 11.0)) * E3 /
+               (8.0 * th * a * b3) +
+           (a * om * (th * nu + nu + th - 1.0) * t12 - 2.0 * th * q * t21) * E2 / (4.0 * th * a * b2) +
+           (a * (2.0 * (2.0 - nu) - 3.0 * th * (5.0 + nu)) - 12.0 * a * om * t12 * t22 +
+            12.0 * q * t21 * t22) * E / (24.0 * a * b) +
+           0.25 * th * t22;
+    c[4] = E3 / (8.0 * th * op * op * op) - (1.0 - th) * t12 * E2 / (4.0 * th * op * op) -
+           (3.0 * th - 2.0) * E / (24.0 * op);
+    d[0] = (n2 - 2.0 * th * nu + 1.0) * E2 / (a * b2) + th * (nu - th) * t12 * E / (a * b) - 0.25;
+    d[1] = (om * om + 8.0 * th * nu - th2 * (5.0 * n2 - 2.0 * nu + 5.0)) * E2 / (4.0 * th * a * b2) -
+           q * t21 * E / (2.0 * a * b) - 0.5 * th;
+    d[2] = E2 / (4.0 * th * op * op) + t12 * E / (2.0 * op) - 0.25 * th;
+    ErrorConstants k;
+    for (int i = 0; i < 5; ++i) k.C[i] = -c[i];
+    for (int i = 0; i < 3; ++i) k.D[i] = -d[i];
+    return k;
+}
+
+// E and nu of the 2D relations (Eq. material_relations): K = lambda + mu,
+// E = 4 K mu / (K + mu), nu = (K - mu) / (K + mu).
+inline void young_poisson(double lam, double mu, double& E, double& nu) {
+    const double K = lam + mu;
+    E = 4.0 * K * mu / (K + mu);
+    nu = (K - mu) / (K + mu);
+}
+
+// Rates of the fourth-order special case (Sec. 7.3.3): tau_12 = tau_21 from
+// App. C (it cancels C5) and tau_22 from C1 = 0 (C1 is affine in tau_22; the
+// tau_22 expression printed in App. C does not cancel C1).  Returns false if
+// tau_22 has no root (theta = nu) or a rate falls outside (0, 2).
+inline bool fourth_order_rates(double lam, double mu, double th, double& w12, double& w22) {
+    double E, nu;
+    young_poisson(lam, mu, E, nu);
+    const double t11 = mu / th;
+    const double t12 = (2.0 - 3.0 * th + 12.0 * th * t11 * t11) / (12.0 * (1.0 - th) * t11);
+    const double c0 = error_constants(E, nu, th, t12, t12, 0.0).C[0];
+    const double c1 = error_constants(E, nu, th, t12, t12, 1.0).C[0];
+    if (!(c1 != c0)) return false;
+    const double t22 = -c0 / (c1 - c0);
+    w12 = 1.0 / (t12 + 0.5);
+    w22 = 1.0 / (t22 + 0.5);
+    auto ok = [](double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; };
+    return ok(w12) && ok(w22);
+}
+
 inline void fill_coefs(SlotDesc& d, const Rates& r) {
     d.cs = 0.25 * (1.0 - r.ws);
     d.cd = 0.25 * (1.0 - r.wd);
@@ -624,19 +714,28 @@ inline hipError_t neutral_reset(int prec, const SlotDesc& d, int sel, const doub
     return neutral_reset_t<__half>(d, sel, mean_target, stag_target, scratch, st);
 }
 
-// Statistics of a force given as FP64 device arrays (two-stage reduction in
-// a fixed order): stats[0..7] = sum gx, sum gy, sum gx^2 + gy^2, max |g|, the
-// staggered sums (even nx / ny, else 0), 0, 0.  scratch: 8 * kErrBlocks
-// doubles; stats: 8 doubles of device memory.  Stream-ordered.
-inline hipError_t force_stats(const double* gx, const double* gy, int nx, int ny, double* scratch,
-                              double* stats, hipStream_t st) {
-    hipLaunchKernelGGL(k_force_stats8, dim3(kErrBlocks), dim3(kBlock), 0, st, gx, gy, nx, ny,
-                       scratch);
+// Statistics of a force given as FP64 device arrays, raw or corrected
+// (ForceSrc; two-stage reduction in a fixed order): stats[0..7] = sum gx,
+// sum gy, sum gx^2 + gy^2, max |g|, the staggered sums (even nx / ny, else
+// 0), 0, 0.  scratch: 8 * kErrBlocks doubles; stats: 8 doubles of device
+// memory.  Stream-ordered.
+inline hipError_t force_stats(const ForceSrc& src, double* scratch, double* stats, hipStream_t st) {
+    hipLaunchKernelGGL(k_force_stats8, dim3(kErrBlocks), dim3(kBlock), 0, st, src, scratch);
     hipLaunchKernelGGL(k_reduce4<kForceMask>, dim3(1), dim3(kBlock), 0, st, scratch, kErrBlocks,
                        stats);
     hipLaunchKernelGGL(k_reduce4<0>, dim3(1), dim3(kBlock), 0, st, scratch + 4 * kErrBlocks,
                        kErrBlocks, stats + 4);
     return hipGetLastError();
+}
+
+inline ForceSrc raw_force(const double* gx, const double* gy, int nx, int ny) {
+    ForceSrc f;
+    f.gx = gx;
+    f.gy = gy;
+    f.nx = nx;
+    f.ny = ny;
+    f.n = (long long)nx * ny;
+    return f;
 }
 
 // Warning bits of a force from its statistics (host): LBM_W_MEAN_REMOVED when
@@ -654,18 +753,19 @@ inline int force_warnings(const double* stats, long long N) {
     return w;
 }
 
-// Mean-projected copy of the FP64 force into the lattice's arithmetic type
-// (and the FP64 copy for the polish phase); stats: the force's statistics in
-// device memory (force_stats), read by the kernel in stream order.
-inline hipError_t upload_force(const Lattice& L, const double* gx, const double* gy,
-                               const double* stats, hipStream_t st) {
+// Mean-projected copy of the FP64 force (raw or corrected) into the
+// lattice's arithmetic type (and the FP64 copy for the polish phase); stats:
+// the force's statistics in device memory (force_stats), read by the kernel
+// in stream order.
+inline hipError_t upload_force(const Lattice& L, const ForceSrc& src, const double* stats,
+                               hipStream_t st) {
     const long long N = L.N, P = L.plane;
     if (L.prec0 == LBM_FP64)
-        hipLaunchKernelGGL(k_force_upload<double>, dim3(blocks_for(N)), dim3(kBlock), 0, st, gx, gy,
-                           N, P, stats, reinterpret_cast<double*>(L.mem.g), (double*)nullptr);
+        hipLaunchKernelGGL(k_force_upload<double>, dim3(blocks_for(N)), dim3(kBlock), 0, st, src, P,
+                           stats, reinterpret_cast<double*>(L.mem.g), (double*)nullptr);
     else
-        hipLaunchKernelGGL(k_force_upload<float>, dim3(blocks_for(N)), dim3(kBlock), 0, st, gx, gy,
-                           N, P, stats, reinterpret_cast<float*>(L.mem.g), L.mem.pg);
+        hipLaunchKernelGGL(k_force_upload<float>, dim3(blocks_for(N)), dim3(kBlock), 0, st, src, P,
+                           stats, reinterpret_cast<float*>(L.mem.g), L.mem.pg);
     return hipGetLastError();
 }
 

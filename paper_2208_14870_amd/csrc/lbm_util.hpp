@@ -189,21 +189,74 @@ static __global__ __launch_bounds__(kBlock) void k_force_stats(const double* gx,
 // partial[4 b ..] and (sum (-1)^x gx for even nx, sum (-1)^y gy for even ny,
 // 0, 0) into partial[4 (gridDim + b) ..].  The staggered sums drive the
 // undamped modes at k = (pi, 0), (0, pi) (see k_neutral_sums).
-static __global__ __launch_bounds__(kBlock) void k_force_stats8(const double* gx, const double* gy,
-                                                                int nx, int ny, double* partial) {
+// The per-step force as the library takes it in: the caller's FP64 arrays,
+// or those arrays with the leading-order correction of the improved scheme
+// (Sec. 4, Eqs. force_correction_x/y):
+//   gx' = gx - (D1 d_xx gx + D2 d_xy gy + D3 d_yy gx),
+//   gy' = gy - (E3 d_xx gy + E2 d_xy gx + E1 d_yy gy),
+// with (D1, D2, D3) the x row's constants, (E1, E2, E3) the y row's (equal to
+// the x row's when tau_12 = tau_21).  The second derivatives are either given
+// (d2: six FP64 planes d_xx gx, d_xy gx, d_yy gx, d_xx gy, d_xy gy, d_yy gy)
+// or the second-order central differences of g on the periodic lattice.
+struct ForceSrc {
+    enum { kRaw = 0, kGiven = 1, kCentral = 2 };
+    const double* gx = nullptr;
+    const double* gy = nullptr;
+    const double* d2 = nullptr;
+    long long n = 0;
+    int nx = 0, ny = 0, mode = kRaw;
+    double cx[3] = {0, 0, 0}, cy[3] = {0, 0, 0};
+
+    // d_xx, d_xy, d_yy of one component at (x, y) by central differences
+    __device__ void central(const double* g, int x, int y, double out[3]) const {
+#pragma clang fp contract(off)
+        const int xp = x + 1 == nx ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
+        const int yp = y + 1 == ny ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
+        const long long r = (long long)y * nx, rp = (long long)yp * nx, rm = (long long)ym * nx;
+        const double c = g[r + x];
+        out[0] = (g[r + xp] - 2.0 * c) + g[r + xm];
+        out[1] = ((g[rp + xp] - g[rp + xm]) - (g[rm + xp] - g[rm + xm])) * 0.25;
+        out[2] = (g[rp + x] - 2.0 * c) + g[rm + x];
+    }
+    __device__ void at(long long i, int x, int y, double& vx, double& vy) const {
+#pragma clang fp contract(off)
+        vx = gx[i];
+        vy = gy[i];
+        if (mode == kRaw) return;
+        double ax[3], ay[3];
+        if (mode == kGiven) {
+            for (int c = 0; c < 3; ++c) {
+                ax[c] = d2[c * n + i];
+                ay[c] = d2[(3 + c) * n + i];
+            }
+        } else {
+            central(gx, x, y, ax);
+            central(gy, x, y, ay);
+        }
+        const double hx = vx - ((cx[0] * ax[0] + cx[1] * ay[1]) + cx[2] * ax[2]);
+        const double hy = vy - ((cy[2] * ay[0] + cy[1] * ax[1]) + cy[0] * ay[2]);
+        vx = hx;
+        vy = hy;
+    }
+};
+
+static __global__ __launch_bounds__(kBlock) void k_force_stats8(ForceSrc src, double* partial) {
     __shared__ double lds[16];
-    const long long n = (long long)nx * ny;
+    const int nx = src.nx, ny = src.ny;
+    const long long n = src.n;
     const double sx = (nx % 2 == 0) ? 1.0 : 0.0, sy = (ny % 2 == 0) ? 1.0 : 0.0;
     double v[4] = {0.0, 0.0, 0.0, 0.0}, w[4] = {0.0, 0.0, 0.0, 0.0};
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (long long)gridDim.x * kBlock) {
         const int x = (int)(i % nx), y = (int)(i / nx);
-        v[0] += gx[i];
-        v[1] += gy[i];
-        v[2] += gx[i] * gx[i] + gy[i] * gy[i];
-        v[3] = fmax(v[3], fmax(fabs(gx[i]), fabs(gy[i])));
-        w[0] += ((x & 1) ? -sx : sx) * gx[i];
-        w[1] += ((y & 1) ? -sy : sy) * gy[i];
+        double gx, gy;
+        src.at(i, x, y, gx, gy);
+        v[0] += gx;
+        v[1] += gy;
+        v[2] += gx * gx + gy * gy;
+        v[3] = fmax(v[3], fmax(fabs(gx), fabs(gy)));
+        w[0] += ((x & 1) ? -sx : sx) * gx;
+        w[1] += ((y & 1) ? -sy : sy) * gy;
     }
     block_reduce4<kForceMask>(v, lds);
     block_reduce4<0>(w, lds);
@@ -213,23 +266,20 @@ static __global__ __launch_bounds__(kBlock) void k_force_stats8(const double* gx
             partial[4 * (gridDim.x + blockIdx.x) + c] = w[c];
         }
 }
-
-// Internal copy of a body force: out = g - shift in the arithmetic type C
-// (planes [2][plane]), and optionally the FP64 copy out64 (the polish state's
-// force), with the shift of force_mean_shift taken from the device statistics
 // st (8 doubles of k_force_stats8 after stage 2).  A zero shift copies g bit
 // for bit.
 template <typename C>
-static __global__ __launch_bounds__(kBlock) void k_force_upload(const double* gx, const double* gy,
-                                                                long long n, long long plane,
+static __global__ __launch_bounds__(kBlock) void k_force_upload(ForceSrc src, long long plane,
                                                                 const double* st, C* out,
                                                                 double* out64) {
 #pragma clang fp contract(off)
     const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long n = src.n;
     if (i >= n) return;
-    double shift[2];
+    double shift[2], gx, gy;
     force_mean_shift(st, (double)n, shift);
-    const double vx = gx[i] - shift[0], vy = gy[i] - shift[1];
+    src.at(i, (int)(i % src.nx), (int)(i / src.nx), gx, gy);
+    const double vx = gx - shift[0], vy = gy - shift[1];
     out[i] = (C)vx;
     out[plane + i] = (C)vy;
     if (out64) {

@@ -24,6 +24,7 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "W_MEAN_REMOVED", 4: "W_STAGGERED_LOAD
           6: "W_MEAN_REMOVED|W_STAGGERED_LOAD", -1: "E_ARG", -2: "E_MATERIAL",
           -3: "E_WORKSPACE", -4: "E_HIP", -5: "E_DIVERGED", -6: "E_STATE"}
 W_MEAN_REMOVED, W_STAGGERED_LOAD = 2, 4
+E_ARG, E_MATERIAL, E_WORKSPACE, E_HIP, E_DIVERGED, E_STATE = -1, -2, -3, -4, -5, -6
 FORCE_WARNINGS = (0, 2, 4, 6)
 
 
@@ -58,6 +59,9 @@ def load() -> ctypes.CDLL:
         "lbm_set_material": (i, [vp, d, d]),
         "lbm_set_rates": (i, [vp, d, d, d, d]),
         "lbm_set_body_force": (i, [vp, vp, vp]),
+        "lbm_set_body_force_corrected": (i, [vp, vp, vp, vp]),
+        "lbm_leading_error_constants": (i, [d, d, d, d, d, d, pd]),
+        "lbm_fourth_order_rates": (i, [d, d, d, pd]),
         "lbm_reset": (i, [vp]),
         "lbm_step": (i, [vp, ll]),
         "lbm_step_checked": (i, [vp, ll, pd]),
@@ -147,6 +151,30 @@ def error_norms_noalloc(ux: torch.Tensor, uy: torch.Tensor, ux_ref: torch.Tensor
                                      ctypes.c_void_p(_stream_ptr(out.device)))
     if rc != 0:
         raise LbmError(rc, lib.lbm_last_error(None).decode())
+
+
+def leading_error_constants(lame_lambda: float, lame_mu: float, theta: float = 1.0 / 3.0,
+                            w12: float = 1.0, w21: float = 1.0, w22: float = 1.0) -> dict:
+    """lbm_leading_error_constants (host only): C1..C5, D1..D3 of the x row and
+    the error estimates R1, R2."""
+    lib = load()
+    out = (ctypes.c_double * 10)()
+    rc = lib.lbm_leading_error_constants(float(lame_lambda), float(lame_mu), float(theta),
+                                         float(w12), float(w21), float(w22), out)
+    if rc != 0:
+        raise LbmError(rc, "leading_error_constants: inadmissible material or rates")
+    keys = ["C1", "C2", "C3", "C4", "C5", "D1", "D2", "D3", "R1", "R2"]
+    return dict(zip(keys, list(out)))
+
+
+def fourth_order_rates(lame_lambda: float, lame_mu: float, theta: float = 1.0 / 3.0):
+    """lbm_fourth_order_rates (host only): (omega_12 = omega_21, omega_22)."""
+    lib = load()
+    out = (ctypes.c_double * 2)()
+    rc = lib.lbm_fourth_order_rates(float(lame_lambda), float(lame_mu), float(theta), out)
+    if rc != 0:
+        raise LbmError(rc, "fourth_order_rates: no admissible rates for this material")
+    return out[0], out[1]
 
 
 class Solver:
@@ -241,6 +269,24 @@ class Solver:
         return self._check(self.lib.lbm_set_body_force(self.h, ctypes.c_void_p(gx.data_ptr()),
                                                        ctypes.c_void_p(gy.data_ptr())),
                            allow=FORCE_WARNINGS)
+
+    def set_body_force_corrected(self, gx: torch.Tensor, gy: torch.Tensor,
+                                 d2g: Optional[torch.Tensor] = None) -> int:
+        """lbm_set_body_force_corrected: the force with the leading-order
+        correction of the improved scheme; d2g (6, ny, nx) float64 holds the
+        planes d_xx gx, d_xy gx, d_yy gx, d_xx gy, d_xy gy, d_yy gy, or None for
+        central differences on the lattice.  Returns the warning bits."""
+        shp = (self.ny, self.nx)
+        gx = _dev_f64(gx, shp, "gx")
+        gy = _dev_f64(gy, shp, "gy")
+        ptr = None
+        if d2g is not None:
+            d2g = _dev_f64(d2g, (6,) + shp, "d2g")
+            ptr = ctypes.c_void_p(d2g.data_ptr())
+        self._keep = [gx, gy, d2g]
+        return self._check(self.lib.lbm_set_body_force_corrected(
+            self.h, ctypes.c_void_p(gx.data_ptr()), ctypes.c_void_p(gy.data_ptr()), ptr),
+            allow=FORCE_WARNINGS)
 
     def reset(self):
         self._check(self.lib.lbm_reset(self.h))

@@ -131,6 +131,20 @@ def solution_of(b: PlaneWaveField, mat: Material) -> PlaneWaveField:
     return PlaneWaveField(b.k.copy(), amps)
 
 
+def stress_of(u: PlaneWaveField, mat: Material, nx: int, ny: int):
+    """Continuum Cauchy stress of a displacement field at the nodes, lattice
+    units (Eq. stress with the 2D relations): sigma = K div(u) I +
+    mu (grad u + grad u^T - div(u) I).  Returns (sxx, syy, sxy)."""
+    def grad(c, axis):  # d u_c / d x_axis, mode by mode (multiply by i k)
+        return PlaneWaveField(u.k, u.amp * (1j * u.k[:, axis])[:, None]).evaluate(nx, ny)[c]
+    dxx, dxy = grad(0, 0), grad(0, 1)
+    dyx, dyy = grad(1, 0), grad(1, 1)
+    div = dxx + dyy
+    K, mu = mat.bulk, mat.lame_mu
+    return (K * div + mu * (2.0 * dxx - div), K * div + mu * (2.0 * dyy - div),
+            mu * (dxy + dyx))
+
+
 def trig_product(coef: Sequence[float], fx: Sequence[str], fy: Sequence[str], kx: float,
                  ky: float) -> PlaneWaveField:
     """Field with components coef[c] * T(kx x) * T'(ky y), T in {cos, sin}, as two
@@ -175,6 +189,7 @@ class Case:
     # component, when known (input of the improved scheme's force correction)
     d2gx: np.ndarray | None = None
     d2gy: np.ndarray | None = None
+    u_field: PlaneWaveField | None = None  # the manufactured solution, if any
 
 
 def manufactured_case(n: int, mat: Material, u: PlaneWaveField, label: str = "",
@@ -184,7 +199,7 @@ def manufactured_case(n: int, mat: Material, u: PlaneWaveField, label: str = "",
     gx, gy = b.evaluate(n, ny)
     ux, uy = u.evaluate(n, ny)
     d2gx, d2gy = b.second_derivatives(n, ny)
-    return Case(n, ny, mat, remove_mean(gx), remove_mean(gy), ux, uy, label, d2gx, d2gy)
+    return Case(n, ny, mat, remove_mean(gx), remove_mean(gy), ux, uy, label, d2gx, d2gy, u)
 
 
 def sin_cos_solution(n: int, amp: float, kx: int = 1, ky: int = 1) -> PlaneWaveField:
