@@ -376,6 +376,18 @@ enum lbm_fused_kernel {
  * LBM_E_ARG, LBM_E_STATE (the wavefront with steps_per_launch > 4). */
 int lbm_set_fused_kernel(lbm_solver *s, int kind, int segment_rows);
 
+/* Optional, half storage (LBM_FP16) with two buffers: on = 1 rounds every
+ * stored population (HBM and the fused kernel's LDS copies) stochastically
+ * instead of to nearest: up with probability equal to the discarded fraction
+ * of a half ulp (13 random bits), so that changes below half an ulp are not
+ * lost and slow modes do not stall.  The random bits are a fixed function of
+ * (site, population, step count since lbm_reset, seed): fused and single-step
+ * launches give identical bits, and reruns repeat.  The register-wavefront
+ * kernel rounds to nearest, so this selects the tile kernel (or single steps
+ * where the tile does not reach).  Not available in place or in a batch.
+ * Errors: LBM_E_STATE (not half storage, or in place). */
+int lbm_set_stochastic_rounding(lbm_solver *s, int on, unsigned int seed);
+
 /* Current launch configuration of plain steps: out[0] steps per launch;
  * out[1] the fused kernel (LBM_FUSED_TILE, LBM_FUSED_WAVEFRONT, or -1 for one
  * step per launch); out[2] its tile rows (tile), segment rows (wavefront) or

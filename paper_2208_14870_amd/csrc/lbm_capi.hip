@@ -122,6 +122,7 @@ struct lbm_solver {
         L.cur = sel();
         phase = 0;
         SlotDesc d = L.desc();
+        d.sr_step = (unsigned)steps;  // stochastic rounding: steps enqueued before
         nitems = L.nitems();
         if (nitems > max_items_) return fail(LBM_E_WORKSPACE, "tile shape exceeds work-list space");
         hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(1), 0, stream, d_desc, d);
@@ -151,11 +152,19 @@ struct lbm_solver {
         return a;
     }
 
+    // After a launch of ns steps: advance the device's stochastic-rounding step.
+    hipError_t advance_sr(int ns, hipStream_t st) {
+        if (!L.sr_on()) return hipSuccess;
+        hipLaunchKernelGGL(k_add_sr_step, dim3(1), dim3(1), 0, st, d_desc, ns);
+        return hipGetLastError();
+    }
+
     hipError_t enqueue_one(int mode, hipStream_t st, long long& ph) {
         hipError_t e = launch_step(L.prec, mode, L.general(), L.eff_vy(),
                                    L.layout(L.cur ^ (int)(ph & 1)), grid, st,
                                    launch_args((int)(ph & 1)));
         ++ph;
+        if (e == hipSuccess) e = advance_sr(1, st);
         return e;
     }
 
@@ -164,8 +173,10 @@ struct lbm_solver {
         hipError_t e =
             L.wave_hs > 0
                 ? launch_wave(L.prec, ns, L.nx, L.ny, L.wave_hs, d_desc, (int)(ph & 1), st)
-                : launch_stepN(L.prec, ns, L.th, grid, st, launch_args((int)(ph & 1)));
+                : launch_stepN(L.prec, ns, L.th, grid, st, launch_args((int)(ph & 1)), false,
+                               L.sr_on());
         ++ph;  // one buffer flip for ns steps
+        if (e == hipSuccess) e = advance_sr(ns, st);
         return e;
     }
 
@@ -232,8 +243,10 @@ struct lbm_solver {
         }
         for (; i < np && e == hipSuccess; ++i) e = enqueue_one(kPlain, st, ph);
         if (e == hipSuccess && span) {
-            e = launch_stepN(L.prec, span, L.th, grid, st, launch_args((int)(ph & 1)), true);
+            e = launch_stepN(L.prec, span, L.th, grid, st, launch_args((int)(ph & 1)), true,
+                             L.sr_on());
             ++ph;
+            if (e == hipSuccess) e = advance_sr(span, st);
             if (e == hipSuccess) e = enqueue_finalize(st);
             return e;
         }
@@ -286,7 +299,7 @@ struct lbm_solver {
     hipError_t run_graph(long long nplain, bool writeu, bool check) {
         const int flip0 = (int)(phase & 1);
         const int kind = (writeu ? 1 : 0) | (check ? 2 : 0) | (L.general() ? 4 : 0) |
-                         (L.inplace ? 8 : 0);
+                         (L.inplace ? 8 : 0) | (L.sr_on() ? 16 : 0);
         const int fused = L.fused() ? L.tb | (L.th << 4) : 0;
         auto key = std::make_tuple(nplain, kind, flip0 ^ (L.cur << 1), L.prec, L.eff_vy(), fused,
                                    L.fused() ? L.wave_hs : 0, grid);
@@ -624,6 +637,7 @@ int lbm_set_time_blocking(lbm_solver* s, int steps_per_launch) {
     if (s->fused_auto)
         L.wave_hs = default_fused_wave_rows(L.prec, steps_per_launch, L.nx, L.ny, s->cus,
                                             !L.tile_fits());
+    if (L.sr) L.wave_hs = 0;  // the wavefront has no stochastic rounding
     else if (steps_per_launch > 4)
         L.wave_hs = 0;  // the wavefront runs 2..4 steps
     return s->sync_desc();
@@ -650,6 +664,9 @@ int lbm_set_fused_kernel(lbm_solver* s, int kind, int segment_rows) {
         s->L.wave_hs = 0;
         s->fused_auto = false;
     } else if (kind == LBM_FUSED_WAVEFRONT) {
+        if (s->L.sr)
+            return s->fail(LBM_E_STATE, "set_fused_kernel: stochastic rounding runs with the tile "
+                                        "or single-step kernels");
         if (segment_rows < 1 || segment_rows > (1 << 20))
             return s->fail(LBM_E_ARG, "set_fused_kernel: segment_rows must be in 1..2^20");
         if (s->L.tb > 4)
@@ -661,6 +678,19 @@ int lbm_set_fused_kernel(lbm_solver* s, int kind, int segment_rows) {
     } else {
         return s->fail(LBM_E_ARG, "set_fused_kernel: kind must be LBM_FUSED_TILE or LBM_FUSED_WAVEFRONT");
     }
+    return s->sync_desc();
+}
+
+int lbm_set_stochastic_rounding(lbm_solver* s, int on, unsigned int seed) {
+    if (!s) return LBM_E_ARG;
+    Lattice& L = s->L;
+    if (on && (L.prec0 != LBM_FP16 || L.inplace))
+        return s->fail(LBM_E_STATE, "set_stochastic_rounding: half storage with two buffers only");
+    L.sr = on != 0;
+    L.sr_seed = seed;
+    // the register wavefront rounds to nearest: tile kernel, or single steps
+    // where the tile's 32-bit plane offsets do not reach
+    if (L.sr) L.wave_hs = 0;
     return s->sync_desc();
 }
 

@@ -45,7 +45,9 @@ struct SlotDesc {
     int tiles_x, tiles_y;  // tile grid of this lattice
     int bx_log2;           // tile width in threads = 1 << bx_log2 (tile height = 256 >> bx_log2)
     int general;           // nonzero: general omega_12/21/22 and theta (host sets the launch variant)
-    int pad_;
+    int sr;                // nonzero: half storage rounds stochastically (two buffers only)
+    unsigned sr_seed;      // seed of the stochastic rounding
+    unsigned sr_step;      // steps done before the next launch (advanced on the device)
     // fast-path coefficients (omega_12 = omega_21 = omega_22 = 1)
     double cs, cd, c11, hth, tq;
     // general-path rates
@@ -104,7 +106,63 @@ template <> struct Store<__half> {
         __half h = __float2half_rn(v);
         __builtin_nontemporal_store(__half_as_ushort(h), glob(reinterpret_cast<unsigned short*>(p)));
     }
+    __device__ static __forceinline__ void st_h(__half* p, __half h) {
+        __builtin_nontemporal_store(__half_as_ushort(h), glob(reinterpret_cast<unsigned short*>(p)));
+    }
 };
+
+// ---------------------------------------------------------------------------
+// stochastic rounding of half storage (optional, lbm_set_stochastic_rounding)
+// ---------------------------------------------------------------------------
+// Round-to-nearest half storage loses every change of a population smaller
+// than half a unit in the last place, so slow modes stall.  Stochastic
+// rounding rounds up with probability equal to the discarded fraction, so the
+// stored value is unbiased.  The random bits are a fixed function of (site,
+// population, step, seed), so the single-step and the fused kernels, which
+// store the same value for the same (site, q, step), round it identically, and
+// reruns repeat.  Per site and step: the 32-bit finaliser of MurmurHash3
+// (Appleby) of the site index mixed with a hash of the step gives one word;
+// three xorshift32 steps (Marsaglia 2003) give three more; population q takes
+// 13 bits of word q/2.  Rounding: the 13 random bits are added to the low 13
+// bits of the FP32 pattern (the bits that FP32 -> FP16 drops for normal half
+// values), which are then cleared, so the conversion to half is exact.  Values
+// below the half normal range (|v| < 2^-14, far below the stored scale) are
+// rounded to nearest by that conversion; canonical NaN and infinity pass
+// unchanged.
+__host__ __device__ __forceinline__ unsigned sr_fmix(unsigned h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+__host__ __device__ __forceinline__ unsigned sr_xorshift(unsigned x) {
+    x ^= x << 13;
+    x ^= x >> 17;
+    x ^= x << 5;
+    return x;
+}
+// hash of a step, wave-uniform
+__host__ __device__ __forceinline__ unsigned sr_step_hash(unsigned step, unsigned seed) {
+    return sr_fmix(step * 0x9e3779b9u ^ seed);
+}
+struct SrBits {
+    unsigned w[4];
+    __device__ __forceinline__ void make(unsigned site, unsigned step_hash) {
+        w[0] = sr_fmix(site ^ step_hash);
+        w[1] = sr_xorshift(w[0] | 1u);
+        w[2] = sr_xorshift(w[1]);
+        w[3] = sr_xorshift(w[2]);
+    }
+    __device__ __forceinline__ unsigned r13(int q) const {
+        return (q & 1) ? (w[q >> 1] >> 13) & 0x1fffu : w[q >> 1] & 0x1fffu;
+    }
+};
+__device__ __forceinline__ __half half_sr(float v, unsigned r13) {
+    const unsigned b = (__float_as_uint(v) + r13) & 0xffffe000u;
+    return __float2half_rn(__uint_as_float(b));
+}
 
 // ---------------------------------------------------------------------------
 // collision of one site (Algorithm 1, collision block), in registers

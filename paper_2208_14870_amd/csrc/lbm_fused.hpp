@@ -90,6 +90,19 @@ __device__ __forceinline__ void lds_write(S* lds, int r, bool swapped,
     }
 }
 
+// lds_write for half storage with stochastic rounding (bits of the writing
+// site for this step).
+template <int RW, int RN>
+__device__ __forceinline__ void lds_write_sr(__half* lds, int r, bool swapped, const float f[8],
+                                             const SrBits& b) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const __half h = half_sr(f[q], b.r13(q));
+        if (swapped) lds[opp(q) * RN + r] = h;
+        else lds[q * RN + r + lds_shift<RW>(q)] = h;
+    }
+}
+
 // Element i of a plane through a 32-bit byte offset (planes of the tile kernel
 // hold fewer than 2^32 bytes): with a wave-uniform base each access is one
 // scalar base plus one 32-bit vector offset, instead of 64-bit address
@@ -146,13 +159,14 @@ struct SlotGeo {
 // addresses without the periodic wrap; the others wrap every coordinate.
 // stepN_collide1 scales the force, collides and writes the post-collision
 // populations to LDS.
-template <typename S, int TH, int NS, int NT = kBlock>
+template <typename S, int TH, int NS, int NT = kBlock, bool SR = false>
 __device__ __forceinline__ void stepN_load(const S* __restrict__ src,
                                            const typename Store<S>::C* __restrict__ g,
                                            long long plane, int nx, int ny, int x0, int y0,
                                            const SlotGeo<TH, NS, NT>& geo,
                                            typename Store<S>::C f[][8],
-                                           typename Store<S>::C gx[], typename Store<S>::C gy[]) {
+                                           typename Store<S>::C gx[], typename Store<S>::C gy[],
+                                           unsigned sid[]) {
     using Geo = SlotGeo<TH, NS, NT>;
     constexpr int R = Geo::R, NM = Geo::NM;
     using C = typename Store<S>::C;
@@ -180,6 +194,7 @@ __device__ __forceinline__ void stepN_load(const S* __restrict__ src,
             f[a][7] = Store<S>::ld(at_u32(pq[7], cp - 1));
             gx[a] = *glob(at_u32(g, c));
             gy[a] = *glob(at_u32(g1, c));
+            if constexpr (SR) sid[a] = c;
         }
         return;
     }
@@ -202,6 +217,7 @@ __device__ __forceinline__ void stepN_load(const S* __restrict__ src,
         f[a][7] = Store<S>::ld(at_u32(pq[7], rp + xm));
         gx[a] = *glob(at_u32(g, r0 + x));
         gy[a] = *glob(at_u32(g1, r0 + x));
+        if constexpr (SR) sid[a] = r0 + x;
     }
 }
 
@@ -232,7 +248,8 @@ __device__ __forceinline__ void stepN_collide1(typename Store<S>::C f[][8],
                                                const typename Store<S>::C gy[],
                                                typename Store<S>::C hg[][2],
                                                typename Store<S>::C qg[][2],
-                                               typename Store<S>::C up[][2]) {
+                                               typename Store<S>::C up[][2],
+                                               const unsigned sid[], bool sr, unsigned sh) {
 #pragma clang fp contract(off)
     using C = typename Store<S>::C;
     using Geo = SlotGeo<TH, NS, NT>;
@@ -248,7 +265,17 @@ __device__ __forceinline__ void stepN_collide1(typename Store<S>::C f[][8],
         }
         collide_h<C, false>(f[a], hg[a][0], hg[a][1], quarter<S>(hg, qg, a, 0),
                             quarter<S>(hg, qg, a, 1), k, up[a][0], up[a][1]);
-        if (geo.active(a, 0)) lds_write<S, RW, RN>(lds, e, true, f[a]);
+        if (geo.active(a, 0)) {
+            if constexpr (std::is_same<S, __half>::value) {
+                if (sr) {
+                    SrBits b;
+                    b.make(sid[a], sh);
+                    lds_write_sr<RW, RN>(lds, e, true, f[a], b);
+                    continue;
+                }
+            }
+            lds_write<S, RW, RN>(lds, e, true, f[a]);
+        }
     }
 }
 
@@ -307,7 +334,9 @@ __device__ __forceinline__ void stepN_rest(S* __restrict__ dst, long long plane,
                                            const typename Store<S>::C hg[][2],
                                            const typename Store<S>::C qg[][2],
                                            typename Store<S>::C up[][2], double* u,
-                                           double inv_scale, double* partial, double* red) {
+                                           double inv_scale, double* partial, double* red,
+                                           const unsigned sid[], bool sr, unsigned step0,
+                                           unsigned seed) {
     using C = typename Store<S>::C;
     using Geo = SlotGeo<TH, NS, NT>;
     constexpr int R = Geo::R, RW = Geo::RW, RN = Geo::RN, NM = Geo::NM;
@@ -325,7 +354,16 @@ __device__ __forceinline__ void stepN_rest(S* __restrict__ dst, long long plane,
                 lds_read<S, RW, RN>(lds, e, even, f);
                 collide_h<C, false>(f, hg[a][0], hg[a][1], quarter<S>(hg, qg, a, 0),
                                     quarter<S>(hg, qg, a, 1), k, ux, uy);
-                lds_write<S, RW, RN>(lds, e, !even, f);
+                bool rounded = false;
+                if constexpr (std::is_same<S, __half>::value) {
+                    if (sr) {
+                        SrBits b;
+                        b.make(sid[a], sr_step_hash(step0 + (unsigned)m, seed));
+                        lds_write_sr<RW, RN>(lds, e, !even, f, b);
+                        rounded = true;
+                    }
+                }
+                if (!rounded) lds_write<S, RW, RN>(lds, e, !even, f);
                 if (MODE == kCheck && m == R - 1) {
                     up[a][0] = ux;
                     up[a][1] = uy;
@@ -346,8 +384,21 @@ __device__ __forceinline__ void stepN_rest(S* __restrict__ dst, long long plane,
             collide_h<C, false>(f, hg[a][0], hg[a][1], quarter<S>(hg, qg, a, 0),
                                 quarter<S>(hg, qg, a, 1), k, ux, uy);
             const unsigned sidx = (unsigned)y * (unsigned)nx + (unsigned)x;
+            bool rounded = false;
+            if constexpr (std::is_same<S, __half>::value) {
+                if (sr) {
+                    SrBits b;
+                    b.make(sidx, sr_step_hash(step0 + (unsigned)R, seed));
 #pragma unroll
-            for (int q = 0; q < 8; ++q) Store<S>::st(at_u32(pq[q], sidx), f[q]);
+                    for (int q = 0; q < 8; ++q)
+                        Store<__half>::st_h(at_u32(pq[q], sidx), half_sr(f[q], b.r13(q)));
+                    rounded = true;
+                }
+            }
+            if (!rounded) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) Store<S>::st(at_u32(pq[q], sidx), f[q]);
+            }
             if constexpr (MODE == kCheck) {
                 const double uxd = (double)ux * inv_scale, uyd = (double)uy * inv_scale;
                 const double dx = uxd - (double)up[a][0] * inv_scale;
@@ -377,7 +428,10 @@ __device__ __forceinline__ void stepN_rest(S* __restrict__ dst, long long plane,
 
 // MODE kPlain (advance) or kCheck (advance; the last two steps form a
 // residual check, partials per tile as the single-step check writes them).
-template <typename S, int TH, int NS, int NT = kBlock, int MODE = kPlain>
+//
+// SR: half storage with stochastic rounding (a separate instantiation, so
+// that the round-to-nearest kernel keeps its register count and occupancy).
+template <typename S, int TH, int NS, int NT = kBlock, int MODE = kPlain, bool SR = false>
 static __global__ __launch_bounds__(NT) void k_stepN(StepLaunch L) {
     using C = typename Store<S>::C;
     using Geo = SlotGeo<TH, NS, NT>;
@@ -396,14 +450,17 @@ static __global__ __launch_bounds__(NT) void k_stepN(StepLaunch L) {
         k.load(d);
         const int x0 = item.tx * kTW, y0 = item.ty * TH;
         C f[NM][8], gx[NM], gy[NM], hg[NM][2], qg[kKeepQuarter<S> ? NM : 1][2], up[NM][2];
-        stepN_load<S, TH, NS, NT>(reinterpret_cast<const S*>(d.buf[sel]),
+        constexpr bool sr = SR && std::is_same<S, __half>::value;
+        unsigned sid[sr ? NM : 1];  // site index per slot (stochastic rounding)
+        stepN_load<S, TH, NS, NT, sr>(reinterpret_cast<const S*>(d.buf[sel]),
                                   reinterpret_cast<const C*>(d.g), d.plane, d.nx, d.ny, x0, y0,
-                                  geo, f, gx, gy);
-        stepN_collide1<S, TH, NS, NT>(f, k, lds, geo, gx, gy, hg, qg, up);
+                                  geo, f, gx, gy, sid);
+        stepN_collide1<S, TH, NS, NT>(f, k, lds, geo, gx, gy, hg, qg, up, sid, sr,
+                                      sr ? sr_step_hash(d.sr_step, d.sr_seed) : 0u);
         __syncthreads();
         stepN_rest<S, TH, NS, NT, MODE>(reinterpret_cast<S*>(d.buf[sel ^ 1]), d.plane, d.nx, d.ny,
                                         x0, y0, k, lds, geo, hg, qg, up, d.u, d.inv_scale,
-                                        L.partial + 3 * it, red);
+                                        L.partial + 3 * it, red, sid, sr, d.sr_step, d.sr_seed);
     }
 }
 

@@ -259,15 +259,16 @@ inline int fused_nt(int prec, int ns, int th) {
     return th == 16 ? 512 : 256;
 }
 
-template <typename S, int TH, int NT, int NS, int NSMAX>
+template <typename S, int TH, int NT, int NS, int NSMAX, bool SR = false>
 inline bool launch_stepN_ns(int ns, bool check, unsigned grid, hipStream_t st, const StepLaunch& L) {
     if (ns == NS) {
-        if (check) hipLaunchKernelGGL((k_stepN<S, TH, NS, NT, kCheck>), dim3(grid), dim3(NT), 0, st, L);
-        else hipLaunchKernelGGL((k_stepN<S, TH, NS, NT>), dim3(grid), dim3(NT), 0, st, L);
+        if (check)
+            hipLaunchKernelGGL((k_stepN<S, TH, NS, NT, kCheck, SR>), dim3(grid), dim3(NT), 0, st, L);
+        else hipLaunchKernelGGL((k_stepN<S, TH, NS, NT, kPlain, SR>), dim3(grid), dim3(NT), 0, st, L);
         return true;
     }
     if constexpr (NS < NSMAX)
-        return launch_stepN_ns<S, TH, NT, NS + 1, NSMAX>(ns, check, grid, st, L);
+        return launch_stepN_ns<S, TH, NT, NS + 1, NSMAX, SR>(ns, check, grid, st, L);
     return false;
 }
 
@@ -276,7 +277,7 @@ inline bool launch_stepN_ns(int ns, bool check, unsigned grid, hipStream_t st, c
 // two steps form a residual check (partials per tile into L.partial, u(n) into
 // the slot's u planes), replacing a write-u step and a check step.
 inline hipError_t launch_stepN(int prec, int ns, int th, unsigned grid, hipStream_t st,
-                               const StepLaunch& L, bool check = false) {
+                               const StepLaunch& L, bool check = false, bool sr = false) {
     bool ok = false;
     if (prec == LBM_FP64 && th == 8)
         ok = launch_stepN_ns<double, 8, 512, 2, 8>(ns, check, grid, st, L);
@@ -288,6 +289,10 @@ inline hipError_t launch_stepN(int prec, int ns, int th, unsigned grid, hipStrea
         ok = launch_stepN_ns<float, 16, 512, 5, 8>(ns, check, grid, st, L);
     else if (prec == LBM_FP32 && th == 24)
         ok = launch_stepN_ns<float, 24, 512, 2, 8>(ns, check, grid, st, L);
+    else if (prec == LBM_FP16 && th == 12 && sr)
+        ok = launch_stepN_ns<__half, 12, 256, 2, 4, true>(ns, check, grid, st, L);
+    else if (prec == LBM_FP16 && th == 16 && sr)
+        ok = launch_stepN_ns<__half, 16, 512, 2, 8, true>(ns, check, grid, st, L);
     else if (prec == LBM_FP16 && th == 12)
         ok = launch_stepN_ns<__half, 12, 256, 2, 4>(ns, check, grid, st, L);
     else if (prec == LBM_FP16 && th == 16)
@@ -469,6 +474,8 @@ struct Lattice {
     double lam = 0, mu = 0;
     bool has_material = false, has_force = false;
     int e_scale = 0;  // half storage: stored = f * 2^-e
+    bool sr = false;       // half storage rounds stochastically (two buffers, no wavefront)
+    unsigned sr_seed = 0;
     double gmax = 0;  // max |g| of the force (initial half scale)
     // The mean first moments of the exact trajectory: sum_x m10, sum_x m01 were
     // mbase at step mbase_steps and grow by gsum = sum_x g (FP64) per step.
@@ -575,8 +582,11 @@ struct Lattice {
         const double sc = (prec == LBM_FP16) ? std::ldexp(1.0, -e_scale) : 1.0;
         d.gscale = sc;
         d.inv_scale = 1.0 / sc;
+        d.sr = sr_on() ? 1 : 0;
+        d.sr_seed = sr_seed;
         return d;
     }
+    bool sr_on() const { return sr && prec == LBM_FP16 && !inplace; }
     bool general() const { return rates.w12 != 1.0 || rates.w21 != 1.0 || rates.w22 != 1.0; }
 };
 

@@ -3,6 +3,8 @@
 // finalisation of the residual partials.
 #pragma once
 
+#include <type_traits>
+
 #include "lbm_common.hpp"
 
 namespace lbm {
@@ -53,8 +55,21 @@ static __global__ __launch_bounds__(kBlock) void k_step(StepLaunch L) {
             C ux, uy;
             collide<C, GENERAL>(f[j], gx, gy, k, ux, uy);
             if constexpr (LAY == kLayPull) {
+                bool rounded = false;
+                if constexpr (std::is_same<S, __half>::value) {
+                    if (d.sr) {  // stochastic rounding of this step's stores
+                        SrBits b;
+                        b.make((unsigned)s, sr_step_hash(d.sr_step, d.sr_seed));
 #pragma unroll
-                for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * plane + s, f[j][q]);
+                        for (int q = 0; q < 8; ++q)
+                            Store<__half>::st_h(dst + q * plane + s, half_sr(f[j][q], b.r13(q)));
+                        rounded = true;
+                    }
+                }
+                if (!rounded) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) Store<S>::st(dst + q * plane + s, f[j][q]);
+                }
             } else if constexpr (LAY == kLayNatural) {
 #pragma unroll
                 for (int q = 0; q < 8; ++q) Store<S>::st(dst + opp(q) * plane + s, f[j][q]);

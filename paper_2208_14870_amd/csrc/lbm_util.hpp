@@ -333,6 +333,8 @@ static __global__ __launch_bounds__(kBlock) void k_build_items(Item* items, int 
 // Small device-side stores (stream-ordered, safe inside captured graphs).
 static __global__ void k_set_int(int* p, int v) { *p = v; }
 static __global__ void k_set_desc(SlotDesc* p, SlotDesc v) { *p = v; }
+// the step count of the stochastic-rounding bits, after a launch of ns steps
+static __global__ void k_add_sr_step(SlotDesc* p, int ns) { p->sr_step += (unsigned)ns; }
 
 // Neutral modes.  (1) The mean first moments: collision adds g to m10, m01 and
 // streaming permutes, so sum_x m10(f(n)) = sum_x m10(f(0)) + n sum_x gx exactly

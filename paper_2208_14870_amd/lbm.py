@@ -81,6 +81,7 @@ def load() -> ctypes.CDLL:
         "lbm_debug_stream_only": (i, [vp, ll]),
         "lbm_set_time_blocking": (i, [vp, i]),
         "lbm_set_fused_kernel": (i, [vp, i, i]),
+        "lbm_set_stochastic_rounding": (i, [vp, i, ctypes.c_uint]),
         "lbm_set_tile_rows": (i, [vp, i]),
         "lbm_get_launch_config": (i, [vp, pi]),
         "lbm_workspace_bytes_inplace": (sz, [i, i, i]),
@@ -350,6 +351,10 @@ class Solver:
     def set_tile_rows(self, rows: int):
         """Tile height of the LDS tile kernel (0: default); see lbm_set_tile_rows."""
         self._check(self.lib.lbm_set_tile_rows(self.h, int(rows)))
+
+    def set_stochastic_rounding(self, on: bool = True, seed: int = 0):
+        """lbm_set_stochastic_rounding (half storage only)."""
+        self._check(self.lib.lbm_set_stochastic_rounding(self.h, 1 if on else 0, int(seed) & 0xffffffff))
 
     def set_fused_kernel(self, kind: str, segment_rows: int = 256):
         """kind "tile" (LDS tile kernel) or "wavefront" (register wavefront with
