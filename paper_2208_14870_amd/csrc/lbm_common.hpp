@@ -256,7 +256,7 @@ __device__ __forceinline__ void collide_h(C f[8], C hgx, C hgy, C qgx, C qgy, co
         f[3] = b - ey;
         f[4] = s + t1;
         f[6] = s - t1;
-        f[5] = -(s + t2);
+        f[5] = (-s) - t2;  // -(s + t2) in one instruction (round-to-nearest is odd)
         f[7] = t2 - s;
     } else {
         const C m22 = sac + sbd;
