@@ -53,7 +53,7 @@ BYTES_PER_SITE = {"fp64": 144, "fp32": 72, "fp16": 40}  # 8 pops in + 8 out + 2 
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
-TRAFFIC_SOURCES = ("lbm_common.hpp", "lbm_fused.hpp")  # the headers that define the tile kernel
+TRAFFIC_SOURCES = ("lbm_common.hpp", "lbm_fused.hpp")  # the headers that define the fused kernels
 
 
 def kernel_source_hash() -> str:
@@ -193,9 +193,9 @@ def parse():
     ap.add_argument("--large-steps", type=int, default=10000)
     ap.add_argument("--large-warm", type=int, default=200)
     ap.add_argument("--large-tb", type=int, default=0,
-                    help="steps per launch of the 8192^2 runs (0: library default; "
-                         "4 selects the default kernel at that depth, the register "
-                         "wavefront for FP64 and FP32)")
+                    help="steps per launch of the 8192^2 runs (0: library default, "
+                         "the register wavefront at eight steps; the default kernel is "
+                         "kept at other depths)")
     return ap.parse_args()
 
 
@@ -227,7 +227,9 @@ def kernel_label(cfg, ctype, sites):
                 f"{nt} threads): {tb} fused steps per launch, {per_site} B per site-update "
                 f"algorithmic, {tb} x {side}^2 site-updates per launch")
     if cfg["kernel"] == "wavefront":
-        return (f"k_wave<{ctype}, {tb}, V> ({rows}-row segments): {tb} fused steps per launch, "
+        v = cfg.get("columns_per_lane", 1)
+        return (f"k_wave<{ctype}, {tb}, {v}> (register wavefront, {rows}-row segments): {tb} fused "
+                f"steps per launch, "
                 f"{per_site} B per site-update algorithmic, {tb} x {side}^2 site-updates per launch")
     return f"k_step<{ctype}, ...>: one step per launch, {per_site} B per site-update algorithmic"
 
@@ -425,8 +427,9 @@ def large_lattice(steps=10000, warm=200, precs=("fp64", "fp32", "fp16", "fp16sr"
                     "launch_config": cfg,
                     "roofline": roofline(prec, sites, us * steps / launches, tbl,
                                          kernel_label(cfg, ctype, sites),
-                                         f"k_stepN_{prec}_8192_counters"
-                                         if cfg["kernel"] == "tile" and key == prec else None)}
+                                         (f"k_stepN_{prec}_8192_counters" if cfg["kernel"] == "tile"
+                                          else f"k_wave_{prec}_8192_counters")
+                                         if key == prec else None)}
         if key == "fp16sr":
             out[key]["rounding"] = "stochastic (13 random bits per stored population)"
     rx, ry = u.get("fp64", (None, None))

@@ -328,15 +328,13 @@ int lbm_set_tile(lbm_solver *s, int bx_log2, int rows_per_thread, int blocks_per
 /* Temporal blocking: with steps_per_launch = k in 2..8, plain steps run k at a
  * time through one fused kernel, so populations cross HBM once per k steps.
  * Results are identical to single steps.  Residual-check steps, remainders
- * and the general-rates variant run one step per launch.  Overrides the tile
- * shape of lbm_set_tile while active.  Default by storage type and size: FP32
- * and FP16 8 above 2^17 sites, else 4; FP64 5, or 4 above 2^22 sites where the
- * wavefront is the default (also after a polish switch); 4 (the wavefront) for
- * lattices beyond the tile kernel's plane limit (see lbm_set_fused_kernel).  The
- * fused kernel follows the default of lbm_set_fused_kernel for k until the
- * caller picks one; k > 4 always runs the LDS tile kernel (the wavefront runs
- * 2..4 steps), or single steps beyond its plane limit.  Errors:
- * LBM_E_ARG (k outside 1..8), LBM_E_STATE (k != 1 in place). */
+ * and the general-rates variant run one step per launch (with the tile kernel
+ * a check rides on the last fused launch).  Overrides the tile shape of
+ * lbm_set_tile while active.  Default by storage type and size: FP32 and FP16
+ * 8 above 2^17 sites, else 4; FP64 5 below 2^20 sites, else 8 (also after a
+ * polish switch).  The fused kernel follows the default of
+ * lbm_set_fused_kernel for k until the caller picks one.  Errors: LBM_E_ARG
+ * (k outside 1..8), LBM_E_STATE (k != 1 in place). */
 int lbm_set_time_blocking(lbm_solver *s, int steps_per_launch);
 
 /* Tile height of the LDS tile kernel (the tile is 64 columns wide): rows in
@@ -355,9 +353,10 @@ enum lbm_fused_kernel {
      * 16 above. */
     LBM_FUSED_TILE = 0,
     /* Register wavefront: a wave owns a strip of columns (one per lane, or
-     * two per lane for FP32/FP16 on even widths) with a ring of k columns
-     * per side (4 with two per lane) and marches along y through segments of
-     * `segment_rows` rows, keeping three rows of every intermediate step in
+     * two per lane for FP32/FP16 on even widths) with a ring of k columns per
+     * side (with two per lane: 4 for k <= 4, k rounded up to even above) and
+     * marches along y through segments of `segment_rows` rows, keeping the
+     * rows of every intermediate step that the next one still reads in
      * registers (x neighbours through cross-lane moves); no LDS. */
     LBM_FUSED_WAVEFRONT = 1
 };
@@ -365,15 +364,15 @@ enum lbm_fused_kernel {
 /* Select the fused kernel for steps_per_launch >= 2.  segment_rows (1..2^20)
  * is used by LBM_FUSED_WAVEFRONT only: each strip is split into segments of
  * that many rows, each recomputing 2k halo rows.  Default (until this is
- * called, and again after a polish switch): for k <= 4 the wavefront on FP64
- * lattices of more than 2^22 sites and on even-width FP32 lattices of at least
- * 2^25 sites, with the tallest segment of 256, 128, 64 or 32 rows that still
- * gives 18 waves per compute unit; the tile kernel otherwise.  The tile kernel
- * addresses a plane with 32-bit byte offsets, so a lattice whose planes hold
- * 2^32 bytes or more in the arithmetic type (above 2^30 FP32/FP16 or 2^29 FP64
- * sites) defaults to the wavefront at four steps per launch whatever its
- * width; at more than four steps it runs single steps.  Errors:
- * LBM_E_ARG, LBM_E_STATE (the wavefront with steps_per_launch > 4). */
+ * called, and again after a polish switch), measured: the wavefront for FP64
+ * lattices from 2^20 sites, FP32 from 2^22 (two columns per lane from 2^25 on
+ * even widths) and FP16 from 2^24, with segments of 128 rows from 2^24 sites
+ * and 32 below (halved down to 32 while the lattice would give fewer than 8
+ * waves per compute unit); the tile kernel otherwise.  The tile kernel addresses a plane
+ * with 32-bit byte offsets, so a lattice whose planes hold 2^32 bytes or more
+ * in the arithmetic type (above 2^30 FP32/FP16 or 2^29 FP64 sites) defaults
+ * to the wavefront whatever its width.  Errors: LBM_E_ARG, LBM_E_STATE
+ * (in place, or the wavefront with stochastic rounding). */
 int lbm_set_fused_kernel(lbm_solver *s, int kind, int segment_rows);
 
 /* Optional, half storage (LBM_FP16) with two buffers: on = 1 rounds every
@@ -394,6 +393,11 @@ int lbm_set_stochastic_rounding(lbm_solver *s, int on, unsigned int seed);
  * rows per thread (one step per launch); out[3] threads per workgroup.
  * out is a host array of 4 ints.  Errors: LBM_E_ARG. */
 int lbm_get_launch_config(const lbm_solver *s, int out[4]);
+
+/* Columns per lane of the register wavefront when plain steps run through it
+ * (1 or 2: a wave's strip is 64 or 128 columns, of which 2 x ring are
+ * recomputed neighbours), 0 otherwise.  Errors: LBM_E_ARG. */
+int lbm_get_wave_columns(const lbm_solver *s);
 
 /* Diagnostic: nsteps of streaming alone (no collision), for bit-exact checks
  * of the periodic index arithmetic (Eq. streaming, Sec. 6.1). */

@@ -172,7 +172,7 @@ struct lbm_solver {
     hipError_t enqueue_fused(int ns, hipStream_t st, long long& ph) {
         hipError_t e =
             L.wave_hs > 0
-                ? launch_wave(L.prec, ns, L.nx, L.ny, L.wave_hs, d_desc, (int)(ph & 1), st)
+                ? launch_wave(L.prec, ns, L.wave_v, L.nx, L.ny, L.wave_hs, d_desc, (int)(ph & 1), st)
                 : launch_stepN(L.prec, ns, L.th, grid, st, launch_args((int)(ph & 1)), false,
                                L.sr_on());
         ++ph;  // one buffer flip for ns steps
@@ -183,7 +183,7 @@ struct lbm_solver {
     // Whether a remainder of r < L.tb plain steps runs as one fused launch.
     bool fused_rest(long long r) const {
         return L.fused() && r >= 2 &&
-               (L.wave_hs > 0 ? r <= 4 : stepN_supported(L.prec, (int)r, L.th));
+               (L.wave_hs > 0 ? r <= 8 : stepN_supported(L.prec, (int)r, L.th));
     }
 
     hipError_t enqueue_finalize(hipStream_t st) {
@@ -394,11 +394,11 @@ static int create_solver(int nx, int ny, int precision, int with_polish, bool in
     L.inplace = inplace;
     default_tile(precision, nx, ny, L.bx_log2, L.vy);
     L.tb = inplace ? 1 : default_time_blocking(precision, (long long)nx * ny);
-    // planes beyond the tile kernel's 32-bit offsets: the wavefront at four steps
-    if (!L.tile_fits()) L.tb = std::min(L.tb, 4);
     L.th = fused_th(precision, L.tb, (long long)nx * ny);
-    L.wave_hs = inplace ? 0 : default_fused_wave_rows(precision, L.tb, nx, ny, s->cus,
-                                                      !L.tile_fits());
+    // planes beyond the tile kernel's 32-bit offsets: the wavefront, any width
+    const FusedChoice fc = default_fused(precision, L.tb, nx, ny, s->cus, !L.tile_fits());
+    L.wave_hs = inplace ? 0 : fc.wave_hs;
+    L.wave_v = fc.wave_v;
     char* base = reinterpret_cast<char*>(workspace);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -634,12 +634,13 @@ int lbm_set_time_blocking(lbm_solver* s, int steps_per_launch) {
     Lattice& L = s->L;
     L.tb = steps_per_launch;
     L.th = fused_th(L.prec, steps_per_launch, L.N, L.th_user);
-    if (s->fused_auto)
-        L.wave_hs = default_fused_wave_rows(L.prec, steps_per_launch, L.nx, L.ny, s->cus,
-                                            !L.tile_fits());
+    if (s->fused_auto) {
+        const FusedChoice fc = default_fused(L.prec, steps_per_launch, L.nx, L.ny, s->cus,
+                                             !L.tile_fits());
+        L.wave_hs = fc.wave_hs;
+    }
+    L.wave_v = wave_cols(L.prec, steps_per_launch, L.nx, L.ny);
     if (L.sr) L.wave_hs = 0;  // the wavefront has no stochastic rounding
-    else if (steps_per_launch > 4)
-        L.wave_hs = 0;  // the wavefront runs 2..4 steps
     return s->sync_desc();
 }
 
@@ -669,11 +670,8 @@ int lbm_set_fused_kernel(lbm_solver* s, int kind, int segment_rows) {
                                         "or single-step kernels");
         if (segment_rows < 1 || segment_rows > (1 << 20))
             return s->fail(LBM_E_ARG, "set_fused_kernel: segment_rows must be in 1..2^20");
-        if (s->L.tb > 4)
-            return s->fail(LBM_E_STATE,
-                           "set_fused_kernel: the wavefront runs 2..4 steps per launch "
-                           "(set_time_blocking first)");
         s->L.wave_hs = segment_rows;
+        s->L.wave_v = wave_cols(s->L.prec, s->L.tb, s->L.nx, s->L.ny);
         s->fused_auto = false;
     } else {
         return s->fail(LBM_E_ARG, "set_fused_kernel: kind must be LBM_FUSED_TILE or LBM_FUSED_WAVEFRONT");
@@ -712,6 +710,11 @@ int lbm_get_launch_config(const lbm_solver* s, int out[4]) {
         out[3] = fused_nt(L.prec, L.tb, L.th);
     }
     return LBM_OK;
+}
+
+int lbm_get_wave_columns(const lbm_solver* s) {
+    if (!s) return LBM_E_ARG;
+    return (s->L.fused() && s->L.wave_hs > 0) ? s->L.wave_v : 0;
 }
 
 int lbm_step(lbm_solver* s, long long nsteps) {
@@ -758,9 +761,10 @@ int promote_solver(lbm_solver* s) {
     s->phase = 0;
     default_tile(LBM_FP64, L.nx, L.ny, L.bx_log2, L.vy);
     L.tb = default_time_blocking(LBM_FP64, L.N);
-    if (!L.tile_fits()) L.tb = std::min(L.tb, 4);
     L.th = fused_th(LBM_FP64, L.tb, L.N);
-    L.wave_hs = default_fused_wave_rows(LBM_FP64, L.tb, L.nx, L.ny, s->cus, !L.tile_fits());
+    const FusedChoice fc = default_fused(LBM_FP64, L.tb, L.nx, L.ny, s->cus, !L.tile_fits());
+    L.wave_hs = fc.wave_hs;
+    L.wave_v = fc.wave_v;
     s->fused_auto = true;
     // sync_desc folds phase into cur: phase is 0 so cur stays 0
     int rc = s->sync_desc();

@@ -478,8 +478,12 @@ static __global__ __launch_bounds__(NT) void k_stepN(StepLaunch L) {
 // output.  No LDS and no barrier; every intermediate level is rounded to the
 // storage type exactly as a store would round it, so the result equals NS
 // single steps bit for bit.  V = 2 (FP32, FP16) needs an even nx, so that a
-// lane's column pair stays adjacent across the periodic wrap; its ring is 4
-// columns for every NS so that pairs stay aligned.
+// lane's column pair stays adjacent across the periodic wrap; its ring is an
+// even number of columns (wave_ring) so that pairs stay aligned.  NS = 2..8:
+// the deep variants keep a level's rows only as long as the next level reads
+// them (the compiler's liveness does this over the unrolled row loop), and
+// run at one or two waves per SIMD on registers alone (FP32 with V = 2 at
+// eight steps: 423 registers, the excess in accumulation registers).
 __device__ __forceinline__ float lane_from_left(float v) {  // lane l <- lane l-1
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
 }
@@ -539,8 +543,10 @@ template <> struct VecIO<__half, 2> {
     }
 };
 
+// Ring columns per side: NS for one column per lane; with two, an even number
+// of at least four, so that a lane's column pair stays aligned.
 template <int NS, int V>
-__host__ __device__ constexpr int wave_ring() { return V == 1 ? NS : 4; }
+__host__ __device__ constexpr int wave_ring() { return V == 1 ? NS : (NS <= 4 ? 4 : (NS + 1) / 2 * 2); }
 template <int NS, int V>
 __host__ __device__ constexpr int wave_width() { return kWave * V - 2 * wave_ring<NS, V>(); }
 

@@ -327,21 +327,28 @@ inline hipError_t launch_solve_small(int prec, bool general, hipStream_t st, con
 // segments of hs rows; two columns per lane for FP32/FP16 on even-width lattices.
 template <typename S, int V>
 inline void launch_wave_t(int ns, unsigned grid, hipStream_t st, const WaveLaunch& W) {
-    if (ns == 2) hipLaunchKernelGGL((k_wave<S, 2, V>), dim3(grid), dim3(kBlock), 0, st, W);
-    else if (ns == 3) hipLaunchKernelGGL((k_wave<S, 3, V>), dim3(grid), dim3(kBlock), 0, st, W);
-    else hipLaunchKernelGGL((k_wave<S, 4, V>), dim3(grid), dim3(kBlock), 0, st, W);
+    switch (ns) {
+        case 2: hipLaunchKernelGGL((k_wave<S, 2, V>), dim3(grid), dim3(kBlock), 0, st, W); break;
+        case 3: hipLaunchKernelGGL((k_wave<S, 3, V>), dim3(grid), dim3(kBlock), 0, st, W); break;
+        case 4: hipLaunchKernelGGL((k_wave<S, 4, V>), dim3(grid), dim3(kBlock), 0, st, W); break;
+        case 5: hipLaunchKernelGGL((k_wave<S, 5, V>), dim3(grid), dim3(kBlock), 0, st, W); break;
+        case 6: hipLaunchKernelGGL((k_wave<S, 6, V>), dim3(grid), dim3(kBlock), 0, st, W); break;
+        case 7: hipLaunchKernelGGL((k_wave<S, 7, V>), dim3(grid), dim3(kBlock), 0, st, W); break;
+        default: hipLaunchKernelGGL((k_wave<S, 8, V>), dim3(grid), dim3(kBlock), 0, st, W); break;
+    }
 }
 
-inline int wave_cols_per_lane(int prec, int nx) { return (prec != LBM_FP64 && nx % 2 == 0) ? 2 : 1; }
-
+// Output columns of a wave's strip (64 V columns less the ring on each side).
 inline int wave_width_of(int ns, int v) {
-    if (v == 2) return wave_width<4, 2>();
-    return ns == 2 ? wave_width<2, 1>() : ns == 3 ? wave_width<3, 1>() : wave_width<4, 1>();
+    const int ring = v == 1 ? ns : (ns <= 4 ? 4 : (ns + 1) / 2 * 2);
+    return kWave * v - 2 * ring;
 }
 
-inline hipError_t launch_wave(int prec, int ns, int nx, int ny, int hs, const SlotDesc* slots,
-                              int flip, hipStream_t st) {
-    const int v = wave_cols_per_lane(prec, nx);
+// v: columns per lane (2 needs an even nx and non-FP64 storage).
+inline hipError_t launch_wave(int prec, int ns, int v, int nx, int ny, int hs,
+                              const SlotDesc* slots, int flip, hipStream_t st) {
+    if (ns < 2 || ns > 8 || hs < 1 || (v == 2 && (prec == LBM_FP64 || nx % 2 != 0)))
+        return hipErrorInvalidValue;
     const int w = wave_width_of(ns, v);
     WaveLaunch W;
     W.slots = slots;
@@ -359,48 +366,58 @@ inline hipError_t launch_wave(int prec, int ns, int nx, int ny, int hs, const Sl
     return hipGetLastError();
 }
 
-// Default fused kernel at up to four steps per launch (measured on MI355X):
-// the register wavefront for FP64 lattices of more than 2^22 sites (2048^2:
-// tile 99 against 87 GLUPS; 2896^2: wavefront 106 against 97) and for
-// even-width FP32 lattices of at least 2^25 sites, the LDS tile kernel
-// otherwise (smaller lattices, FP16).  The
-// segment height is the tallest of 256, 128, 64, 32 rows that still gives
-// 18 waves per compute unit (fewer leave SIMDs idle; shorter segments
-// recompute more halo rows).  Returns the segment height, 0 for the tile kernel.
-// `beyond_tile`: the lattice's planes exceed what the tile kernel addresses
-// (2^32 bytes in the arithmetic type), so the wavefront is the only fused kernel.
-inline int default_wave_rows(int prec, int nx, int ny, int cus, bool beyond_tile = false) {
+// Default fused kernel of a single lattice of N = nx ny sites, measured on
+// MI355X (GLUPS, eight steps per launch: tile kernel / wavefront with one
+// column per lane / with two):
+//   FP32  8192^2 295 / 350 / 432, 4096^2 263 / 335 / 312, 2048^2 239 / 297 / 277,
+//         1024^2 214 / 182 / 164;
+//   FP16  8192^2 380 / 425 / 397, 4096^2 359 / 366 / 288, 2048^2 346 / 269 / 225;
+//   FP64  8192^2 117 / 235, 4096^2 119 / 223, 2048^2 115 / 160, 1024^2 102 / 133
+// (FP64 tile at five steps).  So: the wavefront at eight steps for FP64 from
+// 2^20 sites, FP32 from 2^22 (two columns per lane from 2^25 on even widths)
+// and FP16 from 2^24; the tile kernel below.  Segments of 128 rows from 2^24
+// sites, of 32 below (shorter ones cost more halo than their extra waves gain:
+// FP64 1024^2 91 GLUPS at 16 rows against 133 at 32), halved down to 32 while
+// the lattice would give fewer than eight waves per compute unit.  `beyond_tile`: the planes exceed the tile kernel's
+// 32-bit offsets, so the wavefront (one column per lane, any width) is the
+// only fused kernel.  wave_hs = 0 selects the tile kernel.
+struct FusedChoice {
+    int wave_hs = 0, wave_v = 1;
+};
+// Columns per lane of the wavefront at ns steps: two for FP32 / FP16 on even
+// widths at up to four steps (ring of four), and for FP32 from 2^25 sites at
+// more; one otherwise.
+inline int wave_cols(int prec, int ns, int nx, int ny) {
+    if (prec == LBM_FP64 || nx % 2 != 0) return 1;
+    if (ns <= 4) return 2;
+    return (prec == LBM_FP32 && (long long)nx * ny >= (1LL << 25)) ? 2 : 1;
+}
+inline FusedChoice default_fused(int prec, int ns, int nx, int ny, int cus, bool beyond_tile = false) {
+    FusedChoice c;
     const long long n = (long long)nx * ny;
-    const bool use = beyond_tile || (prec == LBM_FP64 && n > (1LL << 22)) ||
-                     (prec == LBM_FP32 && n >= (1LL << 25) && nx % 2 == 0);
-    if (!use) return 0;
-    const long long strips = (nx + wave_width_of(4, wave_cols_per_lane(prec, nx)) - 1) /
-                             wave_width_of(4, wave_cols_per_lane(prec, nx));
-    for (int hs = 256; hs > 32; hs /= 2)
-        if (strips * ((ny + hs - 1) / hs) >= 18LL * cus) return hs;
-    return 32;
+    const bool wave = beyond_tile || (prec == LBM_FP64 && n >= (1LL << 20)) ||
+                      (prec == LBM_FP32 && n >= (1LL << 22)) || (prec == LBM_FP16 && n >= (1LL << 24));
+    if (!wave || ns < 2) return c;
+    c.wave_v = wave_cols(prec, ns, nx, ny);
+    const long long strips = (nx + wave_width_of(ns, c.wave_v) - 1) / wave_width_of(ns, c.wave_v);
+    int hs = n >= (1LL << 24) ? 128 : 32;
+    while (hs > 32 && strips * ((ny + hs - 1) / hs) < 8LL * cus) hs /= 2;
+    c.wave_hs = hs;
+    return c;
 }
 
 // Default steps per launch for `sites` lattice sites (of one lattice, or of
 // all lattices of one storage type in a batch), measured on MI355X: the LDS
 // tile kernel is bound by its per-launch memory phase, so deeper blocking pays
 // until LDS limits the workgroups per CU.  FP32 and FP16: eight above 2^17
-// sites (FP32 1024^2: 232 against 149 GLUPS, 8192^2: 269 against 206 for the
-// four-step wavefront; FP16 1024^2: 280 against 218, 8192^2: 361 against
-// 330), four on smaller lattices (FP32 256^2: 49 against 42).  FP64 (whose LDS
-// tile is twice as large): five through the tile kernel (1024^2: 106 against
-// 98 GLUPS at four), four where the register wavefront is the default (more
-// than 2^22 sites of a single lattice; a batch always runs tiles).
+// sites (FP32 1024^2: 232 against 149 GLUPS at four), four on smaller lattices
+// (FP32 256^2: 49 against 42).  FP64 (whose LDS tile is twice as large): five
+// through the tile kernel (1024^2: 106 against 98 GLUPS at four), eight where
+// the register wavefront is the default (from 2^20 sites of a single lattice;
+// a batch always runs tiles).
 inline int default_time_blocking(int prec, long long sites, bool tiles_only = false) {
-    if (prec == LBM_FP64) return (tiles_only || sites <= (1LL << 22)) ? 5 : 4;
+    if (prec == LBM_FP64) return (tiles_only || sites < (1LL << 20)) ? 5 : 8;
     return sites > (1LL << 17) ? 8 : 4;
-}
-
-// Default fused kernel for `ns` steps per launch: the register wavefront runs
-// two to four steps, so deeper blocking uses the tile kernel.
-inline int default_fused_wave_rows(int prec, int ns, int nx, int ny, int cus,
-                                   bool beyond_tile = false) {
-    return ns <= 4 ? default_wave_rows(prec, nx, ny, cus, beyond_tile) : 0;
 }
 
 inline hipError_t launch_step(int prec, int mode, bool general, int vy, int layout, unsigned grid,
@@ -541,6 +558,7 @@ struct Lattice {
     int th = 16;      // tile height of the fused LDS kernel (fused_th)
     int th_user = 0;  // tile height chosen by the caller (0: the default)
     int wave_hs = 0;  // > 0: fused launches use the register wavefront, segments of wave_hs rows
+    int wave_v = 1;   // the wavefront's columns per lane
     int cur = 0;      // buffer with the state at flip 0
     bool inplace = false;  // one buffer, in-place streaming (layout alternates per step)
     // layout of the stored field for buffer selector `sel` = cur ^ launch parity

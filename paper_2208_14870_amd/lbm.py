@@ -84,6 +84,7 @@ def load() -> ctypes.CDLL:
         "lbm_set_stochastic_rounding": (i, [vp, i, ctypes.c_uint]),
         "lbm_set_tile_rows": (i, [vp, i]),
         "lbm_get_launch_config": (i, [vp, pi]),
+        "lbm_get_wave_columns": (i, [vp]),
         "lbm_workspace_bytes_inplace": (sz, [i, i, i]),
         "lbm_create_inplace": (i, [i, i, i, vp, sz, vp, ctypes.POINTER(vp)]),
         "lbm_last_error": (ctypes.c_char_p, [vp]),
@@ -346,7 +347,10 @@ class Solver:
         out = (ctypes.c_int * 4)()
         self._check(self.lib.lbm_get_launch_config(self.h, out))
         kind = {0: "tile", 1: "wavefront"}.get(out[1], "single")
-        return {"steps_per_launch": out[0], "kernel": kind, "rows": out[2], "threads": out[3]}
+        cfg = {"steps_per_launch": out[0], "kernel": kind, "rows": out[2], "threads": out[3]}
+        if kind == "wavefront":
+            cfg["columns_per_lane"] = self.lib.lbm_get_wave_columns(self.h)
+        return cfg
 
     def set_tile_rows(self, rows: int):
         """Tile height of the LDS tile kernel (0: default); see lbm_set_tile_rows."""

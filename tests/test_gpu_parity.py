@@ -310,7 +310,7 @@ def test_full_size_8192_sampled(prec, tol):
 def test_beyond_the_tile_kernel_limit(kind, nx):
     """About 1.08e9 FP32 sites, above the 2^30 whose planes the tile kernel
     addresses with 32-bit offsets: by default such lattices run the register
-    wavefront at four steps (two columns per lane on even widths, one on odd),
+    wavefront at eight steps (two columns per lane on even widths, one on odd),
     which like single steps addresses the planes with 64-bit offsets.
     Displacement after 6 steps from f = 0 at sampled sites (corners and edges
     included) against the oracle on light-cone windows of the same force values."""
@@ -333,7 +333,8 @@ def test_beyond_the_tile_kernel_limit(kind, nx):
     cfg = s.launch_config()
     say(f"  launch config {cfg}")
     if kind == "default":
-        assert cfg["kernel"] == "wavefront" and cfg["steps_per_launch"] == 4
+        assert cfg["kernel"] == "wavefront" and cfg["steps_per_launch"] == 8
+        assert cfg["columns_per_lane"] == (2 if nx % 2 == 0 else 1)
     else:
         assert cfg["kernel"] == "single"
     s.step(steps)
@@ -478,18 +479,22 @@ def test_persistent_tile_identical_to_single_steps(prec, nx, ny, steps, bpc):
     ("fp64", 257, 48, 12, 7), ("fp32", 2, 2, 5, 3), ("fp32", 65, 17, 9, 5), ("fp32", 200, 70, 12, 32),
     ("fp16", 5, 3, 5, 2), ("fp16", 97, 31, 8, 9), ("fp64", 1024, 1024, 8, 256),
     ("fp32", 4, 3, 6, 1), ("fp32", 256, 48, 10, 16), ("fp16", 2, 2, 5, 3), ("fp16", 130, 20, 8, 6),
-    ("fp32", 1024, 64, 8, 32)])
+    ("fp32", 1024, 64, 8, 32), ("fp32", 300, 130, 19, 24), ("fp16", 301, 77, 17, 12),
+    ("fp64", 260, 90, 17, 20)])
 def test_wavefront_identical_to_single_steps(prec, nx, ny, steps, rows):
-    """The register-wavefront fused kernel (one column per lane: strips of 64 - 2k
-    columns; two columns per lane for FP32/FP16 on even widths: strips of 120;
-    segments of `rows` rows, several strips and segments, ragged edges, lattices
-    narrower than a strip) gives populations bit-identical to single steps, with
-    residual checks interleaved; the FP64 result matches the oracle."""
+    """The register-wavefront fused kernel at 2..8 steps per launch (one column
+    per lane: strips of 64 - 2k columns; two columns per lane for FP32/FP16 on
+    even widths: strips of 128 - 2 ring, the ring 4 up to four steps and k
+    rounded up to even above; segments of `rows` rows, several strips and
+    segments, ragged edges, lattices narrower than a strip) gives populations
+    bit-identical to single steps, with residual checks interleaved; the FP64
+    result matches the oracle."""
     say(f"wavefront {prec} {nx}x{ny} steps {steps} rows {rows}")
     mat = P.Material.from_shear_poisson(0.9, 0.3)
     f0, gx, gy = _rand_state(nx, ny, 5 + nx)
     res = {}
-    for tb in (1, 2, 3, 4):
+    depths = (1, 2, 3, 4, 5, 6, 7, 8)
+    for tb in depths:
         s = _solver(nx, ny, prec)
         s.set_material(mat.lame_lambda, mat.lame_mu)
         s.set_body_force(dev(gx), dev(gy))
@@ -500,7 +505,7 @@ def test_wavefront_identical_to_single_steps(prec, nx, ny, steps, rows):
         a = host(s.populations())
         n, r, st = s.solve_to_tol(0.0, 11, 5)
         res[tb] = (a, host(s.populations()), n, r)
-    for tb in (2, 3, 4):
+    for tb in depths[1:]:
         np.testing.assert_array_equal(res[tb][0], res[1][0])
         np.testing.assert_array_equal(res[tb][1], res[1][1])
         assert res[tb][2] == res[1][2] and res[tb][3] == pytest.approx(res[1][3], rel=1e-12)
@@ -510,9 +515,9 @@ def test_wavefront_identical_to_single_steps(prec, nx, ny, steps, rows):
 
 
 def test_fused_kernel_argument_errors():
-    """Steps per launch outside 1..8 and the wavefront beyond four steps are
-    refused; deeper blocking switches a wavefront solver to the tile kernel,
-    with results unchanged."""
+    """Steps per launch outside 1..8 and a segment height of 0 are refused; a
+    wavefront solver keeps the wavefront at deeper blocking (with two columns
+    per lane the ring widens to the depth), with results unchanged."""
     from paper_2208_14870_amd import lbm
     s = _solver(16, 16, "fp32")
     with pytest.raises(lbm.LbmError):
@@ -524,8 +529,8 @@ def test_fused_kernel_argument_errors():
         with pytest.raises(lbm.LbmError):
             s.set_time_blocking(bad)
     s.set_time_blocking(6)
-    with pytest.raises(lbm.LbmError):
-        s.set_fused_kernel("wavefront", 16)
+    s.set_fused_kernel("wavefront", 16)
+    assert s.launch_config()["kernel"] == "wavefront"
     mat = P.Material.from_shear_poisson(0.9, 0.3)
     f0, gx, gy = _rand_state(40, 24, 11)
     out = []
@@ -537,7 +542,7 @@ def test_fused_kernel_argument_errors():
         s.set_time_blocking(4)
         s.set_fused_kernel("wavefront", 8)
         if deep:
-            s.set_time_blocking(8)  # leaves the wavefront for the tile kernel
+            s.set_time_blocking(8)  # the wavefront at eight steps
         s.step(16)
         out.append(host(s.populations()))
         s.close()
@@ -547,33 +552,40 @@ def test_fused_kernel_argument_errors():
 def test_launch_config_defaults():
     """Default plain-step launches: eight steps per launch through the LDS tile
     (16 rows, 512 threads) for FP32 and FP16 above 2^17 sites, four below; FP64
-    five steps through 8-row tiles of 512 threads, or four through the
-    wavefront above 2^22 sites; deeper
-    blocking leaves the wavefront; one step per launch in place."""
+    five steps through 8-row tiles of 512 threads below 2^20 sites; the register
+    wavefront at eight steps for FP64 from 2^20 sites, FP32 from 2^22 (two
+    columns per lane from 2^25 on even widths) and FP16 from 2^24; the caller's
+    depth keeps the default kernel, the caller's kernel stays; one step per
+    launch in place."""
     from paper_2208_14870_amd import lbm
     need_gpu()
     cfg = lambda n, m, p, **kw: lbm.Solver(n, m, p, **kw).launch_config()
     assert cfg(1024, 1024, "fp32") == {"steps_per_launch": 8, "kernel": "tile", "rows": 16,
                                        "threads": 512}
-    assert cfg(4096, 4096, "fp16") == {"steps_per_launch": 8, "kernel": "tile", "rows": 16,
+    assert cfg(2048, 1024, "fp16") == {"steps_per_launch": 8, "kernel": "tile", "rows": 16,
                                        "threads": 512}
     assert cfg(256, 256, "fp16") == {"steps_per_launch": 4, "kernel": "tile", "rows": 12,
                                      "threads": 256}
     assert cfg(256, 256, "fp32") == {"steps_per_launch": 4, "kernel": "tile", "rows": 8,
                                      "threads": 512}
-    assert cfg(1024, 1024, "fp64") == {"steps_per_launch": 5, "kernel": "tile", "rows": 8,
-                                       "threads": 512}
-    assert cfg(2048, 2048, "fp64")["kernel"] == "tile"
+    assert cfg(512, 512, "fp64") == {"steps_per_launch": 5, "kernel": "tile", "rows": 8,
+                                     "threads": 512}
+    for n, m, p, rows, v in ((1024, 1024, "fp64", 32, 1), (4096, 4096, "fp64", 128, 1),
+                             (2048, 2048, "fp32", 32, 1), (4096, 4096, "fp32", 128, 1),
+                             (8192, 8192, "fp32", 128, 2), (8191, 8192, "fp32", 128, 1),
+                             (4096, 4096, "fp16", 128, 1)):
+        assert cfg(n, m, p) == {"steps_per_launch": 8, "kernel": "wavefront", "rows": rows,
+                                "threads": 256, "columns_per_lane": v}, (n, m, p)
     s = lbm.Solver(2900, 2900, "fp64")
     c = s.launch_config()
-    assert c["kernel"] == "wavefront" and c["steps_per_launch"] == 4 and c["rows"] in (32, 64, 128, 256)
+    assert c["kernel"] == "wavefront" and c["steps_per_launch"] == 8
     s.set_time_blocking(6)
-    assert s.launch_config() == {"steps_per_launch": 6, "kernel": "tile", "rows": 8, "threads": 512}
-    s.set_time_blocking(3)  # default kernel again at three steps
+    assert s.launch_config()["kernel"] == "wavefront"
+    s.set_time_blocking(3)
     assert s.launch_config()["kernel"] == "wavefront"
     s.set_fused_kernel("tile")
     s.set_time_blocking(4)  # the caller's choice stays
-    assert s.launch_config()["kernel"] == "tile"
+    assert s.launch_config() == {"steps_per_launch": 4, "kernel": "tile", "rows": 8, "threads": 512}
     s.set_time_blocking(1)
     assert s.launch_config()["kernel"] == "single"
     s.close()

@@ -1,7 +1,7 @@
 """Seeded random configurations of the whole solver surface.
 
 Single lattices: random shapes (1..300 per side), storage types, fused kernels
-(LDS tile at 2..8 steps per launch, register wavefront at 2..4 with random
+(LDS tile at 2..8 steps per launch, register wavefront at 2..8 with random
 segment heights, in-place streaming), random step counts and residual-checked
 runs, each against the same lattice stepped once per launch: populations and
 displacement bit-identical, the checked residual equal to rounding of its
@@ -78,7 +78,7 @@ def test_random_single_lattices(seed):
     for case in range(100):
         nx, ny = _side(rng), _side(rng)
         kind = str(rng.choice(["tile", "tile", "wavefront", "inplace"]))
-        tb = {"tile": int(rng.integers(2, 9)), "wavefront": int(rng.integers(2, 5)), "inplace": 1}[kind]
+        tb = {"tile": int(rng.integers(2, 9)), "wavefront": int(rng.integers(2, 9)), "inplace": 1}[kind]
         steps = int(rng.integers(1, 40))
         cfg = dict(case=case, nx=nx, ny=ny, prec=str(rng.choice(["fp64", "fp32", "fp16"])),
                    kind=kind, tb=tb, seg=int(rng.choice([1, 3, 8, 17, 64, 256])), steps=steps,
@@ -171,7 +171,7 @@ def test_random_solves():
         prec = str(rng.choice(["fp64", "fp32", "fp16"]))
         polish = prec != "fp64" and bool(rng.random() < 0.7)
         kind = str(rng.choice(["tile", "wavefront"] if polish else ["tile", "tile", "wavefront", "inplace"]))
-        tb = {"tile": int(rng.integers(2, 9)), "wavefront": int(rng.integers(2, 5)), "inplace": 1}[kind]
+        tb = {"tile": int(rng.integers(2, 9)), "wavefront": int(rng.integers(2, 9)), "inplace": 1}[kind]
         K = int(rng.choice([1, 2, 3, 7, 50, 100, 333]))
         tol = float(rng.choice([1e-6, 1e-8, 1e-10])) if (prec == "fp64" or polish) else 1e-5
         mat = _material(rng)

@@ -1,5 +1,5 @@
 """Seeded sweep over lattice shapes near the kernels' geometric edges (strip
-widths 56/60/120 +-1, tile widths 64 +-1, single rows and columns, segment
+widths 48/56/60/112/120 +-1, tile widths 64 +-1, single rows and columns, segment
 heights that do not divide ny): every fused kernel and the in-place solver give
 populations bit-identical to single steps."""
 import numpy as np
@@ -13,7 +13,8 @@ pytestmark = pytest.mark.gpu
 
 def _shapes(seed, count):
     rng = np.random.default_rng(seed)
-    edges = [1, 2, 3, 55, 56, 57, 59, 60, 61, 63, 64, 65, 119, 120, 121, 122, 128, 129, 240, 241]
+    edges = [1, 2, 3, 47, 48, 49, 55, 56, 57, 59, 60, 61, 63, 64, 65, 111, 112, 113, 119, 120, 121,
+             122, 128, 129, 240, 241]
     out = []
     for _ in range(count):
         nx = int(rng.choice(edges)) if rng.random() < 0.7 else int(rng.integers(1, 300))
@@ -40,7 +41,7 @@ def test_shape_sweep(prec, seed):
         f0, gx, gy = _state(nx, ny, seed * 1000 + k)
         steps = int(rng.integers(5, 14))
         configs = [("single", 1, None), ("tile", int(rng.integers(2, 9)), None),
-                   ("wavefront", int(rng.integers(2, 5)), int(rng.choice([1, 2, 3, 7, 16, 64]))),
+                   ("wavefront", int(rng.integers(2, 9)), int(rng.choice([1, 2, 3, 7, 16, 64]))),
                    ("inplace", 1, None)]
         ref = None
         for kind, tb, rows in configs:
