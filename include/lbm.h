@@ -372,7 +372,7 @@ enum lbm_fused_kernel {
  * with 32-bit byte offsets, so a lattice whose planes hold 2^32 bytes or more
  * in the arithmetic type (above 2^30 FP32/FP16 or 2^29 FP64 sites) defaults
  * to the wavefront whatever its width.  Errors: LBM_E_ARG, LBM_E_STATE
- * (in place, or the wavefront with stochastic rounding). */
+ * (in place). */
 int lbm_set_fused_kernel(lbm_solver *s, int kind, int segment_rows);
 
 /* Optional, half storage (LBM_FP16) with two buffers: on = 1 rounds every
@@ -381,10 +381,9 @@ int lbm_set_fused_kernel(lbm_solver *s, int kind, int segment_rows);
  * of a half ulp (13 random bits), so that changes below half an ulp are not
  * lost and slow modes do not stall.  The random bits are a fixed function of
  * (site, population, step count since lbm_reset, seed): fused and single-step
- * launches give identical bits, and reruns repeat.  The register-wavefront
- * kernel rounds to nearest, so this selects the tile kernel (or single steps
- * where the tile does not reach).  Not available in place or in a batch.
- * Errors: LBM_E_STATE (not half storage, or in place). */
+ * launches (tile and wavefront) give identical bits, and reruns repeat.  Not
+ * available in place or in a batch.  Errors: LBM_E_STATE (not half storage,
+ * or in place). */
 int lbm_set_stochastic_rounding(lbm_solver *s, int on, unsigned int seed);
 
 /* Current launch configuration of plain steps: out[0] steps per launch;

@@ -2,7 +2,8 @@
 
 Times candidate launch shapes (tile width, rows per thread, persistent grid
 or one workgroup per tile, steps per launch, and for a single lattice the
-fused kernel: LDS tile or register wavefront with its segment height) with
+fused kernel: LDS tile with its tile height or register wavefront with its
+segment height) with
 HIP events on the solver's stream and keeps the fastest.  Results are cached in a JSON file keyed by GPU architecture,
 storage precision, workload kind and a size bucket (log2 of the sites per
 step), so a shape is measured once per machine and size class.
@@ -20,9 +21,10 @@ from typing import Callable, Dict, Iterable, List, Optional, Tuple
 
 import torch
 
-# (bx_log2, rows_per_thread, blocks_per_cu, steps_per_launch, wavefront_rows);
-# wavefront_rows 0 = LDS tile kernel for the fused launches
-Shape = Tuple[int, int, int, int, int]
+# (bx_log2, rows_per_thread, blocks_per_cu, steps_per_launch, wavefront_rows,
+# tile_rows); wavefront_rows 0 = LDS tile kernel for the fused launches,
+# tile_rows 0 = the library's default tile height
+Shape = Tuple[int, int, int, int, int, int]
 
 DEFAULT_CACHE = os.environ.get("LBM_AUTOTUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache",
@@ -30,22 +32,25 @@ DEFAULT_CACHE = os.environ.get("LBM_AUTOTUNE_CACHE",
 
 
 def candidates(nx: int, min_bx: int = 3, ny: int = 0, wavefront: bool = False,
-               fused: bool = True) -> List[Shape]:
-    """Single-step tile shapes, the fused LDS tile kernel (whose tile is fixed)
-    with one workgroup per tile or a persistent grid, and (single lattices) the
-    register wavefront with a few segment heights; single-step shapes only for
-    in-place solvers (fused=False)."""
-    out = [(6, 4, k, t, 0) for t in (8, 7, 6, 5, 4, 3, 2) for k in (0, 4)] if fused else []
+               fused: bool = True, precision: str = "fp32") -> List[Shape]:
+    """Single-step tile shapes; the fused LDS tile kernel at 2..8 steps with one
+    workgroup per tile or a persistent grid, and for single FP32 lattices also
+    its 24-row tile at five steps or more; and (single lattices) the register
+    wavefront at 3..8 steps with a few segment heights; single-step shapes only
+    for in-place solvers (fused=False)."""
+    out = [(6, 4, k, t, 0, 0) for t in (8, 7, 6, 5, 4, 3, 2) for k in (0, 4)] if fused else []
+    if fused and wavefront and precision == "fp32":
+        out += [(6, 4, 0, t, 0, 24) for t in (8, 7, 6, 5)]
     if wavefront and fused:
         for rows in (32, 64, 128, 256):
             if rows <= max(ny, 32):
-                out += [(6, 4, 0, t, rows) for t in (4, 3)]
+                out += [(6, 4, 0, t, rows, 0) for t in (8, 6, 4, 3)]
     for b in (5, 6, 7, 8):
         if b < min_bx or (1 << b) > max(2 * nx, 1 << min_bx):
             continue
         for v in (1, 2, 4):
             for k in (0, 4):
-                out.append((b, v, k, 1, 0))
+                out.append((b, v, k, 1, 0, 0))
     return out
 
 
@@ -57,6 +62,8 @@ def _apply(obj, shp: Shape):
             obj.set_fused_kernel("wavefront", shp[4])
         else:
             obj.set_fused_kernel("tile")
+    if hasattr(obj, "set_tile_rows") and not getattr(obj, "inplace", False):
+        obj.set_tile_rows(shp[5] if len(shp) > 5 else 0)
 
 
 def _arch() -> str:
@@ -67,7 +74,7 @@ def _arch() -> str:
 
 
 def _key(kind: str, precision: str, sites: int) -> str:
-    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}|v6"
+    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}|v7"
 
 
 def _load(path: str) -> Dict[str, list]:
@@ -134,7 +141,8 @@ def tune_solver(solver, precision: str, cache_path: Optional[str] = DEFAULT_CACH
         _apply(solver, shp)
         return shp
     res = time_shapes(lambda s: _apply(solver, s), solver.step,
-                      candidates(solver.nx, 0, solver.ny, wavefront=True, fused=not inplace),
+                      candidates(solver.nx, 0, solver.ny, wavefront=True, fused=not inplace,
+                                 precision=precision),
                       sites)
     shp = res[0][1]
     _apply(solver, shp)

@@ -172,7 +172,8 @@ struct lbm_solver {
     hipError_t enqueue_fused(int ns, hipStream_t st, long long& ph) {
         hipError_t e =
             L.wave_hs > 0
-                ? launch_wave(L.prec, ns, L.wave_v, L.nx, L.ny, L.wave_hs, d_desc, (int)(ph & 1), st)
+                ? launch_wave(L.prec, ns, L.wave_v, L.nx, L.ny, L.wave_hs, d_desc, (int)(ph & 1), st,
+                              L.sr_on())
                 : launch_stepN(L.prec, ns, L.th, grid, st, launch_args((int)(ph & 1)), false,
                                L.sr_on());
         ++ph;  // one buffer flip for ns steps
@@ -640,7 +641,6 @@ int lbm_set_time_blocking(lbm_solver* s, int steps_per_launch) {
         L.wave_hs = fc.wave_hs;
     }
     L.wave_v = wave_cols(L.prec, steps_per_launch, L.nx, L.ny);
-    if (L.sr) L.wave_hs = 0;  // the wavefront has no stochastic rounding
     return s->sync_desc();
 }
 
@@ -665,9 +665,6 @@ int lbm_set_fused_kernel(lbm_solver* s, int kind, int segment_rows) {
         s->L.wave_hs = 0;
         s->fused_auto = false;
     } else if (kind == LBM_FUSED_WAVEFRONT) {
-        if (s->L.sr)
-            return s->fail(LBM_E_STATE, "set_fused_kernel: stochastic rounding runs with the tile "
-                                        "or single-step kernels");
         if (segment_rows < 1 || segment_rows > (1 << 20))
             return s->fail(LBM_E_ARG, "set_fused_kernel: segment_rows must be in 1..2^20");
         s->L.wave_hs = segment_rows;
@@ -686,9 +683,6 @@ int lbm_set_stochastic_rounding(lbm_solver* s, int on, unsigned int seed) {
         return s->fail(LBM_E_STATE, "set_stochastic_rounding: half storage with two buffers only");
     L.sr = on != 0;
     L.sr_seed = seed;
-    // the register wavefront rounds to nearest: tile kernel, or single steps
-    // where the tile's 32-bit plane offsets do not reach
-    if (L.sr) L.wave_hs = 0;
     return s->sync_desc();
 }
 

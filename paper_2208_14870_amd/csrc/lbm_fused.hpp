@@ -556,10 +556,14 @@ struct WaveLaunch {
     int strips, segs, hs;  // strips of W output columns, segments of hs rows
 };
 
-template <typename S, int NS, int V>
+// SR: half storage with stochastic rounding (a separate instantiation): level
+// lv of a launch is global step sr_step + lv - 1, and the bits of a column are
+// those of its wrapped site, as the single-step kernel draws them.
+template <typename S, int NS, int V, bool SR = false>
 static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
     using C = typename Store<S>::C;
     constexpr int R = wave_ring<NS, V>();
+    constexpr bool kSR = SR && std::is_same<S, __half>::value;
     constexpr int W = wave_width<NS, V>();
     constexpr int PF = 3;  // rows loaded ahead
     // wave index as a scalar: the row loop and the row bases stay scalar
@@ -666,11 +670,23 @@ static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
                     C ux, uy;
                     collide<C, false>(f[c], G[lv][0][c], G[lv][1][c], k, ux, uy);
                 }
+                SrBits sb[kSR ? V : 1];
+                if constexpr (kSR) {
+                    const unsigned row = (unsigned)wrap_coord(t - lv, ny) * (unsigned)nx;
+                    const unsigned sh = sr_step_hash(d.sr_step + (unsigned)(lv - 1), d.sr_seed);
+#pragma unroll
+                    for (int c = 0; c < V; ++c) sb[c].make(row + (unsigned)(xw + c), sh);
+                }
                 if (lv < NS) {
 #pragma unroll
                     for (int q = 0; q < 8; ++q)
 #pragma unroll
-                        for (int c = 0; c < V; ++c) A[lv][u % 3][q][c] = as_stored<S>(f[c][q]);
+                        for (int c = 0; c < V; ++c) {
+                            if constexpr (kSR)
+                                A[lv][u % 3][q][c] = __half2float(half_sr(f[c][q], sb[c].r13(q)));
+                            else
+                                A[lv][u % 3][q][c] = as_stored<S>(f[c][q]);
+                        }
                 } else {
                     const int y = t - NS;
                     if (out_lane && y >= ya && y < yb) {
@@ -679,7 +695,11 @@ static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
                         for (int q = 0; q < 8; ++q) {
                             C v[V];
 #pragma unroll
-                            for (int c = 0; c < V; ++c) v[c] = f[c][q];
+                            for (int c = 0; c < V; ++c) {
+                                v[c] = f[c][q];
+                                // rounded here, so the store's own rounding is exact
+                                if constexpr (kSR) v[c] = __half2float(half_sr(v[c], sb[c].r13(q)));
+                            }
                             VecIO<S, V>::st(dst + q * plane + o, v);
                         }
                     }

@@ -325,16 +325,25 @@ inline hipError_t launch_solve_small(int prec, bool general, hipStream_t st, con
 
 // Register-wavefront launch of `ns` plain steps on slot 0 (single lattice),
 // segments of hs rows; two columns per lane for FP32/FP16 on even-width lattices.
+// Half storage with two columns per lane runs at most four steps (wave_cols),
+// so its deeper variants are not built.
 template <typename S, int V>
+constexpr int kWaveMaxSteps = (V == 2 && std::is_same<S, __half>::value) ? 4 : 8;
+
+template <typename S, int V, bool SR = false>
 inline void launch_wave_t(int ns, unsigned grid, hipStream_t st, const WaveLaunch& W) {
     switch (ns) {
-        case 2: hipLaunchKernelGGL((k_wave<S, 2, V>), dim3(grid), dim3(kBlock), 0, st, W); break;
-        case 3: hipLaunchKernelGGL((k_wave<S, 3, V>), dim3(grid), dim3(kBlock), 0, st, W); break;
-        case 4: hipLaunchKernelGGL((k_wave<S, 4, V>), dim3(grid), dim3(kBlock), 0, st, W); break;
-        case 5: hipLaunchKernelGGL((k_wave<S, 5, V>), dim3(grid), dim3(kBlock), 0, st, W); break;
-        case 6: hipLaunchKernelGGL((k_wave<S, 6, V>), dim3(grid), dim3(kBlock), 0, st, W); break;
-        case 7: hipLaunchKernelGGL((k_wave<S, 7, V>), dim3(grid), dim3(kBlock), 0, st, W); break;
-        default: hipLaunchKernelGGL((k_wave<S, 8, V>), dim3(grid), dim3(kBlock), 0, st, W); break;
+        case 2: hipLaunchKernelGGL((k_wave<S, 2, V, SR>), dim3(grid), dim3(kBlock), 0, st, W); break;
+        case 3: hipLaunchKernelGGL((k_wave<S, 3, V, SR>), dim3(grid), dim3(kBlock), 0, st, W); break;
+        case 4: hipLaunchKernelGGL((k_wave<S, 4, V, SR>), dim3(grid), dim3(kBlock), 0, st, W); break;
+        default:
+            if constexpr (kWaveMaxSteps<S, V> == 8) {
+                if (ns == 5) hipLaunchKernelGGL((k_wave<S, 5, V, SR>), dim3(grid), dim3(kBlock), 0, st, W);
+                else if (ns == 6) hipLaunchKernelGGL((k_wave<S, 6, V, SR>), dim3(grid), dim3(kBlock), 0, st, W);
+                else if (ns == 7) hipLaunchKernelGGL((k_wave<S, 7, V, SR>), dim3(grid), dim3(kBlock), 0, st, W);
+                else hipLaunchKernelGGL((k_wave<S, 8, V, SR>), dim3(grid), dim3(kBlock), 0, st, W);
+            }
+            break;
     }
 }
 
@@ -344,10 +353,12 @@ inline int wave_width_of(int ns, int v) {
     return kWave * v - 2 * ring;
 }
 
-// v: columns per lane (2 needs an even nx and non-FP64 storage).
+// v: columns per lane (2 needs an even nx and non-FP64 storage); sr: half
+// storage with stochastic rounding.
 inline hipError_t launch_wave(int prec, int ns, int v, int nx, int ny, int hs,
-                              const SlotDesc* slots, int flip, hipStream_t st) {
-    if (ns < 2 || ns > 8 || hs < 1 || (v == 2 && (prec == LBM_FP64 || nx % 2 != 0)))
+                              const SlotDesc* slots, int flip, hipStream_t st, bool sr = false) {
+    if (ns < 2 || ns > 8 || hs < 1 || (v == 2 && (prec == LBM_FP64 || nx % 2 != 0)) ||
+        (v == 2 && prec == LBM_FP16 && ns > 4))
         return hipErrorInvalidValue;
     const int w = wave_width_of(ns, v);
     WaveLaunch W;
@@ -361,6 +372,8 @@ inline hipError_t launch_wave(int prec, int ns, int v, int nx, int ny, int hs,
     if (prec == LBM_FP64) launch_wave_t<double, 1>(ns, grid, st, W);
     else if (prec == LBM_FP32 && v == 2) launch_wave_t<float, 2>(ns, grid, st, W);
     else if (prec == LBM_FP32) launch_wave_t<float, 1>(ns, grid, st, W);
+    else if (v == 2 && sr) launch_wave_t<__half, 2, true>(ns, grid, st, W);
+    else if (sr) launch_wave_t<__half, 1, true>(ns, grid, st, W);
     else if (v == 2) launch_wave_t<__half, 2>(ns, grid, st, W);
     else launch_wave_t<__half, 1>(ns, grid, st, W);
     return hipGetLastError();

@@ -40,34 +40,38 @@ def _load(nx, ny, seed, mat):
 
 @pytest.mark.parametrize("nx,ny,steps", [(100, 72, 37), (64, 16, 24), (33, 65, 19), (300, 200, 41)])
 def test_sr_fused_identical_to_single_steps(nx, ny, steps):
-    """Two to eight steps per launch round every population as single steps do
-    (ragged tiles, wrapped rings, a residual check and the half rescale
-    between fused launches); another seed gives other bits."""
+    """Two to eight steps per launch, through the LDS tile and the register
+    wavefront, round every population as single steps do (ragged tiles and
+    strips, wrapped rings, a residual check and the half rescale between fused
+    launches); another seed gives other bits."""
     say(f"stochastic rounding fused vs single {nx}x{ny} steps {steps}")
     mat = P.Material.from_shear_poisson(0.8, 0.3)
     gx, gy = _load(nx, ny, 5 + nx, mat)
     res = {}
-    for tb in (1, 2, 5, 8):
+    runs = [(1, "tile")] + [(tb, k) for tb in (2, 5, 8) for k in ("tile", "wavefront")]
+    for tb, kind in runs:
         s = _solver(nx, ny)
         _setup(s, mat, gx, gy)
         s.set_stochastic_rounding(True, 1234)
         s.set_time_blocking(tb)
+        s.set_fused_kernel(kind, 16)
         s.step(steps)
         a = host(s.populations())
         n, r, st = s.solve_to_tol(0.0, 13, 6)  # checks (and rescales) between launches
-        res[tb] = (a, host(s.populations()), n)
+        res[(tb, kind)] = (a, host(s.populations()), n)
         s.close()
-    for tb in (2, 5, 8):
-        np.testing.assert_array_equal(res[tb][0], res[1][0], err_msg=f"{tb} steps per launch")
-        np.testing.assert_array_equal(res[tb][1], res[1][1], err_msg=f"{tb} steps per launch")
-        assert res[tb][2] == res[1][2]
+    ref = res[(1, "tile")]
+    for key in runs[1:]:
+        np.testing.assert_array_equal(res[key][0], ref[0], err_msg=f"{key}")
+        np.testing.assert_array_equal(res[key][1], ref[1], err_msg=f"{key}")
+        assert res[key][2] == ref[2]
     s = _solver(nx, ny)
     _setup(s, mat, gx, gy)
     s.set_stochastic_rounding(True, 99)
     s.step(steps)
     other = host(s.populations())
     s.close()
-    assert not np.array_equal(other, res[1][0])
+    assert not np.array_equal(other, ref[0])
 
 
 def test_sr_rerun_and_reset_repeat():
@@ -138,7 +142,6 @@ def test_sr_argument_errors():
     u = _solver(256, 256, "fp16")
     u.set_stochastic_rounding(True)
     u.set_time_blocking(4)
-    with pytest.raises(lbm.LbmError):
-        u.set_fused_kernel("wavefront", 64)
-    assert u.launch_config()["kernel"] == "tile"
+    u.set_fused_kernel("wavefront", 64)
+    assert u.launch_config()["kernel"] == "wavefront"
     u.close()
