@@ -444,19 +444,26 @@ def large_lattice(steps=10000, warm=200, precs=("fp64", "fp32", "fp16", "fp16sr"
 
 
 def inplace_run(n=8192, steps=400, warm=8):
-    """In-place streaming (one population buffer) against the two-buffer solver
-    at one step per launch, 8192 x 8192 random load: GLUPS and workspace bytes."""
+    """In-place streaming (one population buffer) against the two-buffer solver,
+    8192 x 8192 random load: one step per launch both ways, then the default
+    fused launches (two buffers) against blocked launches in place (the
+    in-place wavefront with its halo copies, at eight and at four steps):
+    GLUPS and workspace bytes."""
     import torch
     from paper_2208_14870_amd import lbm, problem as P
     c = P.single_8192() if n == 8192 else P.single_1024(0.3, 1, 1, n=n)
     gx = torch.from_numpy(c.gx).cuda()
     gy = torch.from_numpy(c.gy).cuda()
     out = {}
+    runs = [("two_buffers", False, 1, 1), ("inplace", True, 1, 1),
+            ("two_buffers_fused", False, 8, 0), ("inplace_blocked", True, 8, 8),
+            ("inplace_blocked_4", True, 4, 4)]
     for prec in ("fp32", "fp64"):
         row = {}
-        for inplace in (False, True):
-            s = lbm.Solver(n, n, prec, inplace=inplace)
-            s.set_time_blocking(1)
+        for name, inplace, room, tb in runs:
+            s = lbm.Solver(n, n, prec, inplace=inplace, inplace_steps=room)
+            if tb:
+                s.set_time_blocking(tb)
             s.set_material(c.material.lame_lambda, c.material.lame_mu)
             s.set_body_force(gx, gy)
             s.step(warm)
@@ -468,10 +475,12 @@ def inplace_run(n=8192, steps=400, warm=8):
             e1.record()
             torch.cuda.synchronize()
             us = 1e3 * e0.elapsed_time(e1) / steps
-            gbs = BYTES_PER_SITE[prec] * n * n / (us * 1e-6) / 1e9
-            row["inplace" if inplace else "two_buffers"] = {
-                "mlups": round(n * n / us, 1), "gbs": round(gbs, 1),
-                "frac": round(gbs / PEAK_HBM_GBS, 4), "workspace_bytes": s.workspace_bytes}
+            r = {"mlups": round(n * n / us, 1), "workspace_bytes": s.workspace_bytes,
+                 "launch_config": s.launch_config()}
+            if tb == 1:
+                gbs = BYTES_PER_SITE[prec] * n * n / (us * 1e-6) / 1e9
+                r.update(gbs=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4))
+            row[name] = r
             s.close()
             del s
         out[prec] = row

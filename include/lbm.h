@@ -107,12 +107,31 @@ int lbm_create(int nx, int ny, int precision, int with_polish, void *workspace,
  * FP16 storage: lbm_solve_to_tol may rescale the half storage one step earlier
  * or later than the two-buffer solver, which changes the rounding of
  * subnormal halves only.  Same
- * handle and entry points, with these differences: one step per launch
- * (lbm_set_time_blocking accepts only 1, lbm_set_fused_kernel returns
- * LBM_E_STATE), no polish phase, and lbm_solve_to_tol evaluates its residual
- * with a launch that does not step (the state cannot step back in place).
- * Workspace: lbm_workspace_bytes_inplace (0 for invalid sizes). */
+ * handle and entry points, with these differences: no LDS tile kernel, no
+ * stochastic rounding, no polish phase, and lbm_solve_to_tol evaluates its
+ * residual with a launch that does not step (the state cannot step back in
+ * place).
+ * Workspace: lbm_workspace_bytes_inplace (0 for invalid sizes) runs one step
+ * per launch.  Temporal blocking in place (up to k = 2..8 steps per launch
+ * through the register wavefront, LBM_FUSED_WAVEFRONT) needs room for copies
+ * of the columns and rows that neighbouring waves overwrite during a launch:
+ * a ring of columns per strip and 2 x depth rows per segment, taken by a short
+ * copy launch before each blocked launch.  lbm_workspace_bytes_inplace_blocked
+ * (nx, ny, precision, k, segment_rows) is the workspace with that room for
+ * launches of up to k steps with segments of segment_rows rows (0: the default
+ * of lbm_set_time_blocking; FP32 8192^2 at k = 8: about a quarter of the
+ * population buffer more; 0 for invalid arguments).
+ * lbm_create_inplace takes whatever lies beyond lbm_workspace_bytes_inplace
+ * as that room and defaults to the deepest k (8 down to 2) whose default shape
+ * fits, else to one step per launch.  A blocked launch reads the layout it
+ * finds (odd depths start from the even-step layout, even depths from the
+ * odd-step one) and always leaves the odd-step layout, so a sequence of n
+ * steps runs launches of up to k steps with the parity each start needs and a
+ * single step where none fits.  Results are identical to single steps bit for
+ * bit. */
 size_t lbm_workspace_bytes_inplace(int nx, int ny, int precision);
+size_t lbm_workspace_bytes_inplace_blocked(int nx, int ny, int precision, int steps_per_launch,
+                                           int segment_rows);
 int lbm_create_inplace(int nx, int ny, int precision, void *workspace, size_t workspace_bytes,
                        void *stream, lbm_solver **out);
 
@@ -333,8 +352,13 @@ int lbm_set_tile(lbm_solver *s, int bx_log2, int rows_per_thread, int blocks_per
  * lbm_set_tile while active.  Default by storage type and size: FP32 and FP16
  * 8 above 2^17 sites, else 4; FP64 5 below 2^20 sites, else 8 (also after a
  * polish switch).  The fused kernel follows the default of
- * lbm_set_fused_kernel for k until the caller picks one.  Errors: LBM_E_ARG
- * (k outside 1..8), LBM_E_STATE (k != 1 in place). */
+ * lbm_set_fused_kernel for k until the caller picks one.  In place: the
+ * in-place wavefront (see lbm_create_inplace), one column per lane for FP64
+ * and for FP16 above four steps, two otherwise on even widths; segments of
+ * 256 rows, halved down to 32 while the lattice would give fewer than 4096
+ * waves, until the caller picks a segment height.  Errors: LBM_E_ARG (k
+ * outside 1..8), LBM_E_WORKSPACE (in place, k >= 2 and the halo room of the
+ * workspace is too small for k). */
 int lbm_set_time_blocking(lbm_solver *s, int steps_per_launch);
 
 /* Tile height of the LDS tile kernel (the tile is 64 columns wide): rows in
@@ -371,8 +395,10 @@ enum lbm_fused_kernel {
  * waves per compute unit); the tile kernel otherwise.  The tile kernel addresses a plane
  * with 32-bit byte offsets, so a lattice whose planes hold 2^32 bytes or more
  * in the arithmetic type (above 2^30 FP32/FP16 or 2^29 FP64 sites) defaults
- * to the wavefront whatever its width.  Errors: LBM_E_ARG, LBM_E_STATE
- * (in place). */
+ * to the wavefront whatever its width.  In place the wavefront is the only
+ * fused kernel; its segment height sets the rows copied per launch.  Errors:
+ * LBM_E_ARG, LBM_E_STATE (LBM_FUSED_TILE in place), LBM_E_WORKSPACE (in
+ * place, the segment height needs more halo room than the workspace has). */
 int lbm_set_fused_kernel(lbm_solver *s, int kind, int segment_rows);
 
 /* Optional, half storage (LBM_FP16) with two buffers: on = 1 rounds every

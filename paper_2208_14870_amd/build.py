@@ -9,12 +9,13 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = [os.path.join(CSRC, "lbm_capi.hip"), os.path.join(CSRC, "lbm_batch.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in
+           ("lbm_capi.hip", "lbm_batch.hip", "lbm_wave.hip", "lbm_wave_inplace.hip")]
 HEADERS = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")) + [
     os.path.join(ROOT, "include", "lbm.h")]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Wall", "-Wno-unused-function",
     # packed FP32 instructions are disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -23,15 +24,36 @@ HIPCC_FLAGS = [
 
 
 def build(verbose: bool = True) -> str:
-    """Compile every HIP source into liblbm.so (always recompiles)."""
+    """Compile every HIP source into liblbm.so (always recompiles): one hipcc
+    process per source, in parallel, then one link."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     srcs = [s for s in SOURCES if os.path.exists(s)]
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + HIPCC_FLAGS + ["-o", tmp] + srcs
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    tag = "%d" % os.getpid()
+    objs = [os.path.join(CSRC, os.path.basename(s)[:-4] + ".o.tmp" + tag) for s in srcs]
+    procs = []
+    try:
+        for src, obj in zip(srcs, objs):
+            cmd = [hipcc] + HIPCC_FLAGS + ["-c", "-o", obj, src]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append(subprocess.Popen(cmd))
+        failed = [src for src, p in zip(srcs, procs) if p.wait() != 0]
+        if failed:
+            raise subprocess.CalledProcessError(1, "hipcc " + " ".join(failed))
+        tmp = LIB + ".tmp" + tag
+        cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    finally:
+        for p in procs:
+            if p.poll() is None:
+                p.kill()
+                p.wait()
+        for obj in objs:
+            if os.path.exists(obj):
+                os.remove(obj)
     return LIB
 
 

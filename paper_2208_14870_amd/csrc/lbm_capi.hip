@@ -181,6 +181,35 @@ struct lbm_solver {
         return e;
     }
 
+    // In place: one launch of ns steps through the in-place wavefront (odd ns
+    // from kLayNatural, even from kLaySwapped); the layout flips per step, so
+    // the launch parity advances by ns.
+    hipError_t enqueue_fused_ip(int ns, hipStream_t st, long long& ph) {
+        hipError_t e = launch_wave_inplace(L.prec, ns, L.wave_v, L.nx, L.ny, L.wave_hs, d_desc,
+                                           (int)(ph & 1), L.halo, st);
+        ph += ns;
+        return e;
+    }
+
+    // In place: np steps, each launch as deep as L.tb allows with the parity
+    // that the current layout needs (a single step where none is left).
+    hipError_t enqueue_ip(long long np, hipStream_t st, long long& ph) {
+        hipError_t e = hipSuccess;
+        for (long long i = 0; i < np && e == hipSuccess;) {
+            const bool nat = L.layout(L.cur ^ (int)(ph & 1)) == kLayNatural;
+            int ns = (int)std::min<long long>(L.tb, np - i);
+            if ((ns & 1) != (nat ? 1 : 0)) --ns;
+            if (ns >= 2) {
+                e = enqueue_fused_ip(ns, st, ph);
+                i += ns;
+            } else {
+                e = enqueue_one(kPlain, st, ph);
+                ++i;
+            }
+        }
+        return e;
+    }
+
     // Whether a remainder of r < L.tb plain steps runs as one fused launch.
     bool fused_rest(long long r) const {
         return L.fused() && r >= 2 &&
@@ -241,6 +270,9 @@ struct lbm_solver {
                 e = enqueue_fused((int)(np - i), st, ph);
                 i = np;
             }
+        } else if (L.ip_blocked()) {
+            e = enqueue_ip(np, st, ph);
+            i = np;
         }
         for (; i < np && e == hipSuccess; ++i) e = enqueue_one(kPlain, st, ph);
         if (e == hipSuccess && span) {
@@ -280,13 +312,18 @@ struct lbm_solver {
         return span ? span : 1;
     }
 
-    // Enqueue a chunk; long runs are replayed from captured graphs.
+    // Enqueue a chunk; long runs are replayed from captured graphs.  In place
+    // with blocked launches, a graph from kLayNatural holds 63 steps (an odd
+    // launch, then even ones) and one from kLaySwapped 64, so that whole
+    // graphs need no single step to restore the layout's parity.
     hipError_t enqueue_chunk(long long nplain, bool writeu, bool check) {
-        const long long kGraphChunk = graph_chunk();
         hipError_t e;
-        while (nplain >= kGraphChunk) {
-            if ((e = run_graph(kGraphChunk, false, false)) != hipSuccess) return e;
-            nplain -= kGraphChunk;
+        while (true) {
+            long long chunk = graph_chunk();
+            if (L.ip_blocked() && L.layout(sel()) == kLayNatural) chunk = 63;
+            if (nplain < chunk) break;
+            if ((e = run_graph(chunk, false, false)) != hipSuccess) return e;
+            nplain -= chunk;
         }
         if (nplain > 0 || writeu || check) {
             if (launches(nplain, writeu, check) >= 4) return run_graph(nplain, writeu, check);
@@ -301,9 +338,10 @@ struct lbm_solver {
         const int flip0 = (int)(phase & 1);
         const int kind = (writeu ? 1 : 0) | (check ? 2 : 0) | (L.general() ? 4 : 0) |
                          (L.inplace ? 8 : 0) | (L.sr_on() ? 16 : 0);
-        const int fused = L.fused() ? L.tb | (L.th << 4) : 0;
+        const int fused = L.fused() ? L.tb | (L.th << 4)
+                                    : (L.ip_blocked() ? L.tb | (L.wave_v << 8) | (1 << 12) : 0);
         auto key = std::make_tuple(nplain, kind, flip0 ^ (L.cur << 1), L.prec, L.eff_vy(), fused,
-                                   L.fused() ? L.wave_hs : 0, grid);
+                                   (L.fused() || L.ip_blocked()) ? L.wave_hs : 0, grid);
         auto it = graphs.find(key);
         hipError_t e;
         if (it == graphs.end()) {
@@ -350,6 +388,15 @@ size_t lbm_workspace_bytes(int nx, int ny, int precision, int with_polish) {
 
 size_t lbm_workspace_bytes_inplace(int nx, int ny, int precision) {
     return workspace_bytes(nx, ny, precision, false, true);
+}
+
+size_t lbm_workspace_bytes_inplace_blocked(int nx, int ny, int precision, int steps_per_launch,
+                                           int segment_rows) {
+    const size_t b = workspace_bytes(nx, ny, precision, false, true);
+    if (b == 0 || steps_per_launch < 2 || steps_per_launch > 8 || segment_rows < 0 ||
+        segment_rows > (1 << 20))
+        return 0;
+    return b + ip_halo_bytes(precision, steps_per_launch, nx, ny, segment_rows);
 }
 
 static int create_solver(int nx, int ny, int precision, int with_polish, bool inplace,
@@ -400,6 +447,20 @@ static int create_solver(int nx, int ny, int precision, int with_polish, bool in
     const FusedChoice fc = default_fused(precision, L.tb, nx, ny, s->cus, !L.tile_fits());
     L.wave_hs = inplace ? 0 : fc.wave_hs;
     L.wave_v = fc.wave_v;
+    if (inplace) {
+        // room beyond the minimum holds the in-place wavefront's halo copies:
+        // the deepest launch whose default shape fits is the default
+        L.halo = reinterpret_cast<char*>(workspace) + need;
+        L.halo_cap = (workspace_bytes_given - need) / kAlign * kAlign;
+        for (int k = 8; k >= 2; --k) {
+            if (ip_halo_bytes(precision, k, nx, ny) <= L.halo_cap) {
+                L.tb = k;
+                L.wave_v = ip_wave_cols(precision, k, nx);
+                L.wave_hs = ip_segment_rows(k, L.wave_v, nx, ny);
+                break;
+            }
+        }
+    }
     char* base = reinterpret_cast<char*>(workspace);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -630,9 +691,26 @@ int lbm_set_time_blocking(lbm_solver* s, int steps_per_launch) {
     if (!s) return LBM_E_ARG;
     if (steps_per_launch < 1 || steps_per_launch > 8)
         return s->fail(LBM_E_ARG, "set_time_blocking: steps_per_launch must be in 1..8");
-    if (s->L.inplace && steps_per_launch != 1)
-        return s->fail(LBM_E_STATE, "set_time_blocking: in-place streaming runs one step per launch");
     Lattice& L = s->L;
+    if (L.inplace) {
+        if (steps_per_launch >= 2) {
+            const int v = ip_wave_cols(L.prec, steps_per_launch, L.nx);
+            const int hs = s->fused_auto ? ip_segment_rows(steps_per_launch, v, L.nx, L.ny)
+                                         : L.wave_hs;
+            const size_t need = wave_halo_bytes(L.prec, steps_per_launch, v, L.nx, L.ny, hs);
+            if (need > L.halo_cap)
+                return s->fail(LBM_E_WORKSPACE,
+                               "set_time_blocking: in place, " + std::to_string(steps_per_launch) +
+                                   " steps per launch need " + std::to_string(need) +
+                                   " bytes of halo room beyond lbm_workspace_bytes_inplace (have " +
+                                   std::to_string(L.halo_cap) +
+                                   "; see lbm_workspace_bytes_inplace_blocked)");
+            L.wave_v = v;
+            L.wave_hs = hs;
+        }
+        L.tb = steps_per_launch;
+        return s->sync_desc();
+    }
     L.tb = steps_per_launch;
     L.th = fused_th(L.prec, steps_per_launch, L.N, L.th_user);
     if (s->fused_auto) {
@@ -659,8 +737,26 @@ int lbm_set_tile_rows(lbm_solver* s, int rows) {
 
 int lbm_set_fused_kernel(lbm_solver* s, int kind, int segment_rows) {
     if (!s) return LBM_E_ARG;
-    if (s->L.inplace)
-        return s->fail(LBM_E_STATE, "set_fused_kernel: in-place streaming has no fused kernel");
+    if (s->L.inplace) {
+        Lattice& L = s->L;
+        if (kind != LBM_FUSED_WAVEFRONT)
+            return s->fail(LBM_E_STATE, "set_fused_kernel: in place, the wavefront is the only "
+                                        "fused kernel");
+        if (segment_rows < 1 || segment_rows > (1 << 20))
+            return s->fail(LBM_E_ARG, "set_fused_kernel: segment_rows must be in 1..2^20");
+        if (L.tb >= 2) {
+            const size_t need = wave_halo_bytes(L.prec, L.tb, L.wave_v, L.nx, L.ny, segment_rows);
+            if (need > L.halo_cap)
+                return s->fail(LBM_E_WORKSPACE,
+                               "set_fused_kernel: in place, segments of " +
+                                   std::to_string(segment_rows) + " rows need " +
+                                   std::to_string(need) + " bytes of halo room (have " +
+                                   std::to_string(L.halo_cap) + ")");
+        }
+        L.wave_hs = segment_rows;
+        s->fused_auto = false;
+        return s->sync_desc();
+    }
     if (kind == LBM_FUSED_TILE) {
         s->L.wave_hs = 0;
         s->fused_auto = false;
@@ -690,7 +786,11 @@ int lbm_get_launch_config(const lbm_solver* s, int out[4]) {
     if (!s || !out) return LBM_E_ARG;
     const Lattice& L = s->L;
     out[0] = L.tb;
-    if (!L.fused()) {
+    if (L.ip_blocked()) {
+        out[1] = LBM_FUSED_WAVEFRONT;
+        out[2] = L.wave_hs;
+        out[3] = kBlock;
+    } else if (!L.fused()) {
         out[1] = -1;
         out[2] = L.inplace ? 0 : L.eff_vy();
         out[3] = kBlock;
@@ -708,7 +808,7 @@ int lbm_get_launch_config(const lbm_solver* s, int out[4]) {
 
 int lbm_get_wave_columns(const lbm_solver* s) {
     if (!s) return LBM_E_ARG;
-    return (s->L.fused() && s->L.wave_hs > 0) ? s->L.wave_v : 0;
+    return ((s->L.fused() && s->L.wave_hs > 0) || s->L.ip_blocked()) ? s->L.wave_v : 0;
 }
 
 int lbm_step(lbm_solver* s, long long nsteps) {

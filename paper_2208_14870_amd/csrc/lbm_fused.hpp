@@ -554,16 +554,70 @@ struct WaveLaunch {
     const SlotDesc* slots;
     int flip;
     int strips, segs, hs;  // strips of W output columns, segments of hs rows
+    // in place: copies of the ring columns and halo rows taken before the launch
+    // (k_wave_halo), by strip boundary and by segment boundary
+    const void* hx;
+    const void* hy;
 };
+
+// In-place wavefront (one buffer).  Every wave reads and writes the memory of
+// the sites it outputs; the ring columns and halo rows it reads belong to
+// other waves, which overwrite them during the launch, so they are read from
+// copies taken by a launch before (k_wave_halo):
+//   hx, per strip boundary b (at column b W): the 2R columns b W - R .. b W + R - 1
+//     of every row, as [b][plane][row][2R];
+//   hy, per segment boundary j (at row j hs): the 2 NS rows j hs - NS ..
+//     j hs + NS - 1 of every column, as [j][plane][2 NS][nx]
+// (periodic wrap; a strip's left ring is boundary s's first half, its right
+// ring the next boundary's second half).  Layouts (see Layout): a launch from
+// kLayNatural (odd NS) collides each site's own populations at level 1; one
+// from kLaySwapped (even NS) reads f*_q(x) from plane opp(q) and gathers as
+// the two-buffer kernel does; both store f*_q(x) into plane opp(q) at x, so the
+// buffer ends in kLaySwapped, which is the layout NS steps on.
+template <typename S>
+static __global__ __launch_bounds__(kBlock) void k_wave_halo(WaveLaunch L, int W, int R, int NS) {
+    const SlotDesc& d = L.slots[0];
+    const int nx = d.nx, ny = d.ny;
+    const long long plane = d.plane;
+    const S* __restrict__ buf = reinterpret_cast<const S*>(d.buf[d.cur ^ L.flip]);
+    S* __restrict__ hx = reinterpret_cast<S*>(const_cast<void*>(L.hx));
+    S* __restrict__ hy = reinterpret_cast<S*>(const_cast<void*>(L.hy));
+    const long long px = (long long)ny * 2 * R, py = (long long)2 * NS * nx;  // plane strides
+    const long long nxe = (long long)L.strips * px, nye = (long long)L.segs * py;
+    const long long step = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nxe + nye; i += step) {
+        long long s;
+        S* o;
+        long long ps;
+        if (i < nxe) {
+            const long long b = i / px, r = i - b * px;
+            const int row = (int)(r / (2 * R)), j = (int)(r - (long long)row * 2 * R);
+            s = (long long)row * nx + wrap_coord((int)(b * W) - R + j, nx);
+            o = hx + b * 8 * px + r;
+            ps = px;
+        } else {
+            const long long k = i - nxe, b = k / py, r = k - b * py;
+            const int hr = (int)(r / nx), col = (int)(r - (long long)hr * nx);
+            s = (long long)wrap_coord((int)(b * L.hs) - NS + hr, ny) * nx + col;
+            o = hy + b * 8 * py + r;
+            ps = py;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) o[q * ps] = buf[q * plane + s];
+    }
+}
 
 // SR: half storage with stochastic rounding (a separate instantiation): level
 // lv of a launch is global step sr_step + lv - 1, and the bits of a column are
-// those of its wrapped site, as the single-step kernel draws them.
-template <typename S, int NS, int V, bool SR = false>
+// those of its wrapped site, as the single-step kernel draws them.  IP: in
+// place (see k_wave_halo), from kLayNatural for odd NS, kLaySwapped for even.
+template <typename S, int NS, int V, bool SR = false, bool IP = false>
 static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
     using C = typename Store<S>::C;
     constexpr int R = wave_ring<NS, V>();
     constexpr bool kSR = SR && std::is_same<S, __half>::value;
+    static_assert(!(SR && IP), "no stochastic rounding in place");
+    constexpr bool kNat = IP && (NS % 2 == 1);  // level 0 is f(n) itself
     constexpr int W = wave_width<NS, V>();
     constexpr int PF = 3;  // rows loaded ahead
     // wave index as a scalar: the row loop and the row bases stay scalar
@@ -575,8 +629,11 @@ static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
     const int nx = d.nx, ny = d.ny;
     const long long plane = d.plane;
     const int sel = d.cur ^ L.flip;
-    const S* __restrict__ src = reinterpret_cast<const S*>(d.buf[sel]);
-    S* __restrict__ dst = reinterpret_cast<S*>(d.buf[sel ^ 1]);
+    // two buffers: read one, write the other; in place one buffer (no restrict)
+    using SrcP = std::conditional_t<IP, const S*, const S* __restrict__>;
+    using DstP = std::conditional_t<IP, S*, S* __restrict__>;
+    const SrcP src = reinterpret_cast<const S*>(d.buf[sel]);
+    const DstP dst = reinterpret_cast<S*>(d.buf[IP ? sel : (sel ^ 1)]);
     const C* __restrict__ g = reinterpret_cast<const C*>(d.g);
     Coef<C> k;
     k.load(d);
@@ -587,13 +644,41 @@ static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
     const bool out_lane = lane >= R / V && lane < (R + W) / V && x < nx;
     // loads of row t: scalar row base + per-lane byte offset of the column
     const unsigned xs_b = (unsigned)xw * (unsigned)sizeof(S), xg_b = (unsigned)xw * (unsigned)sizeof(C);
+    // in place: ring lanes read the strip boundaries' copies (any row), the
+    // others the segment boundaries' copies in halo rows, else the buffer
+    const S* hxl = nullptr;
+    bool ring = false;
+    if constexpr (IP) {
+        const int xe = min(xs + W, nx);
+        const bool left = lane < R / V, right = x >= xe && x < xe + R;
+        ring = left || right;
+        const int b = left ? sx : (sx + 1 == L.strips ? 0 : sx + 1);
+        hxl = reinterpret_cast<const S*>(L.hx) + (long long)b * 8 * ny * 2 * R +
+              (left ? V * lane : R + (x - xe));
+    }
     auto load_row = [&](int t, C (*a)[V], C (*gg)[V]) {
         const long long r = (long long)wrap_coord(t, ny) * nx;
+        if constexpr (IP) {
+            const S* own = src + r;
+            long long ops = plane;
+            if (t < ya || (t >= yb && t < yb + NS)) {
+                const int b = t < ya ? sy : (sy + 1 == L.segs ? 0 : sy + 1);
+                const int hr = t < ya ? t - (ya - NS) : NS + (t - yb);
+                own = reinterpret_cast<const S*>(L.hy) + (long long)b * 16 * NS * nx +
+                      (long long)hr * nx;
+                ops = 2LL * NS * nx;
+            }
+            const S* p = ring ? hxl + (long long)wrap_coord(t, ny) * 2 * R : own + xw;
+            const long long ps = ring ? (long long)ny * 2 * R : ops;
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            VecIO<S, V>::ld(reinterpret_cast<const S*>(
-                                reinterpret_cast<const char*>(src + (q * plane + r)) + xs_b),
-                            a[q]);
+            for (int q = 0; q < 8; ++q) VecIO<S, V>::ld(p + q * ps, a[q]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                VecIO<S, V>::ld(reinterpret_cast<const S*>(
+                                    reinterpret_cast<const char*>(src + (q * plane + r)) + xs_b),
+                                a[q]);
+        }
         VecIO<C, V>::ld(reinterpret_cast<const C*>(reinterpret_cast<const char*>(g + r) + xg_b), gg[0]);
         VecIO<C, V>::ld(reinterpret_cast<const C*>(reinterpret_cast<const char*>(g + (plane + r)) + xg_b),
                         gg[1]);
@@ -654,16 +739,26 @@ static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
                     return c < V - 1 ? row[q][c + 1] : lane_from_right(row[q][0]);
                 };
                 C f[V][8];
+                if (kNat && lv == 1) {
+                    // f(n) of the site itself (level 0 of row t - 1)
 #pragma unroll
-                for (int c = 0; c < V; ++c) {
-                    f[c][0] = left(R1, 0, c);   // c1 = ( 1, 0) from (x-1, y)
-                    f[c][1] = R2[1][c];         // c2 = ( 0, 1) from (x, y-1)
-                    f[c][2] = right(R1, 2, c);  // c3 = (-1, 0) from (x+1, y)
-                    f[c][3] = R0[3][c];         // c4 = ( 0,-1) from (x, y+1)
-                    f[c][4] = left(R2, 4, c);   // c5 = ( 1, 1) from (x-1, y-1)
-                    f[c][5] = right(R2, 5, c);  // c6 = (-1, 1) from (x+1, y-1)
-                    f[c][6] = right(R0, 6, c);  // c7 = (-1,-1) from (x+1, y+1)
-                    f[c][7] = left(R0, 7, c);   // c8 = ( 1,-1) from (x-1, y+1)
+                    for (int c = 0; c < V; ++c)
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) f[c][q] = R1[q][c];
+                } else {
+                    // in place from kLaySwapped, level 0 holds f*_q in slot opp(q)
+                    auto sq = [&](int q) { return (IP && lv == 1) ? opp(q) : q; };
+#pragma unroll
+                    for (int c = 0; c < V; ++c) {
+                        f[c][0] = left(R1, sq(0), c);   // c1 = ( 1, 0) from (x-1, y)
+                        f[c][1] = R2[sq(1)][c];         // c2 = ( 0, 1) from (x, y-1)
+                        f[c][2] = right(R1, sq(2), c);  // c3 = (-1, 0) from (x+1, y)
+                        f[c][3] = R0[sq(3)][c];         // c4 = ( 0,-1) from (x, y+1)
+                        f[c][4] = left(R2, sq(4), c);   // c5 = ( 1, 1) from (x-1, y-1)
+                        f[c][5] = right(R2, sq(5), c);  // c6 = (-1, 1) from (x+1, y-1)
+                        f[c][6] = right(R0, sq(6), c);  // c7 = (-1,-1) from (x+1, y+1)
+                        f[c][7] = left(R0, sq(7), c);   // c8 = ( 1,-1) from (x-1, y+1)
+                    }
                 }
 #pragma unroll
                 for (int c = 0; c < V; ++c) {
@@ -700,7 +795,8 @@ static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
                                 // rounded here, so the store's own rounding is exact
                                 if constexpr (kSR) v[c] = __half2float(half_sr(v[c], sb[c].r13(q)));
                             }
-                            VecIO<S, V>::st(dst + q * plane + o, v);
+                            // in place: f*_q into plane opp(q) (kLaySwapped)
+                            VecIO<S, V>::st(dst + (IP ? opp(q) : q) * plane + o, v);
                         }
                     }
                 }

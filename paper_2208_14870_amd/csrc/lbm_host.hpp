@@ -13,21 +13,16 @@
 
 #include "lbm.h"
 #include "lbm_device.hpp"
+#include "lbm_host_base.hpp"
 
 namespace lbm_host {
 using namespace lbm;
 
 
-constexpr size_t kAlign = 256;
 // Tiles per vertical band of a single lattice's work list for the fused tile
 // kernel (single steps stream best in row-major order: 8192^2 FP32 81 against
 // 76 GLUPS).
 constexpr int kItemBand = 8;
-inline size_t al(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
-
-inline size_t elem_bytes(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2); }
-inline size_t arith_bytes(int prec) { return prec == LBM_FP64 ? 8 : 4; }
-inline bool valid_prec(int p) { return p == LBM_FP64 || p == LBM_FP32 || p == LBM_FP16; }
 
 inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
@@ -323,62 +318,6 @@ inline hipError_t launch_solve_small(int prec, bool general, hipStream_t st, con
     return hipGetLastError();
 }
 
-// Register-wavefront launch of `ns` plain steps on slot 0 (single lattice),
-// segments of hs rows; two columns per lane for FP32/FP16 on even-width lattices.
-// Half storage with two columns per lane runs at most four steps (wave_cols),
-// so its deeper variants are not built.
-template <typename S, int V>
-constexpr int kWaveMaxSteps = (V == 2 && std::is_same<S, __half>::value) ? 4 : 8;
-
-template <typename S, int V, bool SR = false>
-inline void launch_wave_t(int ns, unsigned grid, hipStream_t st, const WaveLaunch& W) {
-    switch (ns) {
-        case 2: hipLaunchKernelGGL((k_wave<S, 2, V, SR>), dim3(grid), dim3(kBlock), 0, st, W); break;
-        case 3: hipLaunchKernelGGL((k_wave<S, 3, V, SR>), dim3(grid), dim3(kBlock), 0, st, W); break;
-        case 4: hipLaunchKernelGGL((k_wave<S, 4, V, SR>), dim3(grid), dim3(kBlock), 0, st, W); break;
-        default:
-            if constexpr (kWaveMaxSteps<S, V> == 8) {
-                if (ns == 5) hipLaunchKernelGGL((k_wave<S, 5, V, SR>), dim3(grid), dim3(kBlock), 0, st, W);
-                else if (ns == 6) hipLaunchKernelGGL((k_wave<S, 6, V, SR>), dim3(grid), dim3(kBlock), 0, st, W);
-                else if (ns == 7) hipLaunchKernelGGL((k_wave<S, 7, V, SR>), dim3(grid), dim3(kBlock), 0, st, W);
-                else hipLaunchKernelGGL((k_wave<S, 8, V, SR>), dim3(grid), dim3(kBlock), 0, st, W);
-            }
-            break;
-    }
-}
-
-// Output columns of a wave's strip (64 V columns less the ring on each side).
-inline int wave_width_of(int ns, int v) {
-    const int ring = v == 1 ? ns : (ns <= 4 ? 4 : (ns + 1) / 2 * 2);
-    return kWave * v - 2 * ring;
-}
-
-// v: columns per lane (2 needs an even nx and non-FP64 storage); sr: half
-// storage with stochastic rounding.
-inline hipError_t launch_wave(int prec, int ns, int v, int nx, int ny, int hs,
-                              const SlotDesc* slots, int flip, hipStream_t st, bool sr = false) {
-    if (ns < 2 || ns > 8 || hs < 1 || (v == 2 && (prec == LBM_FP64 || nx % 2 != 0)) ||
-        (v == 2 && prec == LBM_FP16 && ns > 4))
-        return hipErrorInvalidValue;
-    const int w = wave_width_of(ns, v);
-    WaveLaunch W;
-    W.slots = slots;
-    W.flip = flip;
-    W.strips = (nx + w - 1) / w;
-    W.hs = hs;
-    W.segs = (ny + hs - 1) / hs;
-    const long long waves = (long long)W.strips * W.segs;
-    const unsigned grid = (unsigned)((waves + kBlock / kWave - 1) / (kBlock / kWave));
-    if (prec == LBM_FP64) launch_wave_t<double, 1>(ns, grid, st, W);
-    else if (prec == LBM_FP32 && v == 2) launch_wave_t<float, 2>(ns, grid, st, W);
-    else if (prec == LBM_FP32) launch_wave_t<float, 1>(ns, grid, st, W);
-    else if (v == 2 && sr) launch_wave_t<__half, 2, true>(ns, grid, st, W);
-    else if (sr) launch_wave_t<__half, 1, true>(ns, grid, st, W);
-    else if (v == 2) launch_wave_t<__half, 2>(ns, grid, st, W);
-    else launch_wave_t<__half, 1>(ns, grid, st, W);
-    return hipGetLastError();
-}
-
 // Default fused kernel of a single lattice of N = nx ny sites, measured on
 // MI355X (GLUPS, eight steps per launch: tile kernel / wavefront with one
 // column per lane / with two):
@@ -417,6 +356,28 @@ inline FusedChoice default_fused(int prec, int ns, int nx, int ny, int cus, bool
     while (hs > 32 && strips * ((ny + hs - 1) / hs) < 8LL * cus) hs /= 2;
     c.wave_hs = hs;
     return c;
+}
+
+// In place: columns per lane (two on even widths except FP64, and half
+// storage beyond four steps) and segment height (256 rows, halved down to 32
+// while the lattice would give fewer than 4096 waves): long segments keep the
+// row copies small (2 ns rows per segment), enough waves keep the chip busy
+// (8192^2 at eight steps, MI355X: FP32 with two columns per lane 275 GLUPS at
+// 256 rows (2368 waves), 292 at 128, 262 at 64; FP64 136 at 256 and at 128).
+inline int ip_wave_cols(int prec, int ns, int nx) {
+    return (prec != LBM_FP64 && nx % 2 == 0 && (prec == LBM_FP32 || ns <= 4)) ? 2 : 1;
+}
+inline int ip_segment_rows(int ns, int v, int nx, int ny) {
+    const long long strips = (nx + wave_width_of(ns, v) - 1) / wave_width_of(ns, v);
+    int hs = 256;
+    while (hs > 32 && strips * ((ny + hs - 1) / hs) < 4096) hs /= 2;
+    return hs;
+}
+// Halo bytes of in-place launches of up to ns steps (hs = 0: the default
+// segment height).  Shallower launches of the same sequence need no more.
+inline size_t ip_halo_bytes(int prec, int ns, int nx, int ny, int hs = 0) {
+    const int v = ip_wave_cols(prec, ns, nx);
+    return wave_halo_bytes(prec, ns, v, nx, ny, hs > 0 ? hs : ip_segment_rows(ns, v, nx, ny));
 }
 
 // Default steps per launch for `sites` lattice sites (of one lattice, or of
@@ -574,6 +535,8 @@ struct Lattice {
     int wave_v = 1;   // the wavefront's columns per lane
     int cur = 0;      // buffer with the state at flip 0
     bool inplace = false;  // one buffer, in-place streaming (layout alternates per step)
+    void* halo = nullptr;  // in place: room for the wavefront's halo copies
+    size_t halo_cap = 0;   // its bytes (0: one step per launch only)
     // layout of the stored field for buffer selector `sel` = cur ^ launch parity
     // (in place, the selector flips every step and starts at 0 in kLayNatural)
     int layout(int sel) const { return !inplace ? kLayPull : (sel ? kLaySwapped : kLayNatural); }
@@ -589,6 +552,8 @@ struct Lattice {
     // arithmetic type, which is at least as wide) with 32-bit byte offsets.
     bool tile_fits() const { return plane * (long long)arith_bytes(prec) <= 0xFFFFFFFFLL; }
     bool fused() const { return tb >= 2 && !general() && !inplace && (wave_hs > 0 || tile_fits()); }
+    // in place, up to tb steps per launch through the in-place wavefront
+    bool ip_blocked() const { return inplace && tb >= 2 && !general() && wave_hs > 0; }
     int eff_bxl() const { return fused() ? 6 : bx_log2; }
     int eff_vy() const { return fused() ? th / 4 : (general() ? 1 : vy); }
     int tile_h() const { return (kBlock >> eff_bxl()) * eff_vy(); }

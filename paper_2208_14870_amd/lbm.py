@@ -86,6 +86,7 @@ def load() -> ctypes.CDLL:
         "lbm_get_launch_config": (i, [vp, pi]),
         "lbm_get_wave_columns": (i, [vp]),
         "lbm_workspace_bytes_inplace": (sz, [i, i, i]),
+        "lbm_workspace_bytes_inplace_blocked": (sz, [i, i, i, i, i]),
         "lbm_create_inplace": (i, [i, i, i, vp, sz, vp, ctypes.POINTER(vp)]),
         "lbm_last_error": (ctypes.c_char_p, [vp]),
         "lbm_batch_slot_bytes": (sz, [i, i, i, i]),
@@ -182,10 +183,14 @@ def fourth_order_rates(lame_lambda: float, lame_mu: float, theta: float = 1.0 / 
 class Solver:
     """One periodic nx x ny lattice (lbm_create ... lbm_destroy); with
     inplace=True, one population buffer with in-place streaming
-    (lbm_create_inplace)."""
+    (lbm_create_inplace), with room for launches of up to `inplace_steps`
+    steps with segments of `inplace_segment_rows` rows (0: the default)
+    (lbm_workspace_bytes_inplace_blocked; inplace_steps=1: the minimal
+    workspace, one step per launch)."""
 
     def __init__(self, nx: int, ny: int, precision: str = "fp64", with_polish: bool = False,
-                 device: str = "cuda", inplace: bool = False):
+                 device: str = "cuda", inplace: bool = False, inplace_steps: int = 8,
+                 inplace_segment_rows: int = 0):
         self.lib = load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the HIP library cannot run")
@@ -195,7 +200,10 @@ class Solver:
         self.inplace = bool(inplace)
         if self.inplace and with_polish:
             raise ValueError("in-place streaming has no polish phase")
-        if self.inplace:
+        if self.inplace and int(inplace_steps) >= 2:
+            nbytes = self.lib.lbm_workspace_bytes_inplace_blocked(
+                self.nx, self.ny, self.precision, int(inplace_steps), int(inplace_segment_rows))
+        elif self.inplace:
             nbytes = self.lib.lbm_workspace_bytes_inplace(self.nx, self.ny, self.precision)
         else:
             nbytes = self.lib.lbm_workspace_bytes(self.nx, self.ny, self.precision,

@@ -65,6 +65,39 @@ def test_inplace_workspace_holds_one_population_buffer(lib):
         assert two - one <= 8 * (n * n + 2048) * esz + 256
 
 
+def test_inplace_blocked_workspace_adds_the_halo_copies(lib):
+    """The in-place workspace for blocked launches adds copies of 2R ring
+    columns per strip and 2k rows per segment (eight planes each): FP32 8192^2
+    at eight steps has strips of 112 columns (two per lane, ring 8) and
+    segments of 128 rows (74 x 64 waves); FP64 strips of 48 columns and
+    segments of 256 rows (171 x 32 waves)."""
+    lib.lbm_workspace_bytes_inplace.restype = ctypes.c_size_t
+    lib.lbm_workspace_bytes_inplace.argtypes = [ctypes.c_int] * 3
+    lib.lbm_workspace_bytes_inplace_blocked.restype = ctypes.c_size_t
+    lib.lbm_workspace_bytes_inplace_blocked.argtypes = [ctypes.c_int] * 5
+    blocked = lib.lbm_workspace_bytes_inplace_blocked
+
+    def f(nx, ny, prec, k, rows=0):
+        return blocked(nx, ny, prec, k, rows)
+
+    assert f(0, 4, 1, 8) == 0 and f(64, 64, 1, 1) == 0 and f(64, 64, 1, 9) == 0
+    assert f(64, 64, 1, 8, -1) == 0
+    n = 8192
+    one = lib.lbm_workspace_bytes_inplace(n, n, 1)
+    halo = 8 * (74 * 16 * n + 64 * 16 * n) * 4
+    assert 0 <= f(n, n, 1, 8) - one - halo <= 512
+    assert halo < 0.27 * 8 * n * n * 4
+    # FP64: one column per lane (ring 8 of 64 columns: strips of 48)
+    halo64 = 8 * (171 * 16 * n + 32 * 16 * n) * 8
+    assert 0 <= f(n, n, 0, 8) - lib.lbm_workspace_bytes_inplace(n, n, 0) - halo64 <= 512
+    # segments of 64 rows: twice the row copies
+    halo_64rows = 8 * (74 * 16 * n + 128 * 16 * n) * 4
+    assert 0 <= f(n, n, 1, 8, 64) - one - halo_64rows <= 512
+    for prec in (0, 1, 2):
+        sizes = [f(1000, 600, prec, k) for k in range(2, 9)]
+        assert sizes == sorted(sizes) and sizes[0] > lib.lbm_workspace_bytes_inplace(1000, 600, prec)
+
+
 def test_binding_has_no_cpu_fallback():
     """The Python binding raises when no GPU is visible instead of computing."""
     import torch

@@ -10,12 +10,14 @@ from gpu_common import assert_elementwise, dev, host, need_gpu, omega, rel_l2, s
 pytestmark = pytest.mark.gpu
 
 
-def _pair(nx, ny, prec, mat, gx, gy, f0=None, rates=None):
+def _pair(nx, ny, prec, mat, gx, gy, f0=None, rates=None, ip_steps=1):
+    """Two-buffer solver at one step per launch and an in-place solver with
+    room for launches of up to ip_steps steps (1: single steps only)."""
     from paper_2208_14870_amd import lbm
     need_gpu()
     out = []
     for inplace in (False, True):
-        s = lbm.Solver(nx, ny, prec, inplace=inplace)
+        s = lbm.Solver(nx, ny, prec, inplace=inplace, inplace_steps=ip_steps)
         if not inplace:
             s.set_time_blocking(1)
         if rates is not None:
@@ -36,16 +38,18 @@ def _rand(nx, ny, seed, scale=1e-3):
     return f, gx, gy
 
 
+@pytest.mark.parametrize("ip", [1, 8])
 @pytest.mark.parametrize("prec,nx,ny", [
     ("fp64", 1, 1), ("fp64", 3, 5), ("fp64", 67, 33), ("fp64", 2, 7), ("fp32", 65, 17),
     ("fp32", 256, 48), ("fp16", 97, 31), ("fp16", 4, 4)])
-def test_inplace_identical_to_two_buffers(prec, nx, ny):
+def test_inplace_identical_to_two_buffers(prec, nx, ny, ip):
     """After odd and even step counts the populations f(n), the displacement and
-    the stress equal the two-buffer solver's exactly; FP64 matches the oracle."""
-    say(f"inplace {prec} {nx}x{ny}")
+    the stress equal the two-buffer solver's exactly (single steps in place, and
+    blocked launches of up to eight); FP64 matches the oracle."""
+    say(f"inplace {prec} {nx}x{ny} up to {ip} steps per launch")
     mat = P.Material.from_shear_poisson(0.8, 0.3)
     f0, gx, gy = _rand(nx, ny, 11 + nx)
-    a, b = _pair(nx, ny, prec, mat, gx, gy, f0)
+    a, b = _pair(nx, ny, prec, mat, gx, gy, f0, ip_steps=ip)
     done = 0
     for n in (1, 2, 5, 8):  # cumulative 1, 3, 8, 16: odd and even
         a.step(n)
@@ -71,13 +75,14 @@ def test_inplace_general_rates():
     np.testing.assert_array_equal(host(b.populations()), host(a.populations()))
 
 
+@pytest.mark.parametrize("ip", [1, 8])
 @pytest.mark.parametrize("prec,K", [("fp64", 1), ("fp64", 2), ("fp64", 7), ("fp32", 50),
                                     ("fp16", 25)])
-def test_inplace_solve_to_tol(prec, K):
+def test_inplace_solve_to_tol(prec, K, ip):
     """Same stop step, residual and state as the two-buffer solver."""
-    say(f"inplace solve {prec} K={K}")
+    say(f"inplace solve {prec} K={K} up to {ip} steps per launch")
     c = P.single_32()
-    a, b = _pair(32, 32, prec, c.material, c.gx, c.gy)
+    a, b = _pair(32, 32, prec, c.material, c.gx, c.gy, ip_steps=ip)
     tol = {"fp64": 1e-10, "fp32": 1e-6, "fp16": 1e-3}[prec]
     ra = a.solve_to_tol(tol, 20000, K)
     rb = b.solve_to_tol(tol, 20000, K)
@@ -89,16 +94,17 @@ def test_inplace_solve_to_tol(prec, K):
         assert ra[0] == 113 or K > 1  # the oracle's stop step at K = 1
 
 
+@pytest.mark.parametrize("ip", [1, 8])
 @pytest.mark.parametrize("prec,n", [("fp64", 2), ("fp64", 17), ("fp32", 40)])
-def test_inplace_step_checked(prec, n):
+def test_inplace_step_checked(prec, n, ip):
     """step_checked in place (its check launch does not step, a plain step
     follows it) leaves the state of the two-buffer solver and returns its
     residual r(n - 1)."""
-    say(f"inplace step_checked {prec} n {n}")
+    say(f"inplace step_checked {prec} n {n} up to {ip} steps per launch")
     c = P.single_32()
     rng = np.random.default_rng(5)
     f0 = rng.standard_normal((8, 32, 32)) * 1e-3
-    a, b = _pair(32, 32, prec, c.material, c.gx, c.gy, f0=f0)
+    a, b = _pair(32, 32, prec, c.material, c.gx, c.gy, f0=f0, ip_steps=ip)
     a.set_time_blocking(8 if prec == "fp32" else 5)
     ra = a.step_checked(n)
     rb = b.step_checked(n)
@@ -148,15 +154,33 @@ def test_inplace_streaming_bit_exact(nx, ny):
 
 
 def test_inplace_arguments():
+    """The minimal workspace runs single steps only; blocked launches need the
+    halo room of lbm_workspace_bytes_inplace_blocked; no tile kernel, polish or
+    stochastic rounding in place."""
     from paper_2208_14870_amd import lbm
     need_gpu()
-    s = lbm.Solver(16, 16, "fp32", inplace=True)
+    s = lbm.Solver(16, 16, "fp32", inplace=True, inplace_steps=1)
+    assert s.launch_config()["steps_per_launch"] == 1
     s.set_time_blocking(1)
     with pytest.raises(lbm.LbmError):
         s.set_time_blocking(2)
     with pytest.raises(lbm.LbmError):
-        s.set_fused_kernel("wavefront", 16)
+        s.set_fused_kernel("tile")
     with pytest.raises(lbm.LbmError):
         s.set_polish(1e-6)
     with pytest.raises(ValueError):
         lbm.Solver(16, 16, "fp32", with_polish=True, inplace=True)
+    b = lbm.Solver(64, 64, "fp32", inplace=True, inplace_steps=4)
+    cfg = b.launch_config()
+    assert cfg["steps_per_launch"] == 4 and cfg["kernel"] == "wavefront"
+    assert cfg["columns_per_lane"] == 2
+    b.set_time_blocking(2)
+    with pytest.raises(lbm.LbmError):
+        b.set_time_blocking(6)  # beyond the room for four
+    with pytest.raises(lbm.LbmError):
+        b.set_fused_kernel("wavefront", 1)  # 64 segments need more row copies
+    b.set_fused_kernel("wavefront", 64)
+    with pytest.raises(lbm.LbmError):
+        b.set_fused_kernel("tile")
+    with pytest.raises(lbm.LbmError):
+        lbm.Solver(16, 16, "fp16", inplace=True).set_stochastic_rounding(True, 1)

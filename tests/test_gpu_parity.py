@@ -555,8 +555,10 @@ def test_launch_config_defaults():
     five steps through 8-row tiles of 512 threads below 2^20 sites; the register
     wavefront at eight steps for FP64 from 2^20 sites, FP32 from 2^22 (two
     columns per lane from 2^25 on even widths) and FP16 from 2^24; the caller's
-    depth keeps the default kernel, the caller's kernel stays; one step per
-    launch in place."""
+    depth keeps the default kernel, the caller's kernel stays; in place the
+    in-place wavefront at the deepest depth the workspace has room for (one
+    step per launch in the minimal workspace), segments of 256 rows halved
+    while the lattice would give fewer than 4096 waves."""
     from paper_2208_14870_amd import lbm
     need_gpu()
     cfg = lambda n, m, p, **kw: lbm.Solver(n, m, p, **kw).launch_config()
@@ -589,8 +591,15 @@ def test_launch_config_defaults():
     s.set_time_blocking(1)
     assert s.launch_config()["kernel"] == "single"
     s.close()
-    c = cfg(256, 256, "fp32", inplace=True)
+    c = cfg(256, 256, "fp32", inplace=True, inplace_steps=1)
     assert c["steps_per_launch"] == 1 and c["kernel"] == "single"
+    assert cfg(256, 256, "fp32", inplace=True) == {
+        "steps_per_launch": 8, "kernel": "wavefront", "rows": 32, "threads": 256,
+        "columns_per_lane": 2}
+    assert cfg(256, 255, "fp16", inplace=True, inplace_steps=4) == {
+        "steps_per_launch": 4, "kernel": "wavefront", "rows": 32, "threads": 256,
+        "columns_per_lane": 2}
+    assert cfg(2049, 8192, "fp64", inplace=True)["rows"] == 64  # 43 strips x 128 segments
 
 
 # ---------------------------------------------------------------------------
