@@ -53,17 +53,23 @@ BYTES_PER_SITE = {"fp64": 144, "fp32": 72, "fp16": 40}  # 8 pops in + 8 out + 2 
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
-TRAFFIC_SOURCES = ("lbm_common.hpp", "lbm_fused.hpp")  # the headers that define the fused kernels
+# the headers that define each fused kernel family
+TRAFFIC_SOURCES = {"tile": ("lbm_common.hpp", "lbm_fused.hpp"),
+                   "wave": ("lbm_common.hpp", "lbm_wave.hpp")}
 
 
-def kernel_source_hash() -> str:
-    """sha256 of the tile kernel's headers with comments and whitespace removed
-    (the code the counters were taken with)."""
+def kernel_family(kernel: str) -> str:
+    return "wave" if "k_wave" in kernel else "tile"
+
+
+def kernel_source_hash(family: str = "tile") -> str:
+    """sha256 of a fused kernel family's headers with comments and whitespace
+    removed (the code the counters were taken with)."""
     import hashlib
     import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2208_14870_amd", "csrc")
-    for f in TRAFFIC_SOURCES:
+    for f in TRAFFIC_SOURCES[family]:
         text = open(os.path.join(csrc, f)).read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
         text = re.sub(r"//[^\n]*", " ", text)
@@ -82,7 +88,7 @@ def measured_counters(name, kernel=None):
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if kernel_source_hash() != rec.get("source_sha256"):
+    if kernel_source_hash(kernel_family(rec.get("kernel", ""))) != rec.get("source_sha256"):
         return None
     if kernel is not None and kernel not in rec.get("kernel", ""):
         return None
@@ -217,19 +223,21 @@ def make_solvers(cases, prec):
     return out
 
 
-def kernel_label(cfg, ctype, sites):
-    """Name and algorithmic traffic of the plain-step kernel of a launch config."""
+def kernel_label(cfg, ctype, sites, sr=False):
+    """Name (with its full template arguments, as the profiler names it) and
+    algorithmic traffic of the plain-step kernel of a launch config."""
     tb, rows, nt = cfg["steps_per_launch"], cfg["rows"], cfg["threads"]
     per_site = {"double": 144, "float": 72, "__half": 40}[ctype]
     side = int(round(math.sqrt(sites)))
-    if cfg["kernel"] == "tile":  # template arguments: type, tile rows, steps, threads, plain mode
-        return (f"k_stepN<{ctype}, {rows}, {tb}, {nt}, 0> (LDS tile 64 x {rows} + ring {tb - 1}, "
-                f"{nt} threads): {tb} fused steps per launch, {per_site} B per site-update "
-                f"algorithmic, {tb} x {side}^2 site-updates per launch")
-    if cfg["kernel"] == "wavefront":
+    srs = "true" if sr else "false"
+    if cfg["kernel"] == "tile":  # type, tile rows, steps, threads, plain mode, rounding
+        return (f"k_stepN<{ctype}, {rows}, {tb}, {nt}, 0, {srs}> (LDS tile 64 x {rows} + ring "
+                f"{tb - 1}, {nt} threads): {tb} fused steps per launch, {per_site} B per "
+                f"site-update algorithmic, {tb} x {side}^2 site-updates per launch")
+    if cfg["kernel"] == "wavefront":  # type, steps, columns per lane, rounding, in place
         v = cfg.get("columns_per_lane", 1)
-        return (f"k_wave<{ctype}, {tb}, {v}> (register wavefront, {rows}-row segments): {tb} fused "
-                f"steps per launch, "
+        return (f"k_wave<{ctype}, {tb}, {v}, {srs}, false> (register wavefront, {rows}-row "
+                f"segments): {tb} fused steps per launch, "
                 f"{per_site} B per site-update algorithmic, {tb} x {side}^2 site-updates per launch")
     return f"k_step<{ctype}, ...>: one step per launch, {per_site} B per site-update algorithmic"
 
@@ -426,7 +434,7 @@ def large_lattice(steps=10000, warm=200, precs=("fp64", "fp32", "fp16", "fp16sr"
         out[key] = {"mlups": round(sites / us, 1), "us_per_step": round(us, 2),
                     "launch_config": cfg,
                     "roofline": roofline(prec, sites, us * steps / launches, tbl,
-                                         kernel_label(cfg, ctype, sites),
+                                         kernel_label(cfg, ctype, sites, key == "fp16sr"),
                                          (f"k_stepN_{prec}_8192_counters" if cfg["kernel"] == "tile"
                                           else f"k_wave_{prec}_8192_counters")
                                          if key == prec else None)}
@@ -821,7 +829,9 @@ def main():
                        "roofline": roofline("fp64", nsites, r64["plain_kernel_avg_us"],
                                             r64["steps_per_launch"],
                                             kernel_label(r64["launch_config"], "double", nsites),
-                                            "k_stepN_fp64_1024_counters")}
+                                            ("k_wave_fp64_1024_counters"
+                                             if r64["launch_config"]["kernel"] == "wavefront"
+                                             else "k_stepN_fp64_1024_counters"))}
         out["fp32_speedup_over_fp64"] = round(r32["mlups"] / r64["mlups"], 3)
         log("the same sweep, its 8 lattices advanced together (batch)")
         out["sweep_batched_fp32"] = sweep_batched(cases, args.steps, args.chunk)

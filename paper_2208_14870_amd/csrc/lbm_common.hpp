@@ -304,6 +304,17 @@ __device__ __forceinline__ void collide(C f[8], C gx, C gy, const Coef<C>& k, C&
 //   which is f(n+1)_q there: the buffer is back in kLayNatural.
 enum Layout : int { kLayPull = 0, kLayNatural = 1, kLaySwapped = 2 };
 
+// v modulo n in 0..n-1 (periodic coordinates; any v)
+__device__ __forceinline__ int wrap_coord(int v, int n) {
+    if (v < 0) v += n;
+    if (v < 0) v = ((v % n) + n) % n;
+    if (v >= n) {
+        v -= n;
+        if (v >= n) v %= n;
+    }
+    return v;
+}
+
 // opposite direction: c_opp(q) = -c_q (paper order 1..8 -> 0..7)
 __host__ __device__ constexpr int opp(int q) { return q < 4 ? q ^ 2 : 4 + ((q - 4) ^ 2); }
 

@@ -8,5 +8,6 @@
 #include "lbm_common.hpp"
 #include "lbm_step.hpp"
 #include "lbm_fused.hpp"
+#include "lbm_wave.hpp"
 #include "lbm_util.hpp"
 #include "lbm_small.hpp"

@@ -6,7 +6,7 @@
 #include <algorithm>
 #include <type_traits>
 
-#include "lbm_fused.hpp"
+#include "lbm_wave.hpp"
 #include "lbm_host_base.hpp"
 
 namespace lbm_host {
