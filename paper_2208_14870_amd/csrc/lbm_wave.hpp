@@ -170,9 +170,13 @@ static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
     constexpr bool kNat = IP && (NS % 2 == 1);  // level 0 is f(n) itself
     constexpr int W = wave_width<NS, V>();
     constexpr int PF = 3;  // rows loaded ahead
-    // wave index as a scalar: the row loop and the row bases stay scalar
-    const int wid = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlock / kWave) +
-                                                   (int)(threadIdx.x >> 6));
+    // wave index as a scalar: the row loop and the row bases stay scalar.
+    // Blocks go to the 8 XCDs round-robin; each XCD takes a contiguous range of
+    // blocks, so that strips side by side, whose rings overlap, run on one XCD
+    // at the same time and share its L2.
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int lb = (b % 8) * (nb / 8) + min(b % 8, nb % 8) + b / 8;
+    const int wid = __builtin_amdgcn_readfirstlane(lb * (kBlock / kWave) + (int)(threadIdx.x >> 6));
     const int lane = (int)(threadIdx.x & (kWave - 1));
     if (wid >= L.strips * L.segs) return;  // whole waves leave; no barrier follows
     const SlotDesc& d = L.slots[0];
@@ -262,6 +266,9 @@ static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
 #pragma unroll
         for (int u = 0; u < 6; ++u) {
             const int t = t0 + u;
+            // (rows from yb + NS on feed no output; loading them anyway keeps
+            // the loop free of branches: skipping them measured slower, FP16
+            // 8192^2 375 against 446 GLUPS)
             load_row(t + PF, A0[(u + PF) % 6], Gp[(u + PF) % 6]);
 #pragma unroll
             for (int j = NS; j > 0; --j)
