@@ -12,7 +12,8 @@ in [0, pi/4] (5 points); a lattice-specific check uses the lattice's own
 wavevectors 2 pi (a/nx, b/ny).
 
 This is a planning tool for choosing material / time-step parameters; the
-GPU library does not call it.
+GPU library does not call it (its error estimates R1, R2 come from the
+library's host-only lbm_leading_error_constants).
 """
 from __future__ import annotations
 
@@ -179,14 +180,30 @@ def predicted_steps(rho: float, tol: float) -> int:
     return int(math.ceil(1.0 + math.log(tol / (1.0 - rho)) / math.log(rho)))
 
 
+def error_estimates(lame_lambda: float, lame_mu: float, theta: float = 1.0 / 3.0):
+    """(R1, R2) of Eq. rss_estimate: the root-sum-square of the leading-order
+    error constants left with the improved scheme's force correction (C1..C5),
+    and without it (C1..C5, D1..D3) (Sec. 4, App. B), from the library's host
+    function lbm_leading_error_constants (no GPU involved)."""
+    from . import lbm
+    c = lbm.leading_error_constants(lame_lambda, lame_mu, theta)
+    return c["R1"], c["R2"]
+
+
 def advise(nu: float, n: int, young: Optional[Iterable[float]] = None, tol: float = 1e-8,
-           max_error: Optional[float] = None) -> Tuple[list, Optional[dict]]:
+           max_error: Optional[float] = None,
+           criterion: str = "steps") -> Tuple[list, Optional[dict]]:
     """Choice of the dimensionless Young's modulus (Eq. scalingE: the ratio of time
     step to damping for a given physical E) for an n x n lattice at Poisson ratio
     nu.  For each candidate: stability on the paper's grid, the steps to reach tol
-    for the slowest decaying lattice mode, and the steady-state error of the lowest
-    diagonal load mode k = 2 pi (1, 1)/n.  Returns (rows, the stable row with the
-    fewest steps whose error is at most max_error, or None)."""
+    for the slowest decaying lattice mode, the steady-state error of the lowest
+    diagonal load mode k = 2 pi (1, 1)/n, and the error estimates R1 (with the
+    force correction) and R2 (without) of Sec. 4.  Returns (rows, the pick or
+    None): criterion "steps" picks the stable row with the fewest steps whose
+    error is at most max_error; "R1" / "R2" pick the stable row with the
+    smallest estimate, as Sec. 4 picks E~ for the improved / standard scheme."""
+    if criterion not in ("steps", "R1", "R2"):
+        raise ValueError("criterion must be 'steps', 'R1' or 'R2'")
     young = np.geomspace(0.01, 10.0, 25) if young is None else young
     rows = []
     for E in young:
@@ -194,9 +211,13 @@ def advise(nu: float, n: int, young: Optional[Iterable[float]] = None, tol: floa
         stable = is_stable(lam, mu)
         rho, _ = slowest_decay(lam, mu, n, n)
         k = 2 * math.pi / n
+        r1, r2 = error_estimates(lam, mu)
         rows.append({"young": float(E), "lame_lambda": lam, "lame_mu": mu, "stable": stable,
                      "rho": rho, "steps": predicted_steps(rho, tol),
-                     "error_k11": mode_error(lam, mu, k, k)})
-    ok = [r for r in rows if r["stable"] and r["steps"] > 0 and
-          (max_error is None or r["error_k11"] <= max_error)]
-    return rows, (min(ok, key=lambda r: r["steps"]) if ok else None)
+                     "error_k11": mode_error(lam, mu, k, k), "R1": r1, "R2": r2})
+    if criterion == "steps":
+        ok = [r for r in rows if r["stable"] and r["steps"] > 0 and
+              (max_error is None or r["error_k11"] <= max_error)]
+        return rows, (min(ok, key=lambda r: r["steps"]) if ok else None)
+    ok = [r for r in rows if r["stable"]]
+    return rows, (min(ok, key=lambda r: r[criterion]) if ok else None)

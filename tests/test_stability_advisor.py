@@ -129,3 +129,22 @@ def test_advise_picks_the_fastest_stable_accurate_modulus():
     ok = [r for r in rows if r["stable"] and r["error_k11"] <= 0.02]
     assert best is not None and best["steps"] == min(r["steps"] for r in ok)
     assert best["young"] != 0.082
+
+
+def test_advise_by_error_estimate_picks_the_papers_modulus():
+    """Sec. 4 / Sec. 7.3.2: picking E~ by the smallest R1 (the estimate with the
+    force correction) at nu = 0.8 gives about the 0.085 the paper uses; the
+    advisor's R1, R2 are the library's host computation, equal to the oracle's
+    (which is pinned against the exact discrete symbols)."""
+    young = np.geomspace(0.02, 0.5, 120)
+    rows, best = ST.advise(0.8, 40, young=young, criterion="R1")
+    assert best is not None and best["stable"]
+    assert abs(best["young"] - 0.085) <= 0.1 * 0.085, best["young"]
+    for r in rows[::17]:
+        want = O.error_estimates(O.leading_error_constants(r["young"], 0.8))
+        assert r["R1"] == pytest.approx(want[0], rel=1e-10)
+        assert r["R2"] == pytest.approx(want[1], rel=1e-10)
+    _, by_r2 = ST.advise(0.8, 40, young=young, criterion="R2")
+    assert by_r2["R2"] >= 4.0 * best["R1"]
+    with pytest.raises(ValueError):
+        ST.advise(0.8, 40, young=young, criterion="fast")
