@@ -32,12 +32,20 @@ DEFAULT_CACHE = os.environ.get("LBM_AUTOTUNE_CACHE",
 
 
 def candidates(nx: int, min_bx: int = 3, ny: int = 0, wavefront: bool = False,
-               fused: bool = True, precision: str = "fp32") -> List[Shape]:
+               fused: bool = True, precision: str = "fp32", inplace: bool = False) -> List[Shape]:
     """Single-step tile shapes; the fused LDS tile kernel at 2..8 steps with one
     workgroup per tile or a persistent grid, and for single FP32 lattices also
     its 24-row tile at five steps or more; and (single lattices) the register
-    wavefront at 3..8 steps with a few segment heights; single-step shapes only
-    for in-place solvers (fused=False)."""
+    wavefront at 3..8 steps with a few segment heights.  In place: single-step
+    shapes and the in-place wavefront (those the solver's halo room admits are
+    timed); fused=False: single-step shapes only."""
+    if inplace:
+        out = []
+        if fused:
+            for rows in (64, 128, 256):
+                if rows <= max(ny, 32):
+                    out += [(6, 4, 0, t, rows, 0) for t in (8, 6, 4)]
+        return out + [s for s in candidates(nx, min_bx, ny, fused=False) if s[3] == 1]
     out = [(6, 4, k, t, 0, 0) for t in (8, 7, 6, 5, 4, 3, 2) for k in (0, 4)] if fused else []
     if fused and wavefront and precision == "fp32":
         out += [(6, 4, 0, t, 0, 24) for t in (8, 7, 6, 5)]
@@ -55,6 +63,15 @@ def candidates(nx: int, min_bx: int = 3, ny: int = 0, wavefront: bool = False,
 
 
 def _apply(obj, shp: Shape):
+    if getattr(obj, "inplace", False):
+        # in place the depth is checked against the halo room for the segment
+        # height: set the height at one step per launch, then the depth
+        obj.set_time_blocking(1)
+        obj.set_tile(shp[0], shp[1], shp[2])
+        if shp[4] > 0:
+            obj.set_fused_kernel("wavefront", shp[4])
+        obj.set_time_blocking(shp[3])
+        return
     obj.set_time_blocking(shp[3])
     obj.set_tile(shp[0], shp[1], shp[2])
     if hasattr(obj, "set_fused_kernel") and not getattr(obj, "inplace", False):
@@ -74,7 +91,7 @@ def _arch() -> str:
 
 
 def _key(kind: str, precision: str, sites: int) -> str:
-    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}|v7"
+    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}|v8"
 
 
 def _load(path: str) -> Dict[str, list]:
@@ -102,9 +119,13 @@ def time_shapes(set_shape: Callable[[Shape], None], step: Callable[[int], None],
     """Returns [(microseconds per step, shape)] sorted fastest first.  Step
     counts are whole multiples of the shape's steps per launch, so that only
     the shape's own launches are timed."""
+    from .lbm import LbmError
     res = []
     for shp in shapes:
-        set_shape(shp)
+        try:
+            set_shape(shp)
+        except LbmError:  # a shape this solver does not admit (e.g. halo room)
+            continue
         t = max(1, shp[3])
         k = 4 * t
         step(k)  # warm the shape (graph capture, caches)
@@ -141,8 +162,8 @@ def tune_solver(solver, precision: str, cache_path: Optional[str] = DEFAULT_CACH
         _apply(solver, shp)
         return shp
     res = time_shapes(lambda s: _apply(solver, s), solver.step,
-                      candidates(solver.nx, 0, solver.ny, wavefront=True, fused=not inplace,
-                                 precision=precision),
+                      candidates(solver.nx, 0, solver.ny, wavefront=True, precision=precision,
+                                 inplace=inplace),
                       sites)
     shp = res[0][1]
     _apply(solver, shp)

@@ -43,14 +43,30 @@ def test_tune_batch(tmp_path):
 
 
 def test_tune_inplace_solver(tmp_path):
-    """In-place solvers are tuned over single-step shapes only."""
-    say("autotune in-place solver 128x96 fp32")
+    """In-place solvers are tuned over single-step shapes and the in-place
+    wavefront shapes their halo room admits; the tuned solver's populations
+    equal the two-buffer solver's single steps bit for bit.  With the minimal
+    workspace only single-step shapes remain."""
+    say("autotune in-place solver 128x128 fp32")
     need_gpu()
     from paper_2208_14870_amd import autotune, lbm
     c = P.single_1024(0.3, 1, 1, n=128)
-    s = lbm.Solver(128, 128, "fp32", inplace=True)
-    s.set_material(c.material.lame_lambda, c.material.lame_mu)
-    s.set_body_force(dev(c.gx), dev(c.gy))
-    shp = autotune.tune_solver(s, "fp32", cache_path=str(tmp_path / "t.json"))
-    assert shp in autotune.candidates(128, 0, 128, wavefront=True, fused=False)
-    assert shp[3] == 1 and shp[4] == 0
+    ref = lbm.Solver(128, 128, "fp32")
+    ref.set_time_blocking(1)
+    ref.set_material(c.material.lame_lambda, c.material.lame_mu)
+    ref.set_body_force(dev(c.gx), dev(c.gy))
+    ref.step(37)
+    want = host(ref.populations())
+    ref.close()
+    for room in (8, 1):
+        s = lbm.Solver(128, 128, "fp32", inplace=True, inplace_steps=room)
+        s.set_material(c.material.lame_lambda, c.material.lame_mu)
+        s.set_body_force(dev(c.gx), dev(c.gy))
+        shp = autotune.tune_solver(s, "fp32", cache_path=str(tmp_path / f"t{room}.json"))
+        assert shp in autotune.candidates(128, 0, 128, wavefront=True, inplace=True)
+        if room == 1:
+            assert shp[3] == 1 and shp[4] == 0
+        s.reset()
+        s.step(37)
+        np.testing.assert_array_equal(host(s.populations()), want)
+        s.close()
