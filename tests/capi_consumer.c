@@ -3,7 +3,10 @@
  * lattice to a tolerance through include/lbm.h and writes the displacement.
  *
  * usage: capi_consumer nx ny lambda mu precision tol max_steps check_every
- *                      force.bin displacement.bin
+ *                      force.bin displacement.bin [inplace_steps]
+ * inplace_steps (optional, default 0): 0 two buffers (lbm_create); 1 in place
+ * with the minimal workspace (lbm_workspace_bytes_inplace); k in 2..8 in place
+ * with room for launches of up to k steps (lbm_workspace_bytes_inplace_blocked).
  * force.bin: gx then gy, FP64, [ny][nx] each (x fastest); displacement.bin
  * receives ux then uy in the same layout.  Prints one JSON line (solve status,
  * the warning bits of lbm_set_body_force, steps, residual); exit status 0
@@ -24,11 +27,12 @@ static int hip_ok(hipError_t e, const char *what) {
 }
 
 int main(int argc, char **argv) {
-    if (argc != 11) {
+    if (argc != 11 && argc != 12) {
         fprintf(stderr, "usage: %s nx ny lambda mu precision tol max_steps check_every "
-                        "force.bin displacement.bin\n", argv[0]);
+                        "force.bin displacement.bin [inplace_steps]\n", argv[0]);
         return 2;
     }
+    const int inplace_steps = argc == 12 ? atoi(argv[11]) : 0;
     const int nx = atoi(argv[1]), ny = atoi(argv[2]);
     const double lam = atof(argv[3]), mu = atof(argv[4]);
     const int precision = atoi(argv[5]);
@@ -46,7 +50,10 @@ int main(int argc, char **argv) {
     }
     fclose(fin);
 
-    const size_t ws = lbm_workspace_bytes(nx, ny, precision, 0);
+    const size_t ws = inplace_steps >= 2
+                          ? lbm_workspace_bytes_inplace_blocked(nx, ny, precision, inplace_steps, 0)
+                      : inplace_steps == 1 ? lbm_workspace_bytes_inplace(nx, ny, precision)
+                                           : lbm_workspace_bytes(nx, ny, precision, 0);
     void *d_ws = NULL;
     double *d_g = NULL, *d_u = NULL;
     if (ws == 0 || !hip_ok(hipMalloc(&d_ws, ws), "hipMalloc workspace") ||
@@ -56,7 +63,8 @@ int main(int argc, char **argv) {
         return 1;
 
     lbm_solver *s = NULL;
-    int rc = lbm_create(nx, ny, precision, 0, d_ws, ws, NULL, &s);
+    int rc = inplace_steps > 0 ? lbm_create_inplace(nx, ny, precision, d_ws, ws, NULL, &s)
+                               : lbm_create(nx, ny, precision, 0, d_ws, ws, NULL, &s);
     if (rc != LBM_OK) {
         fprintf(stderr, "lbm_create: %s\n", lbm_last_error(NULL));
         return 1;
@@ -87,15 +95,18 @@ int main(int argc, char **argv) {
     /* the library works on the null stream here, so this copy follows it */
     if (!hip_ok(hipMemcpy(host, d_u, 2 * n * sizeof(double), hipMemcpyDeviceToHost), "download"))
         return 1;
-    lbm_destroy(s);
     FILE *fout = fopen(argv[10], "wb");
     if (!fout || fwrite(host, sizeof(double), 2 * n, fout) != 2 * n) {
         fprintf(stderr, "cannot write %s\n", argv[10]);
         return 1;
     }
     fclose(fout);
-    printf("{\"status\": %d, \"force_status\": %d, \"steps\": %lld, \"residual\": %.17g}\n",
-           status, force_status, steps, residual);
+    int cfg[4] = {0, 0, 0, 0};
+    lbm_get_launch_config(s, cfg);
+    printf("{\"status\": %d, \"force_status\": %d, \"steps\": %lld, \"residual\": %.17g, "
+           "\"steps_per_launch\": %d, \"kernel\": %d}\n",
+           status, force_status, steps, residual, cfg[0], cfg[1]);
+    lbm_destroy(s);
     hipFree(d_u);
     hipFree(d_g);
     hipFree(d_ws);

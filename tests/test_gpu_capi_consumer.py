@@ -71,3 +71,36 @@ def test_c_consumer_mean_removed(tmp_path):
     ox, oy = O.displacement(f, px, py)
     assert st == 0 and rec["steps"] == n
     assert_elementwise((u[0], u[1]), (ox, oy), 1e-12, "u")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c_consumer_inplace_blocked(tmp_path, precision):
+    """From plain C: an in-place solver with room for eight steps per launch
+    (lbm_workspace_bytes_inplace_blocked, lbm_create_inplace) takes the in-place
+    wavefront and reaches the two-buffer solver's stop step, residual and
+    displacement exactly; the minimal in-place workspace runs one step per
+    launch to the same result."""
+    need_gpu()
+    assert os.path.exists(EXE), "C consumer not built (run __graft_entry__.build())"
+    case = P.single_1024(0.3, 4, 3, n=96)
+    mat = case.material
+    fin = str(tmp_path / "force.bin")
+    np.concatenate([case.gx.ravel(), case.gy.ravel()]).astype(np.float64).tofile(fin)
+    tol = 1e-9 if precision == 0 else 1e-6
+    out = {}
+    for ip in (0, 1, 8):
+        fout = str(tmp_path / f"u{ip}.bin")
+        say(f"C consumer 96x96, precision {precision}, inplace_steps {ip}")
+        r = subprocess.run([EXE, "96", "96", repr(mat.lame_lambda), repr(mat.lame_mu),
+                            str(precision), repr(tol), "40000", "37", fin, fout, str(ip)],
+                           capture_output=True, text=True, timeout=120)
+        assert r.returncode == 0, r.stderr
+        rec = json.loads(r.stdout.strip().splitlines()[-1])
+        out[ip] = (rec, np.fromfile(fout, dtype=np.float64))
+    assert out[8][0]["steps_per_launch"] == 8 and out[8][0]["kernel"] == 1
+    assert out[1][0]["steps_per_launch"] == 1
+    for ip in (1, 8):
+        assert out[ip][0]["status"] == out[0][0]["status"] == 0
+        assert out[ip][0]["steps"] == out[0][0]["steps"]
+        assert out[ip][0]["residual"] == pytest.approx(out[0][0]["residual"], rel=1e-12)
+        np.testing.assert_array_equal(out[ip][1], out[0][1])
