@@ -390,9 +390,9 @@ enum lbm_fused_kernel {
  * that many rows, each recomputing 2k halo rows.  Default (until this is
  * called, and again after a polish switch), measured: the wavefront for FP64
  * lattices from 2^20 sites, FP32 from 2^22 (two columns per lane from 2^25 on
- * even widths) and FP16 from 2^24, with segments of 128 rows from 2^24 sites
- * and 32 below (halved down to 32 while the lattice would give fewer than 8
- * waves per compute unit); the tile kernel otherwise.  The tile kernel addresses a plane
+ * even widths) and FP16 from 2^24, with segments as long as leaves one wave
+ * per SIMD over the lattice's strips (16 to 128 rows); the tile kernel
+ * otherwise.  The tile kernel addresses a plane
  * with 32-bit byte offsets, so a lattice whose planes hold 2^32 bytes or more
  * in the arithmetic type (above 2^30 FP32/FP16 or 2^29 FP64 sites) defaults
  * to the wavefront whatever its width.  In place the wavefront is the only

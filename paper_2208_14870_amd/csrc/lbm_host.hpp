@@ -327,10 +327,13 @@ inline hipError_t launch_solve_small(int prec, bool general, hipStream_t st, con
 //   FP64  8192^2 117 / 235, 4096^2 119 / 223, 2048^2 115 / 160, 1024^2 102 / 133
 // (FP64 tile at five steps).  So: the wavefront at eight steps for FP64 from
 // 2^20 sites, FP32 from 2^22 (two columns per lane from 2^25 on even widths)
-// and FP16 from 2^24; the tile kernel below.  Segments of 128 rows from 2^24
-// sites, of 32 below (shorter ones cost more halo than their extra waves gain:
-// FP64 1024^2 91 GLUPS at 16 rows against 133 at 32), halved down to 32 while
-// the lattice would give fewer than eight waves per compute unit.  `beyond_tile`: the planes exceed the tile kernel's
+// and FP16 from 2^24; the tile kernel below.  Segments: as long as leaves
+// one wave per SIMD (4 per compute unit) over the strips, at most 128 rows and
+// at least 16: a lattice that fills the chip once with long segments reads the
+// fewest halo rows (GLUPS at eight steps by segment rows, MI355X: FP64 1024^2
+// 156 at 32, 165-169 at 23-24, 110 at 16; FP64 2048^2 191 at 32, 228 at 90-96,
+// 217 at 128; FP32 2048^2 343 at 32, 399 at 90; FP64 / FP32 4096^2 best at
+// 128; every type at 8192^2 best at 128).  `beyond_tile`: the planes exceed the tile kernel's
 // 32-bit offsets, so the wavefront (one column per lane, any width) is the
 // only fused kernel.  wave_hs = 0 selects the tile kernel.
 struct FusedChoice {
@@ -352,9 +355,10 @@ inline FusedChoice default_fused(int prec, int ns, int nx, int ny, int cus, bool
     if (!wave || ns < 2) return c;
     c.wave_v = wave_cols(prec, ns, nx, ny);
     const long long strips = (nx + wave_width_of(ns, c.wave_v) - 1) / wave_width_of(ns, c.wave_v);
-    int hs = n >= (1LL << 24) ? 128 : 32;
-    while (hs > 32 && strips * ((ny + hs - 1) / hs) < 8LL * cus) hs /= 2;
-    c.wave_hs = hs;
+    // segments as long as one wave per SIMD allows (fewest halo rows with the
+    // chip filled), 16..128 rows
+    const long long per = std::max(1LL, 4LL * cus / strips);
+    c.wave_hs = (int)std::min<long long>(128, std::max<long long>(16, (ny + per - 1) / per));
     return c;
 }
 

@@ -65,14 +65,26 @@ def test_inplace_identical_to_two_buffers(prec, nx, ny, ip):
         assert_elementwise(host(b.populations()), fn, 1e-12, "f")
 
 
-def test_inplace_general_rates():
-    say("inplace general rates")
+@pytest.mark.parametrize("ip", [1, 8])
+def test_inplace_general_rates(ip):
+    """General rates have no fused kernel: in place they run one step per
+    launch whatever the halo room, with the two-buffer results; setting the
+    standard rates again returns to blocked launches."""
+    say(f"inplace general rates, room for {ip} steps per launch")
     mat = P.Material.from_shear_poisson(0.6, 0.25)
     f0, gx, gy = _rand(40, 24, 3)
-    a, b = _pair(40, 24, "fp64", mat, gx, gy, f0, rates=(0.3, 1.2, 0.9, 1.1))
+    a, b = _pair(40, 24, "fp64", mat, gx, gy, f0, rates=(0.3, 1.2, 0.9, 1.1), ip_steps=ip)
+    assert b.launch_config()["kernel"] == "single"
     a.step(9)
     b.step(9)
     np.testing.assert_array_equal(host(b.populations()), host(a.populations()))
+    if ip == 8:
+        for s_ in (a, b):
+            s_.set_rates(1.0 / 3.0, 1.0, 1.0, 1.0)
+        assert b.launch_config()["kernel"] == "wavefront"
+        a.step(13)
+        b.step(13)
+        np.testing.assert_array_equal(host(b.populations()), host(a.populations()))
 
 
 @pytest.mark.parametrize("ip", [1, 8])

@@ -554,7 +554,10 @@ def test_launch_config_defaults():
     (16 rows, 512 threads) for FP32 and FP16 above 2^17 sites, four below; FP64
     five steps through 8-row tiles of 512 threads below 2^20 sites; the register
     wavefront at eight steps for FP64 from 2^20 sites, FP32 from 2^22 (two
-    columns per lane from 2^25 on even widths) and FP16 from 2^24; the caller's
+    columns per lane from 2^25 on even widths) and FP16 from 2^24, with
+    segments as long as one wave per SIMD (1024 on 256 compute units) allows,
+    16 to 128 rows (1024^2 FP64: 22 strips of 48 columns, 46 per strip, 23
+    rows; 2048^2: 43 strips, 23 per strip, 90 rows); the caller's
     depth keeps the default kernel, the caller's kernel stays; in place the
     in-place wavefront at the deepest depth the workspace has room for (one
     step per launch in the minimal workspace), segments of 256 rows halved
@@ -572,8 +575,9 @@ def test_launch_config_defaults():
                                      "threads": 512}
     assert cfg(512, 512, "fp64") == {"steps_per_launch": 5, "kernel": "tile", "rows": 8,
                                      "threads": 512}
-    for n, m, p, rows, v in ((1024, 1024, "fp64", 32, 1), (4096, 4096, "fp64", 128, 1),
-                             (2048, 2048, "fp32", 32, 1), (4096, 4096, "fp32", 128, 1),
+    for n, m, p, rows, v in ((1024, 1024, "fp64", 23, 1), (4096, 4096, "fp64", 128, 1),
+                             (2048, 2048, "fp64", 90, 1),
+                             (2048, 2048, "fp32", 90, 1), (4096, 4096, "fp32", 128, 1),
                              (8192, 8192, "fp32", 128, 2), (8191, 8192, "fp32", 128, 1),
                              (4096, 4096, "fp16", 128, 1)):
         assert cfg(n, m, p) == {"steps_per_launch": 8, "kernel": "wavefront", "rows": rows,
