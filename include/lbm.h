@@ -350,8 +350,8 @@ int lbm_set_tile(lbm_solver *s, int bx_log2, int rows_per_thread, int blocks_per
  * and the general-rates variant run one step per launch (with the tile kernel
  * a check rides on the last fused launch).  Overrides the tile shape of
  * lbm_set_tile while active.  Default by storage type and size: FP32 and FP16
- * 8 above 2^17 sites, else 4; FP64 5 below 2^20 sites, else 8 (also after a
- * polish switch).  The fused kernel follows the default of
+ * 8 above 2^17 sites, else 4; FP64 5 below 458752 sites (the tile kernel),
+ * else 8 (the wavefront; also after a polish switch).  The fused kernel follows the default of
  * lbm_set_fused_kernel for k until the caller picks one.  In place: the
  * in-place wavefront (see lbm_create_inplace), one column per lane for FP64
  * and for FP16 above four steps, two otherwise on even widths; segments of
@@ -389,8 +389,8 @@ enum lbm_fused_kernel {
  * is used by LBM_FUSED_WAVEFRONT only: each strip is split into segments of
  * that many rows, each recomputing 2k halo rows.  Default (until this is
  * called, and again after a polish switch), measured: the wavefront for FP64
- * lattices from 2^20 sites, FP32 from 2^22 (two columns per lane from 2^25 on
- * even widths) and FP16 from 2^24, with segments as long as leaves one wave
+ * lattices from 458752 sites (about 677^2), FP32 above 2^20 (two columns per
+ * lane from 2^25 on even widths) and FP16 from 2^24, with segments as long as leaves one wave
  * per SIMD over the lattice's strips (16 to 128 rows); the tile kernel
  * otherwise.  The tile kernel addresses a plane
  * with 32-bit byte offsets, so a lattice whose planes hold 2^32 bytes or more

@@ -319,23 +319,29 @@ inline hipError_t launch_solve_small(int prec, bool general, hipStream_t st, con
 }
 
 // Default fused kernel of a single lattice of N = nx ny sites, measured on
-// MI355X (GLUPS, eight steps per launch: tile kernel / wavefront with one
-// column per lane / with two):
-//   FP32  8192^2 295 / 350 / 432, 4096^2 263 / 335 / 312, 2048^2 239 / 297 / 277,
-//         1024^2 214 / 182 / 164;
-//   FP16  8192^2 380 / 425 / 397, 4096^2 359 / 366 / 288, 2048^2 346 / 269 / 225;
-//   FP64  8192^2 117 / 235, 4096^2 119 / 223, 2048^2 115 / 160, 1024^2 102 / 133
-// (FP64 tile at five steps).  So: the wavefront at eight steps for FP64 from
-// 2^20 sites, FP32 from 2^22 (two columns per lane from 2^25 on even widths)
-// and FP16 from 2^24; the tile kernel below.  Segments: as long as leaves
-// one wave per SIMD (4 per compute unit) over the strips, at most 128 rows and
-// at least 16: a lattice that fills the chip once with long segments reads the
-// fewest halo rows (GLUPS at eight steps by segment rows, MI355X: FP64 1024^2
-// 156 at 32, 165-169 at 23-24, 110 at 16; FP64 2048^2 191 at 32, 228 at 90-96,
-// 217 at 128; FP32 2048^2 343 at 32, 399 at 90; FP64 / FP32 4096^2 best at
-// 128; every type at 8192^2 best at 128).  `beyond_tile`: the planes exceed the tile kernel's
+// MI355X (GLUPS at eight steps per launch, kernel alone; FP64 tile at five):
+//   FP32  tile / wavefront: 1024^2 241 / 241, 1100^2 212 / 271, 1448^2 231 /
+//         333, 2048^2 239 / 399, 4096^2 263 / 377, 8192^2 295 / 432 (two
+//         columns per lane);
+//   FP16  1448^2 311 / 278, 2048^2 343 / 314, 2896^2 361 / 285, 4096^2 359 / 413,
+//         8192^2 380 / 449;
+//   FP64  512^2 94 / 54, 600^2 90 / 74, 724^2 87 / 103, 880^2 93 / 143,
+//         2048^2 115 / 228, 8192^2 117 / 235.
+// So: the wavefront at eight steps for FP32 above 2^20 sites (two columns per
+// lane from 2^25 on even widths), FP64 from 458752 (about 677^2) and FP16 from
+// 2^24; the tile kernel below.  Segments: as long as leaves one wave per SIMD
+// (4 per compute unit) over the strips, at most 128 rows and at least 16: a
+// lattice that fills the chip once with long segments reads the fewest halo
+// rows (GLUPS at eight steps by segment rows: FP64 1024^2 156 at 32, 165-169
+// at 23-24, 110 at 16; FP64 2048^2 191 at 32, 228 at 90-96, 217 at 128; FP32
+// 2048^2 343 at 32, 399 at 90; FP64 / FP32 4096^2 best at 128; every type at
+// 8192^2 best at 128).  `beyond_tile`: the planes exceed the tile kernel's
 // 32-bit offsets, so the wavefront (one column per lane, any width) is the
 // only fused kernel.  wave_hs = 0 selects the tile kernel.
+inline bool wave_by_default(int prec, long long n) {
+    return (prec == LBM_FP64 && n >= 458752) || (prec == LBM_FP32 && n > (1LL << 20)) ||
+           (prec == LBM_FP16 && n >= (1LL << 24));
+}
 struct FusedChoice {
     int wave_hs = 0, wave_v = 1;
 };
@@ -350,8 +356,7 @@ inline int wave_cols(int prec, int ns, int nx, int ny) {
 inline FusedChoice default_fused(int prec, int ns, int nx, int ny, int cus, bool beyond_tile = false) {
     FusedChoice c;
     const long long n = (long long)nx * ny;
-    const bool wave = beyond_tile || (prec == LBM_FP64 && n >= (1LL << 20)) ||
-                      (prec == LBM_FP32 && n >= (1LL << 22)) || (prec == LBM_FP16 && n >= (1LL << 24));
+    const bool wave = beyond_tile || wave_by_default(prec, n);
     if (!wave || ns < 2) return c;
     c.wave_v = wave_cols(prec, ns, nx, ny);
     const long long strips = (nx + wave_width_of(ns, c.wave_v) - 1) / wave_width_of(ns, c.wave_v);
@@ -391,10 +396,10 @@ inline size_t ip_halo_bytes(int prec, int ns, int nx, int ny, int hs = 0) {
 // sites (FP32 1024^2: 232 against 149 GLUPS at four), four on smaller lattices
 // (FP32 256^2: 49 against 42).  FP64 (whose LDS tile is twice as large): five
 // through the tile kernel (1024^2: 106 against 98 GLUPS at four), eight where
-// the register wavefront is the default (from 2^20 sites of a single lattice;
-// a batch always runs tiles).
+// the register wavefront is the default (wave_by_default, single lattices; a
+// batch always runs tiles).
 inline int default_time_blocking(int prec, long long sites, bool tiles_only = false) {
-    if (prec == LBM_FP64) return (tiles_only || sites < (1LL << 20)) ? 5 : 8;
+    if (prec == LBM_FP64) return (tiles_only || !wave_by_default(prec, sites)) ? 5 : 8;
     return sites > (1LL << 17) ? 8 : 4;
 }
 
