@@ -2,7 +2,8 @@
 
 Single lattices: random shapes (1..300 per side), storage types, fused kernels
 (LDS tile at 2..8 steps per launch, register wavefront at 2..8 with random
-segment heights, in-place streaming), random step counts and residual-checked
+segment heights, in-place streaming one step per launch and blocked through
+the in-place wavefront), random step counts and residual-checked
 runs, each against the same lattice stepped once per launch: populations and
 displacement bit-identical, the checked residual equal to rounding of its
 reduction order (the partial sums follow the tile shape), and FP64 within 1e-12
@@ -52,11 +53,19 @@ def _load(rng, nx, ny, scale=1e-5):
 
 def _run_single(lbm, cfg, mat, f0, gx, gy, reference):
     nx, ny = cfg["nx"], cfg["ny"]
-    s = lbm.Solver(nx, ny, cfg["prec"], inplace=(not reference and cfg["kind"] == "inplace"))
+    kind = cfg["kind"]
+    inplace = not reference and kind in ("inplace", "inplace_blocked")
+    s = lbm.Solver(nx, ny, cfg["prec"], inplace=inplace,
+                   inplace_steps=cfg["tb"] if kind == "inplace_blocked" else 1,
+                   inplace_segment_rows=cfg["seg"] if kind == "inplace_blocked" else 0)
     s.set_material(mat.lame_lambda, mat.lame_mu)
     s.set_body_force(dev(gx), dev(gy))
-    if reference or cfg["kind"] == "inplace":
+    if reference or kind == "inplace":
         s.set_time_blocking(1)
+    elif kind == "inplace_blocked":
+        s.set_time_blocking(1)
+        s.set_fused_kernel("wavefront", cfg["seg"])
+        s.set_time_blocking(cfg["tb"])
     else:
         s.set_time_blocking(cfg["tb"])
         s.set_fused_kernel("tile" if cfg["kind"] == "tile" else "wavefront", cfg["seg"])
@@ -77,8 +86,8 @@ def test_random_single_lattices(seed):
     rng = np.random.default_rng(seed)
     for case in range(100):
         nx, ny = _side(rng), _side(rng)
-        kind = str(rng.choice(["tile", "tile", "wavefront", "inplace"]))
-        tb = {"tile": int(rng.integers(2, 9)), "wavefront": int(rng.integers(2, 9)), "inplace": 1}[kind]
+        kind = str(rng.choice(["tile", "tile", "wavefront", "inplace", "inplace_blocked"]))
+        tb = 1 if kind == "inplace" else int(rng.integers(2, 9))
         steps = int(rng.integers(1, 40))
         cfg = dict(case=case, nx=nx, ny=ny, prec=str(rng.choice(["fp64", "fp32", "fp16"])),
                    kind=kind, tb=tb, seg=int(rng.choice([1, 3, 8, 17, 64, 256])), steps=steps,
@@ -170,8 +179,9 @@ def test_random_solves():
         nx, ny = int(rng.integers(3, 70)), int(rng.integers(3, 70))
         prec = str(rng.choice(["fp64", "fp32", "fp16"]))
         polish = prec != "fp64" and bool(rng.random() < 0.7)
-        kind = str(rng.choice(["tile", "wavefront"] if polish else ["tile", "tile", "wavefront", "inplace"]))
-        tb = {"tile": int(rng.integers(2, 9)), "wavefront": int(rng.integers(2, 9)), "inplace": 1}[kind]
+        kind = str(rng.choice(["tile", "wavefront"] if polish
+                              else ["tile", "tile", "wavefront", "inplace", "inplace_blocked"]))
+        tb = 1 if kind == "inplace" else int(rng.integers(2, 9))
         K = int(rng.choice([1, 2, 3, 7, 50, 100, 333]))
         tol = float(rng.choice([1e-6, 1e-8, 1e-10])) if (prec == "fp64" or polish) else 1e-5
         mat = _material(rng)
@@ -185,14 +195,21 @@ def test_random_solves():
                                         tb=tb, K=K, tol=tol)))
         out = []
         for reference in (True, False):
+            blocked = not reference and kind == "inplace_blocked"
             s = lbm.Solver(nx, ny, prec, with_polish=polish,
-                           inplace=(not reference and kind == "inplace"))
+                           inplace=(not reference and kind.startswith("inplace")),
+                           inplace_steps=tb if blocked else 1,
+                           inplace_segment_rows=seg if blocked else 0)
             s.set_material(mat.lame_lambda, mat.lame_mu)
             s.set_body_force(dev(gx), dev(gy))
             if polish:
                 s.set_polish(1e-5)
             if reference or kind == "inplace":
                 s.set_time_blocking(1)
+            elif blocked:
+                s.set_time_blocking(1)
+                s.set_fused_kernel("wavefront", seg)
+                s.set_time_blocking(tb)
             else:
                 s.set_time_blocking(tb)
                 s.set_fused_kernel("tile" if kind == "tile" else "wavefront", seg)
@@ -212,7 +229,7 @@ def test_random_solves():
 
 def test_random_outputs_against_the_oracle():
     """Populations, displacement and stress after random step counts (two
-    buffers at 1..8 steps per launch, or in place at odd and even counts) from
+    buffers or in place, at 1..8 steps per launch, odd and even counts) from
     random states, against the oracle: FP64 1e-12, FP32 2e-6 (populations) /
     2e-5, FP16 3e-3 / 3e-2 relative; error norms against numpy to 1e-12."""
     from paper_2208_14870_amd import lbm
@@ -222,7 +239,7 @@ def test_random_outputs_against_the_oracle():
         nx, ny = int(rng.integers(1, 90)), int(rng.integers(1, 90))
         prec = str(rng.choice(["fp64", "fp32", "fp16"]))
         inplace = bool(rng.random() < 0.4)
-        tb = 1 if inplace else int(rng.integers(1, 9))
+        tb = int(rng.integers(1, 9))  # in place: blocked through the in-place wavefront from 2
         steps = int(rng.integers(0, 12))
         say("outputs " + json.dumps(dict(case=case, nx=nx, ny=ny, prec=prec, inplace=inplace,
                                           tb=tb, steps=steps)))
