@@ -436,6 +436,13 @@ const char *lbm_last_error(const lbm_solver *s);
 /* Batches: many independent lattices of uneven size and material stepped    */
 /* together, one persistent launch per step over a (lattice, tile) work list. */
 /* ------------------------------------------------------------------------ */
+/* Plain fused steps of the large lattices (those a single solver would step
+ * through the register wavefront: FP32 above 2^20 sites, FP64 from 458752,
+ * FP16 from 2^24) run through a wavefront launch over a list of their
+ * (lattice, strip, segment) waves, one column per lane, beside the tile
+ * launch of the others; a precision holding such a lattice defaults to eight
+ * steps per launch.  Residual checks run through the tile kernel for every
+ * lattice.  Results are identical either way (each equals single steps). */
 
 /* Bytes of arena one lattice occupies in a batch at `precision` (with
  * `with_polish`: plus its FP64 polish state).  Used for admission. */

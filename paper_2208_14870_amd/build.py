@@ -10,7 +10,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
 SOURCES = [os.path.join(CSRC, f) for f in
-           ("lbm_capi.hip", "lbm_batch.hip", "lbm_wave.hip", "lbm_wave_inplace.hip")]
+           ("lbm_capi.hip", "lbm_batch.hip", "lbm_wave.hip", "lbm_wave_inplace.hip",
+            "lbm_wave_batch.hip")]
 HEADERS = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")) + [
     os.path.join(ROOT, "include", "lbm.h")]
 

@@ -84,6 +84,7 @@ struct BSlot {
     Lattice L;
     size_t off = 0, bytes = 0;
     long long steps = 0;
+    bool wave = false;  // plain fused steps through the batch's wavefront list
     long long checked_phase = -1;  // its precision's phase right after the last check launch
     int first = 0, count = 0;
     int warn = 0;  // warning bits of its force (lbm_batch_force_warnings)
@@ -142,6 +143,9 @@ struct lbm_batch {
     int* d_first = nullptr;
     int* d_count = nullptr;
     int* d_range = nullptr;  // 3 x {begin, end}: one range per precision
+    int* d_range_tile = nullptr;  // 3 x {begin, end}: its lattices stepped by the tile kernel
+    int* d_wrange = nullptr;      // 3 x {begin, end}: its wavefront items in d_witems
+    WaveItem* d_witems = nullptr;
     double* d_result = nullptr;
     double* d_stats = nullptr;  // 4 doubles per slot: sum gx, sum gy, sum |g|^2, max |g|
     Item* d_items = nullptr;
@@ -157,6 +161,9 @@ struct lbm_batch {
     Arena arena;
     std::vector<BSlot> slots;
     int range_host[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    int range_tile_host[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    int wrange_host[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    std::vector<WaveItem> h_witems;
     // launches per precision since the descriptors were written: lattices of one
     // storage type share a launch parity (buffer selector cur ^ (phase & 1));
     // each type runs its own steps per launch, so each keeps its own count
@@ -177,7 +184,7 @@ struct lbm_batch {
     long long items_bound = 0;        // upper bound of the work list of the active slots
     int guard_checks = 8;             // divergence guard of every slot (0: rise rule off)
     std::string err;
-    std::map<std::tuple<long long, int, int, int, unsigned, unsigned, unsigned>, hipGraphExec_t> graphs;
+    std::map<std::vector<long long>, hipGraphExec_t> graphs;
 
     int fail(int code, const std::string& m) {
         err = m;
@@ -196,13 +203,26 @@ struct lbm_batch {
         return (int)(phase[0] & 1) | (int)(phase[1] & 1) << 1 | (int)(phase[2] & 1) << 2;
     }
 
-    unsigned grid_for(int prec) const {
-        const int n = range_host[prec][1] - range_host[prec][0];
+    unsigned bucket(int n) const {
         if (n <= 0) return 0;
         // power-of-two buckets keep captured graphs valid while the list changes
         unsigned g = 8;
         while (g < (unsigned)n) g <<= 1;
         if (blocks_per_cu > 0) g = std::min(g, (unsigned)(cus * blocks_per_cu + 7) / 8 * 8);
+        return g;
+    }
+    // every lattice of a precision (single steps, residual checks)
+    unsigned grid_for(int prec) const { return bucket(range_host[prec][1] - range_host[prec][0]); }
+    // the lattices the tile kernel steps in plain fused launches
+    unsigned grid_tile_for(int prec) const {
+        return bucket(range_tile_host[prec][1] - range_tile_host[prec][0]);
+    }
+    // workgroups of four waves for the wavefront list (power-of-two buckets)
+    unsigned grid_wave_for(int prec) const {
+        const int n = wrange_host[prec][1] - wrange_host[prec][0];
+        if (n <= 0) return 0;
+        unsigned g = 8;
+        while (g * (kBlock / kWave) < (unsigned)n) g <<= 1;
         return g;
     }
 
@@ -235,32 +255,72 @@ struct lbm_batch {
         }
         for (int p = 0; p < 3; ++p) {
             long long sites = 0;
+            bool large = false;  // a lattice that takes the wavefront list at eight steps
             for (int i = 0; i < max_slots; ++i)
-                if (slots[i].active && slots[i].L.prec == p) sites += slots[i].L.N;
-            if (tb_auto[p]) tb[p] = default_time_blocking(p, sites, true);
+                if (slots[i].active && slots[i].L.prec == p) {
+                    sites += slots[i].L.N;
+                    large = large || wave_by_default(p, slots[i].L.N);
+                }
+            // the wavefront runs eight steps best (FP64 4 x 1500^2 in a batch:
+            // 116 GLUPS at the tile's five), and large lattices carry the work
+            if (tb_auto[p]) tb[p] = large ? 8 : default_time_blocking(p, sites, true);
             th[p] = fused_th(p, tb[p], sites);
         }
+        // Per precision: the tile work list of every lattice (single steps and
+        // residual checks), the lattices the tile kernel steps in plain fused
+        // launches first; the large lattices (wave_by_default) take those
+        // launches through the wavefront list instead, one item per wave.
+        h_witems.clear();
         for (int p = 0; p < 3; ++p) {
             range_host[p][0] = (int)total;
-            for (int i = 0; i < max_slots; ++i) {
-                BSlot& s = slots[i];
-                if (!s.active || s.L.prec != p) continue;
-                s.L.bx_log2 = bx_log2;
-                s.L.vy = vy;
-                s.L.tb = tb[p];
-                s.L.th = th[p];
-                s.first = (int)total;
-                s.count = s.L.nitems();
-                total += s.count;
-                h_rows[nrows++] = SlotRow{i, s.first, s.L.tiles_x(), s.count};
+            wrange_host[p][0] = (int)h_witems.size();
+            long long wave_cols_rows = 0;  // strips x rows of its wavefront lattices
+            const int w = tb[p] >= 2 ? wave_width_of(tb[p], 1) : 0;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int i = 0; i < max_slots; ++i) {
+                    BSlot& s = slots[i];
+                    if (!s.active || s.L.prec != p) continue;
+                    s.wave = w > 0 && wave_by_default(p, s.L.N);
+                    if (s.wave != (pass == 1)) continue;
+                    s.L.bx_log2 = bx_log2;
+                    s.L.vy = vy;
+                    s.L.tb = tb[p];
+                    s.L.th = th[p];
+                    s.first = (int)total;
+                    s.count = s.L.nitems();
+                    total += s.count;
+                    h_rows[nrows++] = SlotRow{i, s.first, s.L.tiles_x(), s.count};
+                    if (s.wave) wave_cols_rows += (long long)((s.L.nx + w - 1) / w) * s.L.ny;
+                }
+                if (pass == 0) {
+                    range_tile_host[p][0] = range_host[p][0];
+                    range_tile_host[p][1] = (int)total;
+                }
             }
             range_host[p][1] = (int)total;
+            // segments as long as leaves one wave per SIMD over the list, 16..128 rows
+            const int hs = (int)std::min<long long>(
+                128, std::max<long long>(16, (wave_cols_rows + 4LL * cus - 1) / (4LL * cus)));
+            for (int i = 0; i < max_slots && w > 0; ++i) {
+                const BSlot& s = slots[i];
+                if (!s.active || s.L.prec != p || !s.wave) continue;
+                const int strips = (s.L.nx + w - 1) / w;
+                for (int ya = 0; ya < s.L.ny; ya += hs)
+                    for (int sx = 0; sx < strips; ++sx)
+                        h_witems.push_back(WaveItem{i, sx, ya, std::min(ya + hs, s.L.ny)});
+            }
+            wrange_host[p][1] = (int)h_witems.size();
         }
-        if (total > cap_items) return fail(LBM_E_WORKSPACE, "work list exceeds batch capacity");
+        if (total > cap_items || (long long)h_witems.size() > cap_items)
+            return fail(LBM_E_WORKSPACE, "work list exceeds batch capacity");
         int* rng = reinterpret_cast<int*>(h_rows + max_slots);
         for (int p = 0; p < 3; ++p) {
             rng[2 * p] = range_host[p][0];
             rng[2 * p + 1] = range_host[p][1];
+            rng[6 + 2 * p] = range_tile_host[p][0];
+            rng[6 + 2 * p + 1] = range_tile_host[p][1];
+            rng[12 + 2 * p] = wrange_host[p][0];
+            rng[12 + 2 * p + 1] = wrange_host[p][1];
         }
         e = hipMemcpyAsync(d_rows, h_rows, (max_slots + 2) * sizeof(SlotRow),
                            hipMemcpyHostToDevice, stream);
@@ -271,6 +331,13 @@ struct lbm_batch {
         hipLaunchKernelGGL(k_set_counts, dim3(blocks_for(max_slots)), dim3(kBlock), 0, stream,
                            d_first, d_count, d_rows, nrows, max_slots);
         e = hipMemcpyAsync(d_range, rng, 6 * sizeof(int), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_range_tile, rng + 6, 6 * sizeof(int), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_wrange, rng + 12, 6 * sizeof(int), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess && !h_witems.empty())
+            e = hipMemcpy(d_witems, h_witems.data(), h_witems.size() * sizeof(WaveItem),
+                          hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "rebuild");
         // descriptors of the active slots: one copy from pinned staging (the
@@ -285,11 +352,11 @@ struct lbm_batch {
         return LBM_OK;
     }
 
-    StepLaunch args(int prec, int flip) const {
+    StepLaunch args(int prec, int flip, bool tile_only = false) const {
         StepLaunch a;
         a.slots = d_desc;
         a.items = d_items;
-        a.range = d_range + 2 * prec;
+        a.range = (tile_only ? d_range_tile : d_range) + 2 * prec;
         a.partial = d_partial;
         a.flip = flip;
         a.rows = eff_vy(prec);
@@ -348,11 +415,22 @@ struct lbm_batch {
             int span = 0;
             if (check) check_plan(p, nsteps, np, span);
             long long ph = phase[p], i = 0;
+            // plain fused launches: the tile kernel over its lattices and the
+            // wavefront over the list of the large ones, the same steps
+            const unsigned gt = grid_tile_for(p), gw = grid_wave_for(p);
+            const int nw = wrange_host[p][1] - wrange_host[p][0];
+            auto fused = [&](int ns, int flip) {
+                hipError_t r = hipSuccess;
+                if (gt) r = launch_stepN(p, ns, th[p], gt, st, args(p, flip, true));
+                if (r == hipSuccess && gw)
+                    r = launch_wave_list(p, ns, d_desc, d_witems, d_wrange + 2 * p, nw, flip, gw, st);
+                return r;
+            };
             if (tb[p] >= 2) {
                 for (; i + tb[p] <= np && e == hipSuccess; i += tb[p], ++ph)
-                    e = launch_stepN(p, tb[p], th[p], g, st, args(p, (int)(ph & 1)));
+                    e = fused(tb[p], (int)(ph & 1));
                 if (e == hipSuccess && fused_rest(p, np - i)) {
-                    e = launch_stepN(p, (int)(np - i), th[p], g, st, args(p, (int)(ph & 1)));
+                    e = fused((int)(np - i), (int)(ph & 1));
                     ++ph;
                     i = np;
                 }
@@ -419,11 +497,15 @@ int lbm_batch_create(int max_slots, void* arena, size_t arena_bytes, void* strea
     b->d_first = reinterpret_cast<int*>(take(max_slots * sizeof(int)));
     b->d_count = reinterpret_cast<int*>(take(max_slots * sizeof(int)));
     b->d_range = reinterpret_cast<int*>(take(6 * sizeof(int)));
+    b->d_range_tile = reinterpret_cast<int*>(take(6 * sizeof(int)));
+    b->d_wrange = reinterpret_cast<int*>(take(6 * sizeof(int)));
     b->d_result = reinterpret_cast<double*>(take(4 * max_slots * sizeof(double)));
     b->d_stats = reinterpret_cast<double*>(take(8 * max_slots * sizeof(double)));
-    b->d_rows = reinterpret_cast<SlotRow*>(take((max_slots + 2) * sizeof(SlotRow)));
+    b->d_rows = reinterpret_cast<SlotRow*>(take((max_slots + 5) * sizeof(SlotRow)));
     b->d_red = reinterpret_cast<double*>(take((kErrBlocks * 8 + 16) * sizeof(double)));
     b->d_items = reinterpret_cast<Item*>(take(b->cap_items * sizeof(Item)));
+    // wavefront items: no more than tile items (a wave covers at least 48 x 16 sites)
+    b->d_witems = reinterpret_cast<WaveItem*>(take(b->cap_items * sizeof(WaveItem)));
     b->d_partial = reinterpret_cast<double*>(take(b->cap_items * 3 * sizeof(double)));
     if (off > arena_bytes) {
         g_batch_create_error = "batch_create: arena smaller than the batch bookkeeping (" +
@@ -440,7 +522,7 @@ int lbm_batch_create(int max_slots, void* arena, size_t arena_bytes, void* strea
     if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&b->h_rows), (max_slots + 2) * sizeof(SlotRow),
+        e = hipHostMalloc(reinterpret_cast<void**>(&b->h_rows), (max_slots + 5) * sizeof(SlotRow),
                           hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&b->h_result),
@@ -623,10 +705,14 @@ int lbm_batch_step(lbm_batch* b, long long nsteps, int check) {
     for (int p = 0; p < 3; ++p)
         if (b->grid_for(p)) nl += b->launches(p, nsteps, check != 0);
     if (nl >= 4) {
-        auto key = std::make_tuple(nsteps, (check ? 1 : 0) | b->flips() << 1,
+        std::vector<long long> key{nsteps, (check ? 1 : 0) | b->flips() << 1,
                                    b->tb[0] | b->tb[1] << 4 | b->tb[2] << 8,
-                                   b->th[0] | b->th[1] << 6 | b->th[2] << 12,
-                                   b->grid_for(0), b->grid_for(1), b->grid_for(2));
+                                   b->th[0] | b->th[1] << 6 | b->th[2] << 12};
+        for (int p = 0; p < 3; ++p) {
+            key.push_back(b->grid_for(p));
+            key.push_back(b->grid_tile_for(p));
+            key.push_back(b->grid_wave_for(p));
+        }
         auto it = b->graphs.find(key);
         if (it == b->graphs.end()) {
             if (b->graphs.size() > 16) b->drop_graphs();

@@ -12,6 +12,7 @@
 
 namespace lbm {
 struct WaveLaunch;
+struct WaveItem;
 }
 
 namespace lbm_host {
@@ -51,6 +52,17 @@ inline size_t wave_halo_bytes(int prec, int ns, int v, int nx, int ny, int hs) {
     return wave_halo_x_bytes(prec, ns, v, nx, ny) +
            al((size_t)(8 * segs * 2LL * ns * nx) * elem_bytes(prec));
 }
+
+// Wavefront over a list of waves of several lattices (a batch; two buffers,
+// one column per lane, any widths): the launch runs items[wrange[0] ..
+// wrange[1] - 1] (wrange in device memory), each naming its lattice's
+// descriptor slot, strip (of 64 - 2 ns' columns for the list's depth ns' >=
+// ns: a shallower launch leaves the surplus strips idle) and rows.  nitems:
+// the list's current length, to check the grid (workgroups of four waves).
+// Defined in lbm_wave_batch.hip.
+hipError_t launch_wave_list(int prec, int ns, const SlotDesc* slots, const WaveItem* items,
+                            const int* wrange, int nitems, int flip, unsigned grid,
+                            hipStream_t st);
 
 // In-place launch of ns steps: the halo copy, then the wavefront.  The buffer
 // must be in kLayNatural for odd ns and kLaySwapped for even ns; it ends in

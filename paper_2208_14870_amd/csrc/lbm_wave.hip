@@ -43,6 +43,8 @@ hipError_t launch_wave(int prec, int ns, int v, int nx, int ny, int hs, const Sl
     const int w = wave_width_of(ns, v);
     WaveLaunch W;
     W.slots = slots;
+    W.items = nullptr;
+    W.wrange = nullptr;
     W.flip = flip;
     W.strips = (nx + w - 1) / w;
     W.hs = hs;

@@ -97,8 +97,19 @@ __host__ __device__ constexpr int wave_ring() { return V == 1 ? NS : (NS <= 4 ? 
 template <int NS, int V>
 __host__ __device__ constexpr int wave_width() { return kWave * V - 2 * wave_ring<NS, V>(); }
 
+// One wave's work in a list over several lattices (a batch): lattice slot,
+// strip, and output rows ya .. yb - 1.
+struct WaveItem {
+    int slot, sx, ya, yb;
+};
+
 struct WaveLaunch {
     const SlotDesc* slots;
+    // list mode: the waves' items (slots index the descriptor table), the
+    // launch's items[wrange[0] .. wrange[1] - 1] (device memory, so that a
+    // captured launch stays valid while the list changes)
+    const WaveItem* items;
+    const int* wrange;
     int flip;
     // strips of W output columns (strip s from column s W, so that its stores
     // start on the strip width: shifting the strips to align the loads instead
@@ -161,12 +172,15 @@ static __global__ __launch_bounds__(kBlock) void k_wave_halo(WaveLaunch L, int W
 // lv of a launch is global step sr_step + lv - 1, and the bits of a column are
 // those of its wrapped site, as the single-step kernel draws them.  IP: in
 // place (see k_wave_halo), from kLayNatural for odd NS, kLaySwapped for even.
-template <typename S, int NS, int V, bool SR = false, bool IP = false>
+// LIST: each wave takes its lattice, strip and rows from L.items (a batch of
+// lattices; two buffers, no stochastic rounding).
+template <typename S, int NS, int V, bool SR = false, bool IP = false, bool LIST = false>
 static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
     using C = typename Store<S>::C;
     constexpr int R = wave_ring<NS, V>();
     constexpr bool kSR = SR && std::is_same<S, __half>::value;
     static_assert(!(SR && IP), "no stochastic rounding in place");
+    static_assert(!(LIST && (SR || IP)), "lists run two buffers with rounding to nearest");
     constexpr bool kNat = IP && (NS % 2 == 1);  // level 0 is f(n) itself
     constexpr int W = wave_width<NS, V>();
     constexpr int PF = 3;  // rows loaded ahead
@@ -178,8 +192,16 @@ static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
     const int lb = (b % 8) * (nb / 8) + min(b % 8, nb % 8) + b / 8;
     const int wid = __builtin_amdgcn_readfirstlane(lb * (kBlock / kWave) + (int)(threadIdx.x >> 6));
     const int lane = (int)(threadIdx.x & (kWave - 1));
-    if (wid >= L.strips * L.segs) return;  // whole waves leave; no barrier follows
-    const SlotDesc& d = L.slots[0];
+    // whole waves leave; no barrier follows
+    WaveItem item{0, 0, 0, 0};
+    if constexpr (LIST) {
+        const int wb = L.wrange[0];
+        if (wid >= L.wrange[1] - wb) return;
+        item = L.items[wb + wid];
+    } else {
+        if (wid >= L.strips * L.segs) return;
+    }
+    const SlotDesc& d = L.slots[item.slot];
     const int nx = d.nx, ny = d.ny;
     const long long plane = d.plane;
     const int sel = d.cur ^ L.flip;
@@ -191,8 +213,9 @@ static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
     const C* __restrict__ g = reinterpret_cast<const C*>(d.g);
     Coef<C> k;
     k.load(d);
-    const int sx = wid % L.strips, sy = wid / L.strips;
-    const int xs = sx * W, ya = sy * L.hs, yb = min(ya + L.hs, ny);
+    const int sx = LIST ? item.sx : wid % L.strips, sy = LIST ? 0 : wid / L.strips;
+    const int xs = sx * W;
+    const int ya = LIST ? item.ya : sy * L.hs, yb = LIST ? item.yb : min(ya + L.hs, ny);
     const int x = xs - R + V * lane;  // first column of this lane
     const int xw = wrap_coord(x, nx);
     const bool out_lane = lane >= R / V && lane < (R + W) / V && x < nx;

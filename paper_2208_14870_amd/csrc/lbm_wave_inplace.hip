@@ -48,6 +48,8 @@ hipError_t launch_wave_inplace(int prec, int ns, int v, int nx, int ny, int hs,
     const int w = wave_width_of(ns, v), r = wave_ring_of(ns, v);
     WaveLaunch W;
     W.slots = slots;
+    W.items = nullptr;
+    W.wrange = nullptr;
     W.flip = flip;
     W.strips = (nx + w - 1) / w;
     W.hs = hs;

@@ -1,0 +1,117 @@
+"""Large lattices in a batch take their plain fused steps through the
+wavefront list (one wave per lattice, strip and segment), the others through
+the tile kernel, and every residual check through the tile kernel: every
+lattice equals a solo solver stepped once per launch, bit for bit."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2208_14870_amd import problem as P
+from gpu_common import assert_elementwise, dev, host, need_gpu, omega, say
+
+pytestmark = pytest.mark.gpu
+
+GIB = 1 << 30
+
+# (nx, ny, precision): FP32 above 2^20 sites and FP64 from 458752 sites take
+# the wavefront list (odd and even widths), the rest the tile kernel
+SPECS = [(1100, 960, "fp32"), (1025, 1031, "fp32"), (700, 700, "fp64"), (677, 600, "fp64"),
+         (64, 64, "fp32"), (33, 65, "fp32"), (7, 5, "fp64"), (96, 40, "fp16")]
+
+
+def _load(nx, ny, seed):
+    rng = np.random.default_rng(seed)
+    gx = P.remove_mean(rng.standard_normal((ny, nx)) * 1e-5)
+    gy = P.remove_mean(rng.standard_normal((ny, nx)) * 1e-5)
+    return gx, gy
+
+
+def _solo(nx, ny, prec, mat, gx, gy, steps):
+    from paper_2208_14870_amd import lbm
+    s = lbm.Solver(nx, ny, prec)
+    s.set_time_blocking(1)
+    s.set_material(mat.lame_lambda, mat.lame_mu)
+    s.set_body_force(dev(gx), dev(gy))
+    s.step(steps)
+    u = [host(t) for t in s.displacement()]
+    s.close()
+    return u
+
+
+def test_batch_wavefront_list_equals_solo_single_steps():
+    """Plain chunks (whole launches and remainders), a checked chunk, a removal
+    and a late addition of a large lattice: every resident lattice equals its
+    solo run stepped once per launch; the check's residual equals the solo
+    solver's checked step."""
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    say("batch with wavefront list: 8 lattices")
+    b = lbm.Batch(16, 3 * GIB)
+    mat = P.Material.from_shear_poisson(0.9, 0.3)
+    loads, slots, steps = {}, {}, {}
+    for k, (nx, ny, prec) in enumerate(SPECS):
+        loads[k] = _load(nx, ny, 10 + k)
+        slots[k] = b.add(nx, ny, mat.lame_lambda, mat.lame_mu, dev(loads[k][0]), dev(loads[k][1]),
+                         prec)
+        steps[k] = 0
+    for n, check in ((37, False), (13, False), (50, True), (3, False)):
+        b.step(n, check=check)
+        for k in steps:
+            steps[k] += n
+        if check:
+            r, done = b.residuals()
+    # a checked chunk's residual: that of a solo solver's checked step
+    for k in (0, 2):
+        nx, ny, prec = SPECS[k]
+        s = lbm.Solver(nx, ny, prec)
+        s.set_time_blocking(1)
+        s.set_material(mat.lame_lambda, mat.lame_mu)
+        s.set_body_force(dev(loads[k][0]), dev(loads[k][1]))
+        s.step(50)
+        rs = s.step_checked(50)
+        s.close()
+        assert r[slots[k]] == pytest.approx(rs, rel=1e-12), (k, r[slots[k]], rs)
+    b.remove(slots[1])
+    del steps[1]
+    k = len(SPECS)
+    loads[k] = _load(1040, 1040, 99)
+    slots[k] = b.add(1040, 1040, mat.lame_lambda, mat.lame_mu, dev(loads[k][0]), dev(loads[k][1]),
+                     "fp32")
+    steps[k] = 0
+    b.step(21)
+    for kk in steps:
+        steps[kk] += 21
+    specs = SPECS + [(1040, 1040, "fp32")]
+    for kk, n in steps.items():
+        nx, ny, prec = specs[kk]
+        say(f"  slot {kk}: {nx}x{ny} {prec}, {n} steps")
+        want = _solo(nx, ny, prec, mat, loads[kk][0], loads[kk][1], n)
+        got = [host(t) for t in b.displacement(slots[kk])]
+        if prec == "fp16":
+            sc = max(np.max(np.abs(want[0])), np.max(np.abs(want[1])), 1e-300)
+            assert max(np.max(np.abs(got[0] - want[0])), np.max(np.abs(got[1] - want[1]))) <= 1e-9 * sc
+        else:
+            np.testing.assert_array_equal(got[0], want[0], err_msg=f"slot {kk}")
+            np.testing.assert_array_equal(got[1], want[1], err_msg=f"slot {kk}")
+    b.close()
+
+
+@pytest.mark.parametrize("tb", [2, 5, 8])
+def test_batch_wavefront_list_depths_against_the_oracle(tb):
+    """At 2, 5 and 8 steps per launch a 700 x 700 FP64 lattice in a batch (the
+    wavefront list) matches the oracle element-wise at sampled rows."""
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    say(f"batch wavefront list fp64 700x700 tb {tb}")
+    nx = ny = 700
+    mat = P.Material.from_shear_poisson(1.0, 0.3)
+    gx, gy = _load(nx, ny, 3)
+    b = lbm.Batch(4, 2 * GIB)
+    b.set_time_blocking(tb)
+    s = b.add(nx, ny, mat.lame_lambda, mat.lame_mu, dev(gx), dev(gy), "fp64")
+    b.step(11)
+    ux, uy = (host(t) for t in b.displacement(s))
+    b.close()
+    f = O.run(O.zero_state(nx, ny), gx, gy, omega(mat), 11)
+    ox, oy = O.displacement(f, gx, gy)
+    assert_elementwise((ux, uy), (ox, oy), 1e-12, "u")
