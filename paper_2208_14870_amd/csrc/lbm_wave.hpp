@@ -186,21 +186,19 @@ static __global__ __launch_bounds__(kBlock) void k_wave(WaveLaunch L) {
     constexpr int PF = 3;  // rows loaded ahead
     // wave index as a scalar: the row loop and the row bases stay scalar.
     // Blocks go to the 8 XCDs round-robin; each XCD takes a contiguous range of
-    // blocks, so that strips side by side, whose rings overlap, run on one XCD
-    // at the same time and share its L2.
-    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    // the blocks that have work, so that strips side by side, whose rings
+    // overlap, run on one XCD at the same time and share its L2 (a list's grid
+    // is rounded up: its surplus blocks leave first, or the work would gather
+    // on the first XCDs).
+    const int nwaves = LIST ? L.wrange[1] - L.wrange[0] : L.strips * L.segs;
+    const int nb = (nwaves + kBlock / kWave - 1) / (kBlock / kWave), b = (int)blockIdx.x;
+    if (b >= nb) return;  // whole blocks leave; no barrier follows
     const int lb = (b % 8) * (nb / 8) + min(b % 8, nb % 8) + b / 8;
     const int wid = __builtin_amdgcn_readfirstlane(lb * (kBlock / kWave) + (int)(threadIdx.x >> 6));
     const int lane = (int)(threadIdx.x & (kWave - 1));
-    // whole waves leave; no barrier follows
+    if (wid >= nwaves) return;  // whole waves leave
     WaveItem item{0, 0, 0, 0};
-    if constexpr (LIST) {
-        const int wb = L.wrange[0];
-        if (wid >= L.wrange[1] - wb) return;
-        item = L.items[wb + wid];
-    } else {
-        if (wid >= L.strips * L.segs) return;
-    }
+    if constexpr (LIST) item = L.items[L.wrange[0] + wid];
     const SlotDesc& d = L.slots[item.slot];
     const int nx = d.nx, ny = d.ny;
     const long long plane = d.plane;
