@@ -115,3 +115,35 @@ def test_batch_wavefront_list_depths_against_the_oracle(tb):
     f = O.run(O.zero_state(nx, ny), gx, gy, omega(mat), 11)
     ox, oy = O.displacement(f, gx, gy)
     assert_elementwise((ux, uy), (ox, oy), 1e-12, "u")
+
+
+def test_batch_wavefront_list_promote():
+    """A large FP32 lattice with its polish reservation switches to FP64 in a
+    batch (from the FP32 wavefront list to the FP64 one) next to a small
+    lattice: after 120 + 80 steps both are within the FP32 phase's rounding of
+    the oracle, and the large one equals the same lattice promoted alone."""
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    say("batch wavefront list promote 1100x960")
+    mat = P.Material.from_shear_poisson(1.0, 0.3)
+    out = []
+    for mix in (False, True):
+        b = lbm.Batch(8, 3 * GIB)
+        gx, gy = _load(1100, 960, 5)
+        s = b.add(1100, 960, mat.lame_lambda, mat.lame_mu, dev(gx), dev(gy), "fp32",
+                  with_polish=True)
+        if mix:
+            hx, hy = _load(96, 64, 6)
+            b.add(96, 64, mat.lame_lambda, mat.lame_mu, dev(hx), dev(hy), "fp32", with_polish=True)
+        b.step(120, check=True)
+        b.promote(s)
+        b.step(80, check=True)
+        out.append([host(t) for t in b.displacement(s)])
+        b.close()
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    f = O.run(O.zero_state(1100, 960), gx, gy, omega(mat), 200)
+    ox, oy = O.displacement(f, gx, gy)
+    err = np.sqrt(np.sum((out[0][0] - ox) ** 2 + (out[0][1] - oy) ** 2) / np.sum(ox ** 2 + oy ** 2))
+    say(f"  fp32 -> fp64 rel err vs oracle: {err:.3e}")
+    assert err <= 1e-5
