@@ -234,9 +234,9 @@ def kernel_label(cfg, ctype, sites, sr=False):
         return (f"k_stepN<{ctype}, {rows}, {tb}, {nt}, 0, {srs}> (LDS tile 64 x {rows} + ring "
                 f"{tb - 1}, {nt} threads): {tb} fused steps per launch, {per_site} B per "
                 f"site-update algorithmic, {tb} x {side}^2 site-updates per launch")
-    if cfg["kernel"] == "wavefront":  # type, steps, columns per lane, rounding, in place
+    if cfg["kernel"] == "wavefront":  # type, steps, columns per lane, rounding, in place, work list
         v = cfg.get("columns_per_lane", 1)
-        return (f"k_wave<{ctype}, {tb}, {v}, {srs}, false> (register wavefront, {rows}-row "
+        return (f"k_wave<{ctype}, {tb}, {v}, {srs}, false, false> (register wavefront, {rows}-row "
                 f"segments): {tb} fused steps per launch, "
                 f"{per_site} B per site-update algorithmic, {tb} x {side}^2 site-updates per launch")
     return f"k_step<{ctype}, ...>: one step per launch, {per_site} B per site-update algorithmic"
