@@ -436,13 +436,16 @@ const char *lbm_last_error(const lbm_solver *s);
 /* Batches: many independent lattices of uneven size and material stepped    */
 /* together, one persistent launch per step over a (lattice, tile) work list. */
 /* ------------------------------------------------------------------------ */
-/* Plain fused steps of the large lattices (those a single solver would step
- * through the register wavefront: FP32 above 2^20 sites, FP64 from 458752,
- * FP16 from 2^24) run through a wavefront launch over a list of their
- * (lattice, strip, segment) waves, one column per lane, beside the tile
- * launch of the others; a precision holding such a lattice defaults to eight
- * steps per launch.  Residual checks run through the tile kernel for every
- * lattice.  Results are identical either way (each equals single steps). */
+/* Plain fused steps of some lattices run through a wavefront launch over a
+ * list of their (lattice, strip, segment) waves, one column per lane, beside
+ * the tile launch of the others.  By default (see
+ * lbm_batch_set_wavefront_sites) these are, per storage type, all of its
+ * lattices once they hold at least 2^22 (FP64), 2^23 (FP32) or 2^24 (FP16)
+ * sites together, and otherwise those a single solver would step through the
+ * register wavefront (FP32 above 2^20 sites, FP64 from 458752, FP16 from
+ * 2^24).  A precision with lattices on the list defaults to eight steps per
+ * launch.  Residual checks run through the tile kernel for every lattice.
+ * Results are identical either way (each equals single steps). */
 
 /* Bytes of arena one lattice occupies in a batch at `precision` (with
  * `with_polish`: plus its FP64 polish state).  Used for admission. */
@@ -522,6 +525,14 @@ int lbm_batch_set_tile(lbm_batch *b, int bx_log2, int rows_per_thread, int block
  * total sites of its lattices in the batch (FP64 5, FP32 / FP16 8 above 2^17
  * sites).  Errors: LBM_E_ARG. */
 int lbm_batch_set_time_blocking(lbm_batch *b, int steps_per_launch);
+
+/* Which lattices of one storage type (precision LBM_FP64, LBM_FP32 or
+ * LBM_FP16) take their plain fused steps through the wavefront list: those
+ * with nx * ny >= min_sites (0: all of them), or with -1 the default rule
+ * above (the batch autotuner times it against all and none).  Applies to the
+ * plain fused launches only (two or more steps per launch).  Errors:
+ * LBM_E_ARG. */
+int lbm_batch_set_wavefront_sites(lbm_batch *b, int precision, long long min_sites);
 
 /* Temporal blocking for the lattices of one storage type only (precision
  * LBM_FP64, LBM_FP32 or LBM_FP16; steps_per_launch 1..8).  Lattices of each

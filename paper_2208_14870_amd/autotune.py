@@ -83,6 +83,18 @@ def _apply(obj, shp: Shape):
         obj.set_tile_rows(shp[5] if len(shp) > 5 else 0)
 
 
+def batch_candidates() -> List[Shape]:
+    """Batch shapes.  Element 4 says which lattices take the wavefront list:
+    0 the default rule (with every shape of candidates(64, 3)), 1 all of them
+    and 2 none (at the depths where the wavefront and the tile run best)."""
+    return candidates(64, 3) + [(6, 4, 0, 8, 1, 0), (6, 4, 0, 8, 2, 0), (6, 4, 0, 5, 2, 0)]
+
+
+def _apply_batch(batch, precision: str, shp: Shape):
+    _apply(batch, shp)
+    batch.set_wavefront_sites(precision, {0: -1, 1: 0}.get(shp[4], 1 << 62))
+
+
 def _arch() -> str:
     try:
         return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
@@ -91,7 +103,7 @@ def _arch() -> str:
 
 
 def _key(kind: str, precision: str, sites: int) -> str:
-    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}|v8"
+    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}|v9"
 
 
 def _load(path: str) -> Dict[str, list]:
@@ -180,12 +192,12 @@ def tune_batch(batch, precision: str, sites: int, cache_path: Optional[str] = DE
     cache = _load(cache_path) if cache_path else {}
     if not force and key in cache:
         shp = tuple(cache[key])
-        _apply(batch, shp)
+        _apply_batch(batch, precision, shp)
         return shp
-    res = time_shapes(lambda s: _apply(batch, s), lambda n: batch.step(n), candidates(64, 3),
-                      sites)
+    res = time_shapes(lambda s: _apply_batch(batch, precision, s), lambda n: batch.step(n),
+                      batch_candidates(), sites)
     shp = res[0][1]
-    _apply(batch, shp)
+    _apply_batch(batch, precision, shp)
     if cache_path:
         cache[key] = list(shp)
         _store(cache_path, cache)

@@ -174,6 +174,10 @@ struct lbm_batch {
     // set by the caller, the default for the precision's current total sites
     int tb[3] = {4, 4, 4};
     bool tb_auto[3] = {true, true, true};
+    // lattices of each storage type with at least this many sites take the
+    // wavefront list (-1: the default rule, see on_wave_list)
+    long long wave_min[3] = {-1, -1, -1};
+    bool wave_all[3] = {false, false, false};  // default rule, total above batch_wave_total
     // fused tile height per precision, from the precision's current total sites
     // (short tiles once few sites remain, e.g. the tail of a set of solves)
     int th[3] = {8, 16, 12};
@@ -229,6 +233,13 @@ struct lbm_batch {
 
     int ensure() { return dirty ? rebuild() : LBM_OK; }
 
+    // Default rule: every lattice of the type once its lattices hold at least
+    // batch_wave_total sites together, else those a single solver steps
+    // through the wavefront.
+    bool on_wave_list(int p, long long sites) const {
+        return wave_min[p] < 0 ? wave_all[p] || wave_by_default(p, sites) : sites >= wave_min[p];
+    }
+
     // Recompute the work list: items grouped by precision, then by slot id.
     int rebuild() {
         long long total = 0;
@@ -257,19 +268,20 @@ struct lbm_batch {
             long long sites = 0;
             bool large = false;  // a lattice that takes the wavefront list at eight steps
             for (int i = 0; i < max_slots; ++i)
-                if (slots[i].active && slots[i].L.prec == p) {
-                    sites += slots[i].L.N;
-                    large = large || wave_by_default(p, slots[i].L.N);
-                }
+                if (slots[i].active && slots[i].L.prec == p) sites += slots[i].L.N;
+            wave_all[p] = sites >= batch_wave_total(p);
+            for (int i = 0; i < max_slots; ++i)
+                if (slots[i].active && slots[i].L.prec == p)
+                    large = large || on_wave_list(p, slots[i].L.N);
             // the wavefront runs eight steps best (FP64 4 x 1500^2 in a batch:
-            // 116 GLUPS at the tile's five), and large lattices carry the work
+            // 116 GLUPS at the tile's five), and its lattices carry the work
             if (tb_auto[p]) tb[p] = large ? 8 : default_time_blocking(p, sites, true);
             th[p] = fused_th(p, tb[p], sites);
         }
         // Per precision: the tile work list of every lattice (single steps and
         // residual checks), the lattices the tile kernel steps in plain fused
-        // launches first; the large lattices (wave_by_default) take those
-        // launches through the wavefront list instead, one item per wave.
+        // launches first; the lattices of the wavefront list (on_wave_list)
+        // take those launches through it instead, one item per wave.
         h_witems.clear();
         for (int p = 0; p < 3; ++p) {
             range_host[p][0] = (int)total;
@@ -280,7 +292,7 @@ struct lbm_batch {
                 for (int i = 0; i < max_slots; ++i) {
                     BSlot& s = slots[i];
                     if (!s.active || s.L.prec != p) continue;
-                    s.wave = w > 0 && wave_by_default(p, s.L.N);
+                    s.wave = w > 0 && on_wave_list(p, s.L.N);
                     if (s.wave != (pass == 1)) continue;
                     s.L.bx_log2 = bx_log2;
                     s.L.vy = vy;
@@ -689,6 +701,16 @@ int lbm_batch_set_time_blocking_for(lbm_batch* b, int precision, int steps_per_l
                        "batch_set_time_blocking_for: precision LBM_FP64/FP32/FP16, steps_per_launch in 1..8");
     b->tb[precision] = steps_per_launch;
     b->tb_auto[precision] = false;
+    b->drop_graphs();
+    return b->rebuild();
+}
+
+int lbm_batch_set_wavefront_sites(lbm_batch* b, int precision, long long min_sites) {
+    if (!b) return LBM_E_ARG;
+    if (!valid_prec(precision) || min_sites < -1)
+        return b->fail(LBM_E_ARG,
+                       "batch_set_wavefront_sites: precision LBM_FP64/FP32/FP16, min_sites >= -1");
+    b->wave_min[precision] = min_sites;
     b->drop_graphs();
     return b->rebuild();
 }

@@ -342,6 +342,17 @@ inline bool wave_by_default(int prec, long long n) {
     return (prec == LBM_FP64 && n >= 458752) || (prec == LBM_FP32 && n > (1LL << 20)) ||
            (prec == LBM_FP16 && n >= (1LL << 24));
 }
+// In a batch, lattices of one storage type fill the chip together, so above
+// these totals every lattice of the type takes the wavefront list (GLUPS at
+// eight steps, tile / wavefront list, 2000 steps in checked chunks of 100:
+// FP64 512 lattices of sides 64..512 (43.9 M sites) 112 / 199, 8 x 1024^2
+// 104 / 182, 64 lattices 256..512 (12.4 M) 116 / 162, 512 lattices 64..128
+// (5.3 M) 108 / 140, 16 lattices 128..256 (0.74 M) 92 / 78; FP32 in the same
+// order 272 / 316, 267 / 308, 279 / 268, 249 / 223, 187 / 124; FP16 43.9 M
+// 358 / 381).  Below them only the lattices of wave_by_default do.
+inline long long batch_wave_total(int prec) {
+    return prec == LBM_FP64 ? (1LL << 22) : prec == LBM_FP32 ? (1LL << 23) : (1LL << 24);
+}
 struct FusedChoice {
     int wave_hs = 0, wave_v = 1;
 };

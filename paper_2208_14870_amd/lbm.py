@@ -105,6 +105,7 @@ def load() -> ctypes.CDLL:
         "lbm_batch_info": (i, [vp, pi, ctypes.POINTER(sz), ctypes.POINTER(sz)]),
         "lbm_batch_set_time_blocking": (i, [vp, i]),
         "lbm_batch_set_time_blocking_for": (i, [vp, i, i]),
+        "lbm_batch_set_wavefront_sites": (i, [vp, i, ll]),
         "lbm_batch_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sigs.items():
@@ -520,6 +521,13 @@ class Batch:
         else:
             self._check(self.lib.lbm_batch_set_time_blocking_for(
                 self.h, PRECISIONS[precision], int(steps_per_launch)))
+
+    def set_wavefront_sites(self, precision: str, min_sites: int):
+        """Lattices of `precision` with at least `min_sites` sites (0: all) take
+        their plain fused steps through the wavefront list; -1: the default
+        rule (the lattices a single solver steps through the wavefront)."""
+        self._check(self.lib.lbm_batch_set_wavefront_sites(self.h, PRECISIONS[precision],
+                                                           int(min_sites)))
 
     def displacements(self, slots):
         """Displacements of several lattices as host arrays [(ux, uy), ...]:

@@ -39,7 +39,7 @@ def test_tune_batch(tmp_path):
         b.add(c.nx, c.ny, c.material.lame_lambda, c.material.lame_mu, dev(c.gx), dev(c.gy), "fp32")
     shp = autotune.tune_batch(b, "fp32", sum(c.nx * c.ny for c in cases),
                               cache_path=str(tmp_path / "t.json"))
-    assert shp in autotune.candidates(64, 3)
+    assert shp in autotune.batch_candidates()
 
 
 def test_tune_inplace_solver(tmp_path):

@@ -147,3 +147,47 @@ def test_batch_wavefront_list_promote():
     err = np.sqrt(np.sum((out[0][0] - ox) ** 2 + (out[0][1] - oy) ** 2) / np.sum(ox ** 2 + oy ** 2))
     say(f"  fp32 -> fp64 rel err vs oracle: {err:.3e}")
     assert err <= 1e-5
+
+
+# small and ragged lattices of every storage type (widths below one strip,
+# single-strip and several-strip lattices)
+SMALL = [(64, 64, "fp32"), (33, 65, "fp32"), (7, 5, "fp32"), (130, 70, "fp64"), (5, 9, "fp64"),
+         (96, 40, "fp16"), (49, 200, "fp16")]
+
+
+@pytest.mark.parametrize("rule", ["all", "threshold", "none"])
+def test_batch_wavefront_sites(rule):
+    """lbm_batch_set_wavefront_sites: every lattice on the wavefront list, those
+    with at least 5000 sites, or none, through plain chunks and a checked chunk,
+    then the default rule for a last chunk: every lattice equals its solo run
+    stepped once per launch.  A minimum below -1 is rejected."""
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    say(f"batch wavefront sites: {rule}")
+    b = lbm.Batch(16, GIB)
+    mat = P.Material.from_shear_poisson(0.9, 0.3)
+    loads, slots = {}, {}
+    for k, (nx, ny, prec) in enumerate(SMALL):
+        loads[k] = _load(nx, ny, 40 + k)
+        slots[k] = b.add(nx, ny, mat.lame_lambda, mat.lame_mu, dev(loads[k][0]), dev(loads[k][1]),
+                         prec)
+    ms = {"all": 0, "threshold": 5000, "none": 1 << 62}[rule]
+    for prec in ("fp64", "fp32", "fp16"):
+        b.set_wavefront_sites(prec, ms)
+    for n, check in ((37, False), (50, True), (3, False)):
+        b.step(n, check=check)
+    for prec in ("fp64", "fp32", "fp16"):
+        b.set_wavefront_sites(prec, -1)
+    b.step(19)
+    with pytest.raises(lbm.LbmError):
+        b.set_wavefront_sites("fp32", -2)
+    for k, (nx, ny, prec) in enumerate(SMALL):
+        want = _solo(nx, ny, prec, mat, loads[k][0], loads[k][1], 109)
+        got = [host(t) for t in b.displacement(slots[k])]
+        if prec == "fp16":
+            sc = max(np.max(np.abs(want[0])), np.max(np.abs(want[1])), 1e-300)
+            assert max(np.max(np.abs(got[0] - want[0])), np.max(np.abs(got[1] - want[1]))) <= 1e-9 * sc
+        else:
+            np.testing.assert_array_equal(got[0], want[0], err_msg=f"slot {k}")
+            np.testing.assert_array_equal(got[1], want[1], err_msg=f"slot {k}")
+    b.close()
