@@ -191,3 +191,36 @@ def test_batch_wavefront_sites(rule):
             np.testing.assert_array_equal(got[0], want[0], err_msg=f"slot {k}")
             np.testing.assert_array_equal(got[1], want[1], err_msg=f"slot {k}")
     b.close()
+
+
+def test_batch_wavefront_total_crossing():
+    """The default rule moves small FP64 lattices onto the wavefront list while
+    a 2048 x 2048 lattice brings the FP64 sites to 2^22, and back to the tile
+    list when it leaves: chunks before, during and after, plain and checked;
+    every lattice equals its solo run stepped once per launch."""
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    say("batch wavefront total crossing: fp64 2048^2 joins and leaves")
+    mat = P.Material.from_shear_poisson(1.0, 0.3)
+    small = [(64, 64), (33, 65), (130, 70), (5, 9)]
+    b = lbm.Batch(8, 3 * GIB)
+    loads = {k: _load(nx, ny, 70 + k) for k, (nx, ny) in enumerate(small)}
+    slots = {k: b.add(nx, ny, mat.lame_lambda, mat.lame_mu, dev(loads[k][0]), dev(loads[k][1]),
+                      "fp64") for k, (nx, ny) in enumerate(small)}
+    b.step(21)                      # tiles (5 steps per launch by default)
+    bg = _load(2048, 2048, 77)
+    big = b.add(2048, 2048, mat.lame_lambda, mat.lame_mu, dev(bg[0]), dev(bg[1]), "fp64")
+    b.step(30, check=True)          # every lattice on the list, 8 steps per launch
+    b.step(9)
+    ux, uy = (host(t) for t in b.displacement(big))
+    b.remove(big)
+    b.step(17, check=True)          # tiles again
+    for k, (nx, ny) in enumerate(small):
+        want = _solo(nx, ny, "fp64", mat, loads[k][0], loads[k][1], 77)
+        got = [host(t) for t in b.displacement(slots[k])]
+        np.testing.assert_array_equal(got[0], want[0], err_msg=f"slot {k}")
+        np.testing.assert_array_equal(got[1], want[1], err_msg=f"slot {k}")
+    b.close()
+    want = _solo(2048, 2048, "fp64", mat, bg[0], bg[1], 39)
+    np.testing.assert_array_equal(ux, want[0])
+    np.testing.assert_array_equal(uy, want[1])
