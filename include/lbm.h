@@ -521,9 +521,10 @@ int lbm_batch_get_displacement(lbm_batch *b, int slot, double *ux, double *uy);
 int lbm_batch_set_tile(lbm_batch *b, int bx_log2, int rows_per_thread, int blocks_per_cu);
 
 /* Temporal blocking for all lattices of the batch (see lbm_set_time_blocking,
- * 1..8).  Until set, each storage type takes the tile kernel's default for the
- * total sites of its lattices in the batch (FP64 5, FP32 / FP16 8 above 2^17
- * sites).  Errors: LBM_E_ARG. */
+ * 1..8).  Until set, a storage type with lattices on the wavefront list runs
+ * eight steps per launch, and otherwise takes the tile kernel's default for
+ * the total sites of its lattices in the batch (FP64 5, FP32 / FP16 8 above
+ * 2^17 sites).  Errors: LBM_E_ARG. */
 int lbm_batch_set_time_blocking(lbm_batch *b, int steps_per_launch);
 
 /* Which lattices of one storage type (precision LBM_FP64, LBM_FP32 or
