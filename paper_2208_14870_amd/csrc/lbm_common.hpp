@@ -496,12 +496,14 @@ __device__ __forceinline__ void xcd_slice(const int* range, int& last, int& stri
     const int begin = range[0];
     const int nitems = range[1] - begin;
     const int G = gridDim.x;
-    const int nx8 = (G % 8 == 0) ? 8 : 1;
-    const int xcd = blockIdx.x % nx8;
-    const int lb = blockIdx.x / nx8;
-    const int first = begin + (int)(((long long)nitems * xcd) / nx8);
-    last = begin + (int)(((long long)nitems * (xcd + 1)) / nx8);
-    stride = G / nx8;
+    // 8 slices when the grid is a multiple of 8, else one; the quotients by
+    // 8 or 1 as shifts of non-negative values
+    const int sh = (G % 8 == 0) ? 3 : 0;
+    const int xcd = (int)blockIdx.x & ((1 << sh) - 1);
+    const int lb = (int)blockIdx.x >> sh;
+    const int first = begin + (int)(((long long)nitems * xcd) >> sh);
+    last = begin + (int)(((long long)nitems * (xcd + 1)) >> sh);
+    stride = G >> sh;
     start = first + lb;
 }
 
