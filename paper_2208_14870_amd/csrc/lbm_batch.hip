@@ -266,7 +266,7 @@ struct lbm_batch {
         }
         for (int p = 0; p < 3; ++p) {
             long long sites = 0;
-            bool large = false;  // a lattice that takes the wavefront list at eight steps
+            bool large = false;  // a lattice on the wavefront list: eight steps per launch
             for (int i = 0; i < max_slots; ++i)
                 if (slots[i].active && slots[i].L.prec == p) sites += slots[i].L.N;
             wave_all[p] = sites >= batch_wave_total(p);
@@ -428,7 +428,7 @@ struct lbm_batch {
             if (check) check_plan(p, nsteps, np, span);
             long long ph = phase[p], i = 0;
             // plain fused launches: the tile kernel over its lattices and the
-            // wavefront over the list of the large ones, the same steps
+            // wavefront over the list of the others, the same steps
             const unsigned gt = grid_tile_for(p), gw = grid_wave_for(p);
             const int nw = wrange_host[p][1] - wrange_host[p][0];
             auto fused = [&](int ns, int flip) {

@@ -1,6 +1,6 @@
 // Register-wavefront launches over a list of waves of several lattices (the
-// batch's large lattices): k_wave<..., LIST> with one column per lane for every
-// storage type and depth, in a translation unit of its own.
+// lattices on a batch's wavefront list): k_wave<..., LIST> with one column per
+// lane for every storage type and depth, in a translation unit of its own.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

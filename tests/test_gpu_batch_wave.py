@@ -1,7 +1,9 @@
-"""Large lattices in a batch take their plain fused steps through the
-wavefront list (one wave per lattice, strip and segment), the others through
-the tile kernel, and every residual check through the tile kernel: every
-lattice equals a solo solver stepped once per launch, bit for bit."""
+"""Lattices on a batch's wavefront list (the large ones, all of a storage
+type once it holds enough sites, or as lbm_batch_set_wavefront_sites says)
+take their plain fused steps through it (one wave per lattice, strip and
+segment), the others through the tile kernel, and every residual check through
+the tile kernel: every lattice equals a solo solver stepped once per launch,
+bit for bit."""
 import numpy as np
 import pytest
 
