@@ -715,8 +715,9 @@ def main():
         print(json.dumps(cpu_baseline(args.cpu_seconds)), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                          "(the multi-GPU decomposition is a design note, not built)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (the "
+                          "library has no multi-GPU decomposition: lattices would shard "
+                          "whole, a large lattice by slabs with halo exchange)"}))
         sys.exit(2)
     import torch
     from paper_2208_14870_amd import lbm
