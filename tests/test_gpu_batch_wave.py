@@ -226,3 +226,40 @@ def test_batch_wavefront_total_crossing():
     want = _solo(2048, 2048, "fp64", mat, bg[0], bg[1], 39)
     np.testing.assert_array_equal(ux, want[0])
     np.testing.assert_array_equal(uy, want[1])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_workload_full_size_sampled(prec):
+    """The batched workload at full size (512 lattices of sides 64..512, seed 4,
+    43.9 M sites: every lattice on the wavefront list at eight steps, as the
+    benchmark runs it), 21 plain steps and a checked chunk of 21: on six sampled
+    lattices (the smallest and largest among them) FP64 matches the oracle
+    element-wise within 1e-12, FP32 equals its solo single steps bit for bit."""
+    from paper_2208_14870_amd import lbm
+    need_gpu()
+    say(f"batched workload full size, {prec}")
+    cases = P.batch_cases(512, seed=4)
+    sites = sum(c.nx * c.ny for c in cases)
+    arena = int(sites * lbm.Batch.slot_bytes(1024, 1024, prec) / (1024 * 1024) * 1.3) + GIB
+    b = lbm.Batch(520, arena)
+    slots = [b.add(c.nx, c.ny, c.material.lame_lambda, c.material.lame_mu, dev(c.gx), dev(c.gy),
+                   prec) for c in cases]
+    b.step(21)
+    b.step(21, check=True)
+    r, _ = b.residuals()
+    assert np.all(np.isfinite(r[:len(cases)]))
+    order = sorted(range(len(cases)), key=lambda i: cases[i].nx * cases[i].ny)
+    rng = np.random.default_rng(11)
+    pick = [order[0], order[-1]] + [int(i) for i in rng.choice(len(cases), 4, replace=False)]
+    for i in pick:
+        c = cases[i]
+        ux, uy = (host(t) for t in b.displacement(slots[i]))
+        say(f"  lattice {i}: {c.nx}x{c.ny}")
+        if prec == "fp64":
+            f = O.run(O.zero_state(c.nx, c.ny), c.gx, c.gy, omega(c.material), 42)
+            assert_elementwise((ux, uy), O.displacement(f, c.gx, c.gy), 1e-12, f"lattice {i}")
+        else:
+            want = _solo(c.nx, c.ny, "fp32", c.material, c.gx, c.gy, 42)
+            np.testing.assert_array_equal(ux, want[0], err_msg=f"lattice {i}")
+            np.testing.assert_array_equal(uy, want[1], err_msg=f"lattice {i}")
+    b.close()
