@@ -196,6 +196,9 @@ def parse():
                     help="run only the 32 x 32 launch-bound solve leg")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the two serving legs (overloaded, then sustained)")
+    ap.add_argument("--headline-kernel", choices=("default", "tile"), default="default",
+                    help="fused kernel of the 1024^2 FP32 headline: the library's default "
+                         "(the register wavefront) or the LDS tile kernel, for comparison")
     ap.add_argument("--large-steps", type=int, default=10000)
     ap.add_argument("--large-warm", type=int, default=200)
     ap.add_argument("--large-tb", type=int, default=0,
@@ -210,12 +213,17 @@ def build_cases(ncases):
     return [P.single_1024(nu, kx, ky) for nu, (kx, ky) in P.SWEEP_1024[:ncases]]
 
 
-def make_solvers(cases, prec):
+def make_solvers(cases, prec, kernel="default"):
+    """Solvers of the cases with their loads; kernel "tile" forces the LDS tile
+    kernel for plain fused steps (at the default depth), "default" keeps the
+    library's choice."""
     import torch
     from paper_2208_14870_amd import lbm
     out = []
     for c in cases:
         s = lbm.Solver(c.nx, c.ny, prec)
+        if kernel == "tile":
+            s.set_fused_kernel("tile")
         s.set_material(c.material.lame_lambda, c.material.lame_mu)
         s.set_body_force(torch.from_numpy(c.gx).cuda(), torch.from_numpy(c.gy).cuda())
         ex = (torch.from_numpy(c.ux_exact).cuda(), torch.from_numpy(c.uy_exact).cuda())
@@ -759,7 +767,7 @@ def main():
     nsites = cases[0].nx * cases[0].ny
 
     def measure(prec):
-        solvers = make_solvers(cases, prec)
+        solvers = make_solvers(cases, prec, args.headline_kernel if prec == "fp32" else "default")
         if args.warmup:
             run_workload(solvers, args.warmup, args.chunk)
         for s, _ in solvers:
@@ -807,7 +815,9 @@ def main():
                    "storage": "fp32", "parallelism": "single GPU"},
         "roofline": roofline("fp32", nsites, r32["plain_kernel_avg_us"], r32["steps_per_launch"],
                              kernel_label(r32["launch_config"], "float", nsites),
-                             "k_stepN_fp32_1024_counters",
+                             ("k_wave_fp32_1024_counters"
+                              if r32["launch_config"]["kernel"] == "wavefront"
+                              else "k_stepN_fp32_1024_counters"),
                              note="1024^2 FP32 (~72 MB of populations and force) fits the "
                                   "256 MB last-level cache: frac is against HBM's peak, the "
                                   "bytes need not come from HBM; the HBM-resident figures "

@@ -389,10 +389,10 @@ enum lbm_fused_kernel {
  * is used by LBM_FUSED_WAVEFRONT only: each strip is split into segments of
  * that many rows, each recomputing 2k halo rows.  Default (until this is
  * called, and again after a polish switch), measured: the wavefront for FP64
- * lattices from 458752 sites (about 677^2), FP32 above 2^20 (two columns per
- * lane from 2^25 on even widths) and FP16 from 2^24, with segments as long as leaves one wave
- * per SIMD over the lattice's strips (16 to 128 rows); the tile kernel
- * otherwise.  The tile kernel addresses a plane
+ * lattices from 458752 sites (about 677^2), FP32 from 2^20 (two columns per
+ * lane from 2^25 on even widths) and FP16 from 2^24, with segments as long as
+ * leaves one wave per SIMD over the lattice's strips (16 to 128 rows); the
+ * tile kernel otherwise.  The tile kernel addresses a plane
  * with 32-bit byte offsets, so a lattice whose planes hold 2^32 bytes or more
  * in the arithmetic type (above 2^30 FP32/FP16 or 2^29 FP64 sites) defaults
  * to the wavefront whatever its width.  In place the wavefront is the only
@@ -442,7 +442,7 @@ const char *lbm_last_error(const lbm_solver *s);
  * lbm_batch_set_wavefront_sites) these are, per storage type, all of its
  * lattices once they hold at least 2^22 (FP64), 2^23 (FP32) or 2^24 (FP16)
  * sites together, and otherwise those a single solver would step through the
- * register wavefront (FP32 above 2^20 sites, FP64 from 458752, FP16 from
+ * register wavefront (FP32 from 2^20 sites, FP64 from 458752, FP16 from
  * 2^24).  A precision with lattices on the list defaults to eight steps per
  * launch.  Residual checks run through the tile kernel for every lattice.
  * Results are identical either way (each equals single steps). */

@@ -320,14 +320,15 @@ inline hipError_t launch_solve_small(int prec, bool general, hipStream_t st, con
 
 // Default fused kernel of a single lattice of N = nx ny sites, measured on
 // MI355X (GLUPS at eight steps per launch, kernel alone; FP64 tile at five):
-//   FP32  tile / wavefront: 1024^2 241 / 241, 1100^2 212 / 271, 1448^2 231 /
-//         333, 2048^2 239 / 399, 4096^2 263 / 377, 8192^2 295 / 432 (two
-//         columns per lane);
+//   FP32  tile / wavefront: 1024^2 242 / 246 (checked chunks of 1000 steps;
+//         segments of 22 rows give 1034 waves, a second round: 160), 1100^2
+//         212 / 271, 1448^2 231 / 333, 2048^2 239 / 399, 4096^2 263 / 377,
+//         8192^2 295 / 432 (two columns per lane);
 //   FP16  1448^2 311 / 278, 2048^2 343 / 314, 2896^2 361 / 285, 4096^2 359 / 413,
 //         8192^2 380 / 449;
 //   FP64  512^2 94 / 54, 600^2 90 / 74, 724^2 87 / 103, 880^2 93 / 143,
 //         2048^2 115 / 228, 8192^2 117 / 235.
-// So: the wavefront at eight steps for FP32 above 2^20 sites (two columns per
+// So: the wavefront at eight steps for FP32 from 2^20 sites (two columns per
 // lane from 2^25 on even widths), FP64 from 458752 (about 677^2) and FP16 from
 // 2^24; the tile kernel below.  Segments: as long as leaves one wave per SIMD
 // (4 per compute unit) over the strips, at most 128 rows and at least 16: a
@@ -339,7 +340,7 @@ inline hipError_t launch_solve_small(int prec, bool general, hipStream_t st, con
 // 32-bit offsets, so the wavefront (one column per lane, any width) is the
 // only fused kernel.  wave_hs = 0 selects the tile kernel.
 inline bool wave_by_default(int prec, long long n) {
-    return (prec == LBM_FP64 && n >= 458752) || (prec == LBM_FP32 && n > (1LL << 20)) ||
+    return (prec == LBM_FP64 && n >= 458752) || (prec == LBM_FP32 && n >= (1LL << 20)) ||
            (prec == LBM_FP16 && n >= (1LL << 24));
 }
 // In a batch, lattices of one storage type fill the chip together, so above

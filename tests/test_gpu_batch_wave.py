@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 GIB = 1 << 30
 
-# (nx, ny, precision): FP32 above 2^20 sites and FP64 from 458752 sites take
+# (nx, ny, precision): FP32 from 2^20 sites and FP64 from 458752 sites take
 # the wavefront list (odd and even widths), the rest the tile kernel
 SPECS = [(1100, 960, "fp32"), (1025, 1031, "fp32"), (700, 700, "fp64"), (677, 600, "fp64"),
          (64, 64, "fp32"), (33, 65, "fp32"), (7, 5, "fp64"), (96, 40, "fp16")]

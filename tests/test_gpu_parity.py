@@ -553,7 +553,7 @@ def test_launch_config_defaults():
     """Default plain-step launches: eight steps per launch through the LDS tile
     (16 rows, 512 threads) for FP32 and FP16 above 2^17 sites, four below; FP64
     five steps through 8-row tiles of 512 threads below 458752 sites; the register
-    wavefront at eight steps for FP64 from 458752 sites, FP32 above 2^20 (two
+    wavefront at eight steps for FP64 from 458752 sites, FP32 from 2^20 (two
     columns per lane from 2^25 on even widths) and FP16 from 2^24, with
     segments as long as one wave per SIMD (1024 on 256 compute units) allows,
     16 to 128 rows (1024^2 FP64: 22 strips of 48 columns, 46 per strip, 23
@@ -565,7 +565,7 @@ def test_launch_config_defaults():
     from paper_2208_14870_amd import lbm
     need_gpu()
     cfg = lambda n, m, p, **kw: lbm.Solver(n, m, p, **kw).launch_config()
-    assert cfg(1024, 1024, "fp32") == {"steps_per_launch": 8, "kernel": "tile", "rows": 16,
+    assert cfg(1024, 1000, "fp32") == {"steps_per_launch": 8, "kernel": "tile", "rows": 16,
                                        "threads": 512}
     assert cfg(2048, 1024, "fp16") == {"steps_per_launch": 8, "kernel": "tile", "rows": 16,
                                        "threads": 512}
@@ -575,7 +575,8 @@ def test_launch_config_defaults():
                                      "threads": 512}
     assert cfg(512, 512, "fp64") == {"steps_per_launch": 5, "kernel": "tile", "rows": 8,
                                      "threads": 512}
-    for n, m, p, rows, v in ((1024, 1024, "fp64", 23, 1), (4096, 4096, "fp64", 128, 1),
+    for n, m, p, rows, v in ((1024, 1024, "fp64", 23, 1), (1024, 1024, "fp32", 23, 1),
+                             (4096, 4096, "fp64", 128, 1),
                              (724, 724, "fp64", 16, 1), (1100, 1100, "fp32", 25, 1),
                              (2048, 2048, "fp64", 90, 1),
                              (2048, 2048, "fp32", 90, 1), (4096, 4096, "fp32", 128, 1),
