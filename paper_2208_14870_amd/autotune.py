@@ -103,7 +103,7 @@ def _arch() -> str:
 
 
 def _key(kind: str, precision: str, sites: int) -> str:
-    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}|v9"
+    return f"{_arch()}|{kind}|{precision}|2^{int(round(math.log2(max(sites, 1))))}|v10"
 
 
 def _load(path: str) -> Dict[str, list]:
@@ -162,6 +162,22 @@ def time_shapes(set_shape: Callable[[Shape], None], step: Callable[[int], None],
     return res
 
 
+def solver_candidates(solver, precision: str) -> List[Shape]:
+    """The shapes tune_solver times for a solver: candidates() for its size and
+    kind and, when its current plain-step kernel is the wavefront (the
+    library's default for the larger lattices), that shape with its segment
+    height."""
+    inplace = getattr(solver, "inplace", False)
+    out = candidates(solver.nx, 0, solver.ny, wavefront=True, precision=precision,
+                     inplace=inplace)
+    cfg = solver.launch_config()
+    if cfg["kernel"] == "wavefront":
+        cur = (6, 4, 0, cfg["steps_per_launch"], cfg["rows"], 0)
+        if cur not in out:
+            out = [cur] + out
+    return out
+
+
 def tune_solver(solver, precision: str, cache_path: Optional[str] = DEFAULT_CACHE,
                 force: bool = False) -> Shape:
     """Pick and apply the fastest launch shape for a single-lattice solver."""
@@ -174,9 +190,7 @@ def tune_solver(solver, precision: str, cache_path: Optional[str] = DEFAULT_CACH
         _apply(solver, shp)
         return shp
     res = time_shapes(lambda s: _apply(solver, s), solver.step,
-                      candidates(solver.nx, 0, solver.ny, wavefront=True, precision=precision,
-                                 inplace=inplace),
-                      sites)
+                      solver_candidates(solver, precision), sites)
     shp = res[0][1]
     _apply(solver, shp)
     if cache_path:

@@ -18,8 +18,10 @@ def test_tune_solver_and_cache(tmp_path):
     s.set_material(c.material.lame_lambda, c.material.lame_mu)
     s.set_body_force(dev(c.gx), dev(c.gy))
     cache = str(tmp_path / "tune.json")
+    cands = autotune.solver_candidates(s, "fp64")
+    assert cands == autotune.candidates(256, 0, 256, wavefront=True, precision="fp64")
     shp = autotune.tune_solver(s, "fp64", cache_path=cache)
-    assert shp in autotune.candidates(256, 0, 256, wavefront=True)
+    assert shp in cands
     assert autotune.tune_solver(s, "fp64", cache_path=cache) == shp  # from the cache
     s.reset()
     s.step(50)
@@ -62,11 +64,27 @@ def test_tune_inplace_solver(tmp_path):
         s = lbm.Solver(128, 128, "fp32", inplace=True, inplace_steps=room)
         s.set_material(c.material.lame_lambda, c.material.lame_mu)
         s.set_body_force(dev(c.gx), dev(c.gy))
+        cands = autotune.solver_candidates(s, "fp32")
         shp = autotune.tune_solver(s, "fp32", cache_path=str(tmp_path / f"t{room}.json"))
-        assert shp in autotune.candidates(128, 0, 128, wavefront=True, inplace=True)
+        assert shp in cands
         if room == 1:
             assert shp[3] == 1 and shp[4] == 0
         s.reset()
         s.step(37)
         np.testing.assert_array_equal(host(s.populations()), want)
         s.close()
+
+
+def test_solver_candidates_include_the_default_wavefront():
+    """A solver whose default plain-step kernel is the wavefront (1024^2 FP32:
+    eight steps, 23-row segments) has that shape among the tuner's candidates;
+    a tile-kernel solver (512^2 FP32) has the plain candidate list."""
+    need_gpu()
+    from paper_2208_14870_amd import autotune, lbm
+    s = lbm.Solver(1024, 1024, "fp32")
+    assert autotune.solver_candidates(s, "fp32")[0] == (6, 4, 0, 8, 23, 0)
+    s.close()
+    s = lbm.Solver(512, 512, "fp32")
+    assert autotune.solver_candidates(s, "fp32") == autotune.candidates(
+        512, 0, 512, wavefront=True, precision="fp32")
+    s.close()
