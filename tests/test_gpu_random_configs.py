@@ -118,6 +118,13 @@ def test_random_batches(seed):
         tbs = {p: int(rng.integers(1, 9)) for p in ("fp64", "fp32", "fp16")}
         for p, k in tbs.items():
             b.set_time_blocking(k, p)
+        # which lattices take the wavefront list: the default rule, all, or a
+        # random minimum size
+        wave = {p: int(rng.choice([-1, 0, int(rng.integers(1, 20000))]))
+                for p in ("fp64", "fp32", "fp16")}
+        for p, m in wave.items():
+            b.set_wavefront_sites(p, m)
+        say(f"trial {trial}: depths {tbs}, wavefront list {wave}")
         lat = {}
 
         def add():
@@ -145,7 +152,7 @@ def test_random_batches(seed):
             if rng.random() < 0.3:
                 add()
         _, steps = b.residuals()
-        say(f"trial {trial} depths {tbs} plan {plan} lattices "
+        say(f"trial {trial} depths {tbs} wavefront list {wave} plan {plan} lattices "
             + str([(sl, v[0], v[1], v[2], int(steps[sl])) for sl, v in lat.items()]))
         for slot, (nx, ny, prec, mat, gx, gy) in lat.items():
             bx, by = (host(t) for t in b.displacement(slot))
