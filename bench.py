@@ -177,6 +177,8 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-oracle-large", action="store_true",
+                    help="only time the CPU oracle on the 8192^2 load (20 steps, extrapolated)")
     ap.add_argument("--cpu-oracle-only", action="store_true",
                     help="time the CPU oracle only (no GPU) and print its JSON")
     ap.add_argument("--large-only", default="",
@@ -703,6 +705,29 @@ def cpu_baseline(seconds: float):
                       f"{dt:.1f} s, FP64, OpenMP over rows"}
 
 
+def cpu_oracle_large(nsteps: int = 20):
+    """The FP64 CPU oracle on the 8192 x 8192 random load for `nsteps` steps
+    (all host cores): a short timing whose MLUPS stand for the 10,200-step run,
+    which the oracle would take hours to finish."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2208_14870_amd import problem as P
+    c = P.single_8192()
+    om = O.omega_vector(c.material.lame_lambda, c.material.lame_mu)
+    f = O.zero_state(c.nx, c.ny)
+    f = O.run(f, c.gx, c.gy, om, 1)  # first touch of the arrays, untimed
+    t0 = time.perf_counter()
+    f = O.run(f, c.gx, c.gy, om, nsteps)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    mlups = c.nx * c.ny * nsteps / dt / 1e6
+    return {"value": mlups, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "extrapolated": True,
+            "sample": f"8192x8192 random 16-mode load: {nsteps} steps in {dt:.1f} s, FP64, "
+                      f"OpenMP over rows; the 200 + 10000 steps of the workload at this rate "
+                      f"would take {c.nx * c.ny * 10200 / mlups / 1e6 / 3600:.1f} h"}
+
+
 def cpu_baseline_one_thread(seconds: float):
     """The same oracle sample on one thread, in a child process (OpenMP reads
     its thread count at start-up)."""
@@ -721,6 +746,9 @@ def main():
     args = parse()
     if args.cpu_oracle_only:
         print(json.dumps(cpu_baseline(args.cpu_seconds)), flush=True)
+        return
+    if args.cpu_oracle_large:
+        print(json.dumps({"cpu_oracle_8192": cpu_oracle_large()}), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (the "
