@@ -178,7 +178,8 @@ def parse():
                     help="also run one 1 GiB device copy (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-oracle-large", action="store_true",
-                    help="only time the CPU oracle on the 8192^2 load (20 steps, extrapolated)")
+                    help="only time the CPU oracle on the 8192^2 load (20 steps, extrapolated) "
+                         "and on lattices sampled from the 512-lattice workload")
     ap.add_argument("--cpu-oracle-only", action="store_true",
                     help="time the CPU oracle only (no GPU) and print its JSON")
     ap.add_argument("--large-only", default="",
@@ -728,6 +729,29 @@ def cpu_oracle_large(nsteps: int = 20):
                       f"would take {c.nx * c.ny * 10200 / mlups / 1e6 / 3600:.1f} h"}
 
 
+def cpu_oracle_batch_sample(nlat: int = 8, steps: int = 200):
+    """The FP64 CPU oracle on `nlat` lattices sampled from the 512-lattice
+    workload (seed 4), `steps` steps each, one after another (all host cores)."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2208_14870_amd import problem as P
+    cases = P.batch_cases(512, seed=4)
+    pick = np.random.default_rng(12).choice(len(cases), nlat, replace=False)
+    sites, dt = 0, 0.0
+    for i in pick:
+        c = cases[int(i)]
+        om = O.omega_vector(c.material.lame_lambda, c.material.lame_mu)
+        t0 = time.perf_counter()
+        O.run(O.zero_state(c.nx, c.ny), c.gx, c.gy, om, steps)
+        dt += time.perf_counter() - t0
+        sites += c.nx * c.ny
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return {"value": sites * steps / dt / 1e6, "unit": "MLUPS", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"{nlat} lattices of the 512-lattice workload ({sites} sites), "
+                      f"{steps} steps each, {dt:.1f} s, FP64, OpenMP over rows"}
+
+
 def cpu_baseline_one_thread(seconds: float):
     """The same oracle sample on one thread, in a child process (OpenMP reads
     its thread count at start-up)."""
@@ -748,7 +772,8 @@ def main():
         print(json.dumps(cpu_baseline(args.cpu_seconds)), flush=True)
         return
     if args.cpu_oracle_large:
-        print(json.dumps({"cpu_oracle_8192": cpu_oracle_large()}), flush=True)
+        print(json.dumps({"cpu_oracle_8192": cpu_oracle_large(),
+                          "cpu_oracle_batch_sample": cpu_oracle_batch_sample()}), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (the "
